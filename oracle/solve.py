@@ -1,0 +1,390 @@
+"""The inner loop and the implicit backward, one graph at a time (CPU, float64).
+
+Forward (Section 2 "Solving NLS"; Section 4.2): for t = 0..K-1
+  1. linearise every cost at theta_t: c_i, C_i, r_i = w_i c_i, J_i = w_i C_i
+     (robust costs reweighted by rho'(s_i), s_i = ||r_i||^2);
+  2. H = sum_i J_i^T J_i, g = sum_i J_i^T r_i, S_t = 1/2 sum_i rho(s_i);
+  3. damp: H + lambda I (Levenberg-Marquardt with a fixed lambda; lambda = 0 is
+     Gauss-Newton);
+  4. Cholesky factorisation, delta = (H + lambda I)^-1 g;
+  5. retract: X_k <- X_k Exp(-delta_k), Euclidean points p <- p - delta_p.
+Then a final linearisation at theta_K (lambda = 0) gives S_K and the
+undamped Gauss-Newton Hessian H*, whose factor is kept for the backward.
+
+Bundle adjustment eliminates the point blocks with the Schur complement
+(Section 4.2, BaSpaCho paragraph): S = B - E C^-1 E^T on the camera block,
+then back-substitutes delta_p = C^-1 (g_p - E^T delta_c).
+
+Backward (Section 4.3 "Implicit differentiation", Proposition 1 and its
+proof in Appendix H): with v = dL/dtheta at theta_K (tangent, caller-given),
+  u = H*^-1 v,   dL/dphi = -d/dphi [ u^T g(theta_K; phi) ]  with u held fixed,
+where g = sum_i J_i^T r_i is written as a function of the parameters phi
+(log-weights, measurement tangent perturbations Z <- Z Exp(tau), observation
+weights) and differentiated by torch.autograd.
+
+Per-graph status: 0 ok, 1 the factorisation failed (not positive definite),
+2 a non-finite value appeared.  A failed graph keeps its last iterate, repeats
+its last objective value and gets zero gradients.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import costs, lie
+
+DT = torch.float64
+OK, NOT_PD, NONFINITE = 0, 1, 2
+
+
+def _T(x):
+    return torch.as_tensor(np.asarray(x), dtype=DT)
+
+
+# ---------------------------------------------------------------------------
+# per-graph views of a batched problem
+# ---------------------------------------------------------------------------
+@dataclass
+class Graph:
+    G: lie.Group
+    X: torch.Tensor                     # [N, m, m] current poses
+    ei: torch.Tensor                    # [E] local index i
+    ej: torch.Tensor                    # [E] local index j
+    Z: torch.Tensor                     # [E, m, m]
+    logw_e: torch.Tensor                # [E]
+    pv: torch.Tensor                    # [P] local pose index of each prior
+    PZ: torch.Tensor                    # [P, m, m]
+    logw_p: torch.Tensor                # [P]
+    # bundle adjustment (None for pose graphs)
+    pts: torch.Tensor | None = None     # [Np, 3]
+    oc: torch.Tensor | None = None      # [O] local camera index
+    op: torch.Tensor | None = None      # [O] local point index
+    uv: torch.Tensor | None = None      # [O, 2]
+    w_o: torch.Tensor | None = None     # [O]
+    intr: tuple | None = None
+    delta: float = 0.0
+    tau: torch.Tensor | None = None     # [E, dof] measurement tangent perturbation
+
+    @property
+    def n_pose(self):
+        return self.X.shape[0]
+
+    @property
+    def is_ba(self):
+        return self.pts is not None
+
+
+def graphs_of(problem: dict, poses=None, points=None) -> list[Graph]:
+    G = lie.group(problem["group"])
+    poses = problem["poses_init"] if poses is None else poses
+    out = []
+    B = len(problem["pose_off"]) - 1
+    for b in range(B):
+        p0, p1 = int(problem["pose_off"][b]), int(problem["pose_off"][b + 1])
+        e0, e1 = int(problem["edge_off"][b]), int(problem["edge_off"][b + 1])
+        q0, q1 = int(problem["prior_off"][b]), int(problem["prior_off"][b + 1])
+        ij = np.asarray(problem["edge_ij"][e0:e1], dtype=np.int64).reshape(-1, 2) - p0
+        g = Graph(
+            G=G,
+            X=G.from_storage(_T(poses[p0:p1])),
+            ei=torch.as_tensor(ij[:, 0]), ej=torch.as_tensor(ij[:, 1]),
+            Z=G.from_storage(_T(problem["edge_meas"][e0:e1]).reshape(-1, *np.shape(poses)[1:])),
+            logw_e=_T(problem["edge_logw"][e0:e1]),
+            pv=torch.as_tensor(np.asarray(problem["prior_var"][q0:q1], dtype=np.int64) - p0),
+            PZ=G.from_storage(_T(problem["prior_meas"][q0:q1])),
+            logw_p=_T(problem["prior_logw"][q0:q1]),
+        )
+        if "point_off" in problem:
+            t0, t1 = int(problem["point_off"][b]), int(problem["point_off"][b + 1])
+            o0, o1 = int(problem["obs_off"][b]), int(problem["obs_off"][b + 1])
+            pts = problem["points_init"] if points is None else points
+            g.pts = _T(pts[t0:t1])
+            g.oc = torch.as_tensor(np.asarray(problem["obs_cam"][o0:o1], dtype=np.int64) - p0)
+            g.op = torch.as_tensor(np.asarray(problem["obs_pt"][o0:o1], dtype=np.int64) - t0)
+            g.uv = _T(problem["obs_uv"][o0:o1])
+            g.w_o = _T(problem["obs_w"][o0:o1])
+            g.intr = tuple(float(x) for x in problem["intrinsics"])
+            g.delta = float(problem["huber_delta"])
+        out.append(g)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# linearisation
+# ---------------------------------------------------------------------------
+@dataclass
+class Lin:
+    S: torch.Tensor                      # objective 1/2 sum rho(s)
+    H: torch.Tensor                      # pose-graph: [n, n]; BA: camera block [6Nc, 6Nc]
+    g: torch.Tensor                      # pose-graph: [n];    BA: camera part [6Nc]
+    # bundle adjustment only
+    E: torch.Tensor | None = None        # [6Nc, 3Np]
+    C: torch.Tensor | None = None        # [Np, 3, 3]
+    gp: torch.Tensor | None = None       # [Np, 3]
+    extra: dict = field(default_factory=dict)
+
+
+def _scatter_blocks(N: int, d: int, rows, cols, blocks) -> torch.Tensor:
+    """Sum d x d blocks into a dense [N*d, N*d] matrix."""
+    Hb = torch.zeros(N, N, d, d, dtype=DT)
+    Hb = Hb.index_put((rows, cols), blocks, accumulate=True)
+    return Hb.permute(0, 2, 1, 3).reshape(N * d, N * d)
+
+
+def _scatter_vec(N: int, d: int, idx, vecs) -> torch.Tensor:
+    return torch.zeros(N, d, dtype=DT).index_add(0, idx, vecs).reshape(N * d)
+
+
+def pose_costs(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None):
+    """Residual/Jacobian blocks of the relative-pose and prior costs."""
+    G = g.G
+    Z = g.Z if tau is None else g.Z @ G.exp(tau)
+    logw_e = g.logw_e if logw_e is None else logw_e
+    logw_p = g.logw_p if logw_p is None else logw_p
+    c_e, Ci, Cj = costs.between(G, X[g.ei], X[g.ej], Z)
+    c_p, Cp = costs.prior(G, X[g.pv], g.PZ)
+    return dict(c_e=c_e, Ci=Ci, Cj=Cj, w_e=torch.exp(logw_e), c_p=c_p, Cp=Cp, w_p=torch.exp(logw_p))
+
+
+def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None) -> Lin:
+    G, d, N = g.G, g.G.dof, X.shape[0]
+    k = pose_costs(g, X, tau, logw_e, logw_p)
+    w2e = (k["w_e"] ** 2)[:, None, None]
+    w2p = (k["w_p"] ** 2)[:, None, None]
+    Ci, Cj, Cp = k["Ci"], k["Cj"], k["Cp"]
+    tr = lambda A: A.transpose(-1, -2)
+    rows = torch.cat([g.ei, g.ej, g.ei, g.ej, g.pv])
+    cols = torch.cat([g.ei, g.ej, g.ej, g.ei, g.pv])
+    blocks = torch.cat([w2e * tr(Ci) @ Ci, w2e * tr(Cj) @ Cj, w2e * tr(Ci) @ Cj,
+                        w2e * tr(Cj) @ Ci, w2p * tr(Cp) @ Cp])
+    H = _scatter_blocks(N, d, rows, cols, blocks)
+    ge_i = (w2e * tr(Ci) @ k["c_e"][..., None])[..., 0]
+    ge_j = (w2e * tr(Cj) @ k["c_e"][..., None])[..., 0]
+    gp = (w2p * tr(Cp) @ k["c_p"][..., None])[..., 0]
+    gvec = _scatter_vec(N, d, torch.cat([g.ei, g.ej, g.pv]), torch.cat([ge_i, ge_j, gp]))
+    S = 0.5 * ((k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)).sum() + \
+        0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+    return Lin(S=S, H=H, g=gvec, extra=k)
+
+
+def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None):
+    w_o = g.w_o if w_o is None else w_o
+    c, Cc, Cq = costs.reprojection(X[g.oc], pts[g.op], g.uv, g.intr)
+    r2 = (w_o ** 2) * (c ** 2).sum(-1)
+    rho, drho = costs.huber(r2, g.delta)
+    c_p, Cp = costs.prior(g.G, X[g.pv], g.PZ)
+    return dict(c=c, Cc=Cc, Cq=Cq, w_o=w_o, rho=rho, drho=drho, c_p=c_p, Cp=Cp,
+                w_p=torch.exp(g.logw_p))
+
+
+def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None) -> Lin:
+    Nc, Np = X.shape[0], pts.shape[0]
+    k = ba_costs(g, X, pts, w_o)
+    tr = lambda A: A.transpose(-1, -2)
+    a = (k["drho"] * k["w_o"] ** 2)[:, None, None]          # rho' w^2
+    Cc, Cq = k["Cc"], k["Cq"]
+    w2p = (k["w_p"] ** 2)[:, None, None]
+    B = _scatter_blocks(Nc, 6, torch.cat([g.oc, g.pv]), torch.cat([g.oc, g.pv]),
+                        torch.cat([a * tr(Cc) @ Cc, w2p * tr(k["Cp"]) @ k["Cp"]]))
+    Eb = torch.zeros(Nc, Np, 6, 3, dtype=DT).index_put((g.oc, g.op), a * tr(Cc) @ Cq, accumulate=True)
+    E = Eb.permute(0, 2, 1, 3).reshape(Nc * 6, Np * 3)
+    C = torch.zeros(Np, 3, 3, dtype=DT).index_add(0, g.op, a * tr(Cq) @ Cq)
+    gc = _scatter_vec(Nc, 6, torch.cat([g.oc, g.pv]),
+                      torch.cat([(a * tr(Cc) @ k["c"][..., None])[..., 0],
+                                 (w2p * tr(k["Cp"]) @ k["c_p"][..., None])[..., 0]]))
+    gp = torch.zeros(Np, 3, dtype=DT).index_add(0, g.op, (a * tr(Cq) @ k["c"][..., None])[..., 0])
+    S = 0.5 * k["rho"].sum() + 0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+    return Lin(S=S, H=B, g=gc, E=E, C=C, gp=gp, extra=k)
+
+
+# ---------------------------------------------------------------------------
+# linear solves
+# ---------------------------------------------------------------------------
+def _chol(A: torch.Tensor):
+    L, info = torch.linalg.cholesky_ex(A)
+    return (L if int(info) == 0 else None)
+
+
+def _finite(*ts) -> bool:
+    return all(bool(torch.isfinite(t).all()) for t in ts)
+
+
+def pose_graph_step(lin: Lin, lam: float):
+    """delta = (H + lam I)^-1 g by Cholesky; returns (delta, L) or (None, None)."""
+    n = lin.H.shape[0]
+    L = _chol(lin.H + lam * torch.eye(n, dtype=DT))
+    if L is None:
+        return None, None
+    return torch.cholesky_solve(lin.g[:, None], L)[:, 0], L
+
+
+def schur_factor(lin: Lin, lam: float):
+    """Damped Schur complement on the camera block and its Cholesky factor."""
+    nc = lin.H.shape[0]
+    Cl = lin.C + lam * torch.eye(3, dtype=DT)
+    Ci = torch.linalg.inv(Cl)                                   # [Np, 3, 3]
+    Np = Ci.shape[0]
+    Cinv = torch.block_diag(*Ci) if Np else torch.zeros(0, 0, dtype=DT)
+    EC = lin.E @ Cinv
+    Sm = lin.H + lam * torch.eye(nc, dtype=DT) - EC @ lin.E.T
+    L = _chol(Sm)
+    return L, Ci, EC
+
+
+def schur_solve(lin: Lin, L, Ci, EC, rhs_c, rhs_p):
+    """Solve [[B, E], [E^T, C]] [x_c; x_p] = [rhs_c; rhs_p] given the Schur factor."""
+    rc = rhs_c - EC @ rhs_p.reshape(-1)
+    xc = torch.cholesky_solve(rc[:, None], L)[:, 0]
+    xp = (Ci @ (rhs_p - (lin.E.T @ xc).reshape(-1, 3))[..., None])[..., 0]
+    return xc, xp
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+@dataclass
+class GraphResult:
+    X: torch.Tensor
+    pts: torch.Tensor | None
+    objective: list
+    status: int
+    lin: Lin | None = None        # final linearisation at theta_K
+    factor: tuple | None = None   # cached factor of H* (or of the Schur complement)
+
+
+def solve_graph(g: Graph, iterations: int, lam: float, tau=None) -> GraphResult:
+    X = g.X.clone()
+    pts = None if g.pts is None else g.pts.clone()
+    obj, status = [], OK
+    for _ in range(iterations):
+        if g.is_ba:
+            lin = linearize_ba(g, X, pts)
+            ok = _finite(lin.S, lin.H, lin.g, lin.E, lin.C, lin.gp)
+        else:
+            lin = linearize_pose_graph(g, X, tau=tau)
+            ok = _finite(lin.S, lin.H, lin.g)
+        obj.append(float(lin.S))
+        if not ok:
+            status = NONFINITE
+            break
+        if g.is_ba:
+            L, Ci, EC = schur_factor(lin, lam)
+            if L is None:
+                status = NOT_PD
+                break
+            dc, dp = schur_solve(lin, L, Ci, EC, lin.g, lin.gp)
+            X = g.G.retract(X, -dc.reshape(-1, 6))
+            pts = pts - dp
+        else:
+            delta, L = pose_graph_step(lin, lam)
+            if delta is None:
+                status = NOT_PD
+                break
+            X = g.G.retract(X, -delta.reshape(-1, g.G.dof))
+    res = GraphResult(X=X, pts=pts, objective=obj, status=status)
+    if status != OK:
+        res.objective = obj + [obj[-1]] * (iterations + 1 - len(obj))
+        return res
+    # final linearisation at theta_K, undamped
+    lin = linearize_ba(g, X, pts) if g.is_ba else linearize_pose_graph(g, X, tau=tau)
+    res.objective = obj + [float(lin.S)]
+    res.lin = lin
+    if not _finite(lin.S, lin.H, lin.g):
+        res.status = NONFINITE
+        return res
+    if g.is_ba:
+        L, Ci, EC = schur_factor(lin, 0.0)
+        res.factor = None if L is None else (L, Ci, EC)
+    else:
+        L = _chol(lin.H)
+        res.factor = None if L is None else (L,)
+    if res.factor is None:
+        res.status = NOT_PD
+    return res
+
+
+def solve(problem: dict, iterations: int, lam: float = 0.0, graphs=None):
+    """Run the inner loop on every graph; returns (results, stacked outputs)."""
+    gs = graphs_of(problem) if graphs is None else graphs
+    results = [solve_graph(g, iterations, lam) for g in gs]
+    G = lie.group(problem["group"])
+    poses = torch.cat([G.to_storage(r.X) for r in results]).numpy()
+    out = dict(poses=poses, objective=np.array([r.objective for r in results]),
+               status=np.array([r.status for r in results], dtype=np.int32))
+    if gs and gs[0].is_ba:
+        out["points"] = torch.cat([r.pts for r in results]).numpy()
+    return results, out
+
+
+# ---------------------------------------------------------------------------
+# backward (Proposition 1)
+# ---------------------------------------------------------------------------
+def adjoint(res: GraphResult, v_pose: torch.Tensor, v_pts=None):
+    """u = H*^-1 v with the factor kept by the final linearisation."""
+    if res.lin.E is None:
+        (L,) = res.factor
+        return torch.cholesky_solve(v_pose.reshape(-1, 1), L)[:, 0].reshape(v_pose.shape), None
+    L, Ci, EC = res.factor
+    uc, up = schur_solve(res.lin, L, Ci, EC, v_pose.reshape(-1), v_pts)
+    return uc.reshape(v_pose.shape), up
+
+
+def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
+    """dL/dphi = -d/dphi [u^T g(theta_K; phi)] for the graph's parameters."""
+    d = g.G.dof
+    if res.status != OK:
+        z = dict(edge_logw=torch.zeros(len(g.ei), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
+                 tau=torch.zeros(len(g.ei), d, dtype=DT))
+        if g.is_ba:
+            z["obs_w"] = torch.zeros(len(g.oc), dtype=DT)
+        return z
+    u, up = adjoint(res, v_pose, v_pts)
+    if g.is_ba:
+        w = g.w_o.clone().requires_grad_(True)
+        lin = linearize_ba(g, res.X, res.pts, w_o=w)
+        Y = (lin.g * u.reshape(-1)).sum() + (lin.gp * up).sum()
+        (dw,) = torch.autograd.grad(Y, [w])
+        return dict(obs_w=-dw, u=u, u_pts=up)
+    le = g.logw_e.clone().requires_grad_(True)
+    lp = g.logw_p.clone().requires_grad_(True)
+    tau = torch.zeros(len(g.ei), d, dtype=DT, requires_grad=True)
+    lin = linearize_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp)
+    Y = (lin.g * u.reshape(-1)).sum()
+    de, dp, dt = torch.autograd.grad(Y, [le, lp, tau])
+    return dict(edge_logw=-de, prior_logw=-dp, tau=-dt, u=u)
+
+
+def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graphs=None) -> dict:
+    gs = graphs_of(problem) if graphs is None else graphs
+    outs = []
+    for b, (g, r) in enumerate(zip(gs, results)):
+        p0, p1 = int(problem["pose_off"][b]), int(problem["pose_off"][b + 1])
+        vp = _T(v_pose[p0:p1])
+        vq = None
+        if g.is_ba:
+            t0, t1 = int(problem["point_off"][b]), int(problem["point_off"][b + 1])
+            vq = _T(v_pts[t0:t1]) if v_pts is not None else torch.zeros(t1 - t0, 3, dtype=DT)
+        outs.append(implicit_grad_graph(g, r, vp, vq))
+    keys = [k for k in outs[0] if k not in ("u", "u_pts")]
+    out = {k: torch.cat([o[k] for o in outs]).numpy() for k in keys}
+    if all("u" in o for o in outs):
+        out["u"] = torch.cat([o["u"].reshape(-1, gs[0].G.dof) for o in outs]).numpy()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# outer loss used by the workloads: L = sum_k ||Log(X_gt,k^-1 X_k)||^2
+# ---------------------------------------------------------------------------
+def pose_error_loss_and_seed(group: str, poses: np.ndarray, poses_gt: np.ndarray):
+    """Loss value and its tangent gradient v_k = d/dxi L(X_k Exp(xi)) at xi = 0
+    (the right-perturbation gradient of Appendix D, Eq. grad1)."""
+    G = lie.group(group)
+    X = G.from_storage(_T(poses))
+    Xg = G.from_storage(_T(poses_gt))
+    xi = torch.zeros(X.shape[0], G.dof, dtype=DT, requires_grad=True)
+    e = G.log(G.inv(Xg) @ G.retract(X, xi))
+    L = (e ** 2).sum()
+    (v,) = torch.autograd.grad(L, [xi])
+    return float(L), v.numpy()

@@ -1,0 +1,235 @@
+"""Pins of the oracle's inner loop and implicit backward:
+closed-form Euclidean problems, the LM step against a direct solve, the Schur
+step against the full system, and Proposition 1 against finite differences of
+the stopped Newton step and of the fully re-solved problem."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lie, toy
+from oracle import solve as S
+
+DT = torch.float64
+rng = np.random.default_rng(2024)
+
+
+# ---------------------------------------------------------------------------
+# Euclidean problems with closed forms
+# ---------------------------------------------------------------------------
+def test_linear_gaussian_one_step_is_least_squares():
+    A = torch.as_tensor(rng.normal(size=(40, 7)), dtype=DT)
+    b = torch.as_tensor(rng.normal(size=40), dtype=DT)
+    w = torch.as_tensor(rng.uniform(0.5, 2.0, size=40), dtype=DT)
+    theta0 = torch.as_tensor(rng.normal(size=7), dtype=DT)
+    one = toy.gauss_newton(lambda th: toy.linear_gaussian_residual(th, A, b, w), theta0, 1)
+    ref = np.linalg.lstsq((w[:, None] * A).numpy(), (w * b).numpy(), rcond=None)[0]
+    assert np.abs(one.numpy() - ref).max() < 1e-12
+
+
+def test_linear_gaussian_weight_gradient_closed_form():
+    """theta*(w) = (A^T W^2 A)^-1 A^T W^2 b; its derivative against Prop. 1
+    (the Gauss-Newton Hessian is the exact Hessian for a linear problem)."""
+    A = torch.as_tensor(rng.normal(size=(12, 3)), dtype=DT)
+    b = torch.as_tensor(rng.normal(size=12), dtype=DT)
+    w = torch.as_tensor(rng.uniform(0.5, 2.0, size=12), dtype=DT)
+    v = torch.as_tensor(rng.normal(size=3), dtype=DT)
+
+    def theta_star(ww):
+        W2 = torch.diag(ww * ww)
+        return torch.linalg.solve(A.T @ W2 @ A, A.T @ W2 @ b)
+
+    th = theta_star(w)
+    ours = toy.implicit_grad(lambda t, ww: toy.linear_gaussian_residual(t, A, b, ww), th, w, v)
+    ref = torch.autograd.functional.vjp(theta_star, w, v)[1]
+    assert float((ours - ref).abs().max()) < 1e-10 * max(1.0, float(ref.abs().max()))
+
+
+def test_curve_fit_listing1_closed_forms():
+    """Listing 1: r_i = y_i - v exp(x_i); v* = sum y e^x / sum e^2x after one
+    step, and dv*/dx_k = (y_k e^x_k S2 - 2 e^2x_k S1) / S2^2 with S1 = sum y e^x,
+    S2 = sum e^2x."""
+    x = torch.as_tensor(rng.normal(size=20), dtype=DT)
+    y = 2.0 * torch.exp(x) + torch.as_tensor(0.1 * rng.normal(size=20), dtype=DT)
+    v = toy.gauss_newton(lambda vv: toy.curve_fit_residual(vv, x, y), torch.ones(1, dtype=DT), 1)
+    ex, e2x = torch.exp(x), torch.exp(2 * x)
+    S1, S2 = (y * ex).sum(), e2x.sum()
+    assert abs(float(v[0] - S1 / S2)) < 1e-12
+    # L = (v* - v_true)^2, dL/dv = 2 (v* - 2)
+    dLdv = 2 * (v - 2.0)
+    grad = toy.implicit_grad(lambda vv, xx: toy.curve_fit_residual(vv, xx, y), v, x, dLdv)
+    ref = dLdv[0] * (y * ex * S2 - 2 * e2x * S1) / S2 ** 2
+    assert float((grad - ref).abs().max()) < 1e-10 * float(ref.abs().max())
+
+
+# ---------------------------------------------------------------------------
+# damping and the Schur complement
+# ---------------------------------------------------------------------------
+def test_lm_step_equals_direct_solve_and_gn_limit():
+    p = synth.walk_se3(batch=1, n_poses=10, n_loops=5)
+    g = S.graphs_of(p)[0]
+    lin = S.linearize_pose_graph(g, g.X)
+    for lam in [1e-3, 1.0]:
+        delta, _ = S.pose_graph_step(lin, lam)
+        ref = np.linalg.solve(lin.H.numpy() + lam * np.eye(lin.H.shape[0]), lin.g.numpy())
+        assert np.abs(delta.numpy() - ref).max() < 1e-10 * np.abs(ref).max()
+    d0, _ = S.pose_graph_step(lin, 0.0)
+    d1, _ = S.pose_graph_step(lin, 1e-13)
+    assert float((d0 - d1).abs().max()) < 1e-6 * float(d0.abs().max())
+
+
+def _small_ba(noiseless=False):
+    return synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, noiseless=noiseless)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-3])
+def test_schur_step_equals_full_system(lam):
+    p = _small_ba()
+    g = S.graphs_of(p)[0]
+    lin = S.linearize_ba(g, g.X, g.pts)
+    L, Ci, EC = S.schur_factor(lin, lam)
+    dc, dp = S.schur_solve(lin, L, Ci, EC, lin.g, lin.gp)
+    nc, npnt = lin.H.shape[0], lin.C.shape[0]
+    Hf = np.zeros((nc + 3 * npnt, nc + 3 * npnt))
+    Hf[:nc, :nc] = lin.H.numpy()
+    Hf[:nc, nc:] = lin.E.numpy()
+    Hf[nc:, :nc] = lin.E.numpy().T
+    for k in range(npnt):
+        Hf[nc + 3 * k: nc + 3 * k + 3, nc + 3 * k: nc + 3 * k + 3] = lin.C[k].numpy()
+    Hf += lam * np.eye(Hf.shape[0])
+    ref = np.linalg.solve(Hf, np.concatenate([lin.g.numpy(), lin.gp.numpy().reshape(-1)]))
+    got = np.concatenate([dc.numpy(), dp.numpy().reshape(-1)])
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Proposition 1 against finite differences of the stopped Newton step:
+# F(phi) = v^T (-Hbar^-1 g(theta_K; phi)) with Hbar frozen has dF/dphi equal
+# to the implicit gradient exactly.
+# ---------------------------------------------------------------------------
+def _fd_stopped_newton(g, res, v, which, h=1e-6):
+    (L,) = res.factor
+    d = g.G.dof
+
+    def F(le, lp, tau):
+        lin = S.linearize_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp)
+        return float(-(v.reshape(-1) * torch.cholesky_solve(lin.g[:, None], L)[:, 0]).sum())
+
+    le0, lp0 = g.logw_e.clone(), g.logw_p.clone()
+    tau0 = torch.zeros(len(g.ei), d, dtype=DT)
+    out = []
+    if which == "edge_logw":
+        for k in range(len(le0)):
+            a, b_ = le0.clone(), le0.clone()
+            a[k] += h
+            b_[k] -= h
+            out.append((F(a, lp0, tau0) - F(b_, lp0, tau0)) / (2 * h))
+    elif which == "prior_logw":
+        for k in range(len(lp0)):
+            a, b_ = lp0.clone(), lp0.clone()
+            a[k] += h
+            b_[k] -= h
+            out.append((F(le0, a, tau0) - F(le0, b_, tau0)) / (2 * h))
+    else:
+        for k in range(len(le0)):
+            row = []
+            for j in range(d):
+                a, b_ = tau0.clone(), tau0.clone()
+                a[k, j] += h
+                b_[k, j] -= h
+                row.append((F(le0, lp0, a) - F(le0, lp0, b_)) / (2 * h))
+            out.append(row)
+    return np.asarray(out)
+
+
+@pytest.mark.parametrize("make,lam", [
+    (lambda: synth.circle_se2(), 0.0),
+    (lambda: synth.walk_se3(batch=1, n_poses=8, n_loops=4), 1e-3),
+])
+def test_implicit_gradient_matches_stopped_newton_fd(make, lam):
+    p = make()
+    g = S.graphs_of(p)[0]
+    res = S.solve_graph(g, 6, lam)
+    assert res.status == S.OK
+    v = torch.as_tensor(rng.normal(size=(g.n_pose, g.G.dof)), dtype=DT)
+    gr = S.implicit_grad_graph(g, res, v)
+    for key in ["edge_logw", "prior_logw", "tau"]:
+        fd = _fd_stopped_newton(g, res, v, key)
+        ours = gr[key].numpy()
+        scale = max(1e-3, np.abs(fd).max())
+        assert np.abs(ours - fd).max() < 1e-6 * scale, key
+
+
+def test_implicit_gradient_ba_obs_weights_fd():
+    p = _small_ba()
+    p["obs_w"] = np.exp(rng.normal(scale=0.3, size=len(p["obs_w"])))
+    g = S.graphs_of(p)[0]
+    g.w_o = torch.as_tensor(p["obs_w"], dtype=DT)
+    res = S.solve_graph(g, 5, 1e-3)
+    assert res.status == S.OK
+    v = torch.as_tensor(rng.normal(size=(g.n_pose, 6)), dtype=DT)
+    vq = torch.as_tensor(rng.normal(size=(g.pts.shape[0], 3)), dtype=DT)
+    ours = S.implicit_grad_graph(g, res, v, vq)["obs_w"].numpy()
+    # the Huber branch switches: make sure both branches occur in this test
+    lin = S.linearize_ba(g, res.X, res.pts)
+    assert bool((lin.extra["drho"] < 1).any()) and bool((lin.extra["drho"] == 1).any())
+    L, Ci, EC = res.factor
+
+    def F(w):
+        li = S.linearize_ba(g, res.X, res.pts, w_o=w)
+        xc, xp = S.schur_solve(res.lin, L, Ci, EC, li.g, li.gp)   # H frozen at theta_K
+        return float(-((v.reshape(-1) * xc).sum() + (vq * xp).sum()))
+
+    h = 1e-6
+    fd = []
+    for k in range(len(g.w_o)):
+        a, b_ = g.w_o.clone(), g.w_o.clone()
+        a[k] += h
+        b_[k] -= h
+        fd.append((F(a) - F(b_)) / (2 * h))
+    fd = np.asarray(fd)
+    assert np.abs(ours - fd).max() < 1e-6 * np.abs(fd).max()
+
+
+def test_implicit_gradient_noiseless_resolve_fd():
+    """Noiseless graph: theta* = ground truth, r = 0, so the Gauss-Newton Hessian
+    is the exact Hessian and Prop. 1 is the exact derivative of the re-solved
+    problem.  Loss L = sum_k <a_k, Log(X_gt,k^-1 X_k)>."""
+    p = synth.walk_se3(batch=1, n_poses=8, n_loops=5, noiseless=True)
+    G = lie.SE3
+    a = torch.as_tensor(rng.normal(size=(8, 6)), dtype=DT)
+    Xgt = G.from_storage(torch.as_tensor(p["poses_gt"]))
+
+    def loss(X):
+        return float((a * G.log(G.inv(Xgt) @ X)).sum())
+
+    g = S.graphs_of(p, poses=p["poses_gt"])[0]
+    res = S.solve_graph(g, 3, 0.0)
+    v = (G.jr_inv(G.log(G.inv(Xgt) @ res.X)).transpose(-1, -2) @ a[..., None])[..., 0]
+    ours = S.implicit_grad_graph(g, res, v)["tau"].numpy()
+    h = 1e-6
+    for k in [0, 3, 9]:
+        for j in range(6):
+            tp = torch.zeros(len(g.ei), 6, dtype=DT)
+            tm = tp.clone()
+            tp[k, j], tm[k, j] = h, -h
+            fp = loss(S.solve_graph(g, 8, 0.0, tau=tp).X)
+            fm = loss(S.solve_graph(g, 8, 0.0, tau=tm).X)
+            assert abs((fp - fm) / (2 * h) - ours[k, j]) < 1e-6 * max(1.0, np.abs(ours).max())
+
+
+def test_failed_graph_is_frozen_with_zero_gradient():
+    """Without the gauge prior and with lambda = 0 the Hessian is singular: the
+    graph keeps its initial poses and gets zero gradients."""
+    p = synth.walk_se3(batch=2, n_poses=8, n_loops=4)
+    gs = S.graphs_of(p)
+    g = gs[1]
+    g.pv = g.pv[:0]
+    g.PZ = g.PZ[:0]
+    g.logw_p = g.logw_p[:0]
+    res = S.solve_graph(g, 4, 0.0)
+    assert res.status == S.NOT_PD
+    assert torch.equal(res.X, g.X)
+    assert len(set(res.objective)) == 1 and len(res.objective) == 5
+    gr = S.implicit_grad_graph(g, res, torch.ones(8, 6, dtype=DT))
+    assert float(gr["tau"].abs().max()) == 0.0
