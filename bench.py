@@ -1,0 +1,236 @@
+"""Throughput of the batched DNLS inner step on one MI355X.
+
+One step = the whole hot path over one batch: K Levenberg-Marquardt steps
+(cost evaluation, J^T J / J^T r assembly, damping, Cholesky, triangular
+solves, retraction), the final undamped linearisation that caches the
+factor, and the implicit backward (adjoint solve with the cached factor and
+the per-cost vector-Jacobian products).
+
+Workload: 128 SE(3) random-walk pose graphs of 64 poses (63 odometry edges,
+64 loop closures, prior on pose 0), 10 LM steps at lambda = 1e-3, dense
+384 x 384 normal equations; float32 linearisation / assembly with float64
+factorisation (mixed), plus the same run in float64 for comparison.
+Inputs are synthetic and resident in device memory before timing starts.
+
+Prints one JSON line.  value = graph-steps per second = B * K / (seconds per step).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="se3_walk64_b128", batch=128, poses=64, loops=64, iterations=10, lam=1e-3)
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+KERNEL_SOURCES = ["paper_2207_09442_amd/csrc/dnls.hip", "paper_2207_09442_amd/csrc/dense.hpp",
+                  "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/lie.hpp"]
+
+
+def algorithmic_flops(problem: dict, K: int) -> float:
+    """FLOPs the method needs per solve+backward (not what the kernels spend):
+    per graph and step n^3/3 (Cholesky) + 2 n^2 (two triangular solves) +
+    2100 per cost (evaluation ~1000, J^T J / J^T r assembly ~1100); the final
+    linearisation adds one factorisation and one linearisation; the backward
+    adds two triangular solves and ~400 per cost."""
+    d = 6 if problem["group"] == "SE3" else 3
+    total = 0.0
+    for b in range(len(problem["pose_off"]) - 1):
+        n = d * (problem["pose_off"][b + 1] - problem["pose_off"][b])
+        c = (problem["edge_off"][b + 1] - problem["edge_off"][b]) + (problem["prior_off"][b + 1] - problem["prior_off"][b])
+        step = n ** 3 / 3 + 2 * n ** 2 + 2100 * c
+        total += K * step + (n ** 3 / 3 + 2100 * c) + (2 * n ** 2 + 400 * c)
+    return total
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "dense_solve_se3_walk64_b128_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_hash") != kernel_hash():
+        return None
+    return rec.get(kernel)
+
+
+def cpu_baseline(problem: dict, K: int, lam: float, n_graphs: int):
+    """The CPU oracle on the first n_graphs graphs (forward + implicit backward)."""
+    import torch
+
+    from oracle import solve as S
+    gs = S.graphs_of(problem)[:n_graphs]
+    t0 = time.perf_counter()
+    res = [S.solve_graph(g, K, lam) for g in gs]
+    seeds = []
+    for b, r in enumerate(res):
+        lo, hi = problem["pose_off"][b], problem["pose_off"][b + 1]
+        _, v = S.pose_error_loss_and_seed(problem["group"], gs[0].G.to_storage(r.X).numpy(),
+                                          problem["poses_gt"][lo:hi])
+        seeds.append(v)
+    grads = [S.implicit_grad_graph(g, r, torch.as_tensor(v)) for g, r, v in zip(gs, res, seeds)]
+    dt = time.perf_counter() - t0
+    return dt, res, seeds, grads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--cpu-graphs", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(graphs are independent, so a multi-GPU run would shard the batch with no "
+              "communication; this build runs on a single device).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2207_09442_amd import Plan
+
+    dev = torch.device("cuda:0")
+    W = WORKLOAD
+    K, lam = W["iterations"], W["lam"]
+    p = synth.walk_se3(batch=W["batch"], n_poses=W["poses"], n_loops=W["loops"])
+    t = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.float64, device=dev).contiguous()
+    em, el, pm, pl = t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"])
+    init = t(p["poses_init"])
+    gt = t(p["poses_gt"])
+
+    def run(precision: str, refine: int):
+        plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device=dev)
+        poses = init.clone()
+        # seed: tangent gradient of L = sum ||X - X_gt||^2 on the storage at the
+        # warm-up solution (an input of the backward, fixed during timing)
+        objective, status = plan.solve(poses, em, el, pm, pl)
+        from paper_2207_09442_amd import project_grad
+        seed = project_grad(p["group"], poses.reshape(plan.V, -1), (2 * (poses - gt)).reshape(plan.V, -1))
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        fwd_ms, bwd_ms = [], []
+
+        def one_step(record: bool):
+            poses.copy_(init)
+            if record:
+                ev[0].record(stream)
+            obj, st = plan.solve(poses, em, el, pm, pl)
+            if record:
+                ev[1].record(stream)
+            out = plan.backward(poses, em, el, pm, pl, st, seed)
+            if record:
+                ev[2].record(stream)
+            return obj, st, out
+
+        for _ in range(args.warmup):
+            one_step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step(True)
+            torch.cuda.synchronize()
+            fwd_ms.append(ev[0].elapsed_time(ev[1]))
+            bwd_ms.append(ev[1].elapsed_time(ev[2]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # the timed loop again without per-step host synchronisation: the value
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            obj, st, out = one_step(False)
+        torch.cuda.synchronize()
+        wall2 = time.perf_counter() - t1
+        return dict(plan=plan, poses=poses.cpu().numpy(), status=st.cpu().numpy(), grads={k: v.cpu().numpy() for k, v in out.items()},
+                    seed=seed, ms_step=1e3 * wall2 / args.steps, fwd_ms=float(np.mean(fwd_ms)),
+                    bwd_ms=float(np.mean(bwd_ms)), synced_ms=1e3 * wall / args.steps)
+
+    mixed = run("mixed", args.refine)
+    fp64 = run("fp64", 0)
+    B = W["batch"]
+    graph_steps = B * K
+    value = graph_steps / (mixed["ms_step"] * 1e-3)
+    flops = algorithmic_flops(p, K)
+    fwd_flops = flops - sum(2 * (6 * 64) ** 2 + 400 * 128 for _ in range(B))
+    achieved = fwd_flops / (mixed["fwd_ms"] * 1e-3) / 1e12
+    traffic = measured_traffic("k_dense_solve")
+    line = {
+        "metric": "GN/LM steps/sec incl. implicit-diff backward, mixed vs FP64 at 1e-5 rel err",
+        "value": value,
+        "unit": "graph-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "batch": B, "poses": W["poses"], "loop_closures": W["loops"],
+                   "iterations": K, "optimizer": "LM", "lambda": lam, "precision": "mixed",
+                   "refine": args.refine, "solver": "dense"},
+        "fp64": {"value": graph_steps / (fp64["ms_step"] * 1e-3), "ms_per_step": fp64["ms_step"],
+                 "fwd_ms": fp64["fwd_ms"], "bwd_ms": fp64["bwd_ms"]},
+        "mixed_breakdown": {"fwd_ms": mixed["fwd_ms"], "bwd_ms": mixed["bwd_ms"]},
+        "roofline": {"bound": "mfma", "kernel": "k_dense_solve", "achieved": achieved,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic,
+                     "algorithmic_flops_per_launch": fwd_flops},
+    }
+    if not args.no_cpu:
+        import torch as _t
+        ng = min(args.cpu_graphs, B)
+        dt, res, seeds, grads = cpu_baseline(p, K, lam, ng)
+        line["cpu_baseline"] = {"value": ng * K / dt, "unit": "graph-steps/s", "cores": _t.get_num_threads(),
+                                "kind": "oracle",
+                                "sample": f"first {ng} of the {B} graphs, forward (K={K}) + implicit backward, "
+                                          f"{dt:.1f} s"}
+        # errors of both GPU paths against the oracle on the sampled graphs
+        errs = {}
+        for name, r in (("mixed", mixed), ("fp64", fp64)):
+            pe, ge = 0.0, 0.0
+            # backward of the GPU runs used the GPU seed; recompute with the oracle's seeds
+            full = np.zeros((p["pose_off"][-1], 6))
+            for b in range(ng):
+                full[p["pose_off"][b]:p["pose_off"][b + 1]] = seeds[b]
+            st_dev = torch.as_tensor(r["status"], device=dev)
+            poses_dev = t(r["poses"])
+            gr = r["plan"].backward(poses_dev, em, el, pm, pl, st_dev, t(full))
+            gr = {k: v.cpu().numpy() for k, v in gr.items()}
+            for b in range(ng):
+                lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
+                e0, e1 = p["edge_off"][b], p["edge_off"][b + 1]
+                ref = res[b].X[:, :3, :].numpy()
+                pe = max(pe, np.linalg.norm(r["poses"][lo:hi] - ref) / np.linalg.norm(ref))
+                mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel()])
+                theirs = np.concatenate([grads[b]["edge_logw"].numpy(), grads[b]["tau"].numpy().ravel()])
+                ge = max(ge, np.linalg.norm(mine - theirs) / np.linalg.norm(theirs))
+            errs[name] = {"pose_rel_err_max": pe, "grad_rel_err_max": ge}
+        line["error_vs_oracle"] = errs
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * dnls.h -- C ABI of the batched differentiable nonlinear least-squares
+ * (DNLS) inner step on MI355X (gfx950).
+ *
+ * The calls follow the problem statement of "Theseus: A Library for
+ * Differentiable Nonlinear Optimization" (arXiv 2207.09442):
+ *   - variables theta_j on Lie groups (SE(2), SE(3)) or R^3 (Section 2, Eq. nls);
+ *   - cost functions c_i with scalar cost weights w_i = exp(l_i), residual
+ *     r_i = w_i c_i (Eq. nls; Section 3 core API: Variable, CostFunction,
+ *     CostWeight, Objective);
+ *   - an optimizer: K Gauss-Newton or Levenberg-Marquardt steps
+ *     (H + lambda I) delta = g, theta <- theta (-) delta by right retraction
+ *     (Section 2 "Solving NLS");
+ *   - an implicit backward through the final iterate (Section 4.3,
+ *     Proposition 1), with the factorisation kept from the forward pass
+ *     (Section 4.2 "Backward for custom linear solvers").
+ *
+ * Conventions
+ *   SE(3) element storage: 12 doubles, the 3x4 matrix [R | t] row-major.
+ *   SE(2) element storage: 4 doubles (x, y, cos theta, sin theta).
+ *   Tangent order: [translation; rotation] -- (rho, phi) in R^6 for SE(3),
+ *   (rho_x, rho_y, theta) for SE(2).  Perturbations act on the right:
+ *   X <- X Exp(xi) (Appendix D, Eq. grad1).
+ *   Relative-pose cost of edge (i, j) with measurement Z:
+ *     c = Log(Z^-1 X_i^-1 X_j); prior on pose p with target P: c = Log(P^-1 X_p);
+ *   pinhole reprojection of world point q by world-to-camera pose T:
+ *     c = (fx x/z + cx, fy y/z + cy) - uv with (x, y, z) = R q + t.
+ *   All indices are global over the batch and int32; graph b owns the
+ *   half-open ranges [off[b], off[b+1]) of every per-graph table.
+ *
+ * Ownership: the caller owns every device buffer (inputs, outputs,
+ * workspaces and the factor cache); the library never frees caller memory.
+ * A plan owns only small immutable index tables that it copies to the
+ * device at creation and frees in dnls_plan_destroy.  Plans are immutable
+ * after creation, so concurrent calls on different streams with distinct
+ * workspaces and outputs are allowed.
+ *
+ * Errors: argument and HIP runtime errors are returned as dnls_status and
+ * described by dnls_last_error() (thread-local).  Numerical failures never
+ * abort: they are reported per graph in the status output
+ * (DNLS_GRAPH_NOT_PD, DNLS_GRAPH_NONFINITE); a failed graph keeps its last
+ * iterate, repeats its last objective value and receives zero gradients.
+ * Kernel launches are asynchronous on the given stream; an asynchronous
+ * device fault surfaces at the next synchronising call.
+ */
+#ifndef DNLS_H
+#define DNLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dnls_plan_s* dnls_plan;
+
+typedef enum {
+  DNLS_OK = 0,
+  DNLS_ERR_INVALID_ARG = 1,
+  DNLS_ERR_UNSUPPORTED = 2,
+  DNLS_ERR_HIP = 3,
+  DNLS_ERR_WORKSPACE = 4,
+  DNLS_ERR_NO_FACTOR = 5
+} dnls_status;
+
+/* per-graph numerical status written by dnls_solve */
+enum { DNLS_GRAPH_OK = 0, DNLS_GRAPH_NOT_PD = 1, DNLS_GRAPH_NONFINITE = 2 };
+
+typedef enum { DNLS_SE2 = 2, DNLS_SE3 = 3 } dnls_group;
+
+/* Linear solver of the normal equations (Section 4.2):
+ *   DENSE  per-graph dense Cholesky of the pose system;
+ *   SCHUR  bundle adjustment: points eliminated by the Schur complement,
+ *          dense Cholesky of the camera system;
+ *   SPARSE per-graph block-sparse supernodal Cholesky of the pose system. */
+typedef enum { DNLS_SOLVER_DENSE = 0, DNLS_SOLVER_SCHUR = 1, DNLS_SOLVER_SPARSE = 2 } dnls_solver;
+
+/* FP64: everything in float64.
+ * MIXED: inside the K steps, residuals, Jacobians and the J^T J assembly are
+ *   float32 with float32 accumulation; damping, factorisation, solves and
+ *   retraction stay float64.  With refine > 0 the right-hand side and
+ *   `refine` matrix-free float64 residual corrections per step are added (the
+ *   factor of the float32-assembled matrix serves as preconditioner).  The
+ *   final linearisation, whose factor the implicit backward reuses, is
+ *   assembled in float64 in both precisions. */
+typedef enum { DNLS_PREC_FP64 = 0, DNLS_PREC_MIXED = 1 } dnls_precision;
+
+/* Problem structure (host pointers, read during dnls_plan_create only). */
+typedef struct {
+  int32_t batch;              /* B >= 1 graphs */
+  int32_t group;              /* dnls_group of the pose variables */
+  const int32_t* pose_off;    /* [B+1] pose ranges */
+  const int32_t* edge_off;    /* [B+1] relative-pose cost ranges */
+  const int32_t* edge_ij;     /* [2*E] (i, j) per edge, both in the edge's graph, i != j */
+  const int32_t* prior_off;   /* [B+1] prior cost ranges */
+  const int32_t* prior_var;   /* [P] pose of each prior */
+  /* bundle adjustment (solver SCHUR), else NULL / 0 */
+  const int32_t* point_off;   /* [B+1] R^3 point ranges */
+  const int32_t* obs_off;     /* [B+1] observation ranges */
+  const int32_t* obs_cam;     /* [O] camera (pose) index */
+  const int32_t* obs_pt;      /* [O] point index */
+  double fx, fy, cx, cy;      /* pinhole intrinsics */
+  double huber_delta;         /* Huber threshold on ||w c|| (> 0), SCHUR only */
+} dnls_problem;
+
+typedef struct {
+  int32_t solver;             /* dnls_solver */
+  int32_t precision;          /* dnls_precision */
+  int32_t iterations;         /* K >= 0 optimizer steps */
+  int32_t refine;             /* 0..4 float64 correction sweeps (MIXED only) */
+  double lambda;              /* Levenberg-Marquardt damping >= 0; 0 = Gauss-Newton */
+} dnls_options;
+
+/* Arguments of dnls_solve (device pointers unless stated). */
+typedef struct {
+  double* poses;              /* [V][12|4] in: theta_0, out: theta_K (in place) */
+  double* points;             /* [Vp][3] in/out (SCHUR), else NULL */
+  const double* edge_meas;    /* [E][12|4] measurements Z */
+  const double* edge_logw;    /* [E] log cost weights */
+  const double* edge_tau;     /* [E][dof] or NULL: Z <- Z Exp(tau) */
+  const double* prior_meas;   /* [P][12|4] prior targets */
+  const double* prior_logw;   /* [P] */
+  const double* obs_uv;       /* [O][2] measured pixels (SCHUR) */
+  const double* obs_w;        /* [O] observation weights (SCHUR) */
+  double* objective;          /* [B][K+1] out: S(theta_t) for t = 0..K */
+  int32_t* status;            /* [B] out: DNLS_GRAPH_* */
+  void* factor;               /* factor cache, factor_bytes, written for dnls_backward */
+  void* workspace;            /* solve_ws bytes */
+} dnls_solve_args;
+
+/* Arguments of dnls_backward: everything must be the state left by the
+ * dnls_solve call that filled `factor` (same plan, same parameters). */
+typedef struct {
+  const double* poses;        /* [V][12|4] theta_K */
+  const double* points;       /* [Vp][3] (SCHUR) else NULL */
+  const double* edge_meas;
+  const double* edge_logw;
+  const double* edge_tau;     /* may be NULL (tau = 0) */
+  const double* prior_meas;
+  const double* prior_logw;
+  const double* obs_uv;
+  const double* obs_w;
+  const int32_t* status;      /* [B] from dnls_solve */
+  const void* factor;         /* from dnls_solve */
+  const double* seed_pose;    /* [V][dof] v = dL/dtheta_K in tangent coordinates */
+  const double* seed_point;   /* [Vp][3] or NULL (SCHUR) */
+  double* grad_edge_logw;     /* [E] out or NULL */
+  double* grad_edge_tau;      /* [E][dof] out or NULL (gradient at tau) */
+  double* grad_prior_logw;    /* [P] out or NULL */
+  double* grad_obs_w;         /* [O] out or NULL (SCHUR) */
+  double* adjoint;            /* [V][dof] out or NULL: u = H*^-1 v (pose part) */
+  void* workspace;            /* backward_ws bytes */
+} dnls_backward_args;
+
+/* Validate the structure and build the plan: per-graph offsets, cost
+ * incidence lists, the dense / Schur / supernodal block maps (symbolic
+ * analysis, done once per structure).  Returns DNLS_ERR_INVALID_ARG on
+ * inconsistent offsets or indices, DNLS_ERR_UNSUPPORTED on a combination
+ * this build does not implement. */
+dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* problem,
+                             const dnls_options* options);
+
+/* Byte sizes of the caller-owned buffers of a plan. */
+dnls_status dnls_plan_workspace(dnls_plan plan, size_t* solve_ws, size_t* factor_bytes,
+                                size_t* backward_ws);
+
+/* Run K optimizer steps and the final linearisation on `stream` (a
+ * hipStream_t, NULL = default stream).  Enqueues kernels only. */
+dnls_status dnls_solve(dnls_plan plan, const dnls_solve_args* args, void* stream);
+
+/* Implicit backward (Proposition 1): u = H*^-1 v with the cached factor of
+ * the undamped Gauss-Newton Hessian at theta_K, then
+ * dL/dphi = -d/dphi [u^T g(theta_K; phi)] for the log-weights, the
+ * measurement tangent perturbations and the observation weights. */
+dnls_status dnls_backward(dnls_plan plan, const dnls_backward_args* args, void* stream);
+
+/* Projection operator of Appendix D: tangent gradient
+ * v_k = <G, d/ds X Exp(s e_k)|_{s=0}> of a Euclidean gradient G given on the
+ * element storage.  poses, grad: [n][12|4]; out: [n][dof] (device). */
+dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses,
+                              const double* grad, double* out, void* stream);
+
+/* Free the plan's device tables.  NULL is accepted. */
+dnls_status dnls_plan_destroy(dnls_plan plan);
+
+/* Message of the last error on this thread ("" if none). */
+const char* dnls_last_error(void);
+
+/* Library version string. */
+const char* dnls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNLS_H */

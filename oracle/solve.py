@@ -255,6 +255,8 @@ class GraphResult:
 
 
 def solve_graph(g: Graph, iterations: int, lam: float, tau=None) -> GraphResult:
+    if tau is None:
+        tau = g.tau
     X = g.X.clone()
     pts = None if g.pts is None else g.pts.clone()
     obj, status = [], OK
@@ -349,7 +351,8 @@ def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
         return dict(obs_w=-dw, u=u, u_pts=up)
     le = g.logw_e.clone().requires_grad_(True)
     lp = g.logw_p.clone().requires_grad_(True)
-    tau = torch.zeros(len(g.ei), d, dtype=DT, requires_grad=True)
+    tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
+    tau = tau0.clone().requires_grad_(True)
     lin = linearize_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp)
     Y = (lin.g * u.reshape(-1)).sum()
     de, dp, dt = torch.autograd.grad(Y, [le, lp, tau])

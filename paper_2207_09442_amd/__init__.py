@@ -1,0 +1,297 @@
+"""Python binding of the MI355X DNLS library (ctypes over include/dnls.h).
+
+Argument marshalling only: every step of the inner loop and of the implicit
+backward runs in the HIP kernels of libdnls.so; PyTorch provides device
+memory and the stream.  The library must have been built (see build.py);
+importing works without it, but any call raises if it is missing.
+
+Objects follow the paper's problem statement (Section 3): a batch of
+objectives given by variables (poses), cost functions (relative-pose and
+prior costs with their measurements) and scalar cost weights (log-weights),
+an optimizer (Gauss-Newton, or Levenberg-Marquardt with a fixed damping)
+and the implicit backward mode (Section 4.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["lib", "Plan", "DNLSFunction", "Layer", "project_grad", "DnlsError", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so")
+
+SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+GROUPS = {"SE2": 2, "SE3": 3}
+STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+class DnlsError(RuntimeError):
+    pass
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("pose_off", _i32p), ("edge_off", _i32p), ("edge_ij", _i32p),
+                ("prior_off", _i32p), ("prior_var", _i32p),
+                ("point_off", _i32p), ("obs_off", _i32p), ("obs_cam", _i32p), ("obs_pt", _i32p),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("huber_delta", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("lambda_", ctypes.c_double)]
+
+
+class _SolveArgs(ctypes.Structure):
+    _fields_ = [(n, _vp) for n in ["poses", "points", "edge_meas", "edge_logw", "edge_tau",
+                                   "prior_meas", "prior_logw", "obs_uv", "obs_w", "objective",
+                                   "status", "factor", "workspace"]]
+
+
+class _BackwardArgs(ctypes.Structure):
+    _fields_ = [(n, _vp) for n in ["poses", "points", "edge_meas", "edge_logw", "edge_tau",
+                                   "prior_meas", "prior_logw", "obs_uv", "obs_w", "status",
+                                   "factor", "seed_pose", "seed_point", "grad_edge_logw",
+                                   "grad_edge_tau", "grad_prior_logw", "grad_obs_w", "adjoint",
+                                   "workspace"]]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libdnls.so (raises DnlsError if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise DnlsError(f"{LIB_PATH} is missing: build it with paper_2207_09442_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.dnls_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Problem), ctypes.POINTER(_Options)]
+        L.dnls_plan_workspace.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.dnls_solve.argtypes = [_vp, ctypes.POINTER(_SolveArgs), _vp]
+        L.dnls_backward.argtypes = [_vp, ctypes.POINTER(_BackwardArgs), _vp]
+        L.dnls_project_grad.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.dnls_plan_destroy.argtypes = [_vp]
+        L.dnls_last_error.restype = ctypes.c_char_p
+        L.dnls_version.restype = ctypes.c_char_p
+        for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_solve", "dnls_backward",
+                  "dnls_project_grad", "dnls_plan_destroy"]:
+            getattr(L, f).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        msg = lib().dnls_last_error().decode()
+        raise DnlsError(f"{what} failed with status {code}: {msg}")
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(_i32p)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(x, device):
+    import torch
+    return torch.as_tensor(np.asarray(x) if not isinstance(x, torch.Tensor) else x,
+                           dtype=torch.float64, device=device).contiguous()
+
+
+class Plan:
+    """A DNLS problem structure with its optimizer settings (dnls_plan_create)
+    plus the caller-owned workspace and factor cache (torch device tensors)."""
+
+    def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
+                 precision: str = "fp64", refine: int = 0, device: str = "cuda"):
+        import torch
+        self.group = problem["group"]
+        self.dof = 6 if self.group == "SE3" else 3
+        self.sz = 12 if self.group == "SE3" else 4
+        self.K = int(iterations)
+        self.device = torch.device(device)
+        self.B = len(problem["pose_off"]) - 1
+        self.V = int(problem["pose_off"][-1])
+        self.E = int(problem["edge_off"][-1])
+        self.P = int(problem["prior_off"][-1])
+        keep = []
+        pr = _Problem()
+        pr.batch = self.B
+        pr.group = GROUPS[self.group]
+        for name in ["pose_off", "edge_off", "prior_off", "prior_var"]:
+            arr, p = _i32(problem[name])
+            keep.append(arr)
+            setattr(pr, name, p)
+        arr, p = _i32(np.asarray(problem["edge_ij"]).reshape(-1))
+        keep.append(arr)
+        pr.edge_ij = p
+        if "point_off" in problem:
+            for name in ["point_off", "obs_off", "obs_cam", "obs_pt"]:
+                arr, p = _i32(problem[name])
+                keep.append(arr)
+                setattr(pr, name, p)
+            pr.fx, pr.fy, pr.cx, pr.cy = (float(x) for x in problem["intrinsics"])
+            pr.huber_delta = float(problem["huber_delta"])
+        op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam))
+        h = _vp()
+        _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
+        self._h = h
+        sw, fb, bw = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().dnls_plan_workspace(h, ctypes.byref(sw), ctypes.byref(fb), ctypes.byref(bw)),
+               "dnls_plan_workspace")
+        self.solve_ws_bytes, self.factor_bytes, self.backward_ws_bytes = sw.value, fb.value, bw.value
+        self.workspace = torch.empty(max(1, sw.value, bw.value) + 256, dtype=torch.uint8, device=self.device)
+        self.factor = torch.empty(max(1, fb.value) + 256, dtype=torch.uint8, device=self.device)
+
+    @staticmethod
+    def _aligned(t):
+        off = (-t.data_ptr()) % 256
+        return ctypes.c_void_p(t.data_ptr() + off)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.dnls_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None):
+        """Runs K steps in place on `poses` (float64 device tensor [V, 3, 4] or
+        [V, 4]); returns (objective [B, K+1], status [B])."""
+        import torch
+        objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
+        status = torch.empty(self.B, dtype=torch.int32, device=self.device)
+        a = _SolveArgs()
+        a.poses = _ptr(poses)
+        a.edge_meas, a.edge_logw, a.edge_tau = _ptr(edge_meas), _ptr(edge_logw), _ptr(edge_tau)
+        a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
+        a.objective, a.status = _ptr(objective), _ptr(status)
+        a.factor = self._aligned(self.factor)
+        a.workspace = self._aligned(self.workspace)
+        _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
+        return objective, status
+
+    def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
+                 edge_tau=None, want_adjoint=False):
+        """Implicit backward with the cached factor; `seed` is dL/dtheta_K in
+        tangent coordinates [V, dof]."""
+        import torch
+        dev, f64 = self.device, torch.float64
+        out = {
+            "edge_logw": torch.empty(self.E, dtype=f64, device=dev),
+            "edge_tau": torch.empty(self.E, self.dof, dtype=f64, device=dev),
+            "prior_logw": torch.empty(self.P, dtype=f64, device=dev),
+        }
+        if want_adjoint:
+            out["adjoint"] = torch.empty(self.V, self.dof, dtype=f64, device=dev)
+        a = _BackwardArgs()
+        a.poses = _ptr(poses)
+        a.edge_meas, a.edge_logw, a.edge_tau = _ptr(edge_meas), _ptr(edge_logw), _ptr(edge_tau)
+        a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
+        a.status = _ptr(status)
+        a.factor = self._aligned(self.factor)
+        a.seed_pose = _ptr(seed.contiguous())
+        a.grad_edge_logw, a.grad_edge_tau = _ptr(out["edge_logw"]), _ptr(out["edge_tau"])
+        a.grad_prior_logw = _ptr(out["prior_logw"])
+        a.adjoint = _ptr(out.get("adjoint"))
+        a.workspace = self._aligned(self.workspace)
+        _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
+        return out
+
+
+def project_grad(group: str, poses, grad):
+    """Tangent gradient of a Euclidean gradient on the element storage
+    (projection operator of Appendix D), computed by the HIP kernel."""
+    import torch
+    n = poses.shape[0]
+    dof = 6 if group == "SE3" else 3
+    out = torch.empty(n, dof, dtype=torch.float64, device=poses.device)
+    _check(lib().dnls_project_grad(GROUPS[group], n, _ptr(poses.contiguous()), _ptr(grad.contiguous()),
+                                   _ptr(out), _stream()), "dnls_project_grad")
+    return out
+
+
+def _autograd_function():
+    import torch
+
+    class DNLSFunction(torch.autograd.Function):
+        """theta* = argmin S(theta; phi) by K steps, differentiable in
+        phi = (edge log-weights, measurement tangent perturbations, prior
+        log-weights) by implicit differentiation (Proposition 1)."""
+
+        @staticmethod
+        def forward(ctx, plan, poses0, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw):
+            poses = poses0.detach().clone().contiguous()
+            objective, status = plan.solve(poses, edge_meas, edge_logw.detach(), prior_meas,
+                                           prior_logw.detach(), edge_tau.detach())
+            ctx.plan = plan
+            ctx.save_for_backward(poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status)
+            ctx.mark_non_differentiable(objective, status)
+            return poses, objective, status
+
+        @staticmethod
+        def backward(ctx, g_poses, g_obj, g_status):
+            poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status = ctx.saved_tensors
+            plan = ctx.plan
+            if g_poses is None:
+                return (None,) * 7
+            seed = project_grad(plan.group, poses.reshape(plan.V, -1), g_poses.reshape(plan.V, -1))
+            gr = plan.backward(poses, edge_meas, edge_logw.detach(), prior_meas, prior_logw.detach(),
+                               status, seed, edge_tau=edge_tau.detach())
+            return (None, None, None, gr["edge_logw"], gr["edge_tau"], None, gr["prior_logw"])
+
+    return DNLSFunction
+
+
+class _Lazy:
+    def __init__(self):
+        self._f = None
+
+    def __getattr__(self, k):
+        if self._f is None:
+            self._f = _autograd_function()
+        return getattr(self._f, k)
+
+
+DNLSFunction = _Lazy()
+
+
+class Layer:
+    """Theseus-style layer: forward(inputs) -> (solution, info) with the
+    implicit backward (Section 3, Listing 1).  `inputs` maps
+    poses / edge_meas / edge_logw / edge_tau / prior_meas / prior_logw to
+    float64 device tensors; missing log-weights and tau default to zero."""
+
+    def __init__(self, plan: Plan):
+        self.plan = plan
+
+    def forward(self, inputs: dict):
+        import torch
+        p, dev = self.plan, self.plan.device
+        z = lambda *s: torch.zeros(*s, dtype=torch.float64, device=dev)
+        edge_logw = inputs.get("edge_logw", z(p.E))
+        edge_tau = inputs.get("edge_tau", z(p.E, p.dof))
+        prior_logw = inputs.get("prior_logw", z(p.P))
+        poses, objective, status = DNLSFunction.apply(p, inputs["poses"], inputs["edge_meas"], edge_logw,
+                                                      edge_tau, inputs["prior_meas"], prior_logw)
+        return {"poses": poses}, {"objective": objective, "status": status}

@@ -1,0 +1,806 @@
+// C-ABI library of the batched DNLS inner step (dense pose-graph path).
+//
+// One workgroup owns one graph for the whole solve: it linearises the costs,
+// gathers the normal equations H = sum J^T J, g = sum J^T r into the
+// caller's factor buffer (Section 2 "Solving NLS"), damps the diagonal
+// (Levenberg-Marquardt), factors with the MFMA Cholesky of dense.hpp, solves,
+// retracts, and repeats K times before the undamped final linearisation whose
+// factor is kept for the implicit backward (Section 4.2, Section 4.3,
+// Proposition 1).  The normal equations are assembled by gathering, for every
+// Hessian block, the Jacobian products of the costs incident to it (index
+// lists built once by the plan), so no atomics are needed and every sum has a
+// fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dnls.h"
+#include "costs.hpp"
+#include "dense.hpp"
+
+using namespace dnls;
+
+namespace {
+
+thread_local std::string g_err;
+
+dnls_status fail(dnls_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(DNLS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+struct GraphDesc {
+  int pose0, npose, edge0, nedge, prior0, nprior, n, npad;
+  long long fac_off;   // doubles: L (npad x npad) then L_jj^-1 tiles (npad/16 x 256)
+  int od0, nod;        // off-diagonal Hessian blocks of the graph
+};
+
+}  // namespace
+
+struct dnls_plan_s {
+  int B = 0, group = 3, d = 6, sz = 12;
+  dnls_options opt{};
+  int V = 0, E = 0, P = 0;
+  int npad_max = 0;
+  std::vector<GraphDesc> gd;
+  size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
+  size_t ws32_off = 0, ycost_off = 0;   // byte offsets inside the solve workspace
+  // device tables
+  GraphDesc* d_gd = nullptr;
+  int* d_order = nullptr;
+  int* d_edge_ij = nullptr;
+  int* d_prior_var = nullptr;
+  int* d_inc_off = nullptr;
+  int* d_inc_slot = nullptr;
+  int4* d_od_blk = nullptr;
+  int* d_od_slot = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+struct DenseArgs {
+  const GraphDesc* gd;
+  const int* order;
+  const int* edge_ij;
+  const int* prior_var;
+  const int* inc_off;
+  const int* inc_slot;
+  const int4* od_blk;
+  const int* od_slot;
+  double* poses;
+  const double* edge_meas;
+  const double* edge_logw;
+  const double* edge_tau;
+  const double* prior_meas;
+  const double* prior_logw;
+  double* objective;
+  int* status;
+  double* factor;
+  double* ws64;      // per-cost records, float64
+  float* ws32;       // per-cost records, float32 (mixed)
+  double* ycost;     // per-cost J delta (d values)
+  const double* seed;
+  double* g_logw_e;
+  double* g_tau;
+  double* g_logw_p;
+  double* adjoint_out;
+  int E;             // total edges (prior records follow the edge records)
+  int K;
+  int refine;
+  double lambda;
+};
+
+// block-wide sum of one double per thread (all threads call)
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kNW; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// Linearise every cost of graph gdesc in precision S into `rec`; returns the
+// objective 1/2 sum ||w c||^2 (block-reduced).
+template <int G, class S>
+__device__ double linearize_graph(const DenseArgs& a, const GraphDesc& g, S* rec, double* red) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz, RN = CostRec<d>::n;
+  double sacc = 0.0;
+  const int ncost = g.nedge + g.nprior;
+  for (int k = threadIdx.x; k < ncost; k += kNT) {
+    S c[d], Ci[d * d], Cj[d * d];
+    double w;
+    S* out;
+    if (k < g.nedge) {
+      const int e = g.edge0 + k;
+      const int i = a.edge_ij[2 * e], j = a.edge_ij[2 * e + 1];
+      double Z[sz];
+      perturbed_meas<G>(a.edge_meas + (size_t)e * sz, a.edge_tau ? a.edge_tau + (size_t)e * d : nullptr, Z);
+      between_cost<G, S>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
+      w = exp(a.edge_logw[e]);
+      out = rec + (size_t)e * RN;
+    } else {
+      const int p = g.prior0 + (k - g.nedge);
+      prior_cost<G, S>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Cj);
+#pragma unroll
+      for (int q = 0; q < d * d; ++q) Ci[q] = S(0);
+      w = exp(a.prior_logw[p]);
+      out = rec + (size_t)(a.E + p) * RN;
+    }
+    const S ws = S(w);
+    double cc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d * d; ++q) {
+      out[q] = ws * Ci[q];
+      out[d * d + q] = ws * Cj[q];
+    }
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      out[2 * d * d + q] = ws * c[q];
+      cc += double(c[q]) * double(c[q]);
+    }
+    sacc += 0.5 * w * w * cc;
+  }
+  return block_sum(sacc, red);
+}
+
+// Assemble the lower triangle of H (+ lambda on the diagonal, identity on the
+// padding) into A (row-major npad x npad), with products in precision S.
+template <int G, class S>
+__device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec, double* A, double lambda) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int npad = g.npad;
+  // zero the lower-triangular tiles
+  const int T = npad >> 4;
+  const int ntile = T * (T + 1) / 2;
+  for (int u = threadIdx.x; u < ntile * 64; u += kNT) {
+    const int tile = u >> 6, part = u & 63;
+    int i = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= tile) ++i;
+    while (i * (i + 1) / 2 > tile) --i;
+    const int j = tile - i * (i + 1) / 2;
+    const int row = 16 * i + (part >> 2), col = 16 * j + 4 * (part & 3);
+    *reinterpret_cast<d4v*>(A + (size_t)row * npad + col) = d4v{0.0, 0.0, 0.0, 0.0};
+  }
+  __syncthreads();
+  // diagonal blocks
+  const int nd = g.npose * d * d;
+  for (int u = threadIdx.x; u < nd; u += kNT) {
+    const int p = u / (d * d), rc = u % (d * d), r = rc / d, c = rc % d;
+    const int gp = g.pose0 + p;
+    S acc = S(0);
+    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+      const int slot = a.inc_slot[s];
+      const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+#pragma unroll
+      for (int k = 0; k < d; ++k) acc += J[k * d + r] * J[k * d + c];
+    }
+    double v = double(acc);
+    if (r == c) v += lambda;
+    A[(size_t)(p * d + r) * npad + p * d + c] = v;
+  }
+  // off-diagonal blocks (row pose > column pose)
+  const int no = g.nod * d * d;
+  for (int u = threadIdx.x; u < no; u += kNT) {
+    const int b = u / (d * d), rc = u % (d * d), r = rc / d, c = rc % d;
+    const int4 blk = a.od_blk[g.od0 + b];
+    S acc = S(0);
+    for (int s = blk.z; s < blk.z + blk.w; ++s) {
+      const int slot = a.od_slot[s];
+      const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+      const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
+#pragma unroll
+      for (int k = 0; k < d; ++k) acc += Jr[k * d + r] * Jc[k * d + c];
+    }
+    A[(size_t)(blk.x * d + r) * npad + blk.y * d + c] = double(acc);
+  }
+  for (int r = g.n + threadIdx.x; r < npad; r += kNT) A[(size_t)r * npad + r] = 1.0;
+  __syncthreads();
+}
+
+// b[p*d + r] = sum over incident costs of J^T (w c)   (zero on the padding)
+template <int G, class S>
+__device__ void assemble_g(const DenseArgs& a, const GraphDesc& g, const S* rec, double* b) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) {
+    double v = 0.0;
+    if (u < g.n) {
+      const int p = u / d, r = u % d, gp = g.pose0 + p;
+      S acc = S(0);
+      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+        const int slot = a.inc_slot[s];
+        const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        const S* res = rec + (size_t)(slot >> 1) * RN + 2 * d * d;
+#pragma unroll
+        for (int k = 0; k < d; ++k) acc += J[k * d + r] * res[k];
+      }
+      v = double(acc);
+    }
+    b[u] = v;
+  }
+  __syncthreads();
+}
+
+// y = (H + lambda I) x with H = sum J^T J applied matrix-free in float64.
+template <int G>
+__device__ void matvec_H(const DenseArgs& a, const GraphDesc& g, const double* rec, const double* x,
+                         double* y, double lambda) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int ncost = g.nedge + g.nprior;
+  for (int k = threadIdx.x; k < ncost; k += kNT) {
+    int cost, pi, pj;
+    if (k < g.nedge) {
+      cost = g.edge0 + k;
+      pi = a.edge_ij[2 * cost] - g.pose0;
+      pj = a.edge_ij[2 * cost + 1] - g.pose0;
+    } else {
+      const int p = g.prior0 + (k - g.nedge);
+      cost = a.E + p;
+      pi = -1;
+      pj = a.prior_var[p] - g.pose0;
+    }
+    const double* J = rec + (size_t)cost * RN;
+    double out[d];
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        if (pi >= 0) acc += J[r * d + q] * x[pi * d + q];
+        acc += J[d * d + r * d + q] * x[pj * d + q];
+      }
+      out[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < d; ++r) a.ycost[(size_t)cost * d + r] = out[r];
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < g.npad; u += kNT) {
+    double v = 0.0;
+    if (u < g.n) {
+      const int p = u / d, r = u % d, gp = g.pose0 + p;
+      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+        const int slot = a.inc_slot[s];
+        const double* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        const double* yc = a.ycost + (size_t)(slot >> 1) * d;
+#pragma unroll
+        for (int k = 0; k < d; ++k) v += J[k * d + r] * yc[k];
+      }
+      v += lambda * x[u];
+    }
+    y[u] = v;
+  }
+  __syncthreads();
+}
+
+struct KernelLds {
+  DenseLds dl;
+  double red[kNW];
+  int flag;
+};
+
+// ---------------------------------------------------------------------------
+// forward: K steps + final linearisation, one workgroup per graph
+// ---------------------------------------------------------------------------
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  double* A = a.factor + g.fac_off;
+  double* linv = A + (size_t)g.npad * g.npad;
+  double* vb = dyn;                // right-hand side / step
+  double* vx = dyn + g.npad;       // refinement residual
+  double* vy = dyn + 2 * g.npad;   // matrix-free product
+  int status = DNLS_GRAPH_OK;
+  double last_obj = 0.0;
+  int last_it = 0;
+  for (int it = 0; it <= a.K; ++it) {
+    const bool final_lin = (it == a.K);
+    const double lam = final_lin ? 0.0 : a.lambda;
+    double S = 0.0;
+    // the mixed path linearises in float32 inside the loop; the float64
+    // linearisation feeds its refinement sweeps and the final (cached) factor
+    const bool lin32 = MIXED && !final_lin;
+    const bool lin64 = !MIXED || a.refine > 0 || final_lin;
+    if (lin32) S = linearize_graph<G, float>(a, g, a.ws32, L.red);
+    if (lin64) S = linearize_graph<G, double>(a, g, a.ws64, L.red);
+    last_obj = S;
+    last_it = it;
+    if (threadIdx.x == 0) a.objective[(size_t)b * (a.K + 1) + it] = S;
+    if (!isfinite(S)) {
+      status = DNLS_GRAPH_NONFINITE;
+      break;
+    }
+    if (final_lin) {
+      // undamped factor of H* for the backward, assembled in float64
+      assemble_H<G, double>(a, g, a.ws64, A, 0.0);
+      if (!chol_dense(A, g.npad, linv, L.dl)) status = DNLS_GRAPH_NOT_PD;
+      break;
+    }
+    if (MIXED) {
+      assemble_H<G, float>(a, g, a.ws32, A, lam);
+      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vb);
+      else assemble_g<G, float>(a, g, a.ws32, vb);
+    } else {
+      assemble_H<G, double>(a, g, a.ws64, A, lam);
+      assemble_g<G, double>(a, g, a.ws64, vb);
+    }
+    if (!chol_dense(A, g.npad, linv, L.dl)) {
+      status = DNLS_GRAPH_NOT_PD;
+      break;
+    }
+    if (MIXED && a.refine > 0) {
+      // keep the right-hand side: vy = g64
+      for (int u = threadIdx.x; u < g.npad; u += kNT) vy[u] = vb[u];
+      __syncthreads();
+    }
+    trsv_lower(A, g.npad, linv, vb, L.dl);
+    trsv_upper_t(A, g.npad, linv, vb, L.dl);
+    if (MIXED) {
+      for (int sweep = 0; sweep < a.refine; ++sweep) {
+        // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
+        matvec_H<G>(a, g, a.ws64, vb, vx, lam);
+        for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
+        __syncthreads();
+        trsv_lower(A, g.npad, linv, vx, L.dl);
+        trsv_upper_t(A, g.npad, linv, vx, L.dl);
+        for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
+        __syncthreads();
+      }
+    }
+    // retraction X <- X Exp(-delta)
+    for (int p = threadIdx.x; p < g.npose; p += kNT)
+      retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, vb + p * d);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // a failed graph repeats its last objective for the steps that did not run
+    for (int t = last_it + 1; t <= a.K; ++t) a.objective[(size_t)b * (a.K + 1) + t] = last_obj;
+    a.status[b] = status;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward: adjoint solve with the cached factor, then per-cost VJP
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  const bool ok = a.status[b] == DNLS_GRAPH_OK;
+  if (!ok) {
+    for (int k = threadIdx.x; k < g.nedge; k += kNT) {
+      const int e = g.edge0 + k;
+      if (a.g_logw_e) a.g_logw_e[e] = 0.0;
+      if (a.g_tau)
+        for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
+    }
+    for (int k = threadIdx.x; k < g.nprior; k += kNT)
+      if (a.g_logw_p) a.g_logw_p[g.prior0 + k] = 0.0;
+    if (a.adjoint_out)
+      for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = 0.0;
+    return;
+  }
+  const double* A = a.factor + g.fac_off;
+  const double* linv = A + (size_t)g.npad * g.npad;
+  double* vu = dyn;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
+  __syncthreads();
+  // float64 linearisation at theta_K: residuals and Jacobians for the VJP
+  linearize_graph<G, double>(a, g, a.ws64, L.red);
+  trsv_lower(A, g.npad, linv, vu, L.dl);
+  trsv_upper_t(A, g.npad, linv, vu, L.dl);
+  if (a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
+  // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
+  const int ncost = g.nedge + g.nprior;
+  for (int k = threadIdx.x; k < ncost; k += kNT) {
+    int cost, pi, pj;
+    double w;
+    if (k < g.nedge) {
+      cost = g.edge0 + k;
+      pi = a.edge_ij[2 * cost] - g.pose0;
+      pj = a.edge_ij[2 * cost + 1] - g.pose0;
+      w = exp(a.edge_logw[cost]);
+    } else {
+      const int p = g.prior0 + (k - g.nedge);
+      cost = a.E + p;
+      pi = -1;
+      pj = a.prior_var[p] - g.pose0;
+      w = exp(a.prior_logw[p]);
+    }
+    const double* J = a.ws64 + (size_t)cost * RN;
+    const double* r = J + 2 * d * d;
+    double y[d], yr = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < d; ++m) {
+        if (pi >= 0) acc += J[q * d + m] * vu[pi * d + m];
+        acc += J[d * d + q * d + m] * vu[pj * d + m];
+      }
+      y[q] = acc;
+      yr += acc * r[q];
+    }
+    if (k < g.nedge) {
+      if (a.g_logw_e) a.g_logw_e[cost] = -2.0 * yr;
+      if (a.g_tau) {
+        // dL/dtau = w^2 d/ds [Jl^-1(c)^T c] along cdot = C u = y / w
+        double c[d], cd[d], out[d];
+#pragma unroll
+        for (int q = 0; q < d; ++q) {
+          c[q] = r[q] / w;
+          cd[q] = y[q] / w;
+        }
+        dual_jlinvT_c<G>(c, cd, out);
+        // chain rule through Z Exp(tau) at a non-zero tau: Exp(tau + dt) =
+        // Exp(tau) Exp(Jr(tau) dt), so dL/dtau = Jr(tau)^T dL/dxi
+        double gt[d];
+#pragma unroll
+        for (int q = 0; q < d; ++q) gt[q] = w * w * out[q];
+        if (a.edge_tau) {
+          double tau[d], Jt[d * d];
+#pragma unroll
+          for (int q = 0; q < d; ++q) tau[q] = a.edge_tau[(size_t)cost * d + q];
+          if constexpr (G == 3) se3_jr(tau, Jt);
+          else se2_jr(tau, Jt);
+#pragma unroll
+          for (int q = 0; q < d; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < d; ++m) acc += Jt[m * d + q] * gt[m];
+            a.g_tau[(size_t)cost * d + q] = acc;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < d; ++q) a.g_tau[(size_t)cost * d + q] = gt[q];
+        }
+      }
+    } else if (a.g_logw_p) {
+      a.g_logw_p[cost - a.E] = -2.0 * yr;
+    }
+  }
+}
+
+// projection operator of Appendix D (one thread per element)
+template <int G>
+__global__ void k_project(long long n, const double* X, const double* Gr, double* out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  if constexpr (G == 3) {
+    const double* x = X + e * 12;
+    const double* gr = Gr + e * 12;
+    double M[9];
+    // M = R^T G_R
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) M[r * 3 + q] = x[0 * 4 + r] * gr[0 * 4 + q] + x[1 * 4 + r] * gr[1 * 4 + q] + x[2 * 4 + r] * gr[2 * 4 + q];
+    double* o = out + e * 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o[k] = x[0 * 4 + k] * gr[3] + x[1 * 4 + k] * gr[7] + x[2 * 4 + k] * gr[11];
+    o[3] = M[7] - M[5];
+    o[4] = M[2] - M[6];
+    o[5] = M[3] - M[1];
+  } else {
+    const double* x = X + e * 4;
+    const double* gr = Gr + e * 4;
+    const double c = x[2], s = x[3];
+    double* o = out + e * 3;
+    o[0] = c * gr[0] + s * gr[1];
+    o[1] = -s * gr[0] + c * gr[1];
+    o[2] = -s * gr[2] + c * gr[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+template <class T>
+dnls_status upload(dnls_plan p, T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return DNLS_OK;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)));
+  p->allocs.push_back(*dst);
+  HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DNLS_OK;
+}
+
+bool check_off(const int32_t* off, int B, int total_hint, int* total) {
+  if (!off || off[0] != 0) return false;
+  for (int b = 0; b < B; ++b)
+    if (off[b + 1] < off[b]) return false;
+  *total = off[B];
+  (void)total_hint;
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <int G, bool MIXED>
+dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
+  const size_t lds = 3 * (size_t)p->npad_max * sizeof(double);
+  hipLaunchKernelGGL((k_dense_solve<G, MIXED>), dim3(p->B), dim3(kNT), lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+template <int G>
+dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)p->npad_max * sizeof(double);
+  hipLaunchKernelGGL((k_dense_backward<G>), dim3(p->B), dim3(kNT), lds, st, a);
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* dnls_last_error(void) { return g_err.c_str(); }
+
+const char* dnls_version(void) { return "dnls-gfx950 0.1"; }
+
+dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_options* op) {
+  g_err.clear();
+  if (!out || !pr || !op) return fail(DNLS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (pr->batch < 1) return fail(DNLS_ERR_INVALID_ARG, "batch must be >= 1");
+  if (pr->group != DNLS_SE2 && pr->group != DNLS_SE3) return fail(DNLS_ERR_INVALID_ARG, "group must be SE2 or SE3");
+  if (op->iterations < 0) return fail(DNLS_ERR_INVALID_ARG, "iterations must be >= 0");
+  if (!(op->lambda >= 0.0)) return fail(DNLS_ERR_INVALID_ARG, "lambda must be >= 0");
+  if (op->precision != DNLS_PREC_FP64 && op->precision != DNLS_PREC_MIXED)
+    return fail(DNLS_ERR_INVALID_ARG, "unknown precision");
+  if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
+  if (op->solver != DNLS_SOLVER_DENSE)
+    return fail(DNLS_ERR_UNSUPPORTED, "this entry point handles the DENSE solver");
+  const int B = pr->batch;
+  int V = 0, E = 0, P = 0;
+  if (!check_off(pr->pose_off, B, 0, &V) || !check_off(pr->edge_off, B, 0, &E) ||
+      !check_off(pr->prior_off, B, 0, &P))
+    return fail(DNLS_ERR_INVALID_ARG, "offsets must start at 0 and be non-decreasing");
+  if (E > 0 && !pr->edge_ij) return fail(DNLS_ERR_INVALID_ARG, "edge_ij is NULL");
+  if (P > 0 && !pr->prior_var) return fail(DNLS_ERR_INVALID_ARG, "prior_var is NULL");
+
+  auto* p = new dnls_plan_s();
+  p->B = B;
+  p->group = pr->group;
+  p->d = pr->group == DNLS_SE3 ? 6 : 3;
+  p->sz = pr->group == DNLS_SE3 ? 12 : 4;
+  p->opt = *op;
+  p->V = V;
+  p->E = E;
+  p->P = P;
+  const int d = p->d;
+
+  // per-pose incidence (slots = cost * 2 + side) and off-diagonal blocks
+  std::vector<std::vector<int>> inc(V);
+  std::vector<int> edge_ij(2 * (size_t)E), prior_var(P);
+  std::vector<int4> od_blk;
+  std::vector<int> od_slot;
+  p->gd.resize(B);
+  long long fac = 0;
+  for (int b = 0; b < B; ++b) {
+    GraphDesc& g = p->gd[b];
+    g.pose0 = pr->pose_off[b];
+    g.npose = pr->pose_off[b + 1] - g.pose0;
+    g.edge0 = pr->edge_off[b];
+    g.nedge = pr->edge_off[b + 1] - g.edge0;
+    g.prior0 = pr->prior_off[b];
+    g.nprior = pr->prior_off[b + 1] - g.prior0;
+    g.n = g.npose * d;
+    g.npad = std::max(16, (g.n + 15) / 16 * 16);
+    if (g.npad > 4096) {
+      delete p;
+      return fail(DNLS_ERR_UNSUPPORTED, "dense solver supports at most 4096 unknowns per graph");
+    }
+    g.fac_off = fac;
+    fac += (long long)g.npad * g.npad + (long long)(g.npad / 16) * 256;
+    fac = (fac + 31) / 32 * 32;
+    p->npad_max = std::max(p->npad_max, g.npad);
+    std::map<std::pair<int, int>, std::vector<int>> blocks;
+    for (int e = g.edge0; e < g.edge0 + g.nedge; ++e) {
+      const int i = pr->edge_ij[2 * (size_t)e], j = pr->edge_ij[2 * (size_t)e + 1];
+      if (i < g.pose0 || i >= g.pose0 + g.npose || j < g.pose0 || j >= g.pose0 + g.npose || i == j) {
+        delete p;
+        return fail(DNLS_ERR_INVALID_ARG, "edge " + std::to_string(e) + " has an index outside its graph or i == j");
+      }
+      edge_ij[2 * (size_t)e] = i;
+      edge_ij[2 * (size_t)e + 1] = j;
+      inc[i].push_back(2 * e + 0);
+      inc[j].push_back(2 * e + 1);
+      const int li = i - g.pose0, lj = j - g.pose0;
+      if (li > lj) blocks[{li, lj}].push_back(2 * e + 0);   // row side = i
+      else blocks[{lj, li}].push_back(2 * e + 1);           // row side = j
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      const int v = pr->prior_var[q];
+      if (v < g.pose0 || v >= g.pose0 + g.npose) {
+        delete p;
+        return fail(DNLS_ERR_INVALID_ARG, "prior " + std::to_string(q) + " refers to a pose outside its graph");
+      }
+      prior_var[q] = v;
+      inc[v].push_back(2 * (E + q) + 1);
+    }
+    g.od0 = (int)od_blk.size();
+    for (auto& kv : blocks) {
+      od_blk.push_back(int4{kv.first.first, kv.first.second, (int)od_slot.size(), (int)kv.second.size()});
+      for (int s : kv.second) od_slot.push_back(s);
+    }
+    g.nod = (int)od_blk.size() - g.od0;
+  }
+  std::vector<int> inc_off(V + 1, 0), inc_slot;
+  for (int v = 0; v < V; ++v) {
+    inc_off[v + 1] = inc_off[v] + (int)inc[v].size();
+    for (int s : inc[v]) inc_slot.push_back(s);
+  }
+  // largest graphs first
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->gd[x].npad > p->gd[y].npad; });
+
+  dnls_status st;
+  if ((st = upload(p, &p->d_gd, p->gd)) != DNLS_OK ||
+      (st = upload(p, &p->d_order, order)) != DNLS_OK ||
+      (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
+      (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK ||
+      (st = upload(p, &p->d_inc_off, inc_off)) != DNLS_OK ||
+      (st = upload(p, &p->d_inc_slot, inc_slot)) != DNLS_OK ||
+      (st = upload(p, &p->d_od_blk, od_blk)) != DNLS_OK ||
+      (st = upload(p, &p->d_od_slot, od_slot)) != DNLS_OK) {
+    std::string msg = g_err;
+    dnls_plan_destroy(p);
+    return fail(st, msg);
+  }
+  const size_t ncost = (size_t)E + P;
+  const size_t rn = 2 * (size_t)d * d + d;
+  size_t ws = align256(ncost * rn * sizeof(double));
+  p->ws32_off = ws;
+  if (op->precision == DNLS_PREC_MIXED) ws += align256(ncost * rn * sizeof(float));
+  p->ycost_off = ws;
+  ws += align256(ncost * d * sizeof(double));
+  p->ws_bytes = ws;
+  p->bwd_bytes = ws;
+  p->fac_bytes = (size_t)fac * sizeof(double);
+  *out = p;
+  return DNLS_OK;
+}
+
+dnls_status dnls_plan_workspace(dnls_plan p, size_t* solve_ws, size_t* factor_bytes, size_t* backward_ws) {
+  if (!p) return fail(DNLS_ERR_INVALID_ARG, "null plan");
+  if (solve_ws) *solve_ws = p->ws_bytes;
+  if (factor_bytes) *factor_bytes = p->fac_bytes;
+  if (backward_ws) *backward_ws = p->bwd_bytes;
+  return DNLS_OK;
+}
+
+static DenseArgs base_args(dnls_plan p) {
+  DenseArgs a{};
+  a.gd = p->d_gd;
+  a.order = p->d_order;
+  a.edge_ij = p->d_edge_ij;
+  a.prior_var = p->d_prior_var;
+  a.inc_off = p->d_inc_off;
+  a.inc_slot = p->d_inc_slot;
+  a.od_blk = p->d_od_blk;
+  a.od_slot = p->d_od_slot;
+  a.E = p->E;
+  a.K = p->opt.iterations;
+  a.refine = p->opt.precision == DNLS_PREC_MIXED ? p->opt.refine : 0;
+  a.lambda = p->opt.lambda;
+  return a;
+}
+
+dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
+  g_err.clear();
+  if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
+  if (!s->poses || !s->objective || !s->status || !s->factor || !s->workspace)
+    return fail(DNLS_ERR_INVALID_ARG, "poses, objective, status, factor and workspace are required");
+  if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+    return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
+  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
+    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  DenseArgs a = base_args(p);
+  a.poses = s->poses;
+  a.edge_meas = s->edge_meas;
+  a.edge_logw = s->edge_logw;
+  a.edge_tau = s->edge_tau;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.objective = s->objective;
+  a.status = s->status;
+  a.factor = static_cast<double*>(s->factor);
+  char* ws = static_cast<char*>(s->workspace);
+  a.ws64 = reinterpret_cast<double*>(ws);
+  a.ws32 = reinterpret_cast<float*>(ws + p->ws32_off);
+  a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
+  if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
+  return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);
+}
+
+dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream) {
+  g_err.clear();
+  if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
+  if (!s->poses || !s->status || !s->factor || !s->workspace || !s->seed_pose)
+    return fail(DNLS_ERR_INVALID_ARG, "poses, status, factor, seed_pose and workspace are required");
+  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
+    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  DenseArgs a = base_args(p);
+  a.poses = const_cast<double*>(s->poses);
+  a.edge_meas = s->edge_meas;
+  a.edge_logw = s->edge_logw;
+  a.edge_tau = s->edge_tau;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.status = const_cast<int*>(s->status);
+  a.factor = const_cast<double*>(static_cast<const double*>(s->factor));
+  char* ws = static_cast<char*>(s->workspace);
+  a.ws64 = reinterpret_cast<double*>(ws);
+  a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
+  a.seed = s->seed_pose;
+  a.g_logw_e = s->grad_edge_logw;
+  a.g_tau = s->grad_edge_tau;
+  a.g_logw_p = s->grad_prior_logw;
+  a.adjoint_out = s->adjoint;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the cached factor is float64-assembled in both precisions
+  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st);
+  return launch_backward<2>(p, a, st);
+}
+
+dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses, const double* grad, double* out,
+                              void* stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!poses || !grad || !out))) return fail(DNLS_ERR_INVALID_ARG, "bad arguments");
+  if (group != DNLS_SE2 && group != DNLS_SE3) return fail(DNLS_ERR_INVALID_ARG, "group must be SE2 or SE3");
+  if (n == 0) return DNLS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nt = 256;
+  const unsigned nb = (unsigned)((n + nt - 1) / nt);
+  if (group == DNLS_SE3) hipLaunchKernelGGL(k_project<3>, dim3(nb), dim3(nt), 0, st, (long long)n, poses, grad, out);
+  else hipLaunchKernelGGL(k_project<2>, dim3(nb), dim3(nt), 0, st, (long long)n, poses, grad, out);
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+dnls_status dnls_plan_destroy(dnls_plan p) {
+  if (!p) return DNLS_OK;
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+  return DNLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the
+C-ABI binding and the CPU oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import solve as S
+
+DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
+
+
+def t(x, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(x), dtype=dtype, device=DEV).contiguous()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def per_graph_rel(a, b, off):
+    """max over graphs of ||a_b - b_b|| / ||b_b||"""
+    worst = 0.0
+    for g in range(len(off) - 1):
+        lo, hi = int(off[g]), int(off[g + 1])
+        if hi > lo:
+            worst = max(worst, rel(a[lo:hi], b[lo:hi]))
+    return worst
+
+
+def gpu_solve(p, K, lam, precision="fp64", refine=0, tau=None):
+    from paper_2207_09442_amd import Plan
+    plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device=DEV)
+    poses = t(p["poses_init"])
+    dev = dict(edge_meas=t(p["edge_meas"]), edge_logw=t(p["edge_logw"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]), edge_tau=None if tau is None else t(tau))
+    objective, status = plan.solve(poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"],
+                                   dev["prior_logw"], edge_tau=dev["edge_tau"])
+    torch.cuda.synchronize()
+    return plan, poses, objective, status, dev
+
+
+def gpu_backward(plan, poses, status, dev, seed, want_adjoint=False):
+    out = plan.backward(poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"], dev["prior_logw"],
+                        status, t(seed), edge_tau=dev["edge_tau"], want_adjoint=want_adjoint)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def oracle_graphs(p, tau=None, graphs=None):
+    gs = S.graphs_of(p)
+    if tau is not None:
+        for b, g in enumerate(gs):
+            e0, e1 = int(p["edge_off"][b]), int(p["edge_off"][b + 1])
+            g.tau = torch.as_tensor(np.asarray(tau[e0:e1]), dtype=torch.float64)
+    if graphs is not None:
+        gs = [gs[b] for b in graphs]
+    return gs
+
+
+def oracle_solve(p, K, lam, tau=None, graphs=None):
+    """Oracle forward for all graphs (or the listed ones); returns
+    (results, poses per listed graph list, objective, status)."""
+    gs = oracle_graphs(p, tau, graphs)
+    res = [S.solve_graph(g, K, lam, tau=g.tau) for g in gs]
+    return gs, res
+
+
+def oracle_grads(gs, res, seeds):
+    """seeds: list of [N_b, dof] arrays per graph."""
+    out = []
+    for g, r, v in zip(gs, res, seeds):
+        o = S.implicit_grad_graph(g, r, torch.as_tensor(v, dtype=torch.float64))
+        out.append({k: x.detach().numpy() for k, x in o.items()})
+    return out
