@@ -169,19 +169,20 @@ def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_
     return Lin(S=S, H=H, g=gvec, extra=k)
 
 
-def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None):
+def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None):
     w_o = g.w_o if w_o is None else w_o
+    logw_p = g.logw_p if logw_p is None else logw_p
     c, Cc, Cq = costs.reprojection(X[g.oc], pts[g.op], g.uv, g.intr)
     r2 = (w_o ** 2) * (c ** 2).sum(-1)
     rho, drho = costs.huber(r2, g.delta)
     c_p, Cp = costs.prior(g.G, X[g.pv], g.PZ)
     return dict(c=c, Cc=Cc, Cq=Cq, w_o=w_o, rho=rho, drho=drho, c_p=c_p, Cp=Cp,
-                w_p=torch.exp(g.logw_p))
+                w_p=torch.exp(logw_p))
 
 
-def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None) -> Lin:
+def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None) -> Lin:
     Nc, Np = X.shape[0], pts.shape[0]
-    k = ba_costs(g, X, pts, w_o)
+    k = ba_costs(g, X, pts, w_o, logw_p)
     tr = lambda A: A.transpose(-1, -2)
     a = (k["drho"] * k["w_o"] ** 2)[:, None, None]          # rho' w^2
     Cc, Cq = k["Cc"], k["Cq"]
@@ -226,8 +227,8 @@ def schur_factor(lin: Lin, lam: float):
     Cl = lin.C + lam * torch.eye(3, dtype=DT)
     Ci = torch.linalg.inv(Cl)                                   # [Np, 3, 3]
     Np = Ci.shape[0]
-    Cinv = torch.block_diag(*Ci) if Np else torch.zeros(0, 0, dtype=DT)
-    EC = lin.E @ Cinv
+    # E C^-1 with C^-1 block-diagonal: multiply each point's 3 columns by its block
+    EC = torch.einsum("rpk,pkj->rpj", lin.E.reshape(nc, Np, 3), Ci).reshape(nc, 3 * Np)
     Sm = lin.H + lam * torch.eye(nc, dtype=DT) - EC @ lin.E.T
     L = _chol(Sm)
     return L, Ci, EC
@@ -340,15 +341,16 @@ def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
         z = dict(edge_logw=torch.zeros(len(g.ei), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
                  tau=torch.zeros(len(g.ei), d, dtype=DT))
         if g.is_ba:
-            z["obs_w"] = torch.zeros(len(g.oc), dtype=DT)
+            z = dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT))
         return z
     u, up = adjoint(res, v_pose, v_pts)
     if g.is_ba:
         w = g.w_o.clone().requires_grad_(True)
-        lin = linearize_ba(g, res.X, res.pts, w_o=w)
+        lp = g.logw_p.clone().requires_grad_(True)
+        lin = linearize_ba(g, res.X, res.pts, w_o=w, logw_p=lp)
         Y = (lin.g * u.reshape(-1)).sum() + (lin.gp * up).sum()
-        (dw,) = torch.autograd.grad(Y, [w])
-        return dict(obs_w=-dw, u=u, u_pts=up)
+        dw, dp = torch.autograd.grad(Y, [w, lp])
+        return dict(obs_w=-dw, prior_logw=-dp, u=u, u_pts=up)
     le = g.logw_e.clone().requires_grad_(True)
     lp = g.logw_p.clone().requires_grad_(True)
     tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)

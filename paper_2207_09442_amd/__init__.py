@@ -134,6 +134,8 @@ class Plan:
         self.V = int(problem["pose_off"][-1])
         self.E = int(problem["edge_off"][-1])
         self.P = int(problem["prior_off"][-1])
+        self.Vp = int(problem["point_off"][-1]) if "point_off" in problem else 0
+        self.O = int(problem["obs_off"][-1]) if "obs_off" in problem else 0
         keep = []
         pr = _Problem()
         pr.batch = self.B
@@ -213,6 +215,48 @@ class Plan:
         a.seed_pose = _ptr(seed.contiguous())
         a.grad_edge_logw, a.grad_edge_tau = _ptr(out["edge_logw"]), _ptr(out["edge_tau"])
         a.grad_prior_logw = _ptr(out["prior_logw"])
+        a.adjoint = _ptr(out.get("adjoint"))
+        a.workspace = self._aligned(self.workspace)
+        _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
+        return out
+
+
+    # ------------------------------------------------------------------
+    def solve_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw):
+        """Bundle adjustment (solver "schur"): K steps in place on `cams`
+        [Vc, 3, 4] and `points` [Vp, 3]; returns (objective [B, K+1], status [B])."""
+        import torch
+        objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
+        status = torch.empty(self.B, dtype=torch.int32, device=self.device)
+        a = _SolveArgs()
+        a.poses, a.points = _ptr(cams), _ptr(points)
+        a.obs_uv, a.obs_w = _ptr(obs_uv), _ptr(obs_w)
+        a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
+        a.objective, a.status = _ptr(objective), _ptr(status)
+        a.factor = self._aligned(self.factor)
+        a.workspace = self._aligned(self.workspace)
+        _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
+        return objective, status
+
+    def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,
+                    seed_pt=None, want_adjoint=False):
+        """Implicit backward of bundle adjustment: gradients of the observation
+        weights and prior log-weights for tangent seeds on cameras (and points)."""
+        import torch
+        dev, f64 = self.device, torch.float64
+        out = {"obs_w": torch.empty(self.O, dtype=f64, device=dev),
+               "prior_logw": torch.empty(self.P, dtype=f64, device=dev)}
+        if want_adjoint:
+            out["adjoint"] = torch.empty(self.V, 6, dtype=f64, device=dev)
+        a = _BackwardArgs()
+        a.poses, a.points = _ptr(cams), _ptr(points)
+        a.obs_uv, a.obs_w = _ptr(obs_uv), _ptr(obs_w)
+        a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
+        a.status = _ptr(status)
+        a.factor = self._aligned(self.factor)
+        a.seed_pose = _ptr(seed_cam.contiguous())
+        a.seed_point = _ptr(None if seed_pt is None else seed_pt.contiguous())
+        a.grad_obs_w, a.grad_prior_logw = _ptr(out["obs_w"]), _ptr(out["prior_logw"])
         a.adjoint = _ptr(out.get("adjoint"))
         a.workspace = self._aligned(self.workspace)
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")

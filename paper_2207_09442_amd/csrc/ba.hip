@@ -1,0 +1,809 @@
+// Bundle adjustment with the Schur complement (solver SCHUR).
+//
+// Variables: world-to-camera poses T (SE(3)) and world points q (R^3).  Cost
+// per observation: pinhole reprojection c = pi(R q + t) - uv with a scalar
+// weight w and a Huber loss on s = ||w c||^2 (Section 3 cost library: the
+// reprojection error and robust losses; Appendix E.3).  The Gauss-Newton step
+// uses the first-order reweighting rho'(s): J~ = sqrt(rho') w C, r~ =
+// sqrt(rho') w c.  Camera priors c = Log(P^-1 T) fix the gauge.
+//
+// The point blocks are eliminated (Section 4.2: the Schur complement trick
+// that sparse solvers for bundle adjustment rely on): with B the camera
+// block, E the camera-point blocks and C the block-diagonal point block,
+//   S = B - E C^-1 E^T,  g_s = g_c - E C^-1 g_p,
+//   S delta_c = g_s (dense MFMA Cholesky),  delta_p = C^-1 (g_p - E^T delta_c).
+// Levenberg-Marquardt damping adds lambda to the diagonals of B and C.
+// The backward (Proposition 1) solves H* u = v with the same elimination and
+// the cached factor of S*, then forms dL/dw_o = -d/dw_o [rho'(s) w^2 (C u)^T c].
+//
+// Kernels per step (grid y = problem): linearise observations, point blocks
+// and E C^-1, Schur complement by gathering per camera pair (plan-built
+// contribution lists: no atomics), dense factor + solve (one workgroup per
+// problem), point back-substitution and retraction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "costs.hpp"
+#include "dense.hpp"
+#include "plan.hpp"
+
+namespace dnls {
+namespace {
+
+constexpr int kBT = 256;
+constexpr int kObsRec = 20;   // J~cam (2x6), J~pt (2x3), r~ (2)
+constexpr int kPriorRec = 42; // w C (6x6), w c (6)
+
+struct BAArgs {
+  const BADesc* bd;
+  const int* obs_cam;
+  const int* obs_pt;
+  const int* cam_obs_off;
+  const int* cam_obs;
+  const int* pt_obs_off;
+  const int* pt_obs;
+  const int4* sblk;
+  const int2* spair;
+  const int* prior_var;
+  double* cams;
+  double* pts;
+  const double* obs_uv;
+  const double* obs_w;
+  const double* prior_meas;
+  const double* prior_logw;
+  double fx, fy, cx, cy, delta;
+  void* orec;
+  double* prec;
+  double* E;
+  double* F;
+  double* Cinv;
+  double* gp;
+  double* partial;
+  double* dc;
+  int* frozen;
+  double* lastobj;
+  double* objective;
+  int* status;
+  double* factor;
+  int K, it, npad_max, nx_lin;
+  double lambda;
+  // backward
+  const double* seed_c;
+  const double* seed_p;
+  double* uc;
+  double* up;
+  double* g_w;
+  double* g_logw_p;
+  double* adjoint_out;
+};
+
+__device__ double block_sum_ba(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// Reprojection residual and Jacobians; camera/point in float64 storage,
+// derivatives in precision S.  Returns false if the point is behind the camera.
+template <class S>
+__device__ __forceinline__ void reproj(const double* T, const double* q, const double* uv, const BAArgs& a,
+                                       double c[2], S Jc[12], S Jp[6]) {
+  double pc[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) pc[r] = T[r * 4] * q[0] + T[r * 4 + 1] * q[1] + T[r * 4 + 2] * q[2] + T[r * 4 + 3];
+  const double iz = 1.0 / pc[2];
+  c[0] = a.fx * pc[0] * iz + a.cx - uv[0];
+  c[1] = a.fy * pc[1] * iz + a.cy - uv[1];
+  // dpi/dpc (2x3)
+  const S d00 = S(a.fx * iz), d02 = S(-a.fx * pc[0] * iz * iz);
+  const S d11 = S(a.fy * iz), d12 = S(-a.fy * pc[1] * iz * iz);
+  S R[9], Q[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) R[r * 3 + k] = S(T[r * 4 + k]);
+    Q[r] = S(q[r]);
+  }
+  // Jp = dpi R
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Jp[k] = d00 * R[k] + d02 * R[6 + k];
+    Jp[3 + k] = d11 * R[3 + k] + d12 * R[6 + k];
+  }
+  // Jc = dpi R [I, -q^] = [Jp, -Jp q^];  (Jp q^)_k = (q x Jp_row)... written out:
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const S* jp = Jp + 3 * r;
+    Jc[r * 6 + 0] = jp[0];
+    Jc[r * 6 + 1] = jp[1];
+    Jc[r * 6 + 2] = jp[2];
+    // -(jp^T q^) = -(q^T ... ): row vector jp * (-q^) = (jp x q)... explicit:
+    // (-q^) = [[0, q2, -q1], [-q2, 0, q0], [q1, -q0, 0]]
+    Jc[r * 6 + 3] = -jp[1] * Q[2] + jp[2] * Q[1];
+    Jc[r * 6 + 4] = jp[0] * Q[2] - jp[2] * Q[0];
+    Jc[r * 6 + 5] = -jp[0] * Q[1] + jp[1] * Q[0];
+  }
+}
+
+__device__ __forceinline__ void huber(double s, double delta, double& rho, double& drho) {
+  if (s <= delta * delta) {
+    rho = s;
+    drho = 1.0;
+  } else {
+    const double r = ::sqrt(s);
+    rho = 2.0 * delta * r - delta * delta;
+    drho = delta / r;
+  }
+}
+
+// 1. linearise observations (and the problem's priors in its first block)
+template <class S>
+__global__ void __launch_bounds__(kBT) k_ba_lin(BAArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  double sacc = 0.0;
+  if (!a.frozen[b]) {
+    const int lo = blockIdx.x * kBT + threadIdx.x;
+    if (lo < g.nobs) {
+      const int o = g.obs0 + lo;
+      double c[2];
+      S Jc[12], Jp[6];
+      reproj<S>(a.cams + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a, c,
+                Jc, Jp);
+      const double w = a.obs_w[o];
+      double rho, drho;
+      huber(w * w * (c[0] * c[0] + c[1] * c[1]), a.delta, rho, drho);
+      const double sw = ::sqrt(drho) * w;
+      S* rec = reinterpret_cast<S*>(a.orec) + (size_t)o * kObsRec;
+      const S ss = S(sw);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rec[k] = ss * Jc[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rec[12 + k] = ss * Jp[k];
+      rec[18] = S(sw * c[0]);
+      rec[19] = S(sw * c[1]);
+      sacc += 0.5 * rho;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior) {
+      const int q = g.prior0 + threadIdx.x;
+      double c[6], C[36];
+      prior_cost<3, double>(a.cams + (size_t)a.prior_var[q] * 12, a.prior_meas + (size_t)q * 12, c, C);
+      const double w = exp(a.prior_logw[q]);
+      double* pr = a.prec + (size_t)q * kPriorRec;
+      double cc = 0.0;
+      for (int k = 0; k < 36; ++k) pr[k] = w * C[k];
+      for (int k = 0; k < 6; ++k) {
+        pr[36 + k] = w * c[k];
+        cc += c[k] * c[k];
+      }
+      sacc += 0.5 * w * w * cc;
+    }
+  }
+  const double tot = block_sum_ba(sacc, red);
+  if (threadIdx.x == 0) a.partial[b * a.nx_lin + blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ bool inv3(const double m[9], double r[9]) {
+  r[0] = m[4] * m[8] - m[5] * m[7];
+  r[1] = m[2] * m[7] - m[1] * m[8];
+  r[2] = m[1] * m[5] - m[2] * m[4];
+  r[3] = m[5] * m[6] - m[3] * m[8];
+  r[4] = m[0] * m[8] - m[2] * m[6];
+  r[5] = m[2] * m[3] - m[0] * m[5];
+  r[6] = m[3] * m[7] - m[4] * m[6];
+  r[7] = m[1] * m[6] - m[0] * m[7];
+  r[8] = m[0] * m[4] - m[1] * m[3];
+  const double det = m[0] * r[0] + m[1] * r[3] + m[2] * r[6];
+  const double id = 1.0 / det;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r[k] *= id;
+  return det > 0.0;
+}
+
+// 2. point blocks C = sum J~p^T J~p + lambda I, g_p, C^-1, E_o = J~c^T J~p, F_o = E_o C^-1
+template <class S>
+__global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int lp = blockIdx.x * kBT + threadIdx.x;
+  if (lp >= g.npt) return;
+  const int pt = g.pt0 + lp;
+  const S* rec = reinterpret_cast<const S*>(a.orec);
+  S C[9], gg[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) C[k] = S(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gg[k] = S(0);
+  for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+    const S* r = rec + (size_t)a.pt_obs[s] * kObsRec;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) C[i * 3 + j] += r[12 + i] * r[12 + j] + r[15 + i] * r[15 + j];
+      gg[i] += r[12 + i] * r[18] + r[15 + i] * r[19];
+    }
+  }
+  double Cd[9], Ci[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Cd[k] = double(C[k]) + ((k % 4 == 0) ? lambda : 0.0);
+  inv3(Cd, Ci);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a.Cinv[(size_t)pt * 9 + k] = Ci[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a.gp[(size_t)pt * 3 + k] = double(gg[k]);
+  for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+    const int o = a.pt_obs[s];
+    const S* r = rec + (size_t)o * kObsRec;
+    double Eo[18];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Eo[i * 3 + j] = double(r[i] * r[12 + j] + r[6 + i] * r[15 + j]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a.E[(size_t)o * 18 + i * 3 + j] = Eo[i * 3 + j];
+        a.F[(size_t)o * 18 + i * 3 + j] = Eo[i * 3] * Ci[j] + Eo[i * 3 + 1] * Ci[3 + j] + Eo[i * 3 + 2] * Ci[6 + j];
+      }
+  }
+}
+
+// 3. Schur complement S (lower blocks, all) and g_s into the augmented row
+template <class S>
+__global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  double* A = a.factor + g.fac_off;
+  const int npad = g.npad;
+  const S* rec = reinterpret_cast<const S*>(a.orec);
+  // padding rows and the augmented tile
+  if (blockIdx.x == 0) {
+    for (int e = threadIdx.x; e < (npad - g.n) * npad; e += kBT) {
+      const int r = g.n + e / npad, c = e % npad;
+      A[(size_t)r * npad + c] = (r == c) ? 1.0 : 0.0;
+    }
+    for (int e = threadIdx.x; e < 16 * npad; e += kBT) {
+      const int r = npad + e / npad, c = e % npad;
+      if (r > npad || c >= g.n) A[(size_t)r * npad + c] = 0.0;
+    }
+  }
+  const int lb = blockIdx.x * kBT + threadIdx.x;
+  if (lb >= g.nblk) return;
+  const int4 blk = a.sblk[g.blk0 + lb];
+  const int ca = blk.x, cb = blk.y;
+  double v[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) v[k] = 0.0;
+  if (ca == cb) {
+    const int cam = g.cam0 + ca;
+    S h[36];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) h[k] = S(0);
+    double gs[6] = {0, 0, 0, 0, 0, 0};
+    S gsl[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gsl[k] = S(0);
+    for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+      const int o = a.cam_obs[s];
+      const S* r = rec + (size_t)o * kObsRec;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) h[i * 6 + j] += r[i] * r[j] + r[6 + i] * r[6 + j];
+        gsl[i] += r[i] * r[18] + r[6 + i] * r[19];
+      }
+      // - F_o g_p
+      const double* Fo = a.F + (size_t)o * 18;
+      const double* gpp = a.gp + (size_t)a.obs_pt[o] * 3;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) gs[i] -= Fo[i * 3] * gpp[0] + Fo[i * 3 + 1] * gpp[1] + Fo[i * 3 + 2] * gpp[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 36; ++k) v[k] = double(h[k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gs[k] += double(gsl[k]);
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      if (a.prior_var[q] != cam) continue;
+      const double* pr = a.prec + (size_t)q * kPriorRec;
+      for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) {
+          double t = 0.0;
+          for (int k = 0; k < 6; ++k) t += pr[k * 6 + i] * pr[k * 6 + j];
+          v[i * 6 + j] += t;
+        }
+        double t = 0.0;
+        for (int k = 0; k < 6; ++k) t += pr[k * 6 + i] * pr[36 + k];
+        gs[i] += t;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i * 7] += lambda;
+    double* aug = A + (size_t)npad * npad;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) aug[ca * 6 + i] = gs[i];
+  }
+  for (int s = blk.z; s < blk.z + blk.w; ++s) {
+    const int2 pr = a.spair[s];
+    const double* Fa = a.F + (size_t)pr.x * 18;
+    const double* Eb = a.E + (size_t)pr.y * 18;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) v[i * 6 + j] -= Fa[i * 3] * Eb[j * 3] + Fa[i * 3 + 1] * Eb[j * 3 + 1] + Fa[i * 3 + 2] * Eb[j * 3 + 2];
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) A[(size_t)(ca * 6 + i) * npad + cb * 6 + j] = v[i * 6 + j];
+}
+
+struct BALds {
+  DenseLds dl;
+  double red[kNW];
+};
+
+// 4. objective, factorisation and camera step (one workgroup per problem)
+__global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
+  extern __shared__ double dyn[];
+  __shared__ BALds L;
+  const int b = blockIdx.x;
+  const BADesc g = a.bd[b];
+  double* obj = a.objective + (size_t)b * (a.K + 1);
+  if (a.frozen[b]) {
+    if (threadIdx.x == 0) obj[a.it] = a.lastobj[b];
+    return;
+  }
+  double S = 0.0;
+  for (int k = 0; k < a.nx_lin; ++k) S += a.partial[b * a.nx_lin + k];
+  if (threadIdx.x == 0) {
+    obj[a.it] = S;
+    a.lastobj[b] = S;
+  }
+  if (!isfinite(S)) {
+    if (threadIdx.x == 0) {
+      a.frozen[b] = DNLS_GRAPH_NONFINITE;
+      a.status[b] = DNLS_GRAPH_NONFINITE;
+    }
+    return;
+  }
+  double* A = a.factor + g.fac_off;
+  double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  const bool ok = chol_dense(A, g.npad, winv, L.dl);
+  if (!ok) {
+    if (threadIdx.x == 0) {
+      a.frozen[b] = DNLS_GRAPH_NOT_PD;
+      a.status[b] = DNLS_GRAPH_NOT_PD;
+    }
+    return;
+  }
+  if (final_lin) return;
+  double* x = dyn;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) x[u] = A[(size_t)g.npad * g.npad + u];
+  __syncthreads();
+  trsv_upper_t(A, g.npad, winv, x, L.dl);
+  for (int u = threadIdx.x; u < g.npad; u += kNT) a.dc[(size_t)b * a.npad_max + u] = x[u];
+}
+
+// 5. point back-substitution and retraction of cameras and points
+__global__ void __launch_bounds__(kBT) k_ba_update(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  const double* dc = a.dc + (size_t)b * a.npad_max;
+  if (t < g.npt) {
+    const int pt = g.pt0 + t;
+    double r[3] = {a.gp[(size_t)pt * 3], a.gp[(size_t)pt * 3 + 1], a.gp[(size_t)pt * 3 + 2]};
+    for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+      const int o = a.pt_obs[s];
+      const double* Eo = a.E + (size_t)o * 18;
+      const double* d = dc + (a.obs_cam[o] - g.cam0) * 6;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc += Eo[i * 3 + j] * d[i];
+        r[j] -= acc;
+      }
+    }
+    const double* Ci = a.Cinv + (size_t)pt * 9;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a.pts[(size_t)pt * 3 + j] -= Ci[j * 3] * r[0] + Ci[j * 3 + 1] * r[1] + Ci[j * 3 + 2] * r[2];
+  }
+  if (t < g.ncam) retract_minus<3>(a.cams + (size_t)(g.cam0 + t) * 12, dc + t * 6);
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// u_c = S*^-1 (v_c - sum_o F_o v_p(o))  (one workgroup per problem)
+__global__ void __launch_bounds__(kNT) k_ba_bwd_cam(BAArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ BALds L;
+  const int b = blockIdx.x;
+  const BADesc g = a.bd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) return;
+  const double* A = a.factor + g.fac_off;
+  const double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  double* x = dyn;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) {
+    double v = 0.0;
+    if (u < g.n) {
+      const int ca = u / 6, i = u % 6, cam = g.cam0 + ca;
+      v = a.seed_c[(size_t)cam * 6 + i];
+      if (a.seed_p)
+        for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+          const int o = a.cam_obs[s];
+          const double* Fo = a.F + (size_t)o * 18 + i * 3;
+          const double* vp = a.seed_p + (size_t)a.obs_pt[o] * 3;
+          v -= Fo[0] * vp[0] + Fo[1] * vp[1] + Fo[2] * vp[2];
+        }
+    }
+    x[u] = v;
+  }
+  __syncthreads();
+  trsv_lower(A, g.npad, winv, x, L.dl);
+  trsv_upper_t(A, g.npad, winv, x, L.dl);
+  for (int u = threadIdx.x; u < g.npad; u += kNT) a.uc[(size_t)b * a.npad_max + u] = x[u];
+  if (a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.cam0 * 6 + u] = x[u];
+}
+
+// u_p = C^-1 (v_p - sum_o E_o^T u_c(o))
+__global__ void __launch_bounds__(kBT) k_ba_bwd_pt(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t >= g.npt) return;
+  const int pt = g.pt0 + t;
+  const double* uc = a.uc + (size_t)b * a.npad_max;
+  double r[3] = {0, 0, 0};
+  if (a.seed_p)
+    for (int j = 0; j < 3; ++j) r[j] = a.seed_p[(size_t)pt * 3 + j];
+  for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+    const int o = a.pt_obs[s];
+    const double* Eo = a.E + (size_t)o * 18;
+    const double* d = uc + (a.obs_cam[o] - g.cam0) * 6;
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < 6; ++i) acc += Eo[i * 3 + j] * d[i];
+      r[j] -= acc;
+    }
+  }
+  const double* Ci = a.Cinv + (size_t)pt * 9;
+  for (int j = 0; j < 3; ++j) a.up[(size_t)pt * 3 + j] = Ci[j * 3] * r[0] + Ci[j * 3 + 1] * r[1] + Ci[j * 3 + 2] * r[2];
+}
+
+// per-observation and per-prior VJP
+__global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  const bool ok = a.status[b] == DNLS_GRAPH_OK;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  const double* uc = a.uc + (size_t)b * a.npad_max;
+  if (t < g.nobs && a.g_w) {
+    const int o = g.obs0 + t;
+    double gw = 0.0;
+    if (ok) {
+      double c[2], Jc[12], Jp[6];
+      reproj<double>(a.cams + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a,
+                     c, Jc, Jp);
+      const double* ucam = uc + (a.obs_cam[o] - g.cam0) * 6;
+      const double* upt = a.up + (size_t)a.obs_pt[o] * 3;
+      double y[2];
+      for (int r = 0; r < 2; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 6; ++k) acc += Jc[r * 6 + k] * ucam[k];
+        for (int k = 0; k < 3; ++k) acc += Jp[r * 3 + k] * upt[k];
+        y[r] = acc;
+      }
+      const double w = a.obs_w[o];
+      const double yc = y[0] * c[0] + y[1] * c[1];
+      const double cn2 = c[0] * c[0] + c[1] * c[1];
+      if (w * w * cn2 <= a.delta * a.delta) gw = -2.0 * w * yc;
+      else gw = -a.delta * yc / ::sqrt(cn2);
+    }
+    a.g_w[o] = gw;
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior && a.g_logw_p) {
+    const int q = g.prior0 + threadIdx.x;
+    double gl = 0.0;
+    if (ok) {
+      double c[6], C[36];
+      prior_cost<3, double>(a.cams + (size_t)a.prior_var[q] * 12, a.prior_meas + (size_t)q * 12, c, C);
+      const double w = exp(a.prior_logw[q]);
+      const double* u = uc + (a.prior_var[q] - g.cam0) * 6;
+      double yr = 0.0;
+      for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 6; ++k) acc += C[r * 6 + k] * u[k];
+        yr += w * acc * w * c[r];
+      }
+      gl = -2.0 * yr;
+    }
+    a.g_logw_p[q] = gl;
+  }
+}
+
+__global__ void k_ba_reset(int* frozen, int* status, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    frozen[b] = 0;
+    status[b] = DNLS_GRAPH_OK;
+  }
+}
+
+bool offsets_ok(const int32_t* off, int B, int* total) {
+  if (!off || off[0] != 0) return false;
+  for (int b = 0; b < B; ++b)
+    if (off[b + 1] < off[b]) return false;
+  *total = off[B];
+  return true;
+}
+
+BAArgs base_args(dnls_plan p) {
+  BAArgs a{};
+  a.bd = p->d_bd;
+  a.obs_cam = p->d_obs_cam;
+  a.obs_pt = p->d_obs_pt;
+  a.cam_obs_off = p->d_cam_obs_off;
+  a.cam_obs = p->d_cam_obs;
+  a.pt_obs_off = p->d_pt_obs_off;
+  a.pt_obs = p->d_pt_obs;
+  a.sblk = p->d_sblk;
+  a.spair = p->d_spair;
+  a.prior_var = p->d_prior_var;
+  a.fx = p->intr[0];
+  a.fy = p->intr[1];
+  a.cx = p->intr[2];
+  a.cy = p->intr[3];
+  a.delta = p->huber;
+  a.K = p->opt.iterations;
+  a.npad_max = p->npad_max;
+  a.lambda = p->opt.lambda;
+  return a;
+}
+
+int max_of(const std::vector<BADesc>& v, int BADesc::*f) {
+  int m = 1;
+  for (const auto& x : v) m = std::max(m, x.*f);
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_options* op) {
+  const int B = pr->batch;
+  int Vc = 0, Vp = 0, O = 0, P = 0;
+  if (!offsets_ok(pr->pose_off, B, &Vc) || !offsets_ok(pr->point_off, B, &Vp) || !offsets_ok(pr->obs_off, B, &O) ||
+      !offsets_ok(pr->prior_off, B, &P))
+    return fail(DNLS_ERR_INVALID_ARG, "bundle adjustment needs pose/point/obs/prior offsets starting at 0, non-decreasing");
+  if (pr->group != DNLS_SE3) return fail(DNLS_ERR_UNSUPPORTED, "bundle adjustment uses SE3 cameras");
+  if (O > 0 && (!pr->obs_cam || !pr->obs_pt)) return fail(DNLS_ERR_INVALID_ARG, "obs_cam / obs_pt are NULL");
+  if (P > 0 && !pr->prior_var) return fail(DNLS_ERR_INVALID_ARG, "prior_var is NULL");
+  if (!(pr->huber_delta > 0.0)) return fail(DNLS_ERR_INVALID_ARG, "huber_delta must be > 0");
+  if (pr->edge_off && pr->edge_off[B] != 0) return fail(DNLS_ERR_UNSUPPORTED, "relative-pose costs are not part of the SCHUR path");
+  p->V = Vc;
+  p->Vp = Vp;
+  p->O = O;
+  p->P = P;
+  p->E = 0;
+  p->intr[0] = pr->fx;
+  p->intr[1] = pr->fy;
+  p->intr[2] = pr->cx;
+  p->intr[3] = pr->cy;
+  p->huber = pr->huber_delta;
+  std::vector<int> obs_cam(O), obs_pt(O), prior_var(P);
+  std::vector<std::vector<int>> cam_obs(Vc), pt_obs(Vp);
+  std::vector<int4> sblk;
+  std::vector<int2> spair;
+  p->bd.resize(B);
+  long long fac = 0;
+  for (int b = 0; b < B; ++b) {
+    BADesc& g = p->bd[b];
+    g.cam0 = pr->pose_off[b];
+    g.ncam = pr->pose_off[b + 1] - g.cam0;
+    g.pt0 = pr->point_off[b];
+    g.npt = pr->point_off[b + 1] - g.pt0;
+    g.obs0 = pr->obs_off[b];
+    g.nobs = pr->obs_off[b + 1] - g.obs0;
+    g.prior0 = pr->prior_off[b];
+    g.nprior = pr->prior_off[b + 1] - g.prior0;
+    if (g.nprior > kBT) return fail(DNLS_ERR_UNSUPPORTED, "at most 256 camera priors per problem");
+    g.n = 6 * g.ncam;
+    g.npad = std::max(kNB, (g.n + kNB - 1) / kNB * kNB);
+    if (g.npad > kMaxDenseN) return fail(DNLS_ERR_UNSUPPORTED, "camera system larger than the dense limit");
+    g.fac_off = fac;
+    fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
+    fac = (fac + 31) / 32 * 32;
+    p->npad_max = std::max(p->npad_max, g.npad);
+    for (int o = g.obs0; o < g.obs0 + g.nobs; ++o) {
+      const int c = pr->obs_cam[o], q = pr->obs_pt[o];
+      if (c < g.cam0 || c >= g.cam0 + g.ncam || q < g.pt0 || q >= g.pt0 + g.npt)
+        return fail(DNLS_ERR_INVALID_ARG, "observation " + std::to_string(o) + " refers outside its problem");
+      obs_cam[o] = c;
+      obs_pt[o] = q;
+      cam_obs[c].push_back(o);
+      pt_obs[q].push_back(o);
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      const int v = pr->prior_var[q];
+      if (v < g.cam0 || v >= g.cam0 + g.ncam)
+        return fail(DNLS_ERR_INVALID_ARG, "prior " + std::to_string(q) + " refers outside its problem");
+      prior_var[q] = v;
+    }
+    // Schur contributions F_oa E_ob^T of every point to camera pair (cam oa >= cam ob)
+    std::map<std::pair<int, int>, std::vector<int2>> blocks;
+    for (int q = g.pt0; q < g.pt0 + g.npt; ++q)
+      for (int oa : pt_obs[q])
+        for (int ob : pt_obs[q]) {
+          const int ca = obs_cam[oa] - g.cam0, cb = obs_cam[ob] - g.cam0;
+          if (ca >= cb) blocks[{ca, cb}].push_back(int2{oa, ob});
+        }
+    g.blk0 = (int)sblk.size();
+    for (int ca = 0; ca < g.ncam; ++ca)
+      for (int cb = 0; cb <= ca; ++cb) {
+        auto it = blocks.find({ca, cb});
+        const int start = (int)spair.size();
+        int cnt = 0;
+        if (it != blocks.end()) {
+          for (const int2& x : it->second) spair.push_back(x);
+          cnt = (int)it->second.size();
+        }
+        sblk.push_back(int4{ca, cb, start, cnt});
+      }
+    g.nblk = (int)sblk.size() - g.blk0;
+  }
+  std::vector<int> cam_off(Vc + 1, 0), cam_list, pt_off(Vp + 1, 0), pt_list;
+  for (int c = 0; c < Vc; ++c) {
+    cam_off[c + 1] = cam_off[c] + (int)cam_obs[c].size();
+    for (int o : cam_obs[c]) cam_list.push_back(o);
+  }
+  for (int q = 0; q < Vp; ++q) {
+    pt_off[q + 1] = pt_off[q] + (int)pt_obs[q].size();
+    for (int o : pt_obs[q]) pt_list.push_back(o);
+  }
+  const int nx = (max_of(p->bd, &BADesc::nobs) + kBT - 1) / kBT;
+  p->nlin_blocks = nx;
+  dnls_status st;
+  if ((st = upload(p, &p->d_bd, p->bd)) != DNLS_OK || (st = upload(p, &p->d_obs_cam, obs_cam)) != DNLS_OK ||
+      (st = upload(p, &p->d_obs_pt, obs_pt)) != DNLS_OK || (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK ||
+      (st = upload(p, &p->d_cam_obs_off, cam_off)) != DNLS_OK || (st = upload(p, &p->d_cam_obs, cam_list)) != DNLS_OK ||
+      (st = upload(p, &p->d_pt_obs_off, pt_off)) != DNLS_OK || (st = upload(p, &p->d_pt_obs, pt_list)) != DNLS_OK ||
+      (st = upload(p, &p->d_sblk, sblk)) != DNLS_OK || (st = upload(p, &p->d_spair, spair)) != DNLS_OK)
+    return st;
+  // solve workspace: obs records, prior records, objective partials, camera steps, frozen flags
+  size_t off = 0;
+  p->ba_off[0] = off; off += align256((size_t)O * kObsRec * sizeof(double));
+  p->ba_off[1] = off; off += align256((size_t)P * kPriorRec * sizeof(double));
+  p->ba_off[2] = off; off += align256((size_t)B * nx * sizeof(double));
+  p->ba_off[3] = off; off += align256((size_t)B * p->npad_max * sizeof(double));
+  p->ba_off[4] = off; off += align256((size_t)B * sizeof(int));
+  p->ba_off[5] = off; off += align256((size_t)B * sizeof(double));
+  p->ba_off[6] = off; off += align256((size_t)Vp * 3 * sizeof(double));   // u_p (backward)
+  p->ws_bytes = off;
+  p->bwd_bytes = off;
+  // factor cache: Schur factors, then E, F, C^-1, g_p of the final linearisation
+  size_t fb = align256((size_t)fac * sizeof(double));
+  p->ba_fac_off[0] = fb; fb += align256((size_t)O * 18 * sizeof(double));
+  p->ba_fac_off[1] = fb; fb += align256((size_t)O * 18 * sizeof(double));
+  p->ba_fac_off[2] = fb; fb += align256((size_t)Vp * 9 * sizeof(double));
+  p->ba_fac_off[3] = fb; fb += align256((size_t)Vp * 3 * sizeof(double));
+  p->fac_bytes = fb;
+  (void)op;
+  return DNLS_OK;
+}
+
+static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
+  char* w = static_cast<char*>(ws);
+  char* f = static_cast<char*>(factor);
+  a.orec = w + p->ba_off[0];
+  a.prec = reinterpret_cast<double*>(w + p->ba_off[1]);
+  a.partial = reinterpret_cast<double*>(w + p->ba_off[2]);
+  a.dc = reinterpret_cast<double*>(w + p->ba_off[3]);
+  a.uc = a.dc;
+  a.frozen = reinterpret_cast<int*>(w + p->ba_off[4]);
+  a.lastobj = reinterpret_cast<double*>(w + p->ba_off[5]);
+  a.up = reinterpret_cast<double*>(w + p->ba_off[6]);
+  a.factor = reinterpret_cast<double*>(f);
+  a.E = reinterpret_cast<double*>(f + p->ba_fac_off[0]);
+  a.F = reinterpret_cast<double*>(f + p->ba_fac_off[1]);
+  a.Cinv = reinterpret_cast<double*>(f + p->ba_fac_off[2]);
+  a.gp = reinterpret_cast<double*>(f + p->ba_fac_off[3]);
+  a.nx_lin = p->nlin_blocks;
+}
+
+dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+    return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv, obs_w and prior data are required");
+  BAArgs a = base_args(p);
+  bind_ws(p, a, s->workspace, s->factor);
+  a.cams = s->poses;
+  a.pts = s->points;
+  a.obs_uv = s->obs_uv;
+  a.obs_w = s->obs_w;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.objective = s->objective;
+  a.status = s->status;
+  const int B = p->B;
+  const dim3 blk(kBT);
+  const dim3 g_lin(p->nlin_blocks, B);
+  const dim3 g_pt((max_of(p->bd, &BADesc::npt) + kBT - 1) / kBT, B);
+  const dim3 g_blk((max_of(p->bd, &BADesc::nblk) + kBT - 1) / kBT, B);
+  const int nupd = std::max(max_of(p->bd, &BADesc::npt), max_of(p->bd, &BADesc::ncam));
+  const dim3 g_upd((nupd + kBT - 1) / kBT, B);
+  const size_t lds = (size_t)p->npad_max * sizeof(double);
+  const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
+  hipLaunchKernelGGL(k_ba_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, a.status, B);
+  for (int it = 0; it <= p->opt.iterations; ++it) {
+    const bool final_lin = it == p->opt.iterations;
+    const double lam = final_lin ? 0.0 : p->opt.lambda;
+    a.it = it;
+    // the final (cached) linearisation is float64 in both precisions
+    if (mixed && !final_lin) {
+      hipLaunchKernelGGL(k_ba_lin<float>, g_lin, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_point<float>, g_pt, blk, 0, st, a, lam);
+      hipLaunchKernelGGL(k_ba_schur<float>, g_blk, blk, 0, st, a, lam);
+    } else {
+      hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, lam);
+      hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, lam);
+    }
+    hipLaunchKernelGGL(k_ba_factor, dim3(B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
+    if (!final_lin) hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
+  if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)))
+    return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv and obs_w are required");
+  BAArgs a = base_args(p);
+  bind_ws(p, a, s->workspace, const_cast<void*>(s->factor));
+  a.cams = const_cast<double*>(s->poses);
+  a.pts = const_cast<double*>(s->points);
+  a.obs_uv = s->obs_uv;
+  a.obs_w = s->obs_w;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.status = const_cast<int*>(s->status);
+  a.seed_c = s->seed_pose;
+  a.seed_p = s->seed_point;
+  a.g_w = s->grad_obs_w;
+  a.g_logw_p = s->grad_prior_logw;
+  a.adjoint_out = s->adjoint;
+  const int B = p->B;
+  const dim3 blk(kBT);
+  const dim3 g_pt((max_of(p->bd, &BADesc::npt) + kBT - 1) / kBT, B);
+  const int nobs = std::max(max_of(p->bd, &BADesc::nobs), 1);
+  const dim3 g_obs((nobs + kBT - 1) / kBT, B);
+  const size_t lds = (size_t)p->npad_max * sizeof(double);
+  hipLaunchKernelGGL(k_ba_bwd_cam, dim3(B), dim3(kNT), lds, st, a);
+  hipLaunchKernelGGL(k_ba_bwd_pt, g_pt, blk, 0, st, a);
+  hipLaunchKernelGGL(k_ba_bwd_obs, g_obs, blk, 0, st, a);
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+}  // namespace dnls

@@ -1,19 +1,26 @@
-// Workgroup-level dense linear algebra for one graph per workgroup:
-// blocked left-looking Cholesky on FP64 MFMA tiles and the two triangular
-// solves that reuse the factor.
+// Workgroup-level dense linear algebra, one graph per workgroup (256 threads):
+// blocked left-looking Cholesky on FP64 MFMA tiles and the triangular solves
+// that reuse the factor.
 //
-// Storage: the matrix is row-major with leading dimension npad (a multiple
-// of 16); only its lower triangle is read.  After chol_dense it holds the
-// factor L (lower) and `linv` holds, for every 16x16 diagonal tile j, the
-// inverse of L_jj (row-major, 256 doubles per tile).
+// Storage: row-major, leading dimension npad (a multiple of 64), only the
+// lower triangle is read.  The buffer has 16 extra rows (row tile "T16"): row
+// npad holds the right-hand side b^T, so the factorisation also produces
+// y = L^-1 b in that row (the forward substitution rides along as an
+// augmented row).  After chol_dense the lower triangle holds L, and
+// winv[J] (64 x 64 row-major per panel) holds L_JJ^-1 of every diagonal
+// 64 x 64 block.
 //
 // MFMA f64 16x16x4 operand layouts (lane l, lq = l / 16, lm = l % 16):
-//   A (16 x 4): lane supplies A[lm][k]   with k = lq
-//   B (4 x 16): lane supplies B[k][lm]   with k = lq
-//   C (16 x 16): lane holds   C[lq + 4 r][lm], r = 0..3
-// A reduction index k may be permuted freely as long as A and B agree; the
-// kernels below give lane l the four consecutive k = 4 lq + s (s = 0..3) so
-// that each lane fetches one 32-byte vector per four MFMAs.
+//   A (16 x 4): lane supplies A[lm][k]     B (4 x 16): lane supplies B[k][lm]
+//   C (16 x 16): lane holds C[lq + 4 r][lm], r = 0..3
+// Within one 16-wide k tile, MFMA number s gives lane l the index
+// k = 4 lq + s for A and B alike (a permutation of k, so the sum is
+// unchanged) and each lane fetches one 32-byte vector for four MFMAs.
+//
+// The panel update computes the transposed tile D^T = A_iJ^T - L_J L_i^T:
+// its C layout puts row lm of D in lane lm with columns lq + 4 r in the four
+// registers, which is exactly the A-operand layout needed by the triangular
+// solve D L_JJ^-T that follows -- no transpose through LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,15 +29,17 @@ namespace dnls {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-constexpr int kNT = 256;            // threads per workgroup
-constexpr int kNW = kNT / 64;       // waves per workgroup
-constexpr int kRB = 4;              // row tiles per wave and pass
-constexpr int kTS = 17;             // LDS row stride of a 16x16 tile (bank spread)
+constexpr int kNT = 256;             // threads per workgroup
+constexpr int kNW = kNT / 64;        // waves per workgroup
+constexpr int kNB = 64;              // panel width
+constexpr int kSP = 68;              // LDS row stride (doubles) of a 64-wide panel
+constexpr int kMaxDenseN = 2048;     // npad limit of the one-workgroup dense path
 
 struct DenseLds {
-  double diag[16 * kTS];
-  double inv[16 * kTS];
-  double red[16 * kTS];
+  double stage[2][kNB * kSP];        // double-buffered panel chunk L_J[0:64][k0:k0+64]
+  double W[kNB * kSP];               // L_JJ^-1 of the current panel
+  double vec[kNB];                   // broadcast vector of the solves
+  double red[kNW];
   int flag;
 };
 
@@ -38,196 +47,306 @@ __device__ __forceinline__ d4v mfma16(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Factor the 16x16 SPD tile held in lds.diag (lower part used) on one wave:
-// lane i (i < 16) owns row i.  Writes L_jj to lds.diag (full tile, upper
-// zero), L_jj^-1 to lds.inv, and returns false if a pivot is not positive.
-__device__ inline bool chol16_wave(DenseLds& s) {
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// acc += A (16x16 at a, row stride lda) * M^T (M 16x16 at m, row stride ldm)
+__device__ __forceinline__ void mma_abt(d4v& acc, const double* a, int lda, const double* m, int ldm, double sign) {
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+  const d4v av = *reinterpret_cast<const d4v*>(a + lm * lda + 4 * lq);
+  const d4v bv = *reinterpret_cast<const d4v*>(m + lm * ldm + 4 * lq);
+  acc = mfma16(sign * av[0], bv[0], acc);
+  acc = mfma16(sign * av[1], bv[1], acc);
+  acc = mfma16(sign * av[2], bv[2], acc);
+  acc = mfma16(sign * av[3], bv[3], acc);
+}
+
+// acc += A (16x16 at a, stride lda) * M (16x16 at m, stride ldm)
+__device__ __forceinline__ void mma_ab(d4v& acc, const double* a, int lda, const double* m, int ldm, double sign) {
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+  const d4v av = *reinterpret_cast<const d4v*>(a + lm * lda + 4 * lq);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma16(sign * av[s], m[(4 * lq + s) * ldm + lm], acc);
+}
+
+// C-layout accumulator -> 16x16 tile at t (stride ldt)
+__device__ __forceinline__ void store_tile(double* t, int ldt, const d4v& acc) {
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[(lq + 4 * r) * ldt + lm] = acc[r];
+}
+__device__ __forceinline__ d4v load_tile(const double* t, int ldt) {
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+  d4v acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = t[(lq + 4 * r) * ldt + lm];
+  return acc;
+}
+
+// Cholesky factor and inverse of the 16x16 SPD tile at t (stride ldt, lower
+// part read) on one wave: lane i (i = lane % 16) owns row i; broadcasts go
+// through v_readlane.  Writes L (upper part zero) back to t and L^-1 to w.
+// Returns false if a pivot is not positive (NaN included).
+__device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int ldw) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
   double a[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = s.diag[i * kTS + q];
+  for (int q = 0; q < 16; ++q) a[q] = t[i * ldt + q];
   bool ok = true;
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
-    const double piv = __shfl(a[p], p);
+    const double piv = readlane_d(a[p], p);
     ok = ok && (piv > 0.0);
     const double d = ::sqrt(piv);
-    const double lip = (i == p) ? d : (i > p ? a[p] / d : 0.0);
+    const double rd = 1.0 / d;
+    const double lip = (i > p) ? a[p] * rd : (i == p ? d : 0.0);
     a[p] = lip;
 #pragma unroll
-    for (int q = p + 1; q < 16; ++q) {
-      const double lqp = __shfl(lip, q);
-      if (i >= q) a[q] -= lip * lqp;
-    }
+    for (int q = p + 1; q < 16; ++q) a[q] = __builtin_fma(-lip, readlane_d(lip, q), a[q]);
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) a[q] = (q > i) ? 0.0 : a[q];
-  // X = L^-1 by forward substitution over rows; lane i owns row i of X
+  // X = L^-1, lane i owns row i:  X[i] = (e_i - sum_{k<i} L[i][k] X[k]) / L[i][i]
   double x[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) x[c] = (c == i) ? 1.0 : 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const double lkk = __shfl(a[k], k);
-    if (i == k) {
+    const double rkk = 1.0 / readlane_d(a[k], k);
 #pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = x[c] / lkk;
-    }
+    for (int c = 0; c <= k; ++c) x[c] = (i == k) ? x[c] * rkk : x[c];
+    const double lik = (i > k) ? a[k] : 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const double xkc = __shfl(x[c], k);
-      if (i > k) x[c] -= a[k] * xkc;
-    }
+    for (int c = 0; c <= k; ++c) x[c] = __builtin_fma(-lik, readlane_d(x[c], k), x[c]);
   }
   if (lane < 16) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      s.diag[i * kTS + q] = a[q];
-      s.inv[i * kTS + q] = x[q];
+      t[i * ldt + q] = a[q];
+      w[i * ldw + q] = x[q];
     }
   }
   return ok;
 }
 
-// In-place blocked left-looking Cholesky of the npad x npad row-major
-// matrix A.  All threads of the workgroup must call it.  Returns false
-// (uniformly) if the matrix is not numerically positive definite.
-__device__ inline bool chol_dense(double* __restrict__ A, int npad, double* __restrict__ linv, DenseLds& s) {
+// Factor the 64x64 diagonal block D (LDS, stride kSP, lower part read) in
+// place into L_JJ, and its inverse into W (stride kSP).  All threads call.
+__device__ __forceinline__ bool chol64(double* D, double* W, DenseLds& s) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  bool ok = true;
+  for (int b = 0; b < 4; ++b) {
+    double* Dbb = D + 16 * b * kSP + 16 * b;
+    if (wave == 0) {
+      const bool okb = chol16_wave(Dbb, kSP, W + 16 * b * kSP + 16 * b, kSP);
+      if (lane == 0) s.flag = okb ? 0 : 1;
+    }
+    __syncthreads();
+    if (s.flag) ok = false;
+    // L_rb = D_rb W_bb^T for r > b
+    {
+      const int r = b + 1 + wave;
+      if (r < 4) {
+        d4v acc = {0.0, 0.0, 0.0, 0.0};
+        mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, W + 16 * b * kSP + 16 * b, kSP, 1.0);
+        store_tile(D + 16 * r * kSP + 16 * b, kSP, acc);
+      }
+    }
+    __syncthreads();
+    // trailing update D_rc -= L_rb L_cb^T, b < c <= r < 4
+    {
+      int idx = 0;
+      for (int r = b + 1; r < 4; ++r)
+        for (int c = b + 1; c <= r; ++c, ++idx)
+          if ((idx & 3) == wave) {
+            d4v acc = load_tile(D + 16 * r * kSP + 16 * c, kSP);
+            mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, D + 16 * c * kSP + 16 * b, kSP, -1.0);
+            store_tile(D + 16 * r * kSP + 16 * c, kSP, acc);
+          }
+    }
+    __syncthreads();
+  }
+  // off-diagonal blocks of the inverse, by distance from the diagonal:
+  // W_rc = -W_rr sum_{k=c}^{r-1} L_rk W_kc
+  for (int dl = 1; dl < 4; ++dl) {
+    const int c = wave, r = c + dl;
+    d4v t = {0.0, 0.0, 0.0, 0.0};
+    if (r < 4)
+      for (int k = c; k < r; ++k) mma_ab(t, D + 16 * r * kSP + 16 * k, kSP, W + 16 * k * kSP + 16 * c, kSP, 1.0);
+    // stage T in the (still unused) upper triangle of D: block (c, r)
+    if (r < 4) store_tile(D + 16 * c * kSP + 16 * r, kSP, t);
+    __syncthreads();
+    if (r < 4) {
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+      mma_ab(acc, W + 16 * r * kSP + 16 * r, kSP, D + 16 * c * kSP + 16 * r, kSP, -1.0);
+      store_tile(W + 16 * r * kSP + 16 * c, kSP, acc);
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix A
+// (row npad = right-hand side): on return A holds L and y = L^-1 b in row
+// npad, winv holds the inverses of the diagonal blocks.  All threads call;
+// returns false (uniformly) if the matrix is not positive definite.
+__device__ __forceinline__ bool chol_dense(double* __restrict__ A, int npad, double* __restrict__ winv, DenseLds& s) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
-  const int T = npad >> 4;
-  for (int j = 0; j < T; ++j) {
-    // Phase A: tiles (i, j), i >= j:  A_ij -= sum_{k<j} L_ik L_jk^T
-    for (int i0 = j + wave * kRB; i0 < T; i0 += kNW * kRB) {
-      d4v acc[kRB];
+  const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
+  const int P = npad / kNB;
+  bool ok = true;
+  for (int J = 0; J < P; ++J) {
+    const int col0 = kNB * J;
+    const int nchunk = J;             // k chunks of 64 columns
+    for (int i0 = 4 * J; i0 <= T16; i0 += kNW) {
+      const int i = i0 + wave;
+      const bool active = i <= T16;
+      const double* Arow = A + (size_t)(16 * i + lm) * npad;
+      // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
+      d4v acc[4];
 #pragma unroll
-      for (int t = 0; t < kRB; ++t) {
-        const int i = i0 + t;
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc[t][r] = (i < T) ? A[(size_t)(16 * i + lq + 4 * r) * npad + 16 * j + lm] : 0.0;
-      }
-      const double* brow = A + (size_t)(16 * j + lm) * npad + 4 * lq;
-      for (int k = 0; k < j; ++k) {
-        const d4v bv = *reinterpret_cast<const d4v*>(brow + 16 * k);
+        for (int r = 0; r < 4; ++r) acc[c][r] = active ? Arow[col0 + 16 * c + lq + 4 * r] : 0.0;
+      if (nchunk > 0) {
+        // stage chunk 0 of L_J[0:64][0:64] into LDS, prefetch this wave's operands
+        d4v st[4], bop[4], bnx[4];
+        const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
 #pragma unroll
-        for (int t = 0; t < kRB; ++t) {
-          const int i = i0 + t;
-          if (i < T) {
-            const d4v av = *reinterpret_cast<const d4v*>(A + (size_t)(16 * i + lm) * npad + 16 * k + 4 * lq);
-            acc[t] = mfma16(-av[0], bv[0], acc[t]);
-            acc[t] = mfma16(-av[1], bv[1], acc[t]);
-            acc[t] = mfma16(-av[2], bv[2], acc[t]);
-            acc[t] = mfma16(-av[3], bv[3], acc[t]);
+        for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+          bop[kt] = active ? *reinterpret_cast<const d4v*>(Arow + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ++ch) {
+          const bool more = ch + 1 < nchunk;
+          if (more) {
+            const int k1 = kNB * (ch + 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + k1 + scol + 4 * q);
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt)
+              bnx[kt] = active ? *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
           }
+          const double* buf = s.stage[ch & 1];
+          if (active) {
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+              d4v aop[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
+            }
+          }
+          if (more) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<d4v*>(&s.stage[(ch + 1) & 1][srow * kSP + scol + 4 * q]) = st[q];
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) bop[kt] = bnx[kt];
+          }
+          __syncthreads();
         }
       }
+      if (i0 == 4 * J) {
+        // the diagonal block: factor in LDS
+        double* D = s.stage[0];
 #pragma unroll
-      for (int t = 0; t < kRB; ++t) {
-        const int i = i0 + t;
-        if (i == j) {
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) s.diag[(lq + 4 * r) * kTS + lm] = acc[t][r];
-        } else if (i < T) {
+          for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
+        __syncthreads();
+        if (!chol64(D, s.W, s)) ok = false;
+        // write L_JJ (zero above the diagonal) and its inverse
+        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
+          const int r = e >> 6, c = e & 63;
+          A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
+          winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+        }
+        __syncthreads();
+      } else if (active) {
+        // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
-          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + 16 * j + lm] = acc[t][r];
+        for (int cn = 0; cn < 4; ++cn) {
+          d4v out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kt = 0; kt <= cn; ++kt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
         }
       }
-    }
-    __syncthreads();
-    // Phase B: factor and invert the diagonal tile
-    if (wave == 0) {
-      const bool ok = chol16_wave(s);
-      if (lane == 0) s.flag = ok ? 0 : 1;
-      if (lane < 16) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          A[(size_t)(16 * j + lane) * npad + 16 * j + q] = s.diag[lane * kTS + q];
-          linv[j * 256 + lane * 16 + q] = s.inv[lane * kTS + q];
-        }
-      }
-    }
-    __syncthreads();
-    if (s.flag) return false;
-    // Phase C: L_ij = A_ij L_jj^-T for i > j
-    for (int i0 = j + 1 + wave * kRB; i0 < T; i0 += kNW * kRB) {
-      d4v acc[kRB];
-      double bk[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bk[q] = s.inv[lm * kTS + 4 * lq + q];
-#pragma unroll
-      for (int t = 0; t < kRB; ++t) {
-        acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
-        const int i = i0 + t;
-        if (i < T) {
-          const d4v av = *reinterpret_cast<const d4v*>(A + (size_t)(16 * i + lm) * npad + 16 * j + 4 * lq);
-          acc[t] = mfma16(av[0], bk[0], acc[t]);
-          acc[t] = mfma16(av[1], bk[1], acc[t]);
-          acc[t] = mfma16(av[2], bk[2], acc[t]);
-          acc[t] = mfma16(av[3], bk[3], acc[t]);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < kRB; ++t) {
-        const int i = i0 + t;
-        if (i < T) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + 16 * j + lm] = acc[t][r];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  return true;
-}
-
-// x <- L^-1 x  (x in LDS, length npad); all threads call.
-__device__ inline void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ linv,
-                                  double* x, DenseLds& s) {
-  const int T = npad >> 4;
-  const int r = threadIdx.x >> 4, q = threadIdx.x & 15;
-  for (int j = 0; j < T; ++j) {
-    double acc = 0.0;
-    const double* row = L + (size_t)(16 * j + r) * npad;
-    for (int c = q; c < 16 * j; c += 16) acc += row[c] * x[c];
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-    if (q == 0) s.red[r] = x[16 * j + r] - acc;
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      const double* li = linv + j * 256 + threadIdx.x * 16;
-      double y = 0.0;
-      for (int c = 0; c <= (int)threadIdx.x; ++c) y += li[c] * s.red[c];
-      x[16 * j + threadIdx.x] = y;
     }
     __syncthreads();
   }
+  return ok;
 }
 
-// x <- L^-T x  (x in LDS, length npad); all threads call.
-__device__ inline void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ linv,
+// x <- L^-T x for x in LDS (length npad): right-looking by 64-row panels,
+// each thread owns whole columns of the update (no reductions).
+__device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
                                     double* x, DenseLds& s) {
-  const int T = npad >> 4;
-  const int c = threadIdx.x & 15, q = threadIdx.x >> 4;
-  for (int j = T - 1; j >= 0; --j) {
-    double acc = 0.0;
-    for (int r = 16 * (j + 1) + q; r < npad; r += 16) acc += L[(size_t)r * npad + 16 * j + c] * x[r];
-    s.red[q * kTS + c] = acc;
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      double z = 0.0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) z += s.red[k * kTS + threadIdx.x];
-      s.diag[threadIdx.x] = x[16 * j + threadIdx.x] - z;
+  const int P = npad / kNB;
+  for (int J = P - 1; J >= 0; --J) {
+    const int r0 = kNB * J;
+    // x_J = W_JJ^T x_J:  xj[c] = sum_{r >= c} W[r][c] x[r0 + r]
+    if (threadIdx.x < kNB) {
+      const int c = threadIdx.x;
+      const double* w = winv + (size_t)J * kNB * kNB;
+      double acc = 0.0;
+      for (int r = c; r < kNB; ++r) acc += w[r * kNB + c] * x[r0 + r];
+      s.vec[c] = acc;
     }
     __syncthreads();
-    if (threadIdx.x < 16) {
-      // x_j[c] = sum_r Linv[r][c] z[r], Linv lower: r >= c
-      const double* li = linv + j * 256;
-      double y = 0.0;
-      for (int rr = threadIdx.x; rr < 16; ++rr) y += li[rr * 16 + threadIdx.x] * s.diag[rr];
-      x[16 * j + threadIdx.x] = y;
+    if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
+    // x[0:r0] -= L[r0:r0+64][0:r0]^T x_J
+    for (int c = threadIdx.x; c < r0; c += kNT) {
+      double acc = 0.0;
+#pragma unroll 16
+      for (int r = 0; r < kNB; ++r) acc += L[(size_t)(r0 + r) * npad + c] * s.vec[r];
+      x[c] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// x <- L^-1 x for x in LDS (length npad): right-looking by panels, thread per row.
+__device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
+                                  double* x, DenseLds& s) {
+  const int P = npad / kNB;
+  for (int J = 0; J < P; ++J) {
+    const int r0 = kNB * J;
+    if (threadIdx.x < kNB) {
+      const int r = threadIdx.x;
+      const double* w = winv + (size_t)J * kNB * kNB + r * kNB;
+      double acc = 0.0;
+      for (int c = 0; c <= r; ++c) acc += w[c] * x[r0 + c];
+      s.vec[r] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
+    for (int r = r0 + kNB + threadIdx.x; r < npad; r += kNT) {
+      const double* row = L + (size_t)r * npad + r0;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q) {
+        const d4v v = *reinterpret_cast<const d4v*>(row + 4 * q);
+        acc += v[0] * s.vec[4 * q] + v[1] * s.vec[4 * q + 1] + v[2] * s.vec[4 * q + 2] + v[3] * s.vec[4 * q + 3];
+      }
+      x[r] -= acc;
     }
     __syncthreads();
   }

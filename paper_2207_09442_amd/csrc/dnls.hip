@@ -20,55 +20,13 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/dnls.h"
 #include "costs.hpp"
 #include "dense.hpp"
+#include "plan.hpp"
 
 using namespace dnls;
 
-namespace {
-
-thread_local std::string g_err;
-
-dnls_status fail(dnls_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(DNLS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-  } while (0)
-
-struct GraphDesc {
-  int pose0, npose, edge0, nedge, prior0, nprior, n, npad;
-  long long fac_off;   // doubles: L (npad x npad) then L_jj^-1 tiles (npad/16 x 256)
-  int od0, nod;        // off-diagonal Hessian blocks of the graph
-};
-
-}  // namespace
-
-struct dnls_plan_s {
-  int B = 0, group = 3, d = 6, sz = 12;
-  dnls_options opt{};
-  int V = 0, E = 0, P = 0;
-  int npad_max = 0;
-  std::vector<GraphDesc> gd;
-  size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
-  size_t ws32_off = 0, ycost_off = 0;   // byte offsets inside the solve workspace
-  // device tables
-  GraphDesc* d_gd = nullptr;
-  int* d_order = nullptr;
-  int* d_edge_ij = nullptr;
-  int* d_prior_var = nullptr;
-  int* d_inc_off = nullptr;
-  int* d_inc_slot = nullptr;
-  int4* d_od_blk = nullptr;
-  int* d_od_slot = nullptr;
-  std::vector<void*> allocs;
-};
+thread_local std::string dnls::g_err;
 
 namespace {
 
@@ -166,79 +124,104 @@ __device__ double linearize_graph(const DenseArgs& a, const GraphDesc& g, S* rec
 }
 
 // Assemble the lower triangle of H (+ lambda on the diagonal, identity on the
-// padding) into A (row-major npad x npad), with products in precision S.
+// padding) into A (row-major npad x npad plus the 16-row augmented tile),
+// one thread per 6x6 (3x3) Hessian block, products accumulated in precision S.
 template <int G, class S>
 __device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec, double* A, double lambda) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
   const int npad = g.npad;
-  // zero the lower-triangular tiles
-  const int T = npad >> 4;
-  const int ntile = T * (T + 1) / 2;
-  for (int u = threadIdx.x; u < ntile * 64; u += kNT) {
-    const int tile = u >> 6, part = u & 63;
-    int i = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
-    while ((i + 1) * (i + 2) / 2 <= tile) ++i;
-    while (i * (i + 1) / 2 > tile) --i;
-    const int j = tile - i * (i + 1) / 2;
-    const int row = 16 * i + (part >> 2), col = 16 * j + 4 * (part & 3);
-    *reinterpret_cast<d4v*>(A + (size_t)row * npad + col) = d4v{0.0, 0.0, 0.0, 0.0};
+  // zero every row up to the end of its 64-wide diagonal block, and the augmented tile
+  const int q4 = npad >> 2;
+  for (int u = threadIdx.x; u < (npad + 16) * q4; u += kNT) {
+    const int r = u / q4, c = 4 * (u - r * q4);
+    if (r >= npad || c < kNB * (r / kNB + 1))
+      *reinterpret_cast<d4v*>(A + (size_t)r * npad + c) = d4v{0.0, 0.0, 0.0, 0.0};
   }
   __syncthreads();
-  // diagonal blocks
-  const int nd = g.npose * d * d;
-  for (int u = threadIdx.x; u < nd; u += kNT) {
-    const int p = u / (d * d), rc = u % (d * d), r = rc / d, c = rc % d;
-    const int gp = g.pose0 + p;
-    S acc = S(0);
-    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
-      const int slot = a.inc_slot[s];
-      const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+  for (int u = threadIdx.x; u < g.npose + g.nod; u += kNT) {
+    S h[d * d];
 #pragma unroll
-      for (int k = 0; k < d; ++k) acc += J[k * d + r] * J[k * d + c];
-    }
-    double v = double(acc);
-    if (r == c) v += lambda;
-    A[(size_t)(p * d + r) * npad + p * d + c] = v;
-  }
-  // off-diagonal blocks (row pose > column pose)
-  const int no = g.nod * d * d;
-  for (int u = threadIdx.x; u < no; u += kNT) {
-    const int b = u / (d * d), rc = u % (d * d), r = rc / d, c = rc % d;
-    const int4 blk = a.od_blk[g.od0 + b];
-    S acc = S(0);
-    for (int s = blk.z; s < blk.z + blk.w; ++s) {
-      const int slot = a.od_slot[s];
-      const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
-      const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
+    for (int q = 0; q < d * d; ++q) h[q] = S(0);
+    int rb, cb;
+    if (u < g.npose) {
+      rb = cb = u;
+      const int gp = g.pose0 + u;
+      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+        const int slot = a.inc_slot[s];
+        const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        S j[d * d];
 #pragma unroll
-      for (int k = 0; k < d; ++k) acc += Jr[k * d + r] * Jc[k * d + c];
+        for (int q = 0; q < d * d; ++q) j[q] = J[q];
+#pragma unroll
+        for (int k = 0; k < d; ++k)
+#pragma unroll
+          for (int r = 0; r < d; ++r)
+#pragma unroll
+            for (int c = 0; c < d; ++c) h[r * d + c] += j[k * d + r] * j[k * d + c];
+      }
+    } else {
+      const int4 blk = a.od_blk[g.od0 + (u - g.npose)];
+      rb = blk.x;
+      cb = blk.y;
+      for (int s = blk.z; s < blk.z + blk.w; ++s) {
+        const int slot = a.od_slot[s];
+        const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
+        S jr[d * d], jc[d * d];
+#pragma unroll
+        for (int q = 0; q < d * d; ++q) {
+          jr[q] = Jr[q];
+          jc[q] = Jc[q];
+        }
+#pragma unroll
+        for (int k = 0; k < d; ++k)
+#pragma unroll
+          for (int r = 0; r < d; ++r)
+#pragma unroll
+            for (int c = 0; c < d; ++c) h[r * d + c] += jr[k * d + r] * jc[k * d + c];
+      }
     }
-    A[(size_t)(blk.x * d + r) * npad + blk.y * d + c] = double(acc);
+#pragma unroll
+    for (int r = 0; r < d; ++r)
+#pragma unroll
+      for (int c = 0; c < d; ++c)
+        A[(size_t)(rb * d + r) * npad + cb * d + c] = double(h[r * d + c]) + ((rb == cb && r == c) ? lambda : 0.0);
   }
   for (int r = g.n + threadIdx.x; r < npad; r += kNT) A[(size_t)r * npad + r] = 1.0;
   __syncthreads();
 }
 
-// b[p*d + r] = sum over incident costs of J^T (w c)   (zero on the padding)
+// b[p*d + r] = sum over incident costs of J^T (w c), zero on the padding;
+// with aug != nullptr also written to the augmented row of the matrix.
 template <int G, class S>
-__device__ void assemble_g(const DenseArgs& a, const GraphDesc& g, const S* rec, double* b) {
+__device__ void assemble_g(const DenseArgs& a, const GraphDesc& g, const S* rec, double* b, double* aug) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
-  for (int u = threadIdx.x; u < g.npad; u += kNT) {
-    double v = 0.0;
-    if (u < g.n) {
-      const int p = u / d, r = u % d, gp = g.pose0 + p;
-      S acc = S(0);
-      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
-        const int slot = a.inc_slot[s];
-        const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
-        const S* res = rec + (size_t)(slot >> 1) * RN + 2 * d * d;
+  for (int p = threadIdx.x; p < g.npose; p += kNT) {
+    const int gp = g.pose0 + p;
+    S h[d];
 #pragma unroll
-        for (int k = 0; k < d; ++k) acc += J[k * d + r] * res[k];
-      }
-      v = double(acc);
+    for (int r = 0; r < d; ++r) h[r] = S(0);
+    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+      const int slot = a.inc_slot[s];
+      const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+      const S* res = rec + (size_t)(slot >> 1) * RN + 2 * d * d;
+      S j[d * d], rr[d];
+#pragma unroll
+      for (int q = 0; q < d * d; ++q) j[q] = J[q];
+#pragma unroll
+      for (int q = 0; q < d; ++q) rr[q] = res[q];
+#pragma unroll
+      for (int k = 0; k < d; ++k)
+#pragma unroll
+        for (int r = 0; r < d; ++r) h[r] += j[k * d + r] * rr[k];
     }
-    b[u] = v;
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      b[p * d + r] = double(h[r]);
+      if (aug) aug[p * d + r] = double(h[r]);
+    }
   }
+  for (int u = g.n + threadIdx.x; u < g.npad; u += kNT) b[u] = 0.0;
   __syncthreads();
 }
 
@@ -311,10 +294,10 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   const int b = a.order[blockIdx.x];
   const GraphDesc g = a.gd[b];
   double* A = a.factor + g.fac_off;
-  double* linv = A + (size_t)g.npad * g.npad;
-  double* vb = dyn;                // right-hand side / step
-  double* vx = dyn + g.npad;       // refinement residual
-  double* vy = dyn + 2 * g.npad;   // matrix-free product
+  double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  double* vb = dyn;                // step
+  double* vx = dyn + g.npad;       // refinement residual / matrix-free product
+  double* vy = dyn + 2 * g.npad;   // right-hand side g
   int status = DNLS_GRAPH_OK;
   double last_obj = 0.0;
   int last_it = 0;
@@ -338,36 +321,34 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     if (final_lin) {
       // undamped factor of H* for the backward, assembled in float64
       assemble_H<G, double>(a, g, a.ws64, A, 0.0);
-      if (!chol_dense(A, g.npad, linv, L.dl)) status = DNLS_GRAPH_NOT_PD;
+      if (!chol_dense(A, g.npad, winv, L.dl)) status = DNLS_GRAPH_NOT_PD;
       break;
     }
+    double* aug = A + (size_t)g.npad * g.npad;   // right-hand side row of the factorisation
     if (MIXED) {
       assemble_H<G, float>(a, g, a.ws32, A, lam);
-      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vb);
-      else assemble_g<G, float>(a, g, a.ws32, vb);
+      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vy, aug);
+      else assemble_g<G, float>(a, g, a.ws32, vy, aug);
     } else {
       assemble_H<G, double>(a, g, a.ws64, A, lam);
-      assemble_g<G, double>(a, g, a.ws64, vb);
+      assemble_g<G, double>(a, g, a.ws64, vy, aug);
     }
-    if (!chol_dense(A, g.npad, linv, L.dl)) {
+    if (!chol_dense(A, g.npad, winv, L.dl)) {
       status = DNLS_GRAPH_NOT_PD;
       break;
     }
-    if (MIXED && a.refine > 0) {
-      // keep the right-hand side: vy = g64
-      for (int u = threadIdx.x; u < g.npad; u += kNT) vy[u] = vb[u];
-      __syncthreads();
-    }
-    trsv_lower(A, g.npad, linv, vb, L.dl);
-    trsv_upper_t(A, g.npad, linv, vb, L.dl);
+    // delta = L^-T y with y = L^-1 g from the augmented row
+    for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
+    __syncthreads();
+    trsv_upper_t(A, g.npad, winv, vb, L.dl);
     if (MIXED) {
       for (int sweep = 0; sweep < a.refine; ++sweep) {
         // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
         matvec_H<G>(a, g, a.ws64, vb, vx, lam);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
         __syncthreads();
-        trsv_lower(A, g.npad, linv, vx, L.dl);
-        trsv_upper_t(A, g.npad, linv, vx, L.dl);
+        trsv_lower(A, g.npad, winv, vx, L.dl);
+        trsv_upper_t(A, g.npad, winv, vx, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
@@ -409,14 +390,14 @@ __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
     return;
   }
   const double* A = a.factor + g.fac_off;
-  const double* linv = A + (size_t)g.npad * g.npad;
+  const double* winv = A + (size_t)(g.npad + 16) * g.npad;
   double* vu = dyn;
   for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
   __syncthreads();
   // float64 linearisation at theta_K: residuals and Jacobians for the VJP
   linearize_graph<G, double>(a, g, a.ws64, L.red);
-  trsv_lower(A, g.npad, linv, vu, L.dl);
-  trsv_upper_t(A, g.npad, linv, vu, L.dl);
+  trsv_lower(A, g.npad, winv, vu, L.dl);
+  trsv_upper_t(A, g.npad, winv, vu, L.dl);
   if (a.adjoint_out)
     for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
   // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
@@ -524,16 +505,6 @@ __global__ void k_project(long long n, const double* X, const double* Gr, double
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-template <class T>
-dnls_status upload(dnls_plan p, T** dst, const std::vector<T>& v) {
-  *dst = nullptr;
-  if (v.empty()) return DNLS_OK;
-  HIP_TRY(hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)));
-  p->allocs.push_back(*dst);
-  HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return DNLS_OK;
-}
-
 bool check_off(const int32_t* off, int B, int total_hint, int* total) {
   if (!off || off[0] != 0) return false;
   for (int b = 0; b < B; ++b)
@@ -542,8 +513,6 @@ bool check_off(const int32_t* off, int B, int total_hint, int* total) {
   (void)total_hint;
   return true;
 }
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <int G, bool MIXED>
 dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
@@ -583,8 +552,24 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->precision != DNLS_PREC_FP64 && op->precision != DNLS_PREC_MIXED)
     return fail(DNLS_ERR_INVALID_ARG, "unknown precision");
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
+  if (op->solver == DNLS_SOLVER_SCHUR) {
+    auto* p = new dnls_plan_s();
+    p->B = pr->batch;
+    p->group = pr->group;
+    p->d = 6;
+    p->sz = 12;
+    p->opt = *op;
+    const dnls_status st = ba_plan_create(p, pr, op);
+    if (st != DNLS_OK) {
+      const std::string msg = g_err;
+      dnls_plan_destroy(p);
+      return fail(st, msg);
+    }
+    *out = p;
+    return DNLS_OK;
+  }
   if (op->solver != DNLS_SOLVER_DENSE)
-    return fail(DNLS_ERR_UNSUPPORTED, "this entry point handles the DENSE solver");
+    return fail(DNLS_ERR_UNSUPPORTED, "solver not available in this build");
   const int B = pr->batch;
   int V = 0, E = 0, P = 0;
   if (!check_off(pr->pose_off, B, 0, &V) || !check_off(pr->edge_off, B, 0, &E) ||
@@ -620,13 +605,15 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     g.prior0 = pr->prior_off[b];
     g.nprior = pr->prior_off[b + 1] - g.prior0;
     g.n = g.npose * d;
-    g.npad = std::max(16, (g.n + 15) / 16 * 16);
-    if (g.npad > 4096) {
+    g.npad = std::max(kNB, (g.n + kNB - 1) / kNB * kNB);
+    if (g.npad > kMaxDenseN) {
       delete p;
-      return fail(DNLS_ERR_UNSUPPORTED, "dense solver supports at most 4096 unknowns per graph");
+      return fail(DNLS_ERR_UNSUPPORTED, "dense solver supports at most " + std::to_string(kMaxDenseN) +
+                                            " unknowns per graph");
     }
     g.fac_off = fac;
-    fac += (long long)g.npad * g.npad + (long long)(g.npad / 16) * 256;
+    // L (npad x npad) + augmented right-hand-side tile (16 x npad) + panel inverses
+    fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
     fac = (fac + 31) / 32 * 32;
     p->npad_max = std::max(p->npad_max, g.npad);
     std::map<std::pair<int, int>, std::vector<int>> blocks;
@@ -727,6 +714,9 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
   if (!s->poses || !s->objective || !s->status || !s->factor || !s->workspace)
     return fail(DNLS_ERR_INVALID_ARG, "poses, objective, status, factor and workspace are required");
+  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
+    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_solve(p, s, static_cast<hipStream_t>(stream));
   if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
     return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
@@ -756,6 +746,9 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
   if (!s->poses || !s->status || !s->factor || !s->workspace || !s->seed_pose)
     return fail(DNLS_ERR_INVALID_ARG, "poses, status, factor, seed_pose and workspace are required");
+  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
+    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_backward(p, s, static_cast<hipStream_t>(stream));
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   DenseArgs a = base_args(p);

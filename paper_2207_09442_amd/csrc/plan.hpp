@@ -1,0 +1,102 @@
+// Internal declarations shared by the translation units of the library: the
+// plan object behind the opaque dnls_plan handle, error reporting, and the
+// entry points of the bundle-adjustment (Schur) path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dnls.h"
+
+namespace dnls {
+
+extern thread_local std::string g_err;
+
+inline dnls_status fail(dnls_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::dnls::fail(DNLS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// one pose graph of the dense path
+struct GraphDesc {
+  int pose0, npose, edge0, nedge, prior0, nprior, n, npad;
+  long long fac_off;   // doubles: L ((npad + 16) x npad) then the 64x64 panel inverses
+  int od0, nod;        // off-diagonal Hessian blocks of the graph
+};
+
+// one bundle-adjustment problem of the Schur path
+struct BADesc {
+  int cam0, ncam, pt0, npt, obs0, nobs, prior0, nprior, n, npad;
+  long long fac_off;   // doubles: Schur factor ((npad + 16) x npad) then panel inverses
+  int blk0, nblk;      // camera-pair blocks of the Schur complement (lower, all)
+  int lin_blk0, nlin_blk;   // linearisation thread blocks of this problem
+};
+
+}  // namespace dnls
+
+struct dnls_plan_s {
+  int B = 0, group = 3, d = 6, sz = 12;
+  dnls_options opt{};
+  int V = 0, E = 0, P = 0;
+  int npad_max = 0;
+  std::vector<dnls::GraphDesc> gd;
+  size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
+  size_t ws32_off = 0, ycost_off = 0;   // byte offsets inside the solve workspace
+  // device tables of the dense path
+  dnls::GraphDesc* d_gd = nullptr;
+  int* d_order = nullptr;
+  int* d_edge_ij = nullptr;
+  int* d_prior_var = nullptr;
+  int* d_inc_off = nullptr;
+  int* d_inc_slot = nullptr;
+  int4* d_od_blk = nullptr;
+  int* d_od_slot = nullptr;
+  // bundle adjustment (solver SCHUR)
+  int Vp = 0, O = 0;
+  double intr[4] = {0, 0, 0, 0};
+  double huber = 0.0;
+  std::vector<dnls::BADesc> bd;
+  int nlin_blocks = 0;
+  dnls::BADesc* d_bd = nullptr;
+  int* d_lin_prob = nullptr;      // problem of each linearisation thread block
+  int* d_obs_cam = nullptr;
+  int* d_obs_pt = nullptr;
+  int* d_cam_obs_off = nullptr;   // per camera: observations, then priors
+  int* d_cam_obs = nullptr;
+  int* d_pt_obs_off = nullptr;
+  int* d_pt_obs = nullptr;
+  int4* d_sblk = nullptr;         // (row cam, col cam, start, count) per Schur block
+  int2* d_spair = nullptr;        // (obs a, obs b) contributions
+  size_t ba_off[16] = {0};        // byte offsets of the BA workspace regions
+  size_t ba_fac_off[4] = {0};     // byte offsets of the BA backward cache inside the factor
+  std::vector<void*> allocs;
+};
+
+namespace dnls {
+
+template <class T>
+dnls_status upload(dnls_plan p, T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return DNLS_OK;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T)));
+  p->allocs.push_back(*dst);
+  HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DNLS_OK;
+}
+
+dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_options* op);
+dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st);
+dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st);
+
+}  // namespace dnls

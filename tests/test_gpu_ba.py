@@ -1,0 +1,99 @@
+"""GPU parity of the bundle-adjustment (Schur) path against the CPU oracle.
+
+FP64 path: cameras, points, objective and gradients within 1e-10 relative
+per problem.  Mixed path (float32 Jacobians and assembly, float64 Schur
+complement and factor, float64 final linearisation): 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lie
+from oracle import solve as S
+
+from gpu_util import rel, t
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(5)
+
+
+def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True):
+    from paper_2207_09442_amd import Plan
+    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device)
+    cams, pts = t(p["poses_init"]), t(p["points_init"])
+    dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]))
+    objective, status = plan.solve_ba(cams, pts, **dev)
+    torch.cuda.synchronize()
+    B = len(p["pose_off"]) - 1
+    problems = list(range(B)) if problems is None else problems
+    gs = S.graphs_of(p)
+    st = status.cpu().numpy()
+    got_c, got_p, obj = cams.cpu().numpy(), pts.cpu().numpy(), objective.cpu().numpy()
+    seed_c = np.zeros((p["pose_off"][-1], 6))
+    seed_p = np.zeros((p["point_off"][-1], 3))
+    worst = dict(cam=0.0, pt=0.0, obj=0.0, grad=0.0)
+    res = {}
+    for b in problems:
+        r = S.solve_graph(gs[b], K, lam)
+        res[b] = r
+        assert st[b] == r.status
+        c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
+        q0, q1 = p["point_off"][b], p["point_off"][b + 1]
+        worst["cam"] = max(worst["cam"], rel(got_c[c0:c1], lie.SE3.to_storage(r.X).numpy()))
+        worst["pt"] = max(worst["pt"], rel(got_p[q0:q1], r.pts.numpy()))
+        worst["obj"] = max(worst["obj"], rel(obj[b], r.objective))
+        # seed: camera pose error (outer loss of the workload) plus a random point seed
+        _, v = S.pose_error_loss_and_seed("SE3", lie.SE3.to_storage(r.X).numpy(), p["poses_gt"][c0:c1])
+        seed_c[c0:c1] = v
+        if seed_points:
+            seed_p[q0:q1] = rng.normal(size=(q1 - q0, 3))
+    gr = plan.backward_ba(cams, pts, status=status, seed_cam=t(seed_c), seed_pt=t(seed_p), **dev)
+    torch.cuda.synchronize()
+    gw, gl = gr["obs_w"].cpu().numpy(), gr["prior_logw"].cpu().numpy()
+    for b in problems:
+        c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
+        q0, q1 = p["point_off"][b], p["point_off"][b + 1]
+        o0, o1 = p["obs_off"][b], p["obs_off"][b + 1]
+        r0, r1 = p["prior_off"][b], p["prior_off"][b + 1]
+        ref = S.implicit_grad_graph(gs[b], res[b], torch.as_tensor(seed_c[c0:c1]), torch.as_tensor(seed_p[q0:q1]))
+        mine = np.concatenate([gw[o0:o1], gl[r0:r1]])
+        theirs = np.concatenate([ref["obs_w"].detach().numpy(), ref["prior_logw"].detach().numpy()])
+        worst["grad"] = max(worst["grad"], rel(mine, theirs))
+    print(f"\n[ba {precision}] " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
+    for k in ["cam", "pt", "grad"]:
+        assert worst[k] < tol, (k, worst[k])
+    assert worst["obj"] < max(tol, 1e-12) * (1e3 if precision == "mixed" else 1)
+    return worst
+
+
+def test_ba_small_fp64():
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=60, obs_per_point=4, seed=1)
+    p["obs_w"] = np.exp(rng.normal(scale=0.2, size=len(p["obs_w"])))
+    _run(p, 5, 1e-3)
+
+
+def test_ba_uneven_problems_fp64():
+    """Two problems of different camera counts (ragged camera systems, padding)."""
+    a = synth.bundle_adjustment(batch=1, n_cams=9, n_points=50, obs_per_point=4, seed=2)
+    b = synth.bundle_adjustment(batch=1, n_cams=14, n_points=70, obs_per_point=5, seed=3)
+    p = {}
+    for k in a:
+        if k in ("group", "intrinsics", "huber_delta"):
+            p[k] = a[k]
+        elif k.endswith("_off"):
+            p[k] = np.concatenate([a[k], a[k][-1] + b[k][1:]]).astype(np.int32)
+        elif k in ("obs_cam", "prior_var"):
+            p[k] = np.concatenate([a[k], b[k] + a["pose_off"][-1]]).astype(np.int32)
+        elif k == "obs_pt":
+            p[k] = np.concatenate([a[k], b[k] + a["point_off"][-1]]).astype(np.int32)
+        else:
+            p[k] = np.concatenate([a[k], b[k]])
+    _run(p, 4, 1e-3)
+
+
+def test_ba_ring64_full_size_fp64_and_mixed():
+    """4 problems x (64 cameras, 2048 points, 16384 observations), 10 LM steps."""
+    p = synth.bundle_adjustment(batch=4)
+    _run(p, 10, 1e-3, problems=[0, 3])
+    _run(p, 10, 1e-3, precision="mixed", problems=[0, 3], tol=1e-5)

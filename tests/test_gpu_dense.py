@@ -24,10 +24,10 @@ pytestmark = pytest.mark.gpu
 rng = np.random.default_rng(77)
 
 
-def _seeds(p, poses_ref_by_graph):
+def _seeds(p, poses_ref_by_graph, graphs):
     """Loss L = sum ||Log(X_gt^-1 X)||^2 and its tangent seed per graph."""
     seeds = []
-    for b, X in enumerate(poses_ref_by_graph):
+    for b, X in zip(graphs, poses_ref_by_graph):
         lo, hi = int(p["pose_off"][b]), int(p["pose_off"][b + 1])
         _, v = S.pose_error_loss_and_seed(p["group"], X, p["poses_gt"][lo:hi])
         seeds.append(v)
@@ -52,7 +52,7 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
         worst_pose = max(worst_pose, rel(got[lo:hi], ref_poses[gi]))
         worst_obj = max(worst_obj, rel(obj[b], res[gi].objective))
     # backward with the seed of the oracle's solution (same v on both sides)
-    seeds = _seeds(p, ref_poses)
+    seeds = _seeds(p, ref_poses, graphs)
     full_seed = np.zeros((p["pose_off"][-1], G.dof))
     for gi, b in enumerate(graphs):
         full_seed[p["pose_off"][b]:p["pose_off"][b + 1]] = seeds[gi]
@@ -217,3 +217,14 @@ def test_autograd_layer_end_to_end():
     ref_tau = np.concatenate([o["tau"] for o in ref])
     assert rel(logw.grad.cpu().numpy(), ref_logw) < 1e-9
     assert rel(tau.grad.cpu().numpy(), ref_tau) < 1e-9
+
+
+def test_uneven_b256_sampled_graphs():
+    """256 graphs with N uniform in [32, 256] in one launch (largest first),
+    10 Gauss-Newton steps; the smallest, the largest and two other graphs
+    are checked against the oracle in both precisions."""
+    p = synth.uneven_walk_se3(batch=256)
+    sizes = np.diff(p["pose_off"])
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 200})
+    _compare(p, 10, 0.0, graphs=pick)
+    _compare(p, 10, 0.0, precision="mixed", refine=1, graphs=pick, tol_pose=1e-5, tol_grad=1e-5)
