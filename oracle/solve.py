@@ -169,6 +169,32 @@ def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_
     return Lin(S=S, H=H, g=gvec, extra=k)
 
 
+def linearize_pose_graph_sparse(g: Graph, X: torch.Tensor):
+    """Same normal equations as linearize_pose_graph, as a scipy CSR matrix
+    (for graphs too large for a dense matrix); returns (S, H, g)."""
+    import scipy.sparse as sp
+    d, N = g.G.dof, X.shape[0]
+    k = pose_costs(g, X)
+    w2e = (k["w_e"] ** 2)[:, None, None]
+    w2p = (k["w_p"] ** 2)[:, None, None]
+    Ci, Cj, Cp = k["Ci"], k["Cj"], k["Cp"]
+    tr = lambda A: A.transpose(-1, -2)
+    rows = torch.cat([g.ei, g.ej, g.ei, g.ej, g.pv]).numpy()
+    cols = torch.cat([g.ei, g.ej, g.ej, g.ei, g.pv]).numpy()
+    blocks = torch.cat([w2e * tr(Ci) @ Ci, w2e * tr(Cj) @ Cj, w2e * tr(Ci) @ Cj,
+                        w2e * tr(Cj) @ Ci, w2p * tr(Cp) @ Cp]).numpy()
+    rr = (rows[:, None, None] * d + np.arange(d)[None, :, None]) + 0 * np.arange(d)[None, None, :]
+    cc = (cols[:, None, None] * d + np.arange(d)[None, None, :]) + 0 * np.arange(d)[None, :, None]
+    H = sp.coo_matrix((blocks.ravel(), (rr.ravel(), cc.ravel())), shape=(N * d, N * d)).tocsr()
+    ge_i = (w2e * tr(Ci) @ k["c_e"][..., None])[..., 0]
+    ge_j = (w2e * tr(Cj) @ k["c_e"][..., None])[..., 0]
+    gp = (w2p * tr(Cp) @ k["c_p"][..., None])[..., 0]
+    gvec = _scatter_vec(N, d, torch.cat([g.ei, g.ej, g.pv]), torch.cat([ge_i, ge_j, gp]))
+    S = 0.5 * ((k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)).sum() + \
+        0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+    return float(S), H, gvec.numpy()
+
+
 def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None):
     w_o = g.w_o if w_o is None else w_o
     logw_p = g.logw_p if logw_p is None else logw_p

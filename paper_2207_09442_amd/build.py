@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libdnls.so")
-SOURCES = [os.path.join(HERE, "csrc", "dnls.hip"), os.path.join(HERE, "csrc", "ba.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("dnls.hip", "ba.hip", "sparse.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

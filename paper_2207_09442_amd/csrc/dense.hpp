@@ -86,27 +86,54 @@ __device__ __forceinline__ d4v load_tile(const double* t, int ldt) {
   return acc;
 }
 
+// Broadcast of lane q of each 16-lane row to the whole row (DPP row_newbcast).
+__device__ __forceinline__ int bcast16_i(int v, int q) {
+  switch (q) {
+    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x151, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x152, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, v, 0x153, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x154, 0xf, 0xf, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, v, 0x155, 0xf, 0xf, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, v, 0x156, 0xf, 0xf, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, v, 0x157, 0xf, 0xf, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x158, 0xf, 0xf, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, v, 0x159, 0xf, 0xf, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, v, 0x15a, 0xf, 0xf, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, v, 0x15b, 0xf, 0xf, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, v, 0x15c, 0xf, 0xf, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, v, 0x15d, 0xf, 0xf, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, v, 0x15e, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0x15f, 0xf, 0xf, false);
+  }
+}
+__device__ __forceinline__ double bcast16(double v, int q) {
+  return __hiloint2double(bcast16_i(__double2hiint(v), q), bcast16_i(__double2loint(v), q));
+}
+
 // Cholesky factor and inverse of the 16x16 SPD tile at t (stride ldt, lower
-// part read) on one wave: lane i (i = lane % 16) owns row i; broadcasts go
-// through v_readlane.  Writes L (upper part zero) back to t and L^-1 to w.
-// Returns false if a pivot is not positive (NaN included).
+// part read) on one wave: lane i (i = lane % 16) owns row i; the column
+// values each step needs are broadcast within the 16-lane row by DPP, and
+// 1/L_kk from the factorisation is reused by the inverse.  Writes L (upper
+// part zero) back to t and L^-1 to w.  Returns false if a pivot is not
+// positive (NaN included).
 __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int ldw) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
-  double a[16];
+  double a[16], rdv[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) a[q] = t[i * ldt + q];
   bool ok = true;
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
-    const double piv = readlane_d(a[p], p);
+    const double piv = bcast16(a[p], p);
     ok = ok && (piv > 0.0);
-    const double d = ::sqrt(piv);
-    const double rd = 1.0 / d;
-    const double lip = (i > p) ? a[p] * rd : (i == p ? d : 0.0);
+    const double rd = rsqrt(piv);            // 1 / L_pp
+    rdv[p] = rd;
+    const double lip = (i > p) ? a[p] * rd : (i == p ? piv * rd : 0.0);
     a[p] = lip;
 #pragma unroll
-    for (int q = p + 1; q < 16; ++q) a[q] = __builtin_fma(-lip, readlane_d(lip, q), a[q]);
+    for (int q = p + 1; q < 16; ++q) a[q] = __builtin_fma(-lip, bcast16(lip, q), a[q]);
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) a[q] = (q > i) ? 0.0 : a[q];
@@ -116,12 +143,11 @@ __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int l
   for (int c = 0; c < 16; ++c) x[c] = (c == i) ? 1.0 : 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const double rkk = 1.0 / readlane_d(a[k], k);
 #pragma unroll
-    for (int c = 0; c <= k; ++c) x[c] = (i == k) ? x[c] * rkk : x[c];
+    for (int c = 0; c <= k; ++c) x[c] = (i == k) ? x[c] * rdv[k] : x[c];
     const double lik = (i > k) ? a[k] : 0.0;
 #pragma unroll
-    for (int c = 0; c <= k; ++c) x[c] = __builtin_fma(-lik, readlane_d(x[c], k), x[c]);
+    for (int c = 0; c <= k; ++c) x[c] = __builtin_fma(-lik, bcast16(x[c], k), x[c]);
   }
   if (lane < 16) {
 #pragma unroll
@@ -133,13 +159,16 @@ __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int l
   return ok;
 }
 
-// Factor the 64x64 diagonal block D (LDS, stride kSP, lower part read) in
-// place into L_JJ, and its inverse into W (stride kSP).  All threads call.
-__device__ __forceinline__ bool chol64(double* D, double* W, DenseLds& s) {
+// Factor the (16 NBLK)^2 diagonal block D (LDS, stride kSP, lower part read)
+// in place into L_JJ, and its inverse into W (stride kSP).  All threads of a
+// workgroup of at least NBLK waves call.
+template <int NBLK>
+__device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
   bool ok = true;
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < NBLK; ++b) {
     double* Dbb = D + 16 * b * kSP + 16 * b;
     if (wave == 0) {
       const bool okb = chol16_wave(Dbb, kSP, W + 16 * b * kSP + 16 * b, kSP);
@@ -150,7 +179,7 @@ __device__ __forceinline__ bool chol64(double* D, double* W, DenseLds& s) {
     // L_rb = D_rb W_bb^T for r > b
     {
       const int r = b + 1 + wave;
-      if (r < 4) {
+      if (r < NBLK) {
         d4v acc = {0.0, 0.0, 0.0, 0.0};
         mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, W + 16 * b * kSP + 16 * b, kSP, 1.0);
         store_tile(D + 16 * r * kSP + 16 * b, kSP, acc);
@@ -160,9 +189,9 @@ __device__ __forceinline__ bool chol64(double* D, double* W, DenseLds& s) {
     // trailing update D_rc -= L_rb L_cb^T, b < c <= r < 4
     {
       int idx = 0;
-      for (int r = b + 1; r < 4; ++r)
+      for (int r = b + 1; r < NBLK; ++r)
         for (int c = b + 1; c <= r; ++c, ++idx)
-          if ((idx & 3) == wave) {
+          if ((idx % nw) == wave) {
             d4v acc = load_tile(D + 16 * r * kSP + 16 * c, kSP);
             mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, D + 16 * c * kSP + 16 * b, kSP, -1.0);
             store_tile(D + 16 * r * kSP + 16 * c, kSP, acc);
@@ -172,15 +201,15 @@ __device__ __forceinline__ bool chol64(double* D, double* W, DenseLds& s) {
   }
   // off-diagonal blocks of the inverse, by distance from the diagonal:
   // W_rc = -W_rr sum_{k=c}^{r-1} L_rk W_kc
-  for (int dl = 1; dl < 4; ++dl) {
+  for (int dl = 1; dl < NBLK; ++dl) {
     const int c = wave, r = c + dl;
     d4v t = {0.0, 0.0, 0.0, 0.0};
-    if (r < 4)
+    if (r < NBLK)
       for (int k = c; k < r; ++k) mma_ab(t, D + 16 * r * kSP + 16 * k, kSP, W + 16 * k * kSP + 16 * c, kSP, 1.0);
     // stage T in the (still unused) upper triangle of D: block (c, r)
-    if (r < 4) store_tile(D + 16 * c * kSP + 16 * r, kSP, t);
+    if (r < NBLK) store_tile(D + 16 * c * kSP + 16 * r, kSP, t);
     __syncthreads();
-    if (r < 4) {
+    if (r < NBLK) {
       d4v acc = {0.0, 0.0, 0.0, 0.0};
       mma_ab(acc, W + 16 * r * kSP + 16 * r, kSP, D + 16 * c * kSP + 16 * r, kSP, -1.0);
       store_tile(W + 16 * r * kSP + 16 * c, kSP, acc);
@@ -267,7 +296,7 @@ __device__ __forceinline__ bool chol_dense(double* __restrict__ A, int npad, dou
 #pragma unroll
           for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
         __syncthreads();
-        if (!chol64(D, s.W, s)) ok = false;
+        if (!chol_block<4>(D, s.W, s)) ok = false;
         // write L_JJ (zero above the diagonal) and its inverse
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
@@ -295,28 +324,59 @@ __device__ __forceinline__ bool chol_dense(double* __restrict__ A, int npad, dou
   return ok;
 }
 
+// v[0:64] <- W v (lower = true) or W^T v (lower = false) for the 64x64
+// lower-triangular panel inverse W (global, row-major); all threads call,
+// 4 partial sums per output reduced through LDS.
+__device__ __forceinline__ void panel_inv_matvec(const double* __restrict__ W, const double* v, double* out,
+                                                 bool lower, DenseLds& s) {
+  const int c = threadIdx.x & 63, part = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (lower) {
+    // out[c] = sum_{k <= c} W[c][k] v[k], k in this part's 16 columns
+    const d4v* row = reinterpret_cast<const d4v*>(W + c * kNB + 16 * part);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const d4v w = row[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 16 * part + 4 * q + e;
+        acc += (k <= c) ? w[e] * v[k] : 0.0;
+      }
+    }
+  } else {
+    // out[c] = sum_{r >= c} W[r][c] v[r], r in this part's 16 rows
+    double w[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q] = W[(16 * part + q) * kNB + c];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 16 * part + q;
+      acc += (r >= c) ? w[q] * v[r] : 0.0;
+    }
+  }
+  s.W[part * kNB + c] = acc;
+  __syncthreads();
+  if (threadIdx.x < kNB) out[c] = s.W[c] + s.W[kNB + c] + s.W[2 * kNB + c] + s.W[3 * kNB + c];
+  __syncthreads();
+}
+
 // x <- L^-T x for x in LDS (length npad): right-looking by 64-row panels,
 // each thread owns whole columns of the update (no reductions).
 __device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
-                                    double* x, DenseLds& s) {
+                                             double* x, DenseLds& s) {
   const int P = npad / kNB;
   for (int J = P - 1; J >= 0; --J) {
     const int r0 = kNB * J;
-    // x_J = W_JJ^T x_J:  xj[c] = sum_{r >= c} W[r][c] x[r0 + r]
-    if (threadIdx.x < kNB) {
-      const int c = threadIdx.x;
-      const double* w = winv + (size_t)J * kNB * kNB;
-      double acc = 0.0;
-      for (int r = c; r < kNB; ++r) acc += w[r * kNB + c] * x[r0 + r];
-      s.vec[c] = acc;
-    }
-    __syncthreads();
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, false, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
     // x[0:r0] -= L[r0:r0+64][0:r0]^T x_J
     for (int c = threadIdx.x; c < r0; c += kNT) {
+      double l[kNB];
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) l[r] = L[(size_t)(r0 + r) * npad + c];
       double acc = 0.0;
-#pragma unroll 16
-      for (int r = 0; r < kNB; ++r) acc += L[(size_t)(r0 + r) * npad + c] * s.vec[r];
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) acc += l[r] * s.vec[r];
       x[c] -= acc;
     }
     __syncthreads();
@@ -325,27 +385,21 @@ __device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int n
 
 // x <- L^-1 x for x in LDS (length npad): right-looking by panels, thread per row.
 __device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
-                                  double* x, DenseLds& s) {
+                                           double* x, DenseLds& s) {
   const int P = npad / kNB;
   for (int J = 0; J < P; ++J) {
     const int r0 = kNB * J;
-    if (threadIdx.x < kNB) {
-      const int r = threadIdx.x;
-      const double* w = winv + (size_t)J * kNB * kNB + r * kNB;
-      double acc = 0.0;
-      for (int c = 0; c <= r; ++c) acc += w[c] * x[r0 + c];
-      s.vec[r] = acc;
-    }
-    __syncthreads();
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, true, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
     for (int r = r0 + kNB + threadIdx.x; r < npad; r += kNT) {
-      const double* row = L + (size_t)r * npad + r0;
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0);
+      d4v v[kNB / 4];
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
       double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < kNB / 4; ++q) {
-        const d4v v = *reinterpret_cast<const d4v*>(row + 4 * q);
-        acc += v[0] * s.vec[4 * q] + v[1] * s.vec[4 * q + 1] + v[2] * s.vec[4 * q + 2] + v[3] * s.vec[4 * q + 3];
-      }
+      for (int q = 0; q < kNB / 4; ++q)
+        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
       x[r] -= acc;
     }
     __syncthreads();

@@ -23,6 +23,7 @@
 #include "costs.hpp"
 #include "dense.hpp"
 #include "plan.hpp"
+#include "pose_costs.hpp"
 
 using namespace dnls;
 
@@ -79,46 +80,22 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Linearise every cost of graph gdesc in precision S into `rec`; returns the
+__device__ __forceinline__ PoseCostData cost_data(const DenseArgs& a) {
+  return PoseCostData{a.edge_ij, a.prior_var, a.poses, a.edge_meas, a.edge_logw,
+                      a.edge_tau, a.prior_meas, a.prior_logw, a.E};
+}
+
+// Linearise every cost of graph g in precision S into `rec`; returns the
 // objective 1/2 sum ||w c||^2 (block-reduced).
 template <int G, class S>
 __device__ double linearize_graph(const DenseArgs& a, const GraphDesc& g, S* rec, double* red) {
-  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz, RN = CostRec<d>::n;
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const PoseCostData cd = cost_data(a);
   double sacc = 0.0;
   const int ncost = g.nedge + g.nprior;
   for (int k = threadIdx.x; k < ncost; k += kNT) {
-    S c[d], Ci[d * d], Cj[d * d];
-    double w;
-    S* out;
-    if (k < g.nedge) {
-      const int e = g.edge0 + k;
-      const int i = a.edge_ij[2 * e], j = a.edge_ij[2 * e + 1];
-      double Z[sz];
-      perturbed_meas<G>(a.edge_meas + (size_t)e * sz, a.edge_tau ? a.edge_tau + (size_t)e * d : nullptr, Z);
-      between_cost<G, S>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
-      w = exp(a.edge_logw[e]);
-      out = rec + (size_t)e * RN;
-    } else {
-      const int p = g.prior0 + (k - g.nedge);
-      prior_cost<G, S>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Cj);
-#pragma unroll
-      for (int q = 0; q < d * d; ++q) Ci[q] = S(0);
-      w = exp(a.prior_logw[p]);
-      out = rec + (size_t)(a.E + p) * RN;
-    }
-    const S ws = S(w);
-    double cc = 0.0;
-#pragma unroll
-    for (int q = 0; q < d * d; ++q) {
-      out[q] = ws * Ci[q];
-      out[d * d + q] = ws * Cj[q];
-    }
-#pragma unroll
-    for (int q = 0; q < d; ++q) {
-      out[2 * d * d + q] = ws * c[q];
-      cc += double(c[q]) * double(c[q]);
-    }
-    sacc += 0.5 * w * w * cc;
+    const int rk = (k < g.nedge) ? g.edge0 + k : a.E + g.prior0 + (k - g.nedge);
+    sacc += linearize_cost<G, S>(cd, rk, rec + (size_t)rk * RN);
   }
   return block_sum(sacc, red);
 }
@@ -401,73 +378,21 @@ __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
   if (a.adjoint_out)
     for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
   // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
+  const PoseCostData cd = cost_data(a);
   const int ncost = g.nedge + g.nprior;
   for (int k = threadIdx.x; k < ncost; k += kNT) {
-    int cost, pi, pj;
-    double w;
+    int rk;
+    const double *ui = nullptr, *uj;
     if (k < g.nedge) {
-      cost = g.edge0 + k;
-      pi = a.edge_ij[2 * cost] - g.pose0;
-      pj = a.edge_ij[2 * cost + 1] - g.pose0;
-      w = exp(a.edge_logw[cost]);
+      rk = g.edge0 + k;
+      ui = vu + (a.edge_ij[2 * rk] - g.pose0) * d;
+      uj = vu + (a.edge_ij[2 * rk + 1] - g.pose0) * d;
     } else {
       const int p = g.prior0 + (k - g.nedge);
-      cost = a.E + p;
-      pi = -1;
-      pj = a.prior_var[p] - g.pose0;
-      w = exp(a.prior_logw[p]);
+      rk = a.E + p;
+      uj = vu + (a.prior_var[p] - g.pose0) * d;
     }
-    const double* J = a.ws64 + (size_t)cost * RN;
-    const double* r = J + 2 * d * d;
-    double y[d], yr = 0.0;
-#pragma unroll
-    for (int q = 0; q < d; ++q) {
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < d; ++m) {
-        if (pi >= 0) acc += J[q * d + m] * vu[pi * d + m];
-        acc += J[d * d + q * d + m] * vu[pj * d + m];
-      }
-      y[q] = acc;
-      yr += acc * r[q];
-    }
-    if (k < g.nedge) {
-      if (a.g_logw_e) a.g_logw_e[cost] = -2.0 * yr;
-      if (a.g_tau) {
-        // dL/dtau = w^2 d/ds [Jl^-1(c)^T c] along cdot = C u = y / w
-        double c[d], cd[d], out[d];
-#pragma unroll
-        for (int q = 0; q < d; ++q) {
-          c[q] = r[q] / w;
-          cd[q] = y[q] / w;
-        }
-        dual_jlinvT_c<G>(c, cd, out);
-        // chain rule through Z Exp(tau) at a non-zero tau: Exp(tau + dt) =
-        // Exp(tau) Exp(Jr(tau) dt), so dL/dtau = Jr(tau)^T dL/dxi
-        double gt[d];
-#pragma unroll
-        for (int q = 0; q < d; ++q) gt[q] = w * w * out[q];
-        if (a.edge_tau) {
-          double tau[d], Jt[d * d];
-#pragma unroll
-          for (int q = 0; q < d; ++q) tau[q] = a.edge_tau[(size_t)cost * d + q];
-          if constexpr (G == 3) se3_jr(tau, Jt);
-          else se2_jr(tau, Jt);
-#pragma unroll
-          for (int q = 0; q < d; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int m = 0; m < d; ++m) acc += Jt[m * d + q] * gt[m];
-            a.g_tau[(size_t)cost * d + q] = acc;
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < d; ++q) a.g_tau[(size_t)cost * d + q] = gt[q];
-        }
-      }
-    } else if (a.g_logw_p) {
-      a.g_logw_p[cost - a.E] = -2.0 * yr;
-    }
+    cost_vjp<G>(cd, rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p);
   }
 }
 
@@ -568,8 +493,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     *out = p;
     return DNLS_OK;
   }
-  if (op->solver != DNLS_SOLVER_DENSE)
-    return fail(DNLS_ERR_UNSUPPORTED, "solver not available in this build");
+  if (op->solver != DNLS_SOLVER_DENSE && op->solver != DNLS_SOLVER_SPARSE)
+    return fail(DNLS_ERR_UNSUPPORTED, "unknown solver");
   const int B = pr->batch;
   int V = 0, E = 0, P = 0;
   if (!check_off(pr->pose_off, B, 0, &V) || !check_off(pr->edge_off, B, 0, &E) ||
@@ -588,6 +513,16 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   p->E = E;
   p->P = P;
   const int d = p->d;
+  if (op->solver == DNLS_SOLVER_SPARSE) {
+    const dnls_status st = sp_plan_create(p, pr);
+    if (st != DNLS_OK) {
+      const std::string msg = g_err;
+      dnls_plan_destroy(p);
+      return fail(st, msg);
+    }
+    *out = p;
+    return DNLS_OK;
+  }
 
   // per-pose incidence (slots = cost * 2 + side) and off-diagonal blocks
   std::vector<std::vector<int>> inc(V);
@@ -719,6 +654,9 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_solve(p, s, static_cast<hipStream_t>(stream));
   if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
     return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
+  if (p->opt.solver == DNLS_SOLVER_SPARSE) return sp_solve(p, s, static_cast<hipStream_t>(stream));
+  if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+    return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   DenseArgs a = base_args(p);
@@ -749,6 +687,7 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_backward(p, s, static_cast<hipStream_t>(stream));
+  if (p->opt.solver == DNLS_SOLVER_SPARSE) return sp_backward(p, s, static_cast<hipStream_t>(stream));
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   DenseArgs a = base_args(p);

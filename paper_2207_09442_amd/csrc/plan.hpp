@@ -43,6 +43,20 @@ struct BADesc {
   int lin_blk0, nlin_blk;   // linearisation thread blocks of this problem
 };
 
+// one pose graph of the block-sparse path
+struct SpDesc {
+  int pose0, npose, edge0, nedge, prior0, nprior, n;
+  int P;               // tile rows = tile columns
+  int ntile;           // non-zero tiles of the factor
+  int tix_off;         // tile-id table [P x P] offset
+  int col_off;         // column pointer offset (P + 1 entries)
+  int od0, nod;        // off-diagonal Hessian blocks
+  int nvec;            // vector length (P x tile size)
+  long long vec_off;   // doubles: 3 vectors of nvec in the workspace
+  long long pool_off;  // doubles: tile pool
+  long long winv_off;  // doubles: inverses of the diagonal tiles
+};
+
 }  // namespace dnls
 
 struct dnls_plan_s {
@@ -80,6 +94,17 @@ struct dnls_plan_s {
   int2* d_spair = nullptr;        // (obs a, obs b) contributions
   size_t ba_off[16] = {0};        // byte offsets of the BA workspace regions
   size_t ba_fac_off[4] = {0};     // byte offsets of the BA backward cache inside the factor
+  // block-sparse path (solver SPARSE)
+  std::vector<dnls::SpDesc> sd;
+  dnls::SpDesc* d_sd = nullptr;
+  int* d_pos = nullptr;
+  int* d_tix = nullptr;
+  int* d_colptr = nullptr;
+  int* d_rowidx = nullptr;
+  std::vector<int> sp_ntrsm;
+  std::vector<long long> sp_npair;
+  int sp_maxP = 0;
+  size_t sp_off[8] = {0};
   std::vector<void*> allocs;
 };
 
@@ -98,5 +123,8 @@ dnls_status upload(dnls_plan p, T** dst, const std::vector<T>& v) {
 dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_options* op);
 dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st);
 dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st);
+dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr);
+dnls_status sp_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st);
+dnls_status sp_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st);
 
 }  // namespace dnls

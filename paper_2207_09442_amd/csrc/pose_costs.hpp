@@ -1,0 +1,121 @@
+// Per-cost kernels of the pose-graph objective shared by the dense and the
+// block-sparse paths: linearisation of one cost into its record
+// (w C_i, w C_j, w c) and the per-cost vector-Jacobian product of the
+// implicit backward (Proposition 1):
+//   dL/dl_e   = -2 (J u)^T r                        (w = exp(l), J = w C, r = w c)
+//   dL/dtau_e = w^2 d/ds [Jl^-1(c(s))^T c(s)]        along c' = C u, then the
+//               chain rule Jr(tau)^T for a non-zero base tau
+// The tau formula follows from dc/dtau = -Jl^-1(c) and the symmetry of
+// mixed partial derivatives of 1/2 ||c(theta (+) s u, tau)||^2.
+#pragma once
+
+#include "costs.hpp"
+
+namespace dnls {
+
+struct PoseCostData {
+  const int* edge_ij;       // [E][2] global pose indices
+  const int* prior_var;     // [P]
+  const double* poses;
+  const double* edge_meas;
+  const double* edge_logw;
+  const double* edge_tau;   // may be null
+  const double* prior_meas;
+  const double* prior_logw;
+  int E;                    // records: edges [0, E), priors [E, E + P)
+};
+
+// Linearise cost k (record index) into rec (CostRec<d>::n values of S);
+// returns 1/2 w^2 ||c||^2.
+template <int G, class S>
+__device__ __forceinline__ double linearize_cost(const PoseCostData& a, int k, S* rec) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  S c[d], Ci[d * d], Cj[d * d];
+  double w;
+  if (k < a.E) {
+    const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+    double Z[sz];
+    perturbed_meas<G>(a.edge_meas + (size_t)k * sz, a.edge_tau ? a.edge_tau + (size_t)k * d : nullptr, Z);
+    between_cost<G, S>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
+    w = exp(a.edge_logw[k]);
+  } else {
+    const int p = k - a.E;
+    prior_cost<G, S>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Cj);
+#pragma unroll
+    for (int q = 0; q < d * d; ++q) Ci[q] = S(0);
+    w = exp(a.prior_logw[p]);
+  }
+  const S ws = S(w);
+  double cc = 0.0;
+#pragma unroll
+  for (int q = 0; q < d * d; ++q) {
+    rec[q] = ws * Ci[q];
+    rec[d * d + q] = ws * Cj[q];
+  }
+#pragma unroll
+  for (int q = 0; q < d; ++q) {
+    rec[2 * d * d + q] = ws * c[q];
+    cc += double(c[q]) * double(c[q]);
+  }
+  return 0.5 * w * w * cc;
+}
+
+// Per-cost VJP of cost k from its float64 record and the adjoint u of its
+// poses (ui is null for a prior).  Null gradient outputs are skipped.
+template <int G>
+__device__ __forceinline__ void cost_vjp(const PoseCostData& a, int k, const double* rec, const double* ui,
+                                         const double* uj, double* g_logw_e, double* g_tau, double* g_logw_p) {
+  constexpr int d = GroupTraits<G>::d;
+  const double* r = rec + 2 * d * d;
+  double y[d], yr = 0.0;
+#pragma unroll
+  for (int q = 0; q < d; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < d; ++m) {
+      if (ui) acc += rec[q * d + m] * ui[m];
+      acc += rec[d * d + q * d + m] * uj[m];
+    }
+    y[q] = acc;
+    yr += acc * r[q];
+  }
+  if (k >= a.E) {
+    if (g_logw_p) g_logw_p[k - a.E] = -2.0 * yr;
+    return;
+  }
+  if (g_logw_e) g_logw_e[k] = -2.0 * yr;
+  if (!g_tau) return;
+  const double w = exp(a.edge_logw[k]);
+  double c[d], cd[d], out[d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) {
+    c[q] = r[q] / w;
+    cd[q] = y[q] / w;
+  }
+  dual_jlinvT_c<G>(c, cd, out);
+  double gt[d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) gt[q] = w * w * out[q];
+  if (a.edge_tau) {
+    // Exp(tau + dt) = Exp(tau) Exp(Jr(tau) dt)  =>  dL/dtau = Jr(tau)^T dL/dxi
+    double tau[d], Jt[d * d];
+#pragma unroll
+    for (int q = 0; q < d; ++q) tau[q] = a.edge_tau[(size_t)k * d + q];
+    if constexpr (G == 3)
+      se3_jr(tau, Jt);
+    else
+      se2_jr(tau, Jt);
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < d; ++m) acc += Jt[m * d + q] * gt[m];
+      g_tau[(size_t)k * d + q] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < d; ++q) g_tau[(size_t)k * d + q] = gt[q];
+  }
+}
+
+}  // namespace dnls

@@ -1,0 +1,855 @@
+// Block-sparse pose graphs (solver SPARSE): tile-supernodal right-looking
+// Cholesky on FP64 MFMA, for large graphs such as the 16^3 lattice.
+//
+// Symbolic analysis (once, host, symbolic.hpp): minimum-degree order of the
+// pose graph, postorder of its elimination tree, and the non-zero 48 x 48
+// tiles of the factor (48 = 8 poses = 3 MFMA tiles, so tiles never split a
+// pose).  Numeric factorisation, per tile column J (host loop, batched over
+// graphs in grid y):
+//   1. factor the diagonal tile:        L_JJ L_JJ^T = A_JJ, W = L_JJ^-1
+//   2. triangular solve down the column: L_IJ = A_IJ W^T
+//   3. right-looking update of every pair of tiles of the column:
+//        A_IK -= L_IJ L_KJ^T   (I >= K, both non-zero in column J)
+// Each target tile of step 3 is written by exactly one workgroup, so no
+// atomics are needed.  Linearisation, assembly and the triangular solves use
+// the same per-cost code as the dense path; the step is retracted in the
+// original pose order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "costs.hpp"
+#include "dense.hpp"
+#include "plan.hpp"
+#include "pose_costs.hpp"
+#include "symbolic.hpp"
+
+namespace dnls {
+namespace {
+
+constexpr int kTS = 48;            // tile size
+constexpr int kTT = kTS * kTS;     // doubles per tile
+constexpr int kBT = 256;           // threads of the grid kernels
+constexpr int kTW = 192;           // threads of the tile kernels (3 waves x 16 rows)
+
+struct SpArgs {
+  const SpDesc* sd;
+  const int* edge_ij;
+  const int* prior_var;
+  const int* pos;          // position of every pose in its graph's elimination order
+  const int* inc_off;
+  const int* inc_slot;
+  const int4* od_blk;
+  const int* od_slot;
+  const int* tix;          // tile ids: [tix_off + I * P + J], -1 if zero
+  const int* colptr;       // [col_off + J] .. [col_off + J + 1] -> rowidx
+  const int* rowidx;       // tile rows of each column, diagonal first
+  double* poses;
+  const double* edge_meas;
+  const double* edge_logw;
+  const double* edge_tau;
+  const double* prior_meas;
+  const double* prior_logw;
+  double* objective;
+  int* status;
+  double* factor;          // tile pools and panel inverses
+  double* ws64;
+  float* ws32;
+  double* ycost;
+  double* vec;             // per graph: [3][nvec]: step, right-hand side, residual
+  double* partial;
+  int* failed;
+  double* lastobj;
+  const double* seed;
+  double* uout;            // backward: adjoint in original pose order [V][d]
+  double* g_logw_e;
+  double* g_tau;
+  double* g_logw_p;
+  int E, K, it, nx, refine;
+  double lambda;
+};
+
+__device__ __forceinline__ PoseCostData cost_data(const SpArgs& a) {
+  return PoseCostData{a.edge_ij, a.prior_var, a.poses, a.edge_meas, a.edge_logw,
+                      a.edge_tau, a.prior_meas, a.prior_logw, a.E};
+}
+
+__device__ __forceinline__ double* tile_ptr(const SpArgs& a, const SpDesc& g, int I, int J) {
+  const int id = a.tix[g.tix_off + I * g.P + J];
+  return a.factor + g.pool_off + (size_t)id * kTT;
+}
+
+__device__ double block_sum_sp(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+// linearisation of the costs of graph blockIdx.y (grid x over its costs)
+template <int G, class S>
+__global__ void __launch_bounds__(kBT) k_sp_lin(SpArgs a, S* rec) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  double s = 0.0;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (!a.failed[b] && k < g.nedge + g.nprior) {
+    const int rk = (k < g.nedge) ? g.edge0 + k : a.E + g.prior0 + (k - g.nedge);
+    s = linearize_cost<G, S>(cost_data(a), rk, rec + (size_t)rk * RN);
+  }
+  s = block_sum_sp(s, red);
+  if (threadIdx.x == 0) a.partial[b * a.nx + blockIdx.x] = s;
+}
+
+// objective of the step and the non-finite check (thread per graph)
+__global__ void k_sp_objective(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double* obj = a.objective + (size_t)b * (a.K + 1);
+  if (a.failed[b]) {
+    obj[a.it] = a.lastobj[b];
+    return;
+  }
+  double S = 0.0;
+  for (int k = 0; k < a.nx; ++k) S += a.partial[b * a.nx + k];
+  obj[a.it] = S;
+  a.lastobj[b] = S;
+  if (!isfinite(S)) {
+    a.failed[b] = DNLS_GRAPH_NONFINITE;
+    a.status[b] = DNLS_GRAPH_NONFINITE;
+  }
+}
+
+// zero every tile of the graph's pool
+__global__ void __launch_bounds__(kBT) k_sp_zero(SpArgs a) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  d4v* pool = reinterpret_cast<d4v*>(a.factor + g.pool_off);
+  const size_t n4 = (size_t)g.ntile * (kTT / 4);
+  for (size_t u = (size_t)blockIdx.x * kBT + threadIdx.x; u < n4; u += (size_t)gridDim.x * kBT)
+    pool[u] = d4v{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ __forceinline__ void put(const SpArgs& a, const SpDesc& g, int row, int col, double v) {
+  double* t = tile_ptr(a, g, row / kTS, col / kTS);
+  t[(row % kTS) * kTS + col % kTS] = v;
+}
+
+// Hessian blocks into the tiles (permuted, lower triangle), g into vec[1]
+template <int G, class S>
+__global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, double lambda, int rhs_from_rec) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose + g.nod) {
+    S h[d * d];
+#pragma unroll
+    for (int q = 0; q < d * d; ++q) h[q] = S(0);
+    int pa, pb;
+    if (u < g.npose) {
+      pa = pb = u;
+      const int gp = g.pose0 + u;
+      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+        const int slot = a.inc_slot[s];
+        const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+#pragma unroll
+        for (int k = 0; k < d; ++k)
+#pragma unroll
+          for (int r = 0; r < d; ++r)
+#pragma unroll
+            for (int c = 0; c < d; ++c) h[r * d + c] += J[k * d + r] * J[k * d + c];
+      }
+    } else {
+      const int4 blk = a.od_blk[g.od0 + (u - g.npose)];
+      pa = blk.x;
+      pb = blk.y;
+      for (int s = blk.z; s < blk.z + blk.w; ++s) {
+        const int slot = a.od_slot[s];
+        const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
+#pragma unroll
+        for (int k = 0; k < d; ++k)
+#pragma unroll
+          for (int r = 0; r < d; ++r)
+#pragma unroll
+            for (int c = 0; c < d; ++c) h[r * d + c] += Jr[k * d + r] * Jc[k * d + c];
+      }
+    }
+    const int ra = a.pos[g.pose0 + pa], rb = a.pos[g.pose0 + pb];
+#pragma unroll
+    for (int r = 0; r < d; ++r)
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        double v = double(h[r * d + c]);
+        if (pa == pb) {
+          if (c > r) continue;
+          if (c == r) v += lambda;
+          put(a, g, ra * d + r, ra * d + c, v);
+        } else if (ra > rb) {
+          put(a, g, ra * d + r, rb * d + c, v);
+        } else {
+          put(a, g, rb * d + c, ra * d + r, v);
+        }
+      }
+  }
+  // padding of the last tile
+  if (blockIdx.x == 0)
+    for (int r = g.n + threadIdx.x; r < g.P * kTS; r += kBT) put(a, g, r, r, 1.0);
+  // right-hand side g (permuted) into vec[1]
+  double* rhs = a.vec + g.vec_off + g.nvec;
+  if (rhs_from_rec && u < g.npose) {
+    const int gp = g.pose0 + u, ra = a.pos[gp];
+    S acc[d];
+#pragma unroll
+    for (int r = 0; r < d; ++r) acc[r] = S(0);
+    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+      const int slot = a.inc_slot[s];
+      const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+      const S* res = rec + (size_t)(slot >> 1) * RN + 2 * d * d;
+#pragma unroll
+      for (int k = 0; k < d; ++k)
+#pragma unroll
+        for (int r = 0; r < d; ++r) acc[r] += J[k * d + r] * res[k];
+    }
+#pragma unroll
+    for (int r = 0; r < d; ++r) rhs[ra * d + r] = double(acc[r]);
+  }
+  if (blockIdx.x == 0)
+    for (int r = g.n + threadIdx.x; r < g.nvec; r += kBT) rhs[r] = 0.0;
+}
+
+// float64 right-hand side into vec[1] (mixed path with refinement)
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_rhs64(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u >= g.npose) return;
+  const int gp = g.pose0 + u, ra = a.pos[gp];
+  double acc[d];
+#pragma unroll
+  for (int r = 0; r < d; ++r) acc[r] = 0.0;
+  for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+    const int slot = a.inc_slot[s];
+    const double* J = a.ws64 + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+    const double* res = a.ws64 + (size_t)(slot >> 1) * RN + 2 * d * d;
+#pragma unroll
+    for (int k = 0; k < d; ++k)
+#pragma unroll
+      for (int r = 0; r < d; ++r) acc[r] += J[k * d + r] * res[k];
+  }
+  double* rhs = a.vec + g.vec_off + g.nvec;
+#pragma unroll
+  for (int r = 0; r < d; ++r) rhs[ra * d + r] = acc[r];
+}
+
+// 1. diagonal tile of column J
+__global__ void __launch_bounds__(kNT) k_sp_diag(SpArgs a, int J) {
+  __shared__ DenseLds s;
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || J >= g.P) return;
+  double* T = tile_ptr(a, g, J, J);
+  double* D = s.stage[0];
+  for (int e = threadIdx.x; e < kTT; e += kNT) D[(e / kTS) * kSP + e % kTS] = T[e];
+  __syncthreads();
+  const bool ok = chol_block<3>(D, s.W, s);
+  double* winv = a.factor + g.winv_off + (size_t)J * kTT;
+  for (int e = threadIdx.x; e < kTT; e += kNT) {
+    const int r = e / kTS, c = e % kTS;
+    T[e] = (c <= r) ? D[r * kSP + c] : 0.0;
+    winv[e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+  }
+  if (!ok && threadIdx.x == 0) {
+    a.failed[b] = DNLS_GRAPH_NOT_PD;
+    a.status[b] = DNLS_GRAPH_NOT_PD;
+  }
+}
+
+// 2. L_IJ = A_IJ W^T for the tiles below the diagonal of column J
+__global__ void __launch_bounds__(kTW) k_sp_trsm(SpArgs a, int J) {
+  __shared__ double W[kTS * (kTS + 4)];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || J >= g.P) return;
+  const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
+  const int t = blockIdx.x;
+  if (t >= c1 - c0 - 1) return;
+  const int I = a.rowidx[c0 + 1 + t];
+  const double* winv = a.factor + g.winv_off + (size_t)J * kTT;
+  constexpr int LW = kTS + 4;
+  for (int e = threadIdx.x; e < kTT; e += kTW) W[(e / kTS) * LW + e % kTS] = winv[e];
+  __syncthreads();
+  double* T = tile_ptr(a, g, I, J);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+  // rows 16 wave .. +16 of the tile; out[m][n] = sum_k A[m][k] W[n][k]
+  d4v acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = d4v{0.0, 0.0, 0.0, 0.0};
+  const double* arow = T + (16 * wave + lm) * kTS;
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt) {
+    const d4v av = *reinterpret_cast<const d4v*>(arow + 16 * kt + 4 * lq);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (kt > c) continue;   // W lower triangular
+      const d4v wv = *reinterpret_cast<const d4v*>(&W[(16 * c + lm) * LW + 16 * kt + 4 * lq]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[c] = mfma16(av[q], wv[q], acc[c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
+}
+
+// 3. A_IK -= L_IJ L_KJ^T for every pair I >= K of tiles below the diagonal of J
+__global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
+  __shared__ double LK[kTS * (kTS + 4)];
+  constexpr int LW = kTS + 4;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || J >= g.P) return;
+  const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
+  const int m = c1 - c0 - 1;
+  const long long t = blockIdx.x;
+  if (t >= (long long)m * (m + 1) / 2) return;
+  // triangular index t -> (p, q), p >= q
+  int p = (int)((::sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((long long)(p + 1) * (p + 2) / 2 <= t) ++p;
+  while ((long long)p * (p + 1) / 2 > t) --p;
+  const int q = (int)(t - (long long)p * (p + 1) / 2);
+  const int I = a.rowidx[c0 + 1 + p], Kt = a.rowidx[c0 + 1 + q];
+  const double* LI = tile_ptr(a, g, I, J);
+  const double* LKg = tile_ptr(a, g, Kt, J);
+  double* T = tile_ptr(a, g, I, Kt);
+  for (int e = threadIdx.x; e < kTT / 4; e += kTW) {
+    const int r = (4 * e) / kTS, c = (4 * e) % kTS;
+    *reinterpret_cast<d4v*>(&LK[r * LW + c]) = *reinterpret_cast<const d4v*>(LKg + 4 * e);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+  d4v acc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[c][r] = T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm];
+  d4v av[3];
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * wave + lm) * kTS + 16 * kt + 4 * lq);
+  __syncthreads();
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const d4v bv = *reinterpret_cast<const d4v*>(&LK[(16 * c + lm) * LW + 16 * kt + 4 * lq]);
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) acc[c] = mfma16(-av[kt][qq], bv[qq], acc[c]);
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
+}
+
+// v[0:48] <- W v or W^T v for a 48x48 lower-triangular tile inverse (global);
+// threads 0..47 produce the result into out (LDS).  All threads call.
+__device__ __forceinline__ void tile_inv_matvec(const double* W, const double* v, double* out, bool lower) {
+  if (threadIdx.x < kTS) {
+    const int c = threadIdx.x;
+    double acc = 0.0;
+    if (lower)
+      for (int k = 0; k <= c; ++k) acc += W[c * kTS + k] * v[k];
+    else
+      for (int r = c; r < kTS; ++r) acc += W[r * kTS + c] * v[r];
+    out[c] = acc;
+  }
+  __syncthreads();
+}
+
+// x <- (L L^T)^-1 x on the graph's tile factor (x global, permuted order)
+__device__ void sp_solve(const SpArgs& a, const SpDesc& g, double* x, double* sv, double* red) {
+  // forward: right-looking by tile columns
+  for (int J = 0; J < g.P; ++J) {
+    tile_inv_matvec(a.factor + g.winv_off + (size_t)J * kTT, x + J * kTS, sv, true);
+    if (threadIdx.x < kTS) x[J * kTS + threadIdx.x] = sv[threadIdx.x];
+    const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
+    const int m = c1 - c0 - 1;
+    for (int e = threadIdx.x; e < m * kTS; e += blockDim.x) {
+      const int I = a.rowidx[c0 + 1 + e / kTS], r = e % kTS;
+      const double* row = tile_ptr(a, g, I, J) + r * kTS;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < kTS; ++k) acc += row[k] * sv[k];
+      x[I * kTS + r] -= acc;
+    }
+    __syncthreads();
+  }
+  // backward: x_J = W^T (x_J - sum_I L_IJ^T x_I)
+  const int nparts = blockDim.x / kTS;
+  for (int J = g.P - 1; J >= 0; --J) {
+    const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
+    const int m = c1 - c0 - 1;
+    const int c = threadIdx.x % kTS, part = threadIdx.x / kTS;
+    double acc = 0.0;
+    if (part < nparts)
+      for (int i = part; i < m; i += nparts) {
+        const int I = a.rowidx[c0 + 1 + i];
+        const double* T = tile_ptr(a, g, I, J);
+        const double* xi = x + I * kTS;
+        for (int r = 0; r < kTS; ++r) acc += T[r * kTS + c] * xi[r];
+      }
+    if (part < nparts) red[part * kTS + c] = acc;
+    __syncthreads();
+    if (threadIdx.x < kTS) {
+      double z = x[J * kTS + threadIdx.x];
+      for (int pp = 0; pp < nparts; ++pp) z -= red[pp * kTS + threadIdx.x];
+      sv[kTS + threadIdx.x] = z;
+    }
+    __syncthreads();
+    tile_inv_matvec(a.factor + g.winv_off + (size_t)J * kTT, sv + kTS, sv, false);
+    if (threadIdx.x < kTS) x[J * kTS + threadIdx.x] = sv[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// step: solve, then retract in the original pose order
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_step(SpArgs a, int retract) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  __shared__ double sv[2 * kTS];
+  __shared__ double red[kBT];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  double* x = a.vec + g.vec_off;
+  const double* rhs = x + g.nvec;
+  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] = rhs[u];
+  __syncthreads();
+  sp_solve(a, g, x, sv, red);
+  if (retract)
+    for (int p = threadIdx.x; p < g.npose; p += kBT)
+      retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x + a.pos[g.pose0 + p] * d);
+}
+
+// refinement: J delta per cost (float64 records), delta read in permuted order
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  const double* x = a.vec + g.vec_off;
+  int rk, pi = -1, pj;
+  if (k < g.nedge) {
+    rk = g.edge0 + k;
+    pi = a.pos[a.edge_ij[2 * rk]];
+    pj = a.pos[a.edge_ij[2 * rk + 1]];
+  } else {
+    rk = a.E + g.prior0 + (k - g.nedge);
+    pj = a.pos[a.prior_var[g.prior0 + (k - g.nedge)]];
+  }
+  const double* J = a.ws64 + (size_t)rk * RN;
+#pragma unroll
+  for (int r = 0; r < d; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      if (pi >= 0) acc += J[r * d + q] * x[pi * d + q];
+      acc += J[d * d + r * d + q] * x[pj * d + q];
+    }
+    a.ycost[(size_t)rk * d + r] = acc;
+  }
+}
+
+// refinement: residual = g64 - (H64 + lambda) delta into vec[2], then solve
+// and add to delta (one workgroup per graph)
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_refine(SpArgs a, double lambda, int retract) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz, RN = CostRec<d>::n;
+  __shared__ double sv[2 * kTS];
+  __shared__ double red[kBT];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  double* x = a.vec + g.vec_off;
+  const double* rhs = x + g.nvec;
+  double* res = x + 2 * g.nvec;
+  for (int p = threadIdx.x; p < g.npose; p += kBT) {
+    const int gp = g.pose0 + p, ra = a.pos[gp];
+    double hv[d];
+#pragma unroll
+    for (int r = 0; r < d; ++r) hv[r] = lambda * x[ra * d + r];
+    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+      const int slot = a.inc_slot[s];
+      const double* J = a.ws64 + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+      const double* yc = a.ycost + (size_t)(slot >> 1) * d;
+#pragma unroll
+      for (int k = 0; k < d; ++k)
+#pragma unroll
+        for (int r = 0; r < d; ++r) hv[r] += J[k * d + r] * yc[k];
+    }
+#pragma unroll
+    for (int r = 0; r < d; ++r) res[ra * d + r] = rhs[ra * d + r] - hv[r];
+  }
+  for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
+  __syncthreads();
+  sp_solve(a, g, res, sv, red);
+  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] += res[u];
+  __syncthreads();
+  if (retract)
+    for (int p = threadIdx.x; p < g.npose; p += kBT)
+      retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x + a.pos[g.pose0 + p] * d);
+}
+
+// backward: u = H*^-1 v (one workgroup per graph), u in original order
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_adjoint(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d;
+  __shared__ double sv[2 * kTS];
+  __shared__ double red[kBT];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) {
+    for (int u = threadIdx.x; u < g.n; u += kBT) a.uout[(size_t)g.pose0 * d + u] = 0.0;
+    return;
+  }
+  double* x = a.vec + g.vec_off;
+  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] = 0.0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < g.npose; p += kBT)
+    for (int r = 0; r < d; ++r) x[a.pos[g.pose0 + p] * d + r] = a.seed[(size_t)(g.pose0 + p) * d + r];
+  __syncthreads();
+  sp_solve(a, g, x, sv, red);
+  for (int p = threadIdx.x; p < g.npose; p += kBT)
+    for (int r = 0; r < d; ++r) a.uout[(size_t)(g.pose0 + p) * d + r] = x[a.pos[g.pose0 + p] * d + r];
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_vjp(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  const bool ok = a.status[b] == DNLS_GRAPH_OK;
+  int rk;
+  const double *ui = nullptr, *uj;
+  if (k < g.nedge) {
+    rk = g.edge0 + k;
+    ui = a.uout + (size_t)a.edge_ij[2 * rk] * d;
+    uj = a.uout + (size_t)a.edge_ij[2 * rk + 1] * d;
+  } else {
+    rk = a.E + g.prior0 + (k - g.nedge);
+    uj = a.uout + (size_t)a.prior_var[rk - a.E] * d;
+  }
+  if (!ok) {
+    if (k < g.nedge) {
+      if (a.g_logw_e) a.g_logw_e[rk] = 0.0;
+      if (a.g_tau)
+        for (int q = 0; q < d; ++q) a.g_tau[(size_t)rk * d + q] = 0.0;
+    } else if (a.g_logw_p) {
+      a.g_logw_p[rk - a.E] = 0.0;
+    }
+    return;
+  }
+  cost_vjp<G>(cost_data(a), rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p);
+}
+
+__global__ void k_sp_reset(int* failed, int* status, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    failed[b] = 0;
+    status[b] = DNLS_GRAPH_OK;
+  }
+}
+
+__global__ void k_sp_failed_from_status(int* failed, const int* status, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) failed[b] = status[b] != DNLS_GRAPH_OK;
+}
+
+int max_desc(const std::vector<SpDesc>& v, int SpDesc::*f) {
+  int m = 1;
+  for (const auto& x : v) m = std::max(m, x.*f);
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
+  const int B = pr->batch, d = p->d;
+  std::vector<int> edge_ij(2 * (size_t)p->E), prior_var(p->P), pos(p->V);
+  std::vector<std::vector<int>> inc(p->V);
+  std::vector<int4> od_blk;
+  std::vector<int> od_slot, tix, colptr, rowidx;
+  p->sd.resize(B);
+  long long fac = 0, vecoff = 0;
+  int maxP = 0;
+  for (int b = 0; b < B; ++b) {
+    SpDesc& g = p->sd[b];
+    g.pose0 = pr->pose_off[b];
+    g.npose = pr->pose_off[b + 1] - g.pose0;
+    g.edge0 = pr->edge_off[b];
+    g.nedge = pr->edge_off[b + 1] - g.edge0;
+    g.prior0 = pr->prior_off[b];
+    g.nprior = pr->prior_off[b + 1] - g.prior0;
+    g.n = g.npose * d;
+    std::vector<std::vector<int>> adj(g.npose);
+    std::map<std::pair<int, int>, std::vector<int>> blocks;
+    for (int e = g.edge0; e < g.edge0 + g.nedge; ++e) {
+      const int i = pr->edge_ij[2 * (size_t)e], j = pr->edge_ij[2 * (size_t)e + 1];
+      if (i < g.pose0 || i >= g.pose0 + g.npose || j < g.pose0 || j >= g.pose0 + g.npose || i == j)
+        return fail(DNLS_ERR_INVALID_ARG, "edge " + std::to_string(e) + " has an index outside its graph or i == j");
+      edge_ij[2 * (size_t)e] = i;
+      edge_ij[2 * (size_t)e + 1] = j;
+      inc[i].push_back(2 * e + 0);
+      inc[j].push_back(2 * e + 1);
+      const int li = i - g.pose0, lj = j - g.pose0;
+      adj[li].push_back(lj);
+      adj[lj].push_back(li);
+      if (li > lj) blocks[{li, lj}].push_back(2 * e + 0);
+      else blocks[{lj, li}].push_back(2 * e + 1);
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      const int v = pr->prior_var[q];
+      if (v < g.pose0 || v >= g.pose0 + g.npose)
+        return fail(DNLS_ERR_INVALID_ARG, "prior " + std::to_string(q) + " refers to a pose outside its graph");
+      prior_var[q] = v;
+      inc[v].push_back(2 * (p->E + q) + 1);
+    }
+    // ordering: minimum degree, then an elimination-tree postorder
+    const std::vector<int> order = sym::min_degree_order(g.npose, adj);
+    std::vector<int> lpos(g.npose);
+    for (int k = 0; k < g.npose; ++k) lpos[order[k]] = k;
+    lpos = sym::postorder_positions(g.npose, adj, lpos);
+    for (int v = 0; v < g.npose; ++v) pos[g.pose0 + v] = lpos[v];
+    std::vector<std::pair<int, int>> bl;
+    for (auto& kv : blocks) bl.push_back(kv.first);
+    const sym::TileStructure ts = sym::tile_symbolic(g.npose, d, kTS, lpos, bl);
+    g.P = ts.P;
+    maxP = std::max(maxP, g.P);
+    g.ntile = (int)ts.row_idx.size();
+    g.tix_off = (int)tix.size();
+    tix.resize(tix.size() + (size_t)g.P * g.P, -1);
+    g.col_off = (int)colptr.size();
+    const int rbase = (int)rowidx.size();
+    for (int J = 0; J <= g.P; ++J) colptr.push_back(rbase + ts.col_ptr[J]);
+    for (int J = 0; J < g.P; ++J)
+      for (int k = ts.col_ptr[J]; k < ts.col_ptr[J + 1]; ++k) {
+        const int I = ts.row_idx[k];
+        tix[g.tix_off + (size_t)I * g.P + J] = k;
+        rowidx.push_back(I);
+      }
+    g.pool_off = fac;
+    fac += (long long)g.ntile * kTT;
+    g.winv_off = fac;
+    fac += (long long)g.P * kTT;
+    fac = (fac + 31) / 32 * 32;
+    g.nvec = g.P * kTS;
+    g.vec_off = vecoff;
+    vecoff += 3LL * g.nvec;
+    g.od0 = (int)od_blk.size();
+    for (auto& kv : blocks) {
+      od_blk.push_back(int4{kv.first.first, kv.first.second, (int)od_slot.size(), (int)kv.second.size()});
+      for (int s : kv.second) od_slot.push_back(s);
+    }
+    g.nod = (int)od_blk.size() - g.od0;
+  }
+  std::vector<int> inc_off(p->V + 1, 0), inc_slot;
+  for (int v = 0; v < p->V; ++v) {
+    inc_off[v + 1] = inc_off[v] + (int)inc[v].size();
+    for (int s : inc[v]) inc_slot.push_back(s);
+  }
+  // per tile column: the widest column and pair count over the batch
+  p->sp_ntrsm.assign(maxP, 0);
+  p->sp_npair.assign(maxP, 0);
+  for (int b = 0; b < B; ++b) {
+    const SpDesc& g = p->sd[b];
+    for (int J = 0; J < g.P; ++J) {
+      const int m = colptr[g.col_off + J + 1] - colptr[g.col_off + J] - 1;
+      p->sp_ntrsm[J] = std::max(p->sp_ntrsm[J], m);
+      p->sp_npair[J] = std::max(p->sp_npair[J], (long long)m * (m + 1) / 2);
+    }
+  }
+  p->sp_maxP = maxP;
+  dnls_status st;
+  if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
+      (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK || (st = upload(p, &p->d_pos, pos)) != DNLS_OK ||
+      (st = upload(p, &p->d_inc_off, inc_off)) != DNLS_OK || (st = upload(p, &p->d_inc_slot, inc_slot)) != DNLS_OK ||
+      (st = upload(p, &p->d_od_blk, od_blk)) != DNLS_OK || (st = upload(p, &p->d_od_slot, od_slot)) != DNLS_OK ||
+      (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
+      (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK)
+    return st;
+  const size_t ncost = (size_t)p->E + p->P;
+  const size_t rn = 2 * (size_t)d * d + d;
+  const int nx = (max_desc(p->sd, &SpDesc::nedge) + max_desc(p->sd, &SpDesc::nprior) + kBT - 1) / kBT;
+  p->nlin_blocks = nx;
+  size_t off = 0;
+  p->sp_off[0] = off; off += align256(ncost * rn * sizeof(double));                 // ws64
+  p->sp_off[1] = off; off += align256(ncost * rn * sizeof(float));                  // ws32
+  p->sp_off[2] = off; off += align256(ncost * d * sizeof(double));                  // ycost
+  p->sp_off[3] = off; off += align256((size_t)vecoff * sizeof(double));             // vectors
+  p->sp_off[4] = off; off += align256((size_t)B * nx * sizeof(double));             // partials
+  p->sp_off[5] = off; off += align256((size_t)B * sizeof(int));                     // failed
+  p->sp_off[6] = off; off += align256((size_t)B * sizeof(double));                  // last objective
+  p->sp_off[7] = off; off += align256((size_t)p->V * d * sizeof(double));           // adjoint
+  p->ws_bytes = off;
+  p->bwd_bytes = off;
+  p->fac_bytes = (size_t)fac * sizeof(double);
+  return DNLS_OK;
+}
+
+static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
+  SpArgs a{};
+  a.sd = p->d_sd;
+  a.edge_ij = p->d_edge_ij;
+  a.prior_var = p->d_prior_var;
+  a.pos = p->d_pos;
+  a.inc_off = p->d_inc_off;
+  a.inc_slot = p->d_inc_slot;
+  a.od_blk = p->d_od_blk;
+  a.od_slot = p->d_od_slot;
+  a.tix = p->d_tix;
+  a.colptr = p->d_colptr;
+  a.rowidx = p->d_rowidx;
+  char* w = static_cast<char*>(ws);
+  a.ws64 = reinterpret_cast<double*>(w + p->sp_off[0]);
+  a.ws32 = reinterpret_cast<float*>(w + p->sp_off[1]);
+  a.ycost = reinterpret_cast<double*>(w + p->sp_off[2]);
+  a.vec = reinterpret_cast<double*>(w + p->sp_off[3]);
+  a.partial = reinterpret_cast<double*>(w + p->sp_off[4]);
+  a.failed = reinterpret_cast<int*>(w + p->sp_off[5]);
+  a.lastobj = reinterpret_cast<double*>(w + p->sp_off[6]);
+  a.uout = reinterpret_cast<double*>(w + p->sp_off[7]);
+  a.factor = static_cast<double*>(factor);
+  a.E = p->E;
+  a.K = p->opt.iterations;
+  a.nx = p->nlin_blocks;
+  a.refine = p->opt.precision == DNLS_PREC_MIXED ? p->opt.refine : 0;
+  a.lambda = p->opt.lambda;
+  return a;
+}
+
+template <int G>
+static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
+  const int B = p->B;
+  for (int J = 0; J < p->sp_maxP; ++J) {
+    hipLaunchKernelGGL(k_sp_diag, dim3(B), dim3(kNT), 0, st, a, J);
+    if (p->sp_ntrsm[J] > 0) {
+      hipLaunchKernelGGL(k_sp_trsm, dim3(p->sp_ntrsm[J], B), dim3(kTW), 0, st, a, J);
+      hipLaunchKernelGGL(k_sp_update, dim3((unsigned)p->sp_npair[J], B), dim3(kTW), 0, st, a, J);
+    }
+  }
+}
+
+template <int G>
+static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  constexpr int d = GroupTraits<G>::d;
+  SpArgs a = sp_args(p, s->workspace, s->factor);
+  a.poses = s->poses;
+  a.edge_meas = s->edge_meas;
+  a.edge_logw = s->edge_logw;
+  a.edge_tau = s->edge_tau;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.objective = s->objective;
+  a.status = s->status;
+  const int B = p->B;
+  const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
+  const dim3 g_cost(p->nlin_blocks, B);
+  const dim3 g_blk((max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::nod) + kBT - 1) / kBT, B);
+  const dim3 g_zero(256, B);
+  hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  for (int it = 0; it <= p->opt.iterations; ++it) {
+    const bool final_lin = it == p->opt.iterations;
+    const double lam = final_lin ? 0.0 : p->opt.lambda;
+    a.it = it;
+    const bool lin32 = mixed && !final_lin;
+    const bool lin64 = !mixed || a.refine > 0 || final_lin;
+    if (lin32) hipLaunchKernelGGL((k_sp_lin<G, float>), g_cost, dim3(kBT), 0, st, a, a.ws32);
+    if (lin64) hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
+    hipLaunchKernelGGL(k_sp_objective, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+    hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
+    if (lin32) {
+      hipLaunchKernelGGL((k_sp_assemble<G, float>), g_blk, dim3(kBT), 0, st, a, (const float*)a.ws32, lam,
+                         a.refine > 0 ? 0 : 1);
+      if (a.refine > 0) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
+    } else {
+      hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, lam, 1);
+    }
+    sp_factor<G>(p, a, st);
+    if (final_lin) break;
+    const bool refine = lin32 && a.refine > 0;
+    hipLaunchKernelGGL(k_sp_step<G>, dim3(B), dim3(kBT), 0, st, a, refine ? 0 : 1);
+    if (refine)
+      for (int sw = 0; sw < a.refine; ++sw) {
+        hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a);
+        hipLaunchKernelGGL(k_sp_refine<G>, dim3(B), dim3(kBT), 0, st, a, lam, sw + 1 == a.refine ? 1 : 0);
+      }
+  }
+  HIP_TRY(hipGetLastError());
+  (void)d;
+  return DNLS_OK;
+}
+
+template <int G>
+static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
+  SpArgs a = sp_args(p, s->workspace, const_cast<void*>(s->factor));
+  a.poses = const_cast<double*>(s->poses);
+  a.edge_meas = s->edge_meas;
+  a.edge_logw = s->edge_logw;
+  a.edge_tau = s->edge_tau;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.status = const_cast<int*>(s->status);
+  a.seed = s->seed_pose;
+  a.g_logw_e = s->grad_edge_logw;
+  a.g_tau = s->grad_edge_tau;
+  a.g_logw_p = s->grad_prior_logw;
+  const int B = p->B;
+  const dim3 g_cost(p->nlin_blocks, B);
+  // float64 records at theta_K for the graphs whose solve succeeded
+  hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
+  hipLaunchKernelGGL(k_sp_adjoint<G>, dim3(B), dim3(kBT), 0, st, a);
+  hipLaunchKernelGGL(k_sp_vjp<G>, g_cost, dim3(kBT), 0, st, a);
+  HIP_TRY(hipGetLastError());
+  if (s->adjoint)
+    HIP_TRY(hipMemcpyAsync(s->adjoint, a.uout, (size_t)p->V * p->d * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return DNLS_OK;
+}
+
+dnls_status sp_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  if (p->group == DNLS_SE3) return sp_solve_impl<3>(p, s, st);
+  return sp_solve_impl<2>(p, s, st);
+}
+
+dnls_status sp_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
+  if (p->group == DNLS_SE3) return sp_backward_impl<3>(p, s, st);
+  return sp_backward_impl<2>(p, s, st);
+}
+
+}  // namespace dnls

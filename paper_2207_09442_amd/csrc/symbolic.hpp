@@ -78,6 +78,54 @@ inline std::vector<int> min_degree_order(int n, const std::vector<std::vector<in
   return order;
 }
 
+// Elimination tree of the matrix with the given pattern in elimination
+// order pos[] (Liu's algorithm with path compression), then a postorder of
+// it: an equivalent elimination order (same fill) in which every subtree is
+// contiguous, so that fixed-size tiles group related columns.
+inline std::vector<int> postorder_positions(int n, const std::vector<std::vector<int>>& adj,
+                                            const std::vector<int>& pos) {
+  std::vector<int> inv(n);
+  for (int v = 0; v < n; ++v) inv[pos[v]] = v;
+  std::vector<int> parent(n, -1), anc(n, -1);
+  for (int j = 0; j < n; ++j) {
+    const int v = inv[j];
+    for (int u : adj[v]) {
+      int r = pos[u];
+      if (r >= j) continue;
+      while (anc[r] != -1 && anc[r] != j) {
+        const int next = anc[r];
+        anc[r] = j;
+        r = next;
+      }
+      if (anc[r] == -1) {
+        anc[r] = j;
+        parent[r] = j;
+      }
+    }
+  }
+  std::vector<std::vector<int>> children(n);
+  std::vector<int> roots;
+  for (int j = 0; j < n; ++j) (parent[j] >= 0 ? children[parent[j]] : roots).push_back(j);
+  std::vector<int> post;
+  post.reserve(n);
+  std::vector<std::pair<int, int>> stack;
+  for (auto it = roots.rbegin(); it != roots.rend(); ++it) stack.emplace_back(*it, 0);
+  while (!stack.empty()) {
+    auto& top = stack.back();
+    const int v = top.first;
+    if (top.second < (int)children[v].size()) {
+      const int c = children[v][top.second++];
+      stack.emplace_back(c, 0);
+    } else {
+      post.push_back(v);
+      stack.pop_back();
+    }
+  }
+  std::vector<int> newpos(n);
+  for (int k = 0; k < n; ++k) newpos[inv[post[k]]] = k;
+  return newpos;
+}
+
 struct TileStructure {
   int P = 0;                       // tile rows = tile columns
   std::vector<int> col_ptr;        // [P+1]

@@ -7,7 +7,7 @@
 
 #include "../../paper_2207_09442_amd/csrc/symbolic.hpp"
 
-int main() {
+int main(int argc, char**) {
   int n, d, ts, m;
   if (std::scanf("%d %d %d %d", &n, &d, &ts, &m) != 4) return 1;
   std::vector<std::vector<int>> adj(n);
@@ -22,9 +22,13 @@ int main() {
   const std::vector<int> order = dnls::sym::min_degree_order(n, adj);
   std::vector<int> pos(n);
   for (int k = 0; k < n; ++k) pos[order[k]] = k;
+  const bool post = (argc > 1);
+  if (post) pos = dnls::sym::postorder_positions(n, adj, pos);
+  std::vector<int> final_order(n);
+  for (int v = 0; v < n; ++v) final_order[pos[v]] = v;
   const dnls::sym::TileStructure t = dnls::sym::tile_symbolic(n, d, ts, pos, blocks);
   std::printf("order");
-  for (int v : order) std::printf(" %d", v);
+  for (int v : (post ? final_order : order)) std::printf(" %d", v);
   std::printf("\nP %d\ncol_ptr", t.P);
   for (int v : t.col_ptr) std::printf(" %d", v);
   std::printf("\nrow_idx");

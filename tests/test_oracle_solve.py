@@ -233,3 +233,13 @@ def test_failed_graph_is_frozen_with_zero_gradient():
     assert len(set(res.objective)) == 1 and len(res.objective) == 5
     gr = S.implicit_grad_graph(g, res, torch.ones(8, 6, dtype=DT))
     assert float(gr["tau"].abs().max()) == 0.0
+
+
+def test_sparse_assembly_equals_dense():
+    p = synth.lattice_se3(batch=1, side=3)
+    g = S.graphs_of(p)[0]
+    lin = S.linearize_pose_graph(g, g.X)
+    s, H, gv = S.linearize_pose_graph_sparse(g, g.X)
+    assert abs(s - float(lin.S)) < 1e-12 * max(1.0, s)
+    assert np.abs(H.toarray() - lin.H.numpy()).max() < 1e-12 * np.abs(H.toarray()).max()
+    assert np.abs(gv - lin.g.numpy()).max() < 1e-12 * np.abs(gv).max()

@@ -27,9 +27,10 @@ def driver(tmp_path_factory):
     return exe
 
 
-def run(exe, n, d, ts, pairs):
+def run(exe, n, d, ts, pairs, post=False):
     inp = f"{n} {d} {ts} {len(pairs)}\n" + "".join(f"{a} {b}\n" for a, b in pairs)
-    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    out = subprocess.run([exe] + (["post"] if post else []), input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
     vals = {line.split()[0]: line.split()[1:] for line in out if line.strip()}
     order = [int(x) for x in vals["order"]]
     col_ptr = [int(x) for x in vals["col_ptr"]]
@@ -78,12 +79,12 @@ def test_min_degree_matches_restatement(driver, seed):
     assert order == py_min_degree(n, pairs)
 
 
-@pytest.mark.parametrize("ts,d", [(16, 6), (64, 6), (16, 3)])
-def test_tile_pattern_covers_numeric_factor(driver, ts, d):
+@pytest.mark.parametrize("ts,d,post", [(16, 6, False), (64, 6, False), (16, 3, False), (48, 6, True), (12, 3, True)])
+def test_tile_pattern_covers_numeric_factor(driver, ts, d, post):
     rng = np.random.default_rng(ts + d)
     n = 30
     pairs = random_pairs(rng, n, 55)
-    order, cols = run(driver, n, d, ts, pairs)
+    order, cols = run(driver, n, d, ts, pairs, post=post)
     pos = np.empty(n, int)
     pos[order] = np.arange(n)
     N = n * d
@@ -112,11 +113,14 @@ def test_tile_pattern_covers_numeric_factor(driver, ts, d):
 
 
 def test_lattice_fill_is_moderate(driver):
-    """The 8^3 lattice with 10% long-range edges: the factor has far fewer
-    tiles than the dense lower triangle."""
-    p = synth.lattice_se3(batch=1, side=8)
+    """The 10^3 lattice with 10% long-range edges and 48-wide tiles: the
+    elimination-tree postorder keeps the tile fill well below the dense lower
+    triangle (and below the plain minimum-degree order)."""
+    p = synth.lattice_se3(batch=1, side=10)
     pairs = [tuple(x) for x in p["edge_ij"].tolist()]
-    order, cols = run(driver, 512, 6, 64, pairs)
-    P = len(cols)
-    ntiles = sum(len(c) for c in cols)
-    assert ntiles < 0.8 * P * (P + 1) / 2
+    _, cols_md = run(driver, 1000, 6, 48, pairs)
+    _, cols_po = run(driver, 1000, 6, 48, pairs, post=True)
+    P = len(cols_po)
+    n_md, n_po = sum(len(c) for c in cols_md), sum(len(c) for c in cols_po)
+    assert n_po < n_md
+    assert n_po < 0.5 * P * (P + 1) / 2
