@@ -31,7 +31,9 @@ sys.path.insert(0, ROOT)
 WORKLOAD = dict(name="se3_walk64_b128", batch=128, poses=64, loops=64, iterations=10, lam=1e-3)
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 KERNEL_SOURCES = ["paper_2207_09442_amd/csrc/dnls.hip", "paper_2207_09442_amd/csrc/dense.hpp",
-                  "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/lie.hpp"]
+                  "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/pose_costs.hpp",
+                  "paper_2207_09442_amd/csrc/lie.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_dense_solve_se3_walk64_b128_traffic.txt")
 
 
 def algorithmic_flops(problem: dict, K: int) -> float:
@@ -58,35 +60,56 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "dense_solve_se3_walk64_b128_traffic.json")
+def measured_traffic():
+    """HBM bytes per launch of the mixed-precision solve kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by
+    the same counters' reading on a plain copy of known size), or None if the
+    summary was taken on other kernel sources."""
     try:
-        with open(path) as fh:
-            rec = json.load(fh)
+        with open(TRAFFIC_SUMMARY) as fh:
+            rec = dict(line.split(":", 1) for line in fh.read().splitlines() if ":" in line)
     except OSError:
         return None
+    rec = {k.strip(): v.strip() for k, v in rec.items()}
     if rec.get("source_hash") != kernel_hash():
         return None
-    return rec.get(kernel)
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
-def cpu_baseline(problem: dict, K: int, lam: float, n_graphs: int):
-    """The CPU oracle on the first n_graphs graphs (forward + implicit backward)."""
+def copy_calibration(nbytes: int, reps: int) -> None:
+    """A plain device-to-device copy of nbytes, reps times: the reference
+    kernel whose FETCH_SIZE / WRITE_SIZE readings calibrate the traffic
+    counters (it moves exactly nbytes each way)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def cpu_baseline(problem: dict, K: int, lam: float, n_graphs: int, passes: int):
+    """The CPU oracle on the first n_graphs graphs (forward + implicit
+    backward), repeated `passes` times; returns the time of all passes."""
     import torch
 
     from oracle import solve as S
     gs = S.graphs_of(problem)[:n_graphs]
     t0 = time.perf_counter()
-    res = [S.solve_graph(g, K, lam) for g in gs]
-    seeds = []
-    for b, r in enumerate(res):
-        lo, hi = problem["pose_off"][b], problem["pose_off"][b + 1]
-        _, v = S.pose_error_loss_and_seed(problem["group"], gs[0].G.to_storage(r.X).numpy(),
-                                          problem["poses_gt"][lo:hi])
-        seeds.append(v)
-    grads = [S.implicit_grad_graph(g, r, torch.as_tensor(v)) for g, r, v in zip(gs, res, seeds)]
+    for _ in range(passes):
+        res = [S.solve_graph(g, K, lam) for g in gs]
+        seeds = []
+        for b, r in enumerate(res):
+            lo, hi = problem["pose_off"][b], problem["pose_off"][b + 1]
+            _, v = S.pose_error_loss_and_seed(problem["group"], gs[0].G.to_storage(r.X).numpy(),
+                                              problem["poses_gt"][lo:hi])
+            seeds.append(v)
+        grads = [S.implicit_grad_graph(g, r, torch.as_tensor(v)) for g, r, v in zip(gs, res, seeds)]
     dt = time.perf_counter() - t0
     return dt, res, seeds, grads
 
@@ -97,14 +120,21 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--refine", type=int, default=1)
-    ap.add_argument("--cpu-graphs", type=int, default=48)
+    ap.add_argument("--cpu-graphs", type=int, default=128)
+    ap.add_argument("--cpu-passes", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(graphs are independent, so a multi-GPU run would shard the batch with no "
               "communication; this build runs on a single device).", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(1, args.steps))
+        return
 
     import torch
 
@@ -174,7 +204,7 @@ def main():
     flops = algorithmic_flops(p, K)
     fwd_flops = flops - sum(2 * (6 * 64) ** 2 + 400 * 128 for _ in range(B))
     achieved = fwd_flops / (mixed["fwd_ms"] * 1e-3) / 1e12
-    traffic = measured_traffic("k_dense_solve")
+    traffic = measured_traffic()
     line = {
         "metric": "GN/LM steps/sec incl. implicit-diff backward, mixed vs FP64 at 1e-5 rel err",
         "value": value,
@@ -202,11 +232,12 @@ def main():
     if not args.no_cpu:
         import torch as _t
         ng = min(args.cpu_graphs, B)
-        dt, res, seeds, grads = cpu_baseline(p, K, lam, ng)
-        line["cpu_baseline"] = {"value": ng * K / dt, "unit": "graph-steps/s", "cores": _t.get_num_threads(),
-                                "kind": "oracle",
-                                "sample": f"first {ng} of the {B} graphs, forward (K={K}) + implicit backward, "
-                                          f"{dt:.1f} s"}
+        npass = max(1, args.cpu_passes)
+        dt, res, seeds, grads = cpu_baseline(p, K, lam, ng, npass)
+        line["cpu_baseline"] = {"value": npass * ng * K / dt, "unit": "graph-steps/s",
+                                "cores": _t.get_num_threads(), "kind": "oracle",
+                                "sample": f"{npass} pass(es) over the first {ng} of the {B} graphs, forward "
+                                          f"(K={K}) + implicit backward, {dt:.1f} s"}
         # errors of both GPU paths against the oracle on the sampled graphs
         errs = {}
         for name, r in (("mixed", mixed), ("fp64", fp64)):
