@@ -1,16 +1,20 @@
 """Throughput of the batched DNLS inner step on one MI355X.
 
-One step = the whole hot path over one batch: K Levenberg-Marquardt steps
-(cost evaluation, J^T J / J^T r assembly, damping, Cholesky, triangular
-solves, retraction), the final undamped linearisation that caches the
-factor, and the implicit backward (adjoint solve with the cached factor and
-the per-cost vector-Jacobian products).
+One step = the whole hot path over one batch: K Gauss-Newton /
+Levenberg-Marquardt steps (cost evaluation, J^T J / J^T r assembly, damping,
+Cholesky, triangular solves, retraction), the final undamped linearisation
+that caches the factor, and the implicit backward (adjoint solve with the
+cached factor and the per-cost vector-Jacobian products).
 
-Workload: 128 SE(3) random-walk pose graphs of 64 poses (63 odometry edges,
-64 loop closures, prior on pose 0), 10 LM steps at lambda = 1e-3, dense
-384 x 384 normal equations; float32 linearisation / assembly with float64
-factorisation (mixed), plus the same run in float64 for comparison.
-Inputs are synthetic and resident in device memory before timing starts.
+Default workload (the headline line): 128 SE(3) random-walk pose graphs of
+64 poses (63 odometry edges, 64 loop closures, prior on pose 0), 10 LM steps
+at lambda = 1e-3, dense 384 x 384 normal equations; float32 linearisation /
+assembly with float64 factorisation and one float64 refinement sweep
+(mixed), plus the same run in float64 for comparison.  --workload selects
+one of the other evaluation configurations instead (SE(2) circle, 16^3
+lattice on the block-sparse solver, 256 walks of 32..256 poses, bundle
+adjustment on the Schur path).  Inputs are synthetic and resident in device
+memory before timing starts.
 
 Prints one JSON line.  value = graph-steps per second = B * K / (seconds per step).
 """
@@ -28,28 +32,48 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(name="se3_walk64_b128", batch=128, poses=64, loops=64, iterations=10, lam=1e-3)
+DEFAULT_WORKLOAD = "se3_walk64_b128"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 KERNEL_SOURCES = ["paper_2207_09442_amd/csrc/dnls.hip", "paper_2207_09442_amd/csrc/dense.hpp",
                   "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/pose_costs.hpp",
                   "paper_2207_09442_amd/csrc/lie.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_dense_solve_se3_walk64_b128_traffic.txt")
+COST_FLOPS = 2100     # per pose-graph cost and linearisation: evaluation ~1000 + assembly ~1100
+OBS_FLOPS = 340       # per reprojection cost and linearisation
+BWD_COST_FLOPS = 400  # per cost in the backward (VJP)
 
 
-def algorithmic_flops(problem: dict, K: int) -> float:
-    """FLOPs the method needs per solve+backward (not what the kernels spend):
-    per graph and step n^3/3 (Cholesky) + 2 n^2 (two triangular solves) +
-    2100 per cost (evaluation ~1000, J^T J / J^T r assembly ~1100); the final
-    linearisation adds one factorisation and one linearisation; the backward
-    adds two triangular solves and ~400 per cost."""
+def algorithmic_flops(problem: dict, K: int, factor_flops: float) -> tuple[float, float]:
+    """(solve, backward) FLOPs the method needs (not what the kernels spend).
+    Solve: K + 1 linearisations and factorisations (factor_flops each, from
+    the plan's symbolic analysis) plus 2 n^2 per step for the two triangular
+    solves of every dense graph; bundle adjustment adds the Schur complement
+    per point (k observations: k (k + 1) / 2 camera-pair blocks at
+    2 * 6 * 3 * 6 flops and k E C^-1 products at 2 * 6 * 3 * 3).  Backward:
+    two triangular solves and the VJP per cost."""
     d = 6 if problem["group"] == "SE3" else 3
-    total = 0.0
-    for b in range(len(problem["pose_off"]) - 1):
-        n = d * (problem["pose_off"][b + 1] - problem["pose_off"][b])
-        c = (problem["edge_off"][b + 1] - problem["edge_off"][b]) + (problem["prior_off"][b + 1] - problem["prior_off"][b])
-        step = n ** 3 / 3 + 2 * n ** 2 + 2100 * c
-        total += K * step + (n ** 3 / 3 + 2100 * c) + (2 * n ** 2 + 400 * c)
-    return total
+    B = len(problem["pose_off"]) - 1
+    n_pose = np.diff(problem["pose_off"]).astype(np.float64)
+    costs = np.diff(problem["edge_off"]) + np.diff(problem["prior_off"])
+    n = d * n_pose
+    tri = 2.0 * n ** 2
+    lin = COST_FLOPS * costs.astype(np.float64)
+    if "obs_off" in problem:
+        obs = np.diff(problem["obs_off"]).astype(np.float64)
+        k = np.bincount(problem["obs_pt"], minlength=int(problem["point_off"][-1])).astype(np.float64)
+        schur = np.zeros(B)
+        for b in range(B):
+            kb = k[problem["point_off"][b]:problem["point_off"][b + 1]]
+            schur[b] = np.sum(kb * (kb + 1) / 2 * 216 + kb * 108)
+        lin = lin + OBS_FLOPS * obs + schur
+        bwd_costs = costs + obs
+    else:
+        bwd_costs = costs
+    if problem.get("_sparse"):
+        tri = np.zeros(B)   # 4 nnz(L): below 0.1% of the factorisation on the lattice
+    solve = (K + 1) * factor_flops + float(np.sum((K + 1) * lin + K * tri))
+    backward = float(np.sum(tri + BWD_COST_FLOPS * bwd_costs))
+    return solve, backward
 
 
 def kernel_hash() -> str:
@@ -109,9 +133,15 @@ def cpu_baseline(problem: dict, K: int, lam: float, n_graphs: int, passes: int):
             _, v = S.pose_error_loss_and_seed(problem["group"], gs[0].G.to_storage(r.X).numpy(),
                                               problem["poses_gt"][lo:hi])
             seeds.append(v)
-        grads = [S.implicit_grad_graph(g, r, torch.as_tensor(v)) for g, r, v in zip(gs, res, seeds)]
+        grads = [S.implicit_grad_graph(g, r, torch.as_tensor(v),
+                                       torch.zeros(g.pts.shape[0], 3, dtype=torch.float64) if g.is_ba else None)
+                 for g, r, v in zip(gs, res, seeds)]
     dt = time.perf_counter() - t0
     return dt, res, seeds, grads
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -119,8 +149,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--refine", type=int, default=1)
-    ap.add_argument("--cpu-graphs", type=int, default=128)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
+                    choices=["se2_circle_b1", "se3_walk64_b128", "se3_lattice16_b8", "se3_uneven_b256",
+                             "ba_ring64_b4"])
+    ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
+    ap.add_argument("--cpu-graphs", type=int, default=None,
+                    help="graphs in the CPU oracle sample (default: the whole batch of the headline "
+                         "workload, a few graphs otherwise)")
     ap.add_argument("--cpu-passes", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -139,37 +174,55 @@ def main():
     import torch
 
     import synth
-    from paper_2207_09442_amd import Plan
+    from paper_2207_09442_amd import Plan, project_grad
 
     dev = torch.device("cuda:0")
-    W = WORKLOAD
-    K, lam = W["iterations"], W["lam"]
-    p = synth.walk_se3(batch=W["batch"], n_poses=W["poses"], n_loops=W["loops"])
+    W = synth.WORKLOADS[args.workload]
+    K, lam, solver = W["iterations"], W["lam"], W["solver"]
+    p = W["fn"](**W["kwargs"])
+    ba = solver == "schur"
+    B = len(p["pose_off"]) - 1
     t = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.float64, device=dev).contiguous()
-    em, el, pm, pl = t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"])
-    init = t(p["poses_init"])
-    gt = t(p["poses_gt"])
+    init, gt = t(p["poses_init"]), t(p["poses_gt"])
+    if ba:
+        aux = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+                   prior_logw=t(p["prior_logw"]))
+        pts_init = t(p["points_init"])
+    else:
+        aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
     def run(precision: str, refine: int):
-        plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device=dev)
+        plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=dev)
         poses = init.clone()
+        pts = pts_init.clone() if ba else None
+
+        def solve():
+            return plan.solve_ba(poses, pts, **aux) if ba else plan.solve(poses, *aux)
+
         # seed: tangent gradient of L = sum ||X - X_gt||^2 on the storage at the
         # warm-up solution (an input of the backward, fixed during timing)
-        objective, status = plan.solve(poses, em, el, pm, pl)
-        from paper_2207_09442_amd import project_grad
+        solve()
         seed = project_grad(p["group"], poses.reshape(plan.V, -1), (2 * (poses - gt)).reshape(plan.V, -1))
+
+        def backward(st):
+            if ba:
+                return plan.backward_ba(poses, pts, status=st, seed_cam=seed, **aux)
+            return plan.backward(poses, *aux, st, seed)
+
         stream = torch.cuda.current_stream()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         fwd_ms, bwd_ms = [], []
 
         def one_step(record: bool):
             poses.copy_(init)
+            if ba:
+                pts.copy_(pts_init)
             if record:
                 ev[0].record(stream)
-            obj, st = plan.solve(poses, em, el, pm, pl)
+            obj, st = solve()
             if record:
                 ev[1].record(stream)
-            out = plan.backward(poses, em, el, pm, pl, st, seed)
+            out = backward(st)
             if record:
                 ev[2].record(stream)
             return obj, st, out
@@ -177,34 +230,48 @@ def main():
         for _ in range(args.warmup):
             one_step(False)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        progress(f"{precision}: warm-up done")
+        # per-step events (solve and backward separately; one host sync per step)
         for _ in range(args.steps):
             one_step(True)
             torch.cuda.synchronize()
             fwd_ms.append(ev[0].elapsed_time(ev[1]))
             bwd_ms.append(ev[1].elapsed_time(ev[2]))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        # the timed loop again without per-step host synchronisation: the value
+        progress(f"{precision}: per-step events done, solve {np.mean(fwd_ms):.3f} ms")
+        # the timed loop: K steps back to back, synchronised on both sides
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
             obj, st, out = one_step(False)
         torch.cuda.synchronize()
-        wall2 = time.perf_counter() - t1
-        return dict(plan=plan, poses=poses.cpu().numpy(), status=st.cpu().numpy(), grads={k: v.cpu().numpy() for k, v in out.items()},
-                    seed=seed, ms_step=1e3 * wall2 / args.steps, fwd_ms=float(np.mean(fwd_ms)),
-                    bwd_ms=float(np.mean(bwd_ms)), synced_ms=1e3 * wall / args.steps)
+        wall = time.perf_counter() - t1
+        progress(f"{precision}: timed loop done, {1e3 * wall / args.steps:.3f} ms/step")
+        return dict(plan=plan, poses=poses.cpu().numpy(), status=st.cpu().numpy(),
+                    grads={k: v.cpu().numpy() for k, v in out.items()}, ms_step=1e3 * wall / args.steps,
+                    fwd_ms=float(np.mean(fwd_ms)), bwd_ms=float(np.mean(bwd_ms)))
 
-    mixed = run("mixed", args.refine)
-    fp64 = run("fp64", 0)
-    B = W["batch"]
+    main_prec = W["precision"]
+    runs = {}
+    if main_prec == "mixed":
+        runs["mixed"] = run("mixed", args.refine)
+    runs["fp64"] = run("fp64", 0)
+    head = runs[main_prec]
     graph_steps = B * K
-    value = graph_steps / (mixed["ms_step"] * 1e-3)
-    flops = algorithmic_flops(p, K)
-    fwd_flops = flops - sum(2 * (6 * 64) ** 2 + 400 * 128 for _ in range(B))
-    achieved = fwd_flops / (mixed["fwd_ms"] * 1e-3) / 1e12
-    traffic = measured_traffic()
+    value = graph_steps / (head["ms_step"] * 1e-3)
+    f_alg, f_exec = head["plan"].flops()
+    if solver == "sparse":
+        p["_sparse"] = True
+    solve_flops, bwd_flops = algorithmic_flops(p, K, f_alg)
+    p.pop("_sparse", None)
+    achieved = solve_flops / (head["fwd_ms"] * 1e-3) / 1e12
+    single_kernel = solver == "dense"
+    kernel = ("k_dense_solve<3, true>" if main_prec == "mixed" else "k_dense_solve<%d, false>"
+              % (3 if p["group"] == "SE3" else 2)) if single_kernel else "solve (all kernels of dnls_solve)"
+    cfg = {"workload": args.workload, "batch": B, "iterations": K,
+           "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
+           "refine": args.refine if main_prec == "mixed" else 0, "solver": solver}
+    if args.workload == "se3_walk64_b128":
+        cfg.update(poses=64, loop_closures=64)
     line = {
         "metric": "GN/LM steps/sec incl. implicit-diff backward, mixed vs FP64 at 1e-5 rel err",
         "value": value,
@@ -212,55 +279,72 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": mixed["ms_step"],
+        "ms_per_step": head["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": W["name"], "batch": B, "poses": W["poses"], "loop_closures": W["loops"],
-                   "iterations": K, "optimizer": "LM", "lambda": lam, "precision": "mixed",
-                   "refine": args.refine, "solver": "dense"},
-        "fp64": {"value": graph_steps / (fp64["ms_step"] * 1e-3), "ms_per_step": fp64["ms_step"],
-                 "fwd_ms": fp64["fwd_ms"], "bwd_ms": fp64["bwd_ms"]},
-        "mixed_breakdown": {"fwd_ms": mixed["fwd_ms"], "bwd_ms": mixed["bwd_ms"]},
-        "roofline": {"bound": "mfma", "kernel": "k_dense_solve", "achieved": achieved,
+        "config": cfg,
+        "breakdown": {"solve_ms": head["fwd_ms"], "backward_ms": head["bwd_ms"]},
+        "roofline": {"bound": "mfma", "kernel": kernel, "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": traffic,
-                     "algorithmic_flops_per_launch": fwd_flops},
+                     "traffic": measured_traffic() if args.workload == DEFAULT_WORKLOAD else None,
+                     "algorithmic_flops_per_launch": solve_flops,
+                     "factor_flops_algorithmic": f_alg, "factor_flops_executed": f_exec},
     }
-    if not args.no_cpu:
+    if main_prec == "mixed":
+        f = runs["fp64"]
+        line["fp64"] = {"value": graph_steps / (f["ms_step"] * 1e-3), "ms_per_step": f["ms_step"],
+                        "solve_ms": f["fwd_ms"], "backward_ms": f["bwd_ms"]}
+    if args.workload == "se2_circle_b1":
+        line["us_per_graph_step"] = 1e3 * head["ms_step"] / K
+    # the oracle's sparse path on a 4096-pose lattice takes minutes per graph: no CPU sample there
+    default_cpu = {"se3_walk64_b128": 128, "se2_circle_b1": 1, "se3_uneven_b256": 32,
+                   "ba_ring64_b4": 4, "se3_lattice16_b8": 0}[args.workload]
+    ng = min(B, default_cpu if args.cpu_graphs is None else args.cpu_graphs)
+    if not args.no_cpu and ng > 0:
+        progress(f"CPU oracle on {ng} graph(s)")
         import torch as _t
-        ng = min(args.cpu_graphs, B)
         npass = max(1, args.cpu_passes)
         dt, res, seeds, grads = cpu_baseline(p, K, lam, ng, npass)
         line["cpu_baseline"] = {"value": npass * ng * K / dt, "unit": "graph-steps/s",
                                 "cores": _t.get_num_threads(), "kind": "oracle",
                                 "sample": f"{npass} pass(es) over the first {ng} of the {B} graphs, forward "
                                           f"(K={K}) + implicit backward, {dt:.1f} s"}
-        # errors of both GPU paths against the oracle on the sampled graphs
-        errs = {}
-        for name, r in (("mixed", mixed), ("fp64", fp64)):
-            pe, ge = 0.0, 0.0
-            # backward of the GPU runs used the GPU seed; recompute with the oracle's seeds
-            full = np.zeros((p["pose_off"][-1], 6))
-            for b in range(ng):
-                full[p["pose_off"][b]:p["pose_off"][b + 1]] = seeds[b]
-            st_dev = torch.as_tensor(r["status"], device=dev)
-            poses_dev = t(r["poses"])
-            gr = r["plan"].backward(poses_dev, em, el, pm, pl, st_dev, t(full))
-            gr = {k: v.cpu().numpy() for k, v in gr.items()}
-            for b in range(ng):
-                lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
-                e0, e1 = p["edge_off"][b], p["edge_off"][b + 1]
-                ref = res[b].X[:, :3, :].numpy()
-                pe = max(pe, np.linalg.norm(r["poses"][lo:hi] - ref) / np.linalg.norm(ref))
-                mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel()])
-                theirs = np.concatenate([grads[b]["edge_logw"].numpy(), grads[b]["tau"].numpy().ravel()])
-                ge = max(ge, np.linalg.norm(mine - theirs) / np.linalg.norm(theirs))
-            errs[name] = {"pose_rel_err_max": pe, "grad_rel_err_max": ge}
-        line["error_vs_oracle"] = errs
+        if not ba:
+            line["error_vs_oracle"] = errors_vs_oracle(p, runs, res, seeds, grads, aux, ng, t, dev)
     print(json.dumps(line), flush=True)
+
+
+def errors_vs_oracle(p, runs, res, seeds, grads, aux, ng, t, dev):
+    """Pose and gradient errors of the GPU runs against the oracle on the
+    sampled graphs (the backward rerun with the oracle's seeds)."""
+    import torch
+
+    from oracle import lie
+    grp = lie.SE3 if p["group"] == "SE3" else lie.SE2
+    d = 6 if p["group"] == "SE3" else 3
+    errs = {}
+    for name, r in runs.items():
+        pe, ge = 0.0, 0.0
+        full = np.zeros((p["pose_off"][-1], d))
+        for b in range(ng):
+            full[p["pose_off"][b]:p["pose_off"][b + 1]] = seeds[b]
+        st_dev = torch.as_tensor(r["status"], device=dev)
+        gr = r["plan"].backward(t(r["poses"]), *aux, st_dev, t(full))
+        gr = {k: v.cpu().numpy() for k, v in gr.items()}
+        for b in range(ng):
+            lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
+            e0, e1 = p["edge_off"][b], p["edge_off"][b + 1]
+            ref = grp.to_storage(res[b].X).numpy()
+            pe = max(pe, np.linalg.norm(r["poses"][lo:hi] - ref) / np.linalg.norm(ref))
+            mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel()])
+            theirs = np.concatenate([grads[b]["edge_logw"].detach().numpy(),
+                                     grads[b]["tau"].detach().numpy().ravel()])
+            ge = max(ge, np.linalg.norm(mine - theirs) / np.linalg.norm(theirs))
+        errs[name] = {"pose_rel_err_max": pe, "grad_rel_err_max": ge}
+    return errs
 
 
 if __name__ == "__main__":

@@ -165,6 +165,14 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* problem,
 dnls_status dnls_plan_workspace(dnls_plan plan, size_t* solve_ws, size_t* factor_bytes,
                                 size_t* backward_ws);
 
+/* Work of one numeric factorisation of the whole batch, from the symbolic
+ * analysis (host values, either pointer may be NULL).  algorithmic: the
+ * block Cholesky of each graph's d x d block pattern with its fill in the
+ * plan's elimination order (DENSE: (6N)^3/3 per graph, SCHUR: the camera
+ * system), i.e. the flops the method needs (Section 4.2); executed: what the
+ * kernels run, padded panels and whole tiles included. */
+dnls_status dnls_plan_flops(dnls_plan plan, double* algorithmic, double* executed);
+
 /* Run K optimizer steps and the final linearisation on `stream` (a
  * hipStream_t, NULL = default stream).  Enqueues kernels only. */
 dnls_status dnls_solve(dnls_plan plan, const dnls_solve_args* args, void* stream);

@@ -77,13 +77,14 @@ def lib():
         L.dnls_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_Problem), ctypes.POINTER(_Options)]
         L.dnls_plan_workspace.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.dnls_plan_flops.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.dnls_solve.argtypes = [_vp, ctypes.POINTER(_SolveArgs), _vp]
         L.dnls_backward.argtypes = [_vp, ctypes.POINTER(_BackwardArgs), _vp]
         L.dnls_project_grad.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.dnls_plan_destroy.argtypes = [_vp]
         L.dnls_last_error.restype = ctypes.c_char_p
         L.dnls_version.restype = ctypes.c_char_p
-        for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_solve", "dnls_backward",
+        for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_plan_flops", "dnls_solve", "dnls_backward",
                   "dnls_project_grad", "dnls_plan_destroy"]:
             getattr(L, f).restype = ctypes.c_int
         _LIB = L
@@ -164,6 +165,13 @@ class Plan:
         self.solve_ws_bytes, self.factor_bytes, self.backward_ws_bytes = sw.value, fb.value, bw.value
         self.workspace = torch.empty(max(1, sw.value, bw.value) + 256, dtype=torch.uint8, device=self.device)
         self.factor = torch.empty(max(1, fb.value) + 256, dtype=torch.uint8, device=self.device)
+
+    def flops(self):
+        """(algorithmic, executed) flops of one numeric factorisation of the
+        whole batch (dnls_plan_flops)."""
+        a, e = ctypes.c_double(), ctypes.c_double()
+        _check(lib().dnls_plan_flops(self._h, ctypes.byref(a), ctypes.byref(e)), "dnls_plan_flops")
+        return a.value, e.value
 
     @staticmethod
     def _aligned(t):

@@ -631,6 +631,8 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
     if (g.nprior > kBT) return fail(DNLS_ERR_UNSUPPORTED, "at most 256 camera priors per problem");
     g.n = 6 * g.ncam;
     g.npad = std::max(kNB, (g.n + kNB - 1) / kNB * kNB);
+    p->flops_alg += double(g.n) * g.n * g.n / 3.0;
+    p->flops_exec += double(g.npad) * g.npad * g.npad / 3.0;
     if (g.npad > kMaxDenseN) return fail(DNLS_ERR_UNSUPPORTED, "camera system larger than the dense limit");
     g.fac_off = fac;
     fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;

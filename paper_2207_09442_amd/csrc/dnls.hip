@@ -546,6 +546,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
       return fail(DNLS_ERR_UNSUPPORTED, "dense solver supports at most " + std::to_string(kMaxDenseN) +
                                             " unknowns per graph");
     }
+    p->flops_alg += double(g.n) * g.n * g.n / 3.0;
+    p->flops_exec += double(g.npad) * g.npad * g.npad / 3.0;
     g.fac_off = fac;
     // L (npad x npad) + augmented right-hand-side tile (16 x npad) + panel inverses
     fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
@@ -616,6 +618,13 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   p->bwd_bytes = ws;
   p->fac_bytes = (size_t)fac * sizeof(double);
   *out = p;
+  return DNLS_OK;
+}
+
+dnls_status dnls_plan_flops(dnls_plan p, double* algorithmic, double* executed) {
+  if (!p) return fail(DNLS_ERR_INVALID_ARG, "null plan");
+  if (algorithmic) *algorithmic = p->flops_alg;
+  if (executed) *executed = p->flops_exec;
   return DNLS_OK;
 }
 

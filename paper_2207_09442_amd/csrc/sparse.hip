@@ -649,6 +649,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     std::vector<std::pair<int, int>> bl;
     for (auto& kv : blocks) bl.push_back(kv.first);
     const sym::TileStructure ts = sym::tile_symbolic(g.npose, d, kTS, lpos, bl);
+    p->flops_alg += sym::block_flops(sym::block_column_counts(g.npose, adj, lpos), d);
+    p->flops_exec += sym::tile_flops(ts, kTS);
     g.P = ts.P;
     maxP = std::max(maxP, g.P);
     g.ntile = (int)ts.row_idx.size();

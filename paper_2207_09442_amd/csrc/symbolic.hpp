@@ -126,6 +126,50 @@ inline std::vector<int> postorder_positions(int n, const std::vector<std::vector
   return newpos;
 }
 
+// Number of off-diagonal non-zero blocks in every block column of the
+// Cholesky factor when the graph is eliminated in the order pos[] (bitset
+// elimination: each eliminated node joins its later neighbours into a
+// clique).  Indexed by elimination position.
+inline std::vector<int> block_column_counts(int n, const std::vector<std::vector<int>>& adj,
+                                            const std::vector<int>& pos) {
+  const int W = (n + 63) / 64;
+  std::vector<uint64_t> bits((size_t)n * W, 0);
+  auto row = [&](int j) { return bits.data() + (size_t)j * W; };
+  for (int v = 0; v < n; ++v)
+    for (int u : adj[v]) {
+      const int a = pos[v], b = pos[u];
+      if (a < b) row(a)[b >> 6] |= uint64_t(1) << (b & 63);
+      else if (b < a) row(b)[a >> 6] |= uint64_t(1) << (a & 63);
+    }
+  std::vector<int> cnt(n, 0);
+  for (int j = 0; j < n; ++j) {
+    const uint64_t* rj = row(j);
+    int c = 0, first = -1;
+    for (int w = 0; w < W; ++w) {
+      c += popcount64(rj[w]);
+      if (first < 0 && rj[w]) first = w * 64 + __builtin_ctzll(rj[w]);
+    }
+    cnt[j] = c;
+    // the structure of column j (minus its first row) joins the first row's column
+    if (first >= 0) {
+      uint64_t* rp = row(first);
+      for (int w = 0; w < W; ++w) rp[w] |= rj[w];
+      rp[first >> 6] &= ~(uint64_t(1) << (first & 63));
+    }
+  }
+  return cnt;
+}
+
+// Flops of the block Cholesky with d x d blocks, given the off-diagonal
+// block count m_j of every block column: diagonal factor d^3/3, triangular
+// solves m_j d^3, updates of the m_j (m_j + 1) / 2 block pairs 2 d^3 each.
+inline double block_flops(const std::vector<int>& cnt, int d) {
+  const double d3 = double(d) * d * d;
+  double f = 0.0;
+  for (int m : cnt) f += d3 / 3.0 + m * d3 + double(m) * (m + 1) * d3;
+  return f;
+}
+
 struct TileStructure {
   int P = 0;                       // tile rows = tile columns
   std::vector<int> col_ptr;        // [P+1]

@@ -1,6 +1,7 @@
 // CPU driver for the host symbolic analysis (tests only): reads
 //   npose d ts m  then m lines "a b" (pose pairs)
-// and prints the minimum-degree order and the tile structure.
+// and prints the minimum-degree order, the tile structure and the block
+// column counts of the factor.
 #include <cstdio>
 #include <utility>
 #include <vector>
@@ -34,5 +35,9 @@ int main(int argc, char**) {
   std::printf("\nrow_idx");
   for (int v : t.row_idx) std::printf(" %d", v);
   std::printf("\nflops %.6e\n", dnls::sym::tile_flops(t, ts));
+  const std::vector<int> cnt = dnls::sym::block_column_counts(n, adj, pos);
+  std::printf("counts");
+  for (int v : cnt) std::printf(" %d", v);
+  std::printf("\nblock_flops %.6e\n", dnls::sym::block_flops(cnt, d));
   return 0;
 }

@@ -28,7 +28,7 @@ def _declared():
 
 def test_header_declares_the_entry_points():
     names = _declared()
-    for n in ["dnls_plan_create", "dnls_plan_workspace", "dnls_solve", "dnls_backward",
+    for n in ["dnls_plan_create", "dnls_plan_workspace", "dnls_plan_flops", "dnls_solve", "dnls_backward",
               "dnls_project_grad", "dnls_plan_destroy", "dnls_last_error", "dnls_version"]:
         assert n in names
 

@@ -5,7 +5,10 @@
   join its neighbours into a clique) on random graphs;
 * the tile pattern contains every non-zero of the numerical Cholesky factor
   of a random SPD matrix with the graph's block pattern (brute force), and is
-  closed under tile-level elimination."""
+  closed under tile-level elimination;
+* the block column counts equal the non-zero blocks of that numerical
+  factor column by column, and on a complete graph the block flop count is
+  the dense one, close to (n d)^3 / 3."""
 import os
 import subprocess
 
@@ -36,6 +39,8 @@ def run(exe, n, d, ts, pairs, post=False):
     col_ptr = [int(x) for x in vals["col_ptr"]]
     rows = [int(x) for x in vals["row_idx"]]
     cols = [rows[col_ptr[J]:col_ptr[J + 1]] for J in range(int(vals["P"][0]))]
+    run.counts = [int(x) for x in vals["counts"]]
+    run.block_flops = float(vals["block_flops"][0])
     return order, cols
 
 
@@ -124,3 +129,40 @@ def test_lattice_fill_is_moderate(driver):
     n_md, n_po = sum(len(c) for c in cols_md), sum(len(c) for c in cols_po)
     assert n_po < n_md
     assert n_po < 0.5 * P * (P + 1) / 2
+
+
+@pytest.mark.parametrize("seed,post", [(3, False), (4, True)])
+def test_block_counts_equal_numeric_factor(driver, seed, post):
+    rng = np.random.default_rng(seed)
+    n, d = 36, 3
+    pairs = random_pairs(rng, n, 60)
+    order, _ = run(driver, n, d, 12, pairs, post=post)
+    counts = run.counts
+    pos = np.empty(n, int)
+    pos[order] = np.arange(n)
+    N = n * d
+    H = np.zeros((N, N))
+    for a, b in pairs:
+        blk = rng.normal(size=(d, d))
+        ra, rb = pos[a] * d, pos[b] * d
+        H[ra:ra + d, rb:rb + d] += blk
+        H[rb:rb + d, ra:ra + d] += blk.T
+    H += np.eye(N) * (np.abs(H).sum(1).max() + 1.0)
+    L = np.linalg.cholesky(H)
+    for j in range(n):
+        below = L[(j + 1) * d:, j * d:(j + 1) * d].reshape(n - j - 1, d, d)
+        nzb = int(np.sum(np.abs(below).max(axis=(1, 2)) > 1e-13))
+        assert counts[j] == nzb, (j, counts[j], nzb)
+
+
+def test_block_flops_of_complete_graph(driver):
+    n, d = 12, 6
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    run(driver, n, d, 12, pairs)
+    assert run.counts == list(range(n - 1, -1, -1))
+    # sum_j d^3/3 + m d^3 + m(m+1) d^3 with m = n-1-j
+    m = np.arange(n)
+    expect = float(np.sum(d ** 3 / 3 + m * d ** 3 + m * (m + 1) * d ** 3))
+    assert abs(run.block_flops - expect) < 1e-9 * expect
+    N = n * d
+    assert abs(run.block_flops - N ** 3 / 3) < 0.2 * N ** 3 / 3
