@@ -86,37 +86,38 @@ __device__ __forceinline__ d4v load_tile(const double* t, int ldt) {
   return acc;
 }
 
-// Broadcast of lane q of each 16-lane row to the whole row (DPP row_newbcast).
-__device__ __forceinline__ int bcast16_i(int v, int q) {
-  switch (q) {
-    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x150, 0xf, 0xf, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x151, 0xf, 0xf, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x152, 0xf, 0xf, false);
-    case 3: return __builtin_amdgcn_update_dpp(0, v, 0x153, 0xf, 0xf, false);
-    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x154, 0xf, 0xf, false);
-    case 5: return __builtin_amdgcn_update_dpp(0, v, 0x155, 0xf, 0xf, false);
-    case 6: return __builtin_amdgcn_update_dpp(0, v, 0x156, 0xf, 0xf, false);
-    case 7: return __builtin_amdgcn_update_dpp(0, v, 0x157, 0xf, 0xf, false);
-    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x158, 0xf, 0xf, false);
-    case 9: return __builtin_amdgcn_update_dpp(0, v, 0x159, 0xf, 0xf, false);
-    case 10: return __builtin_amdgcn_update_dpp(0, v, 0x15a, 0xf, 0xf, false);
-    case 11: return __builtin_amdgcn_update_dpp(0, v, 0x15b, 0xf, 0xf, false);
-    case 12: return __builtin_amdgcn_update_dpp(0, v, 0x15c, 0xf, 0xf, false);
-    case 13: return __builtin_amdgcn_update_dpp(0, v, 0x15d, 0xf, 0xf, false);
-    case 14: return __builtin_amdgcn_update_dpp(0, v, 0x15e, 0xf, 0xf, false);
-    default: return __builtin_amdgcn_update_dpp(0, v, 0x15f, 0xf, 0xf, false);
-  }
-}
+// Broadcast of lane q of each 16-lane row to the whole row: one 64-bit DPP
+// move with row_newbcast (every source lane is valid, so no previous value
+// is needed).
 __device__ __forceinline__ double bcast16(double v, int q) {
-  return __hiloint2double(bcast16_i(__double2hiint(v), q), bcast16_i(__double2loint(v), q));
+  switch (q) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x150, 0xf, 0xf, true);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x151, 0xf, 0xf, true);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x152, 0xf, 0xf, true);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0x153, 0xf, 0xf, true);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0x154, 0xf, 0xf, true);
+    case 5: return __builtin_amdgcn_mov_dpp(v, 0x155, 0xf, 0xf, true);
+    case 6: return __builtin_amdgcn_mov_dpp(v, 0x156, 0xf, 0xf, true);
+    case 7: return __builtin_amdgcn_mov_dpp(v, 0x157, 0xf, 0xf, true);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x158, 0xf, 0xf, true);
+    case 9: return __builtin_amdgcn_mov_dpp(v, 0x159, 0xf, 0xf, true);
+    case 10: return __builtin_amdgcn_mov_dpp(v, 0x15a, 0xf, 0xf, true);
+    case 11: return __builtin_amdgcn_mov_dpp(v, 0x15b, 0xf, 0xf, true);
+    case 12: return __builtin_amdgcn_mov_dpp(v, 0x15c, 0xf, 0xf, true);
+    case 13: return __builtin_amdgcn_mov_dpp(v, 0x15d, 0xf, 0xf, true);
+    case 14: return __builtin_amdgcn_mov_dpp(v, 0x15e, 0xf, 0xf, true);
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15f, 0xf, 0xf, true);
+  }
 }
 
 // Cholesky factor and inverse of the 16x16 SPD tile at t (stride ldt, lower
 // part read) on one wave: lane i (i = lane % 16) owns row i; the column
-// values each step needs are broadcast within the 16-lane row by DPP, and
-// 1/L_kk from the factorisation is reused by the inverse.  Writes L (upper
-// part zero) back to t and L^-1 to w.  Returns false if a pivot is not
-// positive (NaN included).
+// values each step needs are broadcast within the 16-lane row by DPP.
+// Entries above the diagonal are carried along unmasked (they never feed the
+// lower part) and cleared at the end.  The inverse is formed from unscaled
+// rows y_i = e_i - sum_{k<i} (L_ik / L_kk) y_k, then L^-1 row i = y_i / L_ii,
+// reusing 1/L_kk from the factorisation.  Writes L (upper part zero) back to
+// t and L^-1 to w.  Returns false if a pivot is not positive (NaN included).
 __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int ldw) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
@@ -124,36 +125,33 @@ __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int l
 #pragma unroll
   for (int q = 0; q < 16; ++q) a[q] = t[i * ldt + q];
   bool ok = true;
+  double myrd = 0.0;
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const double piv = bcast16(a[p], p);
     ok = ok && (piv > 0.0);
     const double rd = rsqrt(piv);            // 1 / L_pp
     rdv[p] = rd;
-    const double lip = (i > p) ? a[p] * rd : (i == p ? piv * rd : 0.0);
+    myrd = (i == p) ? rd : myrd;
+    const double lip = a[p] * rd;            // L_ip for i >= p (L_pp = piv / sqrt(piv))
     a[p] = lip;
 #pragma unroll
     for (int q = p + 1; q < 16; ++q) a[q] = __builtin_fma(-lip, bcast16(lip, q), a[q]);
   }
+  double y[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (q > i) ? 0.0 : a[q];
-  // X = L^-1, lane i owns row i:  X[i] = (e_i - sum_{k<i} L[i][k] X[k]) / L[i][i]
-  double x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = (c == i) ? 1.0 : 0.0;
+  for (int c = 0; c < 16; ++c) y[c] = (c == i) ? 1.0 : 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
+    const double coef = (k < i) ? a[k] * rdv[k] : 0.0;
 #pragma unroll
-    for (int c = 0; c <= k; ++c) x[c] = (i == k) ? x[c] * rdv[k] : x[c];
-    const double lik = (i > k) ? a[k] : 0.0;
-#pragma unroll
-    for (int c = 0; c <= k; ++c) x[c] = __builtin_fma(-lik, bcast16(x[c], k), x[c]);
+    for (int c = 0; c <= k; ++c) y[c] = __builtin_fma(-coef, bcast16(y[c], k), y[c]);
   }
   if (lane < 16) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      t[i * ldt + q] = a[q];
-      w[i * ldw + q] = x[q];
+      t[i * ldt + q] = (q > i) ? 0.0 : a[q];
+      w[i * ldw + q] = y[q] * myrd;
     }
   }
   return ok;
@@ -360,47 +358,75 @@ __device__ __forceinline__ void panel_inv_matvec(const double* __restrict__ W, c
   __syncthreads();
 }
 
-// x <- L^-T x for x in LDS (length npad): right-looking by 64-row panels,
-// each thread owns whole columns of the update (no reductions).
+// x <- L^-T x (x in LDS, length npad), each thread owning whole columns of
+// the update (no reductions).  Per panel J (descending):
+// x_J = W_J^T x_J, then x[0:r0] -= L[r0:r0+64][0:r0]^T x_J.  The L loads of
+// the update do not depend on x, so they are issued before the W_J product
+// and their latency overlaps it.
 __device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
                                              double* x, DenseLds& s) {
   const int P = npad / kNB;
   for (int J = P - 1; J >= 0; --J) {
     const int r0 = kNB * J;
-    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, false, s);
-    if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
-    // x[0:r0] -= L[r0:r0+64][0:r0]^T x_J
-    for (int c = threadIdx.x; c < r0; c += kNT) {
-      double l[kNB];
+    const int c = threadIdx.x;
+    double l[kNB];
+    if (c < r0) {
 #pragma unroll
       for (int r = 0; r < kNB; ++r) l[r] = L[(size_t)(r0 + r) * npad + c];
+    }
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, false, s);
+    if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
+    if (c < r0) {
       double acc = 0.0;
 #pragma unroll
       for (int r = 0; r < kNB; ++r) acc += l[r] * s.vec[r];
       x[c] -= acc;
     }
+    for (int c2 = c + kNT; c2 < r0; c2 += kNT) {
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) l[r] = L[(size_t)(r0 + r) * npad + c2];
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kNB; ++r) acc += l[r] * s.vec[r];
+      x[c2] -= acc;
+    }
     __syncthreads();
   }
 }
 
-// x <- L^-1 x for x in LDS (length npad): right-looking by panels, thread per row.
+// x <- L^-1 x (x in LDS).  Per panel J (ascending): x_J = W_J x_J, then
+// x[r] -= L[r][r0:r0+64] x_J for the rows below; the row loads are issued
+// before the W_J product.
 __device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
                                            double* x, DenseLds& s) {
   const int P = npad / kNB;
   for (int J = 0; J < P; ++J) {
     const int r0 = kNB * J;
+    const int r = r0 + kNB + threadIdx.x;
+    d4v v[kNB / 4];
+    if (r < npad) {
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0);
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
+    }
     panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, true, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
-    for (int r = r0 + kNB + threadIdx.x; r < npad; r += kNT) {
-      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0);
-      d4v v[kNB / 4];
+    if (r < npad) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kNB / 4; ++q)
+        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
+      x[r] -= acc;
+    }
+    for (int r2 = r + kNT; r2 < npad; r2 += kNT) {
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r2 * npad + r0);
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q)
         acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
-      x[r] -= acc;
+      x[r2] -= acc;
     }
     __syncthreads();
   }

@@ -50,9 +50,10 @@ struct SpDesc {
   int ntile;           // non-zero tiles of the factor
   int tix_off;         // tile-id table [P x P] offset
   int col_off;         // column pointer offset (P + 1 entries)
+  int row_off;         // row pointer offset (P + 1 entries)
   int od0, nod;        // off-diagonal Hessian blocks
   int nvec;            // vector length (P x tile size)
-  long long vec_off;   // doubles: 3 vectors of nvec in the workspace
+  long long vec_off;   // doubles: 4 vectors of nvec in the workspace
   long long pool_off;  // doubles: tile pool
   long long winv_off;  // doubles: inverses of the diagonal tiles
 };
@@ -102,7 +103,10 @@ struct dnls_plan_s {
   int* d_tix = nullptr;
   int* d_colptr = nullptr;
   int* d_rowidx = nullptr;
+  int* d_rowptr = nullptr;
+  int* d_rowcol = nullptr;
   std::vector<int> sp_ntrsm;
+  std::vector<int> sp_nrow;       // per tile row: widest row (off-diagonal tiles) over the batch
   std::vector<long long> sp_npair;
   int sp_maxP = 0;
   size_t sp_off[8] = {0};

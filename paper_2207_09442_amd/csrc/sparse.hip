@@ -48,6 +48,8 @@ struct SpArgs {
   const int* tix;          // tile ids: [tix_off + I * P + J], -1 if zero
   const int* colptr;       // [col_off + J] .. [col_off + J + 1] -> rowidx
   const int* rowidx;       // tile rows of each column, diagonal first
+  const int* rowptr;       // [row_off + I] .. [row_off + I + 1] -> rowcol
+  const int* rowcol;       // tile columns J < I of each tile row
   double* poses;
   const double* edge_meas;
   const double* edge_logw;
@@ -60,7 +62,7 @@ struct SpArgs {
   double* ws64;
   float* ws32;
   double* ycost;
-  double* vec;             // per graph: [3][nvec]: step, right-hand side, residual
+  double* vec;             // per graph: [4][nvec]: step, right-hand side, work, forward result
   double* partial;
   int* failed;
   double* lastobj;
@@ -369,84 +371,171 @@ __global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
     for (int r = 0; r < 4; ++r) T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
-// v[0:48] <- W v or W^T v for a 48x48 lower-triangular tile inverse (global);
-// threads 0..47 produce the result into out (LDS).  All threads call.
-__device__ __forceinline__ void tile_inv_matvec(const double* W, const double* v, double* out, bool lower) {
+// ---------------------------------------------------------------------------
+// Triangular solves L L^T x = b as sweeps of one launch per tile column
+// (forward) and per tile row (backward); every tile of the column / row is
+// handled by its own workgroup, so each launch touches distinct targets.
+// Vector slots per graph (nvec doubles each): 0 step x, 1 right-hand side,
+// 2 work vector b, 3 forward result y.
+// ---------------------------------------------------------------------------
+constexpr int kSW = kTS + 1;       // LDS row stride of the solve kernels
+
+__device__ __forceinline__ double* slot(const SpArgs& a, const SpDesc& g, int k) {
+  return a.vec + g.vec_off + (long long)k * g.nvec;
+}
+
+// stage a 48 x 48 tile (row-major, global) into LDS with stride kSW
+__device__ __forceinline__ void stage_tile(double* dst, const double* src) {
+  for (int e = threadIdx.x; e < kTT; e += blockDim.x) dst[(e / kTS) * kSW + e % kTS] = src[e];
+}
+
+// forward step of column J: x_J = W_J b_J; b_I -= L_IJ x_J for the tiles I of the column
+__global__ void __launch_bounds__(kTW) k_sp_fwd(SpArgs a, int J, int src, int dst) {
+  __shared__ double Wl[kTS * kSW];
+  __shared__ double T[kTS * kSW];
+  __shared__ double bv[kTS], yv[kTS];
+  __shared__ double part[kTW / kTS][kTS];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || J >= g.P) return;
+  const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
+  const int t = blockIdx.x;
+  if (t > c1 - c0 - 1) return;
+  double* bvec = slot(a, g, src);
+  stage_tile(Wl, a.factor + g.winv_off + (size_t)J * kTT);
+  int I = -1;
+  if (t > 0) {
+    I = a.rowidx[c0 + t];
+    stage_tile(T, tile_ptr(a, g, I, J));
+  }
+  if (threadIdx.x < kTS) bv[threadIdx.x] = bvec[J * kTS + threadIdx.x];
+  __syncthreads();
   if (threadIdx.x < kTS) {
     const int c = threadIdx.x;
     double acc = 0.0;
-    if (lower)
-      for (int k = 0; k <= c; ++k) acc += W[c * kTS + k] * v[k];
-    else
-      for (int r = c; r < kTS; ++r) acc += W[r * kTS + c] * v[r];
-    out[c] = acc;
+    for (int k = 0; k <= c; ++k) acc += Wl[c * kSW + k] * bv[k];
+    yv[c] = acc;
   }
   __syncthreads();
+  if (t == 0) {
+    if (threadIdx.x < kTS) slot(a, g, dst)[J * kTS + threadIdx.x] = yv[threadIdx.x];
+    return;
+  }
+  // rows r = tid % 48, k range quarter q = tid / 48
+  constexpr int NQ = kTW / kTS, KQ = kTS / NQ;
+  const int r = threadIdx.x % kTS, q = threadIdx.x / kTS;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = q * KQ; k < q * KQ + KQ; ++k) acc += T[r * kSW + k] * yv[k];
+  part[q][r] = acc;
+  __syncthreads();
+  if (threadIdx.x < kTS) {
+    double s = 0.0;
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) s += part[qq][threadIdx.x];
+    bvec[I * kTS + threadIdx.x] -= s;
+  }
 }
 
-// x <- (L L^T)^-1 x on the graph's tile factor (x global, permuted order)
-__device__ void sp_solve(const SpArgs& a, const SpDesc& g, double* x, double* sv, double* red) {
-  // forward: right-looking by tile columns
-  for (int J = 0; J < g.P; ++J) {
-    tile_inv_matvec(a.factor + g.winv_off + (size_t)J * kTT, x + J * kTS, sv, true);
-    if (threadIdx.x < kTS) x[J * kTS + threadIdx.x] = sv[threadIdx.x];
-    const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
-    const int m = c1 - c0 - 1;
-    for (int e = threadIdx.x; e < m * kTS; e += blockDim.x) {
-      const int I = a.rowidx[c0 + 1 + e / kTS], r = e % kTS;
-      const double* row = tile_ptr(a, g, I, J) + r * kTS;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < kTS; ++k) acc += row[k] * sv[k];
-      x[I * kTS + r] -= acc;
-    }
-    __syncthreads();
+// backward step of row I: x_I = W_I^T z_I; z_J -= L_IJ^T x_I for the tiles J of the row
+__global__ void __launch_bounds__(kTW) k_sp_bwd(SpArgs a, int I, int zs, int dst) {
+  __shared__ double Wl[kTS * kSW];
+  __shared__ double T[kTS * kSW];
+  __shared__ double zv[kTS], yv[kTS];
+  __shared__ double part[kTW / kTS][kTS];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || I >= g.P) return;
+  const int r0 = a.rowptr[g.row_off + I], r1 = a.rowptr[g.row_off + I + 1];
+  const int t = blockIdx.x;
+  if (t > r1 - r0) return;
+  double* z = slot(a, g, zs);
+  stage_tile(Wl, a.factor + g.winv_off + (size_t)I * kTT);
+  int J = -1;
+  if (t > 0) {
+    J = a.rowcol[r0 + t - 1];
+    stage_tile(T, tile_ptr(a, g, I, J));
   }
-  // backward: x_J = W^T (x_J - sum_I L_IJ^T x_I)
-  const int nparts = blockDim.x / kTS;
-  for (int J = g.P - 1; J >= 0; --J) {
-    const int c0 = a.colptr[g.col_off + J], c1 = a.colptr[g.col_off + J + 1];
-    const int m = c1 - c0 - 1;
-    const int c = threadIdx.x % kTS, part = threadIdx.x / kTS;
+  if (threadIdx.x < kTS) zv[threadIdx.x] = z[I * kTS + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < kTS) {
+    const int c = threadIdx.x;
     double acc = 0.0;
-    if (part < nparts)
-      for (int i = part; i < m; i += nparts) {
-        const int I = a.rowidx[c0 + 1 + i];
-        const double* T = tile_ptr(a, g, I, J);
-        const double* xi = x + I * kTS;
-        for (int r = 0; r < kTS; ++r) acc += T[r * kTS + c] * xi[r];
-      }
-    if (part < nparts) red[part * kTS + c] = acc;
-    __syncthreads();
-    if (threadIdx.x < kTS) {
-      double z = x[J * kTS + threadIdx.x];
-      for (int pp = 0; pp < nparts; ++pp) z -= red[pp * kTS + threadIdx.x];
-      sv[kTS + threadIdx.x] = z;
-    }
-    __syncthreads();
-    tile_inv_matvec(a.factor + g.winv_off + (size_t)J * kTT, sv + kTS, sv, false);
-    if (threadIdx.x < kTS) x[J * kTS + threadIdx.x] = sv[threadIdx.x];
-    __syncthreads();
+    for (int r = c; r < kTS; ++r) acc += Wl[r * kSW + c] * zv[r];
+    yv[c] = acc;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (threadIdx.x < kTS) slot(a, g, dst)[I * kTS + threadIdx.x] = yv[threadIdx.x];
+    return;
+  }
+  constexpr int NQ = kTW / kTS, RQ = kTS / NQ;
+  const int c = threadIdx.x % kTS, q = threadIdx.x / kTS;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = q * RQ; r < q * RQ + RQ; ++r) acc += T[r * kSW + c] * yv[r];
+  part[q][c] = acc;
+  __syncthreads();
+  if (threadIdx.x < kTS) {
+    double s = 0.0;
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) s += part[qq][threadIdx.x];
+    z[J * kTS + threadIdx.x] -= s;
   }
 }
 
-// step: solve, then retract in the original pose order
-template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_step(SpArgs a, int retract) {
-  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
-  __shared__ double sv[2 * kTS];
-  __shared__ double red[kBT];
-  const int b = blockIdx.x;
+// slot[to] = slot[from] (grid x over the vector, y over graphs)
+__global__ void __launch_bounds__(kBT) k_sp_copy(SpArgs a, int from, int to) {
+  const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
-  double* x = a.vec + g.vec_off;
-  const double* rhs = x + g.nvec;
-  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] = rhs[u];
-  __syncthreads();
-  sp_solve(a, g, x, sv, red);
-  if (retract)
-    for (int p = threadIdx.x; p < g.npose; p += kBT)
-      retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x + a.pos[g.pose0 + p] * d);
+  const double* x = slot(a, g, from);
+  double* y = slot(a, g, to);
+  for (int u = blockIdx.x * kBT + threadIdx.x; u < g.nvec; u += gridDim.x * kBT) y[u] = x[u];
+}
+
+// X <- X Exp(-x) per pose, x read in permuted order
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_retract(SpArgs a, int xs) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, slot(a, g, xs) + a.pos[g.pose0 + p] * d);
+}
+
+// refinement residual b = g64 - (H64 + lambda) x (matrix-free, float64
+// records and J x per cost in ycost), padding zero
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* x = slot(a, g, 0);
+  const double* rhs = slot(a, g, 1);
+  double* res = slot(a, g, 2);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int gp = g.pose0 + p, ra = a.pos[gp];
+  double hv[d];
+#pragma unroll
+  for (int r = 0; r < d; ++r) hv[r] = lambda * x[ra * d + r];
+  for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+    const int sl = a.inc_slot[s];
+    const double* J = a.ws64 + (size_t)(sl >> 1) * RN + (sl & 1) * d * d;
+    const double* yc = a.ycost + (size_t)(sl >> 1) * d;
+#pragma unroll
+    for (int k = 0; k < d; ++k)
+#pragma unroll
+      for (int r = 0; r < d; ++r) hv[r] += J[k * d + r] * yc[k];
+  }
+#pragma unroll
+  for (int r = 0; r < d; ++r) res[ra * d + r] = rhs[ra * d + r] - hv[r];
 }
 
 // refinement: J delta per cost (float64 records), delta read in permuted order
@@ -481,67 +570,45 @@ __global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a) {
   }
 }
 
-// refinement: residual = g64 - (H64 + lambda) delta into vec[2], then solve
-// and add to delta (one workgroup per graph)
+// x += correction (slot 2) per pose, then retract on the last sweep
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_refine(SpArgs a, double lambda, int retract) {
-  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz, RN = CostRec<d>::n;
-  __shared__ double sv[2 * kTS];
-  __shared__ double red[kBT];
-  const int b = blockIdx.x;
+__global__ void __launch_bounds__(kBT) k_sp_accumulate(SpArgs a, int retract) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
-  double* x = a.vec + g.vec_off;
-  const double* rhs = x + g.nvec;
-  double* res = x + 2 * g.nvec;
-  for (int p = threadIdx.x; p < g.npose; p += kBT) {
-    const int gp = g.pose0 + p, ra = a.pos[gp];
-    double hv[d];
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  double* x = slot(a, g, 0) + a.pos[g.pose0 + p] * d;
+  const double* dx = slot(a, g, 2) + a.pos[g.pose0 + p] * d;
 #pragma unroll
-    for (int r = 0; r < d; ++r) hv[r] = lambda * x[ra * d + r];
-    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
-      const int slot = a.inc_slot[s];
-      const double* J = a.ws64 + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
-      const double* yc = a.ycost + (size_t)(slot >> 1) * d;
-#pragma unroll
-      for (int k = 0; k < d; ++k)
-#pragma unroll
-        for (int r = 0; r < d; ++r) hv[r] += J[k * d + r] * yc[k];
-    }
-#pragma unroll
-    for (int r = 0; r < d; ++r) res[ra * d + r] = rhs[ra * d + r] - hv[r];
-  }
-  for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
-  __syncthreads();
-  sp_solve(a, g, res, sv, red);
-  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] += res[u];
-  __syncthreads();
-  if (retract)
-    for (int p = threadIdx.x; p < g.npose; p += kBT)
-      retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x + a.pos[g.pose0 + p] * d);
+  for (int r = 0; r < d; ++r) x[r] += dx[r];
+  if (retract) retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x);
 }
 
-// backward: u = H*^-1 v (one workgroup per graph), u in original order
-template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_adjoint(SpArgs a) {
-  constexpr int d = GroupTraits<G>::d;
-  __shared__ double sv[2 * kTS];
-  __shared__ double red[kBT];
-  const int b = blockIdx.x;
+// backward: b = seed in permuted order (padding zero)
+__global__ void __launch_bounds__(kBT) k_sp_seed(SpArgs a, int d) {
+  const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
-  if (a.status[b] != DNLS_GRAPH_OK) {
-    for (int u = threadIdx.x; u < g.n; u += kBT) a.uout[(size_t)g.pose0 * d + u] = 0.0;
-    return;
-  }
-  double* x = a.vec + g.vec_off;
-  for (int u = threadIdx.x; u < g.nvec; u += kBT) x[u] = 0.0;
-  __syncthreads();
-  for (int p = threadIdx.x; p < g.npose; p += kBT)
-    for (int r = 0; r < d; ++r) x[a.pos[g.pose0 + p] * d + r] = a.seed[(size_t)(g.pose0 + p) * d + r];
-  __syncthreads();
-  sp_solve(a, g, x, sv, red);
-  for (int p = threadIdx.x; p < g.npose; p += kBT)
-    for (int r = 0; r < d; ++r) a.uout[(size_t)(g.pose0 + p) * d + r] = x[a.pos[g.pose0 + p] * d + r];
+  if (a.failed[b]) return;
+  double* x = slot(a, g, 2);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) x[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  for (int r = 0; r < d; ++r) x[a.pos[g.pose0 + p] * d + r] = a.seed[(size_t)(g.pose0 + p) * d + r];
+}
+
+// backward: adjoint in the original pose order (zero for graphs not OK)
+__global__ void __launch_bounds__(kBT) k_sp_uout(SpArgs a, int d) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const bool ok = a.status[b] == DNLS_GRAPH_OK;
+  const double* x = slot(a, g, 0);
+  for (int r = 0; r < d; ++r)
+    a.uout[(size_t)(g.pose0 + p) * d + r] = ok ? x[a.pos[g.pose0 + p] * d + r] : 0.0;
 }
 
 template <int G>
@@ -604,7 +671,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   std::vector<int> edge_ij(2 * (size_t)p->E), prior_var(p->P), pos(p->V);
   std::vector<std::vector<int>> inc(p->V);
   std::vector<int4> od_blk;
-  std::vector<int> od_slot, tix, colptr, rowidx;
+  std::vector<int> od_slot, tix, colptr, rowidx, rowptr, rowcol;
   p->sd.resize(B);
   long long fac = 0, vecoff = 0;
   int maxP = 0;
@@ -665,6 +732,18 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
         tix[g.tix_off + (size_t)I * g.P + J] = k;
         rowidx.push_back(I);
       }
+    // transposed structure: the off-diagonal tiles of every tile row
+    {
+      std::vector<std::vector<int>> rows(g.P);
+      for (int J = 0; J < g.P; ++J)
+        for (int k = ts.col_ptr[J] + 1; k < ts.col_ptr[J + 1]; ++k) rows[ts.row_idx[k]].push_back(J);
+      g.row_off = (int)rowptr.size();
+      for (int I = 0; I < g.P; ++I) {
+        rowptr.push_back((int)rowcol.size());
+        for (int J : rows[I]) rowcol.push_back(J);
+      }
+      rowptr.push_back((int)rowcol.size());
+    }
     g.pool_off = fac;
     fac += (long long)g.ntile * kTT;
     g.winv_off = fac;
@@ -672,7 +751,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     fac = (fac + 31) / 32 * 32;
     g.nvec = g.P * kTS;
     g.vec_off = vecoff;
-    vecoff += 3LL * g.nvec;
+    vecoff += 4LL * g.nvec;
     g.od0 = (int)od_blk.size();
     for (auto& kv : blocks) {
       od_blk.push_back(int4{kv.first.first, kv.first.second, (int)od_slot.size(), (int)kv.second.size()});
@@ -688,12 +767,14 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   // per tile column: the widest column and pair count over the batch
   p->sp_ntrsm.assign(maxP, 0);
   p->sp_npair.assign(maxP, 0);
+  p->sp_nrow.assign(maxP, 0);
   for (int b = 0; b < B; ++b) {
     const SpDesc& g = p->sd[b];
     for (int J = 0; J < g.P; ++J) {
       const int m = colptr[g.col_off + J + 1] - colptr[g.col_off + J] - 1;
       p->sp_ntrsm[J] = std::max(p->sp_ntrsm[J], m);
       p->sp_npair[J] = std::max(p->sp_npair[J], (long long)m * (m + 1) / 2);
+      p->sp_nrow[J] = std::max(p->sp_nrow[J], rowptr[g.row_off + J + 1] - rowptr[g.row_off + J]);
     }
   }
   p->sp_maxP = maxP;
@@ -703,7 +784,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
       (st = upload(p, &p->d_inc_off, inc_off)) != DNLS_OK || (st = upload(p, &p->d_inc_slot, inc_slot)) != DNLS_OK ||
       (st = upload(p, &p->d_od_blk, od_blk)) != DNLS_OK || (st = upload(p, &p->d_od_slot, od_slot)) != DNLS_OK ||
       (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
-      (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK)
+      (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK || (st = upload(p, &p->d_rowptr, rowptr)) != DNLS_OK ||
+      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK)
     return st;
   const size_t ncost = (size_t)p->E + p->P;
   const size_t rn = 2 * (size_t)d * d + d;
@@ -737,6 +819,8 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.tix = p->d_tix;
   a.colptr = p->d_colptr;
   a.rowidx = p->d_rowidx;
+  a.rowptr = p->d_rowptr;
+  a.rowcol = p->d_rowcol;
   char* w = static_cast<char*>(ws);
   a.ws64 = reinterpret_cast<double*>(w + p->sp_off[0]);
   a.ws32 = reinterpret_cast<float*>(w + p->sp_off[1]);
@@ -767,6 +851,15 @@ static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
   }
 }
 
+// x (slot dst) = (L L^T)^-1 b (slot 2, destroyed); slot 3 holds the forward result
+static void sp_sweeps(dnls_plan p, const SpArgs& a, int dst, hipStream_t st) {
+  const int B = p->B;
+  for (int J = 0; J < p->sp_maxP; ++J)
+    hipLaunchKernelGGL(k_sp_fwd, dim3(p->sp_ntrsm[J] + 1, B), dim3(kTW), 0, st, a, J, 2, 3);
+  for (int I = p->sp_maxP - 1; I >= 0; --I)
+    hipLaunchKernelGGL(k_sp_bwd, dim3(p->sp_nrow[I] + 1, B), dim3(kTW), 0, st, a, I, 3, dst);
+}
+
 template <int G>
 static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   constexpr int d = GroupTraits<G>::d;
@@ -784,6 +877,8 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   const dim3 g_cost(p->nlin_blocks, B);
   const dim3 g_blk((max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::nod) + kBT - 1) / kBT, B);
   const dim3 g_zero(256, B);
+  const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
+  const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
   hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
   for (int it = 0; it <= p->opt.iterations; ++it) {
     const bool final_lin = it == p->opt.iterations;
@@ -805,11 +900,15 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     sp_factor<G>(p, a, st);
     if (final_lin) break;
     const bool refine = lin32 && a.refine > 0;
-    hipLaunchKernelGGL(k_sp_step<G>, dim3(B), dim3(kBT), 0, st, a, refine ? 0 : 1);
+    hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 1, 2);
+    sp_sweeps(p, a, 0, st);
+    if (!refine) hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, a, 0);
     if (refine)
       for (int sw = 0; sw < a.refine; ++sw) {
         hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a);
-        hipLaunchKernelGGL(k_sp_refine<G>, dim3(B), dim3(kBT), 0, st, a, lam, sw + 1 == a.refine ? 1 : 0);
+        hipLaunchKernelGGL(k_sp_residual<G>, g_pose, dim3(kBT), 0, st, a, lam);
+        sp_sweeps(p, a, 2, st);
+        hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a, sw + 1 == a.refine ? 1 : 0);
       }
   }
   HIP_TRY(hipGetLastError());
@@ -836,7 +935,10 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   // float64 records at theta_K for the graphs whose solve succeeded
   hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
   hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
-  hipLaunchKernelGGL(k_sp_adjoint<G>, dim3(B), dim3(kBT), 0, st, a);
+  const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
+  hipLaunchKernelGGL(k_sp_seed, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
+  sp_sweeps(p, a, 0, st);
+  hipLaunchKernelGGL(k_sp_uout, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
   hipLaunchKernelGGL(k_sp_vjp<G>, g_cost, dim3(kBT), 0, st, a);
   HIP_TRY(hipGetLastError());
   if (s->adjoint)
