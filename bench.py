@@ -153,6 +153,8 @@ def main():
                     choices=["se2_circle_b1", "se3_walk64_b128", "se3_lattice16_b8", "se3_uneven_b256",
                              "ba_ring64_b4"])
     ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
+    ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
+                    help="override the workload's solver (pose graphs only)")
     ap.add_argument("--cpu-graphs", type=int, default=None,
                     help="graphs in the CPU oracle sample (default: the whole batch of the headline "
                          "workload, a few graphs otherwise)")
@@ -179,6 +181,8 @@ def main():
     dev = torch.device("cuda:0")
     W = synth.WORKLOADS[args.workload]
     K, lam, solver = W["iterations"], W["lam"], W["solver"]
+    if args.solver and solver != "schur":
+        solver = args.solver
     p = W["fn"](**W["kwargs"])
     ba = solver == "schur"
     B = len(p["pose_off"]) - 1

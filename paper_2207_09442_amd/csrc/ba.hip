@@ -262,7 +262,18 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
   }
 }
 
-// 3. Schur complement S (lower blocks, all) and g_s into the augmented row
+// sum over the 64 lanes of a wave (butterfly; every lane gets the total)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// 3. Schur complement S (lower blocks, all) and g_s into the augmented row.
+// One wave per camera-pair block: the lanes split the block's contribution
+// list (observations of the camera for a diagonal block, point-sharing
+// observation pairs for every block), then a butterfly sum.
+constexpr int kSchurWaves = kBT / 64;
 template <class S>
 __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
   const int b = blockIdx.y;
@@ -282,29 +293,30 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
       if (r > npad || c >= g.n) A[(size_t)r * npad + c] = 0.0;
     }
   }
-  const int lb = blockIdx.x * kBT + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int lb = blockIdx.x * kSchurWaves + (threadIdx.x >> 6);
   if (lb >= g.nblk) return;
   const int4 blk = a.sblk[g.blk0 + lb];
   const int ca = blk.x, cb = blk.y;
   double v[36];
 #pragma unroll
   for (int k = 0; k < 36; ++k) v[k] = 0.0;
+  double gs[6] = {0, 0, 0, 0, 0, 0};
   if (ca == cb) {
     const int cam = g.cam0 + ca;
     S h[36];
 #pragma unroll
     for (int k = 0; k < 36; ++k) h[k] = S(0);
-    double gs[6] = {0, 0, 0, 0, 0, 0};
     S gsl[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) gsl[k] = S(0);
-    for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+    for (int s = a.cam_obs_off[cam] + lane; s < a.cam_obs_off[cam + 1]; s += 64) {
       const int o = a.cam_obs[s];
       const S* r = rec + (size_t)o * kObsRec;
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) h[i * 6 + j] += r[i] * r[j] + r[6 + i] * r[6 + j];
+        for (int j = 0; j <= i; ++j) h[i * 6 + j] += r[i] * r[j] + r[6 + i] * r[6 + j];
         gsl[i] += r[i] * r[18] + r[6 + i] * r[19];
       }
       // - F_o g_p
@@ -314,9 +326,37 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
       for (int i = 0; i < 6; ++i) gs[i] -= Fo[i * 3] * gpp[0] + Fo[i * 3 + 1] * gpp[1] + Fo[i * 3 + 2] * gpp[2];
     }
 #pragma unroll
-    for (int k = 0; k < 36; ++k) v[k] = double(h[k]);
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) v[i * 6 + j] = double(h[i * 6 + j]);
 #pragma unroll
     for (int k = 0; k < 6; ++k) gs[k] += double(gsl[k]);
+  }
+  for (int s = blk.z + lane; s < blk.z + blk.w; s += 64) {
+    const int2 pr = a.spair[s];
+    const double* Fa = a.F + (size_t)pr.x * 18;
+    const double* Eb = a.E + (size_t)pr.y * 18;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) v[i * 6 + j] -= Fa[i * 3] * Eb[j * 3] + Fa[i * 3 + 1] * Eb[j * 3 + 1] + Fa[i * 3 + 2] * Eb[j * 3 + 2];
+  }
+  // butterfly sums (the diagonal block's J^T J part is symmetric: lower half only)
+#pragma unroll
+  for (int k = 0; k < 36; ++k) v[k] = wave_sum(v[k]);
+  if (ca == cb) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gs[k] = wave_sum(gs[k]);
+  }
+  if (lane != 0) return;
+  if (ca == cb) {
+    const int cam = g.cam0 + ca;
+    // the J^T J part was accumulated on the lower triangle; the E C^-1 E^T
+    // part of a diagonal block is symmetric as well
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) v[i * 6 + j] = v[j * 6 + i];
     for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
       if (a.prior_var[q] != cam) continue;
       const double* pr = a.prec + (size_t)q * kPriorRec;
@@ -336,15 +376,6 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
     double* aug = A + (size_t)npad * npad;
 #pragma unroll
     for (int i = 0; i < 6; ++i) aug[ca * 6 + i] = gs[i];
-  }
-  for (int s = blk.z; s < blk.z + blk.w; ++s) {
-    const int2 pr = a.spair[s];
-    const double* Fa = a.F + (size_t)pr.x * 18;
-    const double* Eb = a.E + (size_t)pr.y * 18;
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-      for (int j = 0; j < 6; ++j) v[i * 6 + j] -= Fa[i * 3] * Eb[j * 3] + Fa[i * 3 + 1] * Eb[j * 3 + 1] + Fa[i * 3 + 2] * Eb[j * 3 + 2];
   }
 #pragma unroll
   for (int i = 0; i < 6; ++i)
@@ -751,7 +782,7 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   const dim3 blk(kBT);
   const dim3 g_lin(p->nlin_blocks, B);
   const dim3 g_pt((max_of(p->bd, &BADesc::npt) + kBT - 1) / kBT, B);
-  const dim3 g_blk((max_of(p->bd, &BADesc::nblk) + kBT - 1) / kBT, B);
+  const dim3 g_blk((max_of(p->bd, &BADesc::nblk) + kSchurWaves - 1) / kSchurWaves, B);
   const int nupd = std::max(max_of(p->bd, &BADesc::npt), max_of(p->bd, &BADesc::ncam));
   const dim3 g_upd((nupd + kBT - 1) / kBT, B);
   const size_t lds = (size_t)p->npad_max * sizeof(double);
