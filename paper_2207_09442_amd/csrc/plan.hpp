@@ -109,6 +109,7 @@ struct dnls_plan_s {
   std::vector<int> sp_nrow;       // per tile row: widest row (off-diagonal tiles) over the batch
   std::vector<long long> sp_npair;
   int sp_maxP = 0;
+  bool sp_solve_wg = false;       // every graph's vector fits one workgroup's LDS
   size_t sp_off[8] = {0};
   std::vector<void*> allocs;
 };

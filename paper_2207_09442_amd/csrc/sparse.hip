@@ -484,6 +484,71 @@ __global__ void __launch_bounds__(kTW) k_sp_bwd(SpArgs a, int I, int zs, int dst
   }
 }
 
+// Whole solve x (slot dst) = (L L^T)^-1 b (slot src) with one workgroup per
+// graph and the vector in LDS, for plans whose graphs have at most
+// kSolveLds unknowns (padded): per tile column a 48x48 product with W_J and
+// the rows of the column's tiles; then per tile row (descending) W_I^T and
+// the transposed tiles of the row.  Two barriers per tile step and no
+// launches, where the sweeps need two launches per tile column.
+constexpr int kSolveLds = 6144;
+__global__ void __launch_bounds__(kBT) k_sp_solve_wg(SpArgs a, int src, int dst) {
+  __shared__ double v[kSolveLds];
+  __shared__ double y[kTS];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* bsrc = slot(a, g, src);
+  for (int u = threadIdx.x; u < g.nvec; u += kBT) v[u] = bsrc[u];
+  __syncthreads();
+  for (int J = 0; J < g.P; ++J) {
+    const double* W = a.factor + g.winv_off + (size_t)J * kTT;
+    if (threadIdx.x < kTS) {
+      const int c = threadIdx.x;
+      double acc = 0.0;
+      for (int k = 0; k <= c; ++k) acc += W[c * kTS + k] * v[J * kTS + k];
+      y[c] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTS) v[J * kTS + threadIdx.x] = y[threadIdx.x];
+    const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
+    for (int e = threadIdx.x; e < m * kTS; e += kBT) {
+      const int I = a.rowidx[c0 + 1 + e / kTS], r = e % kTS;
+      const d4v* row = reinterpret_cast<const d4v*>(tile_ptr(a, g, I, J) + r * kTS);
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kTS / 4; ++q) {
+        const d4v t = row[q];
+        acc += t[0] * y[4 * q] + t[1] * y[4 * q + 1] + t[2] * y[4 * q + 2] + t[3] * y[4 * q + 3];
+      }
+      v[I * kTS + r] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int I = g.P - 1; I >= 0; --I) {
+    const double* W = a.factor + g.winv_off + (size_t)I * kTT;
+    if (threadIdx.x < kTS) {
+      const int c = threadIdx.x;
+      double acc = 0.0;
+      for (int r = c; r < kTS; ++r) acc += W[r * kTS + c] * v[I * kTS + r];
+      y[c] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTS) v[I * kTS + threadIdx.x] = y[threadIdx.x];
+    const int r0 = a.rowptr[g.row_off + I], nr = a.rowptr[g.row_off + I + 1] - r0;
+    for (int e = threadIdx.x; e < nr * kTS; e += kBT) {
+      const int J = a.rowcol[r0 + e / kTS], c = e % kTS;
+      const double* T = tile_ptr(a, g, I, J);
+      double acc = 0.0;
+#pragma unroll 8
+      for (int r = 0; r < kTS; ++r) acc += T[r * kTS + c] * y[r];
+      v[J * kTS + c] -= acc;
+    }
+    __syncthreads();
+  }
+  double* xdst = slot(a, g, dst);
+  for (int u = threadIdx.x; u < g.nvec; u += kBT) xdst[u] = v[u];
+}
+
 // slot[to] = slot[from] (grid x over the vector, y over graphs)
 __global__ void __launch_bounds__(kBT) k_sp_copy(SpArgs a, int from, int to) {
   const int b = blockIdx.y;
@@ -778,6 +843,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     }
   }
   p->sp_maxP = maxP;
+  p->sp_solve_wg = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
   dnls_status st;
   if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
       (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK || (st = upload(p, &p->d_pos, pos)) != DNLS_OK ||
@@ -854,6 +920,10 @@ static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
 // x (slot dst) = (L L^T)^-1 b (slot 2, destroyed); slot 3 holds the forward result
 static void sp_sweeps(dnls_plan p, const SpArgs& a, int dst, hipStream_t st) {
   const int B = p->B;
+  if (p->sp_solve_wg) {
+    hipLaunchKernelGGL(k_sp_solve_wg, dim3(B), dim3(kBT), 0, st, a, 2, dst);
+    return;
+  }
   for (int J = 0; J < p->sp_maxP; ++J)
     hipLaunchKernelGGL(k_sp_fwd, dim3(p->sp_ntrsm[J] + 1, B), dim3(kTW), 0, st, a, J, 2, 3);
   for (int I = p->sp_maxP - 1; I >= 0; --I)

@@ -396,7 +396,7 @@ WORKLOADS = {
     "se3_lattice16_b8": dict(fn=lattice_se3, kwargs=dict(batch=8), iterations=15, optimizer="GN",
                              lam=0.0, solver="sparse", precision="mixed"),
     "se3_uneven_b256": dict(fn=uneven_walk_se3, kwargs=dict(batch=256), iterations=10,
-                            optimizer="GN", lam=0.0, solver="dense", precision="mixed"),
+                            optimizer="GN", lam=0.0, solver="sparse", precision="mixed"),
     "ba_ring64_b4": dict(fn=bundle_adjustment, kwargs=dict(batch=4), iterations=10,
                          optimizer="LM", lam=1e-3, solver="schur", precision="mixed"),
 }
