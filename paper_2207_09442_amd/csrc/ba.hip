@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
   }
   double* A = a.factor + g.fac_off;
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
-  const bool ok = chol_dense(A, g.npad, winv, L.dl);
+  const bool ok = chol_dense(A, A, g.npad, winv, L.dl);
   if (!ok) {
     if (threadIdx.x == 0) {
       a.frozen[b] = DNLS_GRAPH_NOT_PD;

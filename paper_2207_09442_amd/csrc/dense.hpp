@@ -217,11 +217,13 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
   return ok;
 }
 
-// Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix A
-// (row npad = right-hand side): on return A holds L and y = L^-1 b in row
-// npad, winv holds the inverses of the diagonal blocks.  All threads call;
-// returns false (uniformly) if the matrix is not positive definite.
-__device__ __forceinline__ bool chol_dense(double* __restrict__ A, int npad, double* __restrict__ winv, DenseLds& s) {
+// Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix H
+// (row npad = right-hand side; lower part read) into L (same layout; L may
+// be H itself): on return L holds the factor and y = L^-1 b in row npad,
+// winv holds the inverses of the diagonal blocks.  H is only read, so a
+// caller can keep its structural zeros across factorisations.  All threads
+// call; returns false (uniformly) if the matrix is not positive definite.
+__device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad, double* __restrict__ winv, DenseLds& s) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
   const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
@@ -234,12 +236,13 @@ __device__ __forceinline__ bool chol_dense(double* __restrict__ A, int npad, dou
       const int i = i0 + wave;
       const bool active = i <= T16;
       const double* Arow = A + (size_t)(16 * i + lm) * npad;
+      const double* Hrow = H + (size_t)(16 * i + lm) * npad;
       // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
       d4v acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[c][r] = active ? Arow[col0 + 16 * c + lq + 4 * r] : 0.0;
+        for (int r = 0; r < 4; ++r) acc[c][r] = active ? Hrow[col0 + 16 * c + lq + 4 * r] : 0.0;
       if (nchunk > 0) {
         // stage chunk 0 of L_J[0:64][0:64] into LDS, prefetch this wave's operands
         d4v st[4], bop[4], bnx[4];

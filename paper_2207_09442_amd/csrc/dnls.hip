@@ -55,6 +55,7 @@ struct DenseArgs {
   double* ws64;      // per-cost records, float64
   float* ws32;       // per-cost records, float32 (mixed)
   double* ycost;     // per-cost J delta (d values)
+  double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
   const double* seed;
   double* g_logw_e;
   double* g_tau;
@@ -103,11 +104,12 @@ __device__ double linearize_graph(const DenseArgs& a, const GraphDesc& g, S* rec
 // Assemble the lower triangle of H (+ lambda on the diagonal, identity on the
 // padding) into A (row-major npad x npad plus the 16-row augmented tile),
 // one thread per 6x6 (3x3) Hessian block, products accumulated in precision S.
-template <int G, class S>
-__device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec, double* A, double lambda) {
-  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+// Once per solve: zero every row of H up to the end of its 64-wide diagonal
+// block (the part the factorisation reads) and the augmented tile, and put
+// 1 on the diagonal of the padding.  The assembly then rewrites only the
+// structurally non-zero blocks, so the zeros persist across iterations.
+__device__ void init_H(const GraphDesc& g, double* A) {
   const int npad = g.npad;
-  // zero every row up to the end of its 64-wide diagonal block, and the augmented tile
   const int q4 = npad >> 2;
   for (int u = threadIdx.x; u < (npad + 16) * q4; u += kNT) {
     const int r = u / q4, c = 4 * (u - r * q4);
@@ -115,6 +117,16 @@ __device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec,
       *reinterpret_cast<d4v*>(A + (size_t)r * npad + c) = d4v{0.0, 0.0, 0.0, 0.0};
   }
   __syncthreads();
+  for (int r = g.n + threadIdx.x; r < npad; r += kNT) A[(size_t)r * npad + r] = 1.0;
+  __syncthreads();
+}
+
+// H = sum J^T J (+ lambda I) on the non-zero 6x6 / 3x3 blocks of the lower
+// triangle (H prepared by init_H)
+template <int G, class S>
+__device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec, double* A, double lambda) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int npad = g.npad;
   for (int u = threadIdx.x; u < g.npose + g.nod; u += kNT) {
     S h[d * d];
 #pragma unroll
@@ -164,7 +176,6 @@ __device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec,
       for (int c = 0; c < d; ++c)
         A[(size_t)(rb * d + r) * npad + cb * d + c] = double(h[r * d + c]) + ((rb == cb && r == c) ? lambda : 0.0);
   }
-  for (int r = g.n + threadIdx.x; r < npad; r += kNT) A[(size_t)r * npad + r] = 1.0;
   __syncthreads();
 }
 
@@ -272,12 +283,14 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   const GraphDesc g = a.gd[b];
   double* A = a.factor + g.fac_off;
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  double* H = a.hbuf + g.h_off;    // assembled system (workspace), read by the factorisation
   double* vb = dyn;                // step
   double* vx = dyn + g.npad;       // refinement residual / matrix-free product
   double* vy = dyn + 2 * g.npad;   // right-hand side g
   int status = DNLS_GRAPH_OK;
   double last_obj = 0.0;
   int last_it = 0;
+  init_H(g, H);
   for (int it = 0; it <= a.K; ++it) {
     const bool final_lin = (it == a.K);
     const double lam = final_lin ? 0.0 : a.lambda;
@@ -297,20 +310,21 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     }
     if (final_lin) {
       // undamped factor of H* for the backward, assembled in float64
-      assemble_H<G, double>(a, g, a.ws64, A, 0.0);
-      if (!chol_dense(A, g.npad, winv, L.dl)) status = DNLS_GRAPH_NOT_PD;
+      assemble_H<G, double>(a, g, a.ws64, H, 0.0);
+      if (!chol_dense(A, H, g.npad, winv, L.dl)) status = DNLS_GRAPH_NOT_PD;
       break;
     }
-    double* aug = A + (size_t)g.npad * g.npad;   // right-hand side row of the factorisation
+    double* haug = H + (size_t)g.npad * g.npad;  // right-hand side row of the system
+    double* aug = A + (size_t)g.npad * g.npad;   // ... and of the factor: y = L^-1 g
     if (MIXED) {
-      assemble_H<G, float>(a, g, a.ws32, A, lam);
-      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vy, aug);
-      else assemble_g<G, float>(a, g, a.ws32, vy, aug);
+      assemble_H<G, float>(a, g, a.ws32, H, lam);
+      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vy, haug);
+      else assemble_g<G, float>(a, g, a.ws32, vy, haug);
     } else {
-      assemble_H<G, double>(a, g, a.ws64, A, lam);
-      assemble_g<G, double>(a, g, a.ws64, vy, aug);
+      assemble_H<G, double>(a, g, a.ws64, H, lam);
+      assemble_g<G, double>(a, g, a.ws64, vy, haug);
     }
-    if (!chol_dense(A, g.npad, winv, L.dl)) {
+    if (!chol_dense(A, H, g.npad, winv, L.dl)) {
       status = DNLS_GRAPH_NOT_PD;
       break;
     }
@@ -530,7 +544,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   std::vector<int4> od_blk;
   std::vector<int> od_slot;
   p->gd.resize(B);
-  long long fac = 0;
+  long long fac = 0, hsz = 0;
   for (int b = 0; b < B; ++b) {
     GraphDesc& g = p->gd[b];
     g.pose0 = pr->pose_off[b];
@@ -549,6 +563,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     p->flops_alg += double(g.n) * g.n * g.n / 3.0;
     p->flops_exec += double(g.npad) * g.npad * g.npad / 3.0;
     g.fac_off = fac;
+    g.h_off = hsz;
+    hsz += (long long)(g.npad + 16) * g.npad;
     // L (npad x npad) + augmented right-hand-side tile (16 x npad) + panel inverses
     fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
     fac = (fac + 31) / 32 * 32;
@@ -614,8 +630,10 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->precision == DNLS_PREC_MIXED) ws += align256(ncost * rn * sizeof(float));
   p->ycost_off = ws;
   ws += align256(ncost * d * sizeof(double));
+  p->h_off = ws;
+  ws += align256((size_t)hsz * sizeof(double));
   p->ws_bytes = ws;
-  p->bwd_bytes = ws;
+  p->bwd_bytes = p->h_off;   // the backward does not use the assembled systems
   p->fac_bytes = (size_t)fac * sizeof(double);
   *out = p;
   return DNLS_OK;
@@ -682,6 +700,7 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.ws64 = reinterpret_cast<double*>(ws);
   a.ws32 = reinterpret_cast<float*>(ws + p->ws32_off);
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
+  a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
@@ -711,6 +730,7 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   char* ws = static_cast<char*>(s->workspace);
   a.ws64 = reinterpret_cast<double*>(ws);
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
+  a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
   a.seed = s->seed_pose;
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
