@@ -1,5 +1,7 @@
-"""GPU parity of the dense pose-graph path (C-ABI -> HIP kernels) against the
-CPU oracle on the same seeded inputs.
+"""GPU parity of the pose-graph paths (C-ABI -> HIP kernels) against the CPU
+oracle on the same seeded inputs.  The edge cases (SE(2), ragged batches with
+weights and measurement tangents, mixed precision, K = 0, failed graphs, a
+single-pose graph) run on both the dense and the block-sparse solver.
 
 Tolerances
   FP64 path: 1e-10 relative per graph for poses, objective and gradients.
@@ -39,8 +41,8 @@ def _seeds(p, poses_ref_by_graph, graphs):
 
 
 def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_pose=1e-10, tol_grad=1e-10,
-             gate_grad=True, grad_cond_scale=None):
-    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau)
+             gate_grad=True, grad_cond_scale=None, solver="dense"):
+    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver)
     B = len(p["pose_off"]) - 1
     graphs = list(range(B)) if graphs is None else graphs
     gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs)
@@ -77,7 +79,7 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
             tol_b = max(tol_grad, grad_cond_scale * (ev[-1] / ev[0]) * np.finfo(np.float64).eps)
         if err >= tol_b:
             over.append((b, err, tol_b))
-    print(f"\n[{precision} refine={refine}] pose {worst_pose:.2e} objective {worst_obj:.2e} grad {worst_grad:.2e}")
+    print(f"\n[{solver} {precision} refine={refine}] pose {worst_pose:.2e} objective {worst_obj:.2e} grad {worst_grad:.2e}")
     assert worst_pose < tol_pose
     assert worst_obj < max(tol_pose, 1e-12) * (1e3 if precision == "mixed" else 1)
     if gate_grad:
@@ -85,41 +87,47 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
     return worst_pose, worst_grad
 
 
-def test_se2_circle_fp64():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_se2_circle_fp64(solver):
     """16-pose SE(2) circle, batch 1, 10 Gauss-Newton steps (48x48 system)."""
     p = synth.circle_se2()
-    _compare(p, 10, 0.0)
+    _compare(p, 10, 0.0, solver=solver)
 
 
-def test_se3_uneven_ragged_fp64_with_weights_and_tau():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_se3_uneven_ragged_fp64_with_weights_and_tau(solver):
     """Uneven small graphs (ragged tiles: n = 6N not a multiple of 16), random
     log-weights, non-zero measurement perturbation tau, LM damping."""
     p = synth.uneven_walk_se3(batch=6, n_min=3, n_max=40, seed=3)
     p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
     p["prior_logw"] = rng.normal(scale=0.3, size=len(p["prior_logw"]))
     tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), 6))
-    _compare(p, 6, 1e-3, tau=tau)
+    _compare(p, 6, 1e-3, tau=tau, solver=solver)
 
 
-def test_se2_batch_gn_fp64():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_se2_batch_gn_fp64(solver):
     p = synth.circle_se2(batch=5, n_poses=24, n_loops=10, seed=5)
-    _compare(p, 8, 0.0)
+    _compare(p, 8, 0.0, solver=solver)
 
 
 @pytest.mark.parametrize("refine", [1, 2])
-def test_se3_mixed_refined(refine):
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_se3_mixed_refined(refine, solver):
     p = synth.walk_se3(batch=4, n_poses=40, n_loops=40, seed=11)
-    _compare(p, 10, 1e-3, precision="mixed", refine=refine, tol_pose=1e-5, tol_grad=1e-5)
+    _compare(p, 10, 1e-3, precision="mixed", refine=refine, tol_pose=1e-5, tol_grad=1e-5, solver=solver)
 
 
-def test_se3_mixed_unrefined_poses():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_se3_mixed_unrefined_poses(solver):
     p = synth.walk_se3(batch=4, n_poses=40, n_loops=40, seed=11)
-    _compare(p, 10, 1e-3, precision="mixed", refine=0, tol_pose=1e-5, gate_grad=False)
+    _compare(p, 10, 1e-3, precision="mixed", refine=0, tol_pose=1e-5, gate_grad=False, solver=solver)
 
 
-def test_k_zero_final_linearisation_only():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_k_zero_final_linearisation_only(solver):
     p = synth.walk_se3(batch=3, n_poses=10, n_loops=6, seed=13)
-    _compare(p, 0, 1e-3)
+    _compare(p, 0, 1e-3, solver=solver)
 
 
 def test_walk64_b128_sampled_graphs_fp64_and_mixed():
@@ -130,7 +138,8 @@ def test_walk64_b128_sampled_graphs_fp64_and_mixed():
     _compare(p, 10, 1e-3, precision="mixed", refine=1, graphs=[0, 37, 81, 127], tol_pose=1e-5, tol_grad=1e-5)
 
 
-def test_failed_graphs_are_frozen():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_failed_graphs_are_frozen(solver):
     """Graph 1 has an isolated pose (no cost touches it) and lambda = 0, so its
     Hessian has an exactly zero diagonal block (NOT_PD); graph 2 has a NaN
     measurement (NONFINITE).  Both keep their initial poses, repeat their
@@ -143,7 +152,7 @@ def test_failed_graphs_are_frozen():
     p["edge_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     p["edge_meas"] = p["edge_meas"].copy()
     p["edge_meas"][p["edge_off"][2] + 1, 0, 3] = np.nan
-    plan, poses, objective, status, dev = gpu_solve(p, 5, 0.0)
+    plan, poses, objective, status, dev = gpu_solve(p, 5, 0.0, solver=solver)
     st = status.cpu().numpy()
     assert st.tolist() == [0, 1, 2]
     got = poses.cpu().numpy()
@@ -163,7 +172,8 @@ def test_failed_graphs_are_frozen():
         assert np.all(gr["edge_logw"][e0:e1] == 0) and np.all(gr["edge_tau"][e0:e1] == 0)
 
 
-def test_single_pose_graph_and_prior_only():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_single_pose_graph_and_prior_only(solver):
     """Degenerate graph: one pose, no edges, only its prior (n = 6 -> padded 16)."""
     p = synth.walk_se3(batch=2, n_poses=2, n_loops=0, seed=19)
     # make graph 0 a single pose: keep pose 0 only
@@ -177,7 +187,7 @@ def test_single_pose_graph_and_prior_only():
     q["edge_logw"] = p["edge_logw"][1:]
     q["prior_var"] = np.array([0, 1], np.int32)
     q["poses_init"][0, :, 3] += 0.3
-    _compare(q, 3, 0.0)
+    _compare(q, 3, 0.0, solver=solver)
 
 
 def test_projection_operator_matches_tangent_gradient():
