@@ -155,6 +155,9 @@ def main():
     ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
                     help="override the workload's solver (pose graphs only)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick solver, sparse solve schedule and graph capture with the autotuner "
+                         "(pose graphs only; timed before the benchmark, cached)")
     ap.add_argument("--cpu-graphs", type=int, default=None,
                     help="graphs in the CPU oracle sample (default: the whole batch of the headline "
                          "workload, a few graphs otherwise)")
@@ -195,8 +198,17 @@ def main():
     else:
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
+    schedule = dict(sparse_solve="auto", graph=False)
+    if args.autotune and not ba:
+        from paper_2207_09442_amd.autotune import autotune
+        best = autotune(p, K, lam, precision=W["precision"], refine=args.refine if W["precision"] == "mixed" else 0,
+                        device=dev)
+        solver = best["solver"]
+        schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"])
+        progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
+
     def run(precision: str, refine: int):
-        plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=dev)
+        plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=dev, **schedule)
         poses = init.clone()
         pts = pts_init.clone() if ba else None
 
@@ -273,7 +285,8 @@ def main():
               % (3 if p["group"] == "SE3" else 2)) if single_kernel else "solve (all kernels of dnls_solve)"
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
-           "refine": args.refine if main_prec == "mixed" else 0, "solver": solver}
+           "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,
+           "schedule": dict(schedule, autotuned=bool(args.autotune and not ba))}
     if args.workload == "se3_walk64_b128":
         cfg.update(poses=64, loop_closures=64)
     line = {

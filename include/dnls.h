@@ -104,12 +104,31 @@ typedef struct {
   double huber_delta;         /* Huber threshold on ||w c|| (> 0), SCHUR only */
 } dnls_problem;
 
+/* Triangular-solve schedule of the SPARSE solver: AUTO picks WORKGROUP when
+ * every graph has at most 6144 (padded) unknowns, else SWEEPS.  WORKGROUP:
+ * one workgroup per graph with the vector in LDS; SWEEPS: one launch per
+ * tile column / row, one workgroup per tile.  Forcing WORKGROUP on a plan
+ * whose graphs are too large is DNLS_ERR_UNSUPPORTED. */
+typedef enum { DNLS_SPSOLVE_AUTO = 0, DNLS_SPSOLVE_WORKGROUP = 1, DNLS_SPSOLVE_SWEEPS = 2 } dnls_sparse_solve;
+
+/* dnls_options.flags */
+enum {
+  /* SPARSE and SCHUR: record the launch sequence of dnls_solve into a HIP
+   * graph on the first call and replay it while the argument pointers stay
+   * the same (recaptured when they change).  The plan then holds mutable
+   * state: calls with this flag must not overlap on one plan.  DENSE is a
+   * single launch and ignores the flag. */
+  DNLS_FLAG_GRAPH = 1
+};
+
 typedef struct {
   int32_t solver;             /* dnls_solver */
   int32_t precision;          /* dnls_precision */
   int32_t iterations;         /* K >= 0 optimizer steps */
   int32_t refine;             /* 0..4 float64 correction sweeps (MIXED only) */
   double lambda;              /* Levenberg-Marquardt damping >= 0; 0 = Gauss-Newton */
+  int32_t sparse_solve;       /* dnls_sparse_solve (SPARSE only) */
+  int32_t flags;              /* DNLS_FLAG_* */
 } dnls_options;
 
 /* Arguments of dnls_solve (device pointers unless stated). */

@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2}
+FLAG_GRAPH = 1
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
 
@@ -47,7 +49,7 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("lambda_", ctypes.c_double)]
+                ("lambda_", ctypes.c_double), ("sparse_solve", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class _SolveArgs(ctypes.Structure):
@@ -124,7 +126,8 @@ class Plan:
     plus the caller-owned workspace and factor cache (torch device tensors)."""
 
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
-                 precision: str = "fp64", refine: int = 0, device: str = "cuda"):
+                 precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
+                 graph: bool = False):
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -155,7 +158,10 @@ class Plan:
                 setattr(pr, name, p)
             pr.fx, pr.fy, pr.cx, pr.cy = (float(x) for x in problem["intrinsics"])
             pr.huber_delta = float(problem["huber_delta"])
-        op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam))
+        op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam),
+                      SPARSE_SOLVES[sparse_solve], FLAG_GRAPH if graph else 0)
+        self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
+                           sparse_solve=sparse_solve, graph=bool(graph))
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h

@@ -491,6 +491,9 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->precision != DNLS_PREC_FP64 && op->precision != DNLS_PREC_MIXED)
     return fail(DNLS_ERR_INVALID_ARG, "unknown precision");
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
+  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_SWEEPS)
+    return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
+  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
   if (op->solver == DNLS_SOLVER_SCHUR) {
     auto* p = new dnls_plan_s();
     p->B = pr->batch;
@@ -671,6 +674,42 @@ static DenseArgs base_args(dnls_plan p) {
   return a;
 }
 
+// Enqueue the launch sequence of a multi-kernel solver (SPARSE, SCHUR) on
+// `st`, through a captured HIP graph when DNLS_FLAG_GRAPH is set: the
+// sequence is recorded once on a private stream and replayed while the
+// argument pointers stay the same.
+static dnls_status solve_multi(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  auto enqueue = [&](hipStream_t q) {
+    return p->opt.solver == DNLS_SOLVER_SCHUR ? ba_solve(p, s, q) : sp_solve(p, s, q);
+  };
+  if (!(p->opt.flags & DNLS_FLAG_GRAPH)) return enqueue(st);
+  const std::vector<const void*> key = {s->poses, s->points, s->edge_meas, s->edge_logw, s->edge_tau,
+                                        s->prior_meas, s->prior_logw, s->obs_uv, s->obs_w,
+                                        s->objective, s->status, s->factor, s->workspace};
+  std::lock_guard<std::mutex> lock(p->graph_mu);
+  if (!p->graph_exec || p->graph_key != key) {
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const dnls_status est = enqueue(p->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(p->cap_stream, &graph);
+    if (est != DNLS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return est;
+    }
+    if (ce != hipSuccess) return fail(DNLS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(DNLS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = exec;
+    p->graph_key = key;
+  }
+  HIP_TRY(hipGraphLaunch(p->graph_exec, st));
+  return DNLS_OK;
+}
+
 dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   g_err.clear();
   if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
@@ -678,14 +717,15 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
     return fail(DNLS_ERR_INVALID_ARG, "poses, objective, status, factor and workspace are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
-  if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_solve(p, s, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->opt.solver == DNLS_SOLVER_SCHUR) {
+    if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+      return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv, obs_w and prior data are required");
+    return solve_multi(p, s, st);
+  }
   if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
     return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
-  if (p->opt.solver == DNLS_SOLVER_SPARSE) return sp_solve(p, s, static_cast<hipStream_t>(stream));
-  if ((p->E > 0 && (!s->edge_meas || !s->edge_logw)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
-    return fail(DNLS_ERR_INVALID_ARG, "cost data pointers are required");
-  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
-    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  if (p->opt.solver == DNLS_SOLVER_SPARSE) return solve_multi(p, s, st);
   DenseArgs a = base_args(p);
   a.poses = s->poses;
   a.edge_meas = s->edge_meas;
@@ -701,7 +741,6 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.ws32 = reinterpret_cast<float*>(ws + p->ws32_off);
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
   return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);
@@ -759,6 +798,8 @@ dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses, con
 
 dnls_status dnls_plan_destroy(dnls_plan p) {
   if (!p) return DNLS_OK;
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
   return DNLS_OK;

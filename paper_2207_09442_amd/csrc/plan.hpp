@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -113,6 +114,11 @@ struct dnls_plan_s {
   bool sp_solve_wg = false;       // every graph's vector fits one workgroup's LDS
   size_t sp_off[8] = {0};
   std::vector<void*> allocs;
+  // captured launch sequence of dnls_solve (DNLS_FLAG_GRAPH)
+  std::mutex graph_mu;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<const void*> graph_key;   // argument pointers the graph was captured with
 };
 
 namespace dnls {

@@ -843,7 +843,12 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     }
   }
   p->sp_maxP = maxP;
-  p->sp_solve_wg = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
+  const bool fits = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
+  if (p->opt.sparse_solve == DNLS_SPSOLVE_WORKGROUP && !fits)
+    return fail(DNLS_ERR_UNSUPPORTED, "the workgroup solve holds at most " + std::to_string(kSolveLds) +
+                                          " unknowns per graph");
+  p->sp_solve_wg = p->opt.sparse_solve == DNLS_SPSOLVE_WORKGROUP ||
+                   (p->opt.sparse_solve == DNLS_SPSOLVE_AUTO && fits);
   dnls_status st;
   if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
       (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK || (st = upload(p, &p->d_pos, pos)) != DNLS_OK ||

@@ -53,7 +53,7 @@ def _create(P, p, **opt):
     keep.append(a)
     pr.edge_ij = ptr
     o = P._Options(opt.get("solver", 0), opt.get("precision", 0), opt.get("iterations", 3),
-                   opt.get("refine", 0), opt.get("lam", 0.0))
+                   opt.get("refine", 0), opt.get("lam", 0.0), opt.get("sparse_solve", 0), opt.get("flags", 0))
     h = ctypes.c_void_p()
     code = P.lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(o))
     return code, P.lib().dnls_last_error().decode()
@@ -81,6 +81,8 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, lam=-1.0)[0] == 1
     assert _create(P, p, refine=9)[0] == 1
     assert _create(P, p, precision=5)[0] == 1
+    assert _create(P, p, sparse_solve=3)[0] == 1
+    assert _create(P, p, flags=6)[0] == 1
 
 
 def test_null_arguments():

@@ -1,0 +1,96 @@
+"""Captured launch sequences (DNLS_FLAG_GRAPH) and forced sparse solve
+schedules give the same results as the eager launches.  Every replay is
+checked against the eager result, with eager work and host synchronisation
+between the replays; a change of the argument pointers forces a new capture."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+from gpu_util import t
+
+pytestmark = pytest.mark.gpu
+
+
+def _pose_graph_run(p, plan, poses0):
+    poses = poses0.clone()
+    dev = [t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"])]
+    obj, st = plan.solve(poses, *dev)
+    torch.cuda.synchronize()
+    return poses.cpu().numpy(), obj.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,refine", [("fp64", 0), ("mixed", 1)])
+def test_sparse_graph_replays_match_eager(precision, refine):
+    from paper_2207_09442_amd import Plan
+    p = synth.uneven_walk_se3(batch=6, n_min=20, n_max=90, seed=21)
+    poses0 = t(p["poses_init"])
+    eager = Plan(p, 6, lam=1e-3, solver="sparse", precision=precision, refine=refine, device=poses0.device)
+    ref = _pose_graph_run(p, eager, poses0)
+    graph = Plan(p, 6, lam=1e-3, solver="sparse", precision=precision, refine=refine, device=poses0.device,
+                 graph=True)
+    poses = poses0.clone()
+    dev = [t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"])]
+    for rep in range(4):
+        poses.copy_(poses0)                       # eager work between replays
+        obj, st = graph.solve(poses, *dev)        # same pointers: capture once, then replay
+        torch.cuda.synchronize()
+        assert np.array_equal(poses.cpu().numpy(), ref[0]), rep
+        assert np.array_equal(obj.cpu().numpy(), ref[1]), rep
+        assert np.array_equal(st.cpu().numpy(), ref[2]), rep
+        _pose_graph_run(p, eager, poses0)         # other work on the stream
+    # new pointers: recaptured
+    got = _pose_graph_run(p, graph, poses0)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_ba_graph_replays_match_eager():
+    from paper_2207_09442_amd import Plan
+    p = synth.bundle_adjustment(batch=2, n_cams=10, n_points=80, obs_per_point=5, seed=3)
+    dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]))
+    c0, q0 = t(p["poses_init"]), t(p["points_init"])
+    eager = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device)
+    cams, pts = c0.clone(), q0.clone()
+    obj_e, st_e = eager.solve_ba(cams, pts, **dev)
+    torch.cuda.synchronize()
+    ref = (cams.cpu().numpy(), pts.cpu().numpy(), obj_e.cpu().numpy())
+    graph = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device, graph=True)
+    cams, pts = c0.clone(), q0.clone()
+    for rep in range(3):
+        cams.copy_(c0)
+        pts.copy_(q0)
+        obj, st = graph.solve_ba(cams, pts, **dev)
+        torch.cuda.synchronize()
+        assert np.array_equal(cams.cpu().numpy(), ref[0]), rep
+        assert np.array_equal(pts.cpu().numpy(), ref[1]), rep
+        assert np.array_equal(obj.cpu().numpy(), ref[2]), rep
+
+
+def test_forced_sparse_solve_schedules_agree():
+    """WORKGROUP and SWEEPS triangular solves on the same problem: same
+    factor, different solve order, so the results agree to rounding."""
+    from paper_2207_09442_amd import Plan
+    p = synth.uneven_walk_se3(batch=5, n_min=20, n_max=90, seed=22)
+    poses0 = t(p["poses_init"])
+    a = _pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve="workgroup", device=poses0.device), poses0)
+    b = _pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve="sweeps", device=poses0.device), poses0)
+    assert np.abs(a[0] - b[0]).max() < 1e-12 * np.abs(a[0]).max()
+    assert a[2].tolist() == b[2].tolist() == [0] * 5
+
+
+def test_autotuner_picks_a_feasible_schedule_and_caches_it(tmp_path):
+    from paper_2207_09442_amd import Plan
+    from paper_2207_09442_amd import autotune as A
+    p = synth.uneven_walk_se3(batch=4, n_min=20, n_max=60, seed=23)
+    cache = str(tmp_path / "tune.json")
+    best = A.autotune(p, 5, 1e-3, cache_path=cache, reps=2)
+    assert best["solver"] in ("dense", "sparse") and best["ms"] > 0
+    assert all(c["ms"] is not None for c in best["candidates"])     # every schedule fits this problem
+    again = A.autotune(p, 5, 1e-3, cache_path=cache)
+    assert again == best                                               # served from the cache
+    poses0 = t(p["poses_init"])
+    ref = _pose_graph_run(p, Plan(p, 5, lam=1e-3, device=poses0.device), poses0)
+    got = _pose_graph_run(p, A.tuned_plan(p, 5, 1e-3, cache_path=cache), poses0)
+    assert np.abs(got[0] - ref[0]).max() < 1e-10 * np.abs(ref[0]).max()
