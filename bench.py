@@ -38,6 +38,7 @@ KERNEL_SOURCES = ["paper_2207_09442_amd/csrc/dnls.hip", "paper_2207_09442_amd/cs
                   "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/pose_costs.hpp",
                   "paper_2207_09442_amd/csrc/lie.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_dense_solve_se3_walk64_b128_traffic.txt")
+MFMA_SUMMARY = os.path.join(ROOT, "profiles", "k_dense_solve_se3_walk64_b128_mfma.txt")
 COST_FLOPS = 2100     # per pose-graph cost and linearisation: evaluation ~1000 + assembly ~1100
 OBS_FLOPS = 340       # per reprojection cost and linearisation
 BWD_COST_FLOPS = 400  # per cost in the backward (VJP)
@@ -84,21 +85,38 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _summary(path: str):
+    """key: value records of a committed rocprofv3 summary, or None if it is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(path) as fh:
+            rec = dict(line.split(":", 1) for line in fh.read().splitlines()
+                       if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    rec = {k.strip(): v.strip() for k, v in rec.items()}
+    return rec if rec.get("source_hash") == kernel_hash() else None
+
+
 def measured_traffic():
     """HBM bytes per launch of the mixed-precision solve kernel from the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by
     the same counters' reading on a plain copy of known size), or None if the
     summary was taken on other kernel sources."""
+    rec = _summary(TRAFFIC_SUMMARY)
     try:
-        with open(TRAFFIC_SUMMARY) as fh:
-            rec = dict(line.split(":", 1) for line in fh.read().splitlines() if ":" in line)
-    except OSError:
+        return float(rec["traffic_bytes_per_launch"]) if rec else None
+    except (KeyError, ValueError):
         return None
-    rec = {k.strip(): v.strip() for k, v in rec.items()}
-    if rec.get("source_hash") != kernel_hash():
-        return None
+
+
+def measured_mfma():
+    """MFMA busy fraction and executed FP64 MFMA flops per launch of the
+    mixed-precision solve kernel (rocprofv3 SQ counters), or None."""
+    rec = _summary(MFMA_SUMMARY)
     try:
-        return float(rec["traffic_bytes_per_launch"])
+        return dict(busy_frac=float(rec["mixed_mfma_busy_frac"]),
+                    executed_flops_per_launch=float(rec["mixed_mfma_flops_per_launch"])) if rec else None
     except (KeyError, ValueError):
         return None
 
@@ -281,6 +299,7 @@ def main():
     p.pop("_sparse", None)
     achieved = solve_flops / (head["fwd_ms"] * 1e-3) / 1e12
     single_kernel = solver == "dense"
+    head_default = args.workload == DEFAULT_WORKLOAD and solver == "dense" and main_prec == "mixed"
     kernel = ("k_dense_solve<3, true>" if main_prec == "mixed" else "k_dense_solve<%d, false>"
               % (3 if p["group"] == "SE3" else 2)) if single_kernel else "solve (all kernels of dnls_solve)"
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
@@ -306,7 +325,8 @@ def main():
         "breakdown": {"solve_ms": head["fwd_ms"], "backward_ms": head["bwd_ms"]},
         "roofline": {"bound": "mfma", "kernel": kernel, "achieved": achieved,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic() if args.workload == DEFAULT_WORKLOAD else None,
+                     "traffic": measured_traffic() if head_default else None,
+                     "mfma_counters": measured_mfma() if head_default else None,
                      "algorithmic_flops_per_launch": solve_flops,
                      "factor_flops_algorithmic": f_alg, "factor_flops_executed": f_exec},
     }
