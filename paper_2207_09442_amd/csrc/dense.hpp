@@ -228,7 +228,28 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
   const int lm = lane & 15, lq = lane >> 4;
   const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
   const int P = npad / kNB;
+  const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
   bool ok = true;
+  // the next group's H tile (transposed accumulator layout) and chunk 0 of
+  // its own rows, loaded while the current group finishes (its triangular
+  // solve, or for the diagonal group the write-back of L_JJ)
+  d4v acc_n[4], bop_n[4];
+  auto prefetch = [&](int J, int i0n) {
+    const int in = i0n + wave, col0 = kNB * J;
+    const bool act = in <= T16;
+    const double* Hr = H + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc_n[c][r] = act ? Hr[col0 + 16 * c + lq + 4 * r] : 0.0;
+    if (J > 0) {
+      const double* Ar = A + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        bop_n[kt] = act ? *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+    }
+  };
+  prefetch(0, 0);
   for (int J = 0; J < P; ++J) {
     const int col0 = kNB * J;
     const int nchunk = J;             // k chunks of 64 columns
@@ -236,24 +257,21 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
       const int i = i0 + wave;
       const bool active = i <= T16;
       const double* Arow = A + (size_t)(16 * i + lm) * npad;
-      const double* Hrow = H + (size_t)(16 * i + lm) * npad;
+      // the last group of a panel is the augmented-row tile (T16 = 4 P), so
+      // the diagonal group always has a successor in its own panel
+      const bool last_group = i0 + kNW > T16;
       // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
       d4v acc[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[c][r] = active ? Hrow[col0 + 16 * c + lq + 4 * r] : 0.0;
+      for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
       if (nchunk > 0) {
-        // stage chunk 0 of L_J[0:64][0:64] into LDS, prefetch this wave's operands
         d4v st[4], bop[4], bnx[4];
-        const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
+        for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-          bop[kt] = active ? *reinterpret_cast<const d4v*>(Arow + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
         __syncthreads();
         for (int ch = 0; ch < nchunk; ++ch) {
           const bool more = ch + 1 < nchunk;
@@ -298,6 +316,7 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
           for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
         __syncthreads();
         if (!chol_block<4>(D, s.W, s)) ok = false;
+        if (!last_group) prefetch(J, i0 + kNW);
         // write L_JJ (zero above the diagonal) and its inverse
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
@@ -305,22 +324,30 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
           winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
         __syncthreads();
-      } else if (active) {
-        // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
+      } else {
+        // the next group's loads (H, and L of panels before J) overlap this
+        // group's triangular solve, which writes panel J only
+        if (!last_group) prefetch(J, i0 + kNW);
+        if (active) {
+          // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
-        for (int cn = 0; cn < 4; ++cn) {
-          d4v out = {0.0, 0.0, 0.0, 0.0};
+          for (int cn = 0; cn < 4; ++cn) {
+            d4v out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int kt = 0; kt <= cn; ++kt) {
+            for (int kt = 0; kt <= cn; ++kt) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
+              for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
           }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
         }
       }
     }
     __syncthreads();
+    // the diagonal group of the next panel reads L of panel 0 (its chunk 0),
+    // which for J = 0 is written by this panel: load after the barrier
+    if (J + 1 < P) prefetch(J + 1, 4 * (J + 1));
   }
   return ok;
 }
