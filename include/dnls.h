@@ -104,12 +104,20 @@ typedef struct {
   double huber_delta;         /* Huber threshold on ||w c|| (> 0), SCHUR only */
 } dnls_problem;
 
-/* Triangular-solve schedule of the SPARSE solver: AUTO picks WORKGROUP when
- * every graph has at most 6144 (padded) unknowns, else SWEEPS.  WORKGROUP:
- * one workgroup per graph with the vector in LDS; SWEEPS: one launch per
- * tile column / row, one workgroup per tile.  Forcing WORKGROUP on a plan
- * whose graphs are too large is DNLS_ERR_UNSUPPORTED. */
-typedef enum { DNLS_SPSOLVE_AUTO = 0, DNLS_SPSOLVE_WORKGROUP = 1, DNLS_SPSOLVE_SWEEPS = 2 } dnls_sparse_solve;
+/* Schedule of the SPARSE solver's factorisation and triangular solves.
+ * WORKGROUP: both with one workgroup per graph (vector in LDS, no launches
+ * between tile steps); SWEEPS: one launch per tile column / row with one
+ * workgroup per tile, for both; HYBRID: per-column factorisation launches,
+ * workgroup solves.  AUTO: WORKGROUP when every graph has at most 6144
+ * (padded) unknowns and 16 tile columns, HYBRID when it has at most 6144
+ * unknowns, else SWEEPS.  WORKGROUP and HYBRID on a plan whose graphs exceed
+ * 6144 unknowns are DNLS_ERR_UNSUPPORTED. */
+typedef enum {
+  DNLS_SPSOLVE_AUTO = 0,
+  DNLS_SPSOLVE_WORKGROUP = 1,
+  DNLS_SPSOLVE_SWEEPS = 2,
+  DNLS_SPSOLVE_HYBRID = 3
+} dnls_sparse_solve;
 
 /* dnls_options.flags */
 enum {

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2}
+SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
 FLAG_GRAPH = 1
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}

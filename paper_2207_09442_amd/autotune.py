@@ -1,6 +1,8 @@
 """Schedule autotuner: picks the solver (dense per-graph kernel or
-block-sparse tiles), the sparse triangular-solve schedule (one workgroup per
-graph or per-tile sweeps) and HIP-graph capture for a problem structure by
+block-sparse tiles), the sparse schedule (factorisation and triangular
+solves in one workgroup per graph, per-column launches, or per-column
+factorisation with workgroup solves) and HIP-graph capture for a problem
+structure by
 timing every feasible candidate on the device, forward and implicit backward
 together.  Results are cached in a JSON file keyed by a hash of the
 structure and the optimizer settings, so a structure is tuned once.
@@ -25,6 +27,8 @@ CANDIDATES = [
     dict(solver="dense", sparse_solve="auto", graph=False),
     dict(solver="sparse", sparse_solve="workgroup", graph=False),
     dict(solver="sparse", sparse_solve="workgroup", graph=True),
+    dict(solver="sparse", sparse_solve="hybrid", graph=False),
+    dict(solver="sparse", sparse_solve="hybrid", graph=True),
     dict(solver="sparse", sparse_solve="sweeps", graph=False),
     dict(solver="sparse", sparse_solve="sweeps", graph=True),
 ]

@@ -491,7 +491,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->precision != DNLS_PREC_FP64 && op->precision != DNLS_PREC_MIXED)
     return fail(DNLS_ERR_INVALID_ARG, "unknown precision");
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
-  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_SWEEPS)
+  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
   if (op->flags & ~int32_t(DNLS_FLAG_GRAPH)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
   if (op->solver == DNLS_SOLVER_SCHUR) {

@@ -111,7 +111,8 @@ struct dnls_plan_s {
   std::vector<int> sp_nrow;       // per tile row: widest row (off-diagonal tiles) over the batch
   std::vector<long long> sp_npair;
   int sp_maxP = 0;
-  bool sp_solve_wg = false;       // every graph's vector fits one workgroup's LDS
+  bool sp_solve_wg = false;       // triangular solves: one workgroup per graph (vector in LDS)
+  bool sp_factor_wg = false;      // factorisation: one workgroup per graph
   size_t sp_off[8] = {0};
   std::vector<void*> allocs;
   // captured launch sequence of dnls_solve (DNLS_FLAG_GRAPH)

@@ -35,6 +35,8 @@ constexpr int kTS = 48;            // tile size
 constexpr int kTT = kTS * kTS;     // doubles per tile
 constexpr int kBT = 256;           // threads of the grid kernels
 constexpr int kTW = 192;           // threads of the tile kernels (3 waves x 16 rows)
+constexpr int kWG = 512;           // threads of the one-workgroup-per-graph kernels (2 waves per SIMD)
+constexpr int kWGW = kWG / 64;
 
 struct SpArgs {
   const SpDesc* sd;
@@ -371,6 +373,110 @@ __global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
     for (int r = 0; r < 4; ++r) T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
+// Whole numeric factorisation with one workgroup per graph (small graphs):
+// per tile column the diagonal tile is factored in LDS, then each wave takes
+// tiles of the column (L_IJ = A_IJ W^T) and then lower pairs of them
+// (A_IK -= L_IJ L_KJ^T), one 48x48 tile at a time, with no launches between
+// the steps.  Same arithmetic per tile as the per-column kernels.
+__device__ __forceinline__ void wave_tile_trsm(double* T, const double* W) {
+  // T <- T W^T, W lower triangular in LDS (stride kSP); one wave, three row slabs
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+#pragma unroll 1
+  for (int sr = 0; sr < 3; ++sr) {
+    d4v acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = d4v{0.0, 0.0, 0.0, 0.0};
+    const double* arow = T + (16 * sr + lm) * kTS;
+    d4v av[3];
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(arow + 16 * kt + 4 * lq);
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (kt > c) continue;
+        const d4v wv = *reinterpret_cast<const d4v*>(&W[(16 * c + lm) * kSP + 16 * kt + 4 * lq]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[c] = mfma16(av[kt][q], wv[q], acc[c]);
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
+  }
+}
+
+__device__ __forceinline__ void wave_tile_update(double* T, const double* LI, const double* LK) {
+  // T -= LI LK^T (48x48 tiles in global memory); one wave, three row slabs
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
+#pragma unroll 1
+  for (int sr = 0; sr < 3; ++sr) {
+    d4v acc[3], av[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[c][r] = T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm];
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * sr + lm) * kTS + 16 * kt + 4 * lq);
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const d4v bv = *reinterpret_cast<const d4v*>(LK + (16 * c + lm) * kTS + 16 * kt + 4 * lq);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[c] = mfma16(-av[kt][q], bv[q], acc[c]);
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
+  __shared__ DenseLds s;
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int wave = threadIdx.x >> 6;
+  for (int J = 0; J < g.P; ++J) {
+    // 1. diagonal tile
+    double* TJ = tile_ptr(a, g, J, J);
+    double* D = s.stage[0];
+    for (int e = threadIdx.x; e < kTT; e += kWG) D[(e / kTS) * kSP + e % kTS] = TJ[e];
+    __syncthreads();
+    const bool ok = chol_block<3>(D, s.W, s);
+    double* winv = a.factor + g.winv_off + (size_t)J * kTT;
+    for (int e = threadIdx.x; e < kTT; e += kWG) {
+      const int r = e / kTS, c = e % kTS;
+      TJ[e] = (c <= r) ? D[r * kSP + c] : 0.0;
+      winv[e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+    }
+    if (!ok) {
+      if (threadIdx.x == 0) {
+        a.failed[b] = DNLS_GRAPH_NOT_PD;
+        a.status[b] = DNLS_GRAPH_NOT_PD;
+      }
+      return;
+    }
+    const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
+    // 2. L_IJ = A_IJ W^T for the tiles below the diagonal (W stays in LDS)
+    for (int t = wave; t < m; t += kWGW) wave_tile_trsm(tile_ptr(a, g, a.rowidx[c0 + 1 + t], J), s.W);
+    __syncthreads();
+    // 3. A_IK -= L_IJ L_KJ^T for every lower pair of them
+    const int npair = m * (m + 1) / 2;
+    for (int t = wave; t < npair; t += kWGW) {
+      int p = (int)((::sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((p + 1) * (p + 2) / 2 <= t) ++p;
+      while (p * (p + 1) / 2 > t) --p;
+      const int q = t - p * (p + 1) / 2;
+      const int I = a.rowidx[c0 + 1 + p], K = a.rowidx[c0 + 1 + q];
+      wave_tile_update(tile_ptr(a, g, I, K), tile_ptr(a, g, I, J), tile_ptr(a, g, K, J));
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Triangular solves L L^T x = b as sweeps of one launch per tile column
 // (forward) and per tile row (backward); every tile of the column / row is
@@ -491,27 +597,33 @@ __global__ void __launch_bounds__(kTW) k_sp_bwd(SpArgs a, int I, int zs, int dst
 // the transposed tiles of the row.  Two barriers per tile step and no
 // launches, where the sweeps need two launches per tile column.
 constexpr int kSolveLds = 6144;
-__global__ void __launch_bounds__(kBT) k_sp_solve_wg(SpArgs a, int src, int dst) {
+constexpr int kFactorWgMaxP = 16;  // AUTO: one-workgroup factorisation up to 16 tile columns
+__global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst) {
   __shared__ double v[kSolveLds];
+  __shared__ double Wl[kTS * kSW];
   __shared__ double y[kTS];
   const int b = blockIdx.x;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
   const double* bsrc = slot(a, g, src);
-  for (int u = threadIdx.x; u < g.nvec; u += kBT) v[u] = bsrc[u];
-  __syncthreads();
+  for (int u = threadIdx.x; u < g.nvec; u += kWG) v[u] = bsrc[u];
+  // the 48 products with W are split over 4 adjacent lanes each (12 terms)
+  const int wr = threadIdx.x >> 2, wp = threadIdx.x & 3;
   for (int J = 0; J < g.P; ++J) {
-    const double* W = a.factor + g.winv_off + (size_t)J * kTT;
-    if (threadIdx.x < kTS) {
-      const int c = threadIdx.x;
+    stage_tile(Wl, a.factor + g.winv_off + (size_t)J * kTT);   // coalesced
+    __syncthreads();
+    if (threadIdx.x < 4 * kTS) {
       double acc = 0.0;
-      for (int k = 0; k <= c; ++k) acc += W[c * kTS + k] * v[J * kTS + k];
-      y[c] = acc;
+#pragma unroll
+      for (int k = 12 * wp; k < 12 * wp + 12; ++k) acc += (k <= wr) ? Wl[wr * kSW + k] * v[J * kTS + k] : 0.0;
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (wp == 0) y[wr] = acc;
     }
     __syncthreads();
     if (threadIdx.x < kTS) v[J * kTS + threadIdx.x] = y[threadIdx.x];
     const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
-    for (int e = threadIdx.x; e < m * kTS; e += kBT) {
+    for (int e = threadIdx.x; e < m * kTS; e += kWG) {
       const int I = a.rowidx[c0 + 1 + e / kTS], r = e % kTS;
       const d4v* row = reinterpret_cast<const d4v*>(tile_ptr(a, g, I, J) + r * kTS);
       double acc = 0.0;
@@ -525,28 +637,31 @@ __global__ void __launch_bounds__(kBT) k_sp_solve_wg(SpArgs a, int src, int dst)
     __syncthreads();
   }
   for (int I = g.P - 1; I >= 0; --I) {
-    const double* W = a.factor + g.winv_off + (size_t)I * kTT;
-    if (threadIdx.x < kTS) {
-      const int c = threadIdx.x;
+    stage_tile(Wl, a.factor + g.winv_off + (size_t)I * kTT);
+    __syncthreads();
+    if (threadIdx.x < 4 * kTS) {
       double acc = 0.0;
-      for (int r = c; r < kTS; ++r) acc += W[r * kTS + c] * v[I * kTS + r];
-      y[c] = acc;
+#pragma unroll
+      for (int r = 12 * wp; r < 12 * wp + 12; ++r) acc += (r >= wr) ? Wl[r * kSW + wr] * v[I * kTS + r] : 0.0;
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (wp == 0) y[wr] = acc;
     }
     __syncthreads();
     if (threadIdx.x < kTS) v[I * kTS + threadIdx.x] = y[threadIdx.x];
     const int r0 = a.rowptr[g.row_off + I], nr = a.rowptr[g.row_off + I + 1] - r0;
-    for (int e = threadIdx.x; e < nr * kTS; e += kBT) {
+    for (int e = threadIdx.x; e < nr * kTS; e += kWG) {
       const int J = a.rowcol[r0 + e / kTS], c = e % kTS;
       const double* T = tile_ptr(a, g, I, J);
       double acc = 0.0;
-#pragma unroll 8
+#pragma unroll 16
       for (int r = 0; r < kTS; ++r) acc += T[r * kTS + c] * y[r];
       v[J * kTS + c] -= acc;
     }
     __syncthreads();
   }
   double* xdst = slot(a, g, dst);
-  for (int u = threadIdx.x; u < g.nvec; u += kBT) xdst[u] = v[u];
+  for (int u = threadIdx.x; u < g.nvec; u += kWG) xdst[u] = v[u];
 }
 
 // slot[to] = slot[from] (grid x over the vector, y over graphs)
@@ -844,11 +959,16 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   }
   p->sp_maxP = maxP;
   const bool fits = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
-  if (p->opt.sparse_solve == DNLS_SPSOLVE_WORKGROUP && !fits)
+  const int mode = p->opt.sparse_solve;
+  if ((mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID) && !fits)
     return fail(DNLS_ERR_UNSUPPORTED, "the workgroup solve holds at most " + std::to_string(kSolveLds) +
                                           " unknowns per graph");
-  p->sp_solve_wg = p->opt.sparse_solve == DNLS_SPSOLVE_WORKGROUP ||
-                   (p->opt.sparse_solve == DNLS_SPSOLVE_AUTO && fits);
+  // AUTO: everything in one workgroup per graph for graphs of a few tile
+  // columns; the per-column launches spread larger graphs over the chip
+  const bool small = fits && maxP <= kFactorWgMaxP;
+  p->sp_solve_wg = mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID ||
+                   (mode == DNLS_SPSOLVE_AUTO && fits);
+  p->sp_factor_wg = mode == DNLS_SPSOLVE_WORKGROUP || (mode == DNLS_SPSOLVE_AUTO && small);
   dnls_status st;
   if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
       (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK || (st = upload(p, &p->d_pos, pos)) != DNLS_OK ||
@@ -913,6 +1033,10 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
 template <int G>
 static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
   const int B = p->B;
+  if (p->sp_factor_wg) {
+    hipLaunchKernelGGL(k_sp_factor_wg, dim3(B), dim3(kWG), 0, st, a);
+    return;
+  }
   for (int J = 0; J < p->sp_maxP; ++J) {
     hipLaunchKernelGGL(k_sp_diag, dim3(B), dim3(kNT), 0, st, a, J);
     if (p->sp_ntrsm[J] > 0) {
@@ -926,7 +1050,7 @@ static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
 static void sp_sweeps(dnls_plan p, const SpArgs& a, int dst, hipStream_t st) {
   const int B = p->B;
   if (p->sp_solve_wg) {
-    hipLaunchKernelGGL(k_sp_solve_wg, dim3(B), dim3(kBT), 0, st, a, 2, dst);
+    hipLaunchKernelGGL(k_sp_solve_wg, dim3(B), dim3(kWG), 0, st, a, 2, dst);
     return;
   }
   for (int J = 0; J < p->sp_maxP; ++J)

@@ -81,7 +81,7 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, lam=-1.0)[0] == 1
     assert _create(P, p, refine=9)[0] == 1
     assert _create(P, p, precision=5)[0] == 1
-    assert _create(P, p, sparse_solve=3)[0] == 1
+    assert _create(P, p, sparse_solve=4)[0] == 1
     assert _create(P, p, flags=6)[0] == 1
 
 

@@ -68,16 +68,19 @@ def test_ba_graph_replays_match_eager():
         assert np.array_equal(obj.cpu().numpy(), ref[2]), rep
 
 
-def test_forced_sparse_solve_schedules_agree():
-    """WORKGROUP and SWEEPS triangular solves on the same problem: same
-    factor, different solve order, so the results agree to rounding."""
+def test_forced_sparse_schedules_agree():
+    """WORKGROUP (factor and solves in one workgroup per graph), HYBRID
+    (per-column factor launches, workgroup solves) and SWEEPS on the same
+    problem: the same tile arithmetic in different orders, so the results
+    agree to rounding."""
     from paper_2207_09442_amd import Plan
     p = synth.uneven_walk_se3(batch=5, n_min=20, n_max=90, seed=22)
     poses0 = t(p["poses_init"])
-    a = _pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve="workgroup", device=poses0.device), poses0)
-    b = _pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve="sweeps", device=poses0.device), poses0)
-    assert np.abs(a[0] - b[0]).max() < 1e-12 * np.abs(a[0]).max()
-    assert a[2].tolist() == b[2].tolist() == [0] * 5
+    runs = [_pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve=m, device=poses0.device), poses0)
+            for m in ("workgroup", "hybrid", "sweeps")]
+    for r in runs[1:]:
+        assert np.abs(r[0] - runs[0][0]).max() < 1e-12 * np.abs(runs[0][0]).max()
+        assert r[2].tolist() == runs[0][2].tolist() == [0] * 5
 
 
 def test_autotuner_picks_a_feasible_schedule_and_caches_it(tmp_path):
