@@ -374,63 +374,59 @@ __global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
 }
 
 // Whole numeric factorisation with one workgroup per graph (small graphs):
-// per tile column the diagonal tile is factored in LDS, then each wave takes
-// tiles of the column (L_IJ = A_IJ W^T) and then lower pairs of them
-// (A_IK -= L_IJ L_KJ^T), one 48x48 tile at a time, with no launches between
-// the steps.  Same arithmetic per tile as the per-column kernels.
-__device__ __forceinline__ void wave_tile_trsm(double* T, const double* W) {
-  // T <- T W^T, W lower triangular in LDS (stride kSP); one wave, three row slabs
+// per tile column the diagonal tile is factored in LDS, then the waves take
+// 16-row slabs of the column's tiles (L_IJ = A_IJ W^T) and then of the lower
+// pairs of them (A_IK -= L_IJ L_KJ^T), with no launches between the steps.
+// Same arithmetic per tile as the per-column kernels.
+// One 16-row slab of a 48x48 tile operation per wave; every operand of the
+// slab is loaded before its first product (one memory round trip).
+// Slab sr of T <- T W^T, W lower triangular in LDS (stride kSP).
+__device__ __forceinline__ void wave_slab_trsm(double* T, const double* W, int sr) {
   const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
-#pragma unroll 1
-  for (int sr = 0; sr < 3; ++sr) {
-    d4v acc[3];
+  d4v av[3], acc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = d4v{0.0, 0.0, 0.0, 0.0};
-    const double* arow = T + (16 * sr + lm) * kTS;
-    d4v av[3];
+  for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(T + (16 * sr + lm) * kTS + 16 * kt + 4 * lq);
 #pragma unroll
-    for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(arow + 16 * kt + 4 * lq);
+  for (int c = 0; c < 3; ++c) acc[c] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kt = 0; kt < 3; ++kt)
+  for (int kt = 0; kt < 3; ++kt)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (kt > c) continue;
-        const d4v wv = *reinterpret_cast<const d4v*>(&W[(16 * c + lm) * kSP + 16 * kt + 4 * lq]);
+    for (int c = 0; c < 3; ++c) {
+      if (kt > c) continue;
+      const d4v wv = *reinterpret_cast<const d4v*>(&W[(16 * c + lm) * kSP + 16 * kt + 4 * lq]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[c] = mfma16(av[kt][q], wv[q], acc[c]);
-      }
+      for (int q = 0; q < 4; ++q) acc[c] = mfma16(av[kt][q], wv[q], acc[c]);
+    }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
-  }
+    for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
-__device__ __forceinline__ void wave_tile_update(double* T, const double* LI, const double* LK) {
-  // T -= LI LK^T (48x48 tiles in global memory); one wave, three row slabs
+// slab sr of T -= LI LK^T (48x48 tiles in global memory)
+__device__ __forceinline__ void wave_slab_update(double* T, const double* LI, const double* LK, int sr) {
   const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
-#pragma unroll 1
-  for (int sr = 0; sr < 3; ++sr) {
-    d4v acc[3], av[3];
+  d4v acc[3], av[3], bv[3][3];
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bv[kt][c] = *reinterpret_cast<const d4v*>(LK + (16 * c + lm) * kTS + 16 * kt + 4 * lq);
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * sr + lm) * kTS + 16 * kt + 4 * lq);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[c][r] = T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm];
+#pragma unroll
+  for (int kt = 0; kt < 3; ++kt)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[c][r] = T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm];
+      for (int q = 0; q < 4; ++q) acc[c] = mfma16(-av[kt][q], bv[kt][c][q], acc[c]);
 #pragma unroll
-    for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * sr + lm) * kTS + 16 * kt + 4 * lq);
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int kt = 0; kt < 3; ++kt)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const d4v bv = *reinterpret_cast<const d4v*>(LK + (16 * c + lm) * kTS + 16 * kt + 4 * lq);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[c] = mfma16(-av[kt][q], bv[q], acc[c]);
-      }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
-  }
+    for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
 __global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
@@ -461,17 +457,20 @@ __global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
     }
     const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
     // 2. L_IJ = A_IJ W^T for the tiles below the diagonal (W stays in LDS)
-    for (int t = wave; t < m; t += kWGW) wave_tile_trsm(tile_ptr(a, g, a.rowidx[c0 + 1 + t], J), s.W);
+#pragma unroll 1
+    for (int u = wave; u < 3 * m; u += kWGW) wave_slab_trsm(tile_ptr(a, g, a.rowidx[c0 + 1 + u / 3], J), s.W, u % 3);
     __syncthreads();
     // 3. A_IK -= L_IJ L_KJ^T for every lower pair of them
     const int npair = m * (m + 1) / 2;
-    for (int t = wave; t < npair; t += kWGW) {
+#pragma unroll 1
+    for (int u = wave; u < 3 * npair; u += kWGW) {
+      const int t = u / 3;
       int p = (int)((::sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
       while ((p + 1) * (p + 2) / 2 <= t) ++p;
       while (p * (p + 1) / 2 > t) --p;
       const int q = t - p * (p + 1) / 2;
       const int I = a.rowidx[c0 + 1 + p], K = a.rowidx[c0 + 1 + q];
-      wave_tile_update(tile_ptr(a, g, I, K), tile_ptr(a, g, I, J), tile_ptr(a, g, K, J));
+      wave_slab_update(tile_ptr(a, g, I, K), tile_ptr(a, g, I, J), tile_ptr(a, g, K, J), u % 3);
     }
     __syncthreads();
   }
