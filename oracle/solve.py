@@ -11,6 +11,13 @@ Forward (Section 2 "Solving NLS"; Section 4.2): for t = 0..K-1
 Then a final linearisation at theta_K (lambda = 0) gives S_K and the
 undamped Gauss-Newton Hessian H*, whose factor is kept for the backward.
 
+Adaptive damping (the paper's Levenberg-Marquardt with adaptive damping,
+Sections 2 and 3; schedule as read for this implementation): after step 4
+the objective is evaluated at the retracted trial point; the step is kept
+iff it is strictly smaller than S_t, and then lambda <- lambda / 10,
+otherwise theta_t is kept and lambda <- 10 lambda, lambda clamped to
+[1e-7, 1e7].
+
 Bundle adjustment eliminates the point blocks with the Schur complement
 (Section 4.2, BaSpaCho paragraph): S = B - E C^-1 E^T on the camera block,
 then back-substitutes delta_p = C^-1 (g_p - E^T delta_c).
@@ -279,14 +286,19 @@ class GraphResult:
     status: int
     lin: Lin | None = None        # final linearisation at theta_K
     factor: tuple | None = None   # cached factor of H* (or of the Schur complement)
+    lambdas: list | None = None   # adaptive damping: lambda used at each step
 
 
-def solve_graph(g: Graph, iterations: int, lam: float, tau=None) -> GraphResult:
+LAMBDA_MIN, LAMBDA_MAX = 1e-7, 1e7
+
+
+def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool = False) -> GraphResult:
     if tau is None:
         tau = g.tau
     X = g.X.clone()
     pts = None if g.pts is None else g.pts.clone()
     obj, status = [], OK
+    lambdas = [] if adaptive else None
     for _ in range(iterations):
         if g.is_ba:
             lin = linearize_ba(g, X, pts)
@@ -311,8 +323,17 @@ def solve_graph(g: Graph, iterations: int, lam: float, tau=None) -> GraphResult:
             if delta is None:
                 status = NOT_PD
                 break
-            X = g.G.retract(X, -delta.reshape(-1, g.G.dof))
-    res = GraphResult(X=X, pts=pts, objective=obj, status=status)
+            trial = g.G.retract(X, -delta.reshape(-1, g.G.dof))
+            if adaptive:
+                lambdas.append(lam)
+                s_trial = float(linearize_pose_graph(g, trial, tau=tau).S)
+                if s_trial < float(lin.S):          # NaN compares false: rejected
+                    X, lam = trial, max(lam / 10.0, LAMBDA_MIN)
+                else:
+                    lam = min(lam * 10.0, LAMBDA_MAX)
+            else:
+                X = trial
+    res = GraphResult(X=X, pts=pts, objective=obj, status=status, lambdas=lambdas)
     if status != OK:
         res.objective = obj + [obj[-1]] * (iterations + 1 - len(obj))
         return res

@@ -274,3 +274,69 @@ def test_unrolled_gradient_approaches_gn_implicit_linearly_in_noise():
     g1, g2, g3 = gap(1.0), gap(0.1), gap(0.01)
     assert 1e-3 < g1 < 0.1
     assert 0.05 < g2 / g1 < 0.2 and 0.05 < g3 / g2 < 0.2
+
+
+def _single_pose_rotation_problem(group, theta0):
+    """One pose, only its prior, off by a pure rotation theta0 about z."""
+    G = lie.group(group)
+    d = G.dof
+    P = G.exp(torch.as_tensor(np.array([[0.3, -0.2, 0.1, 0.05, -0.1, 0.2][:d]]), dtype=torch.float64))
+    rot = np.zeros((1, d))
+    rot[0, d - 1] = theta0
+    X0 = P @ G.exp(torch.as_tensor(rot, dtype=torch.float64))
+    store = lambda X: G.to_storage(X).numpy()
+    return {
+        "group": group, "pose_off": np.array([0, 1], np.int32), "poses_init": store(X0), "poses_gt": store(P),
+        "edge_off": np.array([0, 0], np.int32), "edge_ij": np.zeros((0, 2), np.int32),
+        "edge_meas": store(P)[:0], "edge_logw": np.zeros(0),
+        "prior_off": np.array([0, 1], np.int32), "prior_var": np.array([0], np.int32),
+        "prior_meas": store(P), "prior_logw": np.zeros(1),
+    }
+
+
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+def test_adaptive_lm_closed_form_single_pose(group):
+    """Adaptive damping on one pose with a pure-rotation prior error theta:
+    the Jacobian is block diagonal with a unit rotation block, so the damped
+    step is theta / (1 + lambda), every step decreases S = theta^2 / 2 and is
+    kept, lambda is divided by 10 each time (floor 1e-7), and
+    theta_K = theta_0 prod_t lambda_t / (1 + lambda_t)."""
+    theta0, lam0, K = 0.7, 1.0, 9
+    p = _single_pose_rotation_problem(group, theta0)
+    g = S.graphs_of(p)[0]
+    r = S.solve_graph(g, K, lam0, adaptive=True)
+    lams, theta = [], theta0
+    lam = lam0
+    for _ in range(K):
+        lams.append(lam)
+        theta *= lam / (1.0 + lam)
+        lam = max(lam / 10.0, 1e-7)
+    assert r.lambdas == pytest.approx(lams, rel=1e-15)
+    G = lie.group(group)
+    err = G.log(G.inv(g.PZ[0]) @ r.X[0])
+    expect = np.zeros(G.dof)
+    expect[-1] = theta
+    assert np.abs(err.numpy() - expect).max() < 1e-12 * theta0
+    assert r.objective[-1] == pytest.approx(0.5 * theta ** 2, rel=1e-10)
+
+
+def test_adaptive_lm_rejects_and_recovers():
+    """SE(2) circle from a poor initial guess: the first two damped steps
+    increase the objective and are rejected (theta kept, objective repeated,
+    lambda x 10); afterwards steps are kept (lambda / 10).  The objective
+    sequence never increases, and each repeat coincides with a x10."""
+    p = synth.circle_se2(batch=1, seed=3)
+    g = S.graphs_of(p)[0]
+    rng = np.random.default_rng(13)
+    xi = torch.zeros(g.X.shape[0], 3, dtype=torch.float64)
+    xi[:, 2] = torch.as_tensor(rng.normal(scale=1.6, size=g.X.shape[0]))
+    xi[:, :2] = torch.as_tensor(rng.normal(scale=1.6, size=(g.X.shape[0], 2)))
+    g.X = lie.SE2.retract(g.X, xi)
+    K = 8
+    r = S.solve_graph(g, K, 1e-4, adaptive=True)
+    ob, lams = r.objective, r.lambdas
+    assert all(ob[t + 1] <= ob[t] for t in range(K))
+    rejected = [ob[t + 1] == ob[t] for t in range(K - 1)]
+    assert rejected[:2] == [True, True] and not any(rejected[2:5])
+    for t in range(K - 1):
+        assert lams[t + 1] == (min(lams[t] * 10.0, 1e7) if rejected[t] else max(lams[t] / 10.0, 1e-7))
