@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
                     help="override the workload's solver (pose graphs only)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="Levenberg-Marquardt with adaptive damping from the workload's lambda (dense solver)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick solver, sparse solve schedule and graph capture with the autotuner "
                          "(pose graphs only; timed before the benchmark, cached)")
@@ -216,13 +218,13 @@ def main():
     else:
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
-    schedule = dict(sparse_solve="auto", graph=False)
+    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive))
     if args.autotune and not ba:
         from paper_2207_09442_amd.autotune import autotune
         best = autotune(p, K, lam, precision=W["precision"], refine=args.refine if W["precision"] == "mixed" else 0,
                         device=dev)
         solver = best["solver"]
-        schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"])
+        schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"], adaptive=bool(args.adaptive))
         progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
 
     def run(precision: str, refine: int):

@@ -26,6 +26,7 @@ SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
 FLAG_GRAPH = 1
+FLAG_ADAPTIVE_LM = 2
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
 
@@ -127,7 +128,7 @@ class Plan:
 
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
-                 graph: bool = False):
+                 graph: bool = False, adaptive: bool = False):
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -159,9 +160,10 @@ class Plan:
             pr.fx, pr.fy, pr.cx, pr.cy = (float(x) for x in problem["intrinsics"])
             pr.huber_delta = float(problem["huber_delta"])
         op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam),
-                      SPARSE_SOLVES[sparse_solve], FLAG_GRAPH if graph else 0)
+                      SPARSE_SOLVES[sparse_solve],
+                      (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0))
         self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
-                           sparse_solve=sparse_solve, graph=bool(graph))
+                           sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive))
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h

@@ -56,6 +56,8 @@ struct DenseArgs {
   float* ws32;       // per-cost records, float32 (mixed)
   double* ycost;     // per-cost J delta (d values)
   double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
+  double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated
+  int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
   const double* seed;
   double* g_logw_e;
   double* g_tau;
@@ -101,9 +103,19 @@ __device__ double linearize_graph(const DenseArgs& a, const GraphDesc& g, S* rec
   return block_sum(sacc, red);
 }
 
-// Assemble the lower triangle of H (+ lambda on the diagonal, identity on the
-// padding) into A (row-major npad x npad plus the 16-row augmented tile),
-// one thread per 6x6 (3x3) Hessian block, products accumulated in precision S.
+// objective 1/2 sum w^2 ||c||^2 of the graph at the current poses, float64
+template <int G>
+__device__ double objective_graph(const DenseArgs& a, const GraphDesc& g, double* red) {
+  const PoseCostData cd = cost_data(a);
+  double sacc = 0.0;
+  const int ncost = g.nedge + g.nprior;
+  for (int k = threadIdx.x; k < ncost; k += kNT) {
+    const int rk = (k < g.nedge) ? g.edge0 + k : a.E + g.prior0 + (k - g.nedge);
+    sacc += cost_objective<G>(cd, rk);
+  }
+  return block_sum(sacc, red);
+}
+
 // Once per solve: zero every row of H up to the end of its 64-wide diagonal
 // block (the part the factorisation reads) and the augmented tile, and put
 // 1 on the diagonal of the padding.  The assembly then rewrites only the
@@ -122,7 +134,8 @@ __device__ void init_H(const GraphDesc& g, double* A) {
 }
 
 // H = sum J^T J (+ lambda I) on the non-zero 6x6 / 3x3 blocks of the lower
-// triangle (H prepared by init_H)
+// triangle (H prepared by init_H), one thread per block, products
+// accumulated in precision S
 template <int G, class S>
 __device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec, double* A, double lambda) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
@@ -265,6 +278,8 @@ __device__ void matvec_H(const DenseArgs& a, const GraphDesc& g, const double* r
   __syncthreads();
 }
 
+constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;   // adaptive damping range
+
 struct KernelLds {
   DenseLds dl;
   double red[kNW];
@@ -290,10 +305,11 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   int status = DNLS_GRAPH_OK;
   double last_obj = 0.0;
   int last_it = 0;
+  double lam_cur = a.lambda;       // adaptive damping: this graph's lambda
   init_H(g, H);
   for (int it = 0; it <= a.K; ++it) {
     const bool final_lin = (it == a.K);
-    const double lam = final_lin ? 0.0 : a.lambda;
+    const double lam = final_lin ? 0.0 : lam_cur;
     double S = 0.0;
     // the mixed path linearises in float32 inside the loop; the float64
     // linearisation feeds its refinement sweeps and the final (cached) factor
@@ -343,6 +359,25 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
+    }
+    if (a.adaptive) {
+      // adaptive damping: keep the step iff the float64 objective strictly
+      // decreases (lambda / 10), else restore theta_t (lambda x 10)
+      const double s_t = (MIXED && a.refine == 0) ? objective_graph<G>(a, g, L.red) : S;
+      double* bak = a.pose_bak + (size_t)g.pose0 * sz;
+      for (int u = threadIdx.x; u < g.npose * sz; u += kNT) bak[u] = a.poses[(size_t)g.pose0 * sz + u];
+      for (int p = threadIdx.x; p < g.npose; p += kNT)
+        retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, vb + p * d);
+      __syncthreads();
+      const double s_trial = objective_graph<G>(a, g, L.red);
+      if (s_trial < s_t) {
+        lam_cur = fmax(lam_cur / 10.0, kLambdaMin);
+      } else {
+        for (int u = threadIdx.x; u < g.npose * sz; u += kNT) a.poses[(size_t)g.pose0 * sz + u] = bak[u];
+        lam_cur = fmin(lam_cur * 10.0, kLambdaMax);
+      }
+      __syncthreads();
+      continue;
     }
     // retraction X <- X Exp(-delta)
     for (int p = threadIdx.x; p < g.npose; p += kNT)
@@ -493,7 +528,9 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
-  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
+  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
+  if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver != DNLS_SOLVER_DENSE)
+    return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the dense solver");
   if (op->solver == DNLS_SOLVER_SCHUR) {
     auto* p = new dnls_plan_s();
     p->B = pr->batch;
@@ -635,6 +672,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   ws += align256(ncost * d * sizeof(double));
   p->h_off = ws;
   ws += align256((size_t)hsz * sizeof(double));
+  p->bak_off = ws;
+  if (op->flags & DNLS_FLAG_ADAPTIVE_LM) ws += align256((size_t)V * p->sz * sizeof(double));
   p->ws_bytes = ws;
   p->bwd_bytes = p->h_off;   // the backward does not use the assembled systems
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -741,6 +780,8 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.ws32 = reinterpret_cast<float*>(ws + p->ws32_off);
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
+  a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
+  a.adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) ? 1 : 0;
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
   return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);

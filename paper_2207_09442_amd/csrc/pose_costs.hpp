@@ -60,6 +60,30 @@ __device__ __forceinline__ double linearize_cost(const PoseCostData& a, int k, S
   return 0.5 * w * w * cc;
 }
 
+// 1/2 w^2 ||c||^2 of cost k in float64 (residual only: the Jacobian outputs
+// of the cost functions are dead and removed by the compiler).
+template <int G>
+__device__ __forceinline__ double cost_objective(const PoseCostData& a, int k) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  double c[d], Ci[d * d], Cj[d * d];
+  double w;
+  if (k < a.E) {
+    const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+    double Z[sz];
+    perturbed_meas<G>(a.edge_meas + (size_t)k * sz, a.edge_tau ? a.edge_tau + (size_t)k * d : nullptr, Z);
+    between_cost<G, double>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
+    w = exp(a.edge_logw[k]);
+  } else {
+    const int p = k - a.E;
+    prior_cost<G, double>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Cj);
+    w = exp(a.prior_logw[p]);
+  }
+  double cc = 0.0;
+#pragma unroll
+  for (int q = 0; q < d; ++q) cc += c[q] * c[q];
+  return 0.5 * w * w * cc;
+}
+
 // Per-cost VJP of cost k from its float64 record and the adjoint u of its
 // poses (ui is null for a prior).  Null gradient outputs are skipped.
 template <int G>

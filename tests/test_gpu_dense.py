@@ -41,11 +41,12 @@ def _seeds(p, poses_ref_by_graph, graphs):
 
 
 def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_pose=1e-10, tol_grad=1e-10,
-             gate_grad=True, grad_cond_scale=None, solver="dense"):
-    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver)
+             gate_grad=True, grad_cond_scale=None, solver="dense", adaptive=False):
+    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver,
+                                                    adaptive=adaptive)
     B = len(p["pose_off"]) - 1
     graphs = list(range(B)) if graphs is None else graphs
-    gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs)
+    gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs, adaptive=adaptive)
     got = poses.cpu().numpy()
     G = gs[0].G
     ref_poses = [G.to_storage(r.X).numpy() for r in res]
@@ -84,6 +85,12 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
     assert worst_obj < max(tol_pose, 1e-12) * (1e3 if precision == "mixed" else 1)
     if gate_grad:
         assert not over, over
+    if adaptive:
+        # same accept / reject decisions: a rejected step repeats the objective exactly
+        for gi, b in enumerate(graphs):
+            rep_gpu = [obj[b][t + 1] == obj[b][t] for t in range(K)]
+            rep_ref = [res[gi].objective[t + 1] == res[gi].objective[t] for t in range(K)]
+            assert rep_gpu == rep_ref, (b, rep_gpu, rep_ref)
     return worst_pose, worst_grad
 
 
@@ -278,3 +285,64 @@ def test_gpu_implicit_gradient_against_oracle_unrolled(solver):
     gap = rel(mine, unrolled)
     print(f"\n[{solver}] GPU implicit vs oracle unrolled: {gap:.2e}")
     assert gap < 1e-3
+
+
+
+def _single_pose_rotation(group, theta0):
+    from oracle import lie
+    G = lie.group(group)
+    d = G.dof
+    P = G.exp(torch.as_tensor(np.array([[0.3, -0.2, 0.1, 0.05, -0.1, 0.2][:d]]), dtype=torch.float64))
+    rot = np.zeros((1, d))
+    rot[0, d - 1] = theta0
+    X0 = P @ G.exp(torch.as_tensor(rot, dtype=torch.float64))
+    st = lambda X: G.to_storage(X).numpy()
+    return {"group": group, "pose_off": np.array([0, 1], np.int32), "poses_init": st(X0), "poses_gt": st(P),
+            "edge_off": np.array([0, 0], np.int32), "edge_ij": np.zeros((0, 2), np.int32),
+            "edge_meas": st(P)[:0], "edge_logw": np.zeros(0), "prior_off": np.array([0, 1], np.int32),
+            "prior_var": np.array([0], np.int32), "prior_meas": st(P), "prior_logw": np.zeros(1)}
+
+
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+def test_adaptive_lm_closed_form_single_pose(group):
+    """Adaptive damping from lambda = 1 on a pure-rotation prior error:
+    theta_K = theta_0 prod_t lambda_t / (1 + lambda_t), lambda_t = 10^-t.
+    K = 3 keeps theta_K (3e-4) far from the rounding floor, where the loss
+    seed and the prior-weight gradient (both O(theta^2)) are still
+    meaningful."""
+    from oracle import lie
+    theta0, K = 0.7, 3
+    p = _single_pose_rotation(group, theta0)
+    plan, poses, objective, status, dev = gpu_solve(p, K, 1.0, adaptive=True)
+    theta, lam = theta0, 1.0
+    for _ in range(K):
+        theta *= lam / (1.0 + lam)
+        lam = max(lam / 10.0, 1e-7)
+    G = lie.group(group)
+    X = G.from_storage(torch.as_tensor(poses.cpu().numpy()))
+    err = G.log(G.inv(G.from_storage(torch.as_tensor(p["prior_meas"]))) @ X)[0].numpy()
+    expect = np.zeros(G.dof)
+    expect[-1] = theta
+    assert np.abs(err - expect).max() < 1e-12 * theta0
+    _compare(p, K, 1.0, adaptive=True)
+
+
+def test_adaptive_lm_rejects_and_recovers():
+    """SE(2) circle from a poor initial guess: the first two steps are
+    rejected; the GPU takes the same decisions as the oracle and matches its
+    poses, objectives and implicit gradients."""
+    from oracle import lie
+    p = synth.circle_se2(batch=1, seed=3)
+    rng_ = np.random.default_rng(13)
+    X = lie.SE2.from_storage(torch.as_tensor(p["poses_init"]))
+    xi = torch.zeros(X.shape[0], 3, dtype=torch.float64)
+    xi[:, 2] = torch.as_tensor(rng_.normal(scale=1.6, size=X.shape[0]))
+    xi[:, :2] = torch.as_tensor(rng_.normal(scale=1.6, size=(X.shape[0], 2)))
+    p["poses_init"] = lie.SE2.to_storage(lie.SE2.retract(X, xi)).numpy()
+    _compare(p, 6, 1e-4, adaptive=True)
+
+
+def test_adaptive_lm_se3_batch_fp64_and_mixed():
+    p = synth.uneven_walk_se3(batch=6, n_min=16, n_max=60, seed=31)
+    _compare(p, 5, 1e-2, adaptive=True)
+    _compare(p, 5, 1e-2, precision="mixed", refine=1, tol_pose=1e-5, tol_grad=1e-5, adaptive=True)
