@@ -529,8 +529,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
   if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
-  if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver != DNLS_SOLVER_DENSE)
-    return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the dense solver");
+  if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver == DNLS_SOLVER_SCHUR)
+    return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the pose-graph solvers");
   if (op->solver == DNLS_SOLVER_SCHUR) {
     auto* p = new dnls_plan_s();
     p->B = pr->batch;

@@ -73,6 +73,10 @@ struct SpArgs {
   double* g_logw_e;
   double* g_tau;
   double* g_logw_p;
+  double* lam_g;           // adaptive damping: lambda per graph
+  double* pose_bak;        // adaptive damping: theta_t while the trial step is evaluated
+  double* s_t;             // adaptive damping: float64 objective at theta_t per graph
+  int* rej;                // adaptive damping: the graph's trial step was rejected
   int E, K, it, nx, refine;
   double lambda;
 };
@@ -129,6 +133,7 @@ __global__ void k_sp_objective(SpArgs a, int B) {
   for (int k = 0; k < a.nx; ++k) S += a.partial[b * a.nx + k];
   obj[a.it] = S;
   a.lastobj[b] = S;
+  if (a.s_t) a.s_t[b] = S;
   if (!isfinite(S)) {
     a.failed[b] = DNLS_GRAPH_NONFINITE;
     a.status[b] = DNLS_GRAPH_NONFINITE;
@@ -153,11 +158,13 @@ __device__ __forceinline__ void put(const SpArgs& a, const SpDesc& g, int row, i
 
 // Hessian blocks into the tiles (permuted, lower triangle), g into vec[1]
 template <int G, class S>
-__global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, double lambda, int rhs_from_rec) {
+__global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, double lambda, int rhs_from_rec,
+                                                     int lam_per_graph) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
+  if (lam_per_graph) lambda = a.lam_g[b];
   const int u = blockIdx.x * kBT + threadIdx.x;
   if (u < g.npose + g.nod) {
     S h[d * d];
@@ -688,11 +695,12 @@ __global__ void __launch_bounds__(kBT) k_sp_retract(SpArgs a, int xs) {
 // refinement residual b = g64 - (H64 + lambda) x (matrix-free, float64
 // records and J x per cost in ycost), padding zero
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda) {
+__global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda, int lam_per_graph) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
+  if (lam_per_graph) lambda = a.lam_g[b];
   const double* x = slot(a, g, 0);
   const double* rhs = slot(a, g, 1);
   double* res = slot(a, g, 2);
@@ -827,6 +835,74 @@ __global__ void k_sp_reset(int* failed, int* status, int B) {
     failed[b] = 0;
     status[b] = DNLS_GRAPH_OK;
   }
+}
+
+// ---------------------------------------------------------------------------
+// adaptive damping: keep a step iff the float64 objective strictly decreases
+// (lambda / 10), else restore theta_t (lambda x 10), lambda in [1e-7, 1e7]
+// ---------------------------------------------------------------------------
+constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;
+
+__global__ void k_sp_lam_init(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) a.lam_g[b] = a.lambda;
+}
+
+// float64 objective partial sums of the graph's costs at the current poses
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_obj(SpArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  double s = 0.0;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (!a.failed[b] && k < g.nedge + g.nprior) {
+    const int rk = (k < g.nedge) ? g.edge0 + k : a.E + g.prior0 + (k - g.nedge);
+    s = cost_objective<G>(cost_data(a), rk);
+  }
+  s = block_sum_sp(s, red);
+  if (threadIdx.x == 0) a.partial[b * a.nx + blockIdx.x] = s;
+}
+
+// s_t[b] = sum of the partials (thread per graph)
+__global__ void k_sp_obj_store(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || a.failed[b]) return;
+  double S = 0.0;
+  for (int k = 0; k < a.nx; ++k) S += a.partial[b * a.nx + k];
+  a.s_t[b] = S;
+}
+
+__global__ void __launch_bounds__(kBT) k_sp_backup(SpArgs a, int sz) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  for (int u = blockIdx.x * kBT + threadIdx.x; u < g.npose * sz; u += gridDim.x * kBT)
+    a.pose_bak[(size_t)g.pose0 * sz + u] = a.poses[(size_t)g.pose0 * sz + u];
+}
+
+// decision from the trial objective's partials and s_t (thread per graph)
+__global__ void k_sp_decide(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  a.rej[b] = 0;
+  if (a.failed[b]) return;
+  double S = 0.0;
+  for (int k = 0; k < a.nx; ++k) S += a.partial[b * a.nx + k];
+  if (S < a.s_t[b]) {
+    a.lam_g[b] = fmax(a.lam_g[b] / 10.0, kLambdaMin);
+  } else {
+    a.lam_g[b] = fmin(a.lam_g[b] * 10.0, kLambdaMax);
+    a.rej[b] = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBT) k_sp_restore(SpArgs a, int sz) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b] || !a.rej[b]) return;
+  for (int u = blockIdx.x * kBT + threadIdx.x; u < g.npose * sz; u += gridDim.x * kBT)
+    a.poses[(size_t)g.pose0 * sz + u] = a.pose_bak[(size_t)g.pose0 * sz + u];
 }
 
 __global__ void k_sp_failed_from_status(int* failed, const int* status, int B) {
@@ -990,6 +1066,12 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sp_off[5] = off; off += align256((size_t)B * sizeof(int));                     // failed
   p->sp_off[6] = off; off += align256((size_t)B * sizeof(double));                  // last objective
   p->sp_off[7] = off; off += align256((size_t)p->V * d * sizeof(double));           // adjoint
+  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
+    p->sp_off[8] = off; off += align256((size_t)B * sizeof(double));                // lambda per graph
+    p->sp_off[9] = off; off += align256((size_t)p->V * p->sz * sizeof(double));     // pose backup
+    p->sp_off[10] = off; off += align256((size_t)B * sizeof(double));               // s_t
+    p->sp_off[11] = off; off += align256((size_t)B * sizeof(int));                  // rejected
+  }
   p->ws_bytes = off;
   p->bwd_bytes = off;
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -1020,6 +1102,12 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.failed = reinterpret_cast<int*>(w + p->sp_off[5]);
   a.lastobj = reinterpret_cast<double*>(w + p->sp_off[6]);
   a.uout = reinterpret_cast<double*>(w + p->sp_off[7]);
+  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
+    a.lam_g = reinterpret_cast<double*>(w + p->sp_off[8]);
+    a.pose_bak = reinterpret_cast<double*>(w + p->sp_off[9]);
+    a.s_t = reinterpret_cast<double*>(w + p->sp_off[10]);
+    a.rej = reinterpret_cast<int*>(w + p->sp_off[11]);
+  }
   a.factor = static_cast<double*>(factor);
   a.E = p->E;
   a.K = p->opt.iterations;
@@ -1077,26 +1165,37 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   const dim3 g_zero(256, B);
   const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
   const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
+  const bool adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) != 0;
+  const int sz = GroupTraits<G>::sz;
   hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  if (adaptive) hipLaunchKernelGGL(k_sp_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
   for (int it = 0; it <= p->opt.iterations; ++it) {
     const bool final_lin = it == p->opt.iterations;
     const double lam = final_lin ? 0.0 : p->opt.lambda;
+    const int lam_g = (adaptive && !final_lin) ? 1 : 0;
     a.it = it;
     const bool lin32 = mixed && !final_lin;
     const bool lin64 = !mixed || a.refine > 0 || final_lin;
     if (lin32) hipLaunchKernelGGL((k_sp_lin<G, float>), g_cost, dim3(kBT), 0, st, a, a.ws32);
     if (lin64) hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
     hipLaunchKernelGGL(k_sp_objective, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+    if (lam_g && !lin64) {
+      // the decision compares float64 objectives: S at theta_t in float64
+      hipLaunchKernelGGL(k_sp_obj<G>, g_cost, dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_obj_store, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+    }
     hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
     if (lin32) {
       hipLaunchKernelGGL((k_sp_assemble<G, float>), g_blk, dim3(kBT), 0, st, a, (const float*)a.ws32, lam,
-                         a.refine > 0 ? 0 : 1);
+                         a.refine > 0 ? 0 : 1, lam_g);
       if (a.refine > 0) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
     } else {
-      hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, lam, 1);
+      hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, lam, 1,
+                         lam_g);
     }
     sp_factor<G>(p, a, st);
     if (final_lin) break;
+    if (lam_g) hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, a, sz);
     const bool refine = lin32 && a.refine > 0;
     hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 1, 2);
     sp_sweeps(p, a, 0, st);
@@ -1104,10 +1203,15 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     if (refine)
       for (int sw = 0; sw < a.refine; ++sw) {
         hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a);
-        hipLaunchKernelGGL(k_sp_residual<G>, g_pose, dim3(kBT), 0, st, a, lam);
+        hipLaunchKernelGGL(k_sp_residual<G>, g_pose, dim3(kBT), 0, st, a, lam, lam_g);
         sp_sweeps(p, a, 2, st);
         hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a, sw + 1 == a.refine ? 1 : 0);
       }
+    if (lam_g) {
+      hipLaunchKernelGGL(k_sp_obj<G>, g_cost, dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_decide, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+      hipLaunchKernelGGL(k_sp_restore, g_pose, dim3(kBT), 0, st, a, sz);
+    }
   }
   HIP_TRY(hipGetLastError());
   (void)d;

@@ -83,7 +83,7 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, precision=5)[0] == 1
     assert _create(P, p, sparse_solve=4)[0] == 1
     assert _create(P, p, flags=4)[0] == 1
-    assert _create(P, p, flags=2, solver=2)[0] == 2       # adaptive damping: dense solver only
+    assert _create(P, p, flags=2, solver=1)[0] == 2       # adaptive damping: pose-graph solvers only
 
 
 def test_null_arguments():

@@ -303,8 +303,9 @@ def _single_pose_rotation(group, theta0):
             "prior_var": np.array([0], np.int32), "prior_meas": st(P), "prior_logw": np.zeros(1)}
 
 
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
-def test_adaptive_lm_closed_form_single_pose(group):
+def test_adaptive_lm_closed_form_single_pose(group, solver):
     """Adaptive damping from lambda = 1 on a pure-rotation prior error:
     theta_K = theta_0 prod_t lambda_t / (1 + lambda_t), lambda_t = 10^-t.
     K = 3 keeps theta_K (3e-4) far from the rounding floor, where the loss
@@ -313,7 +314,7 @@ def test_adaptive_lm_closed_form_single_pose(group):
     from oracle import lie
     theta0, K = 0.7, 3
     p = _single_pose_rotation(group, theta0)
-    plan, poses, objective, status, dev = gpu_solve(p, K, 1.0, adaptive=True)
+    plan, poses, objective, status, dev = gpu_solve(p, K, 1.0, adaptive=True, solver=solver)
     theta, lam = theta0, 1.0
     for _ in range(K):
         theta *= lam / (1.0 + lam)
@@ -324,10 +325,11 @@ def test_adaptive_lm_closed_form_single_pose(group):
     expect = np.zeros(G.dof)
     expect[-1] = theta
     assert np.abs(err - expect).max() < 1e-12 * theta0
-    _compare(p, K, 1.0, adaptive=True)
+    _compare(p, K, 1.0, adaptive=True, solver=solver)
 
 
-def test_adaptive_lm_rejects_and_recovers():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_adaptive_lm_rejects_and_recovers(solver):
     """SE(2) circle from a poor initial guess: the first two steps are
     rejected; the GPU takes the same decisions as the oracle and matches its
     poses, objectives and implicit gradients."""
@@ -339,10 +341,12 @@ def test_adaptive_lm_rejects_and_recovers():
     xi[:, 2] = torch.as_tensor(rng_.normal(scale=1.6, size=X.shape[0]))
     xi[:, :2] = torch.as_tensor(rng_.normal(scale=1.6, size=(X.shape[0], 2)))
     p["poses_init"] = lie.SE2.to_storage(lie.SE2.retract(X, xi)).numpy()
-    _compare(p, 6, 1e-4, adaptive=True)
+    _compare(p, 6, 1e-4, adaptive=True, solver=solver)
 
 
-def test_adaptive_lm_se3_batch_fp64_and_mixed():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_adaptive_lm_se3_batch_fp64_and_mixed(solver):
     p = synth.uneven_walk_se3(batch=6, n_min=16, n_max=60, seed=31)
-    _compare(p, 5, 1e-2, adaptive=True)
-    _compare(p, 5, 1e-2, precision="mixed", refine=1, tol_pose=1e-5, tol_grad=1e-5, adaptive=True)
+    _compare(p, 5, 1e-2, adaptive=True, solver=solver)
+    _compare(p, 5, 1e-2, precision="mixed", refine=1, tol_pose=1e-5, tol_grad=1e-5, adaptive=True, solver=solver)
+    _compare(p, 5, 1e-2, precision="mixed", refine=0, tol_pose=1e-5, gate_grad=False, adaptive=True, solver=solver)
