@@ -185,9 +185,29 @@ typedef struct {
   double* grad_edge_tau;      /* [E][dof] out or NULL (gradient at tau) */
   double* grad_prior_logw;    /* [P] out or NULL */
   double* grad_obs_w;         /* [O] out or NULL (SCHUR) */
-  double* adjoint;            /* [V][dof] out or NULL: u = H*^-1 v (pose part) */
+  double* adjoint;            /* [V][dof] out or NULL: u = H*^-1 v (pose part);
+                                 left untouched by DNLS_BACKWARD_DLM */
   void* workspace;            /* backward_ws bytes */
+  int32_t mode;               /* dnls_backward_mode (0 = implicit) */
+  double dlm_eps;             /* DNLS_BACKWARD_DLM: epsilon > 0 */
 } dnls_backward_args;
+
+/* dnls_backward_args.mode */
+typedef enum {
+  /* Proposition 1: u = H*^-1 v with the cached factor. */
+  DNLS_BACKWARD_IMPLICIT = 0,
+  /* Direct loss minimisation (Section 4.3, Appendix G), DENSE only: one
+   * Gauss-Newton step from theta_K on S(theta) + ||eps theta - v/2||^2,
+   * (H* + 2 eps^2 I) delta = -g* + eps v, theta_direct = theta_K Exp(delta),
+   * then dL/dphi = (dS/dphi(theta_K) - dS/dphi(theta_direct)) / eps for the
+   * log-weights and the tangent perturbations tau, with S the objective of
+   * Section 2 (costs weighted by exp(2 log w)).  A first-order estimate of
+   * the implicit gradient that approaches it linearly as eps -> 0; eps <= 0
+   * or non-finite is DNLS_ERR_INVALID_ARG, SPARSE and SCHUR are
+   * DNLS_ERR_UNSUPPORTED.  The factor is not read (a new system is
+   * factored); graphs whose status is not OK get zero gradients. */
+  DNLS_BACKWARD_DLM = 1
+} dnls_backward_mode;
 
 /* Validate the structure and build the plan: per-graph offsets, cost
  * incidence lists, the dense / Schur / supernodal block maps (symbolic

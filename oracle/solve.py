@@ -29,6 +29,13 @@ where g = sum_i J_i^T r_i is written as a function of the parameters phi
 (log-weights, measurement tangent perturbations Z <- Z Exp(tau), observation
 weights) and differentiated by torch.autograd.
 
+Direct loss minimisation (Section 4.3, DLM paragraph; Appendix G): with the
+same v, theta_direct minimises S + ||eps theta - v / 2||^2, computed as one
+Gauss-Newton step from theta_K in the tangent space there,
+  (H* + 2 eps^2 I) delta = -g* + eps v,   theta_direct = theta_K (+) delta,
+and dL/dphi ~ (1 / eps) [dS/dphi (theta_K) - dS/dphi (theta_direct)], which
+tends to the implicit gradient above as eps -> 0.
+
 Per-graph status: 0 ok, 1 the factorisation failed (not positive definite),
 2 a non-finite value appeared.  A failed graph keeps its last iterate, repeats
 its last objective value and gets zero gradients.
@@ -406,6 +413,33 @@ def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
     Y = (lin.g * u.reshape(-1)).sum()
     de, dp, dt = torch.autograd.grad(Y, [le, lp, tau])
     return dict(edge_logw=-de, prior_logw=-dp, tau=-dt, u=u)
+
+
+def dlm_grad_graph(g: Graph, res: GraphResult, v_pose, eps: float) -> dict:
+    """Direct-loss-minimisation gradient of a pose graph (see the module
+    docstring): the objective's parameter gradient at theta_K and at
+    theta_direct, differenced and divided by eps."""
+    d = g.G.dof
+    if res.status != OK:
+        return dict(edge_logw=torch.zeros(len(g.ei), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
+                    tau=torch.zeros(len(g.ei), d, dtype=DT))
+    tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
+
+    def dS(X):
+        le = g.logw_e.clone().requires_grad_(True)
+        lp = g.logw_p.clone().requires_grad_(True)
+        tau = tau0.clone().requires_grad_(True)
+        lin = linearize_pose_graph(g, X, tau=tau, logw_e=le, logw_p=lp)
+        return torch.autograd.grad(lin.S, [le, lp, tau])
+
+    lin = res.lin
+    n = lin.H.shape[0]
+    rhs = -lin.g + eps * torch.as_tensor(v_pose, dtype=DT).reshape(-1)
+    delta = torch.linalg.solve(lin.H + 2.0 * eps * eps * torch.eye(n, dtype=DT), rhs)
+    X_direct = g.G.retract(res.X, delta.reshape(-1, d))
+    a, b = dS(res.X), dS(X_direct)
+    return dict(edge_logw=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, tau=(a[2] - b[2]) / eps,
+                delta=delta.reshape(-1, d))
 
 
 def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graphs=None) -> dict:

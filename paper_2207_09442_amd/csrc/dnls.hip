@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -56,7 +57,8 @@ struct DenseArgs {
   float* ws32;       // per-cost records, float32 (mixed)
   double* ycost;     // per-cost J delta (d values)
   double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
-  double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated
+  double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated; DLM: theta_direct
+  double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
   int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
   const double* seed;
   double* g_logw_e;
@@ -445,6 +447,95 @@ __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// backward by direct loss minimisation (Section 4.3, Appendix G): one
+// Gauss-Newton step from theta_K on S + ||eps theta - v / 2||^2,
+//   (H* + 2 eps^2 I) delta = -g* + eps v,  theta_direct = theta_K (+) delta,
+// then dL/dphi = (dS/dphi(theta_K) - dS/dphi(theta_direct)) / eps
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ void param_grads(const DenseArgs& a, const GraphDesc& g, const double* poses, double scale, bool accumulate) {
+  constexpr int d = GroupTraits<G>::d;
+  PoseCostData cd = cost_data(a);
+  cd.poses = poses;
+  for (int k = threadIdx.x; k < g.nedge + g.nprior; k += kNT) {
+    double dl, dt[d];
+    if (k < g.nedge) {
+      const int e = g.edge0 + k;
+      cost_param_grad<G>(cd, e, &dl, dt);
+      if (a.g_logw_e) a.g_logw_e[e] = (accumulate ? a.g_logw_e[e] : 0.0) + scale * dl;
+      if (a.g_tau)
+#pragma unroll
+        for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = (accumulate ? a.g_tau[(size_t)e * d + q] : 0.0) + scale * dt[q];
+    } else {
+      const int pq = g.prior0 + (k - g.nedge);
+      cost_param_grad<G>(cd, a.E + pq, &dl, dt);
+      if (a.g_logw_p) a.g_logw_p[pq] = (accumulate ? a.g_logw_p[pq] : 0.0) + scale * dl;
+    }
+  }
+  __syncthreads();
+}
+
+template <int G>
+__global__ void __launch_bounds__(kNT) k_dense_backward_dlm(DenseArgs a, double eps) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) {
+    for (int k = threadIdx.x; k < g.nedge; k += kNT) {
+      const int e = g.edge0 + k;
+      if (a.g_logw_e) a.g_logw_e[e] = 0.0;
+      if (a.g_tau)
+        for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
+    }
+    for (int k = threadIdx.x; k < g.nprior; k += kNT)
+      if (a.g_logw_p) a.g_logw_p[g.prior0 + k] = 0.0;
+    return;
+  }
+  // dS/dphi at theta_K, scaled by 1 / eps
+  param_grads<G>(a, g, a.poses, 1.0 / eps, false);
+  // H* + 2 eps^2 I and -g* + eps v, factored in the workspace
+  double* H = a.hbuf + g.h_off;
+  double* winv = a.dlm_winv + g.dlm_winv_off;
+  double* vb = dyn;
+  double* vy = dyn + g.npad;
+  linearize_graph<G, double>(a, g, a.ws64, L.red);
+  init_H(g, H);
+  assemble_H<G, double>(a, g, a.ws64, H, 2.0 * eps * eps);
+  double* haug = H + (size_t)g.npad * g.npad;
+  assemble_g<G, double>(a, g, a.ws64, vy, haug);
+  for (int u = threadIdx.x; u < g.n; u += kNT) haug[u] = -haug[u] + eps * a.seed[(size_t)g.pose0 * d + u];
+  __syncthreads();
+  const bool ok = chol_dense(H, H, g.npad, winv, L.dl);
+  if (!ok) {
+    // cannot happen for a positive definite H* (it was factored in the solve)
+    for (int k = threadIdx.x; k < g.nedge + g.nprior; k += kNT) {
+      if (k < g.nedge) {
+        if (a.g_logw_e) a.g_logw_e[g.edge0 + k] = 0.0;
+        if (a.g_tau)
+          for (int q = 0; q < d; ++q) a.g_tau[(size_t)(g.edge0 + k) * d + q] = 0.0;
+      } else if (a.g_logw_p) {
+        a.g_logw_p[g.prior0 + k - g.nedge] = 0.0;
+      }
+    }
+    return;
+  }
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = haug[u];
+  __syncthreads();
+  trsv_upper_t(H, g.npad, winv, vb, L.dl);
+  // theta_direct = theta_K Exp(delta), i.e. retract_minus by -delta
+  double* Xd = a.pose_bak + (size_t)g.pose0 * sz;
+  for (int u = threadIdx.x; u < g.npose * sz; u += kNT) Xd[u] = a.poses[(size_t)g.pose0 * sz + u];
+  for (int u = threadIdx.x; u < g.n; u += kNT) vb[u] = -vb[u];
+  __syncthreads();
+  for (int p = threadIdx.x; p < g.npose; p += kNT) retract_minus<G>(Xd + (size_t)p * sz, vb + p * d);
+  __syncthreads();
+  // minus dS/dphi at theta_direct, scaled by 1 / eps
+  param_grads<G>(a, g, a.pose_bak, -1.0 / eps, true);
+}
+
 // projection operator of Appendix D (one thread per element)
 template <int G>
 __global__ void k_project(long long n, const double* X, const double* Gr, double* out) {
@@ -497,7 +588,13 @@ dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
 }
 
 template <int G>
-dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st) {
+dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st, int mode, double eps) {
+  if (mode == DNLS_BACKWARD_DLM) {
+    const size_t lds2 = 2 * (size_t)p->npad_max * sizeof(double);
+    hipLaunchKernelGGL((k_dense_backward_dlm<G>), dim3(p->B), dim3(kNT), lds2, st, a, eps);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   const size_t lds = (size_t)p->npad_max * sizeof(double);
   hipLaunchKernelGGL((k_dense_backward<G>), dim3(p->B), dim3(kNT), lds, st, a);
   HIP_TRY(hipGetLastError());
@@ -584,7 +681,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   std::vector<int4> od_blk;
   std::vector<int> od_slot;
   p->gd.resize(B);
-  long long fac = 0, hsz = 0;
+  long long fac = 0, hsz = 0, dlmw = 0;
   for (int b = 0; b < B; ++b) {
     GraphDesc& g = p->gd[b];
     g.pose0 = pr->pose_off[b];
@@ -605,6 +702,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     g.fac_off = fac;
     g.h_off = hsz;
     hsz += (long long)(g.npad + 16) * g.npad;
+    g.dlm_winv_off = dlmw;
+    dlmw += (long long)(g.npad / kNB) * kNB * kNB;
     // L (npad x npad) + augmented right-hand-side tile (16 x npad) + panel inverses
     fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
     fac = (fac + 31) / 32 * 32;
@@ -673,9 +772,11 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   p->h_off = ws;
   ws += align256((size_t)hsz * sizeof(double));
   p->bak_off = ws;
-  if (op->flags & DNLS_FLAG_ADAPTIVE_LM) ws += align256((size_t)V * p->sz * sizeof(double));
+  ws += align256((size_t)V * p->sz * sizeof(double));   // adaptive damping backup / DLM theta_direct
+  p->dlmw_off = ws;
+  ws += align256((size_t)dlmw * sizeof(double));        // DLM backward: panel inverses
   p->ws_bytes = ws;
-  p->bwd_bytes = p->h_off;   // the backward does not use the assembled systems
+  p->bwd_bytes = ws;
   p->fac_bytes = (size_t)fac * sizeof(double);
   *out = p;
   return DNLS_OK;
@@ -781,6 +882,7 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
   a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
+  a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
   a.adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) ? 1 : 0;
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
@@ -794,10 +896,16 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
     return fail(DNLS_ERR_INVALID_ARG, "poses, status, factor, seed_pose and workspace are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
+  if (s->mode != DNLS_BACKWARD_IMPLICIT && s->mode != DNLS_BACKWARD_DLM)
+    return fail(DNLS_ERR_INVALID_ARG, "unknown backward mode");
+  if (s->mode == DNLS_BACKWARD_DLM) {
+    if (p->opt.solver != DNLS_SOLVER_DENSE)
+      return fail(DNLS_ERR_UNSUPPORTED, "the DLM backward is implemented for the DENSE solver");
+    if (!(s->dlm_eps > 0.0) || !std::isfinite(s->dlm_eps))
+      return fail(DNLS_ERR_INVALID_ARG, "dlm_eps must be positive and finite");
+  }
   if (p->opt.solver == DNLS_SOLVER_SCHUR) return ba_backward(p, s, static_cast<hipStream_t>(stream));
   if (p->opt.solver == DNLS_SOLVER_SPARSE) return sp_backward(p, s, static_cast<hipStream_t>(stream));
-  if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
-    return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   DenseArgs a = base_args(p);
   a.poses = const_cast<double*>(s->poses);
   a.edge_meas = s->edge_meas;
@@ -811,6 +919,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.ws64 = reinterpret_cast<double*>(ws);
   a.ycost = reinterpret_cast<double*>(ws + p->ycost_off);
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
+  a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
+  a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
   a.seed = s->seed_pose;
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
@@ -818,8 +928,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.adjoint_out = s->adjoint;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the cached factor is float64-assembled in both precisions
-  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st);
-  return launch_backward<2>(p, a, st);
+  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st, s->mode, s->dlm_eps);
+  return launch_backward<2>(p, a, st, s->mode, s->dlm_eps);
 }
 
 dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses, const double* grad, double* out,

@@ -34,6 +34,7 @@ struct GraphDesc {
   int pose0, npose, edge0, nedge, prior0, nprior, n, npad;
   long long fac_off;   // doubles: L ((npad + 16) x npad) then the 64x64 panel inverses
   long long h_off;     // doubles: assembled H ((npad + 16) x npad) in the solve workspace
+  long long dlm_winv_off;   // doubles: panel inverses of the DLM backward system
   int od0, nod;        // off-diagonal Hessian blocks of the graph
 };
 
@@ -70,7 +71,7 @@ struct dnls_plan_s {
   std::vector<dnls::GraphDesc> gd;
   size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
   double flops_alg = 0.0, flops_exec = 0.0;   // one numeric factorisation over the batch
-  size_t ws32_off = 0, ycost_off = 0, h_off = 0, bak_off = 0;   // byte offsets inside the solve workspace
+  size_t ws32_off = 0, ycost_off = 0, h_off = 0, bak_off = 0, dlmw_off = 0;   // byte offsets inside the solve workspace
   // device tables of the dense path
   dnls::GraphDesc* d_gd = nullptr;
   int* d_order = nullptr;

@@ -84,6 +84,66 @@ __device__ __forceinline__ double cost_objective(const PoseCostData& a, int k) {
   return 0.5 * w * w * cc;
 }
 
+// Parameter gradient of the cost's 1/2 w^2 ||c||^2 at the current poses
+// (direct loss minimisation): dS/dl = w^2 ||c||^2 and, for an edge,
+//   dS/dtau = -w^2 Jr(tau0)^T Jl^-1(c)^T c,  Jl^-1(c) = Jr^-1(-c),
+// from dc/dtau = -Jl^-1(c) Jr(tau0) for Z <- Z Exp(tau) at the base tau0.
+template <int G>
+__device__ __forceinline__ void cost_param_grad(const PoseCostData& a, int k, double* dl, double* dtau) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  double c[d], Ci[d * d], Cj[d * d];
+  double w;
+  const bool edge = k < a.E;
+  if (edge) {
+    const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+    double Z[sz];
+    perturbed_meas<G>(a.edge_meas + (size_t)k * sz, a.edge_tau ? a.edge_tau + (size_t)k * d : nullptr, Z);
+    between_cost<G, double>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
+    w = exp(a.edge_logw[k]);
+  } else {
+    const int p = k - a.E;
+    prior_cost<G, double>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Cj);
+    w = exp(a.prior_logw[p]);
+  }
+  double cc = 0.0;
+#pragma unroll
+  for (int q = 0; q < d; ++q) cc += c[q] * c[q];
+  *dl = w * w * cc;
+  if (!edge) return;
+  double mc[d], Jl[d * d], t[d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) mc[q] = -c[q];
+  if constexpr (G == 3) se3_jr_inv(mc, Jl);
+  else se2_jr_inv(mc, Jl);
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) acc += Jl[q * d + m] * c[q];
+    t[m] = acc;
+  }
+  if (a.edge_tau) {
+    double Jr[d * d], t0[d];
+    const double* tau0 = a.edge_tau + (size_t)k * d;
+#pragma unroll
+    for (int q = 0; q < d; ++q) t0[q] = tau0[q];
+    if constexpr (G == 3) se3_jr(t0, Jr);
+    else se2_jr(t0, Jr);
+    double u[d];
+#pragma unroll
+    for (int m = 0; m < d; ++m) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) acc += Jr[q * d + m] * t[q];
+      u[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < d; ++m) t[m] = u[m];
+  }
+#pragma unroll
+  for (int m = 0; m < d; ++m) dtau[m] = -w * w * t[m];
+}
+
 // Per-cost VJP of cost k from its float64 record and the adjoint u of its
 // poses (ui is null for a prior).  Null gradient outputs are skipped.
 template <int G>

@@ -1,0 +1,125 @@
+"""GPU parity of the direct-loss-minimisation backward (Section 4.3,
+Appendix G) through the C ABI against the oracle's dlm_grad_graph.
+
+The backward is a function of theta_K, so the oracle is evaluated at the
+poses the GPU solve returned (its linearisation there, status OK): the test
+checks the backward alone, independently of the forward's precision.
+
+Tolerance: the estimate is a difference of two objective gradients divided by
+eps, so float64 rounding in either gradient is amplified by |dS/dphi| / |dL/dphi|
+~ 1/eps; with the step solved at condition numbers up to ~1e8 the expected
+relative error is below cond(H) eps64 / eps_dlm, held to
+max(1e-9, 10 cond(H) eps64 / eps_dlm).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import solve as S
+
+from gpu_util import gpu_solve, oracle_graphs, rel, t
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(2207)
+
+
+def _problem(group, seed):
+    if group == "SE3":
+        p = synth.uneven_walk_se3(batch=5, n_min=3, n_max=40, seed=seed)
+    else:
+        p = synth.circle_se2(batch=4, n_poses=20, n_loops=8, seed=seed)
+    p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
+    p["prior_logw"] = rng.normal(scale=0.3, size=len(p["prior_logw"]))
+    dof = 6 if group == "SE3" else 3
+    tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), dof))
+    return p, tau
+
+
+def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None):
+    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau)
+    B = len(p["pose_off"]) - 1
+    graphs = list(range(B)) if graphs is None else graphs
+    dof = plan.dof
+    seed = rng.normal(size=(int(p["pose_off"][-1]), dof))
+    out = plan.backward(poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"], dev["prior_logw"],
+                        status, t(seed), edge_tau=dev["edge_tau"], mode="dlm", eps=eps)
+    torch.cuda.synchronize()
+    gr = {k: v.cpu().numpy() for k, v in out.items()}
+    st = status.cpu().numpy()
+    X = poses.cpu()
+    gs = oracle_graphs(p, tau, graphs)
+    worst = 0.0
+    for gi, b in enumerate(graphs):
+        assert st[b] == S.OK
+        g = gs[gi]
+        lo, hi = int(p["pose_off"][b]), int(p["pose_off"][b + 1])
+        Xb = g.G.from_storage(X[lo:hi])
+        res = S.GraphResult(X=Xb, pts=None, objective=[], status=S.OK,
+                            lin=S.linearize_pose_graph(g, Xb, tau=g.tau))
+        ref = S.dlm_grad_graph(g, res, torch.as_tensor(seed[lo:hi]), eps)
+        e0, e1 = int(p["edge_off"][b]), int(p["edge_off"][b + 1])
+        q0, q1 = int(p["prior_off"][b]), int(p["prior_off"][b + 1])
+        mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel(), gr["prior_logw"][q0:q1]])
+        theirs = np.concatenate([ref["edge_logw"].numpy(), ref["tau"].numpy().ravel(), ref["prior_logw"].numpy()])
+        ev = np.linalg.eigvalsh(res.lin.H.numpy())
+        tol = max(1e-9, 10 * (ev[-1] / ev[0]) * np.finfo(np.float64).eps / eps)
+        err = rel(mine, theirs)
+        worst = max(worst, err / tol)
+        assert err < tol, (b, err, tol)
+    print(f"\n[dlm eps={eps} {precision}] worst error / tolerance {worst:.2e}")
+    return plan, poses, status, dev
+
+
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+@pytest.mark.parametrize("eps", [1e-3, 0.3])
+def test_dlm_matches_oracle_ragged_batch(group, eps):
+    """Ragged batches with random log-weights and measurement tangents; eps
+    small (the gradient regime) and large (the 2 eps^2 damping matters)."""
+    p, tau = _problem(group, seed=31)
+    _dlm_parity(p, tau, 8, 1e-3, eps)
+
+
+def test_dlm_after_mixed_precision_solve():
+    """The backward linearises in float64 whatever the plan's precision."""
+    p, tau = _problem("SE3", seed=32)
+    _dlm_parity(p, tau, 8, 1e-3, 1e-3, precision="mixed", refine=1)
+
+
+def test_dlm_walk64_b128_sampled_graphs():
+    """The 128 x 64-pose LM workload at full size; four sampled graphs."""
+    p = synth.walk_se3(batch=128)
+    _dlm_parity(p, None, 10, 1e-3, 1e-3, graphs=[0, 37, 81, 127])
+
+
+def test_dlm_failed_graphs_and_argument_checks():
+    """A graph whose solve failed (isolated pose, NOT_PD) gets zero
+    gradients; eps <= 0 or non-finite and the DLM mode on the sparse solver
+    are rejected before any launch."""
+    from paper_2207_09442_amd import DnlsError, Plan
+    p = synth.walk_se3(batch=2, n_poses=8, n_loops=4, seed=17)
+    last = int(p["pose_off"][1]) + 7
+    keep = ~((p["edge_ij"][:, 0] == last) | (p["edge_ij"][:, 1] == last))
+    counts = [int(keep[p["edge_off"][b]:p["edge_off"][b + 1]].sum()) for b in range(2)]
+    p["edge_ij"], p["edge_meas"], p["edge_logw"] = p["edge_ij"][keep], p["edge_meas"][keep], p["edge_logw"][keep]
+    p["edge_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    plan, poses, objective, status, dev = gpu_solve(p, 4, 0.0)
+    assert status.cpu().tolist() == [S.OK, S.NOT_PD]
+    seed = t(rng.normal(size=(int(p["pose_off"][-1]), 6)))
+    args = (poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"], dev["prior_logw"], status, seed)
+    out = plan.backward(*args, mode="dlm", eps=1e-3)
+    torch.cuda.synchronize()
+    e0 = int(p["edge_off"][1])
+    assert torch.all(out["edge_logw"][e0:] == 0) and torch.all(out["edge_tau"][e0:] == 0)
+    assert torch.all(out["prior_logw"][int(p["prior_off"][1]):] == 0)
+    assert torch.isfinite(out["edge_logw"][:e0]).all() and out["edge_logw"][:e0].abs().max() > 0
+    for eps in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(DnlsError):
+            plan.backward(*args, mode="dlm", eps=eps)
+    sp = Plan(p, 4, lam=0.0, solver="sparse", device="cuda")
+    with pytest.raises(DnlsError):
+        sp.backward(*args, mode="dlm", eps=1e-3)

@@ -340,3 +340,76 @@ def test_adaptive_lm_rejects_and_recovers():
     assert rejected[:2] == [True, True] and not any(rejected[2:5])
     for t in range(K - 1):
         assert lams[t + 1] == (min(lams[t] * 10.0, 1e7) if rejected[t] else max(lams[t] / 10.0, 1e-7))
+
+
+# ---------------------------------------------------------------------------
+# Direct loss minimisation (Section 4.3, Appendix G)
+# ---------------------------------------------------------------------------
+def _converged_walk(seed=5):
+    p = synth.walk_se3(batch=1, n_poses=10, n_loops=5, seed=seed)
+    g = S.graphs_of(p)[0]
+    tau0 = torch.as_tensor(rng.normal(scale=0.01, size=(len(g.ei), 6)), dtype=DT)
+    import dataclasses
+    g = dataclasses.replace(g, tau=tau0)
+    res = S.solve_graph(g, 12, 0.0)
+    assert res.status == S.OK and float(res.lin.g.abs().max()) < 1e-12
+    return g, res
+
+
+def test_dlm_gradient_tends_linearly_to_implicit():
+    """The DLM estimate differs from the implicit gradient (pinned above by
+    finite differences of the stopped Newton step) by a term linear in eps:
+    the relative gap must fall tenfold per decade of eps."""
+    g, res = _converged_walk()
+    v = torch.as_tensor(rng.normal(size=(g.n_pose, 6)), dtype=DT)
+    gi = S.implicit_grad_graph(g, res, v)
+    ref = torch.cat([gi["edge_logw"], gi["prior_logw"], gi["tau"].reshape(-1)])
+
+    def gap(eps):
+        gd = S.dlm_grad_graph(g, res, v, eps)
+        ours = torch.cat([gd["edge_logw"], gd["prior_logw"], gd["tau"].reshape(-1)])
+        return float((ours - ref).norm() / ref.norm())
+
+    g3, g4, g5 = gap(1e-3), gap(1e-4), gap(1e-5)
+    assert g3 < 0.5
+    assert 0.07 < g4 / g3 < 0.13 and 0.07 < g5 / g4 < 0.13
+
+
+def test_dlm_step_minimises_regularised_gauss_newton_model():
+    """theta_direct = theta_K Exp(delta) with delta the minimiser of
+    1/2 ||r + J delta||^2 + ||eps delta - v/2||^2, J the Jacobian of the
+    weighted residual vector r under right perturbations; J is taken here by
+    central differences of the costs, independently of the oracle's
+    analytic Jacobians, and eps is large so that the 2 eps^2 damping
+    matters."""
+    g, res = _converged_walk(seed=6)
+    d, N = 6, g.n_pose
+    v = torch.as_tensor(rng.normal(size=(N, d)), dtype=DT)
+    eps = 0.7
+
+    def rvec(X):
+        k = S.pose_costs(g, X, g.tau)
+        return torch.cat([(k["w_e"][:, None] * k["c_e"]).reshape(-1), (k["w_p"][:, None] * k["c_p"]).reshape(-1)])
+
+    r0 = rvec(res.X)
+    h = 1e-6
+    cols = []
+    for q in range(N * d):
+        e = torch.zeros(N * d, dtype=DT)
+        e[q] = h
+        cols.append((rvec(g.G.retract(res.X, e.reshape(N, d))) - rvec(g.G.retract(res.X, -e.reshape(N, d)))) / (2 * h))
+    J = torch.stack(cols, 1).numpy()
+    A = np.vstack([J, np.sqrt(2.0) * eps * np.eye(N * d)])
+    rhs = np.concatenate([-r0.numpy(), v.reshape(-1).numpy() / np.sqrt(2.0)])
+    want = np.linalg.lstsq(A, rhs, rcond=None)[0]
+    got = S.dlm_grad_graph(g, res, v, eps)["delta"].reshape(-1).numpy()
+    assert np.abs(got - want).max() < 1e-6 * np.abs(want).max()
+
+
+def test_dlm_failed_graph_gets_zero_gradient():
+    p = synth.walk_se3(batch=1, n_poses=6, n_loops=2, seed=7)
+    g = S.graphs_of(p)[0]
+    res = S.solve_graph(g, 3, 0.0)
+    res.status = S.NOT_PD
+    gd = S.dlm_grad_graph(g, res, torch.ones(g.n_pose, 6, dtype=DT), 1e-3)
+    assert all(float(t.abs().max()) == 0.0 for t in (gd["edge_logw"], gd["prior_logw"], gd["tau"]))
