@@ -175,6 +175,9 @@ def main():
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
                     help="Levenberg-Marquardt with adaptive damping from the workload's lambda (dense solver)")
+    ap.add_argument("--backward", choices=["implicit", "dlm"], default="implicit",
+                    help="backward mode: implicit (Proposition 1) or direct loss minimisation (dense solver)")
+    ap.add_argument("--dlm-eps", type=float, default=1e-3)
     ap.add_argument("--autotune", action="store_true",
                     help="pick solver, sparse solve schedule and graph capture with the autotuner "
                          "(pose graphs only; timed before the benchmark, cached)")
@@ -243,7 +246,7 @@ def main():
         def backward(st):
             if ba:
                 return plan.backward_ba(poses, pts, status=st, seed_cam=seed, **aux)
-            return plan.backward(poses, *aux, st, seed)
+            return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps)
 
         stream = torch.cuda.current_stream()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -307,7 +310,8 @@ def main():
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
            "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,
-           "schedule": dict(schedule, autotuned=bool(args.autotune and not ba))}
+           "schedule": dict(schedule, autotuned=bool(args.autotune and not ba)),
+           "backward": "implicit" if args.backward == "implicit" else f"dlm (eps={args.dlm_eps:g})"}
     if args.workload == "se3_walk64_b128":
         cfg.update(poses=64, loop_closures=64)
     line = {
@@ -342,7 +346,8 @@ def main():
     default_cpu = {"se3_walk64_b128": 128, "se2_circle_b1": 1, "se3_uneven_b256": 32,
                    "ba_ring64_b4": 4, "se3_lattice16_b8": 0}[args.workload]
     ng = min(B, default_cpu if args.cpu_graphs is None else args.cpu_graphs)
-    if not args.no_cpu and ng > 0:
+    # the CPU sample and the error check are of the implicit backward
+    if not args.no_cpu and ng > 0 and args.backward == "implicit":
         progress(f"CPU oracle on {ng} graph(s)")
         import torch as _t
         npass = max(1, args.cpu_passes)

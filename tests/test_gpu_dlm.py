@@ -6,10 +6,12 @@ poses the GPU solve returned (its linearisation there, status OK): the test
 checks the backward alone, independently of the forward's precision.
 
 Tolerance: the estimate is a difference of two objective gradients divided by
-eps, so float64 rounding in either gradient is amplified by |dS/dphi| / |dL/dphi|
-~ 1/eps; with the step solved at condition numbers up to ~1e8 the expected
-relative error is below cond(H) eps64 / eps_dlm, held to
-max(1e-9, 10 cond(H) eps64 / eps_dlm).
+eps, so float64 rounding in either gradient is amplified by about
+|dS/dphi| / |dL/dphi| ~ 1/eps, while the step delta (proportional to eps,
+then divided by it) carries the forward error of the damped solve, about
+cond(H) eps64.  Each graph is held to
+1e-9 + 100 eps64 / eps_dlm + 0.5 cond(H) eps64 (the constant of the
+implicit-gradient tests for the solve term).
 """
 from __future__ import annotations
 
@@ -67,9 +69,11 @@ def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None):
         mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel(), gr["prior_logw"][q0:q1]])
         theirs = np.concatenate([ref["edge_logw"].numpy(), ref["tau"].numpy().ravel(), ref["prior_logw"].numpy()])
         ev = np.linalg.eigvalsh(res.lin.H.numpy())
-        tol = max(1e-9, 10 * (ev[-1] / ev[0]) * np.finfo(np.float64).eps / eps)
+        e64 = np.finfo(np.float64).eps
+        tol = 1e-9 + 100 * e64 / eps + 0.5 * (ev[-1] / ev[0]) * e64
         err = rel(mine, theirs)
         worst = max(worst, err / tol)
+        print(f"  graph {b}: error {err:.2e} tolerance {tol:.2e}")
         assert err < tol, (b, err, tol)
     print(f"\n[dlm eps={eps} {precision}] worst error / tolerance {worst:.2e}")
     return plan, poses, status, dev
