@@ -175,9 +175,11 @@ def main():
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
                     help="Levenberg-Marquardt with adaptive damping from the workload's lambda (dense solver)")
-    ap.add_argument("--backward", choices=["implicit", "dlm"], default="implicit",
-                    help="backward mode: implicit (Proposition 1) or direct loss minimisation (dense solver)")
+    ap.add_argument("--backward", choices=["implicit", "dlm", "exact"], default="implicit",
+                    help="backward mode: implicit (Proposition 1), direct loss minimisation, or implicit with "
+                         "the exact Hessian (the last two on the dense solver)")
     ap.add_argument("--dlm-eps", type=float, default=1e-3)
+    ap.add_argument("--sweeps", type=int, default=8, help="refinement sweeps of the exact-Hessian backward")
     ap.add_argument("--autotune", action="store_true",
                     help="pick solver, sparse solve schedule and graph capture with the autotuner "
                          "(pose graphs only; timed before the benchmark, cached)")
@@ -246,7 +248,7 @@ def main():
         def backward(st):
             if ba:
                 return plan.backward_ba(poses, pts, status=st, seed_cam=seed, **aux)
-            return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps)
+            return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps, sweeps=args.sweeps)
 
         stream = torch.cuda.current_stream()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -311,7 +313,8 @@ def main():
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
            "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,
            "schedule": dict(schedule, autotuned=bool(args.autotune and not ba)),
-           "backward": "implicit" if args.backward == "implicit" else f"dlm (eps={args.dlm_eps:g})"}
+           "backward": {"implicit": "implicit", "dlm": f"dlm (eps={args.dlm_eps:g})",
+                        "exact": f"exact Hessian ({args.sweeps} sweeps)"}[args.backward]}
     if args.workload == "se3_walk64_b128":
         cfg.update(poses=64, loop_closures=64)
     line = {

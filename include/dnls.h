@@ -190,6 +190,7 @@ typedef struct {
   void* workspace;            /* backward_ws bytes */
   int32_t mode;               /* dnls_backward_mode (0 = implicit) */
   double dlm_eps;             /* DNLS_BACKWARD_DLM: epsilon > 0 */
+  int32_t sweeps;             /* DNLS_BACKWARD_EXACT: refinement sweeps in [0, 64] */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */
@@ -206,7 +207,18 @@ typedef enum {
    * or non-finite is DNLS_ERR_INVALID_ARG, SPARSE and SCHUR are
    * DNLS_ERR_UNSUPPORTED.  The factor is not read (a new system is
    * factored); graphs whose status is not OK get zero gradients. */
-  DNLS_BACKWARD_DLM = 1
+  DNLS_BACKWARD_DLM = 1,
+  /* Proposition 1 with the exact Hessian of S in place of the Gauss-Newton
+   * one (DENSE only): Hx = the Hessian of S(theta_K Exp(delta)) at
+   * delta = 0, i.e. J^T J plus the second-order terms of the costs
+   * (differentiated by dual numbers) and of the retraction.  u = Hx^-1 v is
+   * reached by `sweeps` steps of iterative refinement preconditioned by the
+   * cached factor, u <- u + H*^-1 (v - Hx u) from u = H*^-1 v (sweeps = 0
+   * is the Gauss-Newton result); it converges when the spectral radius of
+   * I - H*^-1 Hx is below 1, i.e. for residuals small against the
+   * curvature, and each sweep multiplies the error by about that radius.
+   * Then the same per-cost VJP.  The adjoint output receives u. */
+  DNLS_BACKWARD_EXACT = 2
 } dnls_backward_mode;
 
 /* Validate the structure and build the plan: per-graph offsets, cost

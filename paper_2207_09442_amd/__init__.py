@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
-BACKWARD_MODES = {"implicit": 0, "dlm": 1}
+BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2}
 FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2
 GROUPS = {"SE2": 2, "SE3": 3}
@@ -65,7 +65,8 @@ class _BackwardArgs(ctypes.Structure):
                                    "prior_meas", "prior_logw", "obs_uv", "obs_w", "status",
                                    "factor", "seed_pose", "seed_point", "grad_edge_logw",
                                    "grad_edge_tau", "grad_prior_logw", "grad_obs_w", "adjoint",
-                                   "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double)]
+                                   "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
+                                                  ("sweeps", ctypes.c_int32)]
 
 
 _LIB = None
@@ -211,11 +212,13 @@ class Plan:
         return objective, status
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
-                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3):
+                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8):
         """Backward for `seed` = dL/dtheta_K in tangent coordinates [V, dof]:
-        mode "implicit" (Proposition 1, with the cached factor) or "dlm"
-        (direct loss minimisation with perturbation `eps`, dense solver only;
-        no adjoint)."""
+        mode "implicit" (Proposition 1, with the cached factor), "dlm"
+        (direct loss minimisation with perturbation `eps`; no adjoint) or
+        "exact" (Proposition 1 with the exact Hessian, `sweeps` refinement
+        sweeps preconditioned by the cached factor); the last two on the
+        dense solver only."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {
@@ -238,6 +241,7 @@ class Plan:
         a.workspace = self._aligned(self.workspace)
         a.mode = BACKWARD_MODES[mode]
         a.dlm_eps = float(eps)
+        a.sweeps = int(sweeps)
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
         return out
 

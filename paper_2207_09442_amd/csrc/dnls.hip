@@ -59,6 +59,7 @@ struct DenseArgs {
   double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
   double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated; DLM: theta_direct
   double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
+  double* hvp;       // exact backward: [cost][2][d] second-order Hessian terms
   int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
   const double* seed;
   double* g_logw_e;
@@ -281,6 +282,7 @@ __device__ void matvec_H(const DenseArgs& a, const GraphDesc& g, const double* r
 }
 
 constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;   // adaptive damping range
+constexpr int kMaxExactSweeps = 64;                        // exact-Hessian backward: refinement sweeps
 
 struct KernelLds {
   DenseLds dl;
@@ -396,39 +398,11 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
 // ---------------------------------------------------------------------------
 // backward: adjoint solve with the cached factor, then per-cost VJP
 // ---------------------------------------------------------------------------
+
+// per-cost VJP of the implicit backward for the adjoint vu (LDS) of graph g
 template <int G>
-__global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
+__device__ void vjp_graph(const DenseArgs& a, const GraphDesc& g, const double* vu) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
-  extern __shared__ double dyn[];
-  __shared__ KernelLds L;
-  const int b = a.order[blockIdx.x];
-  const GraphDesc g = a.gd[b];
-  const bool ok = a.status[b] == DNLS_GRAPH_OK;
-  if (!ok) {
-    for (int k = threadIdx.x; k < g.nedge; k += kNT) {
-      const int e = g.edge0 + k;
-      if (a.g_logw_e) a.g_logw_e[e] = 0.0;
-      if (a.g_tau)
-        for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
-    }
-    for (int k = threadIdx.x; k < g.nprior; k += kNT)
-      if (a.g_logw_p) a.g_logw_p[g.prior0 + k] = 0.0;
-    if (a.adjoint_out)
-      for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = 0.0;
-    return;
-  }
-  const double* A = a.factor + g.fac_off;
-  const double* winv = A + (size_t)(g.npad + 16) * g.npad;
-  double* vu = dyn;
-  for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
-  __syncthreads();
-  // float64 linearisation at theta_K: residuals and Jacobians for the VJP
-  linearize_graph<G, double>(a, g, a.ws64, L.red);
-  trsv_lower(A, g.npad, winv, vu, L.dl);
-  trsv_upper_t(A, g.npad, winv, vu, L.dl);
-  if (a.adjoint_out)
-    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
-  // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
   const PoseCostData cd = cost_data(a);
   const int ncost = g.nedge + g.nprior;
   for (int k = threadIdx.x; k < ncost; k += kNT) {
@@ -445,6 +419,146 @@ __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
     }
     cost_vjp<G>(cd, rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p);
   }
+}
+
+template <int G>
+__device__ void zero_grads(const DenseArgs& a, const GraphDesc& g, bool adjoint) {
+  constexpr int d = GroupTraits<G>::d;
+  for (int k = threadIdx.x; k < g.nedge; k += kNT) {
+    const int e = g.edge0 + k;
+    if (a.g_logw_e) a.g_logw_e[e] = 0.0;
+    if (a.g_tau)
+      for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
+  }
+  for (int k = threadIdx.x; k < g.nprior; k += kNT)
+    if (a.g_logw_p) a.g_logw_p[g.prior0 + k] = 0.0;
+  if (adjoint && a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = 0.0;
+}
+
+// y = Hx x with Hx the exact Hessian of S(theta_K Exp(delta)) at delta = 0:
+//   Hx x = sum J^T J x + sum w^2 (dC/ds)^T c - 1/2 [ad(x_p)^T g_p]_p
+// (Gauss-Newton part from the float64 records, second-order cost terms by
+// one dual-number pass per cost, and the term of the retraction's right
+// Jacobian Jr(delta) = I - ad(delta)/2 + ...); gvec is the gradient at theta_K.
+template <int G>
+__device__ void hvp_exact(const DenseArgs& a, const GraphDesc& g, const double* rec, const double* x,
+                          double* y, const double* gvec) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const PoseCostData cd = cost_data(a);
+  const int ncost = g.nedge + g.nprior;
+  for (int k = threadIdx.x; k < ncost; k += kNT) {
+    int cost, pi, pj;
+    if (k < g.nedge) {
+      cost = g.edge0 + k;
+      pi = a.edge_ij[2 * cost] - g.pose0;
+      pj = a.edge_ij[2 * cost + 1] - g.pose0;
+    } else {
+      const int p = g.prior0 + (k - g.nedge);
+      cost = a.E + p;
+      pi = -1;
+      pj = a.prior_var[p] - g.pose0;
+    }
+    const double* J = rec + (size_t)cost * RN;
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        if (pi >= 0) acc += J[r * d + q] * x[pi * d + q];
+        acc += J[d * d + r * d + q] * x[pj * d + q];
+      }
+      a.ycost[(size_t)cost * d + r] = acc;
+    }
+    double* o = a.hvp + (size_t)cost * 2 * d;
+    cost_hvp_residual<G>(cd, cost, J, pi >= 0 ? x + pi * d : nullptr, x + pj * d, o, o + d);
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < g.npad; u += kNT) {
+    double v = 0.0;
+    if (u < g.n) {
+      const int p = u / d, r = u % d, gp = g.pose0 + p;
+      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+        const int slot = a.inc_slot[s];
+        const double* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+        const double* yc = a.ycost + (size_t)(slot >> 1) * d;
+#pragma unroll
+        for (int k = 0; k < d; ++k) v += J[k * d + r] * yc[k];
+        v += a.hvp[(size_t)(slot >> 1) * 2 * d + (slot & 1) * d + r];
+      }
+      double c[d];
+      ad_transpose_mul<G>(x + p * d, gvec + p * d, c);
+      v -= 0.5 * c[r];
+    }
+    y[u] = v;
+  }
+  __syncthreads();
+}
+
+template <int G>
+__global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
+  constexpr int d = GroupTraits<G>::d;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) {
+    zero_grads<G>(a, g, true);
+    return;
+  }
+  const double* A = a.factor + g.fac_off;
+  const double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  double* vu = dyn;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
+  __syncthreads();
+  // float64 linearisation at theta_K: residuals and Jacobians for the VJP
+  linearize_graph<G, double>(a, g, a.ws64, L.red);
+  trsv_lower(A, g.npad, winv, vu, L.dl);
+  trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  if (a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
+  // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
+  vjp_graph<G>(a, g, vu);
+}
+
+// Implicit backward with the exact Hessian: u = Hx^-1 v by iterative
+// refinement preconditioned by the cached Gauss-Newton factor,
+// u <- u + H*^-1 (v - Hx u) from u = H*^-1 v, then the per-cost VJP.
+template <int G>
+__global__ void __launch_bounds__(kNT) k_dense_backward_exact(DenseArgs a, int sweeps) {
+  constexpr int d = GroupTraits<G>::d;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  if (a.status[b] != DNLS_GRAPH_OK) {
+    zero_grads<G>(a, g, true);
+    return;
+  }
+  const double* A = a.factor + g.fac_off;
+  const double* winv = A + (size_t)(g.npad + 16) * g.npad;
+  double* vu = dyn;
+  double* vx = dyn + g.npad;
+  double* vg = dyn + 2 * g.npad;
+  const double* seed = a.seed + (size_t)g.pose0 * d;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? seed[u] : 0.0;
+  __syncthreads();
+  linearize_graph<G, double>(a, g, a.ws64, L.red);
+  assemble_g<G, double>(a, g, a.ws64, vg, nullptr);
+  trsv_lower(A, g.npad, winv, vu, L.dl);
+  trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  for (int it = 0; it < sweeps; ++it) {
+    hvp_exact<G>(a, g, a.ws64, vu, vx, vg);
+    for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = ((u < g.n) ? seed[u] : 0.0) - vx[u];
+    __syncthreads();
+    trsv_lower(A, g.npad, winv, vx, L.dl);
+    trsv_upper_t(A, g.npad, winv, vx, L.dl);
+    for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] += vx[u];
+    __syncthreads();
+  }
+  if (a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
+  vjp_graph<G>(a, g, vu);
 }
 
 // ---------------------------------------------------------------------------
@@ -484,14 +598,7 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_dlm(DenseArgs a, double 
   const int b = a.order[blockIdx.x];
   const GraphDesc g = a.gd[b];
   if (a.status[b] != DNLS_GRAPH_OK) {
-    for (int k = threadIdx.x; k < g.nedge; k += kNT) {
-      const int e = g.edge0 + k;
-      if (a.g_logw_e) a.g_logw_e[e] = 0.0;
-      if (a.g_tau)
-        for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
-    }
-    for (int k = threadIdx.x; k < g.nprior; k += kNT)
-      if (a.g_logw_p) a.g_logw_p[g.prior0 + k] = 0.0;
+    zero_grads<G>(a, g, false);
     return;
   }
   // dS/dphi at theta_K, scaled by 1 / eps
@@ -511,15 +618,7 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_dlm(DenseArgs a, double 
   const bool ok = chol_dense(H, H, g.npad, winv, L.dl);
   if (!ok) {
     // cannot happen for a positive definite H* (it was factored in the solve)
-    for (int k = threadIdx.x; k < g.nedge + g.nprior; k += kNT) {
-      if (k < g.nedge) {
-        if (a.g_logw_e) a.g_logw_e[g.edge0 + k] = 0.0;
-        if (a.g_tau)
-          for (int q = 0; q < d; ++q) a.g_tau[(size_t)(g.edge0 + k) * d + q] = 0.0;
-      } else if (a.g_logw_p) {
-        a.g_logw_p[g.prior0 + k - g.nedge] = 0.0;
-      }
-    }
+    zero_grads<G>(a, g, false);
     return;
   }
   for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = haug[u];
@@ -588,7 +687,13 @@ dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
 }
 
 template <int G>
-dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st, int mode, double eps) {
+dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st, int mode, double eps, int sweeps) {
+  if (mode == DNLS_BACKWARD_EXACT) {
+    const size_t lds3 = 3 * (size_t)p->npad_max * sizeof(double);
+    hipLaunchKernelGGL((k_dense_backward_exact<G>), dim3(p->B), dim3(kNT), lds3, st, a, sweeps);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   if (mode == DNLS_BACKWARD_DLM) {
     const size_t lds2 = 2 * (size_t)p->npad_max * sizeof(double);
     hipLaunchKernelGGL((k_dense_backward_dlm<G>), dim3(p->B), dim3(kNT), lds2, st, a, eps);
@@ -775,6 +880,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   ws += align256((size_t)V * p->sz * sizeof(double));   // adaptive damping backup / DLM theta_direct
   p->dlmw_off = ws;
   ws += align256((size_t)dlmw * sizeof(double));        // DLM backward: panel inverses
+  p->hvp_off = ws;
+  ws += align256(ncost * 2 * d * sizeof(double));       // exact backward: residual terms per cost side
   p->ws_bytes = ws;
   p->bwd_bytes = ws;
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -896,8 +1003,14 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
     return fail(DNLS_ERR_INVALID_ARG, "poses, status, factor, seed_pose and workspace are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
-  if (s->mode != DNLS_BACKWARD_IMPLICIT && s->mode != DNLS_BACKWARD_DLM)
+  if (s->mode != DNLS_BACKWARD_IMPLICIT && s->mode != DNLS_BACKWARD_DLM && s->mode != DNLS_BACKWARD_EXACT)
     return fail(DNLS_ERR_INVALID_ARG, "unknown backward mode");
+  if (s->mode == DNLS_BACKWARD_EXACT) {
+    if (p->opt.solver != DNLS_SOLVER_DENSE)
+      return fail(DNLS_ERR_UNSUPPORTED, "the exact-Hessian backward is implemented for the DENSE solver");
+    if (s->sweeps < 0 || s->sweeps > kMaxExactSweeps)
+      return fail(DNLS_ERR_INVALID_ARG, "sweeps must be in [0, 64]");
+  }
   if (s->mode == DNLS_BACKWARD_DLM) {
     if (p->opt.solver != DNLS_SOLVER_DENSE)
       return fail(DNLS_ERR_UNSUPPORTED, "the DLM backward is implemented for the DENSE solver");
@@ -921,6 +1034,7 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
   a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
   a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
+  a.hvp = reinterpret_cast<double*>(ws + p->hvp_off);
   a.seed = s->seed_pose;
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
@@ -928,8 +1042,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.adjoint_out = s->adjoint;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the cached factor is float64-assembled in both precisions
-  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st, s->mode, s->dlm_eps);
-  return launch_backward<2>(p, a, st, s->mode, s->dlm_eps);
+  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st, s->mode, s->dlm_eps, s->sweeps);
+  return launch_backward<2>(p, a, st, s->mode, s->dlm_eps, s->sweeps);
 }
 
 dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses, const double* grad, double* out,

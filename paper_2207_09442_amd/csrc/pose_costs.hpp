@@ -144,6 +144,114 @@ __device__ __forceinline__ void cost_param_grad(const PoseCostData& a, int k, do
   for (int m = 0; m < d; ++m) dtau[m] = -w * w * t[m];
 }
 
+// out = ad(x)^T v, with ad(x) the linearisation of Ad(Exp(s x)) = I + s ad(x):
+// SE(3), x = (rho, phi): ad = [[phi^, rho^], [0, phi^]], so
+//   ad^T v = (-phi x v_rho, -rho x v_rho - phi x v_phi);
+// SE(2), x = (x, y, th): ad = [[0, -th, y], [th, 0, -x], [0, 0, 0]].
+template <int G>
+DNLS_HD void ad_transpose_mul(const double* x, const double* v, double* out) {
+  if constexpr (G == 3) {
+    double a[3], b[3];
+    cross3(x + 3, v, a);
+    cross3(x, v, b);
+    out[0] = -a[0];
+    out[1] = -a[1];
+    out[2] = -a[2];
+    cross3(x + 3, v + 3, a);
+    out[3] = -b[0] - a[0];
+    out[4] = -b[1] - a[1];
+    out[5] = -b[2] - a[2];
+  } else {
+    out[0] = x[2] * v[1];
+    out[1] = -x[2] * v[0];
+    out[2] = x[1] * v[0] - x[0] * v[1];
+  }
+}
+
+// Second-order (residual) part of the exact Hessian-vector product for cost
+// k along the pose directions xi, xj (xi null for a prior): with
+// c(s) = c at X_i Exp(s xi), X_j Exp(s xj), this is w^2 (dC/ds)^T c for each
+// side, the term that the Gauss-Newton product w^2 C^T C x leaves out.
+//   dC_j/ds = D Jr^-1(c)[c'],  c' = C_i xi + C_j xj   (one dual-number pass)
+//   dC_i/ds = -D Jr^-1(c)[c'] Ad(T) - Jr^-1(c) (Ad(T) ad(xi) - ad(xj) Ad(T)),
+//   T = X_j^-1 X_i, from Ad(Exp(-s xj) T Exp(s xi)).
+// rec is the cost's float64 record (w C_i, w C_j, w c).
+template <int G>
+DNLS_HD void cost_hvp_residual(const PoseCostData& a, int k, const double* rec, const double* xi,
+                               const double* xj, double* oi, double* oj) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  const bool edge = k < a.E;
+  const double w = exp(edge ? a.edge_logw[k] : a.prior_logw[k - a.E]);
+  const double* r = rec + 2 * d * d;
+  Dual<double> cd[d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < d; ++m) {
+      if (edge) acc += rec[q * d + m] * xi[m];
+      acc += rec[d * d + q * d + m] * xj[m];
+    }
+    cd[q] = Dual<double>(r[q] / w, acc / w);
+  }
+  Dual<double> J[d * d];
+  if constexpr (G == 3) se3_jr_inv(cd, J);
+  else se2_jr_inv(cd, J);
+  // av = Jr^-T c, bv = (D Jr^-1)^T c, scaled by w^2 through r = w c
+  double av[d], bv[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      sa += J[q * d + m].v * r[q];
+      sb += J[q * d + m].d * r[q];
+    }
+    av[m] = w * sa;
+    bv[m] = w * sb;
+  }
+#pragma unroll
+  for (int m = 0; m < d; ++m) oj[m] = bv[m];
+  if (!edge) return;
+  const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+  double Ad[d * d];
+  if constexpr (G == 3) {
+    double Xji[12], M[12];
+    se3_inv(a.poses + (size_t)j * sz, Xji);
+    se3_mul(Xji, a.poses + (size_t)i * sz, M);
+    double RM[9], tM[3];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) RM[rr * 3 + q] = M[rr * 4 + q];
+      tM[rr] = M[rr * 4 + 3];
+    }
+    se3_adjoint(RM, tM, Ad);
+  } else {
+    double Xji[4], M[4];
+    se2_inv(a.poses + (size_t)j * sz, Xji);
+    se2_mul(Xji, a.poses + (size_t)i * sz, M);
+    se2_adjoint(M[0], M[1], M[2], M[3], Ad);
+  }
+  // oi = Ad^T (ad(xj)^T av - bv) - ad(xi)^T Ad^T av
+  double ta[d], tj[d], ti[d];
+  ad_transpose_mul<G>(xj, av, tj);
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      s1 += Ad[q * d + m] * av[q];
+      s2 += Ad[q * d + m] * (tj[q] - bv[q]);
+    }
+    ta[m] = s1;
+    oi[m] = s2;
+  }
+  ad_transpose_mul<G>(xi, ta, ti);
+#pragma unroll
+  for (int m = 0; m < d; ++m) oi[m] -= ti[m];
+}
+
 // Per-cost VJP of cost k from its float64 record and the adjoint u of its
 // poses (ui is null for a prior).  Null gradient outputs are skipped.
 template <int G>
