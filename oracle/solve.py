@@ -299,18 +299,59 @@ class GraphResult:
     lin: Lin | None = None        # final linearisation at theta_K
     factor: tuple | None = None   # cached factor of H* (or of the Schur complement)
     lambdas: list | None = None   # adaptive damping: lambda used at each step
+    radii: list | None = None     # dogleg: trust radius used at each step
 
 
 LAMBDA_MIN, LAMBDA_MAX = 1e-7, 1e7
 
 
-def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool = False) -> GraphResult:
+RADIUS_MAX = 1e4
+
+
+def dogleg_step(lin: Lin, L, delta_gn, lam: float, radius: float):
+    """Powell's dogleg inside the trust region ||delta|| <= radius for the
+    model m(delta) = S - g^T delta + 1/2 delta^T (H + lam I) delta of the step
+    theta (-) delta: the Gauss-Newton point if it lies inside, else the
+    scaled gradient if even the Cauchy point lies outside, else the point of
+    the dogleg path on the boundary.  Returns (delta, on_boundary, predicted
+    decrease m(0) - m(delta))."""
+    n = lin.H.shape[0]
+    Hl = lin.H + lam * torch.eye(n, dtype=DT)
+    g = lin.g
+    if float(delta_gn.norm()) <= radius:
+        delta, boundary = delta_gn, False
+    else:
+        gg = float(g @ g)
+        alpha = gg / float(g @ (Hl @ g))
+        if alpha * gg ** 0.5 >= radius:
+            delta = (radius / gg ** 0.5) * g
+        else:
+            sd = alpha * g
+            dd = delta_gn - sd
+            a, b, c = float(dd @ dd), 2.0 * float(sd @ dd), alpha * alpha * gg - radius * radius
+            beta = (-b + (b * b - 4.0 * a * c) ** 0.5) / (2.0 * a)
+            delta = sd + beta * dd
+        boundary = True
+    pred = float(g @ delta) - 0.5 * float(delta @ (Hl @ delta))
+    return delta, boundary, pred
+
+
+def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool = False,
+                dogleg_radius: float | None = None) -> GraphResult:
+    """K optimizer steps on one graph then the final linearisation.  Fixed
+    damping by default; adaptive=True adapts lambda per step; dogleg_radius
+    runs Powell's dogleg with that initial trust radius (accept iff the
+    objective strictly decreases; with rho = actual / predicted decrease the
+    radius becomes ||delta|| / 4 if rho < 1/4 and min(2 radius, 1e4) if
+    rho > 3/4 on the boundary)."""
     if tau is None:
         tau = g.tau
     X = g.X.clone()
     pts = None if g.pts is None else g.pts.clone()
     obj, status = [], OK
     lambdas = [] if adaptive else None
+    radius = dogleg_radius
+    radii = [] if dogleg_radius is not None else None
     for _ in range(iterations):
         if g.is_ba:
             lin = linearize_ba(g, X, pts)
@@ -335,6 +376,19 @@ def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool 
             if delta is None:
                 status = NOT_PD
                 break
+            if radius is not None:
+                radii.append(radius)
+                delta, boundary, pred = dogleg_step(lin, L, delta, lam, radius)
+                trial = g.G.retract(X, -delta.reshape(-1, g.G.dof))
+                s_trial = float(linearize_pose_graph(g, trial, tau=tau).S)
+                rho = (float(lin.S) - s_trial) / pred
+                if s_trial < float(lin.S):
+                    X = trial
+                if not rho >= 0.25:                    # NaN shrinks too
+                    radius = 0.25 * float(delta.norm())
+                elif rho > 0.75 and boundary:
+                    radius = min(2.0 * radius, RADIUS_MAX)
+                continue
             trial = g.G.retract(X, -delta.reshape(-1, g.G.dof))
             if adaptive:
                 lambdas.append(lam)
@@ -345,7 +399,7 @@ def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool 
                     lam = min(lam * 10.0, LAMBDA_MAX)
             else:
                 X = trial
-    res = GraphResult(X=X, pts=pts, objective=obj, status=status, lambdas=lambdas)
+    res = GraphResult(X=X, pts=pts, objective=obj, status=status, lambdas=lambdas, radii=radii)
     if status != OK:
         res.objective = obj + [obj[-1]] * (iterations + 1 - len(obj))
         return res

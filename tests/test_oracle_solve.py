@@ -471,3 +471,51 @@ def test_exact_hessian_equals_gauss_newton_at_zero_residual():
     res = S.solve_graph(g, 4, 0.0)
     Hx = S.exact_hessian_graph(g, res.X)
     assert float((Hx - res.lin.H).abs().max()) < 1e-9 * float(res.lin.H.abs().max())
+
+
+# ---------------------------------------------------------------------------
+# Dogleg (trust region)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+def test_dogleg_closed_form_single_pose(group):
+    """One pose, a pure-rotation prior error theta: g = c, H acts as the
+    identity along c, so the Gauss-Newton and Cauchy points coincide at the
+    target.  While theta > radius the step is the scaled gradient of length
+    radius (rho = 1 on the boundary: the radius doubles); once theta <= radius
+    the Gauss-Newton step lands on the target (inside: the radius stays).
+    theta 1.0 with radius 0.1: theta = 1.0, 0.9, 0.7, 0.3, 0 and radii 0.1,
+    0.2, 0.4, 0.8."""
+    p = _single_pose_rotation_problem(group, 1.0)
+    g = S.graphs_of(p)[0]
+    r = S.solve_graph(g, 4, 0.0, dogleg_radius=0.1)
+    assert r.radii == pytest.approx([0.1, 0.2, 0.4, 0.8], rel=1e-12)
+    assert r.objective == pytest.approx([0.5, 0.405, 0.245, 0.045, 0.0], rel=1e-10, abs=1e-20)
+
+
+def test_dogleg_with_huge_radius_is_gauss_newton():
+    """Every Gauss-Newton point lies inside the region: the first steps are
+    the Gauss-Newton steps exactly until the rounding floor, where Gauss-Newton
+    lets S rise by an ulp and the dogleg refuses such a step."""
+    p = synth.walk_se3(batch=1, n_poses=12, n_loops=8, seed=21)
+    g = S.graphs_of(p)[0]
+    a = S.solve_graph(g, 5, 0.0)
+    b = S.solve_graph(g, 5, 0.0, dogleg_radius=1e6)
+    assert torch.equal(a.X, b.X) and a.objective == b.objective
+    b = S.solve_graph(g, 8, 0.0, dogleg_radius=1e6)
+    assert all(y <= x for x, y in zip(b.objective, b.objective[1:]))
+
+
+def test_dogleg_monotone_and_shrinks_on_rejection():
+    """From a poor initial guess: the objective never increases, every
+    rejected step (repeated objective) shrinks the radius to a quarter of the
+    step length, and some steps are rejected and some land on the boundary."""
+    p = synth.walk_se3(batch=1, n_poses=16, n_loops=10, seed=22, init_noise=(0.6, 0.4))
+    g = S.graphs_of(p)[0]
+    r = S.solve_graph(g, 12, 0.0, dogleg_radius=2.0)
+    ob = r.objective
+    assert all(b <= a for a, b in zip(ob, ob[1:]))
+    rej = [t for t in range(12) if ob[t + 1] == ob[t]]
+    assert rej, "expected at least one rejected step"
+    for t in rej:
+        if t + 1 < 12:
+            assert r.radii[t + 1] < r.radii[t]
