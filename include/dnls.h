@@ -135,7 +135,20 @@ enum {
    * 10; lambda stays in [1e-7, 1e7], per graph.  objective[b][t] is the
    * objective at theta_t, so a rejected step repeats it.  SCHUR:
    * DNLS_ERR_UNSUPPORTED. */
-  DNLS_FLAG_ADAPTIVE_LM = 2
+  DNLS_FLAG_ADAPTIVE_LM = 2,
+  /* DENSE: Powell's dogleg (Section 3 optimizers) with a per-graph trust
+   * radius starting at options.trust_radius (> 0): the Gauss-Newton step of
+   * H + lambda I if its norm is within the radius, else the gradient cut at
+   * the boundary if the Cauchy point alpha g (alpha = g^T g / g^T H g) lies
+   * outside, else the point of the segment from alpha g to the Gauss-Newton
+   * step at distance radius.  The step is kept iff the float64 objective
+   * strictly decreases; with rho = actual / predicted decrease
+   * (g^T delta - 1/2 delta^T (H + lambda I) delta) the radius becomes
+   * ||delta|| / 4 if rho < 1/4 (or is not a number) and min(2 radius, 1e4)
+   * if rho > 3/4 for a step on the boundary.  Excludes
+   * DNLS_FLAG_ADAPTIVE_LM; SPARSE and SCHUR: DNLS_ERR_UNSUPPORTED.  The
+   * mixed path linearises in float64 as well for g and the model. */
+  DNLS_FLAG_DOGLEG = 4
 };
 
 typedef struct {
@@ -146,6 +159,7 @@ typedef struct {
   double lambda;              /* Levenberg-Marquardt damping >= 0; 0 = Gauss-Newton */
   int32_t sparse_solve;       /* dnls_sparse_solve (SPARSE only) */
   int32_t flags;              /* DNLS_FLAG_* */
+  double trust_radius;        /* DNLS_FLAG_DOGLEG: initial trust radius (> 0) */
 } dnls_options;
 
 /* Arguments of dnls_solve (device pointers unless stated). */

@@ -28,6 +28,7 @@ SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
 BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2}
 FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2
+FLAG_DOGLEG = 4
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
 
@@ -51,7 +52,8 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("lambda_", ctypes.c_double), ("sparse_solve", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("lambda_", ctypes.c_double), ("sparse_solve", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("trust_radius", ctypes.c_double)]
 
 
 class _SolveArgs(ctypes.Structure):
@@ -130,7 +132,8 @@ class Plan:
 
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
-                 graph: bool = False, adaptive: bool = False):
+                 graph: bool = False, adaptive: bool = False, dogleg: float | None = None):
+        """dogleg: initial trust radius of Powell's dogleg (dense solver), or None."""
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -163,9 +166,11 @@ class Plan:
             pr.huber_delta = float(problem["huber_delta"])
         op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam),
                       SPARSE_SOLVES[sparse_solve],
-                      (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0))
+                      (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0)
+                      | (FLAG_DOGLEG if dogleg is not None else 0),
+                      float(dogleg) if dogleg is not None else 0.0)
         self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
-                           sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive))
+                           sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive), dogleg=dogleg)
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h

@@ -61,6 +61,8 @@ struct DenseArgs {
   double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
   double* hvp;       // exact backward: [cost][2][d] second-order Hessian terms
   int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
+  int dogleg;        // DNLS_FLAG_DOGLEG
+  double radius0;    // dogleg: initial trust radius
   const double* seed;
   double* g_logw_e;
   double* g_tau;
@@ -282,6 +284,7 @@ __device__ void matvec_H(const DenseArgs& a, const GraphDesc& g, const double* r
 }
 
 constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;   // adaptive damping range
+constexpr double kRadiusMax = 1e4;                         // dogleg: largest trust radius
 constexpr int kMaxExactSweeps = 64;                        // exact-Hessian backward: refinement sweeps
 
 struct KernelLds {
@@ -293,7 +296,7 @@ struct KernelLds {
 // ---------------------------------------------------------------------------
 // forward: K steps + final linearisation, one workgroup per graph
 // ---------------------------------------------------------------------------
-template <int G, bool MIXED>
+template <int G, bool MIXED, bool DOGLEG>
 __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
   extern __shared__ double dyn[];
@@ -310,6 +313,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   double last_obj = 0.0;
   int last_it = 0;
   double lam_cur = a.lambda;       // adaptive damping: this graph's lambda
+  double radius = a.radius0;       // dogleg: this graph's trust radius
   init_H(g, H);
   for (int it = 0; it <= a.K; ++it) {
     const bool final_lin = (it == a.K);
@@ -318,7 +322,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // the mixed path linearises in float32 inside the loop; the float64
     // linearisation feeds its refinement sweeps and the final (cached) factor
     const bool lin32 = MIXED && !final_lin;
-    const bool lin64 = !MIXED || a.refine > 0 || final_lin;
+    const bool lin64 = !MIXED || a.refine > 0 || final_lin || DOGLEG;
     if (lin32) S = linearize_graph<G, float>(a, g, a.ws32, L.red);
     if (lin64) S = linearize_graph<G, double>(a, g, a.ws64, L.red);
     last_obj = S;
@@ -338,7 +342,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     double* aug = A + (size_t)g.npad * g.npad;   // ... and of the factor: y = L^-1 g
     if (MIXED) {
       assemble_H<G, float>(a, g, a.ws32, H, lam);
-      if (a.refine > 0) assemble_g<G, double>(a, g, a.ws64, vy, haug);
+      if (a.refine > 0 || DOGLEG) assemble_g<G, double>(a, g, a.ws64, vy, haug);
       else assemble_g<G, float>(a, g, a.ws32, vy, haug);
     } else {
       assemble_H<G, double>(a, g, a.ws64, H, lam);
@@ -363,6 +367,73 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
+    }
+    if constexpr (DOGLEG) {
+      // Powell's dogleg in the trust region ||delta|| <= radius for the model
+      // S - g^T delta + 1/2 delta^T (H + lambda I) delta (float64 g and H)
+      double part = 0.0;
+      for (int u = threadIdx.x; u < g.n; u += kNT) part += vb[u] * vb[u];
+      const double n_gn = sqrt(block_sum(part, L.red));
+      bool boundary = false;
+      if (!(n_gn <= radius)) {
+        boundary = true;
+        matvec_H<G>(a, g, a.ws64, vy, vx, lam);   // (H + lambda I) g
+        double p1 = 0.0, p2 = 0.0;
+        for (int u = threadIdx.x; u < g.n; u += kNT) {
+          p1 += vy[u] * vy[u];
+          p2 += vy[u] * vx[u];
+        }
+        const double gg = block_sum(p1, L.red);
+        const double gHg = block_sum(p2, L.red);
+        const double alpha = gg / gHg;
+        if (alpha * sqrt(gg) >= radius) {
+          // the Cauchy point is outside: gradient direction cut at the boundary
+          const double sc = radius / sqrt(gg);
+          for (int u = threadIdx.x; u < g.n; u += kNT) vb[u] = sc * vy[u];
+          __syncthreads();
+        } else {
+          // between the Cauchy point alpha g and the Gauss-Newton point
+          double q1 = 0.0, q2 = 0.0;
+          for (int u = threadIdx.x; u < g.n; u += kNT) {
+            const double sd = alpha * vy[u], dd = vb[u] - sd;
+            q1 += dd * dd;
+            q2 += sd * dd;
+          }
+          const double qa = block_sum(q1, L.red);
+          const double qb = 2.0 * block_sum(q2, L.red);
+          const double qc = alpha * alpha * gg - radius * radius;
+          const double beta = (-qb + sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa);
+          for (int u = threadIdx.x; u < g.n; u += kNT) {
+            const double sd = alpha * vy[u];
+            vb[u] = sd + beta * (vb[u] - sd);
+          }
+          __syncthreads();
+        }
+      }
+      // predicted decrease g^T delta - 1/2 delta^T (H + lambda I) delta
+      matvec_H<G>(a, g, a.ws64, vb, vx, lam);
+      double r1 = 0.0, r2 = 0.0;
+      for (int u = threadIdx.x; u < g.n; u += kNT) {
+        r1 += vy[u] * vb[u];
+        r2 += vb[u] * vx[u];
+      }
+      const double pred = block_sum(r1, L.red) - 0.5 * block_sum(r2, L.red);
+      double r3 = 0.0;
+      for (int u = threadIdx.x; u < g.n; u += kNT) r3 += vb[u] * vb[u];
+      const double n_step = sqrt(block_sum(r3, L.red));
+      double* bak = a.pose_bak + (size_t)g.pose0 * sz;
+      for (int u = threadIdx.x; u < g.npose * sz; u += kNT) bak[u] = a.poses[(size_t)g.pose0 * sz + u];
+      for (int p = threadIdx.x; p < g.npose; p += kNT)
+        retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, vb + p * d);
+      __syncthreads();
+      const double s_trial = objective_graph<G>(a, g, L.red);
+      const double rho = (S - s_trial) / pred;
+      if (!(s_trial < S))
+        for (int u = threadIdx.x; u < g.npose * sz; u += kNT) a.poses[(size_t)g.pose0 * sz + u] = bak[u];
+      if (!(rho >= 0.25)) radius = 0.25 * n_step;
+      else if (rho > 0.75 && boundary) radius = fmin(2.0 * radius, kRadiusMax);
+      __syncthreads();
+      continue;
     }
     if (a.adaptive) {
       // adaptive damping: keep the step iff the float64 objective strictly
@@ -681,7 +752,12 @@ bool check_off(const int32_t* off, int B, int total_hint, int* total) {
 template <int G, bool MIXED>
 dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
   const size_t lds = 3 * (size_t)p->npad_max * sizeof(double);
-  hipLaunchKernelGGL((k_dense_solve<G, MIXED>), dim3(p->B), dim3(kNT), lds, st, a);
+  // the dogleg is a separate instantiation: its branch would push the
+  // plain solve's registers into scratch
+  if (a.dogleg)
+    hipLaunchKernelGGL((k_dense_solve<G, MIXED, true>), dim3(p->B), dim3(kNT), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_dense_solve<G, MIXED, false>), dim3(p->B), dim3(kNT), lds, st, a);
   HIP_TRY(hipGetLastError());
   return DNLS_OK;
 }
@@ -730,7 +806,15 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
-  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM)) return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
+  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG))
+    return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
+  if (op->flags & DNLS_FLAG_DOGLEG) {
+    if ((op->flags & DNLS_FLAG_ADAPTIVE_LM))
+      return fail(DNLS_ERR_INVALID_ARG, "adaptive damping and dogleg exclude each other");
+    if (!(op->trust_radius > 0.0) || !std::isfinite(op->trust_radius))
+      return fail(DNLS_ERR_INVALID_ARG, "dogleg needs a positive finite trust_radius");
+    if (op->solver != DNLS_SOLVER_DENSE) return fail(DNLS_ERR_UNSUPPORTED, "dogleg is implemented for the DENSE solver");
+  }
   if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver == DNLS_SOLVER_SCHUR)
     return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the pose-graph solvers");
   if (op->solver == DNLS_SOLVER_SCHUR) {
@@ -991,6 +1075,8 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
   a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
   a.adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) ? 1 : 0;
+  a.dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) ? 1 : 0;
+  a.radius0 = p->opt.trust_radius;
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
   return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);

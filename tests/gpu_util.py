@@ -30,9 +30,10 @@ def per_graph_rel(a, b, off):
     return worst
 
 
-def gpu_solve(p, K, lam, precision="fp64", refine=0, tau=None, solver="dense", adaptive=False):
+def gpu_solve(p, K, lam, precision="fp64", refine=0, tau=None, solver="dense", adaptive=False, dogleg=None):
     from paper_2207_09442_amd import Plan
-    plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=DEV, adaptive=adaptive)
+    plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=DEV, adaptive=adaptive,
+                dogleg=dogleg)
     poses = t(p["poses_init"])
     dev = dict(edge_meas=t(p["edge_meas"]), edge_logw=t(p["edge_logw"]), prior_meas=t(p["prior_meas"]),
                prior_logw=t(p["prior_logw"]), edge_tau=None if tau is None else t(tau))
@@ -60,11 +61,11 @@ def oracle_graphs(p, tau=None, graphs=None):
     return gs
 
 
-def oracle_solve(p, K, lam, tau=None, graphs=None, adaptive=False):
+def oracle_solve(p, K, lam, tau=None, graphs=None, adaptive=False, dogleg=None):
     """Oracle forward for all graphs (or the listed ones); returns
     (graphs, results)."""
     gs = oracle_graphs(p, tau, graphs)
-    res = [S.solve_graph(g, K, lam, tau=g.tau, adaptive=adaptive) for g in gs]
+    res = [S.solve_graph(g, K, lam, tau=g.tau, adaptive=adaptive, dogleg_radius=dogleg) for g in gs]
     return gs, res
 
 

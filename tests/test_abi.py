@@ -53,7 +53,8 @@ def _create(P, p, **opt):
     keep.append(a)
     pr.edge_ij = ptr
     o = P._Options(opt.get("solver", 0), opt.get("precision", 0), opt.get("iterations", 3),
-                   opt.get("refine", 0), opt.get("lam", 0.0), opt.get("sparse_solve", 0), opt.get("flags", 0))
+                   opt.get("refine", 0), opt.get("lam", 0.0), opt.get("sparse_solve", 0), opt.get("flags", 0),
+                   opt.get("radius", 0.0))
     h = ctypes.c_void_p()
     code = P.lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(o))
     return code, P.lib().dnls_last_error().decode()
@@ -82,7 +83,11 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, refine=9)[0] == 1
     assert _create(P, p, precision=5)[0] == 1
     assert _create(P, p, sparse_solve=4)[0] == 1
-    assert _create(P, p, flags=4)[0] == 1
+    assert _create(P, p, flags=8)[0] == 1
+    assert _create(P, p, flags=4)[0] == 1                 # dogleg without a trust radius
+    assert _create(P, p, flags=4, radius=float("nan"))[0] == 1
+    assert _create(P, p, flags=6, radius=1.0)[0] == 1     # dogleg and adaptive damping
+    assert _create(P, p, flags=4, radius=1.0, solver=2)[0] == 2   # dogleg: dense solver only
     assert _create(P, p, flags=2, solver=1)[0] == 2       # adaptive damping: pose-graph solvers only
 
 

@@ -41,12 +41,12 @@ def _seeds(p, poses_ref_by_graph, graphs):
 
 
 def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_pose=1e-10, tol_grad=1e-10,
-             gate_grad=True, grad_cond_scale=None, solver="dense", adaptive=False):
+             gate_grad=True, grad_cond_scale=None, solver="dense", adaptive=False, dogleg=None):
     plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver,
-                                                    adaptive=adaptive)
+                                                    adaptive=adaptive, dogleg=dogleg)
     B = len(p["pose_off"]) - 1
     graphs = list(range(B)) if graphs is None else graphs
-    gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs, adaptive=adaptive)
+    gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs, adaptive=adaptive, dogleg=dogleg)
     got = poses.cpu().numpy()
     G = gs[0].G
     ref_poses = [G.to_storage(r.X).numpy() for r in res]
@@ -85,7 +85,7 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
     assert worst_obj < max(tol_pose, 1e-12) * (1e3 if precision == "mixed" else 1)
     if gate_grad:
         assert not over, over
-    if adaptive:
+    if adaptive or dogleg is not None:
         # same accept / reject decisions: a rejected step repeats the objective exactly
         for gi, b in enumerate(graphs):
             rep_gpu = [obj[b][t + 1] == obj[b][t] for t in range(K)]
@@ -350,3 +350,42 @@ def test_adaptive_lm_se3_batch_fp64_and_mixed(solver):
     _compare(p, 5, 1e-2, adaptive=True, solver=solver)
     _compare(p, 5, 1e-2, precision="mixed", refine=1, tol_pose=1e-5, tol_grad=1e-5, adaptive=True, solver=solver)
     _compare(p, 5, 1e-2, precision="mixed", refine=0, tol_pose=1e-5, gate_grad=False, adaptive=True, solver=solver)
+
+
+# ---------------------------------------------------------------------------
+# Dogleg (trust region), dense solver
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+def test_dogleg_closed_form_single_pose(group):
+    """Pure-rotation prior error 1.0 with radius 0.1: the scaled-gradient
+    steps leave 0.9, 0.7, 0.3 (the radius doubles on the boundary) and the
+    Gauss-Newton step then lands on the target: objectives 0.5, 0.405, 0.245,
+    0.045, 0."""
+    from test_oracle_solve import _single_pose_rotation_problem
+    p = _single_pose_rotation_problem(group, 1.0)
+    plan, poses, objective, status, dev = gpu_solve(p, 4, 0.0, dogleg=0.1)
+    assert status.cpu().tolist() == [0]
+    ob = objective.cpu().numpy()[0]
+    assert ob[:4] == pytest.approx([0.5, 0.405, 0.245, 0.045], rel=1e-12)
+    assert abs(ob[4]) < 1e-24
+    assert np.abs(poses.cpu().numpy()[0] - p["prior_meas"][0]).max() < 1e-12
+
+
+@pytest.mark.parametrize("precision,refine,tol", [("fp64", 0, 1e-10), ("mixed", 1, 1e-5)])
+def test_dogleg_se3_batch_with_rejections(precision, refine, tol):
+    """SE(3) batch from a very poor initial guess (rotations perturbed by
+    2.5 rad): graph 2's first Gauss-Newton step raises the objective and is
+    refused (radius 100 -> 17.7, then doubling), the others take full steps.
+    Same iterates, objectives, accept/reject pattern and implicit gradients as
+    the oracle; K = 6 stops well above the rounding floor, where accept/reject
+    decisions would be decided by the last bit."""
+    p = synth.walk_se3(batch=4, n_poses=10, n_loops=10, seed=48, init_noise=(3.0, 2.5))
+    _compare(p, 6, 0.0, precision=precision, refine=refine, tol_pose=tol, tol_grad=tol, dogleg=100.0,
+             grad_cond_scale=0.5)
+
+
+def test_dogleg_uneven_with_weights_tau_and_damping():
+    p = synth.uneven_walk_se3(batch=6, n_min=3, n_max=40, seed=23)
+    p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
+    tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), 6))
+    _compare(p, 8, 1e-3, tau=tau, dogleg=0.05)
