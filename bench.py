@@ -174,7 +174,9 @@ def main():
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
-                    help="Levenberg-Marquardt with adaptive damping from the workload's lambda (dense solver)")
+                    help="Levenberg-Marquardt with adaptive damping from the workload's lambda")
+    ap.add_argument("--dogleg", type=float, default=None, metavar="RADIUS",
+                    help="Powell's dogleg with this initial trust radius (dense solver)")
     ap.add_argument("--backward", choices=["implicit", "dlm", "exact"], default="implicit",
                     help="backward mode: implicit (Proposition 1), direct loss minimisation, or implicit with "
                          "the exact Hessian (the last two on the dense solver)")
@@ -223,13 +225,14 @@ def main():
     else:
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
-    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive))
+    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg)
     if args.autotune and not ba:
         from paper_2207_09442_amd.autotune import autotune
         best = autotune(p, K, lam, precision=W["precision"], refine=args.refine if W["precision"] == "mixed" else 0,
                         device=dev)
         solver = best["solver"]
-        schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"], adaptive=bool(args.adaptive))
+        schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"], adaptive=bool(args.adaptive),
+                        dogleg=args.dogleg)
         progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
 
     def run(precision: str, refine: int):
@@ -307,7 +310,7 @@ def main():
     achieved = solve_flops / (head["fwd_ms"] * 1e-3) / 1e12
     single_kernel = solver == "dense"
     head_default = args.workload == DEFAULT_WORKLOAD and solver == "dense" and main_prec == "mixed"
-    kernel = ("k_dense_solve<3, true>" if main_prec == "mixed" else "k_dense_solve<%d, false>"
+    kernel = ("k_dense_solve<3, true, false>" if main_prec == "mixed" else "k_dense_solve<%d, false, false>"
               % (3 if p["group"] == "SE3" else 2)) if single_kernel else "solve (all kernels of dnls_solve)"
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
