@@ -34,6 +34,10 @@ d^2 S the Hessian of S(theta_K Exp(delta)) at delta = 0 (torch.autograd),
 which closes the gap between the Gauss-Newton reading of Proposition 1 and
 the derivative of the re-solved optimum when the residuals are not zero.
 
+Unrolled / truncated gradient: torch.autograd through the last T of the K
+plain steps (all K for full unrolling), for the loss whose tangent gradient
+at theta_K is v.
+
 Direct loss minimisation (Section 4.3, DLM paragraph; Appendix G): with the
 same v, theta_direct minimises S + ||eps theta - v / 2||^2, computed as one
 Gauss-Newton step from theta_K in the tangent space there,
@@ -506,6 +510,33 @@ def exact_implicit_grad_graph(g: Graph, res: GraphResult, v_pose) -> dict:
     Y = (lin.g * u.reshape(-1)).sum()
     de, dp, dt = torch.autograd.grad(Y, [le, lp, tau])
     return dict(edge_logw=-de, prior_logw=-dp, tau=-dt, u=u)
+
+
+def unrolled_grad_graph(g: Graph, iterations: int, lam: float, v_pose, steps: int | None = None) -> dict:
+    """Gradient by differentiating through the optimizer's own steps
+    (Section 4.3, unrolling; truncated unrolling keeps only the last `steps`
+    of the K steps): torch.autograd through the plain (fixed-damping) step
+    delta = (H + lam I)^-1 g, X <- X Exp(-delta), of the log-weights, prior
+    log-weights and measurement tangents, for the loss whose tangent gradient
+    at theta_K is v: L = sum_p v_p . Log(theta_K,p^-1 X_p) with theta_K held
+    fixed.  Also returns dL/dxi at theta_{K - steps} ("adjoint")."""
+    import dataclasses
+    d = g.G.dof
+    T = iterations if steps is None else steps
+    start = solve_graph(g, iterations - T, lam) if T < iterations else None
+    X0 = g.X if start is None else start.X.detach()
+    le = g.logw_e.clone().requires_grad_(True)
+    lp = g.logw_p.clone().requires_grad_(True)
+    tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
+    tau = tau0.clone().requires_grad_(True)
+    xi = torch.zeros(X0.shape[0], d, dtype=DT, requires_grad=True)
+    gg = dataclasses.replace(g, X=g.G.retract(X0, xi), logw_e=le, logw_p=lp, tau=tau)
+    r = solve_graph(gg, T, lam)
+    XK = r.X.detach()
+    L = (g.G.log(g.G.inv(XK) @ r.X) * torch.as_tensor(v_pose, dtype=DT)).sum()
+    de, dp, dt, dx = torch.autograd.grad(L, [le, lp, tau, xi], allow_unused=True)
+    z = lambda t, like: torch.zeros_like(like) if t is None else t
+    return dict(edge_logw=z(de, le), prior_logw=z(dp, lp), tau=z(dt, tau), adjoint=z(dx, xi), status=r.status)
 
 
 def dlm_grad_graph(g: Graph, res: GraphResult, v_pose, eps: float) -> dict:

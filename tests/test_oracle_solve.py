@@ -519,3 +519,67 @@ def test_dogleg_monotone_and_shrinks_on_rejection():
     for t in rej:
         if t + 1 < 12:
             assert r.radii[t + 1] < r.radii[t]
+
+
+# ---------------------------------------------------------------------------
+# Unrolled and truncated gradients
+# ---------------------------------------------------------------------------
+def test_unrolled_gradient_matches_fd_of_the_k_step_map():
+    """The unrolled gradient is the exact derivative of the K-step map:
+    central differences of F(phi) = sum_p v_p . Log(theta_K^-1 theta_K(phi))
+    (K = 3 LM steps from the same start) agree to 1e-7; truncation to the
+    last 3 steps equals full unrolling, and its adjoint at theta_0 matches
+    differences in the initial poses."""
+    import dataclasses
+    p = synth.walk_se3(batch=1, n_poses=8, n_loops=4, sigma_t=0.1, sigma_r=0.03, seed=12)
+    g = S.graphs_of(p)[0]
+    g = dataclasses.replace(g, tau=torch.as_tensor(rng.normal(scale=0.01, size=(len(g.ei), 6)), dtype=DT))
+    K, lam = 3, 1e-2
+    v = torch.as_tensor(rng.normal(size=(g.n_pose, 6)), dtype=DT)
+    un = S.unrolled_grad_graph(g, K, lam, v)
+    tr = S.unrolled_grad_graph(g, K, lam, v, steps=K)
+    for k in ("edge_logw", "prior_logw", "tau", "adjoint"):
+        assert torch.equal(un[k], tr[k]), k
+    G = g.G
+    XK = S.solve_graph(g, K, lam).X
+
+    def F(**kw):
+        r = S.solve_graph(dataclasses.replace(g, **kw), K, lam)
+        return float((G.log(G.inv(XK) @ r.X) * v).sum())
+
+    h = 1e-6
+    fd, ours = [], []
+    for k in (0, 4, 9):
+        a, b_ = g.logw_e.clone(), g.logw_e.clone()
+        a[k] += h
+        b_[k] -= h
+        fd.append((F(logw_e=a) - F(logw_e=b_)) / (2 * h))
+        ours.append(float(un["edge_logw"][k]))
+    for k, j in ((2, 1), (7, 5)):
+        a, b_ = g.tau.clone(), g.tau.clone()
+        a[k, j] += h
+        b_[k, j] -= h
+        fd.append((F(tau=a) - F(tau=b_)) / (2 * h))
+        ours.append(float(un["tau"][k, j]))
+    for q, j in ((3, 0), (5, 4)):
+        e = torch.zeros(g.n_pose, 6, dtype=DT)
+        e[q, j] = h
+        fd.append((F(X=G.retract(g.X, e)) - F(X=G.retract(g.X, -e))) / (2 * h))
+        ours.append(float(un["adjoint"][q, j]))
+    fd, ours = np.asarray(fd), np.asarray(ours)
+    assert np.abs(ours - fd).max() < 1e-7 * np.abs(fd).max()
+
+
+def test_truncated_gradient_is_the_last_steps_only():
+    """Truncation to T steps equals full unrolling of a problem that starts at
+    theta_{K-T}."""
+    import dataclasses
+    p = synth.walk_se3(batch=1, n_poses=8, n_loops=4, seed=13)
+    g = S.graphs_of(p)[0]
+    K, T, lam = 5, 2, 1e-3
+    v = torch.as_tensor(rng.normal(size=(g.n_pose, 6)), dtype=DT)
+    tr = S.unrolled_grad_graph(g, K, lam, v, steps=T)
+    mid = S.solve_graph(g, K - T, lam).X
+    un = S.unrolled_grad_graph(dataclasses.replace(g, X=mid), T, lam, v)
+    for k in ("edge_logw", "prior_logw", "tau"):
+        assert torch.allclose(tr[k], un[k], rtol=1e-12, atol=1e-14), k
