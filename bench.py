@@ -177,9 +177,11 @@ def main():
                     help="Levenberg-Marquardt with adaptive damping from the workload's lambda")
     ap.add_argument("--dogleg", type=float, default=None, metavar="RADIUS",
                     help="Powell's dogleg with this initial trust radius (dense solver)")
-    ap.add_argument("--backward", choices=["implicit", "dlm", "exact"], default="implicit",
-                    help="backward mode: implicit (Proposition 1), direct loss minimisation, or implicit with "
-                         "the exact Hessian (the last two on the dense solver)")
+    ap.add_argument("--backward", choices=["implicit", "dlm", "exact", "unroll"], default="implicit",
+                    help="backward mode: implicit (Proposition 1), direct loss minimisation, implicit with "
+                         "the exact Hessian, or unrolled through the last --unroll-steps steps (the last three "
+                         "on the dense solver)")
+    ap.add_argument("--unroll-steps", type=int, default=None, help="truncated unrolling: steps (default all K)")
     ap.add_argument("--dlm-eps", type=float, default=1e-3)
     ap.add_argument("--sweeps", type=int, default=8, help="refinement sweeps of the exact-Hessian backward")
     ap.add_argument("--autotune", action="store_true",
@@ -225,14 +227,15 @@ def main():
     else:
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
-    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg)
+    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg,
+                    keep_iterates=args.backward == "unroll")
     if args.autotune and not ba:
         from paper_2207_09442_amd.autotune import autotune
         best = autotune(p, K, lam, precision=W["precision"], refine=args.refine if W["precision"] == "mixed" else 0,
                         device=dev)
         solver = best["solver"]
         schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"], adaptive=bool(args.adaptive),
-                        dogleg=args.dogleg)
+                        dogleg=args.dogleg, keep_iterates=args.backward == "unroll")
         progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
 
     def run(precision: str, refine: int):
@@ -251,7 +254,8 @@ def main():
         def backward(st):
             if ba:
                 return plan.backward_ba(poses, pts, status=st, seed_cam=seed, **aux)
-            return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps, sweeps=args.sweeps)
+            return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps, sweeps=args.sweeps,
+                                 steps=args.unroll_steps)
 
         stream = torch.cuda.current_stream()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -317,7 +321,8 @@ def main():
            "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,
            "schedule": dict(schedule, autotuned=bool(args.autotune and not ba)),
            "backward": {"implicit": "implicit", "dlm": f"dlm (eps={args.dlm_eps:g})",
-                        "exact": f"exact Hessian ({args.sweeps} sweeps)"}[args.backward]}
+                        "exact": f"exact Hessian ({args.sweeps} sweeps)",
+                        "unroll": f"unrolled ({args.unroll_steps or K} of {K} steps)"}[args.backward]}
     if args.workload == "se3_walk64_b128":
         cfg.update(poses=64, loop_closures=64)
     line = {

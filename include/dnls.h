@@ -148,7 +148,12 @@ enum {
    * if rho > 3/4 for a step on the boundary.  Excludes
    * DNLS_FLAG_ADAPTIVE_LM; SPARSE and SCHUR: DNLS_ERR_UNSUPPORTED.  The
    * mixed path linearises in float64 as well for g and the model. */
-  DNLS_FLAG_DOGLEG = 4
+  DNLS_FLAG_DOGLEG = 4,
+  /* DENSE, fixed damping (not with DNLS_FLAG_ADAPTIVE_LM or
+   * DNLS_FLAG_DOGLEG): dnls_solve also stores the iterates theta_0 ..
+   * theta_{K-1} in the factor cache (factor_bytes grows by K V 12|4
+   * doubles) for the unrolled backward (DNLS_BACKWARD_UNROLL). */
+  DNLS_FLAG_KEEP_ITERATES = 8
 };
 
 typedef struct {
@@ -205,6 +210,7 @@ typedef struct {
   int32_t mode;               /* dnls_backward_mode (0 = implicit) */
   double dlm_eps;             /* DNLS_BACKWARD_DLM: epsilon > 0 */
   int32_t sweeps;             /* DNLS_BACKWARD_EXACT: refinement sweeps in [0, 64] */
+  int32_t steps;              /* DNLS_BACKWARD_UNROLL: last steps differentiated, in [1, K] */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */
@@ -232,7 +238,17 @@ typedef enum {
    * I - H*^-1 Hx is below 1, i.e. for residuals small against the
    * curvature, and each sweep multiplies the error by about that radius.
    * Then the same per-cost VJP.  The adjoint output receives u. */
-  DNLS_BACKWARD_EXACT = 2
+  DNLS_BACKWARD_EXACT = 2,
+  /* Unrolled differentiation (Section 4.3; truncated when steps < K),
+   * DENSE plans with DNLS_FLAG_KEEP_ITERATES: reverse sweep through the
+   * last `steps` optimizer steps theta_{t+1} = theta_t Exp(-delta_t),
+   * delta_t = (H_t + lambda I)^-1 g_t, recomputed in float64 at the kept
+   * iterates (the mixed path's float32 assembly is not differentiated), for
+   * the seed v = dL/dtheta_K; the parameter gradients sum over those steps
+   * and the adjoint output receives dL/dtheta_{K-steps}.  A graph whose
+   * solve failed, or whose float64 step matrix is not positive definite,
+   * gets zero gradients.  The factor of H* is not read. */
+  DNLS_BACKWARD_UNROLL = 3
 } dnls_backward_mode;
 
 /* Validate the structure and build the plan: per-graph offsets, cost

@@ -25,10 +25,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
-BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2}
+BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2, "unroll": 3}
 FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2
 FLAG_DOGLEG = 4
+FLAG_KEEP_ITERATES = 8
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
 
@@ -68,7 +69,7 @@ class _BackwardArgs(ctypes.Structure):
                                    "factor", "seed_pose", "seed_point", "grad_edge_logw",
                                    "grad_edge_tau", "grad_prior_logw", "grad_obs_w", "adjoint",
                                    "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
-                                                  ("sweeps", ctypes.c_int32)]
+                                                  ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32)]
 
 
 _LIB = None
@@ -132,8 +133,10 @@ class Plan:
 
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
-                 graph: bool = False, adaptive: bool = False, dogleg: float | None = None):
-        """dogleg: initial trust radius of Powell's dogleg (dense solver), or None."""
+                 graph: bool = False, adaptive: bool = False, dogleg: float | None = None,
+                 keep_iterates: bool = False):
+        """dogleg: initial trust radius of Powell's dogleg (dense solver), or None;
+        keep_iterates: store theta_0 .. theta_{K-1} for the unrolled backward."""
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -167,10 +170,11 @@ class Plan:
         op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam),
                       SPARSE_SOLVES[sparse_solve],
                       (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0)
-                      | (FLAG_DOGLEG if dogleg is not None else 0),
+                      | (FLAG_DOGLEG if dogleg is not None else 0) | (FLAG_KEEP_ITERATES if keep_iterates else 0),
                       float(dogleg) if dogleg is not None else 0.0)
         self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
-                           sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive), dogleg=dogleg)
+                           sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive), dogleg=dogleg,
+                           keep_iterates=bool(keep_iterates))
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h
@@ -217,13 +221,15 @@ class Plan:
         return objective, status
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
-                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8):
+                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8, steps=None):
         """Backward for `seed` = dL/dtheta_K in tangent coordinates [V, dof]:
         mode "implicit" (Proposition 1, with the cached factor), "dlm"
         (direct loss minimisation with perturbation `eps`; no adjoint) or
         "exact" (Proposition 1 with the exact Hessian, `sweeps` refinement
-        sweeps preconditioned by the cached factor); the last two on the
-        dense solver only."""
+        sweeps preconditioned by the cached factor) or "unroll" (through the
+        last `steps` optimizer steps, all K by default; plans made with
+        keep_iterates=True; the adjoint is dL/dtheta_{K-steps}); the last
+        three on the dense solver only."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {
@@ -247,6 +253,7 @@ class Plan:
         a.mode = BACKWARD_MODES[mode]
         a.dlm_eps = float(eps)
         a.sweeps = int(sweeps)
+        a.steps = self.K if steps is None else int(steps)
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
         return out
 

@@ -59,7 +59,8 @@ struct DenseArgs {
   double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
   double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated; DLM: theta_direct
   double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
-  double* hvp;       // exact backward: [cost][2][d] second-order Hessian terms
+  double* hvp;       // exact / unrolled backward: [cost][2][d] per-cost pose terms
+  double* traj;      // DNLS_FLAG_KEEP_ITERATES: theta_t, t < K, [K][V][sz] in the factor cache
   int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
   int dogleg;        // DNLS_FLAG_DOGLEG
   double radius0;    // dogleg: initial trust radius
@@ -69,6 +70,7 @@ struct DenseArgs {
   double* g_logw_p;
   double* adjoint_out;
   int E;             // total edges (prior records follow the edge records)
+  int V;             // total poses
   int K;
   int refine;
   double lambda;
@@ -318,6 +320,10 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   for (int it = 0; it <= a.K; ++it) {
     const bool final_lin = (it == a.K);
     const double lam = final_lin ? 0.0 : lam_cur;
+    if (a.traj && !final_lin) {
+      double* dst = a.traj + ((size_t)it * a.V + g.pose0) * sz;
+      for (int u = threadIdx.x; u < g.npose * sz; u += kNT) dst[u] = a.poses[(size_t)g.pose0 * sz + u];
+    }
     double S = 0.0;
     // the mixed path linearises in float32 inside the loop; the float64
     // linearisation feeds its refinement sweeps and the final (cached) factor
@@ -632,6 +638,127 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_exact(DenseArgs a, int s
   vjp_graph<G>(a, g, vu);
 }
 
+// Unrolled backward (truncated to the last T steps): reverse sweep through
+// theta_{t+1} = theta_t Exp(-delta_t), delta_t = (H_t + lambda I)^-1 g_t, from
+// the kept iterates.  Per step, with abar the cotangent at theta_{t+1}:
+//   dbar_p = -Jr(-delta_p)^T abar_p,  abar_p <- Ad(Exp(delta_p))^T abar_p,
+//   y = (H_t + lambda I)^-1 dbar, then the gradient of
+//   s = y^T g_t - y^T (H_t + lambda I) delta_t (y, delta_t fixed) is added to
+//   abar (poses) and to the parameter gradients (cost_unroll_vjp).
+template <int G>
+__global__ void __launch_bounds__(kNT) k_dense_backward_unroll(DenseArgs a, int T) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  extern __shared__ double dyn[];
+  __shared__ KernelLds L;
+  const int b = a.order[blockIdx.x];
+  const GraphDesc g = a.gd[b];
+  zero_grads<G>(a, g, true);
+  if (a.status[b] != DNLS_GRAPH_OK) return;
+  double* va = dyn;                // cotangent of the iterate
+  double* vd = dyn + g.npad;       // delta_t
+  double* vw = dyn + 2 * g.npad;   // dbar, then y
+  double* H = a.hbuf + g.h_off;
+  double* haug = H + (size_t)g.npad * g.npad;
+  double* winv = a.dlm_winv + g.dlm_winv_off;
+  for (int u = threadIdx.x; u < g.npad; u += kNT) va[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
+  __syncthreads();
+  const int ncost = g.nedge + g.nprior;
+  for (int t = a.K - 1; t >= a.K - T; --t) {
+    DenseArgs at = a;
+    at.poses = a.traj + (size_t)t * a.V * sz;
+    const PoseCostData cd = cost_data(at);
+    linearize_graph<G, double>(at, g, a.ws64, L.red);
+    init_H(g, H);
+    assemble_H<G, double>(at, g, a.ws64, H, a.lambda);
+    assemble_g<G, double>(at, g, a.ws64, vd, haug);
+    if (!chol_dense(H, H, g.npad, winv, L.dl)) {
+      // the forward factored this system (in float32 on the mixed path): give up on the graph
+      zero_grads<G>(a, g, true);
+      return;
+    }
+    for (int u = threadIdx.x; u < g.npad; u += kNT) vd[u] = haug[u];
+    __syncthreads();
+    trsv_upper_t(H, g.npad, winv, vd, L.dl);
+    // through the retraction
+    for (int p = threadIdx.x; p < g.npose; p += kNT) {
+      double dl[d], md[d], Jr[d * d], Ad[d * d], ab[d];
+      for (int q = 0; q < d; ++q) {
+        dl[q] = vd[p * d + q];
+        md[q] = -dl[q];
+        ab[q] = va[p * d + q];
+      }
+      if constexpr (G == 3) {
+        double E[12], R[9], tv[3];
+        se3_jr(md, Jr);
+        se3_exp(dl, E);
+        for (int r = 0; r < 3; ++r) {
+          for (int q = 0; q < 3; ++q) R[r * 3 + q] = E[r * 4 + q];
+          tv[r] = E[r * 4 + 3];
+        }
+        se3_adjoint(R, tv, Ad);
+      } else {
+        double E[4];
+        se2_jr(md, Jr);
+        se2_exp(dl, E);
+        se2_adjoint(E[0], E[1], E[2], E[3], Ad);
+      }
+      for (int m = 0; m < d; ++m) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < d; ++q) {
+          s1 += Jr[q * d + m] * ab[q];
+          s2 += Ad[q * d + m] * ab[q];
+        }
+        vw[p * d + m] = -s1;
+        va[p * d + m] = s2;
+      }
+    }
+    for (int u = g.n + threadIdx.x; u < g.npad; u += kNT) vw[u] = 0.0;
+    __syncthreads();
+    trsv_lower(H, g.npad, winv, vw, L.dl);
+    trsv_upper_t(H, g.npad, winv, vw, L.dl);
+    // per-cost gradient of s: pose terms to the per-cost buffer, parameters accumulated
+    for (int k = threadIdx.x; k < ncost; k += kNT) {
+      int cost, pi, pj;
+      if (k < g.nedge) {
+        cost = g.edge0 + k;
+        pi = a.edge_ij[2 * cost] - g.pose0;
+        pj = a.edge_ij[2 * cost + 1] - g.pose0;
+      } else {
+        const int pq = g.prior0 + (k - g.nedge);
+        cost = a.E + pq;
+        pi = -1;
+        pj = a.prior_var[pq] - g.pose0;
+      }
+      double* o = a.hvp + (size_t)cost * 2 * d;
+      double dlw, dt[d];
+      cost_unroll_vjp<G>(cd, cost, pi >= 0 ? vw + pi * d : nullptr, vw + pj * d, pi >= 0 ? vd + pi * d : nullptr,
+                         vd + pj * d, o, o + d, &dlw, k < g.nedge ? dt : nullptr);
+      if (pi < 0)
+        for (int q = 0; q < d; ++q) o[q] = 0.0;
+      if (k < g.nedge) {
+        if (a.g_logw_e) a.g_logw_e[cost] += dlw;
+        if (a.g_tau)
+          for (int q = 0; q < d; ++q) a.g_tau[(size_t)cost * d + q] += dt[q];
+      } else if (a.g_logw_p) {
+        a.g_logw_p[cost - a.E] += dlw;
+      }
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < g.n; u += kNT) {
+      const int p = u / d, r = u % d, gp = g.pose0 + p;
+      double v = 0.0;
+      for (int s2 = a.inc_off[gp]; s2 < a.inc_off[gp + 1]; ++s2) {
+        const int slot = a.inc_slot[s2];
+        v += a.hvp[(size_t)(slot >> 1) * 2 * d + (slot & 1) * d + r];
+      }
+      va[u] += v;
+    }
+    __syncthreads();
+  }
+  if (a.adjoint_out)
+    for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = va[u];
+}
+
 // ---------------------------------------------------------------------------
 // backward by direct loss minimisation (Section 4.3, Appendix G): one
 // Gauss-Newton step from theta_K on S + ||eps theta - v / 2||^2,
@@ -764,6 +891,12 @@ dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
 
 template <int G>
 dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st, int mode, double eps, int sweeps) {
+  if (mode == DNLS_BACKWARD_UNROLL) {
+    const size_t lds3 = 3 * (size_t)p->npad_max * sizeof(double);
+    hipLaunchKernelGGL((k_dense_backward_unroll<G>), dim3(p->B), dim3(kNT), lds3, st, a, sweeps);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   if (mode == DNLS_BACKWARD_EXACT) {
     const size_t lds3 = 3 * (size_t)p->npad_max * sizeof(double);
     hipLaunchKernelGGL((k_dense_backward_exact<G>), dim3(p->B), dim3(kNT), lds3, st, a, sweeps);
@@ -806,8 +939,14 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
-  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG))
+  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES))
     return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
+  if (op->flags & DNLS_FLAG_KEEP_ITERATES) {
+    if (op->solver != DNLS_SOLVER_DENSE)
+      return fail(DNLS_ERR_UNSUPPORTED, "kept iterates (unrolled backward) are implemented for the DENSE solver");
+    if (op->flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG))
+      return fail(DNLS_ERR_UNSUPPORTED, "the unrolled backward differentiates the fixed-damping step only");
+  }
   if (op->flags & DNLS_FLAG_DOGLEG) {
     if ((op->flags & DNLS_FLAG_ADAPTIVE_LM))
       return fail(DNLS_ERR_INVALID_ARG, "adaptive damping and dogleg exclude each other");
@@ -968,6 +1107,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   ws += align256(ncost * 2 * d * sizeof(double));       // exact backward: residual terms per cost side
   p->ws_bytes = ws;
   p->bwd_bytes = ws;
+  p->traj_off = fac;   // doubles
+  if (op->flags & DNLS_FLAG_KEEP_ITERATES) fac += (long long)op->iterations * V * p->sz;
   p->fac_bytes = (size_t)fac * sizeof(double);
   *out = p;
   return DNLS_OK;
@@ -999,6 +1140,7 @@ static DenseArgs base_args(dnls_plan p) {
   a.od_blk = p->d_od_blk;
   a.od_slot = p->d_od_slot;
   a.E = p->E;
+  a.V = p->V;
   a.K = p->opt.iterations;
   a.refine = p->opt.precision == DNLS_PREC_MIXED ? p->opt.refine : 0;
   a.lambda = p->opt.lambda;
@@ -1077,6 +1219,7 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) ? 1 : 0;
   a.dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) ? 1 : 0;
   a.radius0 = p->opt.trust_radius;
+  a.traj = (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) ? a.factor + p->traj_off : nullptr;
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   if (p->group == DNLS_SE3) return mixed ? launch_solve<3, true>(p, a, st) : launch_solve<3, false>(p, a, st);
   return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);
@@ -1089,8 +1232,14 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
     return fail(DNLS_ERR_INVALID_ARG, "poses, status, factor, seed_pose and workspace are required");
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
-  if (s->mode != DNLS_BACKWARD_IMPLICIT && s->mode != DNLS_BACKWARD_DLM && s->mode != DNLS_BACKWARD_EXACT)
+  if (s->mode < DNLS_BACKWARD_IMPLICIT || s->mode > DNLS_BACKWARD_UNROLL)
     return fail(DNLS_ERR_INVALID_ARG, "unknown backward mode");
+  if (s->mode == DNLS_BACKWARD_UNROLL) {
+    if (!(p->opt.flags & DNLS_FLAG_KEEP_ITERATES))
+      return fail(DNLS_ERR_INVALID_ARG, "the unrolled backward needs a plan with DNLS_FLAG_KEEP_ITERATES");
+    if (s->steps < 1 || s->steps > p->opt.iterations)
+      return fail(DNLS_ERR_INVALID_ARG, "steps must be in [1, iterations]");
+  }
   if (s->mode == DNLS_BACKWARD_EXACT) {
     if (p->opt.solver != DNLS_SOLVER_DENSE)
       return fail(DNLS_ERR_UNSUPPORTED, "the exact-Hessian backward is implemented for the DENSE solver");
@@ -1121,6 +1270,7 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
   a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
   a.hvp = reinterpret_cast<double*>(ws + p->hvp_off);
+  a.traj = (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) ? a.factor + p->traj_off : nullptr;
   a.seed = s->seed_pose;
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
@@ -1128,8 +1278,9 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.adjoint_out = s->adjoint;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the cached factor is float64-assembled in both precisions
-  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st, s->mode, s->dlm_eps, s->sweeps);
-  return launch_backward<2>(p, a, st, s->mode, s->dlm_eps, s->sweeps);
+  const int count = s->mode == DNLS_BACKWARD_UNROLL ? s->steps : s->sweeps;
+  if (p->group == DNLS_SE3) return launch_backward<3>(p, a, st, s->mode, s->dlm_eps, count);
+  return launch_backward<2>(p, a, st, s->mode, s->dlm_eps, count);
 }
 
 dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses, const double* grad, double* out,

@@ -252,6 +252,186 @@ DNLS_HD void cost_hvp_residual(const PoseCostData& a, int k, const double* rec, 
   for (int m = 0; m < d; ++m) oi[m] -= ti[m];
 }
 
+// One cost's part of the reverse step through delta = (H + lambda I)^-1 g
+// (unrolled differentiation): with y = (H + lambda I)^-1 dL/ddelta and delta
+// held fixed, the gradient of s = (J y)^T (r - J delta) = w^2 (C y)^T e,
+// e = c - C delta, with respect to right perturbations of the cost's poses
+// (oi, oj; oi unused for a prior), its log-weight (2 s) and its measurement
+// tangent.  With u1 = y_j - Ad(T) y_i and u2 = delta_j - Ad(T) delta_i
+// (T = X_j^-1 X_i; y_j and delta_j alone for a prior), C y = Jr^-1(c) u1 and
+// C delta = Jr^-1(c) u2, so through c
+//   ds/dc = w^2 (C y + G),  G_m = e^T (dJr^-1/dc_m) u1 - (C y)^T (dJr^-1/dc_m) u2
+// (one dual-number pass per component of c), moved to the poses by C^T; the
+// pose dependence of Ad(T), d/ds Ad = Ad ad(x_i) - ad(x_j) Ad, adds
+//   oi += w^2 (ad(y_i)^T Ad^T p - ad(delta_i)^T Ad^T q),
+//   oj += w^2 (-ad(Ad y_i)^T p + ad(Ad delta_i)^T q),  p = Jr^-T e, q = Jr^-T C y;
+// and dc/dtau = -Jl^-1(c) Jr(tau0) gives the tangent gradient.
+template <int G>
+DNLS_HD void cost_unroll_vjp(const PoseCostData& a, int k, const double* yi, const double* yj, const double* di,
+                             const double* dj, double* oi, double* oj, double* dlogw, double* dtau) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  const bool edge = k < a.E;
+  double c[d], Ci[d * d], Jinv[d * d], Ad[d * d], w;
+  if (edge) {
+    const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+    double Z[sz];
+    perturbed_meas<G>(a.edge_meas + (size_t)k * sz, a.edge_tau ? a.edge_tau + (size_t)k * d : nullptr, Z);
+    between_cost<G, double>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Jinv);
+    w = exp(a.edge_logw[k]);
+    if constexpr (G == 3) {
+      double Xji[12], M[12], RM[9], tM[3];
+      se3_inv(a.poses + (size_t)j * sz, Xji);
+      se3_mul(Xji, a.poses + (size_t)i * sz, M);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) RM[r * 3 + q] = M[r * 4 + q];
+        tM[r] = M[r * 4 + 3];
+      }
+      se3_adjoint(RM, tM, Ad);
+    } else {
+      double Xji[4], M[4];
+      se2_inv(a.poses + (size_t)j * sz, Xji);
+      se2_mul(Xji, a.poses + (size_t)i * sz, M);
+      se2_adjoint(M[0], M[1], M[2], M[3], Ad);
+    }
+  } else {
+    const int p = k - a.E;
+    prior_cost<G, double>(a.poses + (size_t)a.prior_var[p] * sz, a.prior_meas + (size_t)p * sz, c, Jinv);
+    w = exp(a.prior_logw[p]);
+  }
+  const double w2 = w * w;
+  double u1[d], u2[d], Ayi[d], Adi[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0;
+    if (edge)
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        s1 += Ad[m * d + q] * yi[q];
+        s2 += Ad[m * d + q] * di[q];
+      }
+    Ayi[m] = s1;
+    Adi[m] = s2;
+    u1[m] = yj[m] - s1;
+    u2[m] = dj[m] - s2;
+  }
+  double Cy[d], e[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      s1 += Jinv[m * d + q] * u1[q];
+      s2 += Jinv[m * d + q] * u2[q];
+    }
+    Cy[m] = s1;
+    e[m] = c[m] - s2;
+  }
+  double sval = 0.0;
+#pragma unroll
+  for (int m = 0; m < d; ++m) sval += Cy[m] * e[m];
+  *dlogw = 2.0 * w2 * sval;
+  // ds/dc
+  double gc[d];
+#pragma unroll 1
+  for (int m = 0; m < d; ++m) {
+    Dual<double> cd[d], J[d * d];
+#pragma unroll
+    for (int q = 0; q < d; ++q) cd[q] = Dual<double>(c[q], q == m ? 1.0 : 0.0);
+    if constexpr (G == 3) se3_jr_inv(cd, J);
+    else se2_jr_inv(cd, J);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        t1 += J[r * d + q].d * u1[q];
+        t2 += J[r * d + q].d * u2[q];
+      }
+      acc += e[r] * t1 - Cy[r] * t2;
+    }
+    gc[m] = w2 * (Cy[m] + acc);
+  }
+  // through c: C_j = Jr^-1, C_i = -Jr^-1 Ad
+  double jg[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) acc += Jinv[q * d + m] * gc[q];
+    jg[m] = acc;
+    oj[m] = acc;
+  }
+  if (!edge) return;
+  double pv[d], qv[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      s1 += Jinv[q * d + m] * e[q];
+      s2 += Jinv[q * d + m] * Cy[q];
+    }
+    pv[m] = s1;
+    qv[m] = s2;
+  }
+  double Ap[d], Aq[d], t1[d], t2[d];
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      s1 += Ad[q * d + m] * jg[q];
+      s2 += Ad[q * d + m] * pv[q];
+      s3 += Ad[q * d + m] * qv[q];
+    }
+    oi[m] = -s1;
+    Ap[m] = s2;
+    Aq[m] = s3;
+  }
+  ad_transpose_mul<G>(yi, Ap, t1);
+  ad_transpose_mul<G>(di, Aq, t2);
+#pragma unroll
+  for (int m = 0; m < d; ++m) oi[m] += w2 * (t1[m] - t2[m]);
+  ad_transpose_mul<G>(Ayi, pv, t1);
+  ad_transpose_mul<G>(Adi, qv, t2);
+#pragma unroll
+  for (int m = 0; m < d; ++m) oj[m] += w2 * (t2[m] - t1[m]);
+  if (!dtau) return;
+  // dtau = -Jr(tau0)^T Jl^-T(c) ds/dc,  Jl^-1(c) = Jr^-1(-c)
+  double mc[d], Jl[d * d], tt[d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) mc[q] = -c[q];
+  if constexpr (G == 3) se3_jr_inv(mc, Jl);
+  else se2_jr_inv(mc, Jl);
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) acc += Jl[q * d + m] * gc[q];
+    tt[m] = acc;
+  }
+  if (a.edge_tau) {
+    double Jr[d * d], t0[d];
+#pragma unroll
+    for (int q = 0; q < d; ++q) t0[q] = a.edge_tau[(size_t)k * d + q];
+    if constexpr (G == 3) se3_jr(t0, Jr);
+    else se2_jr(t0, Jr);
+#pragma unroll
+    for (int m = 0; m < d; ++m) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) acc += Jr[q * d + m] * tt[q];
+      dtau[m] = -acc;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < d; ++m) dtau[m] = -tt[m];
+  }
+}
+
 // Per-cost VJP of cost k from its float64 record and the adjoint u of its
 // poses (ui is null for a prior).  Null gradient outputs are skipped.
 template <int G>
