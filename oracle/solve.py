@@ -89,6 +89,7 @@ class Graph:
     intr: tuple | None = None
     delta: float = 0.0
     tau: torch.Tensor | None = None     # [E, dof] measurement tangent perturbation
+    logc_e: torch.Tensor | None = None  # [E] Welsch log-radius of each edge (None: plain least squares)
 
     @property
     def n_pose(self):
@@ -119,6 +120,8 @@ def graphs_of(problem: dict, poses=None, points=None) -> list[Graph]:
             PZ=G.from_storage(_T(problem["prior_meas"][q0:q1])),
             logw_p=_T(problem["prior_logw"][q0:q1]),
         )
+        if problem.get("edge_logc") is not None:
+            g.logc_e = _T(problem["edge_logc"][e0:e1])
         if "point_off" in problem:
             t0, t1 = int(problem["point_off"][b]), int(problem["point_off"][b + 1])
             o0, o1 = int(problem["obs_off"][b]), int(problem["obs_off"][b + 1])
@@ -171,9 +174,26 @@ def pose_costs(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None):
     return dict(c_e=c_e, Ci=Ci, Cj=Cj, w_e=torch.exp(logw_e), c_p=c_p, Cp=Cp, w_p=torch.exp(logw_p))
 
 
-def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None) -> Lin:
+def welsch(s: torch.Tensor, logc: torch.Tensor):
+    """Welsch robust loss on the squared weighted residual s with radius
+    c = exp(logc): rho(s) = c^2 (1 - exp(-s / c^2)) and rho'(s) = exp(-s / c^2)."""
+    c2 = torch.exp(2.0 * logc)
+    return c2 * (1.0 - torch.exp(-s / c2)), torch.exp(-s / c2)
+
+
+def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None, logc_e=None) -> Lin:
+    """Normal equations of the pose-graph objective.  With Welsch radii on the
+    edges (g.logc_e, or logc_e) the edges enter by first-order reweighting:
+    J and r scaled by sqrt(rho'(s)), s = ||w c||^2, and S = 1/2 sum rho(s)."""
     G, d, N = g.G, g.G.dof, X.shape[0]
     k = pose_costs(g, X, tau, logw_e, logw_p)
+    logc_e = g.logc_e if logc_e is None else logc_e
+    se = (k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)
+    if logc_e is not None:
+        rho_e, drho_e = welsch(se, logc_e)
+        k["w_e"] = k["w_e"] * torch.sqrt(drho_e)
+    else:
+        rho_e = se
     w2e = (k["w_e"] ** 2)[:, None, None]
     w2p = (k["w_p"] ** 2)[:, None, None]
     Ci, Cj, Cp = k["Ci"], k["Cj"], k["Cp"]
@@ -187,8 +207,7 @@ def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_
     ge_j = (w2e * tr(Cj) @ k["c_e"][..., None])[..., 0]
     gp = (w2p * tr(Cp) @ k["c_p"][..., None])[..., 0]
     gvec = _scatter_vec(N, d, torch.cat([g.ei, g.ej, g.pv]), torch.cat([ge_i, ge_j, gp]))
-    S = 0.5 * ((k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)).sum() + \
-        0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+    S = 0.5 * rho_e.sum() + 0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
     return Lin(S=S, H=H, g=gvec, extra=k)
 
 
@@ -472,10 +491,18 @@ def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
     lp = g.logw_p.clone().requires_grad_(True)
     tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
     tau = tau0.clone().requires_grad_(True)
-    lin = linearize_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp)
+    params = [le, lp, tau]
+    lc = None
+    if g.logc_e is not None:
+        lc = g.logc_e.clone().requires_grad_(True)
+        params.append(lc)
+    lin = linearize_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp, logc_e=lc)
     Y = (lin.g * u.reshape(-1)).sum()
-    de, dp, dt = torch.autograd.grad(Y, [le, lp, tau])
-    return dict(edge_logw=-de, prior_logw=-dp, tau=-dt, u=u)
+    grads = torch.autograd.grad(Y, params)
+    out = dict(edge_logw=-grads[0], prior_logw=-grads[1], tau=-grads[2], u=u)
+    if lc is not None:
+        out["edge_logc"] = -grads[3]
+    return out
 
 
 def exact_hessian_graph(g: Graph, X: torch.Tensor) -> torch.Tensor:
@@ -553,8 +580,13 @@ def dlm_grad_graph(g: Graph, res: GraphResult, v_pose, eps: float) -> dict:
         le = g.logw_e.clone().requires_grad_(True)
         lp = g.logw_p.clone().requires_grad_(True)
         tau = tau0.clone().requires_grad_(True)
-        lin = linearize_pose_graph(g, X, tau=tau, logw_e=le, logw_p=lp)
-        return torch.autograd.grad(lin.S, [le, lp, tau])
+        params = [le, lp, tau]
+        lc = None
+        if g.logc_e is not None:
+            lc = g.logc_e.clone().requires_grad_(True)
+            params.append(lc)
+        lin = linearize_pose_graph(g, X, tau=tau, logw_e=le, logw_p=lp, logc_e=lc)
+        return torch.autograd.grad(lin.S, params)
 
     lin = res.lin
     n = lin.H.shape[0]
@@ -562,8 +594,11 @@ def dlm_grad_graph(g: Graph, res: GraphResult, v_pose, eps: float) -> dict:
     delta = torch.linalg.solve(lin.H + 2.0 * eps * eps * torch.eye(n, dtype=DT), rhs)
     X_direct = g.G.retract(res.X, delta.reshape(-1, d))
     a, b = dS(res.X), dS(X_direct)
-    return dict(edge_logw=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, tau=(a[2] - b[2]) / eps,
-                delta=delta.reshape(-1, d))
+    out = dict(edge_logw=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, tau=(a[2] - b[2]) / eps,
+               delta=delta.reshape(-1, d))
+    if g.logc_e is not None:
+        out["edge_logc"] = (a[3] - b[3]) / eps
+    return out
 
 
 def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graphs=None) -> dict:

@@ -183,7 +183,7 @@ def circle_se2(batch: int = 1, n_poses: int = 16, n_loops: int = 8, radius: floa
 # SE(3) random walks (fixed or uneven sizes)
 # --------------------------------------------------------------------------
 def _walk_graph(rng, n_poses: int, n_loops: int, sigma_t: float, sigma_r: float,
-                noiseless: bool, init_noise: tuple[float, float] | None = None) -> dict:
+                noiseless: bool, init_noise: tuple[float, float] | None = None, outliers: int = 0) -> dict:
     gt = [np.eye(4)]
     for _ in range(n_poses - 1):
         step_t = np.array([1.0, 0.0, 0.0]) + 0.2 * rng.normal(size=3)
@@ -202,6 +202,10 @@ def _walk_graph(rng, n_poses: int, n_loops: int, sigma_t: float, sigma_r: float,
             init.append(init[-1] @ meas[k])
     else:
         init = [gt[0]] + [T @ _noise3(rng, init_noise[0], init_noise[1]) for T in gt[1:]]
+    # gross outliers: the first `outliers` loop closures get a random relative
+    # pose (drawn last, so the other draws do not depend on the count)
+    for q in range(min(outliers, len(pairs) - (n_poses - 1))):
+        meas[n_poses - 1 + q] = _T3(_rot(rng.uniform(-np.pi, np.pi, size=3) / np.sqrt(3.0)), rng.normal(0.0, 3.0, size=3))
     return {
         "poses_gt": np.stack([_pack3(T) for T in gt]),
         "poses_init": np.stack([_pack3(T) for T in init]),
@@ -214,13 +218,14 @@ def _walk_graph(rng, n_poses: int, n_loops: int, sigma_t: float, sigma_r: float,
 
 def walk_se3(batch: int = 128, n_poses: int = 64, n_loops: int = 64, sigma_t: float = 0.05,
              sigma_r: float = 0.01, noiseless: bool = False, init_noise=None,
-             cfg: int = 2, seed: int = 0) -> dict:
+             cfg: int = 2, seed: int = 0, outliers: int = 0) -> dict:
     """Random-walk trajectories: each step moves about one unit along the body x axis
     with Gaussian jitter (0.2) in translation and rotation vector; odometry edges
     (k, k+1) plus uniformly drawn loop closures; initial guess composed from the
-    noisy odometry."""
+    noisy odometry.  `outliers` loop closures per graph are replaced by random
+    relative poses (the loop-closure outliers of a robust-cost experiment)."""
     graphs = [_walk_graph(rng_for(cfg, b, seed), n_poses, n_loops, sigma_t, sigma_r, noiseless,
-                          init_noise) for b in range(batch)]
+                          init_noise, outliers) for b in range(batch)]
     return _concat(graphs, "SE3")
 
 
