@@ -182,6 +182,12 @@ typedef struct {
   int32_t* status;            /* [B] out: DNLS_GRAPH_* */
   void* factor;               /* factor cache, factor_bytes, written for dnls_backward */
   void* workspace;            /* solve_ws bytes */
+  const double* edge_logc;    /* [E] Welsch log-radii of the edges, or NULL: with
+                                 c = exp(logc) an edge contributes
+                                 1/2 rho(s) = 1/2 c^2 (1 - exp(-s / c^2)),
+                                 s = ||w c_e||^2, and enters the normal
+                                 equations reweighted by rho'(s) (first
+                                 order).  Pose-graph solvers only. */
 } dnls_solve_args;
 
 /* Arguments of dnls_backward: everything must be the state left by the
@@ -211,6 +217,10 @@ typedef struct {
   double dlm_eps;             /* DNLS_BACKWARD_DLM: epsilon > 0 */
   int32_t sweeps;             /* DNLS_BACKWARD_EXACT: refinement sweeps in [0, 64] */
   int32_t steps;              /* DNLS_BACKWARD_UNROLL: last steps differentiated, in [1, K] */
+  const double* edge_logc;    /* [E] Welsch log-radii as in dnls_solve, or NULL;
+                                 not with DNLS_BACKWARD_EXACT / UNROLL
+                                 (DNLS_ERR_UNSUPPORTED) */
+  double* grad_edge_logc;     /* [E] out or NULL: gradient at the log-radii */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */

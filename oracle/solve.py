@@ -190,11 +190,13 @@ def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_
     logc_e = g.logc_e if logc_e is None else logc_e
     se = (k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)
     if logc_e is not None:
+        # reweighted squared weight w^2 rho'(s), without a square root in the
+        # autograd graph (rho' underflows to 0 on gross outliers)
         rho_e, drho_e = welsch(se, logc_e)
-        k["w_e"] = k["w_e"] * torch.sqrt(drho_e)
+        w2e = (k["w_e"] ** 2 * drho_e)[:, None, None]
     else:
         rho_e = se
-    w2e = (k["w_e"] ** 2)[:, None, None]
+        w2e = (k["w_e"] ** 2)[:, None, None]
     w2p = (k["w_p"] ** 2)[:, None, None]
     Ci, Cj, Cp = k["Ci"], k["Cj"], k["Cp"]
     tr = lambda A: A.transpose(-1, -2)

@@ -60,7 +60,7 @@ class _Options(ctypes.Structure):
 class _SolveArgs(ctypes.Structure):
     _fields_ = [(n, _vp) for n in ["poses", "points", "edge_meas", "edge_logw", "edge_tau",
                                    "prior_meas", "prior_logw", "obs_uv", "obs_w", "objective",
-                                   "status", "factor", "workspace"]]
+                                   "status", "factor", "workspace", "edge_logc"]]
 
 
 class _BackwardArgs(ctypes.Structure):
@@ -69,7 +69,8 @@ class _BackwardArgs(ctypes.Structure):
                                    "factor", "seed_pose", "seed_point", "grad_edge_logw",
                                    "grad_edge_tau", "grad_prior_logw", "grad_obs_w", "adjoint",
                                    "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
-                                                  ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32)]
+                                                  ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32),
+                                                  ("edge_logc", _vp), ("grad_edge_logc", _vp)]
 
 
 _LIB = None
@@ -204,9 +205,10 @@ class Plan:
             self._h = None
 
     # ------------------------------------------------------------------
-    def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None):
+    def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None, edge_logc=None):
         """Runs K steps in place on `poses` (float64 device tensor [V, 3, 4] or
-        [V, 4]); returns (objective [B, K+1], status [B])."""
+        [V, 4]); returns (objective [B, K+1], status [B]).  edge_logc: Welsch
+        log-radii of the edges [E] (robust loss), or None."""
         import torch
         objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
         status = torch.empty(self.B, dtype=torch.int32, device=self.device)
@@ -217,11 +219,13 @@ class Plan:
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
         a.workspace = self._aligned(self.workspace)
+        a.edge_logc = _ptr(edge_logc)
         _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
         return objective, status
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
-                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8, steps=None):
+                 edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8, steps=None,
+                 edge_logc=None):
         """Backward for `seed` = dL/dtheta_K in tangent coordinates [V, dof]:
         mode "implicit" (Proposition 1, with the cached factor), "dlm"
         (direct loss minimisation with perturbation `eps`; no adjoint) or
@@ -229,7 +233,8 @@ class Plan:
         sweeps preconditioned by the cached factor) or "unroll" (through the
         last `steps` optimizer steps, all K by default; plans made with
         keep_iterates=True; the adjoint is dL/dtheta_{K-steps}); the last
-        three on the dense solver only."""
+        three on the dense solver only.  With Welsch radii (edge_logc) the
+        output also holds their gradient "edge_logc"."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {
@@ -239,8 +244,11 @@ class Plan:
         }
         if want_adjoint:
             out["adjoint"] = torch.empty(self.V, self.dof, dtype=f64, device=dev)
+        if edge_logc is not None:
+            out["edge_logc"] = torch.empty(self.E, dtype=f64, device=dev)
         a = _BackwardArgs()
         a.poses = _ptr(poses)
+        a.edge_logc, a.grad_edge_logc = _ptr(edge_logc), _ptr(out.get("edge_logc"))
         a.edge_meas, a.edge_logw, a.edge_tau = _ptr(edge_meas), _ptr(edge_logw), _ptr(edge_tau)
         a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
         a.status = _ptr(status)

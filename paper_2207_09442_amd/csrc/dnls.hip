@@ -50,6 +50,7 @@ struct DenseArgs {
   const double* edge_tau;
   const double* prior_meas;
   const double* prior_logw;
+  const double* edge_logc;   // Welsch log-radii or null
   double* objective;
   int* status;
   double* factor;
@@ -68,6 +69,7 @@ struct DenseArgs {
   double* g_logw_e;
   double* g_tau;
   double* g_logw_p;
+  double* g_logc;
   double* adjoint_out;
   int E;             // total edges (prior records follow the edge records)
   int V;             // total poses
@@ -92,7 +94,7 @@ __device__ double block_sum(double v, double* red) {
 
 __device__ __forceinline__ PoseCostData cost_data(const DenseArgs& a) {
   return PoseCostData{a.edge_ij, a.prior_var, a.poses, a.edge_meas, a.edge_logw,
-                      a.edge_tau, a.prior_meas, a.prior_logw, a.E};
+                      a.edge_tau, a.prior_meas, a.prior_logw, a.E, a.edge_logc};
 }
 
 // Linearise every cost of graph g in precision S into `rec`; returns the
@@ -298,8 +300,16 @@ struct KernelLds {
 // ---------------------------------------------------------------------------
 // forward: K steps + final linearisation, one workgroup per graph
 // ---------------------------------------------------------------------------
-template <int G, bool MIXED, bool DOGLEG>
+// GENERAL = false is the plain fixed/adaptive-damping solve with plain least
+// squares; GENERAL = true adds the run-time options that would otherwise push
+// the plain solve's registers into scratch: the dogleg (a.dogleg) and Welsch
+// edges (a.edge_logc).
+template <int G, bool MIXED, bool GENERAL>
 __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
+  if constexpr (!GENERAL) {
+    a.edge_logc = nullptr;
+    a.dogleg = 0;
+  }
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
   extern __shared__ double dyn[];
   __shared__ KernelLds L;
@@ -328,7 +338,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // the mixed path linearises in float32 inside the loop; the float64
     // linearisation feeds its refinement sweeps and the final (cached) factor
     const bool lin32 = MIXED && !final_lin;
-    const bool lin64 = !MIXED || a.refine > 0 || final_lin || DOGLEG;
+    const bool lin64 = !MIXED || a.refine > 0 || final_lin || a.dogleg;
     if (lin32) S = linearize_graph<G, float>(a, g, a.ws32, L.red);
     if (lin64) S = linearize_graph<G, double>(a, g, a.ws64, L.red);
     last_obj = S;
@@ -348,7 +358,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     double* aug = A + (size_t)g.npad * g.npad;   // ... and of the factor: y = L^-1 g
     if (MIXED) {
       assemble_H<G, float>(a, g, a.ws32, H, lam);
-      if (a.refine > 0 || DOGLEG) assemble_g<G, double>(a, g, a.ws64, vy, haug);
+      if (a.refine > 0 || a.dogleg) assemble_g<G, double>(a, g, a.ws64, vy, haug);
       else assemble_g<G, float>(a, g, a.ws32, vy, haug);
     } else {
       assemble_H<G, double>(a, g, a.ws64, H, lam);
@@ -374,7 +384,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         __syncthreads();
       }
     }
-    if constexpr (DOGLEG) {
+    if (GENERAL && a.dogleg) {
       // Powell's dogleg in the trust region ||delta|| <= radius for the model
       // S - g^T delta + 1/2 delta^T (H + lambda I) delta (float64 g and H)
       double part = 0.0;
@@ -494,7 +504,7 @@ __device__ void vjp_graph(const DenseArgs& a, const GraphDesc& g, const double* 
       rk = a.E + p;
       uj = vu + (a.prior_var[p] - g.pose0) * d;
     }
-    cost_vjp<G>(cd, rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p);
+    cost_vjp<G>(cd, rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p, a.g_logc);
   }
 }
 
@@ -504,6 +514,7 @@ __device__ void zero_grads(const DenseArgs& a, const GraphDesc& g, bool adjoint)
   for (int k = threadIdx.x; k < g.nedge; k += kNT) {
     const int e = g.edge0 + k;
     if (a.g_logw_e) a.g_logw_e[e] = 0.0;
+    if (a.g_logc) a.g_logc[e] = 0.0;
     if (a.g_tau)
       for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
   }
@@ -771,17 +782,18 @@ __device__ void param_grads(const DenseArgs& a, const GraphDesc& g, const double
   PoseCostData cd = cost_data(a);
   cd.poses = poses;
   for (int k = threadIdx.x; k < g.nedge + g.nprior; k += kNT) {
-    double dl, dt[d];
+    double dl, dt[d], dlc = 0.0;
     if (k < g.nedge) {
       const int e = g.edge0 + k;
-      cost_param_grad<G>(cd, e, &dl, dt);
+      cost_param_grad<G>(cd, e, &dl, dt, &dlc);
       if (a.g_logw_e) a.g_logw_e[e] = (accumulate ? a.g_logw_e[e] : 0.0) + scale * dl;
+      if (a.g_logc) a.g_logc[e] = (accumulate ? a.g_logc[e] : 0.0) + scale * dlc;
       if (a.g_tau)
 #pragma unroll
         for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = (accumulate ? a.g_tau[(size_t)e * d + q] : 0.0) + scale * dt[q];
     } else {
       const int pq = g.prior0 + (k - g.nedge);
-      cost_param_grad<G>(cd, a.E + pq, &dl, dt);
+      cost_param_grad<G>(cd, a.E + pq, &dl, dt, nullptr);
       if (a.g_logw_p) a.g_logw_p[pq] = (accumulate ? a.g_logw_p[pq] : 0.0) + scale * dl;
     }
   }
@@ -879,9 +891,7 @@ bool check_off(const int32_t* off, int B, int total_hint, int* total) {
 template <int G, bool MIXED>
 dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
   const size_t lds = 3 * (size_t)p->npad_max * sizeof(double);
-  // the dogleg is a separate instantiation: its branch would push the
-  // plain solve's registers into scratch
-  if (a.dogleg)
+  if (a.dogleg || a.edge_logc)
     hipLaunchKernelGGL((k_dense_solve<G, MIXED, true>), dim3(p->B), dim3(kNT), lds, st, a);
   else
     hipLaunchKernelGGL((k_dense_solve<G, MIXED, false>), dim3(p->B), dim3(kNT), lds, st, a);
@@ -1201,6 +1211,7 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   if (p->opt.solver == DNLS_SOLVER_SPARSE) return solve_multi(p, s, st);
   DenseArgs a = base_args(p);
   a.poses = s->poses;
+  a.edge_logc = s->edge_logc;
   a.edge_meas = s->edge_meas;
   a.edge_logw = s->edge_logw;
   a.edge_tau = s->edge_tau;
@@ -1234,6 +1245,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   if (s->mode < DNLS_BACKWARD_IMPLICIT || s->mode > DNLS_BACKWARD_UNROLL)
     return fail(DNLS_ERR_INVALID_ARG, "unknown backward mode");
+  if (s->edge_logc && (s->mode == DNLS_BACKWARD_EXACT || s->mode == DNLS_BACKWARD_UNROLL))
+    return fail(DNLS_ERR_UNSUPPORTED, "the exact-Hessian and unrolled backward do not take Welsch edges");
   if (s->mode == DNLS_BACKWARD_UNROLL) {
     if (!(p->opt.flags & DNLS_FLAG_KEEP_ITERATES))
       return fail(DNLS_ERR_INVALID_ARG, "the unrolled backward needs a plan with DNLS_FLAG_KEEP_ITERATES");
@@ -1275,6 +1288,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
   a.g_logw_p = s->grad_prior_logw;
+  a.edge_logc = s->edge_logc;
+  a.g_logc = s->grad_edge_logc;
   a.adjoint_out = s->adjoint;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the cached factor is float64-assembled in both precisions

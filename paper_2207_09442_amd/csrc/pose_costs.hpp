@@ -7,6 +7,11 @@
 //               chain rule Jr(tau)^T for a non-zero base tau
 // The tau formula follows from dc/dtau = -Jl^-1(c) and the symmetry of
 // mixed partial derivatives of 1/2 ||c(theta (+) s u, tau)||^2.
+//
+// Edges may carry a Welsch robust loss with radius c_e = exp(logc_e):
+// rho(s) = c^2 (1 - exp(-s / c^2)) on s = ||w c||^2, applied by first-order
+// reweighting (J and r scaled by sqrt(rho'(s)), rho'(s) = exp(-s / c^2)) and
+// objective 1/2 rho(s).
 #pragma once
 
 #include "costs.hpp"
@@ -23,7 +28,17 @@ struct PoseCostData {
   const double* prior_meas;
   const double* prior_logw;
   int E;                    // records: edges [0, E), priors [E, E + P)
+  const double* edge_logc;  // [E] Welsch log-radii, or null (plain least squares)
 };
+
+// Welsch reweighting of edge k at squared weighted residual s: returns
+// rho'(s) and sets *half_rho = rho(s) / 2, *x = s / c^2.
+DNLS_HD double welsch_weight(const PoseCostData& a, int k, double s, double* half_rho, double* x) {
+  const double c2 = exp(2.0 * a.edge_logc[k]);
+  *x = s / c2;
+  *half_rho = -0.5 * c2 * expm1(-*x);
+  return exp(-*x);
+}
 
 // Linearise cost k (record index) into rec (CostRec<d>::n values of S);
 // returns 1/2 w^2 ||c||^2.
@@ -45,19 +60,23 @@ __device__ __forceinline__ double linearize_cost(const PoseCostData& a, int k, S
     for (int q = 0; q < d * d; ++q) Ci[q] = S(0);
     w = exp(a.prior_logw[p]);
   }
-  const S ws = S(w);
   double cc = 0.0;
+#pragma unroll
+  for (int q = 0; q < d; ++q) cc += double(c[q]) * double(c[q]);
+  double obj = 0.5 * w * w * cc;
+  if (k < a.E && a.edge_logc) {
+    double x;
+    w *= ::sqrt(welsch_weight(a, k, w * w * cc, &obj, &x));
+  }
+  const S ws = S(w);
 #pragma unroll
   for (int q = 0; q < d * d; ++q) {
     rec[q] = ws * Ci[q];
     rec[d * d + q] = ws * Cj[q];
   }
 #pragma unroll
-  for (int q = 0; q < d; ++q) {
-    rec[2 * d * d + q] = ws * c[q];
-    cc += double(c[q]) * double(c[q]);
-  }
-  return 0.5 * w * w * cc;
+  for (int q = 0; q < d; ++q) rec[2 * d * d + q] = ws * c[q];
+  return obj;
 }
 
 // 1/2 w^2 ||c||^2 of cost k in float64 (residual only: the Jacobian outputs
@@ -81,15 +100,57 @@ __device__ __forceinline__ double cost_objective(const PoseCostData& a, int k) {
   double cc = 0.0;
 #pragma unroll
   for (int q = 0; q < d; ++q) cc += c[q] * c[q];
-  return 0.5 * w * w * cc;
+  double obj = 0.5 * w * w * cc;
+  if (k < a.E && a.edge_logc) {
+    double x;
+    welsch_weight(a, k, w * w * cc, &obj, &x);
+  }
+  return obj;
 }
 
-// Parameter gradient of the cost's 1/2 w^2 ||c||^2 at the current poses
-// (direct loss minimisation): dS/dl = w^2 ||c||^2 and, for an edge,
-//   dS/dtau = -w^2 Jr(tau0)^T Jl^-1(c)^T c,  Jl^-1(c) = Jr^-1(-c),
-// from dc/dtau = -Jl^-1(c) Jr(tau0) for Z <- Z Exp(tau) at the base tau0.
+// t = Jr(tau0)^T Jl^-1(c)^T c for edge k, Jl^-1(c) = Jr^-1(-c): minus the
+// tau-gradient of 1/2 ||c||^2 through dc/dtau = -Jl^-1(c) Jr(tau0) for
+// Z <- Z Exp(tau) at the base tau0 (the chain factor is I when tau is absent).
 template <int G>
-__device__ __forceinline__ void cost_param_grad(const PoseCostData& a, int k, double* dl, double* dtau) {
+DNLS_HD void tau_pullback_c(const PoseCostData& a, int k, const double* c, double* t) {
+  constexpr int d = GroupTraits<G>::d;
+  double mc[d], Jl[d * d];
+#pragma unroll
+  for (int q = 0; q < d; ++q) mc[q] = -c[q];
+  if constexpr (G == 3) se3_jr_inv(mc, Jl);
+  else se2_jr_inv(mc, Jl);
+#pragma unroll
+  for (int m = 0; m < d; ++m) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) acc += Jl[q * d + m] * c[q];
+    t[m] = acc;
+  }
+  if (a.edge_tau) {
+    double Jr[d * d], t0[d], u[d];
+#pragma unroll
+    for (int q = 0; q < d; ++q) t0[q] = a.edge_tau[(size_t)k * d + q];
+    if constexpr (G == 3) se3_jr(t0, Jr);
+    else se2_jr(t0, Jr);
+#pragma unroll
+    for (int m = 0; m < d; ++m) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < d; ++q) acc += Jr[q * d + m] * t[q];
+      u[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < d; ++m) t[m] = u[m];
+  }
+}
+
+// Parameter gradient of the cost's share of the objective at the current
+// poses (direct loss minimisation): plain cost 1/2 w^2 ||c||^2 gives
+// dS/dl = w^2 ||c||^2 = s and, for an edge, dS/dtau = -w^2 Jr(tau0)^T Jl^-1(c)^T c;
+// a Welsch edge 1/2 rho(s) gives dS/dl = rho'(s) s, dS/dtau = rho'(s) x the
+// plain one and dS/dlogc = rho(s) - rho'(s) s (dlc may be null).
+template <int G>
+__device__ __forceinline__ void cost_param_grad(const PoseCostData& a, int k, double* dl, double* dtau, double* dlc) {
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
   double c[d], Ci[d * d], Cj[d * d];
   double w;
@@ -108,40 +169,20 @@ __device__ __forceinline__ void cost_param_grad(const PoseCostData& a, int k, do
   double cc = 0.0;
 #pragma unroll
   for (int q = 0; q < d; ++q) cc += c[q] * c[q];
-  *dl = w * w * cc;
+  const double s = w * w * cc;
+  *dl = s;
   if (!edge) return;
-  double mc[d], Jl[d * d], t[d];
-#pragma unroll
-  for (int q = 0; q < d; ++q) mc[q] = -c[q];
-  if constexpr (G == 3) se3_jr_inv(mc, Jl);
-  else se2_jr_inv(mc, Jl);
-#pragma unroll
-  for (int m = 0; m < d; ++m) {
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < d; ++q) acc += Jl[q * d + m] * c[q];
-    t[m] = acc;
+  double rp = 1.0;
+  if (a.edge_logc) {
+    double half_rho, x;
+    rp = welsch_weight(a, k, s, &half_rho, &x);
+    *dl = rp * s;
+    if (dlc) *dlc = 2.0 * half_rho - rp * s;
   }
-  if (a.edge_tau) {
-    double Jr[d * d], t0[d];
-    const double* tau0 = a.edge_tau + (size_t)k * d;
+  double t[d];
+  tau_pullback_c<G>(a, k, c, t);
 #pragma unroll
-    for (int q = 0; q < d; ++q) t0[q] = tau0[q];
-    if constexpr (G == 3) se3_jr(t0, Jr);
-    else se2_jr(t0, Jr);
-    double u[d];
-#pragma unroll
-    for (int m = 0; m < d; ++m) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < d; ++q) acc += Jr[q * d + m] * t[q];
-      u[m] = acc;
-    }
-#pragma unroll
-    for (int m = 0; m < d; ++m) t[m] = u[m];
-  }
-#pragma unroll
-  for (int m = 0; m < d; ++m) dtau[m] = -w * w * t[m];
+  for (int m = 0; m < d; ++m) dtau[m] = -rp * w * w * t[m];
 }
 
 // out = ad(x)^T v, with ad(x) the linearisation of Ad(Exp(s x)) = I + s ad(x):
@@ -433,11 +474,17 @@ DNLS_HD void cost_unroll_vjp(const PoseCostData& a, int k, const double* yi, con
 }
 
 // Per-cost VJP of cost k from its float64 record and the adjoint u of its
-// poses (ui is null for a prior).  Null gradient outputs are skipped.
+// poses (ui is null for a prior).  Null gradient outputs are skipped.  For a
+// Welsch edge the record holds the reweighted J~, r~ (factor sqrt(rho')), so
+// (J~ u)^T r~ = rho'(s) (J u)^T r =: yr and, with x = s / c^2,
+//   dL/dl = -2 yr (1 - x),  dL/dlogc = -2 x yr,
+//   dL/dtau = rho' x (plain formula) - (2 w^2 / c^2) yr Jr(tau0)^T Jl^-1(c)^T c,
+// the last term from rho'' = -rho' / c^2 and ds/dtau.
 template <int G>
 __device__ __forceinline__ void cost_vjp(const PoseCostData& a, int k, const double* rec, const double* ui,
-                                         const double* uj, double* g_logw_e, double* g_tau, double* g_logw_p) {
-  constexpr int d = GroupTraits<G>::d;
+                                         const double* uj, double* g_logw_e, double* g_tau, double* g_logw_p,
+                                         double* g_logc) {
+  constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
   const double* r = rec + 2 * d * d;
   double y[d], yr = 0.0;
 #pragma unroll
@@ -455,19 +502,45 @@ __device__ __forceinline__ void cost_vjp(const PoseCostData& a, int k, const dou
     if (g_logw_p) g_logw_p[k - a.E] = -2.0 * yr;
     return;
   }
-  if (g_logw_e) g_logw_e[k] = -2.0 * yr;
-  if (!g_tau) return;
   const double w = exp(a.edge_logw[k]);
-  double c[d], cd[d], out[d];
+  double w2eff = w * w, c[d], cd[d];   // w^2 (rho'(s) w^2 for a Welsch edge); c; c' = C u
+  double robust_tau = 0.0;             // coefficient of Jr(tau0)^T Jl^-1(c)^T c in dL/dtau
+  if (a.edge_logc) {
+    // the raw residual and Jacobians (the record holds the reweighted ones,
+    // which vanish where rho' underflows on a gross outlier)
+    const int i = a.edge_ij[2 * k], j = a.edge_ij[2 * k + 1];
+    double Z[sz], Ci[d * d], Cj[d * d];
+    perturbed_meas<G>(a.edge_meas + (size_t)k * sz, a.edge_tau ? a.edge_tau + (size_t)k * d : nullptr, Z);
+    between_cost<G, double>(a.poses + (size_t)i * sz, a.poses + (size_t)j * sz, Z, c, Ci, Cj);
+    double cc = 0.0;
 #pragma unroll
-  for (int q = 0; q < d; ++q) {
-    c[q] = r[q] / w;
-    cd[q] = y[q] / w;
+    for (int q = 0; q < d; ++q) {
+      cc += c[q] * c[q];
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < d; ++m) acc += Ci[q * d + m] * ui[m] + Cj[q * d + m] * uj[m];
+      cd[q] = acc;
+    }
+    double half_rho, x;
+    const double rp = welsch_weight(a, k, w * w * cc, &half_rho, &x);
+    w2eff = rp * w * w;
+    if (g_logw_e) g_logw_e[k] = -2.0 * yr * (1.0 - x);
+    if (g_logc) g_logc[k] = -2.0 * x * yr;
+    robust_tau = -2.0 * w * w * exp(-2.0 * a.edge_logc[k]) * yr;
+  } else {
+    if (g_logw_e) g_logw_e[k] = -2.0 * yr;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      c[q] = r[q] / w;
+      cd[q] = y[q] / w;
+    }
   }
+  if (!g_tau) return;
+  double out[d];
   dual_jlinvT_c<G>(c, cd, out);
   double gt[d];
 #pragma unroll
-  for (int q = 0; q < d; ++q) gt[q] = w * w * out[q];
+  for (int q = 0; q < d; ++q) gt[q] = w2eff * out[q];
   if (a.edge_tau) {
     // Exp(tau + dt) = Exp(tau) Exp(Jr(tau) dt)  =>  dL/dtau = Jr(tau)^T dL/dxi
     double tau[d], Jt[d * d];
@@ -487,6 +560,12 @@ __device__ __forceinline__ void cost_vjp(const PoseCostData& a, int k, const dou
   } else {
 #pragma unroll
     for (int q = 0; q < d; ++q) g_tau[(size_t)k * d + q] = gt[q];
+  }
+  if (robust_tau != 0.0) {
+    double t[d];
+    tau_pullback_c<G>(a, k, c, t);
+#pragma unroll
+    for (int q = 0; q < d; ++q) g_tau[(size_t)k * d + q] += robust_tau * t[q];
   }
 }
 

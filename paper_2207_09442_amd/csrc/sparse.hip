@@ -58,6 +58,7 @@ struct SpArgs {
   const double* edge_tau;
   const double* prior_meas;
   const double* prior_logw;
+  const double* edge_logc; // Welsch log-radii or null
   double* objective;
   int* status;
   double* factor;          // tile pools and panel inverses
@@ -73,6 +74,7 @@ struct SpArgs {
   double* g_logw_e;
   double* g_tau;
   double* g_logw_p;
+  double* g_logc;
   double* lam_g;           // adaptive damping: lambda per graph
   double* pose_bak;        // adaptive damping: theta_t while the trial step is evaluated
   double* s_t;             // adaptive damping: float64 objective at theta_t per graph
@@ -83,7 +85,7 @@ struct SpArgs {
 
 __device__ __forceinline__ PoseCostData cost_data(const SpArgs& a) {
   return PoseCostData{a.edge_ij, a.prior_var, a.poses, a.edge_meas, a.edge_logw,
-                      a.edge_tau, a.prior_meas, a.prior_logw, a.E};
+                      a.edge_tau, a.prior_meas, a.prior_logw, a.E, a.edge_logc};
 }
 
 __device__ __forceinline__ double* tile_ptr(const SpArgs& a, const SpDesc& g, int I, int J) {
@@ -819,6 +821,7 @@ __global__ void __launch_bounds__(kBT) k_sp_vjp(SpArgs a) {
   if (!ok) {
     if (k < g.nedge) {
       if (a.g_logw_e) a.g_logw_e[rk] = 0.0;
+      if (a.g_logc) a.g_logc[rk] = 0.0;
       if (a.g_tau)
         for (int q = 0; q < d; ++q) a.g_tau[(size_t)rk * d + q] = 0.0;
     } else if (a.g_logw_p) {
@@ -826,7 +829,7 @@ __global__ void __launch_bounds__(kBT) k_sp_vjp(SpArgs a) {
     }
     return;
   }
-  cost_vjp<G>(cost_data(a), rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p);
+  cost_vjp<G>(cost_data(a), rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p, a.g_logc);
 }
 
 __global__ void k_sp_reset(int* failed, int* status, int B) {
@@ -1156,6 +1159,7 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   a.edge_tau = s->edge_tau;
   a.prior_meas = s->prior_meas;
   a.prior_logw = s->prior_logw;
+  a.edge_logc = s->edge_logc;
   a.objective = s->objective;
   a.status = s->status;
   const int B = p->B;
@@ -1232,6 +1236,8 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
   a.g_logw_p = s->grad_prior_logw;
+  a.edge_logc = s->edge_logc;
+  a.g_logc = s->grad_edge_logc;
   const int B = p->B;
   const dim3 g_cost(p->nlin_blocks, B);
   // float64 records at theta_K for the graphs whose solve succeeded

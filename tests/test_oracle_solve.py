@@ -645,8 +645,9 @@ def test_welsch_implicit_gradient_matches_stopped_newton_fd():
         a[k] += h
         b_[k] -= h
         fd_w.append((F(lc0, a) - F(lc0, b_)) / (2 * h))
+    # central differences with h = 1e-6 carry ~1e-9 of rounding noise on these gradients (~5e-4)
     for fd, ours in ((np.asarray(fd_c), gr["edge_logc"].numpy()), (np.asarray(fd_w), gr["edge_logw"].numpy())):
-        assert np.abs(ours - fd).max() < 1e-6 * max(1e-3, np.abs(fd).max())
+        assert np.abs(ours - fd).max() < 1e-5 * max(1e-3, np.abs(fd).max())
     assert np.abs(fd_c).max() > 1e-5
 
 
