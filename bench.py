@@ -175,6 +175,8 @@ def main():
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
                     help="Levenberg-Marquardt with adaptive damping from the workload's lambda")
+    ap.add_argument("--no-pair", action="store_true",
+                    help="dense solver: one workgroup per graph even where a co-resident pair per graph fits")
     ap.add_argument("--dogleg", type=float, default=None, metavar="RADIUS",
                     help="Powell's dogleg with this initial trust radius (dense solver)")
     ap.add_argument("--backward", choices=["implicit", "dlm", "exact", "unroll"], default="implicit",
@@ -228,14 +230,14 @@ def main():
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
     schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg,
-                    keep_iterates=args.backward == "unroll")
+                    keep_iterates=args.backward == "unroll", pair=not args.no_pair)
     if args.autotune and not ba:
         from paper_2207_09442_amd.autotune import autotune
         best = autotune(p, K, lam, precision=W["precision"], refine=args.refine if W["precision"] == "mixed" else 0,
                         device=dev)
         solver = best["solver"]
         schedule = dict(sparse_solve=best["sparse_solve"], graph=best["graph"], adaptive=bool(args.adaptive),
-                        dogleg=args.dogleg, keep_iterates=args.backward == "unroll")
+                        dogleg=args.dogleg, keep_iterates=args.backward == "unroll", pair=best.get("pair", False))
         progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
 
     def run(precision: str, refine: int):
@@ -314,8 +316,11 @@ def main():
     achieved = solve_flops / (head["fwd_ms"] * 1e-3) / 1e12
     single_kernel = solver == "dense"
     head_default = args.workload == DEFAULT_WORKLOAD and solver == "dense" and main_prec == "mixed"
-    kernel = ("k_dense_solve<3, true, false>" if main_prec == "mixed" else "k_dense_solve<%d, false, false>"
-              % (3 if p["group"] == "SE3" else 2)) if single_kernel else "solve (all kernels of dnls_solve)"
+    pair_used = single_kernel and head["plan"].pair_active()
+    kernel = ("k_dense_solve<%d, %s, false, %s>" % (3 if p["group"] == "SE3" else 2,
+                                                     "true" if main_prec == "mixed" else "false",
+                                                     "true" if pair_used else "false")
+              if single_kernel else "solve (all kernels of dnls_solve)")
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
            "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,

@@ -65,7 +65,11 @@ typedef enum {
 } dnls_status;
 
 /* per-graph numerical status written by dnls_solve */
-enum { DNLS_GRAPH_OK = 0, DNLS_GRAPH_NOT_PD = 1, DNLS_GRAPH_NONFINITE = 2 };
+enum { DNLS_GRAPH_OK = 0, DNLS_GRAPH_NOT_PD = 1, DNLS_GRAPH_NONFINITE = 2,
+       /* DNLS_FLAG_PAIR: a workgroup of the graph's pair waited for its
+        * partner beyond the poll limit (the cooperative launch makes the
+        * pair co-resident, so this indicates a fault) */
+       DNLS_GRAPH_TIMEOUT = 3 };
 
 typedef enum { DNLS_SE2 = 2, DNLS_SE3 = 3 } dnls_group;
 
@@ -153,7 +157,16 @@ enum {
    * DNLS_FLAG_DOGLEG): dnls_solve also stores the iterates theta_0 ..
    * theta_{K-1} in the factor cache (factor_bytes grows by K V 12|4
    * doubles) for the unrolled backward (DNLS_BACKWARD_UNROLL). */
-  DNLS_FLAG_KEEP_ITERATES = 8
+  DNLS_FLAG_KEEP_ITERATES = 8,
+  /* DENSE, plain least squares with fixed or adaptive damping: when the
+   * device can hold two workgroups per graph at once, dnls_solve runs each
+   * graph on a pair of co-resident workgroups (cooperative launch) that
+   * share every factorisation, for batches too small to fill the device;
+   * otherwise (or with DNLS_FLAG_DOGLEG or Welsch edges) the one-workgroup
+   * kernel runs.  Results equal the one-workgroup path's up to rounding.
+   * The plan holds event counters: calls with this flag must not overlap on
+   * one plan. */
+  DNLS_FLAG_PAIR = 16
 };
 
 typedef struct {
@@ -280,6 +293,13 @@ dnls_status dnls_plan_workspace(dnls_plan plan, size_t* solve_ws, size_t* factor
  * system), i.e. the flops the method needs (Section 4.2); executed: what the
  * kernels run, padded panels and whole tiles included. */
 dnls_status dnls_plan_flops(dnls_plan plan, double* algorithmic, double* executed);
+
+/* The schedule a plan resolved at creation (host values, either pointer may
+ * be NULL): dense_pair = 1 if dnls_solve runs each graph on a co-resident
+ * pair of workgroups (DNLS_FLAG_PAIR requested and the pair fits), else 0;
+ * sparse_solve = the dnls_sparse_solve that AUTO resolved to (SPARSE), else
+ * DNLS_SPSOLVE_AUTO. */
+dnls_status dnls_plan_schedule(dnls_plan plan, int32_t* dense_pair, int32_t* sparse_solve);
 
 /* Run K optimizer steps and the final linearisation on `stream` (a
  * hipStream_t, NULL = default stream).  Enqueues kernels only. */

@@ -30,6 +30,7 @@ FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2
 FLAG_DOGLEG = 4
 FLAG_KEEP_ITERATES = 8
+FLAG_PAIR = 16
 GROUPS = {"SE2": 2, "SE3": 3}
 STATUS = {0: "ok", 1: "not_pd", 2: "nonfinite"}
 
@@ -87,13 +88,15 @@ def lib():
         L.dnls_plan_workspace.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.dnls_plan_flops.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.dnls_plan_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.dnls_solve.argtypes = [_vp, ctypes.POINTER(_SolveArgs), _vp]
         L.dnls_backward.argtypes = [_vp, ctypes.POINTER(_BackwardArgs), _vp]
         L.dnls_project_grad.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.dnls_plan_destroy.argtypes = [_vp]
         L.dnls_last_error.restype = ctypes.c_char_p
         L.dnls_version.restype = ctypes.c_char_p
-        for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_plan_flops", "dnls_solve", "dnls_backward",
+        for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_plan_flops", "dnls_plan_schedule", "dnls_solve",
+                  "dnls_backward",
                   "dnls_project_grad", "dnls_plan_destroy"]:
             getattr(L, f).restype = ctypes.c_int
         _LIB = L
@@ -135,9 +138,10 @@ class Plan:
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
                  graph: bool = False, adaptive: bool = False, dogleg: float | None = None,
-                 keep_iterates: bool = False):
+                 keep_iterates: bool = False, pair: bool = False):
         """dogleg: initial trust radius of Powell's dogleg (dense solver), or None;
-        keep_iterates: store theta_0 .. theta_{K-1} for the unrolled backward."""
+        keep_iterates: store theta_0 .. theta_{K-1} for the unrolled backward;
+        pair: dense solver, two co-resident workgroups per graph when they fit."""
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -171,11 +175,12 @@ class Plan:
         op = _Options(SOLVERS[solver], PRECISIONS[precision], self.K, int(refine), float(lam),
                       SPARSE_SOLVES[sparse_solve],
                       (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0)
-                      | (FLAG_DOGLEG if dogleg is not None else 0) | (FLAG_KEEP_ITERATES if keep_iterates else 0),
+                      | (FLAG_DOGLEG if dogleg is not None else 0) | (FLAG_KEEP_ITERATES if keep_iterates else 0)
+                      | (FLAG_PAIR if pair else 0),
                       float(dogleg) if dogleg is not None else 0.0)
         self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
                            sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive), dogleg=dogleg,
-                           keep_iterates=bool(keep_iterates))
+                           keep_iterates=bool(keep_iterates), pair=bool(pair))
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h
@@ -192,6 +197,16 @@ class Plan:
         a, e = ctypes.c_double(), ctypes.c_double()
         _check(lib().dnls_plan_flops(self._h, ctypes.byref(a), ctypes.byref(e)), "dnls_plan_flops")
         return a.value, e.value
+
+    def schedule(self):
+        """The resolved schedule (dnls_plan_schedule): {"pair": bool, "sparse_solve": name}."""
+        pair, sp = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().dnls_plan_schedule(self._h, ctypes.byref(pair), ctypes.byref(sp)), "dnls_plan_schedule")
+        names = {v: k for k, v in SPARSE_SOLVES.items()}
+        return {"pair": bool(pair.value), "sparse_solve": names[sp.value]}
+
+    def pair_active(self):
+        return self.schedule()["pair"]
 
     @staticmethod
     def _aligned(t):

@@ -1,5 +1,5 @@
-"""Schedule autotuner: picks the solver (dense per-graph kernel or
-block-sparse tiles), the sparse schedule (factorisation and triangular
+"""Schedule autotuner: picks the solver (dense per-graph kernel, on one
+workgroup or a co-resident pair per graph, or block-sparse tiles), the sparse schedule (factorisation and triangular
 solves in one workgroup per graph, per-column launches, or per-column
 factorisation with workgroup solves) and HIP-graph capture for a problem
 structure by
@@ -25,6 +25,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dnls_autotune.j
 
 CANDIDATES = [
     dict(solver="dense", sparse_solve="auto", graph=False),
+    dict(solver="dense", sparse_solve="auto", graph=False, pair=True),
     dict(solver="sparse", sparse_solve="workgroup", graph=False),
     dict(solver="sparse", sparse_solve="workgroup", graph=True),
     dict(solver="sparse", sparse_solve="hybrid", graph=False),
@@ -114,7 +115,8 @@ def autotune(problem: dict, iterations: int, lam: float = 0.0, precision: str = 
     feasible = [c for c in timings if c["ms"] is not None]
     best = min(feasible, key=lambda c: c["ms"])
     result = dict(solver=best["solver"], sparse_solve=best["sparse_solve"], graph=best["graph"],
-                  ms=best["ms"], candidates=timings, tuning_seconds=time.perf_counter() - t0)
+                  pair=bool(best.get("pair", False)), ms=best["ms"], candidates=timings,
+                  tuning_seconds=time.perf_counter() - t0)
     cache[key] = result
     _store(path, cache)
     return result
@@ -126,4 +128,5 @@ def tuned_plan(problem: dict, iterations: int, lam: float = 0.0, precision: str 
     from . import Plan
     best = autotune(problem, iterations, lam, precision, refine, device, **kw)
     return Plan(problem, iterations, lam=lam, precision=precision, refine=refine, device=device,
-                solver=best["solver"], sparse_solve=best["sparse_solve"], graph=best["graph"])
+                solver=best["solver"], sparse_solve=best["sparse_solve"], graph=best["graph"],
+                pair=best.get("pair", False))

@@ -352,6 +352,219 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
   return ok;
 }
 
+// ---------------------------------------------------------------------------
+// Two workgroups per graph: the pair shares one factorisation, each taking
+// every other group of row tiles of a panel (the leader, role 0, starts with
+// the diagonal group), with three kinds of events posted through monotone
+// 64-bit counters in device memory (agent-scope release / acquire): the
+// leader's diagonal block of panel J written (the follower then reads
+// L_JJ^-1 from the factor cache), and each role's end of panel J (both wait
+// for the other before the next panel, whose updates read every row's L).
+// Waits are bounded: after `spin` polls the wait fails and the caller gives
+// up the graph instead of hanging.  The pair must be co-resident, which the
+// cooperative launch of the caller guarantees.
+// ---------------------------------------------------------------------------
+struct PairSync {
+  unsigned long long* lead_h;     // leader: the system of factorisation f is assembled (base + f + 1)
+  unsigned long long* lead_stop;  // leader: left its loop (base + 1)
+  unsigned long long* lead_diag;  // leader: diagonal block J of factorisation f written (base + f P + J + 1)
+  unsigned long long* panel[2];   // role r: panel J of factorisation f finished (base + f P + J + 1)
+  unsigned long long base;        // this launch's origin of the counters
+  int role;
+  int spin;                       // poll limit of a wait
+};
+
+// all threads call: every wave waits until its stores have completed
+// (vmcnt 0), then after the barrier one thread makes them visible at agent
+// scope (one release fence, i.e. one L2 write-back, per event) and
+// publishes v
+__device__ __forceinline__ void pair_post(unsigned long long* ctr, unsigned long long v) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt left at their maxima
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(ctr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// all threads call: thread 0 polls (relaxed loads, no cache invalidation per
+// poll) until *ctr >= target (or *stop >= stop_at when stop is given), then
+// one acquire fence makes the partner's data visible; returns false on
+// timeout or stop, uniformly
+__device__ __forceinline__ bool pair_wait(const unsigned long long* ctr, unsigned long long target,
+                                          const unsigned long long* stop, int spin, DenseLds& s,
+                                          unsigned long long stop_at = 0) {
+  if (threadIdx.x == 0) {
+    int ok = 0;
+    for (int n = 0; n < spin; ++n) {
+      if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+        ok = 1;
+        break;
+      }
+      if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= stop_at) break;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s.flag = ok;
+  }
+  __syncthreads();
+  const bool ok = s.flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Blocked left-looking Cholesky as chol_dense, shared by the pair of
+// workgroups described above; f numbers the factorisation within the launch.
+// Returns the leader's positive-definiteness verdict (the follower's value is
+// meaningless); sets bail (and returns false) if a wait timed out.
+__device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int npad, double* __restrict__ winv,
+                                                DenseLds& s, const PairSync& ps, int f, bool& bail) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lm = lane & 15, lq = lane >> 4;
+  const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
+  const int P = npad / kNB;
+  const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  bool ok = true;
+  // the next group's H tile (transposed accumulator layout) and chunk 0 of
+  // its own rows, loaded while the current group finishes (its triangular
+  // solve, or for the diagonal group the write-back of L_JJ)
+  d4v acc_n[4], bop_n[4];
+  auto prefetch = [&](int J, int i0n) {
+    const int in = i0n + wave, col0 = kNB * J;
+    const bool act = in <= T16;
+    const double* Hr = H + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc_n[c][r] = act ? Hr[col0 + 16 * c + lq + 4 * r] : 0.0;
+    if (J > 0) {
+      const double* Ar = A + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        bop_n[kt] = act ? *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+    }
+  };
+  // this role's row groups of a panel: every other group of 4 row tiles,
+  // the leader's starting with the diagonal group
+  const int first = ps.role * kNW;
+  const unsigned long long fbase = ps.base + (unsigned long long)f * P;
+  prefetch(0, first);
+  for (int J = 0; J < P; ++J) {
+    const int col0 = kNB * J;
+    const int nchunk = J;             // k chunks of 64 columns
+    bool have_w = ps.role == 0;       // the leader factors the diagonal block itself
+    for (int i0 = 4 * J + first; i0 <= T16; i0 += 2 * kNW) {
+      const int i = i0 + wave;
+      const bool active = i <= T16;
+      const double* Arow = A + (size_t)(16 * i + lm) * npad;
+      const bool last_group = i0 + 2 * kNW > T16;
+      // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
+      d4v acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
+      if (nchunk > 0) {
+        d4v st[4], bop[4], bnx[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
+        __syncthreads();
+        for (int ch = 0; ch < nchunk; ++ch) {
+          const bool more = ch + 1 < nchunk;
+          if (more) {
+            const int k1 = kNB * (ch + 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + k1 + scol + 4 * q);
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt)
+              bnx[kt] = active ? *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+          }
+          const double* buf = s.stage[ch & 1];
+          if (active) {
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+              d4v aop[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
+            }
+          }
+          if (more) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<d4v*>(&s.stage[(ch + 1) & 1][srow * kSP + scol + 4 * q]) = st[q];
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) bop[kt] = bnx[kt];
+          }
+          __syncthreads();
+        }
+      }
+      if (i0 == 4 * J) {
+        // the diagonal block: factor in LDS
+        double* D = s.stage[0];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
+        __syncthreads();
+        if (!chol_block<4>(D, s.W, s)) ok = false;
+        if (!last_group) prefetch(J, i0 + 2 * kNW);
+        // write L_JJ (zero above the diagonal) and its inverse
+        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
+          const int r = e >> 6, c = e & 63;
+          A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
+          winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+        }
+        __syncthreads();
+        pair_post(ps.lead_diag, fbase + J + 1);
+      } else {
+        if (!have_w) {
+          // the follower takes L_JJ^-1 from the leader's write-back
+          if (!pair_wait(ps.lead_diag, fbase + J + 1, nullptr, ps.spin, s)) {
+            bail = true;
+            return false;
+          }
+          for (int e = threadIdx.x; e < kNB * kNB; e += kNT) s.W[(e >> 6) * kSP + (e & 63)] = winv[(size_t)J * kNB * kNB + e];
+          __syncthreads();
+          have_w = true;
+        }
+        // the next group's loads (H, and L of panels before J) overlap this
+        // group's triangular solve, which writes panel J only
+        if (!last_group) prefetch(J, i0 + 2 * kNW);
+        if (active) {
+          // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
+#pragma unroll
+          for (int cn = 0; cn < 4; ++cn) {
+            d4v out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kt = 0; kt <= cn; ++kt) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // both roles have written their tiles of panel J
+    pair_post(ps.panel[ps.role], fbase + J + 1);
+    if (!pair_wait(ps.panel[1 - ps.role], fbase + J + 1, nullptr, ps.spin, s)) {
+      bail = true;
+      return false;
+    }
+    if (J + 1 < P && 4 * (J + 1) + first <= T16) prefetch(J + 1, 4 * (J + 1) + first);
+  }
+  return ok;
+}
+
 // v[0:64] <- W v (lower = true) or W^T v (lower = false) for the 64x64
 // lower-triangular panel inverse W (global, row-major); all threads call,
 // 4 partial sums per output reduced through LDS.

@@ -62,6 +62,9 @@ struct DenseArgs {
   double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
   double* hvp;       // exact / unrolled backward: [cost][2][d] per-cost pose terms
   double* traj;      // DNLS_FLAG_KEEP_ITERATES: theta_t, t < K, [K][V][sz] in the factor cache
+  unsigned long long* pair_ctr;   // DNLS_FLAG_PAIR: 8 event counters per graph slot
+  unsigned long long pair_base;   // this launch's counter origin
+  int pair_spin;                  // poll limit of a pair wait
   int adaptive;      // DNLS_FLAG_ADAPTIVE_LM
   int dogleg;        // DNLS_FLAG_DOGLEG
   double radius0;    // dogleg: initial trust radius
@@ -304,7 +307,10 @@ struct KernelLds {
 // squares; GENERAL = true adds the run-time options that would otherwise push
 // the plain solve's registers into scratch: the dogleg (a.dogleg) and Welsch
 // edges (a.edge_logc).
-template <int G, bool MIXED, bool GENERAL>
+// PAIR: two co-resident workgroups per graph (blocks b and b + B of a
+// cooperative launch): the follower only takes its share of every
+// factorisation (chol_dense_pair), the leader runs everything else.
+template <int G, bool MIXED, bool GENERAL, bool PAIR = false>
 __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   if constexpr (!GENERAL) {
     a.edge_logc = nullptr;
@@ -313,11 +319,40 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
   extern __shared__ double dyn[];
   __shared__ KernelLds L;
-  const int b = a.order[blockIdx.x];
+  const int nslot = PAIR ? gridDim.x / 2 : gridDim.x;
+  const int slot = blockIdx.x % nslot;
+  const int b = a.order[slot];
   const GraphDesc g = a.gd[b];
   double* A = a.factor + g.fac_off;
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
   double* H = a.hbuf + g.h_off;    // assembled system (workspace), read by the factorisation
+  PairSync ps{};
+  bool timed_out = false;
+  if constexpr (PAIR) {
+    unsigned long long* c = a.pair_ctr + (size_t)slot * 8;
+    ps = PairSync{c, c + 1, c + 2, {c + 3, c + 4}, a.pair_base, (int)(blockIdx.x / nslot), a.pair_spin};
+    if (ps.role == 1) {
+      for (int f = 0; f <= a.K; ++f) {
+        if (!pair_wait(ps.lead_h, ps.base + f + 1, ps.lead_stop, ps.spin, L.dl, ps.base + 1)) return;
+        bool bail = false;
+        chol_dense_pair(A, H, g.npad, winv, L.dl, ps, f, bail);
+        if (bail) return;
+      }
+      return;
+    }
+  }
+  // factorisation number f of this launch (the step index; K for the final one)
+  auto factor = [&](int f) -> bool {
+    if constexpr (PAIR) {
+      pair_post(ps.lead_h, ps.base + f + 1);
+      bool bail = false;
+      const bool ok = chol_dense_pair(A, H, g.npad, winv, L.dl, ps, f, bail);
+      timed_out = timed_out || bail;
+      return ok && !bail;
+    } else {
+      return chol_dense(A, H, g.npad, winv, L.dl);
+    }
+  };
   double* vb = dyn;                // step
   double* vx = dyn + g.npad;       // refinement residual / matrix-free product
   double* vy = dyn + 2 * g.npad;   // right-hand side g
@@ -348,15 +383,12 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       status = DNLS_GRAPH_NONFINITE;
       break;
     }
+    double* haug = H + (size_t)g.npad * g.npad;  // right-hand side row of the system
+    double* aug = A + (size_t)g.npad * g.npad;   // ... and of the factor: y = L^-1 g
     if (final_lin) {
       // undamped factor of H* for the backward, assembled in float64
       assemble_H<G, double>(a, g, a.ws64, H, 0.0);
-      if (!chol_dense(A, H, g.npad, winv, L.dl)) status = DNLS_GRAPH_NOT_PD;
-      break;
-    }
-    double* haug = H + (size_t)g.npad * g.npad;  // right-hand side row of the system
-    double* aug = A + (size_t)g.npad * g.npad;   // ... and of the factor: y = L^-1 g
-    if (MIXED) {
+    } else if (MIXED) {
       assemble_H<G, float>(a, g, a.ws32, H, lam);
       if (a.refine > 0 || a.dogleg) assemble_g<G, double>(a, g, a.ws64, vy, haug);
       else assemble_g<G, float>(a, g, a.ws32, vy, haug);
@@ -364,10 +396,12 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       assemble_H<G, double>(a, g, a.ws64, H, lam);
       assemble_g<G, double>(a, g, a.ws64, vy, haug);
     }
-    if (!chol_dense(A, H, g.npad, winv, L.dl)) {
+    // one factorisation site per step (the fused kernel keeps one inlined copy)
+    if (!factor(it)) {
       status = DNLS_GRAPH_NOT_PD;
       break;
     }
+    if (final_lin) break;
     // delta = L^-T y with y = L^-1 g from the augmented row
     for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
     __syncthreads();
@@ -474,6 +508,10 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     for (int p = threadIdx.x; p < g.npose; p += kNT)
       retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, vb + p * d);
     __syncthreads();
+  }
+  if constexpr (PAIR) {
+    pair_post(ps.lead_stop, ps.base + 1);
+    if (timed_out) status = DNLS_GRAPH_TIMEOUT;
   }
   if (threadIdx.x == 0) {
     // a failed graph repeats its last objective for the steps that did not run
@@ -888,13 +926,39 @@ bool check_off(const int32_t* off, int B, int total_hint, int* total) {
   return true;
 }
 
+constexpr int kPairSpin = 1 << 24;   // polls of a pair wait (~1 s) before a graph is given up
+
+// Whether the pair kernel of this plan can be launched with every pair
+// co-resident: two workgroups per graph within what the device holds at once.
+template <int G, bool MIXED>
+bool pair_fits(dnls_plan p) {
+  int dev = 0, coop = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+  const size_t lds = 3 * (size_t)p->npad_max * sizeof(double);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_dense_solve<G, MIXED, false, true>),
+                                                   kNT, lds) != hipSuccess)
+    return false;
+  return (long long)per_cu * cus >= 2LL * p->B;
+}
+
 template <int G, bool MIXED>
 dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
   const size_t lds = 3 * (size_t)p->npad_max * sizeof(double);
-  if (a.dogleg || a.edge_logc)
+  if (a.dogleg || a.edge_logc) {
     hipLaunchKernelGGL((k_dense_solve<G, MIXED, true>), dim3(p->B), dim3(kNT), lds, st, a);
-  else
+  } else if ((p->opt.flags & DNLS_FLAG_PAIR) && p->pair_ok) {
+    DenseArgs ap = a;
+    ap.pair_ctr = p->d_pair;
+    ap.pair_base = (++p->pair_epoch) << 20;   // counters only grow: no reset between launches
+    ap.pair_spin = kPairSpin;
+    void* args[] = {&ap};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_dense_solve<G, MIXED, false, true>),
+                                       dim3(2 * p->B), dim3(kNT), args, (unsigned)lds, st));
+  } else {
     hipLaunchKernelGGL((k_dense_solve<G, MIXED, false>), dim3(p->B), dim3(kNT), lds, st, a);
+  }
   HIP_TRY(hipGetLastError());
   return DNLS_OK;
 }
@@ -949,7 +1013,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
-  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES))
+  if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES |
+                           DNLS_FLAG_PAIR))
     return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
   if (op->flags & DNLS_FLAG_KEEP_ITERATES) {
     if (op->solver != DNLS_SOLVER_DENSE)
@@ -1120,7 +1185,31 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   p->traj_off = fac;   // doubles
   if (op->flags & DNLS_FLAG_KEEP_ITERATES) fac += (long long)op->iterations * V * p->sz;
   p->fac_bytes = (size_t)fac * sizeof(double);
+  if (op->flags & DNLS_FLAG_PAIR) {
+    const bool mixed = op->precision == DNLS_PREC_MIXED;
+    p->pair_ok = p->group == DNLS_SE3 ? (mixed ? pair_fits<3, true>(p) : pair_fits<3, false>(p))
+                                      : (mixed ? pair_fits<2, true>(p) : pair_fits<2, false>(p));
+    if (p->pair_ok) {
+      const size_t bytes = (size_t)p->B * 8 * sizeof(unsigned long long);
+      if (hipMalloc(reinterpret_cast<void**>(&p->d_pair), bytes) != hipSuccess ||
+          (p->allocs.push_back(p->d_pair), hipMemset(p->d_pair, 0, bytes)) != hipSuccess) {
+        dnls_plan_destroy(p);
+        return fail(DNLS_ERR_HIP, "allocating the pair counters failed");
+      }
+    }
+  }
   *out = p;
+  return DNLS_OK;
+}
+
+dnls_status dnls_plan_schedule(dnls_plan p, int32_t* dense_pair, int32_t* sparse_solve) {
+  if (!p) return fail(DNLS_ERR_INVALID_ARG, "null plan");
+  if (dense_pair) *dense_pair = (p->opt.solver == DNLS_SOLVER_DENSE && (p->opt.flags & DNLS_FLAG_PAIR) && p->pair_ok) ? 1 : 0;
+  if (sparse_solve) {
+    *sparse_solve = DNLS_SPSOLVE_AUTO;
+    if (p->opt.solver == DNLS_SOLVER_SPARSE)
+      *sparse_solve = p->sp_factor_wg ? DNLS_SPSOLVE_WORKGROUP : (p->sp_solve_wg ? DNLS_SPSOLVE_HYBRID : DNLS_SPSOLVE_SWEEPS);
+  }
   return DNLS_OK;
 }
 

@@ -72,7 +72,11 @@ struct dnls_plan_s {
   size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
   double flops_alg = 0.0, flops_exec = 0.0;   // one numeric factorisation over the batch
   size_t ws32_off = 0, ycost_off = 0, h_off = 0, bak_off = 0, dlmw_off = 0, hvp_off = 0;
-  long long traj_off = 0;   // doubles into the factor cache: kept iterates (DNLS_FLAG_KEEP_ITERATES)   // byte offsets inside the solve workspace
+  long long traj_off = 0;   // doubles into the factor cache: kept iterates (DNLS_FLAG_KEEP_ITERATES)
+  // DNLS_FLAG_PAIR: whether the pair kernel fits, its counters and launch epoch
+  bool pair_ok = false;
+  unsigned long long* d_pair = nullptr;
+  unsigned long long pair_epoch = 0;   // byte offsets inside the solve workspace
   // device tables of the dense path
   dnls::GraphDesc* d_gd = nullptr;
   int* d_order = nullptr;

@@ -25,4 +25,5 @@ def test_cache_round_trip(tmp_path):
     assert A._load(path) == {}
     A._store(path, {"k": {"solver": "sparse", "ms": 1.5}})
     assert A._load(path) == {"k": {"solver": "sparse", "ms": 1.5}}
-    assert [c["solver"] for c in A.CANDIDATES].count("dense") == 1
+    dense = [c for c in A.CANDIDATES if c["solver"] == "dense"]
+    assert len(dense) == 2 and sorted(c.get("pair", False) for c in dense) == [False, True]

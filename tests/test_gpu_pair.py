@@ -1,0 +1,97 @@
+"""GPU parity of the two-workgroups-per-graph dense schedule
+(DNLS_FLAG_PAIR: a co-resident pair of workgroups shares every
+factorisation, synchronised through device-memory event counters) against
+the oracle and against the one-workgroup kernel, through the C ABI: the
+full 128-graph workload (where the pair fits), ragged batches with weights
+and tangents, mixed precision, adaptive damping, failed graphs, and the
+implicit backward on the factor the pair wrote."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import solve as S
+
+from gpu_util import oracle_grads, oracle_solve, rel, t
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(7070)
+
+
+def _solve(p, K, lam, pair, precision="fp64", refine=0, tau=None, adaptive=False):
+    from paper_2207_09442_amd import Plan
+    plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device="cuda", adaptive=adaptive, pair=pair)
+    poses = t(p["poses_init"])
+    aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
+    tau_d = None if tau is None else t(tau)
+    obj, st = plan.solve(poses, *aux, edge_tau=tau_d)
+    torch.cuda.synchronize()
+    return plan, poses, obj, st, aux, tau_d
+
+
+def _check(p, K, lam, graphs=None, tol=1e-10, precision="fp64", refine=0, tau=None, adaptive=False):
+    plan, poses, obj, st, aux, tau_d = _solve(p, K, lam, True, precision, refine, tau, adaptive)
+    assert plan.schedule()["pair"]          # every batch here leaves room for two workgroups per graph
+    _, poses1, obj1, st1, _, _ = _solve(p, K, lam, False, precision, refine, tau, adaptive)
+    got = poses.cpu().numpy()
+    # same algorithm on two schedules: equal up to the rounding of the split factorisation
+    assert np.array_equal(st.cpu().numpy(), st1.cpu().numpy())
+    assert rel(got, poses1.cpu().numpy()) < 1e-12
+    B = len(p["pose_off"]) - 1
+    graphs = list(range(B)) if graphs is None else graphs
+    gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs, adaptive=adaptive)
+    seeds = [rng.normal(size=(int(p["pose_off"][b + 1] - p["pose_off"][b]), 6)) for b in graphs]
+    full = np.zeros((int(p["pose_off"][-1]), 6))
+    for gi, b in enumerate(graphs):
+        full[p["pose_off"][b]:p["pose_off"][b + 1]] = seeds[gi]
+    gr = plan.backward(poses, *aux, st, t(full), edge_tau=tau_d)
+    gr = {k: v.cpu().numpy() for k, v in gr.items()}
+    ref = oracle_grads(gs, res, seeds)
+    ob = obj.cpu().numpy()
+    for gi, b in enumerate(graphs):
+        lo, hi = int(p["pose_off"][b]), int(p["pose_off"][b + 1])
+        e0, e1 = int(p["edge_off"][b]), int(p["edge_off"][b + 1])
+        assert st[b] == res[gi].status == S.OK
+        assert rel(got[lo:hi], gs[gi].G.to_storage(res[gi].X).numpy()) < tol
+        assert rel(ob[b], np.asarray(res[gi].objective)) < max(tol, 1e-12) * (1e3 if precision == "mixed" else 1)
+        mine = np.concatenate([gr["edge_logw"][e0:e1], gr["edge_tau"][e0:e1].ravel()])
+        theirs = np.concatenate([ref[gi]["edge_logw"], ref[gi]["tau"].ravel()])
+        ev = np.linalg.eigvalsh(res[gi].lin.H.numpy())
+        assert rel(mine, theirs) < max(tol, 0.5 * (ev[-1] / ev[0]) * np.finfo(np.float64).eps)
+
+
+def test_pair_walk64_b128_fp64_and_mixed():
+    p = synth.walk_se3(batch=128)
+    _check(p, 10, 1e-3, graphs=[0, 37, 81, 127])
+    _check(p, 10, 1e-3, graphs=[0, 127], precision="mixed", refine=1, tol=1e-5)
+
+
+def test_pair_ragged_with_weights_and_tau():
+    p = synth.uneven_walk_se3(batch=6, n_min=3, n_max=60, seed=71)
+    p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
+    tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), 6))
+    _check(p, 6, 1e-3, tau=tau)
+
+
+def test_pair_adaptive():
+    p = synth.walk_se3(batch=4, n_poses=20, n_loops=12, seed=72)
+    _check(p, 8, 1e-2, adaptive=True)
+
+
+def test_pair_failed_graphs_are_frozen():
+    p = synth.walk_se3(batch=3, n_poses=8, n_loops=4, seed=17)
+    last = int(p["pose_off"][1]) + 7
+    keep = ~((p["edge_ij"][:, 0] == last) | (p["edge_ij"][:, 1] == last))
+    counts = [int(keep[p["edge_off"][b]:p["edge_off"][b + 1]].sum()) for b in range(3)]
+    p["edge_ij"], p["edge_meas"], p["edge_logw"] = p["edge_ij"][keep], p["edge_meas"][keep], p["edge_logw"][keep]
+    p["edge_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    p["edge_meas"] = p["edge_meas"].copy()
+    p["edge_meas"][p["edge_off"][2] + 1, 0, 3] = np.nan
+    _, poses, obj, st, _, _ = _solve(p, 5, 0.0, True)
+    assert st.cpu().tolist() == [0, 1, 2]
+    got = poses.cpu().numpy()
+    for b in (1, 2):
+        lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
+        assert np.array_equal(got[lo:hi], p["poses_init"][lo:hi])
