@@ -171,6 +171,9 @@ def main():
                     choices=["se2_circle_b1", "se3_walk64_b128", "se3_lattice16_b8", "se3_uneven_b256",
                              "ba_ring64_b4"])
     ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
+    ap.add_argument("--refine-last", type=int, default=0,
+                    help="mixed path: refinement sweeps in the last N steps only (N < 0: the first -N "
+                         "steps; 0 = every step, the default, the one that holds 1e-5 on the gradients)")
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
@@ -241,7 +244,8 @@ def main():
         progress(f"autotuned schedule: {solver} {schedule} ({best['ms']:.3f} ms)")
 
     def run(precision: str, refine: int):
-        plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=dev, **schedule)
+        plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=dev,
+                    refine_last=args.refine_last if precision == "mixed" else 0, **schedule)
         poses = init.clone()
         pts = pts_init.clone() if ba else None
 
@@ -323,7 +327,8 @@ def main():
               if single_kernel else "solve (all kernels of dnls_solve)")
     cfg = {"workload": args.workload, "batch": B, "iterations": K,
            "optimizer": W["optimizer"], "lambda": lam, "precision": main_prec,
-           "refine": args.refine if main_prec == "mixed" else 0, "solver": solver,
+           "refine": args.refine if main_prec == "mixed" else 0,
+           "refine_last": args.refine_last if main_prec == "mixed" else 0, "solver": solver,
            "schedule": dict(schedule, autotuned=bool(args.autotune and not ba)),
            "backward": {"implicit": "implicit", "dlm": f"dlm (eps={args.dlm_eps:g})",
                         "exact": f"exact Hessian ({args.sweeps} sweeps)",

@@ -178,6 +178,14 @@ typedef struct {
   int32_t sparse_solve;       /* dnls_sparse_solve (SPARSE only) */
   int32_t flags;              /* DNLS_FLAG_* */
   double trust_radius;        /* DNLS_FLAG_DOGLEG: initial trust radius (> 0) */
+  int32_t refine_last;        /* MIXED: run the refinement sweeps in the last
+                                 refine_last steps only (negative: the first
+                                 -refine_last steps; 0 = every step, the
+                                 default); the other steps use the float32
+                                 step.  Faster, but the float32 steps move
+                                 the trajectory (~1e-6 relative after 10 LM
+                                 steps of the 64-pose walks, gradients
+                                 ~1e-5).  In -iterations..iterations. */
 } dnls_options;
 
 /* Arguments of dnls_solve (device pointers unless stated). */

@@ -55,7 +55,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("sparse_solve", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("trust_radius", ctypes.c_double)]
+                ("trust_radius", ctypes.c_double), ("refine_last", ctypes.c_int32)]
 
 
 class _SolveArgs(ctypes.Structure):
@@ -138,10 +138,12 @@ class Plan:
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
                  graph: bool = False, adaptive: bool = False, dogleg: float | None = None,
-                 keep_iterates: bool = False, pair: bool = False):
+                 keep_iterates: bool = False, pair: bool = False, refine_last: int = 0):
         """dogleg: initial trust radius of Powell's dogleg (dense solver), or None;
         keep_iterates: store theta_0 .. theta_{K-1} for the unrolled backward;
-        pair: dense solver, two co-resident workgroups per graph when they fit."""
+        pair: dense solver, two co-resident workgroups per graph when they fit;
+        refine_last: mixed precision, refinement sweeps in the last steps only
+        (negative: the first steps; 0 = all)."""
         import torch
         self.group = problem["group"]
         self.dof = 6 if self.group == "SE3" else 3
@@ -177,10 +179,10 @@ class Plan:
                       (FLAG_GRAPH if graph else 0) | (FLAG_ADAPTIVE_LM if adaptive else 0)
                       | (FLAG_DOGLEG if dogleg is not None else 0) | (FLAG_KEEP_ITERATES if keep_iterates else 0)
                       | (FLAG_PAIR if pair else 0),
-                      float(dogleg) if dogleg is not None else 0.0)
+                      float(dogleg) if dogleg is not None else 0.0, int(refine_last))
         self.config = dict(solver=solver, precision=precision, refine=int(refine), lam=float(lam),
                            sparse_solve=sparse_solve, graph=bool(graph), adaptive=bool(adaptive), dogleg=dogleg,
-                           keep_iterates=bool(keep_iterates), pair=bool(pair))
+                           keep_iterates=bool(keep_iterates), pair=bool(pair), refine_last=int(refine_last))
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h

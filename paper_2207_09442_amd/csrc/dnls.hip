@@ -78,6 +78,8 @@ struct DenseArgs {
   int V;             // total poses
   int K;
   int refine;
+  int refine_from;   // mixed: steps refine_from <= it < refine_until run the refinement sweeps
+  int refine_until;
   double lambda;
 };
 
@@ -373,7 +375,8 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // the mixed path linearises in float32 inside the loop; the float64
     // linearisation feeds its refinement sweeps and the final (cached) factor
     const bool lin32 = MIXED && !final_lin;
-    const bool lin64 = !MIXED || a.refine > 0 || final_lin || a.dogleg;
+    const bool refine_now = MIXED && !final_lin && a.refine > 0 && it >= a.refine_from && it < a.refine_until;
+    const bool lin64 = !MIXED || refine_now || final_lin || a.dogleg;
     if (lin32) S = linearize_graph<G, float>(a, g, a.ws32, L.red);
     if (lin64) S = linearize_graph<G, double>(a, g, a.ws64, L.red);
     last_obj = S;
@@ -390,7 +393,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       assemble_H<G, double>(a, g, a.ws64, H, 0.0);
     } else if (MIXED) {
       assemble_H<G, float>(a, g, a.ws32, H, lam);
-      if (a.refine > 0 || a.dogleg) assemble_g<G, double>(a, g, a.ws64, vy, haug);
+      if (refine_now || a.dogleg) assemble_g<G, double>(a, g, a.ws64, vy, haug);
       else assemble_g<G, float>(a, g, a.ws32, vy, haug);
     } else {
       assemble_H<G, double>(a, g, a.ws64, H, lam);
@@ -407,7 +410,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     __syncthreads();
     trsv_upper_t(A, g.npad, winv, vb, L.dl);
     if (MIXED) {
-      for (int sweep = 0; sweep < a.refine; ++sweep) {
+      for (int sweep = 0; sweep < (refine_now ? a.refine : 0); ++sweep) {
         // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
         matvec_H<G>(a, g, a.ws64, vb, vx, lam);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
@@ -488,7 +491,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     if (a.adaptive) {
       // adaptive damping: keep the step iff the float64 objective strictly
       // decreases (lambda / 10), else restore theta_t (lambda x 10)
-      const double s_t = (MIXED && a.refine == 0) ? objective_graph<G>(a, g, L.red) : S;
+      const double s_t = lin64 ? S : objective_graph<G>(a, g, L.red);
       double* bak = a.pose_bak + (size_t)g.pose0 * sz;
       for (int u = threadIdx.x; u < g.npose * sz; u += kNT) bak[u] = a.poses[(size_t)g.pose0 * sz + u];
       for (int p = threadIdx.x; p < g.npose; p += kNT)
@@ -1011,6 +1014,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->precision != DNLS_PREC_FP64 && op->precision != DNLS_PREC_MIXED)
     return fail(DNLS_ERR_INVALID_ARG, "unknown precision");
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
+  if (op->refine_last < -op->iterations || op->refine_last > op->iterations)
+    return fail(DNLS_ERR_INVALID_ARG, "refine_last must be in 0..iterations");
   if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
   if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES |
@@ -1242,6 +1247,8 @@ static DenseArgs base_args(dnls_plan p) {
   a.V = p->V;
   a.K = p->opt.iterations;
   a.refine = p->opt.precision == DNLS_PREC_MIXED ? p->opt.refine : 0;
+  a.refine_from = p->opt.refine_last > 0 ? p->opt.iterations - p->opt.refine_last : 0;
+  a.refine_until = p->opt.refine_last < 0 ? -p->opt.refine_last : p->opt.iterations;
   a.lambda = p->opt.lambda;
   return a;
 }

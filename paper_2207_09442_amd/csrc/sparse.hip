@@ -1179,7 +1179,9 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     const int lam_g = (adaptive && !final_lin) ? 1 : 0;
     a.it = it;
     const bool lin32 = mixed && !final_lin;
-    const bool lin64 = !mixed || a.refine > 0 || final_lin;
+    const bool refine_now = lin32 && a.refine > 0 &&
+                            (p->opt.refine_last == 0 || it >= p->opt.iterations - p->opt.refine_last);
+    const bool lin64 = !mixed || refine_now || final_lin;
     if (lin32) hipLaunchKernelGGL((k_sp_lin<G, float>), g_cost, dim3(kBT), 0, st, a, a.ws32);
     if (lin64) hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
     hipLaunchKernelGGL(k_sp_objective, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
@@ -1191,8 +1193,8 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
     if (lin32) {
       hipLaunchKernelGGL((k_sp_assemble<G, float>), g_blk, dim3(kBT), 0, st, a, (const float*)a.ws32, lam,
-                         a.refine > 0 ? 0 : 1, lam_g);
-      if (a.refine > 0) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
+                         refine_now ? 0 : 1, lam_g);
+      if (refine_now) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
     } else {
       hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, lam, 1,
                          lam_g);
@@ -1200,7 +1202,7 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     sp_factor<G>(p, a, st);
     if (final_lin) break;
     if (lam_g) hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, a, sz);
-    const bool refine = lin32 && a.refine > 0;
+    const bool refine = refine_now;
     hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 1, 2);
     sp_sweeps(p, a, 0, st);
     if (!refine) hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, a, 0);
