@@ -163,9 +163,11 @@ enum {
    * graph on a pair of co-resident workgroups (cooperative launch) that
    * share every factorisation, for batches too small to fill the device;
    * otherwise (or with DNLS_FLAG_DOGLEG or Welsch edges) the one-workgroup
-   * kernel runs.  Results equal the one-workgroup path's up to rounding.
-   * The plan holds event counters: calls with this flag must not overlap on
-   * one plan. */
+   * kernel runs.  SCHUR (without DNLS_FLAG_GRAPH): four co-resident
+   * workgroups per problem share the camera-system factorisation when they
+   * fit.  Results equal the one-workgroup path's up to rounding.  The plan
+   * holds event counters: calls with this flag must not overlap on one
+   * plan. */
   DNLS_FLAG_PAIR = 16
 };
 
@@ -303,8 +305,9 @@ dnls_status dnls_plan_workspace(dnls_plan plan, size_t* solve_ws, size_t* factor
 dnls_status dnls_plan_flops(dnls_plan plan, double* algorithmic, double* executed);
 
 /* The schedule a plan resolved at creation (host values, either pointer may
- * be NULL): dense_pair = 1 if dnls_solve runs each graph on a co-resident
- * pair of workgroups (DNLS_FLAG_PAIR requested and the pair fits), else 0;
+ * be NULL): dense_pair = 1 if dnls_solve shares each factorisation among
+ * co-resident workgroups (DNLS_FLAG_PAIR requested and they fit: a pair per
+ * graph for DENSE, four per problem for SCHUR), else 0;
  * sparse_solve = the dnls_sparse_solve that AUTO resolved to (SPARSE), else
  * DNLS_SPSOLVE_AUTO. */
 dnls_status dnls_plan_schedule(dnls_plan plan, int32_t* dense_pair, int32_t* sparse_solve);

@@ -36,6 +36,8 @@ namespace dnls {
 namespace {
 
 constexpr int kBT = 256;
+constexpr int kBaNway = 4;          // DNLS_FLAG_PAIR: workgroups per problem sharing the camera factorisation
+constexpr int kBaPairSpin = 1 << 24;
 constexpr int kObsRec = 20;   // J~cam (2x6), J~pt (2x3), r~ (2)
 constexpr int kPriorRec = 42; // w C (6x6), w c (6)
 
@@ -72,6 +74,10 @@ struct BAArgs {
   double* factor;
   int K, it, npad_max, nx_lin;
   double lambda;
+  // DNLS_FLAG_PAIR: nway co-resident workgroups per problem share the factorisation
+  unsigned long long* pair_ctr;
+  unsigned long long pair_base;
+  int pair_spin, nway;
   // backward
   const double* seed_c;
   const double* seed_p;
@@ -389,10 +395,16 @@ struct BALds {
 };
 
 // 4. objective, factorisation and camera step (one workgroup per problem)
+// MULTI: a cooperative launch of nway workgroups per problem (blocks b,
+// b + B, ...): all of them take part in the factorisation (chol_dense_pair),
+// the leader (role 0) does the rest.
+template <bool MULTI>
 __global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
   extern __shared__ double dyn[];
   __shared__ BALds L;
-  const int b = blockIdx.x;
+  const int nslot = MULTI ? gridDim.x / a.nway : gridDim.x;
+  const int b = blockIdx.x % nslot;
+  const int role = blockIdx.x / nslot;
   const BADesc g = a.bd[b];
   double* obj = a.objective + (size_t)b * (a.K + 1);
   if (a.frozen[b]) {
@@ -401,12 +413,12 @@ __global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
   }
   double S = 0.0;
   for (int k = 0; k < a.nx_lin; ++k) S += a.partial[b * a.nx_lin + k];
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && role == 0) {
     obj[a.it] = S;
     a.lastobj[b] = S;
   }
   if (!isfinite(S)) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && role == 0) {
       a.frozen[b] = DNLS_GRAPH_NONFINITE;
       a.status[b] = DNLS_GRAPH_NONFINITE;
     }
@@ -414,7 +426,23 @@ __global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
   }
   double* A = a.factor + g.fac_off;
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
-  const bool ok = chol_dense(A, A, g.npad, winv, L.dl);
+  bool ok;
+  if constexpr (MULTI) {
+    unsigned long long* c = a.pair_ctr + (size_t)b * 8;
+    const PairSync ps{nullptr, nullptr, c + 2, c + 3, a.pair_base, role, a.nway, a.pair_spin};
+    bool bail = false;
+    ok = chol_dense_pair(A, A, g.npad, winv, L.dl, ps, 0, bail);
+    if (role != 0) return;
+    if (bail) {
+      if (threadIdx.x == 0) {
+        a.frozen[b] = DNLS_GRAPH_TIMEOUT;
+        a.status[b] = DNLS_GRAPH_TIMEOUT;
+      }
+      return;
+    }
+  } else {
+    ok = chol_dense(A, A, g.npad, winv, L.dl);
+  }
   if (!ok) {
     if (threadIdx.x == 0) {
       a.frozen[b] = DNLS_GRAPH_NOT_PD;
@@ -742,7 +770,26 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   p->ba_fac_off[2] = fb; fb += align256((size_t)Vp * 9 * sizeof(double));
   p->ba_fac_off[3] = fb; fb += align256((size_t)Vp * 3 * sizeof(double));
   p->fac_bytes = fb;
-  (void)op;
+  // DNLS_FLAG_PAIR (not with HIP-graph capture, whose replays would reuse the
+  // counter origin): four workgroups per problem share the camera-system
+  // factorisation when they fit on the device at once
+  p->ba_nway = 1;
+  if ((op->flags & DNLS_FLAG_PAIR) && !(op->flags & DNLS_FLAG_GRAPH)) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    const size_t lds = (size_t)p->npad_max * sizeof(double);
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ba_factor<true>), kNT,
+                                                     lds) == hipSuccess &&
+        (long long)per_cu * cus >= (long long)kBaNway * B) {
+      const size_t bytes = (size_t)B * 8 * sizeof(unsigned long long);
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&p->d_pair), bytes));
+      p->allocs.push_back(p->d_pair);
+      HIP_TRY(hipMemset(p->d_pair, 0, bytes));
+      p->ba_nway = kBaNway;
+    }
+  }
   return DNLS_OK;
 }
 
@@ -802,7 +849,19 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
       hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, lam);
       hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, lam);
     }
-    hipLaunchKernelGGL(k_ba_factor, dim3(B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
+    if (p->ba_nway > 1) {
+      BAArgs am = a;
+      am.pair_ctr = p->d_pair;
+      am.pair_base = (++p->pair_epoch) << 20;
+      am.pair_spin = kBaPairSpin;
+      am.nway = p->ba_nway;
+      int fl = final_lin ? 1 : 0;
+      void* args[] = {&am, &fl};
+      HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_ba_factor<true>), dim3(p->ba_nway * B),
+                                         dim3(kNT), args, (unsigned)lds, st));
+    } else {
+      hipLaunchKernelGGL(k_ba_factor<false>, dim3(B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
+    }
     if (!final_lin) hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
   }
   HIP_TRY(hipGetLastError());

@@ -353,9 +353,10 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
 }
 
 // ---------------------------------------------------------------------------
-// Two workgroups per graph: the pair shares one factorisation, each taking
-// every other group of row tiles of a panel (the leader, role 0, starts with
-// the diagonal group), with three kinds of events posted through monotone
+// Several workgroups per graph (a pair for the pose-graph solve, four for the
+// bundle-adjustment camera system) share one factorisation, each taking every
+// nway-th group of row tiles of a panel (the leader, role 0, starts with the
+// diagonal group), with three kinds of events posted through monotone
 // 64-bit counters in device memory (agent-scope release / acquire): the
 // leader's diagonal block of panel J written (the follower then reads
 // L_JJ^-1 from the factor cache), and each role's end of panel J (both wait
@@ -368,9 +369,10 @@ struct PairSync {
   unsigned long long* lead_h;     // leader: the system of factorisation f is assembled (base + f + 1)
   unsigned long long* lead_stop;  // leader: left its loop (base + 1)
   unsigned long long* lead_diag;  // leader: diagonal block J of factorisation f written (base + f P + J + 1)
-  unsigned long long* panel[2];   // role r: panel J of factorisation f finished (base + f P + J + 1)
+  unsigned long long* panel;      // [nway] role r: panel J of factorisation f finished (base + f P + J + 1)
   unsigned long long base;        // this launch's origin of the counters
-  int role;
+  int role;                       // 0 = leader
+  int nway;                       // workgroups sharing the factorisation (2 for the pair)
   int spin;                       // poll limit of a wait
 };
 
@@ -444,20 +446,20 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         bop_n[kt] = act ? *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
     }
   };
-  // this role's row groups of a panel: every other group of 4 row tiles,
+  // this role's row groups of a panel: every nway-th group of 4 row tiles,
   // the leader's starting with the diagonal group
-  const int first = ps.role * kNW;
+  const int first = ps.role * kNW, stride = ps.nway * kNW;
   const unsigned long long fbase = ps.base + (unsigned long long)f * P;
   prefetch(0, first);
   for (int J = 0; J < P; ++J) {
     const int col0 = kNB * J;
     const int nchunk = J;             // k chunks of 64 columns
     bool have_w = ps.role == 0;       // the leader factors the diagonal block itself
-    for (int i0 = 4 * J + first; i0 <= T16; i0 += 2 * kNW) {
+    for (int i0 = 4 * J + first; i0 <= T16; i0 += stride) {
       const int i = i0 + wave;
       const bool active = i <= T16;
       const double* Arow = A + (size_t)(16 * i + lm) * npad;
-      const bool last_group = i0 + 2 * kNW > T16;
+      const bool last_group = i0 + stride > T16;
       // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
       d4v acc[4];
 #pragma unroll
@@ -514,7 +516,7 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
           for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
         __syncthreads();
         if (!chol_block<4>(D, s.W, s)) ok = false;
-        if (!last_group) prefetch(J, i0 + 2 * kNW);
+        if (!last_group) prefetch(J, i0 + stride);
         // write L_JJ (zero above the diagonal) and its inverse
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
@@ -536,7 +538,7 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         }
         // the next group's loads (H, and L of panels before J) overlap this
         // group's triangular solve, which writes panel J only
-        if (!last_group) prefetch(J, i0 + 2 * kNW);
+        if (!last_group) prefetch(J, i0 + stride);
         if (active) {
           // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
@@ -554,12 +556,13 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
       }
     }
     __syncthreads();
-    // both roles have written their tiles of panel J
-    pair_post(ps.panel[ps.role], fbase + J + 1);
-    if (!pair_wait(ps.panel[1 - ps.role], fbase + J + 1, nullptr, ps.spin, s)) {
-      bail = true;
-      return false;
-    }
+    // every role has written its tiles of panel J
+    pair_post(ps.panel + ps.role, fbase + J + 1);
+    for (int r = 0; r < ps.nway; ++r)
+      if (r != ps.role && !pair_wait(ps.panel + r, fbase + J + 1, nullptr, ps.spin, s)) {
+        bail = true;
+        return false;
+      }
     if (J + 1 < P && 4 * (J + 1) + first <= T16) prefetch(J + 1, 4 * (J + 1) + first);
   }
   return ok;

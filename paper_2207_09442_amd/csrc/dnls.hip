@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   bool timed_out = false;
   if constexpr (PAIR) {
     unsigned long long* c = a.pair_ctr + (size_t)slot * 8;
-    ps = PairSync{c, c + 1, c + 2, {c + 3, c + 4}, a.pair_base, (int)(blockIdx.x / nslot), a.pair_spin};
+    ps = PairSync{c, c + 1, c + 2, c + 3, a.pair_base, (int)(blockIdx.x / nslot), 2, a.pair_spin};
     if (ps.role == 1) {
       for (int f = 0; f <= a.K; ++f) {
         if (!pair_wait(ps.lead_h, ps.base + f + 1, ps.lead_stop, ps.spin, L.dl, ps.base + 1)) return;
@@ -1209,7 +1209,9 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
 
 dnls_status dnls_plan_schedule(dnls_plan p, int32_t* dense_pair, int32_t* sparse_solve) {
   if (!p) return fail(DNLS_ERR_INVALID_ARG, "null plan");
-  if (dense_pair) *dense_pair = (p->opt.solver == DNLS_SOLVER_DENSE && (p->opt.flags & DNLS_FLAG_PAIR) && p->pair_ok) ? 1 : 0;
+  if (dense_pair)
+    *dense_pair = ((p->opt.solver == DNLS_SOLVER_DENSE && (p->opt.flags & DNLS_FLAG_PAIR) && p->pair_ok) ||
+                   (p->opt.solver == DNLS_SOLVER_SCHUR && p->ba_nway > 1)) ? 1 : 0;
   if (sparse_solve) {
     *sparse_solve = DNLS_SPSOLVE_AUTO;
     if (p->opt.solver == DNLS_SOLVER_SPARSE)

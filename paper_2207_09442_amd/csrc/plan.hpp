@@ -75,6 +75,7 @@ struct dnls_plan_s {
   long long traj_off = 0;   // doubles into the factor cache: kept iterates (DNLS_FLAG_KEEP_ITERATES)
   // DNLS_FLAG_PAIR: whether the pair kernel fits, its counters and launch epoch
   bool pair_ok = false;
+  int ba_nway = 1;            // SCHUR: workgroups per problem in the factorisation
   unsigned long long* d_pair = nullptr;
   unsigned long long pair_epoch = 0;   // byte offsets inside the solve workspace
   // device tables of the dense path

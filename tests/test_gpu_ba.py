@@ -17,9 +17,10 @@ pytestmark = pytest.mark.gpu
 rng = np.random.default_rng(5)
 
 
-def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True):
+def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False):
     from paper_2207_09442_amd import Plan
-    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device)
+    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device, pair=pair)
+    assert plan.schedule()["pair"] == pair
     cams, pts = t(p["poses_init"]), t(p["points_init"])
     dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
                prior_logw=t(p["prior_logw"]))
@@ -67,10 +68,13 @@ def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True
     return worst
 
 
-def test_ba_small_fp64():
+@pytest.mark.parametrize("pair", [False, True])
+def test_ba_small_fp64(pair):
+    """pair: four workgroups per problem share the factorisation (one panel
+    here, so two of them have no row group and only join the barrier)."""
     p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=60, obs_per_point=4, seed=1)
     p["obs_w"] = np.exp(rng.normal(scale=0.2, size=len(p["obs_w"])))
-    _run(p, 5, 1e-3)
+    _run(p, 5, 1e-3, pair=pair)
 
 
 def test_ba_uneven_problems_fp64():
@@ -92,8 +96,11 @@ def test_ba_uneven_problems_fp64():
     _run(p, 4, 1e-3)
 
 
-def test_ba_ring64_full_size_fp64_and_mixed():
-    """4 problems x (64 cameras, 2048 points, 16384 observations), 10 LM steps."""
+@pytest.mark.parametrize("pair", [False, True])
+def test_ba_ring64_full_size_fp64_and_mixed(pair):
+    """4 problems x (64 cameras, 2048 points, 16384 observations), 10 LM
+    steps; pair: the 384 x 384 camera systems factored by four workgroups
+    each."""
     p = synth.bundle_adjustment(batch=4)
-    _run(p, 10, 1e-3, problems=[0, 3])
-    _run(p, 10, 1e-3, precision="mixed", problems=[0, 3], tol=1e-5)
+    _run(p, 10, 1e-3, problems=[0, 3], pair=pair)
+    _run(p, 10, 1e-3, precision="mixed", problems=[0, 3], tol=1e-5, pair=pair)
