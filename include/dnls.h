@@ -167,7 +167,10 @@ enum {
    * workgroups per problem share the camera-system factorisation when they
    * fit.  Results equal the one-workgroup path's up to rounding.  The plan
    * holds event counters: calls with this flag must not overlap on one
-   * plan. */
+   * plan.  A wait between the workgroups gives up after a poll limit
+   * (about a second; the environment variable DNLS_PAIR_SPIN, read at plan
+   * creation, sets another count): the graph then gets DNLS_GRAPH_TIMEOUT
+   * and undefined poses, and every workgroup exits. */
   DNLS_FLAG_PAIR = 16
 };
 

@@ -37,7 +37,6 @@ namespace {
 
 constexpr int kBT = 256;
 constexpr int kBaNway = 4;          // DNLS_FLAG_PAIR: workgroups per problem sharing the camera factorisation
-constexpr int kBaPairSpin = 1 << 24;
 constexpr int kObsRec = 20;   // J~cam (2x6), J~pt (2x3), r~ (2)
 constexpr int kPriorRec = 42; // w C (6x6), w c (6)
 
@@ -774,6 +773,7 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   // counter origin): four workgroups per problem share the camera-system
   // factorisation when they fit on the device at once
   p->ba_nway = 1;
+  p->pair_spin = pair_spin_limit();
   if ((op->flags & DNLS_FLAG_PAIR) && !(op->flags & DNLS_FLAG_GRAPH)) {
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
     const size_t lds = (size_t)p->npad_max * sizeof(double);
@@ -853,7 +853,7 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
       BAArgs am = a;
       am.pair_ctr = p->d_pair;
       am.pair_base = (++p->pair_epoch) << 20;
-      am.pair_spin = kBaPairSpin;
+      am.pair_spin = p->pair_spin;
       am.nway = p->ba_nway;
       int fl = final_lin ? 1 : 0;
       void* args[] = {&am, &fl};

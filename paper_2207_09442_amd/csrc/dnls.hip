@@ -929,7 +929,6 @@ bool check_off(const int32_t* off, int B, int total_hint, int* total) {
   return true;
 }
 
-constexpr int kPairSpin = 1 << 24;   // polls of a pair wait (~1 s) before a graph is given up
 
 // Whether the pair kernel of this plan can be launched with every pair
 // co-resident: two workgroups per graph within what the device holds at once.
@@ -955,7 +954,7 @@ dnls_status launch_solve(dnls_plan p, const DenseArgs& a, hipStream_t st) {
     DenseArgs ap = a;
     ap.pair_ctr = p->d_pair;
     ap.pair_base = (++p->pair_epoch) << 20;   // counters only grow: no reset between launches
-    ap.pair_spin = kPairSpin;
+    ap.pair_spin = p->pair_spin;
     void* args[] = {&ap};
     HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_dense_solve<G, MIXED, false, true>),
                                        dim3(2 * p->B), dim3(kNT), args, (unsigned)lds, st));
@@ -1191,6 +1190,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->flags & DNLS_FLAG_KEEP_ITERATES) fac += (long long)op->iterations * V * p->sz;
   p->fac_bytes = (size_t)fac * sizeof(double);
   if (op->flags & DNLS_FLAG_PAIR) {
+    p->pair_spin = pair_spin_limit();
     const bool mixed = op->precision == DNLS_PREC_MIXED;
     p->pair_ok = p->group == DNLS_SE3 ? (mixed ? pair_fits<3, true>(p) : pair_fits<3, false>(p))
                                       : (mixed ? pair_fits<2, true>(p) : pair_fits<2, false>(p));

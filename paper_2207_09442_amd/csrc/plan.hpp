@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -28,6 +29,15 @@ inline dnls_status fail(dnls_status st, const std::string& msg) {
   } while (0)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Poll limit of the waits between co-resident workgroups (DNLS_FLAG_PAIR):
+// the environment variable DNLS_PAIR_SPIN (a positive count) overrides the
+// default, which lets tests drive the give-up path without a real fault.
+inline int pair_spin_limit() {
+  const char* e = std::getenv("DNLS_PAIR_SPIN");
+  const long v = e ? std::strtol(e, nullptr, 10) : 0;
+  return v > 0 && v < (1L << 30) ? (int)v : (1 << 24);
+}
 
 // one pose graph of the dense path
 struct GraphDesc {
@@ -76,6 +86,7 @@ struct dnls_plan_s {
   // DNLS_FLAG_PAIR: whether the pair kernel fits, its counters and launch epoch
   bool pair_ok = false;
   int ba_nway = 1;            // SCHUR: workgroups per problem in the factorisation
+  int pair_spin = 1 << 24;    // polls of a wait between the workgroups of a graph (about a second)
   unsigned long long* d_pair = nullptr;
   unsigned long long pair_epoch = 0;   // byte offsets inside the solve workspace
   // device tables of the dense path

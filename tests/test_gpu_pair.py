@@ -95,3 +95,25 @@ def test_pair_failed_graphs_are_frozen():
     for b in (1, 2):
         lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
         assert np.array_equal(got[lo:hi], p["poses_init"][lo:hi])
+
+
+def test_pair_gives_up_without_hanging(monkeypatch):
+    """Failure handling forced from the host: with a poll limit of one
+    (DNLS_PAIR_SPIN=1) the workgroups of a graph stop waiting for each other
+    almost at once; every kernel still exits, and a graph that gave up
+    reports DNLS_GRAPH_TIMEOUT (3) on both schedules that share a
+    factorisation."""
+    monkeypatch.setenv("DNLS_PAIR_SPIN", "1")
+    p = synth.walk_se3(batch=16)
+    _, poses, obj, st, _, _ = _solve(p, 3, 1e-3, True)
+    codes = set(st.cpu().tolist())
+    assert codes <= {S.OK, 3} and 3 in codes
+    from paper_2207_09442_amd import Plan
+    q = synth.bundle_adjustment(batch=2, n_cams=16, n_points=80, obs_per_point=4, seed=4)
+    plan = Plan(q, 3, lam=1e-3, solver="schur", device="cuda", pair=True)
+    assert plan.schedule()["pair"]
+    _, stb = plan.solve_ba(t(q["poses_init"]), t(q["points_init"]), obs_uv=t(q["obs_uv"]), obs_w=t(q["obs_w"]),
+                           prior_meas=t(q["prior_meas"]), prior_logw=t(q["prior_logw"]))
+    torch.cuda.synchronize()
+    codes = set(stb.cpu().tolist())
+    assert codes <= {S.OK, 3} and 3 in codes
