@@ -10,10 +10,13 @@
  *     CostWeight, Objective);
  *   - an optimizer: K Gauss-Newton or Levenberg-Marquardt steps
  *     (H + lambda I) delta = g, theta <- theta (-) delta by right retraction
- *     (Section 2 "Solving NLS");
+ *     (Section 2 "Solving NLS"), with fixed or adaptive damping or Powell's
+ *     dogleg (Section 3 optimizers), optionally Welsch-robust edges;
  *   - an implicit backward through the final iterate (Section 4.3,
  *     Proposition 1), with the factorisation kept from the forward pass
- *     (Section 4.2 "Backward for custom linear solvers").
+ *     (Section 4.2 "Backward for custom linear solvers"), and the other
+ *     backward modes of Section 4.3: direct loss minimisation, unrolled and
+ *     truncated differentiation, and Proposition 1 with the exact Hessian.
  *
  * Conventions
  *   SE(3) element storage: 12 doubles, the 3x4 matrix [R | t] row-major.
@@ -33,13 +36,17 @@
  * A plan owns only small immutable index tables that it copies to the
  * device at creation and frees in dnls_plan_destroy.  Plans are immutable
  * after creation, so concurrent calls on different streams with distinct
- * workspaces and outputs are allowed.
+ * workspaces and outputs are allowed -- except for plans made with
+ * DNLS_FLAG_GRAPH or DNLS_FLAG_PAIR, which keep launch state (a captured
+ * graph, event counters): their calls must not overlap.
  *
  * Errors: argument and HIP runtime errors are returned as dnls_status and
  * described by dnls_last_error() (thread-local).  Numerical failures never
  * abort: they are reported per graph in the status output
  * (DNLS_GRAPH_NOT_PD, DNLS_GRAPH_NONFINITE); a failed graph keeps its last
- * iterate, repeats its last objective value and receives zero gradients.
+ * iterate, repeats its last objective value and receives zero gradients
+ * (DNLS_GRAPH_TIMEOUT, of the shared-factorisation schedules, leaves the
+ * iterate undefined).
  * Kernel launches are asynchronous on the given stream; an asynchronous
  * device fault surfaces at the next synchronising call.
  */
