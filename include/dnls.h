@@ -272,7 +272,7 @@ typedef enum {
    * factored); graphs whose status is not OK get zero gradients. */
   DNLS_BACKWARD_DLM = 1,
   /* Proposition 1 with the exact Hessian of S in place of the Gauss-Newton
-   * one (DENSE only): Hx = the Hessian of S(theta_K Exp(delta)) at
+   * one (DENSE and SPARSE): Hx = the Hessian of S(theta_K Exp(delta)) at
    * delta = 0, i.e. J^T J plus the second-order terms of the costs
    * (differentiated by dual numbers) and of the retraction.  u = Hx^-1 v is
    * reached by `sweeps` steps of iterative refinement preconditioned by the

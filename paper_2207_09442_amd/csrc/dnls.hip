@@ -1352,8 +1352,8 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
       return fail(DNLS_ERR_INVALID_ARG, "steps must be in [1, iterations]");
   }
   if (s->mode == DNLS_BACKWARD_EXACT) {
-    if (p->opt.solver != DNLS_SOLVER_DENSE)
-      return fail(DNLS_ERR_UNSUPPORTED, "the exact-Hessian backward is implemented for the DENSE solver");
+    if (p->opt.solver == DNLS_SOLVER_SCHUR)
+      return fail(DNLS_ERR_UNSUPPORTED, "the exact-Hessian backward is implemented for the pose-graph solvers");
     if (s->sweeps < 0 || s->sweeps > kMaxExactSweeps)
       return fail(DNLS_ERR_INVALID_ARG, "sweeps must be in [0, 64]");
   }

@@ -75,6 +75,7 @@ struct SpArgs {
   double* g_tau;
   double* g_logw_p;
   double* g_logc;
+  double* hvp;             // exact backward: [cost][2][d] second-order terms
   double* lam_g;           // adaptive damping: lambda per graph
   double* pose_bak;        // adaptive damping: theta_t while the trial step is evaluated
   double* s_t;             // adaptive damping: float64 objective at theta_t per graph
@@ -775,6 +776,82 @@ __global__ void __launch_bounds__(kBT) k_sp_accumulate(SpArgs a, int retract) {
   if (retract) retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x);
 }
 
+// exact-Hessian backward, per cost: J u (ycost) and the second-order terms
+// w^2 (dC/ds)^T c of both sides along u (hvp), u in slot 0 (permuted order)
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_hvp_cost(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  const double* x = slot(a, g, 0);
+  int rk, pi = -1, pj;
+  if (k < g.nedge) {
+    rk = g.edge0 + k;
+    pi = a.pos[a.edge_ij[2 * rk]];
+    pj = a.pos[a.edge_ij[2 * rk + 1]];
+  } else {
+    rk = a.E + g.prior0 + (k - g.nedge);
+    pj = a.pos[a.prior_var[g.prior0 + (k - g.nedge)]];
+  }
+  const double* J = a.ws64 + (size_t)rk * RN;
+#pragma unroll
+  for (int r = 0; r < d; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < d; ++q) {
+      if (pi >= 0) acc += J[r * d + q] * x[pi * d + q];
+      acc += J[d * d + r * d + q] * x[pj * d + q];
+    }
+    a.ycost[(size_t)rk * d + r] = acc;
+  }
+  double* o = a.hvp + (size_t)rk * 2 * d;
+  cost_hvp_residual<G>(cost_data(a), rk, J, pi >= 0 ? x + pi * d : nullptr, x + pj * d, o, o + d);
+}
+
+// exact-Hessian backward, per pose: residual v - Hx u of the refinement into
+// slot 2 (permuted order, padding zero), Hx u = sum J^T J u + the cost terms
+// - 1/2 ad(u_p)^T g_p with g_p = sum J^T r at theta_K
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_hvp_res(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* x = slot(a, g, 0);
+  double* res = slot(a, g, 2);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int gp = g.pose0 + p, ra = a.pos[gp];
+  double hv[d], gv[d];
+#pragma unroll
+  for (int r = 0; r < d; ++r) hv[r] = gv[r] = 0.0;
+  for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+    const int sl = a.inc_slot[s];
+    const double* J = a.ws64 + (size_t)(sl >> 1) * RN + (sl & 1) * d * d;
+    const double* rr = a.ws64 + (size_t)(sl >> 1) * RN + 2 * d * d;
+    const double* yc = a.ycost + (size_t)(sl >> 1) * d;
+    const double* hc = a.hvp + (size_t)(sl >> 1) * 2 * d + (sl & 1) * d;
+#pragma unroll
+    for (int k = 0; k < d; ++k)
+#pragma unroll
+      for (int r = 0; r < d; ++r) {
+        hv[r] += J[k * d + r] * yc[k];
+        gv[r] += J[k * d + r] * rr[k];
+      }
+#pragma unroll
+    for (int r = 0; r < d; ++r) hv[r] += hc[r];
+  }
+  double t[d];
+  ad_transpose_mul<G>(x + ra * d, gv, t);
+#pragma unroll
+  for (int r = 0; r < d; ++r) res[ra * d + r] = a.seed[(size_t)gp * d + r] - (hv[r] - 0.5 * t[r]);
+}
+
 // backward: b = seed in permuted order (padding zero)
 __global__ void __launch_bounds__(kBT) k_sp_seed(SpArgs a, int d) {
   const int b = blockIdx.y;
@@ -1075,6 +1152,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     p->sp_off[10] = off; off += align256((size_t)B * sizeof(double));               // s_t
     p->sp_off[11] = off; off += align256((size_t)B * sizeof(int));                  // rejected
   }
+  p->sp_off[12] = off; off += align256(ncost * 2 * d * sizeof(double));             // exact backward: per-cost terms
   p->ws_bytes = off;
   p->bwd_bytes = off;
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -1105,6 +1183,7 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.failed = reinterpret_cast<int*>(w + p->sp_off[5]);
   a.lastobj = reinterpret_cast<double*>(w + p->sp_off[6]);
   a.uout = reinterpret_cast<double*>(w + p->sp_off[7]);
+  a.hvp = reinterpret_cast<double*>(w + p->sp_off[12]);
   if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
     a.lam_g = reinterpret_cast<double*>(w + p->sp_off[8]);
     a.pose_bak = reinterpret_cast<double*>(w + p->sp_off[9]);
@@ -1248,6 +1327,14 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
   hipLaunchKernelGGL(k_sp_seed, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
   sp_sweeps(p, a, 0, st);
+  if (s->mode == DNLS_BACKWARD_EXACT)
+    // u <- u + H*^-1 (v - Hx u), preconditioned by the cached factor
+    for (int sw = 0; sw < s->sweeps; ++sw) {
+      hipLaunchKernelGGL(k_sp_hvp_cost<G>, g_cost, dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_hvp_res<G>, g_pose, dim3(kBT), 0, st, a);
+      sp_sweeps(p, a, 2, st);
+      hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a, 0);
+    }
   hipLaunchKernelGGL(k_sp_uout, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
   hipLaunchKernelGGL(k_sp_vjp<G>, g_cost, dim3(kBT), 0, st, a);
   HIP_TRY(hipGetLastError());

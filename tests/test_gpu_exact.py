@@ -65,25 +65,27 @@ def _errors(p, tau, plan, poses, status, dev, seed, gr, graphs):
     return out
 
 
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
-def test_exact_backward_matches_oracle_ragged_batch(group):
+def test_exact_backward_matches_oracle_ragged_batch(group, solver):
     p, tau = _problem(group, seed=41)
-    plan, poses, objective, status, dev = gpu_solve(p, 10, 1e-3, tau=tau)
+    plan, poses, objective, status, dev = gpu_solve(p, 10, 1e-3, tau=tau, solver=solver)
     assert (status.cpu().numpy() == S.OK).all()
     seed = rng.normal(size=(int(p["pose_off"][-1]), plan.dof))
     gr = _run(plan, poses, status, dev, seed, "exact", sweeps=30)
     B = len(p["pose_off"]) - 1
     for b, (eg, eu, tol) in enumerate(_errors(p, tau, plan, poses, status, dev, seed, gr, list(range(B)))):
-        print(f"\n[exact {group}] graph {b}: gradient {eg:.2e} adjoint {eu:.2e} tolerance {tol:.2e}")
+        print(f"\n[exact {group} {solver}] graph {b}: gradient {eg:.2e} adjoint {eu:.2e} tolerance {tol:.2e}")
         assert eg < tol and eu < tol, (b, eg, eu, tol)
 
 
-def test_exact_backward_converges_geometrically_and_zero_sweeps_is_gauss_newton():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_exact_backward_converges_geometrically_and_zero_sweeps_is_gauss_newton(solver):
     """Sweeps = 0 reproduces the Gauss-Newton implicit backward; the error
     against the oracle's exact gradient then shrinks by about the same factor
     per sweep (the spectral radius of I - H*^-1 Hx)."""
     p = synth.walk_se3(batch=2, n_poses=24, n_loops=16, sigma_t=0.1, sigma_r=0.03, seed=8)
-    plan, poses, objective, status, dev = gpu_solve(p, 12, 0.0)
+    plan, poses, objective, status, dev = gpu_solve(p, 12, 0.0, solver=solver)
     seed = rng.normal(size=(int(p["pose_off"][-1]), 6))
     imp = _run(plan, poses, status, dev, seed, "implicit")
     ex0 = _run(plan, poses, status, dev, seed, "exact", sweeps=0)
@@ -127,7 +129,20 @@ def test_exact_backward_failed_graphs_and_argument_checks():
     for s in (-1, 65):
         with pytest.raises(DnlsError):
             _run(plan, poses, status, dev, seed, "exact", sweeps=s)
-    sp = Plan(p, 4, lam=0.0, solver="sparse", device="cuda")
+    q = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=9)
+    ba = Plan(q, 2, lam=1e-3, solver="schur", device="cuda")
+    cams, pts = t(q["poses_init"]), t(q["points_init"])
+    aux = dict(obs_uv=t(q["obs_uv"]), obs_w=t(q["obs_w"]), prior_meas=t(q["prior_meas"]),
+               prior_logw=t(q["prior_logw"]))
+    _, stb = ba.solve_ba(cams, pts, **aux)
+    from paper_2207_09442_amd import _BackwardArgs, _check, _ptr, _stream, lib
+    import ctypes
+    args = _BackwardArgs()
+    args.poses, args.points = _ptr(cams), _ptr(pts)
+    args.obs_uv, args.obs_w = _ptr(aux["obs_uv"]), _ptr(aux["obs_w"])
+    args.prior_meas, args.prior_logw = _ptr(aux["prior_meas"]), _ptr(aux["prior_logw"])
+    args.status, args.factor, args.workspace = _ptr(stb), ba._aligned(ba.factor), ba._aligned(ba.workspace)
+    args.seed_pose = _ptr(t(np.zeros((8, 6))))
+    args.mode, args.sweeps = 2, 4
     with pytest.raises(DnlsError):
-        sp.backward(poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"], dev["prior_logw"], status,
-                    t(seed), mode="exact", sweeps=4)
+        _check(lib().dnls_backward(ba._h, ctypes.byref(args), _stream()), "dnls_backward")
