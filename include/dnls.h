@@ -260,16 +260,19 @@ typedef struct {
 typedef enum {
   /* Proposition 1: u = H*^-1 v with the cached factor. */
   DNLS_BACKWARD_IMPLICIT = 0,
-  /* Direct loss minimisation (Section 4.3, Appendix G), DENSE only: one
+  /* Direct loss minimisation (Section 4.3, Appendix G), DENSE and SPARSE: one
    * Gauss-Newton step from theta_K on S(theta) + ||eps theta - v/2||^2,
    * (H* + 2 eps^2 I) delta = -g* + eps v, theta_direct = theta_K Exp(delta),
    * then dL/dphi = (dS/dphi(theta_K) - dS/dphi(theta_direct)) / eps for the
    * log-weights and the tangent perturbations tau, with S the objective of
    * Section 2 (costs weighted by exp(2 log w)).  A first-order estimate of
    * the implicit gradient that approaches it linearly as eps -> 0; eps <= 0
-   * or non-finite is DNLS_ERR_INVALID_ARG, SPARSE and SCHUR are
-   * DNLS_ERR_UNSUPPORTED.  The factor is not read (a new system is
-   * factored); graphs whose status is not OK get zero gradients. */
+   * or non-finite is DNLS_ERR_INVALID_ARG, SCHUR is DNLS_ERR_UNSUPPORTED.
+   * DENSE leaves the factor untouched (the new system is factored in the
+   * workspace); SPARSE factors it in the factor cache and then re-factors H*
+   * there (same kernels and inputs as the solve's final linearisation), so
+   * the cache holds the solve's factor again when the call has run.  Graphs
+   * whose status is not OK get zero gradients. */
   DNLS_BACKWARD_DLM = 1,
   /* Proposition 1 with the exact Hessian of S in place of the Gauss-Newton
    * one (DENSE and SPARSE): Hx = the Hessian of S(theta_K Exp(delta)) at

@@ -852,6 +852,55 @@ __global__ void __launch_bounds__(kBT) k_sp_hvp_res(SpArgs a) {
   for (int r = 0; r < d; ++r) res[ra * d + r] = a.seed[(size_t)gp * d + r] - (hv[r] - 0.5 * t[r]);
 }
 
+// DLM backward, per cost: dS/dphi at the poses `x`, times `scale`, stored
+// or added; graphs marked failed get zero gradients
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_param_grads(SpArgs a, const double* x, double scale, int accumulate) {
+  constexpr int d = GroupTraits<G>::d;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  const bool zero = a.failed[b] != 0;
+  PoseCostData cd = cost_data(a);
+  cd.poses = x;
+  double dl = 0.0, dt[d], dlc = 0.0;
+#pragma unroll
+  for (int q = 0; q < d; ++q) dt[q] = 0.0;
+  if (k < g.nedge) {
+    const int e = g.edge0 + k;
+    if (!zero) cost_param_grad<G>(cd, e, &dl, dt, &dlc);
+    if (a.g_logw_e) a.g_logw_e[e] = zero ? 0.0 : (accumulate ? a.g_logw_e[e] : 0.0) + scale * dl;
+    if (a.g_logc) a.g_logc[e] = zero ? 0.0 : (accumulate ? a.g_logc[e] : 0.0) + scale * dlc;
+    if (a.g_tau)
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        double& o = a.g_tau[(size_t)e * d + q];
+        o = zero ? 0.0 : (accumulate ? o : 0.0) + scale * dt[q];
+      }
+  } else {
+    const int pq = g.prior0 + (k - g.nedge);
+    if (!zero) cost_param_grad<G>(cd, a.E + pq, &dl, dt, nullptr);
+    if (a.g_logw_p) a.g_logw_p[pq] = zero ? 0.0 : (accumulate ? a.g_logw_p[pq] : 0.0) + scale * dl;
+  }
+}
+
+// DLM backward: right-hand side g* - eps v in slot 2 (permuted order, padding
+// zero), so that the solve gives -delta of (H* + 2 eps^2 I) delta = -g* + eps v
+__global__ void __launch_bounds__(kBT) k_sp_dlm_rhs(SpArgs a, int d, double eps) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* rhs = slot(a, g, 1);
+  double* x = slot(a, g, 2);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) x[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int ra = a.pos[g.pose0 + p];
+  for (int r = 0; r < d; ++r) x[ra * d + r] = rhs[ra * d + r] - eps * a.seed[(size_t)(g.pose0 + p) * d + r];
+}
+
 // backward: b = seed in permuted order (padding zero)
 __global__ void __launch_bounds__(kBT) k_sp_seed(SpArgs a, int d) {
   const int b = blockIdx.y;
@@ -1153,6 +1202,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     p->sp_off[11] = off; off += align256((size_t)B * sizeof(int));                  // rejected
   }
   p->sp_off[12] = off; off += align256(ncost * 2 * d * sizeof(double));             // exact backward: per-cost terms
+  p->sp_off[13] = off; off += align256((size_t)p->V * p->sz * sizeof(double));       // DLM backward: theta_direct
+  p->sp_off[14] = off; off += align256((size_t)B * sizeof(int));                    // DLM backward: factor status
   p->ws_bytes = off;
   p->bwd_bytes = off;
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -1321,10 +1372,44 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   a.g_logc = s->grad_edge_logc;
   const int B = p->B;
   const dim3 g_cost(p->nlin_blocks, B);
+  const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
   // float64 records at theta_K for the graphs whose solve succeeded
   hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  if (s->mode == DNLS_BACKWARD_DLM) {
+    const double eps = s->dlm_eps;
+    const dim3 g_blk((max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::nod) + kBT - 1) / kBT, B);
+    const dim3 g_zero(256, B);
+    char* w = static_cast<char*>(s->workspace);
+    double* xd = reinterpret_cast<double*>(w + p->sp_off[13]);
+    // dS/dphi at theta_K / eps; then (H* + 2 eps^2 I) assembled in float64
+    // and factored into the factor cache (a failure there marks the graph in
+    // a status copy of the workspace, not in the caller's status)
+    hipLaunchKernelGGL(k_sp_param_grads<G>, g_cost, dim3(kBT), 0, st, a, (const double*)a.poses, 1.0 / eps, 0);
+    hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
+    hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64,
+                       2.0 * eps * eps, 1, 0);
+    SpArgs ad = a;
+    ad.status = reinterpret_cast<int*>(w + p->sp_off[14]);
+    sp_factor<G>(p, ad, st);
+    hipLaunchKernelGGL(k_sp_dlm_rhs, g_pose, dim3(kBT), 0, st, ad, GroupTraits<G>::d, eps);
+    sp_sweeps(p, ad, 0, st);
+    // theta_direct = theta_K Exp(delta) in the workspace, minus dS/dphi there / eps
+    ad.pose_bak = xd;
+    hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, ad, GroupTraits<G>::sz);
+    ad.poses = xd;
+    hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, ad, 0);
+    hipLaunchKernelGGL(k_sp_param_grads<G>, g_cost, dim3(kBT), 0, st, ad, (const double*)xd, -1.0 / eps, 1);
+    // the factor cache again holds the factor of H* (same kernels and inputs
+    // as the final linearisation of the solve)
+    hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+    hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, 0.0, 1, 0);
+    sp_factor<G>(p, a, st);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
-  const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
   hipLaunchKernelGGL(k_sp_seed, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
   sp_sweeps(p, a, 0, st);
   if (s->mode == DNLS_BACKWARD_EXACT)

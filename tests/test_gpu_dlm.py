@@ -42,8 +42,8 @@ def _problem(group, seed):
     return p, tau
 
 
-def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None):
-    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau)
+def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None, solver="dense"):
+    plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver)
     B = len(p["pose_off"]) - 1
     graphs = list(range(B)) if graphs is None else graphs
     dof = plan.dof
@@ -75,17 +75,36 @@ def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None):
         worst = max(worst, err / tol)
         print(f"  graph {b}: error {err:.2e} tolerance {tol:.2e}")
         assert err < tol, (b, err, tol)
-    print(f"\n[dlm eps={eps} {precision}] worst error / tolerance {worst:.2e}")
+    print(f"\n[dlm eps={eps} {precision} {solver}] worst error / tolerance {worst:.2e}")
     return plan, poses, status, dev
 
 
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
 @pytest.mark.parametrize("eps", [1e-3, 0.3])
-def test_dlm_matches_oracle_ragged_batch(group, eps):
+def test_dlm_matches_oracle_ragged_batch(group, eps, solver):
     """Ragged batches with random log-weights and measurement tangents; eps
     small (the gradient regime) and large (the 2 eps^2 damping matters)."""
     p, tau = _problem(group, seed=31)
-    _dlm_parity(p, tau, 8, 1e-3, eps)
+    _dlm_parity(p, tau, 8, 1e-3, eps, solver=solver)
+
+
+def test_dlm_sparse_leaves_the_factor_cache_as_the_solve_left_it():
+    """The block-sparse DLM factors H* + 2 eps^2 I in the factor cache and then
+    re-factors H*: the implicit backward after it is bit-identical to the one
+    before it, and so is the whole factor cache."""
+    p, tau = _problem("SE3", seed=33)
+    plan, poses, objective, status, dev = gpu_solve(p, 6, 1e-3, tau=tau, solver="sparse")
+    seed = t(rng.normal(size=(int(p["pose_off"][-1]), 6)))
+    args = (poses, dev["edge_meas"], dev["edge_logw"], dev["prior_meas"], dev["prior_logw"], status, seed)
+    before = plan.backward(*args, edge_tau=dev["edge_tau"], want_adjoint=True)
+    cache = plan.factor.clone()
+    plan.backward(*args, edge_tau=dev["edge_tau"], mode="dlm", eps=0.3)
+    after = plan.backward(*args, edge_tau=dev["edge_tau"], want_adjoint=True)
+    torch.cuda.synchronize()
+    assert torch.equal(cache, plan.factor)
+    for k in before:
+        assert torch.equal(before[k], after[k]), k
 
 
 def test_dlm_after_mixed_precision_solve():
@@ -102,8 +121,8 @@ def test_dlm_walk64_b128_sampled_graphs():
 
 def test_dlm_failed_graphs_and_argument_checks():
     """A graph whose solve failed (isolated pose, NOT_PD) gets zero
-    gradients; eps <= 0 or non-finite and the DLM mode on the sparse solver
-    are rejected before any launch."""
+    gradients on both pose-graph solvers; eps <= 0 or non-finite and the DLM
+    mode on the Schur solver are rejected before any launch."""
     from paper_2207_09442_amd import DnlsError, Plan
     p = synth.walk_se3(batch=2, n_poses=8, n_loops=4, seed=17)
     last = int(p["pose_off"][1]) + 7
@@ -124,6 +143,26 @@ def test_dlm_failed_graphs_and_argument_checks():
     for eps in (0.0, -1.0, float("nan"), float("inf")):
         with pytest.raises(DnlsError):
             plan.backward(*args, mode="dlm", eps=eps)
-    sp = Plan(p, 4, lam=0.0, solver="sparse", device="cuda")
+    sp, sposes, _, sstatus, _ = gpu_solve(p, 4, 0.0, solver="sparse")
+    assert sstatus.cpu().tolist() == [S.OK, S.NOT_PD]
+    sout = sp.backward(sposes, *args[1:5], sstatus, seed, mode="dlm", eps=1e-3)
+    torch.cuda.synchronize()
+    assert torch.all(sout["edge_logw"][e0:] == 0) and torch.all(sout["edge_tau"][e0:] == 0)
+    assert torch.all(sout["prior_logw"][int(p["prior_off"][1]):] == 0)
+    assert rel(sout["edge_logw"][:e0].cpu().numpy(), out["edge_logw"][:e0].cpu().numpy()) < 1e-8
+    q = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=9)
+    ba = Plan(q, 2, lam=1e-3, solver="schur", device="cuda")
+    cams, pts = t(q["poses_init"]), t(q["points_init"])
+    aux = dict(obs_uv=t(q["obs_uv"]), obs_w=t(q["obs_w"]), prior_meas=t(q["prior_meas"]),
+               prior_logw=t(q["prior_logw"]))
+    _, stb = ba.solve_ba(cams, pts, **aux)
+    from paper_2207_09442_amd import _BackwardArgs, _check, _ptr, _stream, lib
+    a = _BackwardArgs()
+    a.poses, a.points = _ptr(cams), _ptr(pts)
+    a.obs_uv, a.obs_w = _ptr(aux["obs_uv"]), _ptr(aux["obs_w"])
+    a.prior_meas, a.prior_logw = _ptr(aux["prior_meas"]), _ptr(aux["prior_logw"])
+    a.status, a.factor, a.workspace = _ptr(stb), ba._aligned(ba.factor), ba._aligned(ba.workspace)
+    a.seed_pose = _ptr(t(np.zeros((8, 6))))
+    a.mode, a.dlm_eps = 1, 1e-3
     with pytest.raises(DnlsError):
-        sp.backward(*args, mode="dlm", eps=1e-3)
+        _check(lib().dnls_backward(ba._h, ctypes.byref(a), _stream()), "dnls_backward")

@@ -97,9 +97,10 @@ def test_welsch_dogleg():
     _compare(p, tau, 6, 0.0, 1e-10, dogleg=0.5)
 
 
-def test_welsch_dlm():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_welsch_dlm(solver):
     p, tau = _problem(65)
-    _compare(p, tau, 8, 1e-3, 1e-10, grad_tol=1e-8, mode="dlm", eps=1e-3)
+    _compare(p, tau, 8, 1e-3, 1e-10, grad_tol=1e-8, solver=solver, mode="dlm", eps=1e-3)
 
 
 def test_welsch_huge_radius_equals_least_squares_and_unsupported_modes():
