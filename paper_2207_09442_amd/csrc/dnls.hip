@@ -1031,7 +1031,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
       return fail(DNLS_ERR_INVALID_ARG, "adaptive damping and dogleg exclude each other");
     if (!(op->trust_radius > 0.0) || !std::isfinite(op->trust_radius))
       return fail(DNLS_ERR_INVALID_ARG, "dogleg needs a positive finite trust_radius");
-    if (op->solver != DNLS_SOLVER_DENSE) return fail(DNLS_ERR_UNSUPPORTED, "dogleg is implemented for the DENSE solver");
+    if (op->solver == DNLS_SOLVER_SCHUR)
+      return fail(DNLS_ERR_UNSUPPORTED, "dogleg is implemented for the pose-graph solvers");
   }
   if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver == DNLS_SOLVER_SCHUR)
     return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the pose-graph solvers");

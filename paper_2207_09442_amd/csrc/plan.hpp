@@ -131,7 +131,7 @@ struct dnls_plan_s {
   int sp_maxP = 0;
   bool sp_solve_wg = false;       // triangular solves: one workgroup per graph (vector in LDS)
   bool sp_factor_wg = false;      // factorisation: one workgroup per graph
-  size_t sp_off[15] = {0};
+  size_t sp_off[16] = {0};
   std::vector<void*> allocs;
   // captured launch sequence of dnls_solve (DNLS_FLAG_GRAPH)
   std::mutex graph_mu;

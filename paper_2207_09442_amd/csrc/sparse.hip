@@ -79,9 +79,10 @@ struct SpArgs {
   double* lam_g;           // adaptive damping: lambda per graph
   double* pose_bak;        // adaptive damping: theta_t while the trial step is evaluated
   double* s_t;             // adaptive damping: float64 objective at theta_t per graph
-  int* rej;                // adaptive damping: the graph's trial step was rejected
+  int* rej;                // adaptive damping / dogleg: the graph's trial step was rejected
+  double* dl;              // dogleg per graph: radius, predicted decrease, |delta|, on the boundary
   int E, K, it, nx, refine;
-  double lambda;
+  double lambda, radius0;
 };
 
 __device__ __forceinline__ PoseCostData cost_data(const SpArgs& a) {
@@ -730,14 +731,14 @@ __global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda, in
 
 // refinement: J delta per cost (float64 records), delta read in permuted order
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a) {
+__global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a, int xs) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
   const int k = blockIdx.x * kBT + threadIdx.x;
   if (k >= g.nedge + g.nprior) return;
-  const double* x = a.vec + g.vec_off;
+  const double* x = slot(a, g, xs);
   int rk, pi = -1, pj;
   if (k < g.nedge) {
     rk = g.edge0 + k;
@@ -757,6 +758,114 @@ __global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a) {
       acc += J[d * d + r * d + q] * x[pj * d + q];
     }
     a.ycost[(size_t)rk * d + r] = acc;
+  }
+}
+
+// y = (H64 + lambda I) x per pose from J x per cost (ycost), x and y slots
+// in permuted order, padding zero
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_hx(SpArgs a, int xs, int ys, double lambda) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* x = slot(a, g, xs);
+  double* y = slot(a, g, ys);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) y[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int gp = g.pose0 + p, ra = a.pos[gp];
+  double hv[d];
+#pragma unroll
+  for (int r = 0; r < d; ++r) hv[r] = lambda * x[ra * d + r];
+  for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+    const int sl = a.inc_slot[s];
+    const double* J = a.ws64 + (size_t)(sl >> 1) * RN + (sl & 1) * d * d;
+    const double* yc = a.ycost + (size_t)(sl >> 1) * d;
+#pragma unroll
+    for (int k = 0; k < d; ++k)
+#pragma unroll
+      for (int r = 0; r < d; ++r) hv[r] += J[k * d + r] * yc[k];
+  }
+#pragma unroll
+  for (int r = 0; r < d; ++r) y[ra * d + r] = hv[r];
+}
+
+// Powell's dogleg in ||delta|| <= radius for the model
+// S - g^T delta + 1/2 delta^T (H + lambda I) delta, one workgroup per graph:
+// Gauss-Newton step in slot 0, g in slot 1, (H + lambda I) g in slot 2;
+// the chosen step replaces slot 0
+__global__ void __launch_bounds__(kBT) k_sp_dogleg(SpArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  double* x = slot(a, g, 0);
+  const double* gv = slot(a, g, 1);
+  const double* hg = slot(a, g, 2);
+  const double radius = a.dl[4 * b];
+  double p0 = 0.0;
+  for (int u = threadIdx.x; u < g.n; u += kBT) p0 += x[u] * x[u];
+  const double n_gn = ::sqrt(block_sum_sp(p0, red));
+  int boundary = 0;
+  if (!(n_gn <= radius)) {
+    boundary = 1;
+    double p1 = 0.0, p2 = 0.0;
+    for (int u = threadIdx.x; u < g.n; u += kBT) {
+      p1 += gv[u] * gv[u];
+      p2 += gv[u] * hg[u];
+    }
+    const double gg = block_sum_sp(p1, red);
+    const double gHg = block_sum_sp(p2, red);
+    const double alpha = gg / gHg;
+    if (alpha * ::sqrt(gg) >= radius) {
+      // the Cauchy point is outside: gradient direction cut at the boundary
+      const double sc = radius / ::sqrt(gg);
+      for (int u = threadIdx.x; u < g.n; u += kBT) x[u] = sc * gv[u];
+    } else {
+      // between the Cauchy point alpha g and the Gauss-Newton point
+      double q1 = 0.0, q2 = 0.0;
+      for (int u = threadIdx.x; u < g.n; u += kBT) {
+        const double sd = alpha * gv[u], dd = x[u] - sd;
+        q1 += dd * dd;
+        q2 += sd * dd;
+      }
+      const double qa = block_sum_sp(q1, red);
+      const double qb = 2.0 * block_sum_sp(q2, red);
+      const double qc = alpha * alpha * gg - radius * radius;
+      const double beta = (-qb + ::sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa);
+      for (int u = threadIdx.x; u < g.n; u += kBT) {
+        const double sd = alpha * gv[u];
+        x[u] = sd + beta * (x[u] - sd);
+      }
+    }
+  }
+  if (threadIdx.x == 0) a.dl[4 * b + 3] = boundary;
+}
+
+// dogleg: predicted decrease g^T delta - 1/2 delta^T (H + lambda I) delta and
+// |delta| (delta in slot 0, g in slot 1, (H + lambda I) delta in slot 2)
+__global__ void __launch_bounds__(kBT) k_sp_dl_pred(SpArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* x = slot(a, g, 0);
+  const double* gv = slot(a, g, 1);
+  const double* hx = slot(a, g, 2);
+  double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+  for (int u = threadIdx.x; u < g.n; u += kBT) {
+    r1 += gv[u] * x[u];
+    r2 += x[u] * hx[u];
+    r3 += x[u] * x[u];
+  }
+  const double s1 = block_sum_sp(r1, red);
+  const double s2 = block_sum_sp(r2, red);
+  const double s3 = block_sum_sp(r3, red);
+  if (threadIdx.x == 0) {
+    a.dl[4 * b + 1] = s1 - 0.5 * s2;
+    a.dl[4 * b + 2] = ::sqrt(s3);
   }
 }
 
@@ -971,6 +1080,7 @@ __global__ void k_sp_reset(int* failed, int* status, int B) {
 // (lambda / 10), else restore theta_t (lambda x 10), lambda in [1e-7, 1e7]
 // ---------------------------------------------------------------------------
 constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;
+constexpr double kRadiusMax = 1e4;   // dogleg: largest trust radius
 
 __global__ void k_sp_lam_init(SpArgs a, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1011,6 +1121,29 @@ __global__ void __launch_bounds__(kBT) k_sp_backup(SpArgs a, int sz) {
 }
 
 // decision from the trial objective's partials and s_t (thread per graph)
+__global__ void k_sp_dl_init(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) a.dl[4 * b] = a.radius0;
+}
+
+// dogleg: keep the trial step iff the float64 objective strictly decreases;
+// with rho = actual / predicted decrease the radius becomes |delta| / 4 if
+// rho < 1/4 (or undefined) and min(2 radius, kRadiusMax) if rho > 3/4 on the
+// boundary (thread per graph)
+__global__ void k_sp_dl_decide(SpArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  a.rej[b] = 0;
+  if (a.failed[b]) return;
+  double S = 0.0;
+  for (int k = 0; k < a.nx; ++k) S += a.partial[b * a.nx + k];
+  const double s_t = a.s_t[b];
+  const double rho = (s_t - S) / a.dl[4 * b + 1];
+  if (!(S < s_t)) a.rej[b] = 1;
+  if (!(rho >= 0.25)) a.dl[4 * b] = 0.25 * a.dl[4 * b + 2];
+  else if (rho > 0.75 && a.dl[4 * b + 3] != 0.0) a.dl[4 * b] = fmin(2.0 * a.dl[4 * b], kRadiusMax);
+}
+
 __global__ void k_sp_decide(SpArgs a, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -1195,7 +1328,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sp_off[5] = off; off += align256((size_t)B * sizeof(int));                     // failed
   p->sp_off[6] = off; off += align256((size_t)B * sizeof(double));                  // last objective
   p->sp_off[7] = off; off += align256((size_t)p->V * d * sizeof(double));           // adjoint
-  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
+  if (p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG)) {
     p->sp_off[8] = off; off += align256((size_t)B * sizeof(double));                // lambda per graph
     p->sp_off[9] = off; off += align256((size_t)p->V * p->sz * sizeof(double));     // pose backup
     p->sp_off[10] = off; off += align256((size_t)B * sizeof(double));               // s_t
@@ -1204,6 +1337,7 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sp_off[12] = off; off += align256(ncost * 2 * d * sizeof(double));             // exact backward: per-cost terms
   p->sp_off[13] = off; off += align256((size_t)p->V * p->sz * sizeof(double));       // DLM backward: theta_direct
   p->sp_off[14] = off; off += align256((size_t)B * sizeof(int));                    // DLM backward: factor status
+  p->sp_off[15] = off; off += align256((size_t)B * 4 * sizeof(double));             // dogleg state per graph
   p->ws_bytes = off;
   p->bwd_bytes = off;
   p->fac_bytes = (size_t)fac * sizeof(double);
@@ -1235,7 +1369,9 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.lastobj = reinterpret_cast<double*>(w + p->sp_off[6]);
   a.uout = reinterpret_cast<double*>(w + p->sp_off[7]);
   a.hvp = reinterpret_cast<double*>(w + p->sp_off[12]);
-  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
+  a.dl = reinterpret_cast<double*>(w + p->sp_off[15]);
+  a.radius0 = p->opt.trust_radius;
+  if (p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG)) {
     a.lam_g = reinterpret_cast<double*>(w + p->sp_off[8]);
     a.pose_bak = reinterpret_cast<double*>(w + p->sp_off[9]);
     a.s_t = reinterpret_cast<double*>(w + p->sp_off[10]);
@@ -1300,9 +1436,11 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   const dim3 g_pose((max_desc(p->sd, &SpDesc::npose) + kBT - 1) / kBT, B);
   const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
   const bool adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) != 0;
+  const bool dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) != 0;
   const int sz = GroupTraits<G>::sz;
   hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
   if (adaptive) hipLaunchKernelGGL(k_sp_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
+  if (dogleg) hipLaunchKernelGGL(k_sp_dl_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
   for (int it = 0; it <= p->opt.iterations; ++it) {
     const bool final_lin = it == p->opt.iterations;
     const double lam = final_lin ? 0.0 : p->opt.lambda;
@@ -1311,7 +1449,8 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     const bool lin32 = mixed && !final_lin;
     const bool refine_now = lin32 && a.refine > 0 &&
                             (p->opt.refine_last == 0 || it >= p->opt.iterations - p->opt.refine_last);
-    const bool lin64 = !mixed || refine_now || final_lin;
+    // the dogleg's model and decision use the float64 gradient and objective
+    const bool lin64 = !mixed || refine_now || final_lin || dogleg;
     if (lin32) hipLaunchKernelGGL((k_sp_lin<G, float>), g_cost, dim3(kBT), 0, st, a, a.ws32);
     if (lin64) hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
     hipLaunchKernelGGL(k_sp_objective, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
@@ -1323,8 +1462,8 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
     if (lin32) {
       hipLaunchKernelGGL((k_sp_assemble<G, float>), g_blk, dim3(kBT), 0, st, a, (const float*)a.ws32, lam,
-                         refine_now ? 0 : 1, lam_g);
-      if (refine_now) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
+                         (refine_now || dogleg) ? 0 : 1, lam_g);
+      if (refine_now || dogleg) hipLaunchKernelGGL(k_sp_rhs64<G>, g_blk, dim3(kBT), 0, st, a);
     } else {
       hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, lam, 1,
                          lam_g);
@@ -1335,14 +1474,30 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     const bool refine = refine_now;
     hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 1, 2);
     sp_sweeps(p, a, 0, st);
-    if (!refine) hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, a, 0);
+    if (!refine && !dogleg) hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, a, 0);
     if (refine)
       for (int sw = 0; sw < a.refine; ++sw) {
-        hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a);
+        hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a, 0);
         hipLaunchKernelGGL(k_sp_residual<G>, g_pose, dim3(kBT), 0, st, a, lam, lam_g);
         sp_sweeps(p, a, 2, st);
-        hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a, sw + 1 == a.refine ? 1 : 0);
+        hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a,
+                           (sw + 1 == a.refine && !dogleg) ? 1 : 0);
       }
+    if (dogleg) {
+      // (H + lambda I) g, the dogleg step, its predicted decrease, then the
+      // trial retraction from a backup of theta_t
+      hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a, 1);
+      hipLaunchKernelGGL(k_sp_hx<G>, g_pose, dim3(kBT), 0, st, a, 1, 2, lam);
+      hipLaunchKernelGGL(k_sp_dogleg, dim3(B), dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a, 0);
+      hipLaunchKernelGGL(k_sp_hx<G>, g_pose, dim3(kBT), 0, st, a, 0, 2, lam);
+      hipLaunchKernelGGL(k_sp_dl_pred, dim3(B), dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, a, sz);
+      hipLaunchKernelGGL(k_sp_retract<G>, g_pose, dim3(kBT), 0, st, a, 0);
+      hipLaunchKernelGGL(k_sp_obj<G>, g_cost, dim3(kBT), 0, st, a);
+      hipLaunchKernelGGL(k_sp_dl_decide, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+      hipLaunchKernelGGL(k_sp_restore, g_pose, dim3(kBT), 0, st, a, sz);
+    }
     if (lam_g) {
       hipLaunchKernelGGL(k_sp_obj<G>, g_cost, dim3(kBT), 0, st, a);
       hipLaunchKernelGGL(k_sp_decide, dim3((B + 63) / 64), dim3(64), 0, st, a, B);

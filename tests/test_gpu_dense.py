@@ -367,17 +367,18 @@ def test_adaptive_lm_se3_batch_fp64_and_mixed(solver):
 
 
 # ---------------------------------------------------------------------------
-# Dogleg (trust region), dense solver
+# Dogleg (trust region), dense and block-sparse solvers
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
-def test_dogleg_closed_form_single_pose(group):
+def test_dogleg_closed_form_single_pose(group, solver):
     """Pure-rotation prior error 1.0 with radius 0.1: the scaled-gradient
     steps leave 0.9, 0.7, 0.3 (the radius doubles on the boundary) and the
     Gauss-Newton step then lands on the target: objectives 0.5, 0.405, 0.245,
     0.045, 0."""
     from test_oracle_solve import _single_pose_rotation_problem
     p = _single_pose_rotation_problem(group, 1.0)
-    plan, poses, objective, status, dev = gpu_solve(p, 4, 0.0, dogleg=0.1)
+    plan, poses, objective, status, dev = gpu_solve(p, 4, 0.0, dogleg=0.1, solver=solver)
     assert status.cpu().tolist() == [0]
     ob = objective.cpu().numpy()[0]
     assert ob[:4] == pytest.approx([0.5, 0.405, 0.245, 0.045], rel=1e-12)
@@ -385,8 +386,9 @@ def test_dogleg_closed_form_single_pose(group):
     assert np.abs(poses.cpu().numpy()[0] - p["prior_meas"][0]).max() < 1e-12
 
 
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
 @pytest.mark.parametrize("precision,refine,tol", [("fp64", 0, 1e-10), ("mixed", 1, 1e-5)])
-def test_dogleg_se3_batch_with_rejections(precision, refine, tol):
+def test_dogleg_se3_batch_with_rejections(precision, refine, tol, solver):
     """SE(3) batch from a very poor initial guess (rotations perturbed by
     2.5 rad): graph 2's first Gauss-Newton step raises the objective and is
     refused (radius 100 -> 17.7, then doubling), the others take full steps.
@@ -395,11 +397,38 @@ def test_dogleg_se3_batch_with_rejections(precision, refine, tol):
     decisions would be decided by the last bit."""
     p = synth.walk_se3(batch=4, n_poses=10, n_loops=10, seed=48, init_noise=(3.0, 2.5))
     _compare(p, 6, 0.0, precision=precision, refine=refine, tol_pose=tol, tol_grad=tol, dogleg=100.0,
-             grad_cond_scale=0.5)
+             grad_cond_scale=0.5, solver=solver)
 
 
-def test_dogleg_uneven_with_weights_tau_and_damping():
+@pytest.mark.parametrize("solver", ["dense", "sparse"])
+def test_dogleg_uneven_with_weights_tau_and_damping(solver):
     p = synth.uneven_walk_se3(batch=6, n_min=3, n_max=40, seed=23)
     p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
     tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), 6))
-    _compare(p, 8, 1e-3, tau=tau, dogleg=0.05)
+    _compare(p, 8, 1e-3, tau=tau, dogleg=0.05, solver=solver)
+
+
+@pytest.mark.parametrize("schedule", ["sweeps", "workgroup"])
+def test_dogleg_sparse_schedules_and_graph_replay(schedule):
+    """The block-sparse dogleg under the per-column and one-workgroup
+    schedules, and replayed from a captured HIP graph: every replay gives
+    the eager result bit for bit."""
+    from paper_2207_09442_amd import Plan
+    p = synth.walk_se3(batch=3, n_poses=24, n_loops=12, seed=49, init_noise=(1.0, 0.8))
+    plan = Plan(p, 6, lam=0.0, solver="sparse", device="cuda", dogleg=2.0, sparse_solve=schedule)
+    gplan = Plan(p, 6, lam=0.0, solver="sparse", device="cuda", dogleg=2.0, sparse_solve=schedule, graph=True)
+    aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
+    x0 = t(p["poses_init"])
+    ob0, st0 = plan.solve(x0, *aux)
+    torch.cuda.synchronize()
+    gs, res = oracle_solve(p, 6, 0.0, dogleg=2.0)
+    for b, r in enumerate(res):
+        lo, hi = int(p["pose_off"][b]), int(p["pose_off"][b + 1])
+        assert int(st0[b]) == r.status == S.OK
+        assert rel(x0.cpu().numpy()[lo:hi], gs[0].G.to_storage(r.X).numpy()) < 1e-10
+        assert rel(ob0.cpu().numpy()[b], r.objective) < 1e-10
+    for _ in range(3):
+        x1 = t(p["poses_init"])
+        ob1, st1 = gplan.solve(x1, *aux)
+        torch.cuda.synchronize()
+        assert torch.equal(x0, x1) and torch.equal(ob0, ob1) and torch.equal(st0, st1)
