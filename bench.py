@@ -184,8 +184,8 @@ def main():
                     help="Powell's dogleg with this initial trust radius (pose-graph solvers)")
     ap.add_argument("--backward", choices=["implicit", "dlm", "exact", "unroll"], default="implicit",
                     help="backward mode: implicit (Proposition 1), direct loss minimisation, implicit with "
-                         "the exact Hessian (these two on the pose-graph solvers), or unrolled through the last "
-                         "--unroll-steps steps (dense solver)")
+                         "the exact Hessian, or unrolled through the last --unroll-steps steps (pose-graph "
+                         "solvers)")
     ap.add_argument("--unroll-steps", type=int, default=None, help="truncated unrolling: steps (default all K)")
     ap.add_argument("--dlm-eps", type=float, default=1e-3)
     ap.add_argument("--sweeps", type=int, default=8, help="refinement sweeps of the exact-Hessian backward")

@@ -160,7 +160,7 @@ enum {
    * DNLS_FLAG_ADAPTIVE_LM; SCHUR: DNLS_ERR_UNSUPPORTED.  The mixed path
    * linearises in float64 as well for g and the model. */
   DNLS_FLAG_DOGLEG = 4,
-  /* DENSE, fixed damping (not with DNLS_FLAG_ADAPTIVE_LM or
+  /* DENSE and SPARSE, fixed damping (not with DNLS_FLAG_ADAPTIVE_LM or
    * DNLS_FLAG_DOGLEG): dnls_solve also stores the iterates theta_0 ..
    * theta_{K-1} in the factor cache (factor_bytes grows by K V 12|4
    * doubles) for the unrolled backward (DNLS_BACKWARD_UNROLL). */
@@ -286,14 +286,16 @@ typedef enum {
    * Then the same per-cost VJP.  The adjoint output receives u. */
   DNLS_BACKWARD_EXACT = 2,
   /* Unrolled differentiation (Section 4.3; truncated when steps < K),
-   * DENSE plans with DNLS_FLAG_KEEP_ITERATES: reverse sweep through the
+   * DENSE and SPARSE plans with DNLS_FLAG_KEEP_ITERATES: reverse sweep through the
    * last `steps` optimizer steps theta_{t+1} = theta_t Exp(-delta_t),
    * delta_t = (H_t + lambda I)^-1 g_t, recomputed in float64 at the kept
    * iterates (the mixed path's float32 assembly is not differentiated), for
    * the seed v = dL/dtheta_K; the parameter gradients sum over those steps
    * and the adjoint output receives dL/dtheta_{K-steps}.  A graph whose
    * solve failed, or whose float64 step matrix is not positive definite,
-   * gets zero gradients.  The factor of H* is not read. */
+   * gets zero gradients.  The factor of H* is not read; SPARSE factors the
+   * step matrices in the factor cache and then re-factors H* there (same
+   * kernels and inputs as the solve's final linearisation). */
   DNLS_BACKWARD_UNROLL = 3
 } dnls_backward_mode;
 

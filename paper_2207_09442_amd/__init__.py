@@ -249,8 +249,8 @@ class Plan:
         "exact" (Proposition 1 with the exact Hessian, `sweeps` refinement
         sweeps preconditioned by the cached factor) or "unroll" (through the
         last `steps` optimizer steps, all K by default; plans made with
-        keep_iterates=True; the adjoint is dL/dtheta_{K-steps}); "unroll" on
-        the dense solver, "dlm" and "exact" on the pose-graph solvers.  With Welsch radii (edge_logc) the
+        keep_iterates=True; the adjoint is dL/dtheta_{K-steps}); "dlm",
+        "exact" and "unroll" on the pose-graph solvers.  With Welsch radii (edge_logc) the
         output also holds their gradient "edge_logc"."""
         import torch
         dev, f64 = self.device, torch.float64

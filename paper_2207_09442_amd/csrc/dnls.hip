@@ -1021,8 +1021,8 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
                            DNLS_FLAG_PAIR))
     return fail(DNLS_ERR_INVALID_ARG, "unknown flags");
   if (op->flags & DNLS_FLAG_KEEP_ITERATES) {
-    if (op->solver != DNLS_SOLVER_DENSE)
-      return fail(DNLS_ERR_UNSUPPORTED, "kept iterates (unrolled backward) are implemented for the DENSE solver");
+    if (op->solver == DNLS_SOLVER_SCHUR)
+      return fail(DNLS_ERR_UNSUPPORTED, "kept iterates (unrolled backward) are implemented for the pose-graph solvers");
     if (op->flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG))
       return fail(DNLS_ERR_UNSUPPORTED, "the unrolled backward differentiates the fixed-damping step only");
   }

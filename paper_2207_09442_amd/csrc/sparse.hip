@@ -1010,6 +1010,151 @@ __global__ void __launch_bounds__(kBT) k_sp_dlm_rhs(SpArgs a, int d, double eps)
   for (int r = 0; r < d; ++r) x[ra * d + r] = rhs[ra * d + r] - eps * a.seed[(size_t)(g.pose0 + p) * d + r];
 }
 
+// unrolled backward (truncated to the last T steps), a reverse sweep through
+// theta_{t+1} = theta_t Exp(-delta_t), delta_t = (H_t + lambda I)^-1 g_t, the
+// iterates read from the factor cache.  Per step, with abar (uout, original
+// order) the cotangent at theta_{t+1}:
+//   dbar_p = -Jr(-delta_p)^T abar_p,  abar_p <- Ad(Exp(delta_p))^T abar_p,
+//   y = (H_t + lambda I)^-1 dbar, then the gradient of
+//   s = y^T g_t - y^T (H_t + lambda I) delta_t (y, delta_t fixed) is added to
+//   abar and to the parameter gradients.
+
+// abar = seed (init = 1) or, for graphs marked failed, zero (init = 0: only those)
+__global__ void __launch_bounds__(kBT) k_sp_unroll_adj(SpArgs a, int d, int init) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const bool failed = a.failed[b] != 0;
+  if (!init && !failed) return;
+  for (int r = 0; r < d; ++r) {
+    const size_t u = (size_t)(g.pose0 + p) * d + r;
+    a.uout[u] = failed ? 0.0 : a.seed[u];
+  }
+}
+
+// parameter gradients zero (all graphs, or only = 1: the graphs marked failed)
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_grads_zero(SpArgs a, int only) {
+  constexpr int d = GroupTraits<G>::d;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (only && !a.failed[b]) return;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  if (k < g.nedge) {
+    const int e = g.edge0 + k;
+    if (a.g_logw_e) a.g_logw_e[e] = 0.0;
+    if (a.g_tau)
+      for (int q = 0; q < d; ++q) a.g_tau[(size_t)e * d + q] = 0.0;
+  } else if (a.g_logw_p) {
+    a.g_logw_p[g.prior0 + (k - g.nedge)] = 0.0;
+  }
+}
+
+// through the retraction: dbar into slot 2 (permuted order, padding zero),
+// delta_t in slot 0
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_unroll_retr(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* vd = slot(a, g, 0);
+  double* vw = slot(a, g, 2);
+  if (blockIdx.x == 0)
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) vw[u] = 0.0;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int gp = g.pose0 + p, ra = a.pos[gp];
+  double dl[d], md[d], Jr[d * d], Ad[d * d], ab[d];
+  for (int q = 0; q < d; ++q) {
+    dl[q] = vd[ra * d + q];
+    md[q] = -dl[q];
+    ab[q] = a.uout[(size_t)gp * d + q];
+  }
+  if constexpr (G == 3) {
+    double E[12], R[9], tv[3];
+    se3_jr(md, Jr);
+    se3_exp(dl, E);
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) R[r * 3 + q] = E[r * 4 + q];
+      tv[r] = E[r * 4 + 3];
+    }
+    se3_adjoint(R, tv, Ad);
+  } else {
+    double E[4];
+    se2_jr(md, Jr);
+    se2_exp(dl, E);
+    se2_adjoint(E[0], E[1], E[2], E[3], Ad);
+  }
+  for (int m = 0; m < d; ++m) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = 0; q < d; ++q) {
+      s1 += Jr[q * d + m] * ab[q];
+      s2 += Ad[q * d + m] * ab[q];
+    }
+    vw[ra * d + m] = -s1;
+    a.uout[(size_t)gp * d + m] = s2;
+  }
+}
+
+// per cost: the gradient of s at the poses (hvp buffer, both sides) and at
+// the parameters (accumulated); y in slot 2, delta_t in slot 0
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_unroll_cost(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k >= g.nedge + g.nprior) return;
+  const double* vd = slot(a, g, 0);
+  const double* vw = slot(a, g, 2);
+  int rk, pi = -1, pj;
+  if (k < g.nedge) {
+    rk = g.edge0 + k;
+    pi = a.pos[a.edge_ij[2 * rk]];
+    pj = a.pos[a.edge_ij[2 * rk + 1]];
+  } else {
+    rk = a.E + g.prior0 + (k - g.nedge);
+    pj = a.pos[a.prior_var[g.prior0 + (k - g.nedge)]];
+  }
+  double* o = a.hvp + (size_t)rk * 2 * d;
+  double dlw, dt[d];
+  cost_unroll_vjp<G>(cost_data(a), rk, pi >= 0 ? vw + pi * d : nullptr, vw + pj * d,
+                     pi >= 0 ? vd + pi * d : nullptr, vd + pj * d, o, o + d, &dlw, k < g.nedge ? dt : nullptr);
+  if (pi < 0)
+    for (int q = 0; q < d; ++q) o[q] = 0.0;
+  if (k < g.nedge) {
+    if (a.g_logw_e) a.g_logw_e[rk] += dlw;
+    if (a.g_tau)
+      for (int q = 0; q < d; ++q) a.g_tau[(size_t)rk * d + q] += dt[q];
+  } else if (a.g_logw_p) {
+    a.g_logw_p[rk - a.E] += dlw;
+  }
+}
+
+// abar += the pose terms of the step's costs (incidence lists)
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_unroll_gather(SpArgs a) {
+  constexpr int d = GroupTraits<G>::d;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p >= g.npose) return;
+  const int gp = g.pose0 + p;
+  double v[d];
+  for (int r = 0; r < d; ++r) v[r] = 0.0;
+  for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+    const int sl = a.inc_slot[s];
+    const double* o = a.hvp + (size_t)(sl >> 1) * 2 * d + (sl & 1) * d;
+    for (int r = 0; r < d; ++r) v[r] += o[r];
+  }
+  for (int r = 0; r < d; ++r) a.uout[(size_t)gp * d + r] += v[r];
+}
+
 // backward: b = seed in permuted order (padding zero)
 __global__ void __launch_bounds__(kBT) k_sp_seed(SpArgs a, int d) {
   const int b = blockIdx.y;
@@ -1340,6 +1485,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sp_off[15] = off; off += align256((size_t)B * 4 * sizeof(double));             // dogleg state per graph
   p->ws_bytes = off;
   p->bwd_bytes = off;
+  p->traj_off = (long long)fac;   // doubles: kept iterates theta_0 .. theta_{K-1}
+  if (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) fac += (size_t)p->opt.iterations * p->V * p->sz;
   p->fac_bytes = (size_t)fac * sizeof(double);
   return DNLS_OK;
 }
@@ -1437,6 +1584,7 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
   const bool adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) != 0;
   const bool dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) != 0;
+  const bool keep = (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) != 0;
   const int sz = GroupTraits<G>::sz;
   hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
   if (adaptive) hipLaunchKernelGGL(k_sp_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
@@ -1446,6 +1594,11 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
     const double lam = final_lin ? 0.0 : p->opt.lambda;
     const int lam_g = (adaptive && !final_lin) ? 1 : 0;
     a.it = it;
+    if (keep && !final_lin) {
+      SpArgs ak = a;
+      ak.pose_bak = a.factor + p->traj_off + (size_t)it * p->V * sz;
+      hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, ak, sz);
+    }
     const bool lin32 = mixed && !final_lin;
     const bool refine_now = lin32 && a.refine > 0 &&
                             (p->opt.refine_last == 0 || it >= p->opt.iterations - p->opt.refine_last);
@@ -1558,6 +1711,46 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
     // the factor cache again holds the factor of H* (same kernels and inputs
     // as the final linearisation of the solve)
     hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+    hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, 0.0, 1, 0);
+    sp_factor<G>(p, a, st);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
+  if (s->mode == DNLS_BACKWARD_UNROLL) {
+    constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+    const dim3 g_blk((max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::nod) + kBT - 1) / kBT, B);
+    const dim3 g_zero(256, B);
+    const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
+    char* w = static_cast<char*>(s->workspace);
+    int* fstat = reinterpret_cast<int*>(w + p->sp_off[14]);
+    hipLaunchKernelGGL(k_sp_grads_zero<G>, g_cost, dim3(kBT), 0, st, a, 0);
+    hipLaunchKernelGGL(k_sp_unroll_adj, g_pose, dim3(kBT), 0, st, a, d, 1);
+    for (int t = p->opt.iterations - 1; t >= p->opt.iterations - s->steps; --t) {
+      // the step's system at theta_t, factored in the factor cache (a failure
+      // marks the graph in a status copy of the workspace)
+      SpArgs at = a;
+      at.poses = a.factor + p->traj_off + (size_t)t * p->V * sz;
+      at.status = fstat;
+      hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, at, at.ws64);
+      hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, at);
+      hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, at, (const double*)at.ws64,
+                         p->opt.lambda, 1, 0);
+      sp_factor<G>(p, at, st);
+      hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, at, 1, 2);
+      sp_sweeps(p, at, 0, st);
+      hipLaunchKernelGGL(k_sp_unroll_retr<G>, g_pose, dim3(kBT), 0, st, at);
+      sp_sweeps(p, at, 2, st);
+      hipLaunchKernelGGL(k_sp_unroll_cost<G>, g_cost, dim3(kBT), 0, st, at);
+      hipLaunchKernelGGL(k_sp_unroll_gather<G>, g_pose, dim3(kBT), 0, st, at);
+    }
+    hipLaunchKernelGGL(k_sp_grads_zero<G>, g_cost, dim3(kBT), 0, st, a, 1);
+    hipLaunchKernelGGL(k_sp_unroll_adj, g_pose, dim3(kBT), 0, st, a, d, 0);
+    if (s->adjoint)
+      HIP_TRY(hipMemcpyAsync(s->adjoint, a.uout, (size_t)p->V * d * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // the factor cache again holds the factor of H* at theta_K
+    hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+    hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
     hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
     hipLaunchKernelGGL((k_sp_assemble<G, double>), g_blk, dim3(kBT), 0, st, a, (const double*)a.ws64, 0.0, 1, 0);
     sp_factor<G>(p, a, st);
