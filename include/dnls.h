@@ -138,14 +138,14 @@ enum {
    * state: calls with this flag must not overlap on one plan.  DENSE is a
    * single launch and ignores the flag. */
   DNLS_FLAG_GRAPH = 1,
-  /* DENSE and SPARSE: Levenberg-Marquardt with adaptive damping (Sections 2 and 3),
+  /* Every solver: Levenberg-Marquardt with adaptive damping (Sections 2 and 3),
    * starting from options.lambda: after each step the float64 objective is
    * evaluated at the retracted trial point; the step is kept iff it is
    * strictly smaller than the objective at theta_t, and then lambda is
    * divided by 10, otherwise theta_t is restored and lambda is multiplied by
    * 10; lambda stays in [1e-7, 1e7], per graph.  objective[b][t] is the
-   * objective at theta_t, so a rejected step repeats it.  SCHUR:
-   * DNLS_ERR_UNSUPPORTED. */
+   * objective at theta_t, so a rejected step repeats it.  SCHUR: the same
+   * rule on cameras and points together (lambda on both diagonal blocks). */
   DNLS_FLAG_ADAPTIVE_LM = 2,
   /* DENSE and SPARSE: Powell's dogleg (Section 3 optimizers) with a per-graph trust
    * radius starting at options.trust_radius (> 0): the Gauss-Newton step of

@@ -250,6 +250,13 @@ def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None
                 w_p=torch.exp(logw_p))
 
 
+def ba_objective(g: Graph, X: torch.Tensor, pts: torch.Tensor) -> torch.Tensor:
+    """S = 1/2 sum_o rho(w_o^2 ||c_o||^2) + 1/2 sum_p w_p^2 ||c_p||^2 (Huber rho
+    on the observations, as in linearize_ba)."""
+    k = ba_costs(g, X, pts)
+    return 0.5 * k["rho"].sum() + 0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+
+
 def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None) -> Lin:
     Nc, Np = X.shape[0], pts.shape[0]
     k = ba_costs(g, X, pts, w_o, logw_p)
@@ -394,8 +401,18 @@ def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool 
                 status = NOT_PD
                 break
             dc, dp = schur_solve(lin, L, Ci, EC, lin.g, lin.gp)
-            X = g.G.retract(X, -dc.reshape(-1, 6))
-            pts = pts - dp
+            X_trial = g.G.retract(X, -dc.reshape(-1, 6))
+            pts_trial = pts - dp
+            if adaptive:
+                # the same rule as for pose graphs, on cameras and points together
+                lambdas.append(lam)
+                s_trial = float(ba_objective(g, X_trial, pts_trial))
+                if s_trial < float(lin.S):
+                    X, pts, lam = X_trial, pts_trial, max(lam / 10.0, LAMBDA_MIN)
+                else:
+                    lam = min(lam * 10.0, LAMBDA_MAX)
+            else:
+                X, pts = X_trial, pts_trial
         else:
             delta, L = pose_graph_step(lin, lam)
             if delta is None:

@@ -73,6 +73,12 @@ struct BAArgs {
   double* factor;
   int K, it, npad_max, nx_lin;
   double lambda;
+  // DNLS_FLAG_ADAPTIVE_LM: lambda per problem (read by the point and Schur
+  // kernels when set), theta_t backup, trial step rejected
+  double* lam_g;
+  double* bak_c;
+  double* bak_p;
+  int* rej;
   // DNLS_FLAG_PAIR: nway co-resident workgroups per problem share the factorisation
   unsigned long long* pair_ctr;
   unsigned long long pair_base;
@@ -223,6 +229,7 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
   const int b = blockIdx.y;
   const BADesc g = a.bd[b];
   if (a.frozen[b]) return;
+  if (a.lam_g) lambda = a.lam_g[b];
   const int lp = blockIdx.x * kBT + threadIdx.x;
   if (lp >= g.npt) return;
   const int pt = g.pt0 + lp;
@@ -284,6 +291,7 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
   const int b = blockIdx.y;
   const BADesc g = a.bd[b];
   if (a.frozen[b]) return;
+  if (a.lam_g) lambda = a.lam_g[b];
   double* A = a.factor + g.fac_off;
   const int npad = g.npad;
   const S* rec = reinterpret_cast<const S*>(a.orec);
@@ -484,6 +492,51 @@ __global__ void __launch_bounds__(kBT) k_ba_update(BAArgs a) {
     for (int j = 0; j < 3; ++j) a.pts[(size_t)pt * 3 + j] -= Ci[j * 3] * r[0] + Ci[j * 3 + 1] * r[1] + Ci[j * 3 + 2] * r[2];
   }
   if (t < g.ncam) retract_minus<3>(a.cams + (size_t)(g.cam0 + t) * 12, dc + t * 6);
+}
+
+// adaptive damping (Levenberg-Marquardt, Section 3 optimizers): the step is
+// kept iff the float64 objective at the trial point is strictly below S(theta_t)
+// (lambda / 10, floor 1e-7), else cameras and points return to theta_t
+// (lambda x 10, ceiling 1e7)
+constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;
+
+__global__ void k_ba_lam_init(BAArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) a.lam_g[b] = a.lambda;
+}
+
+// theta_t -> backup (dir = 0) or backup -> theta_t for rejected steps (dir = 1)
+__global__ void __launch_bounds__(kBT) k_ba_backup(BAArgs a, int dir) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b] || (dir && !a.rej[b])) return;
+  for (int u = blockIdx.x * kBT + threadIdx.x; u < g.ncam * 12; u += gridDim.x * kBT) {
+    const size_t k = (size_t)g.cam0 * 12 + u;
+    if (dir) a.cams[k] = a.bak_c[k];
+    else a.bak_c[k] = a.cams[k];
+  }
+  for (int u = blockIdx.x * kBT + threadIdx.x; u < g.npt * 3; u += gridDim.x * kBT) {
+    const size_t k = (size_t)g.pt0 * 3 + u;
+    if (dir) a.pts[k] = a.bak_p[k];
+    else a.bak_p[k] = a.pts[k];
+  }
+}
+
+// trial objective from the partials of k_ba_lin<double> at the retracted
+// point against S(theta_t) (thread per problem)
+__global__ void k_ba_decide(BAArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  a.rej[b] = 0;
+  if (a.frozen[b]) return;
+  double S = 0.0;
+  for (int k = 0; k < a.nx_lin; ++k) S += a.partial[b * a.nx_lin + k];
+  if (S < a.lastobj[b]) {
+    a.lam_g[b] = fmax(a.lam_g[b] / 10.0, kLambdaMin);
+  } else {
+    a.lam_g[b] = fmin(a.lam_g[b] * 10.0, kLambdaMax);
+    a.rej[b] = 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -760,6 +813,12 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   p->ba_off[4] = off; off += align256((size_t)B * sizeof(int));
   p->ba_off[5] = off; off += align256((size_t)B * sizeof(double));
   p->ba_off[6] = off; off += align256((size_t)Vp * 3 * sizeof(double));   // u_p (backward)
+  if (op->flags & DNLS_FLAG_ADAPTIVE_LM) {
+    p->ba_off[7] = off; off += align256((size_t)B * sizeof(double));       // lambda per problem
+    p->ba_off[8] = off; off += align256((size_t)B * sizeof(int));          // rejected
+    p->ba_off[9] = off; off += align256((size_t)p->V * 12 * sizeof(double));  // camera backup
+    p->ba_off[10] = off; off += align256((size_t)Vp * 3 * sizeof(double));    // point backup
+  }
   p->ws_bytes = off;
   p->bwd_bytes = off;
   // factor cache: Schur factors, then E, F, C^-1, g_p of the final linearisation
@@ -810,6 +869,12 @@ static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
   a.Cinv = reinterpret_cast<double*>(f + p->ba_fac_off[2]);
   a.gp = reinterpret_cast<double*>(f + p->ba_fac_off[3]);
   a.nx_lin = p->nlin_blocks;
+  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
+    a.lam_g = reinterpret_cast<double*>(w + p->ba_off[7]);
+    a.rej = reinterpret_cast<int*>(w + p->ba_off[8]);
+    a.bak_c = reinterpret_cast<double*>(w + p->ba_off[9]);
+    a.bak_p = reinterpret_cast<double*>(w + p->ba_off[10]);
+  }
 }
 
 dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
@@ -834,11 +899,15 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   const dim3 g_upd((nupd + kBT - 1) / kBT, B);
   const size_t lds = (size_t)p->npad_max * sizeof(double);
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
+  const bool adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) != 0;
+  double* lam_g = a.lam_g;
   hipLaunchKernelGGL(k_ba_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, a.status, B);
+  if (adaptive) hipLaunchKernelGGL(k_ba_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
   for (int it = 0; it <= p->opt.iterations; ++it) {
     const bool final_lin = it == p->opt.iterations;
     const double lam = final_lin ? 0.0 : p->opt.lambda;
     a.it = it;
+    a.lam_g = (adaptive && !final_lin) ? lam_g : nullptr;   // the final linearisation is undamped
     // the final (cached) linearisation is float64 in both precisions
     if (mixed && !final_lin) {
       hipLaunchKernelGGL(k_ba_lin<float>, g_lin, blk, 0, st, a);
@@ -862,7 +931,17 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
     } else {
       hipLaunchKernelGGL(k_ba_factor<false>, dim3(B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
     }
-    if (!final_lin) hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
+    if (!final_lin && adaptive) {
+      hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 0);
+      hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
+      // the trial objective (float64 records at the trial point are rewritten
+      // by the next step's linearisation anyway)
+      hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_decide, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+      hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 1);
+    } else if (!final_lin) {
+      hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
+    }
   }
   HIP_TRY(hipGetLastError());
   return DNLS_OK;

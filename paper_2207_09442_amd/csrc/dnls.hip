@@ -1034,8 +1034,6 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     if (op->solver == DNLS_SOLVER_SCHUR)
       return fail(DNLS_ERR_UNSUPPORTED, "dogleg is implemented for the pose-graph solvers");
   }
-  if ((op->flags & DNLS_FLAG_ADAPTIVE_LM) && op->solver == DNLS_SOLVER_SCHUR)
-    return fail(DNLS_ERR_UNSUPPORTED, "adaptive damping is implemented for the pose-graph solvers");
   if (op->solver == DNLS_SOLVER_SCHUR) {
     auto* p = new dnls_plan_s();
     p->B = pr->batch;

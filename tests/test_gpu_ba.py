@@ -17,9 +17,10 @@ pytestmark = pytest.mark.gpu
 rng = np.random.default_rng(5)
 
 
-def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False):
+def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False, adaptive=False):
     from paper_2207_09442_amd import Plan
-    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device, pair=pair)
+    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device, pair=pair,
+                adaptive=adaptive)
     assert plan.schedule()["pair"] == pair
     cams, pts = t(p["poses_init"]), t(p["points_init"])
     dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
@@ -36,7 +37,7 @@ def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True
     worst = dict(cam=0.0, pt=0.0, obj=0.0, grad=0.0)
     res = {}
     for b in problems:
-        r = S.solve_graph(gs[b], K, lam)
+        r = S.solve_graph(gs[b], K, lam, adaptive=adaptive)
         res[b] = r
         assert st[b] == r.status
         c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
@@ -104,3 +105,30 @@ def test_ba_ring64_full_size_fp64_and_mixed(pair):
     p = synth.bundle_adjustment(batch=4)
     _run(p, 10, 1e-3, problems=[0, 3], pair=pair)
     _run(p, 10, 1e-3, precision="mixed", problems=[0, 3], tol=1e-5, pair=pair)
+
+
+@pytest.mark.parametrize("pair", [False, True])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ba_adaptive_damping(precision, tol, pair):
+    """Adaptive Levenberg-Marquardt on the Schur path: two problems from a
+    fair start (every step kept, lambda / 10) and from a very poor one
+    (cameras 1 rad / 3 m and points 2 off: steps 3 to 8 raise the objective
+    and are refused, lambda x 10 each time, and the step at lambda = 0.1 is
+    kept).  Same cameras, points, objectives (so the same accept / reject
+    pattern) and gradients as the oracle."""
+    a = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=5)
+    b = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, cam_r=1.0, cam_t=3.0,
+                                point_sigma=2.0, seed=2)
+    p = {}
+    for k in a:
+        if k in ("group", "intrinsics", "huber_delta"):
+            p[k] = a[k]
+        elif k.endswith("_off"):
+            p[k] = np.concatenate([a[k], a[k][-1] + b[k][1:]]).astype(np.int32)
+        elif k in ("obs_cam", "prior_var"):
+            p[k] = np.concatenate([a[k], b[k] + a["pose_off"][-1]]).astype(np.int32)
+        elif k == "obs_pt":
+            p[k] = np.concatenate([a[k], b[k] + a["point_off"][-1]]).astype(np.int32)
+        else:
+            p[k] = np.concatenate([a[k], b[k]])
+    _run(p, 10, 1e-7, precision=precision, tol=tol, pair=pair, adaptive=True)

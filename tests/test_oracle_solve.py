@@ -82,6 +82,46 @@ def _small_ba(noiseless=False):
     return synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, noiseless=noiseless)
 
 
+def test_adaptive_lm_ba_follows_full_system_steps():
+    """Adaptive damping on bundle adjustment from a very poor start, replayed
+    independently: each trial step is the damped full (cameras + points)
+    system solved by numpy, the step is kept iff the objective strictly
+    decreases.  The oracle's Schur path gives the same iterates, objectives
+    and lambdas, and the run rejects six steps in a row and then recovers."""
+    p = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, cam_r=1.0, cam_t=3.0,
+                                point_sigma=2.0, seed=2)
+    g = S.graphs_of(p)[0]
+    K, lam = 10, 1e-7
+    r = S.solve_graph(g, K, lam, adaptive=True)
+    X, pts, lams, objs = g.X.clone(), g.pts.clone(), [], []
+    for _ in range(K):
+        lin = S.linearize_ba(g, X, pts)
+        objs.append(float(lin.S))
+        lams.append(lam)
+        nc, npnt = lin.H.shape[0], lin.C.shape[0]
+        Hf = np.zeros((nc + 3 * npnt, nc + 3 * npnt))
+        Hf[:nc, :nc] = lin.H.numpy()
+        Hf[:nc, nc:] = lin.E.numpy()
+        Hf[nc:, :nc] = lin.E.numpy().T
+        for k in range(npnt):
+            Hf[nc + 3 * k: nc + 3 * k + 3, nc + 3 * k: nc + 3 * k + 3] = lin.C[k].numpy()
+        step = np.linalg.solve(Hf + lam * np.eye(Hf.shape[0]),
+                               np.concatenate([lin.g.numpy(), lin.gp.numpy().reshape(-1)]))
+        Xt = lie.SE3.retract(X, -torch.as_tensor(step[:nc]).reshape(-1, 6))
+        pt_t = pts - torch.as_tensor(step[nc:]).reshape(-1, 3)
+        if float(S.linearize_ba(g, Xt, pt_t).S) < float(lin.S):
+            X, pts, lam = Xt, pt_t, max(lam / 10.0, 1e-7)
+        else:
+            lam = min(lam * 10.0, 1e7)
+    objs.append(float(S.linearize_ba(g, X, pts).S))
+    assert r.lambdas == pytest.approx(lams, rel=1e-15)
+    assert np.allclose(r.objective, objs, rtol=1e-10, atol=0)
+    assert (lie.SE3.to_storage(r.X) - lie.SE3.to_storage(X)).abs().max() < 1e-9
+    assert (r.pts - pts).abs().max() < 1e-9
+    rejected = [objs[t + 1] == objs[t] for t in range(K)]
+    assert rejected[3:9] == [True] * 6 and not any(rejected[:3]) and not rejected[9]
+
+
 @pytest.mark.parametrize("lam", [0.0, 1e-3])
 def test_schur_step_equals_full_system(lam):
     p = _small_ba()
