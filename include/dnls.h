@@ -260,19 +260,22 @@ typedef struct {
 typedef enum {
   /* Proposition 1: u = H*^-1 v with the cached factor. */
   DNLS_BACKWARD_IMPLICIT = 0,
-  /* Direct loss minimisation (Section 4.3, Appendix G), DENSE and SPARSE: one
+  /* Direct loss minimisation (Section 4.3, Appendix G), every solver: one
    * Gauss-Newton step from theta_K on S(theta) + ||eps theta - v/2||^2,
    * (H* + 2 eps^2 I) delta = -g* + eps v, theta_direct = theta_K Exp(delta),
    * then dL/dphi = (dS/dphi(theta_K) - dS/dphi(theta_direct)) / eps for the
    * log-weights and the tangent perturbations tau, with S the objective of
    * Section 2 (costs weighted by exp(2 log w)).  A first-order estimate of
    * the implicit gradient that approaches it linearly as eps -> 0; eps <= 0
-   * or non-finite is DNLS_ERR_INVALID_ARG, SCHUR is DNLS_ERR_UNSUPPORTED.
-   * DENSE leaves the factor untouched (the new system is factored in the
-   * workspace); SPARSE factors it in the factor cache and then re-factors H*
-   * there (same kernels and inputs as the solve's final linearisation), so
-   * the cache holds the solve's factor again when the call has run.  Graphs
-   * whose status is not OK get zero gradients. */
+   * or non-finite is DNLS_ERR_INVALID_ARG.  DENSE leaves the factor
+   * untouched (the new system is factored in the workspace); SPARSE and
+   * SCHUR factor it in the factor cache and then re-factor H* there (same
+   * kernels and inputs as the solve's final linearisation), so the cache
+   * holds the solve's factor again when the call has run.  SCHUR: cameras
+   * and points take the step together (2 eps^2 on both diagonal blocks, the
+   * point seed as v's point part, zero if NULL), gradients for the
+   * observation weights (dS/dw = rho'(s) w |c|^2) and prior log-weights.
+   * Graphs whose status is not OK get zero gradients. */
   DNLS_BACKWARD_DLM = 1,
   /* Proposition 1 with the exact Hessian of S in place of the Gauss-Newton
    * one (DENSE and SPARSE): Hx = the Hessian of S(theta_K Exp(delta)) at

@@ -250,10 +250,10 @@ def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None
                 w_p=torch.exp(logw_p))
 
 
-def ba_objective(g: Graph, X: torch.Tensor, pts: torch.Tensor) -> torch.Tensor:
+def ba_objective(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None) -> torch.Tensor:
     """S = 1/2 sum_o rho(w_o^2 ||c_o||^2) + 1/2 sum_p w_p^2 ||c_p||^2 (Huber rho
     on the observations, as in linearize_ba)."""
-    k = ba_costs(g, X, pts)
+    k = ba_costs(g, X, pts, w_o, logw_p)
     return 0.5 * k["rho"].sum() + 0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
 
 
@@ -618,6 +618,47 @@ def dlm_grad_graph(g: Graph, res: GraphResult, v_pose, eps: float) -> dict:
     if g.logc_e is not None:
         out["edge_logc"] = (a[3] - b[3]) / eps
     return out
+
+
+def ba_full_system(lin: Lin) -> torch.Tensor:
+    """The bundle-adjustment normal matrix over cameras and points together,
+    [[H, E], [E^T, blockdiag(C)]], from a linearisation."""
+    nc, npt = lin.H.shape[0], lin.C.shape[0]
+    Hf = torch.zeros(nc + 3 * npt, nc + 3 * npt, dtype=DT)
+    Hf[:nc, :nc] = lin.H
+    Hf[:nc, nc:] = lin.E
+    Hf[nc:, :nc] = lin.E.T
+    Hf[nc:, nc:] = torch.block_diag(*lin.C)
+    return Hf
+
+
+def dlm_grad_ba(g: Graph, res: GraphResult, v_pose, v_pts, eps: float) -> dict:
+    """Direct-loss-minimisation gradient of a bundle-adjustment problem
+    (Section 4.3, Appendix G) for the observation weights and the prior
+    log-weights: one Gauss-Newton step on S + ||eps theta - v/2||^2 over
+    cameras and points together, (H* + 2 eps^2 I) delta = -g* + eps v on the
+    full system, theta_direct = (X Exp(delta_c), p + delta_p), then the
+    objective's parameter gradients differenced and divided by eps."""
+    if res.status != OK:
+        return dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT))
+    lin = res.lin
+    nc = lin.H.shape[0]
+    v = torch.cat([torch.as_tensor(v_pose, dtype=DT).reshape(-1),
+                   (torch.zeros(lin.gp.numel(), dtype=DT) if v_pts is None
+                    else torch.as_tensor(v_pts, dtype=DT).reshape(-1))])
+    Hf = ba_full_system(lin)
+    rhs = -torch.cat([lin.g, lin.gp.reshape(-1)]) + eps * v
+    delta = torch.linalg.solve(Hf + 2.0 * eps * eps * torch.eye(Hf.shape[0], dtype=DT), rhs)
+    X_d = g.G.retract(res.X, delta[:nc].reshape(-1, 6))
+    p_d = res.pts + delta[nc:].reshape(-1, 3)
+
+    def dS(X, pts):
+        w = g.w_o.clone().requires_grad_(True)
+        lp = g.logw_p.clone().requires_grad_(True)
+        return torch.autograd.grad(ba_objective(g, X, pts, w_o=w, logw_p=lp), [w, lp])
+
+    a, b = dS(res.X, res.pts), dS(X_d, p_d)
+    return dict(obs_w=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, delta=delta)
 
 
 def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graphs=None) -> dict:

@@ -301,9 +301,11 @@ class Plan:
         return objective, status
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,
-                    seed_pt=None, want_adjoint=False):
-        """Implicit backward of bundle adjustment: gradients of the observation
-        weights and prior log-weights for tangent seeds on cameras (and points)."""
+                    seed_pt=None, want_adjoint=False, mode="implicit", eps=1e-3):
+        """Backward of bundle adjustment: gradients of the observation weights
+        and prior log-weights for tangent seeds on cameras (and points);
+        mode "implicit" (Proposition 1) or "dlm" (direct loss minimisation
+        with this eps; the adjoint output is not written)."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {"obs_w": torch.empty(self.O, dtype=f64, device=dev),
@@ -321,6 +323,8 @@ class Plan:
         a.grad_obs_w, a.grad_prior_logw = _ptr(out["obs_w"]), _ptr(out["prior_logw"])
         a.adjoint = _ptr(out.get("adjoint"))
         a.workspace = self._aligned(self.workspace)
+        a.mode = BACKWARD_MODES[mode]
+        a.dlm_eps = float(eps)
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
         return out
 

@@ -79,6 +79,8 @@ struct BAArgs {
   double* bak_c;
   double* bak_p;
   int* rej;
+  // DLM backward: the right-hand side becomes g - dlm_eps v (v: seed_c, seed_p)
+  double dlm_eps;
   // DNLS_FLAG_PAIR: nway co-resident workgroups per problem share the factorisation
   unsigned long long* pair_ctr;
   unsigned long long pair_base;
@@ -255,7 +257,8 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) a.Cinv[(size_t)pt * 9 + k] = Ci[k];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) a.gp[(size_t)pt * 3 + k] = double(gg[k]);
+  for (int k = 0; k < 3; ++k)
+    a.gp[(size_t)pt * 3 + k] = double(gg[k]) - (a.dlm_eps > 0.0 && a.seed_p ? a.dlm_eps * a.seed_p[(size_t)pt * 3 + k] : 0.0);
   for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
     const int o = a.pt_obs[s];
     const S* r = rec + (size_t)o * kObsRec;
@@ -386,6 +389,8 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) v[i * 7] += lambda;
+    if (a.dlm_eps > 0.0)
+      for (int i = 0; i < 6; ++i) gs[i] -= a.dlm_eps * a.seed_c[(size_t)cam * 6 + i];
     double* aug = A + (size_t)npad * npad;
 #pragma unroll
     for (int i = 0; i < 6; ++i) aug[ca * 6 + i] = gs[i];
@@ -652,6 +657,49 @@ __global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
   }
 }
 
+// DLM backward (Section 4.3, Appendix G), per observation and prior: dS/dphi
+// at cameras `cams` and points `pts`, times `scale`, stored or added;
+// S = 1/2 sum rho(w^2 |c|^2) + 1/2 sum exp(2 l) |c_p|^2 gives
+// dS/dw = rho'(s) w |c|^2 and dS/dl = exp(2 l) |c_p|^2; problems marked
+// frozen get zero gradients
+__global__ void __launch_bounds__(kBT) k_ba_param_grads(BAArgs a, const double* cams, const double* pts, double scale,
+                                                        int accumulate) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  const bool zero = a.frozen[b] != 0;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t < g.nobs && a.g_w) {
+    const int o = g.obs0 + t;
+    double v = 0.0;
+    if (!zero) {
+      double c[2], Jc[12], Jp[6];
+      reproj<double>(cams + (size_t)a.obs_cam[o] * 12, pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a, c,
+                     Jc, Jp);
+      const double w = a.obs_w[o], cn2 = c[0] * c[0] + c[1] * c[1];
+      double rho, drho;
+      huber(w * w * cn2, a.delta, rho, drho);
+      v = drho * w * cn2;
+    }
+    a.g_w[o] = zero ? 0.0 : (accumulate ? a.g_w[o] : 0.0) + scale * v;
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior && a.g_logw_p) {
+    const int q = g.prior0 + threadIdx.x;
+    double v = 0.0;
+    if (!zero) {
+      double c[6], C[36];
+      prior_cost<3, double>(cams + (size_t)a.prior_var[q] * 12, a.prior_meas + (size_t)q * 12, c, C);
+      const double w2 = exp(2.0 * a.prior_logw[q]);
+      for (int r = 0; r < 6; ++r) v += w2 * c[r] * c[r];
+    }
+    a.g_logw_p[q] = zero ? 0.0 : (accumulate ? a.g_logw_p[q] : 0.0) + scale * v;
+  }
+}
+
+__global__ void k_ba_frozen_from_status(int* frozen, const int* status, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) frozen[b] = status[b] != DNLS_GRAPH_OK;
+}
+
 __global__ void k_ba_reset(int* frozen, int* status, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) {
@@ -816,9 +864,10 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   if (op->flags & DNLS_FLAG_ADAPTIVE_LM) {
     p->ba_off[7] = off; off += align256((size_t)B * sizeof(double));       // lambda per problem
     p->ba_off[8] = off; off += align256((size_t)B * sizeof(int));          // rejected
-    p->ba_off[9] = off; off += align256((size_t)p->V * 12 * sizeof(double));  // camera backup
-    p->ba_off[10] = off; off += align256((size_t)Vp * 3 * sizeof(double));    // point backup
   }
+  p->ba_off[9] = off; off += align256((size_t)p->V * 12 * sizeof(double));  // camera backup / DLM theta_direct
+  p->ba_off[10] = off; off += align256((size_t)Vp * 3 * sizeof(double));    // point backup / DLM theta_direct
+  p->ba_off[11] = off; off += align256((size_t)B * sizeof(int));            // DLM: status of its factorisations
   p->ws_bytes = off;
   p->bwd_bytes = off;
   // factor cache: Schur factors, then E, F, C^-1, g_p of the final linearisation
@@ -869,12 +918,33 @@ static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
   a.Cinv = reinterpret_cast<double*>(f + p->ba_fac_off[2]);
   a.gp = reinterpret_cast<double*>(f + p->ba_fac_off[3]);
   a.nx_lin = p->nlin_blocks;
+  a.bak_c = reinterpret_cast<double*>(w + p->ba_off[9]);
+  a.bak_p = reinterpret_cast<double*>(w + p->ba_off[10]);
   if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
     a.lam_g = reinterpret_cast<double*>(w + p->ba_off[7]);
     a.rej = reinterpret_cast<int*>(w + p->ba_off[8]);
-    a.bak_c = reinterpret_cast<double*>(w + p->ba_off[9]);
-    a.bak_p = reinterpret_cast<double*>(w + p->ba_off[10]);
   }
+}
+
+// factorisation of the assembled camera systems (and, unless final_lin, the
+// camera step): four co-resident workgroups per problem when the plan holds
+// their counters, else one
+static dnls_status launch_ba_factor(dnls_plan p, const BAArgs& a, bool final_lin, hipStream_t st) {
+  const size_t lds = (size_t)p->npad_max * sizeof(double);
+  if (p->ba_nway > 1) {
+    BAArgs am = a;
+    am.pair_ctr = p->d_pair;
+    am.pair_base = (++p->pair_epoch) << 20;
+    am.pair_spin = p->pair_spin;
+    am.nway = p->ba_nway;
+    int fl = final_lin ? 1 : 0;
+    void* args[] = {&am, &fl};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_ba_factor<true>), dim3(p->ba_nway * p->B),
+                                       dim3(kNT), args, (unsigned)lds, st));
+  } else {
+    hipLaunchKernelGGL(k_ba_factor<false>, dim3(p->B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
+  }
+  return DNLS_OK;
 }
 
 dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
@@ -918,19 +988,8 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
       hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, lam);
       hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, lam);
     }
-    if (p->ba_nway > 1) {
-      BAArgs am = a;
-      am.pair_ctr = p->d_pair;
-      am.pair_base = (++p->pair_epoch) << 20;
-      am.pair_spin = p->pair_spin;
-      am.nway = p->ba_nway;
-      int fl = final_lin ? 1 : 0;
-      void* args[] = {&am, &fl};
-      HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_ba_factor<true>), dim3(p->ba_nway * B),
-                                         dim3(kNT), args, (unsigned)lds, st));
-    } else {
-      hipLaunchKernelGGL(k_ba_factor<false>, dim3(B), dim3(kNT), lds, st, a, final_lin ? 1 : 0);
-    }
+    const dnls_status fs = launch_ba_factor(p, a, final_lin, st);
+    if (fs != DNLS_OK) return fs;
     if (!final_lin && adaptive) {
       hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 0);
       hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
@@ -952,6 +1011,7 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
     return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv and obs_w are required");
   BAArgs a = base_args(p);
   bind_ws(p, a, s->workspace, const_cast<void*>(s->factor));
+  a.lam_g = nullptr;   // the backward's systems take the damping passed to the kernels
   a.cams = const_cast<double*>(s->poses);
   a.pts = const_cast<double*>(s->points);
   a.obs_uv = s->obs_uv;
@@ -970,6 +1030,49 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
   const int nobs = std::max(max_of(p->bd, &BADesc::nobs), 1);
   const dim3 g_obs((nobs + kBT - 1) / kBT, B);
   const size_t lds = (size_t)p->npad_max * sizeof(double);
+  if (s->mode == DNLS_BACKWARD_DLM) {
+    // one Gauss-Newton step from theta_K on S + ||eps theta - v/2||^2:
+    // (H* + 2 eps^2 I) delta = -g* + eps v (cameras and points), by the solve's
+    // Schur kernels with the right-hand side g* - eps v (so they produce
+    // -delta and their update lands on theta_direct = theta_K (+) delta), in
+    // copies of the cameras and points; the factor cache is then rebuilt at
+    // theta_K by the same kernels as the solve's final linearisation
+    const double eps = s->dlm_eps;
+    const dim3 g_lin(p->nlin_blocks, B);
+    const dim3 g_blk((max_of(p->bd, &BADesc::nblk) + kSchurWaves - 1) / kSchurWaves, B);
+    const int nupd = std::max(max_of(p->bd, &BADesc::npt), max_of(p->bd, &BADesc::ncam));
+    const dim3 g_upd((nupd + kBT - 1) / kBT, B);
+    char* w = static_cast<char*>(s->workspace);
+    a.status = reinterpret_cast<int*>(w + p->ba_off[11]);   // the caller's status stays untouched
+    a.objective = a.lastobj;                                   // objective slot of the factor kernel
+    a.K = 0;
+    a.it = 0;
+    hipLaunchKernelGGL(k_ba_frozen_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, s->status, B);
+    hipLaunchKernelGGL(k_ba_param_grads, g_obs, blk, 0, st, a, (const double*)a.cams, (const double*)a.pts, 1.0 / eps,
+                       0);
+    BAArgs ad = a;
+    ad.dlm_eps = eps;
+    hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, ad);
+    hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, ad, 2.0 * eps * eps);
+    hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, ad, 2.0 * eps * eps);
+    dnls_status fs = launch_ba_factor(p, ad, false, st);
+    if (fs != DNLS_OK) return fs;
+    HIP_TRY(hipMemcpyAsync(a.bak_c, a.cams, (size_t)p->V * 12 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(a.bak_p, a.pts, (size_t)p->Vp * 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ad.cams = a.bak_c;
+    ad.pts = a.bak_p;
+    hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, ad);
+    hipLaunchKernelGGL(k_ba_param_grads, g_obs, blk, 0, st, ad, (const double*)a.bak_c, (const double*)a.bak_p,
+                       -1.0 / eps, 1);
+    hipLaunchKernelGGL(k_ba_frozen_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, s->status, B);
+    hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
+    hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, 0.0);
+    hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, 0.0);
+    fs = launch_ba_factor(p, a, true, st);
+    if (fs != DNLS_OK) return fs;
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   hipLaunchKernelGGL(k_ba_bwd_cam, dim3(B), dim3(kNT), lds, st, a);
   hipLaunchKernelGGL(k_ba_bwd_pt, g_pt, blk, 0, st, a);
   hipLaunchKernelGGL(k_ba_bwd_obs, g_obs, blk, 0, st, a);

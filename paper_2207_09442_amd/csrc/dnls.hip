@@ -1357,8 +1357,6 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
       return fail(DNLS_ERR_INVALID_ARG, "sweeps must be in [0, 64]");
   }
   if (s->mode == DNLS_BACKWARD_DLM) {
-    if (p->opt.solver == DNLS_SOLVER_SCHUR)
-      return fail(DNLS_ERR_UNSUPPORTED, "the DLM backward is implemented for the pose-graph solvers");
     if (!(s->dlm_eps > 0.0) || !std::isfinite(s->dlm_eps))
       return fail(DNLS_ERR_INVALID_ARG, "dlm_eps must be positive and finite");
   }

@@ -446,6 +446,50 @@ def test_dlm_step_minimises_regularised_gauss_newton_model():
     assert np.abs(got - want).max() < 1e-6 * np.abs(want).max()
 
 
+def test_dlm_ba_gradient_tends_linearly_to_implicit():
+    """Bundle adjustment: the DLM estimate for the observation weights and
+    prior log-weights approaches the implicit gradient (pinned above by
+    finite differences) linearly in eps, with camera and point seeds.  The
+    Huber reweighting converges linearly, so the solve runs to |g| ~ 1e-9
+    (DLM takes theta_K as a stationary point; a residual gradient adds a
+    |g| / eps term)."""
+    p = _small_ba()
+    g = S.graphs_of(p)[0]
+    res = S.solve_graph(g, 100, 0.0)
+    assert float(res.lin.g.norm()) < 1e-8
+    vc = torch.as_tensor(rng.normal(size=(g.X.shape[0], 6)), dtype=DT)
+    vp = torch.as_tensor(rng.normal(size=(g.pts.shape[0], 3)), dtype=DT)
+    gi = S.implicit_grad_graph(g, res, vc, vp)
+    ref = torch.cat([gi["obs_w"], gi["prior_logw"]])
+
+    def gap(eps):
+        gd = S.dlm_grad_ba(g, res, vc, vp, eps)
+        return float((torch.cat([gd["obs_w"], gd["prior_logw"]]) - ref).norm() / ref.norm())
+
+    g2, g3, g4 = gap(1e-2), gap(1e-3), gap(1e-4)
+    assert g2 < 0.05
+    assert 0.07 < g3 / g2 < 0.13 and 0.07 < g4 / g3 < 0.13
+
+
+def test_dlm_ba_step_is_the_schur_solution_of_the_regularised_system():
+    """The DLM step over cameras and points equals the oracle's Schur solve
+    of the same system (H* + 2 eps^2 I, right-hand side -g* + eps v), a
+    different route than the full-system solve the DLM gradient uses."""
+    p = _small_ba()
+    g = S.graphs_of(p)[0]
+    res = S.solve_graph(g, 6, 1e-3)
+    vc = rng.normal(size=(g.X.shape[0], 6))
+    vp = rng.normal(size=(g.pts.shape[0], 3))
+    eps = 0.5
+    gd = S.dlm_grad_ba(g, res, vc, vp, eps)
+    lin = res.lin
+    L, Ci, EC = S.schur_factor(lin, 2.0 * eps * eps)
+    dc, dp = S.schur_solve(lin, L, Ci, EC, -lin.g + eps * torch.as_tensor(vc.reshape(-1)),
+                           -lin.gp + eps * torch.as_tensor(vp))
+    ref = torch.cat([dc, dp.reshape(-1)])
+    assert float((gd["delta"] - ref).norm() / ref.norm()) < 1e-10
+
+
 def test_dlm_failed_graph_gets_zero_gradient():
     p = synth.walk_se3(batch=1, n_poses=6, n_loops=2, seed=7)
     g = S.graphs_of(p)[0]
