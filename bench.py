@@ -222,6 +222,10 @@ def main():
         solver = args.solver
     p = W["fn"](**W["kwargs"])
     ba = solver == "schur"
+    if ba and args.backward not in ("implicit", "dlm"):
+        raise SystemExit(f"--backward {args.backward}: the Schur solver has the implicit and DLM backward modes")
+    if ba and args.dogleg is not None:
+        raise SystemExit("--dogleg: the Schur solver has fixed and adaptive damping")
     B = len(p["pose_off"]) - 1
     t = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.float64, device=dev).contiguous()
     init, gt = t(p["poses_init"]), t(p["poses_gt"])
@@ -259,7 +263,8 @@ def main():
 
         def backward(st):
             if ba:
-                return plan.backward_ba(poses, pts, status=st, seed_cam=seed, **aux)
+                return plan.backward_ba(poses, pts, status=st, seed_cam=seed, mode=args.backward, eps=args.dlm_eps,
+                                        **aux)
             return plan.backward(poses, *aux, st, seed, mode=args.backward, eps=args.dlm_eps, sweeps=args.sweeps,
                                  steps=args.unroll_steps)
 
