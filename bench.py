@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--no-pair", action="store_true",
                     help="dense solver: one workgroup per graph even where a co-resident pair per graph fits")
     ap.add_argument("--dogleg", type=float, default=None, metavar="RADIUS",
-                    help="Powell's dogleg with this initial trust radius (pose-graph solvers)")
+                    help="Powell's dogleg with this initial trust radius")
     ap.add_argument("--backward", choices=["implicit", "dlm", "exact", "unroll"], default="implicit",
                     help="backward mode: implicit (Proposition 1), direct loss minimisation, implicit with "
                          "the exact Hessian, or unrolled through the last --unroll-steps steps (pose-graph "
@@ -224,8 +224,6 @@ def main():
     ba = solver == "schur"
     if ba and args.backward not in ("implicit", "dlm"):
         raise SystemExit(f"--backward {args.backward}: the Schur solver has the implicit and DLM backward modes")
-    if ba and args.dogleg is not None:
-        raise SystemExit("--dogleg: the Schur solver has fixed and adaptive damping")
     B = len(p["pose_off"]) - 1
     t = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.float64, device=dev).contiguous()
     init, gt = t(p["poses_init"]), t(p["poses_gt"])

@@ -147,7 +147,7 @@ enum {
    * objective at theta_t, so a rejected step repeats it.  SCHUR: the same
    * rule on cameras and points together (lambda on both diagonal blocks). */
   DNLS_FLAG_ADAPTIVE_LM = 2,
-  /* DENSE and SPARSE: Powell's dogleg (Section 3 optimizers) with a per-graph trust
+  /* Every solver: Powell's dogleg (Section 3 optimizers) with a per-graph trust
    * radius starting at options.trust_radius (> 0): the Gauss-Newton step of
    * H + lambda I if its norm is within the radius, else the gradient cut at
    * the boundary if the Cauchy point alpha g (alpha = g^T g / g^T H g) lies
@@ -157,8 +157,10 @@ enum {
    * (g^T delta - 1/2 delta^T (H + lambda I) delta) the radius becomes
    * ||delta|| / 4 if rho < 1/4 (or is not a number) and min(2 radius, 1e4)
    * if rho > 3/4 for a step on the boundary.  Excludes
-   * DNLS_FLAG_ADAPTIVE_LM; SCHUR: DNLS_ERR_UNSUPPORTED.  The mixed path
-   * linearises in float64 as well for g and the model. */
+   * DNLS_FLAG_ADAPTIVE_LM.  SCHUR: over cameras and points together (the
+   * Gauss-Newton point from the Schur solve, the model's products matrix-free
+   * from float64 records).  The mixed path linearises in float64 as well for
+   * g and the model (SCHUR: every step in float64). */
   DNLS_FLAG_DOGLEG = 4,
   /* DENSE and SPARSE, fixed damping (not with DNLS_FLAG_ADAPTIVE_LM or
    * DNLS_FLAG_DOGLEG): dnls_solve also stores the iterates theta_0 ..

@@ -401,6 +401,23 @@ def solve_graph(g: Graph, iterations: int, lam: float, tau=None, adaptive: bool 
                 status = NOT_PD
                 break
             dc, dp = schur_solve(lin, L, Ci, EC, lin.g, lin.gp)
+            if radius is not None:
+                # the dogleg over cameras and points together (full system)
+                radii.append(radius)
+                nc = lin.H.shape[0]
+                full = Lin(S=lin.S, H=ba_full_system(lin), g=torch.cat([lin.g, lin.gp.reshape(-1)]))
+                delta, boundary, pred = dogleg_step(full, None, torch.cat([dc, dp.reshape(-1)]), lam, radius)
+                X_trial = g.G.retract(X, -delta[:nc].reshape(-1, 6))
+                pts_trial = pts - delta[nc:].reshape(-1, 3)
+                s_trial = float(ba_objective(g, X_trial, pts_trial))
+                rho = (float(lin.S) - s_trial) / pred
+                if s_trial < float(lin.S):
+                    X, pts = X_trial, pts_trial
+                if not rho >= 0.25:
+                    radius = 0.25 * float(delta.norm())
+                elif rho > 0.75 and boundary:
+                    radius = min(2.0 * radius, RADIUS_MAX)
+                continue
             X_trial = g.G.retract(X, -dc.reshape(-1, 6))
             pts_trial = pts - dp
             if adaptive:

@@ -139,7 +139,7 @@ class Plan:
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
                  graph: bool = False, adaptive: bool = False, dogleg: float | None = None,
                  keep_iterates: bool = False, pair: bool = False, refine_last: int = 0):
-        """dogleg: initial trust radius of Powell's dogleg (pose-graph solvers), or None;
+        """dogleg: initial trust radius of Powell's dogleg, or None;
         keep_iterates: store theta_0 .. theta_{K-1} for the unrolled backward;
         pair: dense solver, two co-resident workgroups per graph when they fit;
         refine_last: mixed precision, refinement sweeps in the last steps only

@@ -81,6 +81,16 @@ struct BAArgs {
   int* rej;
   // DLM backward: the right-hand side becomes g - dlm_eps v (v: seed_c, seed_p)
   double dlm_eps;
+  // DNLS_FLAG_DOGLEG (float64 records): point step, camera gradient, J x per
+  // observation, (H + lambda I) x, per-problem state (radius, predicted
+  // decrease, |delta|, on the boundary)
+  double* dp;
+  double* gc;
+  double* yo;
+  double* hc;
+  double* hp;
+  double* dl;
+  double radius0;
   // DNLS_FLAG_PAIR: nway co-resident workgroups per problem share the factorisation
   unsigned long long* pair_ctr;
   unsigned long long pair_base;
@@ -544,6 +554,247 @@ __global__ void k_ba_decide(BAArgs a, int B) {
   }
 }
 
+// Powell's dogleg over cameras and points together (Section 3 optimizers):
+// the Gauss-Newton step of H + lambda I if |delta| <= radius, else the
+// gradient cut at the boundary if the Cauchy point lies outside, else the
+// boundary point of the path from the Cauchy point to the Gauss-Newton step;
+// kept iff the float64 objective strictly decreases; with rho = actual /
+// predicted decrease the radius becomes |delta| / 4 if rho < 1/4 (or
+// undefined) and min(2 radius, 1e4) if rho > 3/4 on the boundary
+constexpr double kRadiusMax = 1e4;
+
+__global__ void k_ba_dl_init(BAArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) a.dl[4 * b] = a.radius0;
+}
+
+// point part of the Gauss-Newton step, C^-1 (g_p - E^T dc), and the camera
+// gradient sum J~c^T r~ + priors (thread per point / camera)
+__global__ void __launch_bounds__(kBT) k_ba_dl_gn(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  const double* dc = a.dc + (size_t)b * a.npad_max;
+  if (t < g.npt) {
+    const int pt = g.pt0 + t;
+    double r[3] = {a.gp[(size_t)pt * 3], a.gp[(size_t)pt * 3 + 1], a.gp[(size_t)pt * 3 + 2]};
+    for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+      const int o = a.pt_obs[s];
+      const double* Eo = a.E + (size_t)o * 18;
+      const double* d = dc + (a.obs_cam[o] - g.cam0) * 6;
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < 6; ++i) acc += Eo[i * 3 + j] * d[i];
+        r[j] -= acc;
+      }
+    }
+    const double* Ci = a.Cinv + (size_t)pt * 9;
+    for (int j = 0; j < 3; ++j)
+      a.dp[(size_t)pt * 3 + j] = Ci[j * 3] * r[0] + Ci[j * 3 + 1] * r[1] + Ci[j * 3 + 2] * r[2];
+  }
+  if (t < g.ncam) {
+    const int cam = g.cam0 + t;
+    const double* rec = reinterpret_cast<const double*>(a.orec);
+    double gs[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+      const double* r = rec + (size_t)a.cam_obs[s] * kObsRec;
+      for (int i = 0; i < 6; ++i) gs[i] += r[i] * r[18] + r[6 + i] * r[19];
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      if (a.prior_var[q] != cam) continue;
+      const double* pr = a.prec + (size_t)q * kPriorRec;
+      for (int i = 0; i < 6; ++i)
+        for (int k = 0; k < 6; ++k) gs[i] += pr[k * 6 + i] * pr[36 + k];
+    }
+    for (int i = 0; i < 6; ++i) a.gc[(size_t)cam * 6 + i] = gs[i];
+  }
+}
+
+// y_o = J~c x_c + J~p x_p per observation; x = (camera part `xc` with the
+// per-problem layout of dc when cam_local, else global [Vc][6]; points [Vp][3])
+__global__ void __launch_bounds__(kBT) k_ba_dl_jx(BAArgs a, const double* xc, int cam_local, const double* xp) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t >= g.nobs) return;
+  const int o = g.obs0 + t;
+  const double* r = reinterpret_cast<const double*>(a.orec) + (size_t)o * kObsRec;
+  const double* x = cam_local ? xc + (size_t)b * a.npad_max + (a.obs_cam[o] - g.cam0) * 6 : xc + (size_t)a.obs_cam[o] * 6;
+  const double* q = xp + (size_t)a.obs_pt[o] * 3;
+  for (int k = 0; k < 2; ++k) {
+    double acc = 0.0;
+    for (int i = 0; i < 6; ++i) acc += r[k * 6 + i] * x[i];
+    for (int j = 0; j < 3; ++j) acc += r[12 + k * 3 + j] * q[j];
+    a.yo[(size_t)o * 2 + k] = acc;
+  }
+}
+
+// (H + lambda I) x from y_o: cameras (with the priors) into hc, points into hp
+__global__ void __launch_bounds__(kBT) k_ba_dl_hx(BAArgs a, const double* xc, int cam_local, const double* xp,
+                                                  double lambda) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  const double* rec = reinterpret_cast<const double*>(a.orec);
+  if (t < g.ncam) {
+    const int cam = g.cam0 + t;
+    const double* x = cam_local ? xc + (size_t)b * a.npad_max + t * 6 : xc + (size_t)cam * 6;
+    double h[6];
+    for (int i = 0; i < 6; ++i) h[i] = lambda * x[i];
+    for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+      const int o = a.cam_obs[s];
+      const double* r = rec + (size_t)o * kObsRec;
+      const double y0 = a.yo[(size_t)o * 2], y1 = a.yo[(size_t)o * 2 + 1];
+      for (int i = 0; i < 6; ++i) h[i] += r[i] * y0 + r[6 + i] * y1;
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      if (a.prior_var[q] != cam) continue;
+      const double* pr = a.prec + (size_t)q * kPriorRec;
+      for (int k = 0; k < 6; ++k) {
+        double cx = 0.0;
+        for (int j = 0; j < 6; ++j) cx += pr[k * 6 + j] * x[j];
+        for (int i = 0; i < 6; ++i) h[i] += pr[k * 6 + i] * cx;
+      }
+    }
+    for (int i = 0; i < 6; ++i) a.hc[(size_t)cam * 6 + i] = h[i];
+  }
+  if (t < g.npt) {
+    const int pt = g.pt0 + t;
+    double h[3];
+    for (int j = 0; j < 3; ++j) h[j] = lambda * xp[(size_t)pt * 3 + j];
+    for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+      const int o = a.pt_obs[s];
+      const double* r = rec + (size_t)o * kObsRec;
+      const double y0 = a.yo[(size_t)o * 2], y1 = a.yo[(size_t)o * 2 + 1];
+      for (int j = 0; j < 3; ++j) h[j] += r[12 + j] * y0 + r[15 + j] * y1;
+    }
+    for (int j = 0; j < 3; ++j) a.hp[(size_t)pt * 3 + j] = h[j];
+  }
+}
+
+// per-problem reductions over cameras then points: sum f(u, v, w) of three
+// vectors given by (camera part, point part) with the camera layouts above
+struct DlVec {
+  const double* c;
+  int cam_local;
+  const double* p;
+};
+
+__device__ __forceinline__ double dl_at(const BAArgs& a, const BADesc& g, int b, const DlVec& v, int u) {
+  const int nc = g.ncam * 6;
+  if (u < nc) return v.cam_local ? v.c[(size_t)b * a.npad_max + u] : v.c[(size_t)g.cam0 * 6 + u];
+  return v.p[(size_t)g.pt0 * 3 + (u - nc)];
+}
+
+// the dogleg step (one workgroup per problem): Gauss-Newton step in (dc, dp),
+// g in (gc, gp), (H + lambda I) g in (hc, hp); the chosen step replaces (dc, dp)
+__global__ void __launch_bounds__(kBT) k_ba_dogleg(BAArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.x;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const DlVec X{a.dc, 1, a.dp}, Gv{a.gc, 0, a.gp}, HG{a.hc, 0, a.hp};
+  const int n = g.ncam * 6 + g.npt * 3, nc = g.ncam * 6;
+  auto put = [&](int u, double v) {
+    if (u < nc) a.dc[(size_t)b * a.npad_max + u] = v;
+    else a.dp[(size_t)g.pt0 * 3 + (u - nc)] = v;
+  };
+  const double radius = a.dl[4 * b];
+  double p0 = 0.0;
+  for (int u = threadIdx.x; u < n; u += kBT) {
+    const double x = dl_at(a, g, b, X, u);
+    p0 += x * x;
+  }
+  const double n_gn = ::sqrt(block_sum_ba(p0, red));
+  int boundary = 0;
+  if (!(n_gn <= radius)) {
+    boundary = 1;
+    double p1 = 0.0, p2 = 0.0;
+    for (int u = threadIdx.x; u < n; u += kBT) {
+      const double gu = dl_at(a, g, b, Gv, u);
+      p1 += gu * gu;
+      p2 += gu * dl_at(a, g, b, HG, u);
+    }
+    const double gg = block_sum_ba(p1, red);
+    const double gHg = block_sum_ba(p2, red);
+    const double alpha = gg / gHg;
+    if (alpha * ::sqrt(gg) >= radius) {
+      const double sc = radius / ::sqrt(gg);
+      for (int u = threadIdx.x; u < n; u += kBT) put(u, sc * dl_at(a, g, b, Gv, u));
+    } else {
+      double q1 = 0.0, q2 = 0.0;
+      for (int u = threadIdx.x; u < n; u += kBT) {
+        const double sd = alpha * dl_at(a, g, b, Gv, u), dd = dl_at(a, g, b, X, u) - sd;
+        q1 += dd * dd;
+        q2 += sd * dd;
+      }
+      const double qa = block_sum_ba(q1, red);
+      const double qb = 2.0 * block_sum_ba(q2, red);
+      const double qc = alpha * alpha * gg - radius * radius;
+      const double beta = (-qb + ::sqrt(qb * qb - 4.0 * qa * qc)) / (2.0 * qa);
+      for (int u = threadIdx.x; u < n; u += kBT) {
+        const double sd = alpha * dl_at(a, g, b, Gv, u);
+        put(u, sd + beta * (dl_at(a, g, b, X, u) - sd));
+      }
+    }
+  }
+  if (threadIdx.x == 0) a.dl[4 * b + 3] = boundary;
+}
+
+// predicted decrease g^T delta - 1/2 delta^T (H + lambda I) delta and |delta|
+// (delta in (dc, dp), (H + lambda I) delta in (hc, hp)), one workgroup per problem
+__global__ void __launch_bounds__(kBT) k_ba_dl_pred(BAArgs a) {
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.x;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const DlVec X{a.dc, 1, a.dp}, Gv{a.gc, 0, a.gp}, HX{a.hc, 0, a.hp};
+  const int n = g.ncam * 6 + g.npt * 3;
+  double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+  for (int u = threadIdx.x; u < n; u += kBT) {
+    const double x = dl_at(a, g, b, X, u);
+    r1 += dl_at(a, g, b, Gv, u) * x;
+    r2 += x * dl_at(a, g, b, HX, u);
+    r3 += x * x;
+  }
+  const double s1 = block_sum_ba(r1, red);
+  const double s2 = block_sum_ba(r2, red);
+  const double s3 = block_sum_ba(r3, red);
+  if (threadIdx.x == 0) {
+    a.dl[4 * b + 1] = s1 - 0.5 * s2;
+    a.dl[4 * b + 2] = ::sqrt(s3);
+  }
+}
+
+// theta <- theta (-) delta for cameras and points (delta in (dc, dp))
+__global__ void __launch_bounds__(kBT) k_ba_dl_apply(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t < g.npt)
+    for (int j = 0; j < 3; ++j) a.pts[(size_t)(g.pt0 + t) * 3 + j] -= a.dp[(size_t)(g.pt0 + t) * 3 + j];
+  if (t < g.ncam) retract_minus<3>(a.cams + (size_t)(g.cam0 + t) * 12, a.dc + (size_t)b * a.npad_max + t * 6);
+}
+
+// keep the trial step iff the objective decreased; radius update (thread per problem)
+__global__ void k_ba_dl_decide(BAArgs a, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  a.rej[b] = 0;
+  if (a.frozen[b]) return;
+  double S = 0.0;
+  for (int k = 0; k < a.nx_lin; ++k) S += a.partial[b * a.nx_lin + k];
+  const double s_t = a.lastobj[b];
+  const double rho = (s_t - S) / a.dl[4 * b + 1];
+  if (!(S < s_t)) a.rej[b] = 1;
+  if (!(rho >= 0.25)) a.dl[4 * b] = 0.25 * a.dl[4 * b + 2];
+  else if (rho > 0.75 && a.dl[4 * b + 3] != 0.0) a.dl[4 * b] = fmin(2.0 * a.dl[4 * b], kRadiusMax);
+}
+
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
@@ -861,9 +1112,15 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   p->ba_off[4] = off; off += align256((size_t)B * sizeof(int));
   p->ba_off[5] = off; off += align256((size_t)B * sizeof(double));
   p->ba_off[6] = off; off += align256((size_t)Vp * 3 * sizeof(double));   // u_p (backward)
-  if (op->flags & DNLS_FLAG_ADAPTIVE_LM) {
+  if (op->flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG)) {
     p->ba_off[7] = off; off += align256((size_t)B * sizeof(double));       // lambda per problem
     p->ba_off[8] = off; off += align256((size_t)B * sizeof(int));          // rejected
+  }
+  if (op->flags & DNLS_FLAG_DOGLEG) {
+    p->ba_off[12] = off; off += align256((size_t)Vp * 3 * sizeof(double));       // point step
+    p->ba_off[13] = off; off += align256((size_t)p->V * 6 * sizeof(double) * 2);  // camera gradient, (H + lambda I) x
+    p->ba_off[14] = off; off += align256(((size_t)O * 2 + (size_t)Vp * 3) * sizeof(double));  // J x, points of (H + lambda I) x
+    p->ba_off[15] = off; off += align256((size_t)B * 4 * sizeof(double));        // dogleg state
   }
   p->ba_off[9] = off; off += align256((size_t)p->V * 12 * sizeof(double));  // camera backup / DLM theta_direct
   p->ba_off[10] = off; off += align256((size_t)Vp * 3 * sizeof(double));    // point backup / DLM theta_direct
@@ -920,9 +1177,16 @@ static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
   a.nx_lin = p->nlin_blocks;
   a.bak_c = reinterpret_cast<double*>(w + p->ba_off[9]);
   a.bak_p = reinterpret_cast<double*>(w + p->ba_off[10]);
-  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) {
-    a.lam_g = reinterpret_cast<double*>(w + p->ba_off[7]);
-    a.rej = reinterpret_cast<int*>(w + p->ba_off[8]);
+  if (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) a.lam_g = reinterpret_cast<double*>(w + p->ba_off[7]);
+  if (p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG)) a.rej = reinterpret_cast<int*>(w + p->ba_off[8]);
+  if (p->opt.flags & DNLS_FLAG_DOGLEG) {
+    a.dp = reinterpret_cast<double*>(w + p->ba_off[12]);
+    a.gc = reinterpret_cast<double*>(w + p->ba_off[13]);
+    a.hc = a.gc + (size_t)p->V * 6;
+    a.yo = reinterpret_cast<double*>(w + p->ba_off[14]);
+    a.hp = a.yo + (size_t)p->O * 2;
+    a.dl = reinterpret_cast<double*>(w + p->ba_off[15]);
+    a.radius0 = p->opt.trust_radius;
   }
 }
 
@@ -970,16 +1234,21 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   const size_t lds = (size_t)p->npad_max * sizeof(double);
   const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
   const bool adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) != 0;
+  const bool dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) != 0;
   double* lam_g = a.lam_g;
   hipLaunchKernelGGL(k_ba_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, a.status, B);
   if (adaptive) hipLaunchKernelGGL(k_ba_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
+  if (dogleg) hipLaunchKernelGGL(k_ba_dl_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
+  const int nobs = std::max(max_of(p->bd, &BADesc::nobs), 1);
+  const dim3 g_obs((nobs + kBT - 1) / kBT, B);
   for (int it = 0; it <= p->opt.iterations; ++it) {
     const bool final_lin = it == p->opt.iterations;
     const double lam = final_lin ? 0.0 : p->opt.lambda;
     a.it = it;
     a.lam_g = (adaptive && !final_lin) ? lam_g : nullptr;   // the final linearisation is undamped
-    // the final (cached) linearisation is float64 in both precisions
-    if (mixed && !final_lin) {
+    // the final (cached) linearisation is float64 in both precisions, and so
+    // is every step of the dogleg (its model uses the records)
+    if (mixed && !final_lin && !dogleg) {
       hipLaunchKernelGGL(k_ba_lin<float>, g_lin, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_point<float>, g_pt, blk, 0, st, a, lam);
       hipLaunchKernelGGL(k_ba_schur<float>, g_blk, blk, 0, st, a, lam);
@@ -990,7 +1259,20 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
     }
     const dnls_status fs = launch_ba_factor(p, a, final_lin, st);
     if (fs != DNLS_OK) return fs;
-    if (!final_lin && adaptive) {
+    if (!final_lin && dogleg) {
+      hipLaunchKernelGGL(k_ba_dl_gn, g_upd, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_dl_jx, g_obs, blk, 0, st, a, (const double*)a.gc, 0, (const double*)a.gp);
+      hipLaunchKernelGGL(k_ba_dl_hx, g_upd, blk, 0, st, a, (const double*)a.gc, 0, (const double*)a.gp, lam);
+      hipLaunchKernelGGL(k_ba_dogleg, dim3(B), blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_dl_jx, g_obs, blk, 0, st, a, (const double*)a.dc, 1, (const double*)a.dp);
+      hipLaunchKernelGGL(k_ba_dl_hx, g_upd, blk, 0, st, a, (const double*)a.dc, 1, (const double*)a.dp, lam);
+      hipLaunchKernelGGL(k_ba_dl_pred, dim3(B), blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 0);
+      hipLaunchKernelGGL(k_ba_dl_apply, g_upd, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
+      hipLaunchKernelGGL(k_ba_dl_decide, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+      hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 1);
+    } else if (!final_lin && adaptive) {
       hipLaunchKernelGGL(k_ba_backup, g_upd, blk, 0, st, a, 0);
       hipLaunchKernelGGL(k_ba_update, g_upd, blk, 0, st, a);
       // the trial objective (float64 records at the trial point are rewritten

@@ -1031,8 +1031,6 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
       return fail(DNLS_ERR_INVALID_ARG, "adaptive damping and dogleg exclude each other");
     if (!(op->trust_radius > 0.0) || !std::isfinite(op->trust_radius))
       return fail(DNLS_ERR_INVALID_ARG, "dogleg needs a positive finite trust_radius");
-    if (op->solver == DNLS_SOLVER_SCHUR)
-      return fail(DNLS_ERR_UNSUPPORTED, "dogleg is implemented for the pose-graph solvers");
   }
   if (op->solver == DNLS_SOLVER_SCHUR) {
     auto* p = new dnls_plan_s();

@@ -89,7 +89,6 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, flags=4)[0] == 1                 # dogleg without a trust radius
     assert _create(P, p, flags=4, radius=float("nan"))[0] == 1
     assert _create(P, p, flags=6, radius=1.0)[0] == 1     # dogleg and adaptive damping
-    assert _create(P, p, flags=4, radius=1.0, solver=1)[0] == 2   # dogleg: pose-graph solvers only
 
 
 def test_null_arguments():

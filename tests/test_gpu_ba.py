@@ -17,10 +17,11 @@ pytestmark = pytest.mark.gpu
 rng = np.random.default_rng(5)
 
 
-def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False, adaptive=False):
+def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False, adaptive=False,
+         dogleg=None):
     from paper_2207_09442_amd import Plan
     plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device, pair=pair,
-                adaptive=adaptive)
+                adaptive=adaptive, dogleg=dogleg)
     assert plan.schedule()["pair"] == pair
     cams, pts = t(p["poses_init"]), t(p["points_init"])
     dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
@@ -37,7 +38,7 @@ def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True
     worst = dict(cam=0.0, pt=0.0, obj=0.0, grad=0.0)
     res = {}
     for b in problems:
-        r = S.solve_graph(gs[b], K, lam, adaptive=adaptive)
+        r = S.solve_graph(gs[b], K, lam, adaptive=adaptive, dogleg_radius=dogleg)
         res[b] = r
         assert st[b] == r.status
         c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
@@ -116,6 +117,12 @@ def test_ba_adaptive_damping(precision, tol, pair):
     and are refused, lambda x 10 each time, and the step at lambda = 0.1 is
     kept).  Same cameras, points, objectives (so the same accept / reject
     pattern) and gradients as the oracle."""
+    _run(_fair_and_poor(), 10, 1e-7, precision=precision, tol=tol, pair=pair, adaptive=True)
+
+
+def _fair_and_poor():
+    """Two BA problems: the small ring from a fair start, and one from a very
+    poor start (cameras 1 rad / 3 m and points 2 off)."""
     a = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=5)
     b = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, cam_r=1.0, cam_t=3.0,
                                 point_sigma=2.0, seed=2)
@@ -131,7 +138,18 @@ def test_ba_adaptive_damping(precision, tol, pair):
             p[k] = np.concatenate([a[k], b[k] + a["point_off"][-1]]).astype(np.int32)
         else:
             p[k] = np.concatenate([a[k], b[k]])
-    _run(p, 10, 1e-7, precision=precision, tol=tol, pair=pair, adaptive=True)
+    return p
+
+
+@pytest.mark.parametrize("pair", [False, True])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+@pytest.mark.parametrize("radius", [1.0, 10.0])
+def test_ba_dogleg(radius, precision, tol, pair):
+    """Powell's dogleg over cameras and points on the Schur path: radius 1
+    keeps the first steps on the boundary (doubling), radius 10 lets the
+    poor start refuse its fourth step (radius 20 -> 4.67).  Same cameras,
+    points, objectives and gradients as the oracle's full-system dogleg."""
+    _run(_fair_and_poor(), 8, 0.0, precision=precision, tol=tol, pair=pair, dogleg=radius)
 
 
 @pytest.mark.parametrize("pair", [False, True])

@@ -122,6 +122,58 @@ def test_adaptive_lm_ba_follows_full_system_steps():
     assert rejected[3:9] == [True] * 6 and not any(rejected[:3]) and not rejected[9]
 
 
+def test_dogleg_ba_huge_radius_is_gauss_newton_and_replay():
+    """Bundle-adjustment dogleg: with a huge radius every Gauss-Newton step
+    is inside and kept, so it reproduces the plain solve; from a very poor
+    start with radius 10, an independent replay (numpy solves of the full
+    camera + point system for the Gauss-Newton point and the model) gives the
+    same objectives and radii, a refused step included."""
+    p = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=5)
+    g = S.graphs_of(p)[0]
+    a, b = S.solve_graph(g, 5, 0.0), S.solve_graph(g, 5, 0.0, dogleg_radius=1e9)
+    assert a.objective == b.objective
+    q = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, cam_r=1.0, cam_t=3.0,
+                                point_sigma=2.0, seed=2)
+    g = S.graphs_of(q)[0]
+    K, radius = 8, 10.0
+    r = S.solve_graph(g, K, 0.0, dogleg_radius=radius)
+    X, pts, objs, radii = g.X.clone(), g.pts.clone(), [], []
+    for _ in range(K):
+        lin = S.linearize_ba(g, X, pts)
+        objs.append(float(lin.S))
+        radii.append(radius)
+        Hf = S.ba_full_system(lin).numpy()
+        gv = np.concatenate([lin.g.numpy(), lin.gp.numpy().reshape(-1)])
+        dgn = np.linalg.solve(Hf, gv)
+        if np.linalg.norm(dgn) <= radius:
+            d, on_b = dgn, False
+        else:
+            on_b = True
+            alpha = gv @ gv / (gv @ Hf @ gv)
+            if alpha * np.linalg.norm(gv) >= radius:
+                d = radius / np.linalg.norm(gv) * gv
+            else:
+                sd, dd = alpha * gv, dgn - alpha * gv
+                qa, qb, qc = dd @ dd, 2 * sd @ dd, sd @ sd - radius ** 2
+                d = sd + (-qb + np.sqrt(qb * qb - 4 * qa * qc)) / (2 * qa) * dd
+        pred = gv @ d - 0.5 * d @ Hf @ d
+        nc = lin.H.shape[0]
+        Xt = lie.SE3.retract(X, -torch.as_tensor(d[:nc]).reshape(-1, 6))
+        pt_t = pts - torch.as_tensor(d[nc:]).reshape(-1, 3)
+        s_trial = float(S.linearize_ba(g, Xt, pt_t).S)
+        rho = (float(lin.S) - s_trial) / pred
+        if s_trial < float(lin.S):
+            X, pts = Xt, pt_t
+        if not rho >= 0.25:
+            radius = 0.25 * np.linalg.norm(d)
+        elif rho > 0.75 and on_b:
+            radius = min(2 * radius, 1e4)
+    objs.append(float(S.linearize_ba(g, X, pts).S))
+    assert np.allclose(r.objective, objs, rtol=1e-9, atol=0)
+    assert np.allclose(r.radii, radii, rtol=1e-9, atol=0)
+    assert any(objs[t + 1] == objs[t] for t in range(K))
+
+
 @pytest.mark.parametrize("lam", [0.0, 1e-3])
 def test_schur_step_equals_full_system(lam):
     p = _small_ba()
