@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 DEFAULT_WORKLOAD = "se3_walk64_b128"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 KERNEL_SOURCES = ["paper_2207_09442_amd/csrc/dnls.hip", "paper_2207_09442_amd/csrc/dense.hpp",
                   "paper_2207_09442_amd/csrc/costs.hpp", "paper_2207_09442_amd/csrc/pose_costs.hpp",
                   "paper_2207_09442_amd/csrc/lie.hpp"]
@@ -360,6 +361,12 @@ def main():
                      "algorithmic_flops_per_launch": solve_flops,
                      "factor_flops_algorithmic": f_alg, "factor_flops_executed": f_exec},
     }
+    traffic = line["roofline"]["traffic"]
+    if traffic:
+        # measured HBM bytes of the launch over its live duration, against the 8 TB/s peak
+        hbm = traffic / (head["fwd_ms"] * 1e-3) / 1e9
+        line["roofline"]["hbm_GBps"] = hbm
+        line["roofline"]["hbm_frac"] = hbm / PEAK_HBM_GBPS
     if main_prec == "mixed":
         f = runs["fp64"]
         line["fp64"] = {"value": graph_steps / (f["ms_step"] * 1e-3), "ms_per_step": f["ms_step"],

@@ -45,18 +45,22 @@ def test_sparse_graph_replays_match_eager(precision, refine):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_ba_graph_replays_match_eager():
+@pytest.mark.parametrize("opt", [{}, {"adaptive": True}, {"dogleg": 1.0}])
+def test_ba_graph_replays_match_eager(opt):
+    """Fixed damping, adaptive damping and the dogleg on the Schur path (their
+    decisions are taken on the device): every replay of the captured solve
+    equals the eager one bit for bit."""
     from paper_2207_09442_amd import Plan
     p = synth.bundle_adjustment(batch=2, n_cams=10, n_points=80, obs_per_point=5, seed=3)
     dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
                prior_logw=t(p["prior_logw"]))
     c0, q0 = t(p["poses_init"]), t(p["points_init"])
-    eager = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device)
+    eager = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device, **opt)
     cams, pts = c0.clone(), q0.clone()
     obj_e, st_e = eager.solve_ba(cams, pts, **dev)
     torch.cuda.synchronize()
     ref = (cams.cpu().numpy(), pts.cpu().numpy(), obj_e.cpu().numpy())
-    graph = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device, graph=True)
+    graph = Plan(p, 5, lam=1e-3, solver="schur", precision="mixed", device=c0.device, graph=True, **opt)
     cams, pts = c0.clone(), q0.clone()
     for rep in range(3):
         cams.copy_(c0)
