@@ -204,7 +204,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(graphs are independent, so a multi-GPU run would shard the batch with no "
-              "communication; this build runs on a single device).", file=sys.stderr)
+              "communication; the library runs on one device).", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:

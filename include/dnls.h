@@ -308,7 +308,7 @@ typedef enum {
  * incidence lists, the dense / Schur / supernodal block maps (symbolic
  * analysis, done once per structure).  Returns DNLS_ERR_INVALID_ARG on
  * inconsistent offsets or indices, DNLS_ERR_UNSUPPORTED on a combination
- * this build does not implement. */
+ * the library does not implement. */
 dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* problem,
                              const dnls_options* options);
 
