@@ -235,7 +235,7 @@ __device__ __forceinline__ bool inv3(const double m[9], double r[9]) {
   return det > 0.0;
 }
 
-// 2. point blocks C = sum J~p^T J~p + lambda I, g_p, C^-1, E_o = J~c^T J~p, F_o = E_o C^-1
+// 2. point blocks C = sum J~p^T J~p + lambda I, g_p, C^-1 (one thread per point)
 template <class S>
 __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
   const int b = blockIdx.y;
@@ -269,22 +269,32 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     a.gp[(size_t)pt * 3 + k] = double(gg[k]) - (a.dlm_eps > 0.0 && a.seed_p ? a.dlm_eps * a.seed_p[(size_t)pt * 3 + k] : 0.0);
-  for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
-    const int o = a.pt_obs[s];
-    const S* r = rec + (size_t)o * kObsRec;
-    double Eo[18];
+}
+
+// 2b. per observation: E_o = J~c^T J~p and F_o = E_o C^-1 of its point
+// (after k_ba_point; one thread per observation)
+template <class S>
+__global__ void __launch_bounds__(kBT) k_ba_obs_ef(BAArgs a) {
+  const int b = blockIdx.y;
+  const BADesc g = a.bd[b];
+  if (a.frozen[b]) return;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t >= g.nobs) return;
+  const int o = g.obs0 + t;
+  const S* r = reinterpret_cast<const S*>(a.orec) + (size_t)o * kObsRec;
+  const double* Ci = a.Cinv + (size_t)a.obs_pt[o] * 9;
+  double Eo[18];
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) Eo[i * 3 + j] = double(r[i] * r[12 + j] + r[6 + i] * r[15 + j]);
+    for (int j = 0; j < 3; ++j) Eo[i * 3 + j] = double(r[i] * r[12 + j] + r[6 + i] * r[15 + j]);
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        a.E[(size_t)o * 18 + i * 3 + j] = Eo[i * 3 + j];
-        a.F[(size_t)o * 18 + i * 3 + j] = Eo[i * 3] * Ci[j] + Eo[i * 3 + 1] * Ci[3 + j] + Eo[i * 3 + 2] * Ci[6 + j];
-      }
-  }
+    for (int j = 0; j < 3; ++j) {
+      a.E[(size_t)o * 18 + i * 3 + j] = Eo[i * 3 + j];
+      a.F[(size_t)o * 18 + i * 3 + j] = Eo[i * 3] * Ci[j] + Eo[i * 3 + 1] * Ci[3 + j] + Eo[i * 3 + 2] * Ci[6 + j];
+    }
 }
 
 // sum over the 64 lanes of a wave (butterfly; every lane gets the total)
@@ -1251,10 +1261,12 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
     if (mixed && !final_lin && !dogleg) {
       hipLaunchKernelGGL(k_ba_lin<float>, g_lin, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_point<float>, g_pt, blk, 0, st, a, lam);
+      hipLaunchKernelGGL(k_ba_obs_ef<float>, g_obs, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_schur<float>, g_blk, blk, 0, st, a, lam);
     } else {
       hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, lam);
+      hipLaunchKernelGGL(k_ba_obs_ef<double>, g_obs, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, lam);
     }
     const dnls_status fs = launch_ba_factor(p, a, final_lin, st);
@@ -1336,6 +1348,7 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
     ad.dlm_eps = eps;
     hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, ad);
     hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, ad, 2.0 * eps * eps);
+    hipLaunchKernelGGL(k_ba_obs_ef<double>, g_obs, blk, 0, st, ad);
     hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, ad, 2.0 * eps * eps);
     dnls_status fs = launch_ba_factor(p, ad, false, st);
     if (fs != DNLS_OK) return fs;
@@ -1349,6 +1362,7 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
     hipLaunchKernelGGL(k_ba_frozen_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.frozen, s->status, B);
     hipLaunchKernelGGL(k_ba_lin<double>, g_lin, blk, 0, st, a);
     hipLaunchKernelGGL(k_ba_point<double>, g_pt, blk, 0, st, a, 0.0);
+    hipLaunchKernelGGL(k_ba_obs_ef<double>, g_obs, blk, 0, st, a);
     hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, 0.0);
     fs = launch_ba_factor(p, a, true, st);
     if (fs != DNLS_OK) return fs;
