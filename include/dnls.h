@@ -172,7 +172,7 @@ enum {
    * graph on a pair of co-resident workgroups (cooperative launch) that
    * share every factorisation, for batches too small to fill the device;
    * otherwise (or with DNLS_FLAG_DOGLEG or Welsch edges) the one-workgroup
-   * kernel runs.  SCHUR (without DNLS_FLAG_GRAPH): four co-resident
+   * kernel runs.  SCHUR (without DNLS_FLAG_GRAPH): six co-resident
    * workgroups per problem share the camera-system factorisation when they
    * fit.  Results equal the one-workgroup path's up to rounding.  The plan
    * holds event counters: calls with this flag must not overlap on one

@@ -36,7 +36,9 @@ namespace dnls {
 namespace {
 
 constexpr int kBT = 256;
-constexpr int kBaNway = 4;          // DNLS_FLAG_PAIR: workgroups per problem sharing the camera factorisation
+constexpr int kBaNway = 6;          // DNLS_FLAG_PAIR: workgroups per problem sharing the camera factorisation
+constexpr int kBaCtr = 16;          // event counters per problem: diagonal block, then one per workgroup
+static_assert(3 + kBaNway <= kBaCtr, "BA pair counters");
 constexpr int kObsRec = 20;   // J~cam (2x6), J~pt (2x3), r~ (2)
 constexpr int kPriorRec = 42; // w C (6x6), w c (6)
 
@@ -460,7 +462,7 @@ __global__ void __launch_bounds__(kNT) k_ba_factor(BAArgs a, int final_lin) {
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
   bool ok;
   if constexpr (MULTI) {
-    unsigned long long* c = a.pair_ctr + (size_t)b * 8;
+    unsigned long long* c = a.pair_ctr + (size_t)b * kBaCtr;
     const PairSync ps{nullptr, nullptr, c + 2, c + 3, a.pair_base, role, a.nway, a.pair_spin};
     bool bail = false;
     ok = chol_dense_pair(A, A, g.npad, winv, L.dl, ps, 0, bail);
@@ -1145,7 +1147,7 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   p->ba_fac_off[3] = fb; fb += align256((size_t)Vp * 3 * sizeof(double));
   p->fac_bytes = fb;
   // DNLS_FLAG_PAIR (not with HIP-graph capture, whose replays would reuse the
-  // counter origin): four workgroups per problem share the camera-system
+  // counter origin): six workgroups per problem share the camera-system
   // factorisation when they fit on the device at once
   p->ba_nway = 1;
   p->pair_spin = pair_spin_limit();
@@ -1158,7 +1160,7 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ba_factor<true>), kNT,
                                                      lds) == hipSuccess &&
         (long long)per_cu * cus >= (long long)kBaNway * B) {
-      const size_t bytes = (size_t)B * 8 * sizeof(unsigned long long);
+      const size_t bytes = (size_t)B * kBaCtr * sizeof(unsigned long long);
       HIP_TRY(hipMalloc(reinterpret_cast<void**>(&p->d_pair), bytes));
       p->allocs.push_back(p->d_pair);
       HIP_TRY(hipMemset(p->d_pair, 0, bytes));
@@ -1201,7 +1203,7 @@ static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
 }
 
 // factorisation of the assembled camera systems (and, unless final_lin, the
-// camera step): four co-resident workgroups per problem when the plan holds
+// camera step): six co-resident workgroups per problem when the plan holds
 // their counters, else one
 static dnls_status launch_ba_factor(dnls_plan p, const BAArgs& a, bool final_lin, hipStream_t st) {
   const size_t lds = (size_t)p->npad_max * sizeof(double);

@@ -72,8 +72,8 @@ def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True
 
 @pytest.mark.parametrize("pair", [False, True])
 def test_ba_small_fp64(pair):
-    """pair: four workgroups per problem share the factorisation (one panel
-    here, so two of them have no row group and only join the barrier)."""
+    """pair: six workgroups per problem share the factorisation (one panel
+    here, so most of them have no row group and only join the barrier)."""
     p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=60, obs_per_point=4, seed=1)
     p["obs_w"] = np.exp(rng.normal(scale=0.2, size=len(p["obs_w"])))
     _run(p, 5, 1e-3, pair=pair)
@@ -101,7 +101,7 @@ def test_ba_uneven_problems_fp64():
 @pytest.mark.parametrize("pair", [False, True])
 def test_ba_ring64_full_size_fp64_and_mixed(pair):
     """4 problems x (64 cameras, 2048 points, 16384 observations), 10 LM
-    steps; pair: the 384 x 384 camera systems factored by four workgroups
+    steps; pair: the 384 x 384 camera systems factored by six workgroups
     each."""
     p = synth.bundle_adjustment(batch=4)
     _run(p, 10, 1e-3, problems=[0, 3], pair=pair)
