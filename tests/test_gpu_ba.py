@@ -204,3 +204,46 @@ def test_ba_dlm_backward(eps, pair):
         worst = max(worst, err / tol)
         assert err < tol, (b, err, tol)
     print(f"\n[ba dlm eps={eps} pair={pair}] worst error / tolerance {worst:.2e}")
+
+
+@pytest.mark.parametrize("dogleg", [None, 1.0])
+def test_ba_failed_problem_is_frozen(dogleg):
+    """Problem 1 loses every observation of one camera, whose block of the
+    camera system is then singular at lambda = 0: the factorisation fails
+    (NOT_PD), the problem keeps its cameras and points from that step on and
+    repeats its objective, like the oracle's; problem 0 is untouched.  The
+    implicit and DLM backward give problem 1 zero gradients."""
+    from paper_2207_09442_amd import Plan
+    p = _fair_and_poor()
+    lost = int(p["pose_off"][1]) + 5
+    keep = p["obs_cam"] != lost
+    o1 = int(p["obs_off"][1])
+    p["obs_off"] = np.array([0, int(keep[:o1].sum()), int(keep.sum())], np.int32)
+    for k in ("obs_cam", "obs_pt", "obs_uv", "obs_w"):
+        p[k] = p[k][keep]
+    K = 4
+    plan = Plan(p, K, lam=0.0, solver="schur", device=t(0.0).device, dogleg=dogleg)
+    cams, pts = t(p["poses_init"]), t(p["points_init"])
+    dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]))
+    obj, status = plan.solve_ba(cams, pts, **dev)
+    torch.cuda.synchronize()
+    gs = S.graphs_of(p)
+    res = [S.solve_graph(g, K, 0.0, dogleg_radius=dogleg) for g in gs]
+    assert status.cpu().tolist() == [r.status for r in res] == [S.OK, S.NOT_PD]
+    got_c, got_p, ob = cams.cpu().numpy(), pts.cpu().numpy(), obj.cpu().numpy()
+    for b, r in enumerate(res):
+        c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
+        q0, q1 = p["point_off"][b], p["point_off"][b + 1]
+        assert rel(got_c[c0:c1], lie.SE3.to_storage(r.X).numpy()) < 1e-10
+        assert rel(got_p[q0:q1], r.pts.numpy()) < 1e-10
+        assert rel(ob[b], np.asarray(r.objective)) < 1e-10
+    vc = t(rng.normal(size=(int(p["pose_off"][-1]), 6)))
+    o1 = int(p["obs_off"][1])
+    for mode in ("implicit", "dlm"):
+        gr = plan.backward_ba(cams, pts, status=status, seed_cam=vc, mode=mode, **dev)
+        torch.cuda.synchronize()
+        gw = gr["obs_w"].cpu().numpy()
+        r1 = int(p["prior_off"][1])
+        assert np.all(gw[o1:] == 0) and np.all(gr["prior_logw"].cpu().numpy()[r1:] == 0)
+        assert np.all(np.isfinite(gw[:o1])) and np.abs(gw[:o1]).max() > 0
