@@ -256,6 +256,12 @@ typedef struct {
                                  not with DNLS_BACKWARD_EXACT / UNROLL
                                  (DNLS_ERR_UNSUPPORTED) */
   double* grad_edge_logc;     /* [E] out or NULL: gradient at the log-radii */
+  double* grad_obs_delta;     /* [O] out or NULL (SCHUR, implicit and DLM):
+                                 gradient with respect to each observation's
+                                 Huber radius, all equal to the problem's
+                                 radius, so their sum is the gradient of the
+                                 shared radius; zero inside the quadratic
+                                 branch (s <= delta^2) */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */
@@ -276,7 +282,9 @@ typedef enum {
    * holds the solve's factor again when the call has run.  SCHUR: cameras
    * and points take the step together (2 eps^2 on both diagonal blocks, the
    * point seed as v's point part, zero if NULL), gradients for the
-   * observation weights (dS/dw = rho'(s) w |c|^2) and prior log-weights.
+   * observation weights (dS/dw = rho'(s) w |c|^2), the prior log-weights
+   * and the observations' Huber radii (dS/ddelta = sqrt(s) - delta outside
+   * the quadratic branch).
    * Graphs whose status is not OK get zero gradients. */
   DNLS_BACKWARD_DLM = 1,
   /* Proposition 1 with the exact Hessian of S in place of the Gauss-Newton

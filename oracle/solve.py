@@ -239,27 +239,29 @@ def linearize_pose_graph_sparse(g: Graph, X: torch.Tensor):
     return float(S), H, gvec.numpy()
 
 
-def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None):
+def ba_costs(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None, delta_o=None):
+    """Observation and prior costs of a BA problem; delta_o, a per-observation
+    Huber radius, defaults to the problem's radius."""
     w_o = g.w_o if w_o is None else w_o
     logw_p = g.logw_p if logw_p is None else logw_p
     c, Cc, Cq = costs.reprojection(X[g.oc], pts[g.op], g.uv, g.intr)
     r2 = (w_o ** 2) * (c ** 2).sum(-1)
-    rho, drho = costs.huber(r2, g.delta)
+    rho, drho = costs.huber(r2, g.delta if delta_o is None else delta_o)
     c_p, Cp = costs.prior(g.G, X[g.pv], g.PZ)
     return dict(c=c, Cc=Cc, Cq=Cq, w_o=w_o, rho=rho, drho=drho, c_p=c_p, Cp=Cp,
                 w_p=torch.exp(logw_p))
 
 
-def ba_objective(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None) -> torch.Tensor:
+def ba_objective(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None, delta_o=None) -> torch.Tensor:
     """S = 1/2 sum_o rho(w_o^2 ||c_o||^2) + 1/2 sum_p w_p^2 ||c_p||^2 (Huber rho
     on the observations, as in linearize_ba)."""
-    k = ba_costs(g, X, pts, w_o, logw_p)
+    k = ba_costs(g, X, pts, w_o, logw_p, delta_o)
     return 0.5 * k["rho"].sum() + 0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
 
 
-def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None) -> Lin:
+def linearize_ba(g: Graph, X: torch.Tensor, pts: torch.Tensor, w_o=None, logw_p=None, delta_o=None) -> Lin:
     Nc, Np = X.shape[0], pts.shape[0]
-    k = ba_costs(g, X, pts, w_o, logw_p)
+    k = ba_costs(g, X, pts, w_o, logw_p, delta_o)
     tr = lambda A: A.transpose(-1, -2)
     a = (k["drho"] * k["w_o"] ** 2)[:, None, None]          # rho' w^2
     Cc, Cq = k["Cc"], k["Cq"]
@@ -513,16 +515,18 @@ def implicit_grad_graph(g: Graph, res: GraphResult, v_pose, v_pts=None) -> dict:
         z = dict(edge_logw=torch.zeros(len(g.ei), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
                  tau=torch.zeros(len(g.ei), d, dtype=DT))
         if g.is_ba:
-            z = dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT))
+            z = dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
+                     obs_delta=torch.zeros(len(g.oc), dtype=DT))
         return z
     u, up = adjoint(res, v_pose, v_pts)
     if g.is_ba:
         w = g.w_o.clone().requires_grad_(True)
         lp = g.logw_p.clone().requires_grad_(True)
-        lin = linearize_ba(g, res.X, res.pts, w_o=w, logw_p=lp)
+        dl = torch.full((len(g.oc),), float(g.delta), dtype=DT).requires_grad_(True)
+        lin = linearize_ba(g, res.X, res.pts, w_o=w, logw_p=lp, delta_o=dl)
         Y = (lin.g * u.reshape(-1)).sum() + (lin.gp * up).sum()
-        dw, dp = torch.autograd.grad(Y, [w, lp])
-        return dict(obs_w=-dw, prior_logw=-dp, u=u, u_pts=up)
+        dw, dp, dd = torch.autograd.grad(Y, [w, lp, dl])
+        return dict(obs_w=-dw, prior_logw=-dp, obs_delta=-dd, u=u, u_pts=up)
     le = g.logw_e.clone().requires_grad_(True)
     lp = g.logw_p.clone().requires_grad_(True)
     tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
@@ -657,7 +661,8 @@ def dlm_grad_ba(g: Graph, res: GraphResult, v_pose, v_pts, eps: float) -> dict:
     full system, theta_direct = (X Exp(delta_c), p + delta_p), then the
     objective's parameter gradients differenced and divided by eps."""
     if res.status != OK:
-        return dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT))
+        return dict(obs_w=torch.zeros(len(g.oc), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
+                    obs_delta=torch.zeros(len(g.oc), dtype=DT))
     lin = res.lin
     nc = lin.H.shape[0]
     v = torch.cat([torch.as_tensor(v_pose, dtype=DT).reshape(-1),
@@ -672,10 +677,12 @@ def dlm_grad_ba(g: Graph, res: GraphResult, v_pose, v_pts, eps: float) -> dict:
     def dS(X, pts):
         w = g.w_o.clone().requires_grad_(True)
         lp = g.logw_p.clone().requires_grad_(True)
-        return torch.autograd.grad(ba_objective(g, X, pts, w_o=w, logw_p=lp), [w, lp])
+        dl = torch.full((len(g.oc),), float(g.delta), dtype=DT).requires_grad_(True)
+        return torch.autograd.grad(ba_objective(g, X, pts, w_o=w, logw_p=lp, delta_o=dl), [w, lp, dl])
 
     a, b = dS(res.X, res.pts), dS(X_d, p_d)
-    return dict(obs_w=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, delta=delta)
+    return dict(obs_w=(a[0] - b[0]) / eps, prior_logw=(a[1] - b[1]) / eps, obs_delta=(a[2] - b[2]) / eps,
+                delta=delta)
 
 
 def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graphs=None) -> dict:

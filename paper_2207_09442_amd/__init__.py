@@ -71,7 +71,8 @@ class _BackwardArgs(ctypes.Structure):
                                    "grad_edge_tau", "grad_prior_logw", "grad_obs_w", "adjoint",
                                    "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
                                                   ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32),
-                                                  ("edge_logc", _vp), ("grad_edge_logc", _vp)]
+                                                  ("edge_logc", _vp), ("grad_edge_logc", _vp),
+                                                  ("grad_obs_delta", _vp)]
 
 
 _LIB = None
@@ -302,14 +303,16 @@ class Plan:
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,
                     seed_pt=None, want_adjoint=False, mode="implicit", eps=1e-3):
-        """Backward of bundle adjustment: gradients of the observation weights
-        and prior log-weights for tangent seeds on cameras (and points);
+        """Backward of bundle adjustment: gradients of the observation weights,
+        the prior log-weights and the per-observation Huber radii for tangent
+        seeds on cameras (and points);
         mode "implicit" (Proposition 1) or "dlm" (direct loss minimisation
         with this eps; the adjoint output is not written)."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {"obs_w": torch.empty(self.O, dtype=f64, device=dev),
-               "prior_logw": torch.empty(self.P, dtype=f64, device=dev)}
+               "prior_logw": torch.empty(self.P, dtype=f64, device=dev),
+               "obs_delta": torch.empty(self.O, dtype=f64, device=dev)}
         if want_adjoint:
             out["adjoint"] = torch.empty(self.V, 6, dtype=f64, device=dev)
         a = _BackwardArgs()
@@ -321,6 +324,7 @@ class Plan:
         a.seed_pose = _ptr(seed_cam.contiguous())
         a.seed_point = _ptr(None if seed_pt is None else seed_pt.contiguous())
         a.grad_obs_w, a.grad_prior_logw = _ptr(out["obs_w"]), _ptr(out["prior_logw"])
+        a.grad_obs_delta = _ptr(out["obs_delta"])
         a.adjoint = _ptr(out.get("adjoint"))
         a.workspace = self._aligned(self.workspace)
         a.mode = BACKWARD_MODES[mode]

@@ -104,6 +104,7 @@ struct BAArgs {
   double* up;
   double* g_w;
   double* g_logw_p;
+  double* g_delta;         // per-observation Huber radius (implicit and DLM backward)
   double* adjoint_out;
 };
 
@@ -876,9 +877,9 @@ __global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
   const bool ok = a.status[b] == DNLS_GRAPH_OK;
   const int t = blockIdx.x * kBT + threadIdx.x;
   const double* uc = a.uc + (size_t)b * a.npad_max;
-  if (t < g.nobs && a.g_w) {
+  if (t < g.nobs && (a.g_w || a.g_delta)) {
     const int o = g.obs0 + t;
-    double gw = 0.0;
+    double gw = 0.0, gd = 0.0;
     if (ok) {
       double c[2], Jc[12], Jp[6];
       reproj<double>(a.cams + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a,
@@ -895,10 +896,17 @@ __global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
       const double w = a.obs_w[o];
       const double yc = y[0] * c[0] + y[1] * c[1];
       const double cn2 = c[0] * c[0] + c[1] * c[1];
-      if (w * w * cn2 <= a.delta * a.delta) gw = -2.0 * w * yc;
-      else gw = -a.delta * yc / ::sqrt(cn2);
+      // g_o = rho'(s) w^2 C^T c with rho' = 1 inside, delta / sqrt(s) outside
+      // (sqrt(s) = w |c|): d/dw and d/ddelta of -u^T g_o
+      if (w * w * cn2 <= a.delta * a.delta) {
+        gw = -2.0 * w * yc;
+      } else {
+        gw = -a.delta * yc / ::sqrt(cn2);
+        gd = -w * yc / ::sqrt(cn2);
+      }
     }
-    a.g_w[o] = gw;
+    if (a.g_w) a.g_w[o] = gw;
+    if (a.g_delta) a.g_delta[o] = gd;
   }
   if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior && a.g_logw_p) {
     const int q = g.prior0 + threadIdx.x;
@@ -923,17 +931,18 @@ __global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
 // DLM backward (Section 4.3, Appendix G), per observation and prior: dS/dphi
 // at cameras `cams` and points `pts`, times `scale`, stored or added;
 // S = 1/2 sum rho(w^2 |c|^2) + 1/2 sum exp(2 l) |c_p|^2 gives
-// dS/dw = rho'(s) w |c|^2 and dS/dl = exp(2 l) |c_p|^2; problems marked
-// frozen get zero gradients
+// dS/dw = rho'(s) w |c|^2, dS/dl = exp(2 l) |c_p|^2 and, per observation,
+// dS/ddelta = sqrt(s) - delta outside the quadratic branch (0 inside);
+// problems marked frozen get zero gradients
 __global__ void __launch_bounds__(kBT) k_ba_param_grads(BAArgs a, const double* cams, const double* pts, double scale,
                                                         int accumulate) {
   const int b = blockIdx.y;
   const BADesc g = a.bd[b];
   const bool zero = a.frozen[b] != 0;
   const int t = blockIdx.x * kBT + threadIdx.x;
-  if (t < g.nobs && a.g_w) {
+  if (t < g.nobs && (a.g_w || a.g_delta)) {
     const int o = g.obs0 + t;
-    double v = 0.0;
+    double v = 0.0, vd = 0.0;
     if (!zero) {
       double c[2], Jc[12], Jp[6];
       reproj<double>(cams + (size_t)a.obs_cam[o] * 12, pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a, c,
@@ -942,8 +951,11 @@ __global__ void __launch_bounds__(kBT) k_ba_param_grads(BAArgs a, const double* 
       double rho, drho;
       huber(w * w * cn2, a.delta, rho, drho);
       v = drho * w * cn2;
+      // 1/2 d rho / d delta = sqrt(s) - delta outside the quadratic branch
+      if (w * w * cn2 > a.delta * a.delta) vd = w * ::sqrt(cn2) - a.delta;
     }
-    a.g_w[o] = zero ? 0.0 : (accumulate ? a.g_w[o] : 0.0) + scale * v;
+    if (a.g_w) a.g_w[o] = zero ? 0.0 : (accumulate ? a.g_w[o] : 0.0) + scale * v;
+    if (a.g_delta) a.g_delta[o] = zero ? 0.0 : (accumulate ? a.g_delta[o] : 0.0) + scale * vd;
   }
   if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior && a.g_logw_p) {
     const int q = g.prior0 + threadIdx.x;
@@ -1319,6 +1331,7 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
   a.seed_p = s->seed_point;
   a.g_w = s->grad_obs_w;
   a.g_logw_p = s->grad_prior_logw;
+  a.g_delta = s->grad_obs_delta;
   a.adjoint_out = s->adjoint;
   const int B = p->B;
   const dim3 blk(kBT);

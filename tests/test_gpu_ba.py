@@ -53,15 +53,16 @@ def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True
             seed_p[q0:q1] = rng.normal(size=(q1 - q0, 3))
     gr = plan.backward_ba(cams, pts, status=status, seed_cam=t(seed_c), seed_pt=t(seed_p), **dev)
     torch.cuda.synchronize()
-    gw, gl = gr["obs_w"].cpu().numpy(), gr["prior_logw"].cpu().numpy()
+    gw, gl, gd = gr["obs_w"].cpu().numpy(), gr["prior_logw"].cpu().numpy(), gr["obs_delta"].cpu().numpy()
     for b in problems:
         c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
         q0, q1 = p["point_off"][b], p["point_off"][b + 1]
         o0, o1 = p["obs_off"][b], p["obs_off"][b + 1]
         r0, r1 = p["prior_off"][b], p["prior_off"][b + 1]
         ref = S.implicit_grad_graph(gs[b], res[b], torch.as_tensor(seed_c[c0:c1]), torch.as_tensor(seed_p[q0:q1]))
-        mine = np.concatenate([gw[o0:o1], gl[r0:r1]])
-        theirs = np.concatenate([ref["obs_w"].detach().numpy(), ref["prior_logw"].detach().numpy()])
+        mine = np.concatenate([gw[o0:o1], gl[r0:r1], gd[o0:o1]])
+        theirs = np.concatenate([ref["obs_w"].detach().numpy(), ref["prior_logw"].detach().numpy(),
+                                 ref["obs_delta"].detach().numpy()])
         worst["grad"] = max(worst["grad"], rel(mine, theirs))
     print(f"\n[ba {precision}] " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
     for k in ["cam", "pt", "grad"]:
@@ -180,7 +181,7 @@ def test_ba_dlm_backward(eps, pair):
     torch.cuda.synchronize()
     for k in before:
         assert rel(after[k].cpu().numpy(), before[k].cpu().numpy()) < 1e-13, k
-    gw, gl = out["obs_w"].cpu().numpy(), out["prior_logw"].cpu().numpy()
+    gw, gl, gd = out["obs_w"].cpu().numpy(), out["prior_logw"].cpu().numpy(), out["obs_delta"].cpu().numpy()
     st = status.cpu().numpy()
     gs = S.graphs_of(p)
     X_all, P_all = cams.cpu(), pts.cpu()
@@ -196,8 +197,8 @@ def test_ba_dlm_backward(eps, pair):
         Xb, Pb = lie.SE3.from_storage(X_all[c0:c1]), P_all[q0:q1]
         res = S.GraphResult(X=Xb, pts=Pb, objective=[], status=S.OK, lin=S.linearize_ba(g, Xb, Pb))
         ref = S.dlm_grad_ba(g, res, vc[c0:c1], vp[q0:q1], eps)
-        mine = np.concatenate([gw[o0:o1], gl[r0:r1]])
-        theirs = np.concatenate([ref["obs_w"].numpy(), ref["prior_logw"].numpy()])
+        mine = np.concatenate([gw[o0:o1], gl[r0:r1], gd[o0:o1]])
+        theirs = np.concatenate([ref["obs_w"].numpy(), ref["prior_logw"].numpy(), ref["obs_delta"].numpy()])
         ev = np.linalg.eigvalsh(S.ba_full_system(res.lin).numpy())
         tol = 1e-9 + 3e4 * e64 / eps + 0.5 * (ev[-1] / ev[0]) * e64
         err = rel(mine, theirs)
@@ -246,4 +247,5 @@ def test_ba_failed_problem_is_frozen(dogleg):
         gw = gr["obs_w"].cpu().numpy()
         r1 = int(p["prior_off"][1])
         assert np.all(gw[o1:] == 0) and np.all(gr["prior_logw"].cpu().numpy()[r1:] == 0)
+        assert np.all(gr["obs_delta"].cpu().numpy()[o1:] == 0)
         assert np.all(np.isfinite(gw[:o1])) and np.abs(gw[:o1]).max() > 0

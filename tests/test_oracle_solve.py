@@ -281,6 +281,26 @@ def test_implicit_gradient_ba_obs_weights_fd():
         fd.append((F(a) - F(b_)) / (2 * h))
     fd = np.asarray(fd)
     assert np.abs(ours - fd).max() < 1e-6 * np.abs(fd).max()
+    # the per-observation Huber radius (the paper's learned BA kernel radius):
+    # zero for observations inside the quadratic branch
+    od = S.implicit_grad_graph(g, res, v, vq)["obs_delta"].numpy()
+    dl0 = torch.full((len(g.oc),), float(g.delta), dtype=DT)
+
+    def Fd(dl):
+        li = S.linearize_ba(g, res.X, res.pts, delta_o=dl)
+        xc, xp = S.schur_solve(res.lin, L, Ci, EC, li.g, li.gp)
+        return float(-((v.reshape(-1) * xc).sum() + (vq * xp).sum()))
+
+    fdd = []
+    for k in range(len(g.oc)):
+        a, b_ = dl0.clone(), dl0.clone()
+        a[k] += h
+        b_[k] -= h
+        fdd.append((Fd(a) - Fd(b_)) / (2 * h))
+    fdd = np.asarray(fdd)
+    inside = (lin.extra["drho"] == 1).numpy()
+    assert np.all(od[inside] == 0) and np.abs(od[~inside]).max() > 0
+    assert np.abs(od - fdd).max() < 1e-6 * np.abs(fdd).max()
 
 
 def test_implicit_gradient_noiseless_resolve_fd():
@@ -512,11 +532,11 @@ def test_dlm_ba_gradient_tends_linearly_to_implicit():
     vc = torch.as_tensor(rng.normal(size=(g.X.shape[0], 6)), dtype=DT)
     vp = torch.as_tensor(rng.normal(size=(g.pts.shape[0], 3)), dtype=DT)
     gi = S.implicit_grad_graph(g, res, vc, vp)
-    ref = torch.cat([gi["obs_w"], gi["prior_logw"]])
+    ref = torch.cat([gi["obs_w"], gi["prior_logw"], gi["obs_delta"]])
 
     def gap(eps):
         gd = S.dlm_grad_ba(g, res, vc, vp, eps)
-        return float((torch.cat([gd["obs_w"], gd["prior_logw"]]) - ref).norm() / ref.norm())
+        return float((torch.cat([gd["obs_w"], gd["prior_logw"], gd["obs_delta"]]) - ref).norm() / ref.norm())
 
     g2, g3, g4 = gap(1e-2), gap(1e-3), gap(1e-4)
     assert g2 < 0.05
