@@ -377,17 +377,72 @@ def _autograd_function():
     return DNLSFunction
 
 
+def _autograd_function_ba():
+    import torch
+
+    class DNLSFunctionBA(torch.autograd.Function):
+        """Bundle adjustment (cameras*, points*) = argmin S by K steps on the
+        Schur solver, differentiable in the observation weights and the prior
+        log-weights by implicit differentiation (Proposition 1)."""
+
+        @staticmethod
+        def forward(ctx, plan, cams0, points0, obs_uv, obs_w, prior_meas, prior_logw):
+            cams = cams0.detach().clone().contiguous()
+            points = points0.detach().clone().contiguous()
+            objective, status = plan.solve_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach())
+            ctx.plan = plan
+            ctx.save_for_backward(cams, points, obs_uv, obs_w, prior_meas, prior_logw, status)
+            ctx.mark_non_differentiable(objective, status)
+            return cams, points, objective, status
+
+        @staticmethod
+        def backward(ctx, g_cams, g_points, g_obj, g_status):
+            cams, points, obs_uv, obs_w, prior_meas, prior_logw, status = ctx.saved_tensors
+            plan = ctx.plan
+            if g_cams is None and g_points is None:
+                return (None,) * 7
+            if g_cams is None:
+                g_cams = torch.zeros_like(cams)
+            seed_cam = project_grad("SE3", cams.reshape(plan.V, -1), g_cams.reshape(plan.V, -1))
+            seed_pt = None if g_points is None else g_points.contiguous()
+            gr = plan.backward_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach(), status,
+                                  seed_cam, seed_pt)
+            return (None, None, None, None, gr["obs_w"], None, gr["prior_logw"])
+
+    return DNLSFunctionBA
+
+
 class _Lazy:
-    def __init__(self):
+    def __init__(self, make):
+        self._make = make
         self._f = None
 
     def __getattr__(self, k):
         if self._f is None:
-            self._f = _autograd_function()
+            self._f = self._make()
         return getattr(self._f, k)
 
 
-DNLSFunction = _Lazy()
+DNLSFunction = _Lazy(_autograd_function)
+DNLSFunctionBA = _Lazy(_autograd_function_ba)
+
+
+class BALayer:
+    """Bundle-adjustment layer: forward(inputs) -> (solution, info) with the
+    implicit backward into the observation weights and prior log-weights.
+    `inputs` maps cams / points / obs_uv / obs_w / prior_meas / prior_logw to
+    float64 device tensors (missing prior log-weights default to zero)."""
+
+    def __init__(self, plan: Plan):
+        self.plan = plan
+
+    def forward(self, inputs: dict):
+        import torch
+        p = self.plan
+        prior_logw = inputs.get("prior_logw", torch.zeros(p.P, dtype=torch.float64, device=p.device))
+        cams, points, objective, status = DNLSFunctionBA.apply(p, inputs["cams"], inputs["points"], inputs["obs_uv"],
+                                                               inputs["obs_w"], inputs["prior_meas"], prior_logw)
+        return {"cams": cams, "points": points}, {"objective": objective, "status": status}
 
 
 class Layer:

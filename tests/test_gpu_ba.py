@@ -249,3 +249,37 @@ def test_ba_failed_problem_is_frozen(dogleg):
         assert np.all(gw[o1:] == 0) and np.all(gr["prior_logw"].cpu().numpy()[r1:] == 0)
         assert np.all(gr["obs_delta"].cpu().numpy()[o1:] == 0)
         assert np.all(np.isfinite(gw[:o1])) and np.abs(gw[:o1]).max() > 0
+
+
+def test_ba_autograd_layer_end_to_end():
+    """BALayer.forward / loss.backward through DNLSFunctionBA: the gradients
+    of a camera + point loss reach the observation weights and the prior
+    log-weights, equal to the oracle's implicit gradient with the same seeds
+    (camera seed by autograd through the retraction, point seed Euclidean)."""
+    from paper_2207_09442_amd import BALayer, Plan
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=40, obs_per_point=4, seed=13)
+    p["obs_w"] = np.exp(rng.normal(scale=0.2, size=len(p["obs_w"])))
+    plan = Plan(p, 6, lam=1e-3, solver="schur", device=t(0.0).device)
+    obs_w = t(p["obs_w"]).requires_grad_(True)
+    prior_logw = t(p["prior_logw"]).requires_grad_(True)
+    sol, info = BALayer(plan).forward({"cams": t(p["poses_init"]), "points": t(p["points_init"]),
+                                       "obs_uv": t(p["obs_uv"]), "obs_w": obs_w, "prior_meas": t(p["prior_meas"]),
+                                       "prior_logw": prior_logw})
+    loss = ((sol["cams"] - t(p["poses_gt"])) ** 2).sum() + ((sol["points"] - t(p["points_gt"])) ** 2).sum()
+    loss.backward()
+    assert info["status"].cpu().tolist() == [0, 0]
+    gs = S.graphs_of(p)
+    ref_w, ref_l = [], []
+    for b, g in enumerate(gs):
+        r = S.solve_graph(g, 6, 1e-3)
+        c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
+        q0, q1 = p["point_off"][b], p["point_off"][b + 1]
+        xi = torch.zeros(r.X.shape[0], 6, dtype=torch.float64, requires_grad=True)
+        Y = lie.SE3.to_storage(lie.SE3.retract(r.X, xi))
+        (vc,) = torch.autograd.grad(((Y - torch.as_tensor(p["poses_gt"][c0:c1])) ** 2).sum(), [xi])
+        vp = 2.0 * (r.pts - torch.as_tensor(p["points_gt"][q0:q1]))
+        o = S.implicit_grad_graph(g, r, vc, vp)
+        ref_w.append(o["obs_w"].detach().numpy())
+        ref_l.append(o["prior_logw"].detach().numpy())
+    assert rel(obs_w.grad.cpu().numpy(), np.concatenate(ref_w)) < 1e-9
+    assert rel(prior_logw.grad.cpu().numpy(), np.concatenate(ref_l)) < 1e-9
