@@ -351,14 +351,17 @@ def _autograd_function():
     class DNLSFunction(torch.autograd.Function):
         """theta* = argmin S(theta; phi) by K steps, differentiable in
         phi = (edge log-weights, measurement tangent perturbations, prior
-        log-weights) by implicit differentiation (Proposition 1)."""
+        log-weights and, for Welsch edges, their log-radii) by implicit
+        differentiation (Proposition 1)."""
 
         @staticmethod
-        def forward(ctx, plan, poses0, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw):
+        def forward(ctx, plan, poses0, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, edge_logc=None):
             poses = poses0.detach().clone().contiguous()
+            logc = None if edge_logc is None else edge_logc.detach().contiguous()
             objective, status = plan.solve(poses, edge_meas, edge_logw.detach(), prior_meas,
-                                           prior_logw.detach(), edge_tau.detach())
+                                           prior_logw.detach(), edge_tau.detach(), edge_logc=logc)
             ctx.plan = plan
+            ctx.logc = logc
             ctx.save_for_backward(poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status)
             ctx.mark_non_differentiable(objective, status)
             return poses, objective, status
@@ -368,11 +371,11 @@ def _autograd_function():
             poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status = ctx.saved_tensors
             plan = ctx.plan
             if g_poses is None:
-                return (None,) * 7
+                return (None,) * 8
             seed = project_grad(plan.group, poses.reshape(plan.V, -1), g_poses.reshape(plan.V, -1))
             gr = plan.backward(poses, edge_meas, edge_logw.detach(), prior_meas, prior_logw.detach(),
-                               status, seed, edge_tau=edge_tau.detach())
-            return (None, None, None, gr["edge_logw"], gr["edge_tau"], None, gr["prior_logw"])
+                               status, seed, edge_tau=edge_tau.detach(), edge_logc=ctx.logc)
+            return (None, None, None, gr["edge_logw"], gr["edge_tau"], None, gr["prior_logw"], gr.get("edge_logc"))
 
     return DNLSFunction
 
@@ -448,8 +451,10 @@ class BALayer:
 class Layer:
     """Theseus-style layer: forward(inputs) -> (solution, info) with the
     implicit backward (Section 3, Listing 1).  `inputs` maps
-    poses / edge_meas / edge_logw / edge_tau / prior_meas / prior_logw to
-    float64 device tensors; missing log-weights and tau default to zero."""
+    poses / edge_meas / edge_logw / edge_tau / prior_meas / prior_logw (and,
+    for Welsch-robust edges, edge_logc) to float64 device tensors; missing
+    log-weights and tau default to zero, a missing edge_logc means plain
+    least squares."""
 
     def __init__(self, plan: Plan):
         self.plan = plan
@@ -462,5 +467,6 @@ class Layer:
         edge_tau = inputs.get("edge_tau", z(p.E, p.dof))
         prior_logw = inputs.get("prior_logw", z(p.P))
         poses, objective, status = DNLSFunction.apply(p, inputs["poses"], inputs["edge_meas"], edge_logw,
-                                                      edge_tau, inputs["prior_meas"], prior_logw)
+                                                      edge_tau, inputs["prior_meas"], prior_logw,
+                                                      inputs.get("edge_logc"))
         return {"poses": poses}, {"objective": objective, "status": status}

@@ -119,3 +119,35 @@ def test_welsch_huge_radius_equals_least_squares_and_unsupported_modes():
         with pytest.raises(DnlsError):
             plan.backward(poses, *aux, st, t(np.zeros((int(p["pose_off"][-1]), 6))), edge_tau=t(tau),
                           edge_logc=t(p["edge_logc"]), mode=mode)
+
+
+def test_welsch_radius_through_the_autograd_layer():
+    """The paper's PGO learning target: the loss sum ||X - X_gt||^2 on the
+    3x4 storage, back-propagated by Layer / DNLSFunction into the Welsch
+    log-radii (and log-weights), equals the oracle's implicit gradient with
+    the seed taken by autograd through the retraction."""
+    from paper_2207_09442_amd import Layer, Plan
+    from oracle import lie
+    p, tau = _problem(67, batch=2)
+    K = 8
+    plan = Plan(p, K, lam=1e-3, device="cuda")
+    logc = t(p["edge_logc"]).requires_grad_(True)
+    logw = t(p["edge_logw"]).requires_grad_(True)
+    sol, info = Layer(plan).forward({"poses": t(p["poses_init"]), "edge_meas": t(p["edge_meas"]),
+                                     "edge_logw": logw, "edge_tau": t(tau), "prior_meas": t(p["prior_meas"]),
+                                     "edge_logc": logc})
+    ((sol["poses"] - t(p["poses_gt"])) ** 2).sum().backward()
+    assert info["status"].cpu().tolist() == [0, 0]
+    gs = oracle_graphs(p, tau)
+    ref_c, ref_w = [], []
+    for b, g in enumerate(gs):
+        r = S.solve_graph(g, K, 1e-3, tau=g.tau)
+        lo, hi = p["pose_off"][b], p["pose_off"][b + 1]
+        xi = torch.zeros(r.X.shape[0], 6, dtype=torch.float64, requires_grad=True)
+        Y = lie.SE3.to_storage(lie.SE3.retract(r.X, xi))
+        (v,) = torch.autograd.grad(((Y - torch.as_tensor(p["poses_gt"][lo:hi])) ** 2).sum(), [xi])
+        o = S.implicit_grad_graph(g, r, v)
+        ref_c.append(o["edge_logc"].detach().numpy())
+        ref_w.append(o["edge_logw"].detach().numpy())
+    assert rel(logc.grad.cpu().numpy(), np.concatenate(ref_c)) < 1e-8
+    assert rel(logw.grad.cpu().numpy(), np.concatenate(ref_w)) < 1e-8
