@@ -355,12 +355,13 @@ def _autograd_function():
         differentiation (Proposition 1)."""
 
         @staticmethod
-        def forward(ctx, plan, poses0, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, edge_logc=None):
+        def forward(ctx, plan, bwd, poses0, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, edge_logc=None):
             poses = poses0.detach().clone().contiguous()
             logc = None if edge_logc is None else edge_logc.detach().contiguous()
             objective, status = plan.solve(poses, edge_meas, edge_logw.detach(), prior_meas,
                                            prior_logw.detach(), edge_tau.detach(), edge_logc=logc)
             ctx.plan = plan
+            ctx.bwd = bwd
             ctx.logc = logc
             ctx.save_for_backward(poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status)
             ctx.mark_non_differentiable(objective, status)
@@ -371,11 +372,12 @@ def _autograd_function():
             poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status = ctx.saved_tensors
             plan = ctx.plan
             if g_poses is None:
-                return (None,) * 8
+                return (None,) * 9
             seed = project_grad(plan.group, poses.reshape(plan.V, -1), g_poses.reshape(plan.V, -1))
             gr = plan.backward(poses, edge_meas, edge_logw.detach(), prior_meas, prior_logw.detach(),
-                               status, seed, edge_tau=edge_tau.detach(), edge_logc=ctx.logc)
-            return (None, None, None, gr["edge_logw"], gr["edge_tau"], None, gr["prior_logw"], gr.get("edge_logc"))
+                               status, seed, edge_tau=edge_tau.detach(), edge_logc=ctx.logc, **ctx.bwd)
+            return (None, None, None, None, gr["edge_logw"], gr["edge_tau"], None, gr["prior_logw"],
+                    gr.get("edge_logc"))
 
     return DNLSFunction
 
@@ -454,10 +456,16 @@ class Layer:
     poses / edge_meas / edge_logw / edge_tau / prior_meas / prior_logw (and,
     for Welsch-robust edges, edge_logc) to float64 device tensors; missing
     log-weights and tau default to zero, a missing edge_logc means plain
-    least squares."""
+    least squares.  backward_mode: "implicit" (Proposition 1), "dlm",
+    "exact" or "unroll" (Section 4.3; the plan needs keep_iterates=True), with
+    their options (eps, sweeps, steps) as for Plan.backward."""
 
-    def __init__(self, plan: Plan):
+    def __init__(self, plan: Plan, backward_mode: str = "implicit", eps: float = 1e-3, sweeps: int = 8,
+                 steps: int | None = None):
+        if backward_mode not in BACKWARD_MODES:
+            raise DnlsError(f"unknown backward mode {backward_mode!r}")
         self.plan = plan
+        self.bwd = dict(mode=backward_mode, eps=eps, sweeps=sweeps, steps=steps)
 
     def forward(self, inputs: dict):
         import torch
@@ -466,7 +474,7 @@ class Layer:
         edge_logw = inputs.get("edge_logw", z(p.E))
         edge_tau = inputs.get("edge_tau", z(p.E, p.dof))
         prior_logw = inputs.get("prior_logw", z(p.P))
-        poses, objective, status = DNLSFunction.apply(p, inputs["poses"], inputs["edge_meas"], edge_logw,
+        poses, objective, status = DNLSFunction.apply(p, self.bwd, inputs["poses"], inputs["edge_meas"], edge_logw,
                                                       edge_tau, inputs["prior_meas"], prior_logw,
                                                       inputs.get("edge_logc"))
         return {"poses": poses}, {"objective": objective, "status": status}

@@ -432,3 +432,26 @@ def test_dogleg_sparse_schedules_and_graph_replay(schedule):
         ob1, st1 = gplan.solve(x1, *aux)
         torch.cuda.synchronize()
         assert torch.equal(x0, x1) and torch.equal(ob0, ob1) and torch.equal(st0, st1)
+
+
+@pytest.mark.parametrize("mode,kw", [("dlm", {"eps": 1e-3}), ("exact", {"sweeps": 6}), ("unroll", {"steps": 3})])
+def test_autograd_layer_backward_modes(mode, kw):
+    """Layer(plan, backward_mode=...) runs the chosen backward through torch
+    autograd: the gradients equal those of plan.backward with the same mode
+    and the seed the layer builds (tangent projection of dLoss/dX)."""
+    from paper_2207_09442_amd import Layer, Plan, project_grad
+    p = synth.walk_se3(batch=2, n_poses=10, n_loops=6, seed=31)
+    plan = Plan(p, 5, lam=1e-3, device=t(0.0).device, keep_iterates=(mode == "unroll"))
+    logw = t(p["edge_logw"]).requires_grad_(True)
+    tau = torch.zeros(len(p["edge_logw"]), 6, dtype=torch.float64, device=logw.device, requires_grad=True)
+    sol, info = Layer(plan, backward_mode=mode, **kw).forward(
+        {"poses": t(p["poses_init"]), "edge_meas": t(p["edge_meas"]), "edge_logw": logw, "edge_tau": tau,
+         "prior_meas": t(p["prior_meas"])})
+    X = sol["poses"]
+    ((X - t(p["poses_gt"])) ** 2).sum().backward()
+    seed = project_grad("SE3", X.detach().reshape(plan.V, -1), (2 * (X.detach() - t(p["poses_gt"]))).reshape(plan.V, -1))
+    ref = plan.backward(X.detach(), t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]),
+                        torch.zeros(plan.P, dtype=torch.float64, device=logw.device), info["status"], seed,
+                        edge_tau=torch.zeros_like(tau), mode=mode, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(logw.grad, ref["edge_logw"]) and torch.equal(tau.grad, ref["edge_tau"])
