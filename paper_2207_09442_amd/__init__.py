@@ -391,11 +391,12 @@ def _autograd_function_ba():
         log-weights by implicit differentiation (Proposition 1)."""
 
         @staticmethod
-        def forward(ctx, plan, cams0, points0, obs_uv, obs_w, prior_meas, prior_logw):
+        def forward(ctx, plan, bwd, cams0, points0, obs_uv, obs_w, prior_meas, prior_logw):
             cams = cams0.detach().clone().contiguous()
             points = points0.detach().clone().contiguous()
             objective, status = plan.solve_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach())
             ctx.plan = plan
+            ctx.bwd = bwd
             ctx.save_for_backward(cams, points, obs_uv, obs_w, prior_meas, prior_logw, status)
             ctx.mark_non_differentiable(objective, status)
             return cams, points, objective, status
@@ -405,14 +406,14 @@ def _autograd_function_ba():
             cams, points, obs_uv, obs_w, prior_meas, prior_logw, status = ctx.saved_tensors
             plan = ctx.plan
             if g_cams is None and g_points is None:
-                return (None,) * 7
+                return (None,) * 8
             if g_cams is None:
                 g_cams = torch.zeros_like(cams)
             seed_cam = project_grad("SE3", cams.reshape(plan.V, -1), g_cams.reshape(plan.V, -1))
             seed_pt = None if g_points is None else g_points.contiguous()
             gr = plan.backward_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach(), status,
-                                  seed_cam, seed_pt)
-            return (None, None, None, None, gr["obs_w"], None, gr["prior_logw"])
+                                  seed_cam, seed_pt, **ctx.bwd)
+            return (None, None, None, None, None, gr["obs_w"], None, gr["prior_logw"])
 
     return DNLSFunctionBA
 
@@ -436,17 +437,22 @@ class BALayer:
     """Bundle-adjustment layer: forward(inputs) -> (solution, info) with the
     implicit backward into the observation weights and prior log-weights.
     `inputs` maps cams / points / obs_uv / obs_w / prior_meas / prior_logw to
-    float64 device tensors (missing prior log-weights default to zero)."""
+    float64 device tensors (missing prior log-weights default to zero).
+    backward_mode: "implicit" or "dlm" (with eps)."""
 
-    def __init__(self, plan: Plan):
+    def __init__(self, plan: Plan, backward_mode: str = "implicit", eps: float = 1e-3):
+        if backward_mode not in ("implicit", "dlm"):
+            raise DnlsError(f"backward mode {backward_mode!r}: the Schur solver has implicit and dlm")
         self.plan = plan
+        self.bwd = dict(mode=backward_mode, eps=eps)
 
     def forward(self, inputs: dict):
         import torch
         p = self.plan
         prior_logw = inputs.get("prior_logw", torch.zeros(p.P, dtype=torch.float64, device=p.device))
-        cams, points, objective, status = DNLSFunctionBA.apply(p, inputs["cams"], inputs["points"], inputs["obs_uv"],
-                                                               inputs["obs_w"], inputs["prior_meas"], prior_logw)
+        cams, points, objective, status = DNLSFunctionBA.apply(p, self.bwd, inputs["cams"], inputs["points"],
+                                                               inputs["obs_uv"], inputs["obs_w"], inputs["prior_meas"],
+                                                               prior_logw)
         return {"cams": cams, "points": points}, {"objective": objective, "status": status}
 
 

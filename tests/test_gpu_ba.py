@@ -283,3 +283,23 @@ def test_ba_autograd_layer_end_to_end():
         ref_l.append(o["prior_logw"].detach().numpy())
     assert rel(obs_w.grad.cpu().numpy(), np.concatenate(ref_w)) < 1e-9
     assert rel(prior_logw.grad.cpu().numpy(), np.concatenate(ref_l)) < 1e-9
+
+
+def test_ba_autograd_layer_dlm_mode():
+    """BALayer(plan, backward_mode="dlm") equals Plan.backward_ba in DLM mode
+    with the seeds the layer builds."""
+    from paper_2207_09442_amd import BALayer, Plan, project_grad
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=40, obs_per_point=4, seed=14)
+    plan = Plan(p, 6, lam=1e-3, solver="schur", device=t(0.0).device)
+    obs_w = t(p["obs_w"]).requires_grad_(True)
+    dev = dict(obs_uv=t(p["obs_uv"]), prior_meas=t(p["prior_meas"]), prior_logw=t(p["prior_logw"]))
+    sol, info = BALayer(plan, backward_mode="dlm", eps=1e-2).forward(
+        {"cams": t(p["poses_init"]), "points": t(p["points_init"]), "obs_w": obs_w, **dev})
+    C, Q = sol["cams"], sol["points"]
+    (((C - t(p["poses_gt"])) ** 2).sum() + ((Q - t(p["points_gt"])) ** 2).sum()).backward()
+    seed_c = project_grad("SE3", C.detach().reshape(plan.V, -1), (2 * (C.detach() - t(p["poses_gt"]))).reshape(plan.V, -1))
+    seed_p = 2 * (Q.detach() - t(p["points_gt"]))
+    ref = plan.backward_ba(C.detach(), Q.detach(), obs_w=t(p["obs_w"]), status=info["status"], seed_cam=seed_c,
+                           seed_pt=seed_p, mode="dlm", eps=1e-2, **dev)
+    torch.cuda.synchronize()
+    assert torch.equal(obs_w.grad, ref["obs_w"])
