@@ -335,7 +335,7 @@ dnls_status dnls_plan_flops(dnls_plan plan, double* algorithmic, double* execute
 /* The schedule a plan resolved at creation (host values, either pointer may
  * be NULL): dense_pair = 1 if dnls_solve shares each factorisation among
  * co-resident workgroups (DNLS_FLAG_PAIR requested and they fit: a pair per
- * graph for DENSE, four per problem for SCHUR), else 0;
+ * graph for DENSE, six per problem for SCHUR), else 0;
  * sparse_solve = the dnls_sparse_solve that AUTO resolved to (SPARSE), else
  * DNLS_SPSOLVE_AUTO. */
 dnls_status dnls_plan_schedule(dnls_plan plan, int32_t* dense_pair, int32_t* sparse_solve);
