@@ -223,6 +223,10 @@ typedef struct {
                                  s = ||w c_e||^2, and enters the normal
                                  equations reweighted by rho'(s) (first
                                  order).  Pose-graph solvers only. */
+  const double* huber_delta;  /* [B] per-problem Huber radius (> 0), or NULL for
+                                 the plan's huber_delta (SCHUR only; the
+                                 robust kernel's radius as a solve input,
+                                 so that it can be learned) */
 } dnls_solve_args;
 
 /* Arguments of dnls_backward: everything must be the state left by the
@@ -256,12 +260,14 @@ typedef struct {
                                  not with DNLS_BACKWARD_EXACT / UNROLL
                                  (DNLS_ERR_UNSUPPORTED) */
   double* grad_edge_logc;     /* [E] out or NULL: gradient at the log-radii */
+  const double* huber_delta;  /* [B] the per-problem radii given to dnls_solve,
+                                 or NULL (SCHUR) */
   double* grad_obs_delta;     /* [O] out or NULL (SCHUR, implicit and DLM):
                                  gradient with respect to each observation's
                                  Huber radius, all equal to the problem's
-                                 radius, so their sum is the gradient of the
-                                 shared radius; zero inside the quadratic
-                                 branch (s <= delta^2) */
+                                 radius, so their sum over a problem is the
+                                 gradient of its radius; zero inside the
+                                 quadratic branch (s <= delta^2) */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */

@@ -61,7 +61,7 @@ class _Options(ctypes.Structure):
 class _SolveArgs(ctypes.Structure):
     _fields_ = [(n, _vp) for n in ["poses", "points", "edge_meas", "edge_logw", "edge_tau",
                                    "prior_meas", "prior_logw", "obs_uv", "obs_w", "objective",
-                                   "status", "factor", "workspace", "edge_logc"]]
+                                   "status", "factor", "workspace", "edge_logc", "huber_delta"]]
 
 
 class _BackwardArgs(ctypes.Structure):
@@ -72,7 +72,7 @@ class _BackwardArgs(ctypes.Structure):
                                    "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
                                                   ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32),
                                                   ("edge_logc", _vp), ("grad_edge_logc", _vp),
-                                                  ("grad_obs_delta", _vp)]
+                                                  ("huber_delta", _vp), ("grad_obs_delta", _vp)]
 
 
 _LIB = None
@@ -157,6 +157,7 @@ class Plan:
         self.P = int(problem["prior_off"][-1])
         self.Vp = int(problem["point_off"][-1]) if "point_off" in problem else 0
         self.O = int(problem["obs_off"][-1]) if "obs_off" in problem else 0
+        self.obs_off = np.asarray(problem["obs_off"], np.int64) if "obs_off" in problem else None
         keep = []
         pr = _Problem()
         pr.batch = self.B
@@ -285,9 +286,10 @@ class Plan:
 
 
     # ------------------------------------------------------------------
-    def solve_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw):
+    def solve_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, huber_delta=None):
         """Bundle adjustment (solver "schur"): K steps in place on `cams`
-        [Vc, 3, 4] and `points` [Vp, 3]; returns (objective [B, K+1], status [B])."""
+        [Vc, 3, 4] and `points` [Vp, 3]; returns (objective [B, K+1], status [B]).
+        huber_delta: per-problem Huber radii [B], or None for the problem's."""
         import torch
         objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
         status = torch.empty(self.B, dtype=torch.int32, device=self.device)
@@ -298,11 +300,12 @@ class Plan:
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
         a.workspace = self._aligned(self.workspace)
+        a.huber_delta = _ptr(None if huber_delta is None else huber_delta.contiguous())
         _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
         return objective, status
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,
-                    seed_pt=None, want_adjoint=False, mode="implicit", eps=1e-3):
+                    seed_pt=None, want_adjoint=False, mode="implicit", eps=1e-3, huber_delta=None):
         """Backward of bundle adjustment: gradients of the observation weights,
         the prior log-weights and the per-observation Huber radii for tangent
         seeds on cameras (and points);
@@ -329,6 +332,7 @@ class Plan:
         a.workspace = self._aligned(self.workspace)
         a.mode = BACKWARD_MODES[mode]
         a.dlm_eps = float(eps)
+        a.huber_delta = _ptr(None if huber_delta is None else huber_delta.contiguous())
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
         return out
 
@@ -387,16 +391,20 @@ def _autograd_function_ba():
 
     class DNLSFunctionBA(torch.autograd.Function):
         """Bundle adjustment (cameras*, points*) = argmin S by K steps on the
-        Schur solver, differentiable in the observation weights and the prior
-        log-weights by implicit differentiation (Proposition 1)."""
+        Schur solver, differentiable in the observation weights, the prior
+        log-weights and (if given) the per-problem Huber radii by implicit
+        differentiation (Proposition 1) or DLM."""
 
         @staticmethod
-        def forward(ctx, plan, bwd, cams0, points0, obs_uv, obs_w, prior_meas, prior_logw):
+        def forward(ctx, plan, bwd, cams0, points0, obs_uv, obs_w, prior_meas, prior_logw, huber_delta=None):
             cams = cams0.detach().clone().contiguous()
             points = points0.detach().clone().contiguous()
-            objective, status = plan.solve_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach())
+            hd = None if huber_delta is None else huber_delta.detach().contiguous()
+            objective, status = plan.solve_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach(),
+                                              huber_delta=hd)
             ctx.plan = plan
             ctx.bwd = bwd
+            ctx.hd = hd
             ctx.save_for_backward(cams, points, obs_uv, obs_w, prior_meas, prior_logw, status)
             ctx.mark_non_differentiable(objective, status)
             return cams, points, objective, status
@@ -406,14 +414,20 @@ def _autograd_function_ba():
             cams, points, obs_uv, obs_w, prior_meas, prior_logw, status = ctx.saved_tensors
             plan = ctx.plan
             if g_cams is None and g_points is None:
-                return (None,) * 8
+                return (None,) * 9
             if g_cams is None:
                 g_cams = torch.zeros_like(cams)
             seed_cam = project_grad("SE3", cams.reshape(plan.V, -1), g_cams.reshape(plan.V, -1))
             seed_pt = None if g_points is None else g_points.contiguous()
             gr = plan.backward_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach(), status,
-                                  seed_cam, seed_pt, **ctx.bwd)
-            return (None, None, None, None, None, gr["obs_w"], None, gr["prior_logw"])
+                                  seed_cam, seed_pt, huber_delta=ctx.hd, **ctx.bwd)
+            g_delta = None
+            if ctx.hd is not None:
+                # the radius of problem b is shared by its observations
+                cs = torch.cat([gr["obs_delta"].new_zeros(1), torch.cumsum(gr["obs_delta"], 0)])
+                off = torch.as_tensor(plan.obs_off, device=cs.device)
+                g_delta = cs[off[1:]] - cs[off[:-1]]
+            return (None, None, None, None, None, gr["obs_w"], None, gr["prior_logw"], g_delta)
 
     return DNLSFunctionBA
 
@@ -437,8 +451,9 @@ class BALayer:
     """Bundle-adjustment layer: forward(inputs) -> (solution, info) with the
     implicit backward into the observation weights and prior log-weights.
     `inputs` maps cams / points / obs_uv / obs_w / prior_meas / prior_logw to
-    float64 device tensors (missing prior log-weights default to zero).
-    backward_mode: "implicit" or "dlm" (with eps)."""
+    float64 device tensors (missing prior log-weights default to zero), and
+    optionally huber_delta, per-problem Huber radii [B] (the robust kernel's
+    radius, learnable).  backward_mode: "implicit" or "dlm" (with eps)."""
 
     def __init__(self, plan: Plan, backward_mode: str = "implicit", eps: float = 1e-3):
         if backward_mode not in ("implicit", "dlm"):
@@ -452,7 +467,7 @@ class BALayer:
         prior_logw = inputs.get("prior_logw", torch.zeros(p.P, dtype=torch.float64, device=p.device))
         cams, points, objective, status = DNLSFunctionBA.apply(p, self.bwd, inputs["cams"], inputs["points"],
                                                                inputs["obs_uv"], inputs["obs_w"], inputs["prior_meas"],
-                                                               prior_logw)
+                                                               prior_logw, inputs.get("huber_delta"))
         return {"cams": cams, "points": points}, {"objective": objective, "status": status}
 
 

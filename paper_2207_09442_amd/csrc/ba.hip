@@ -60,6 +60,7 @@ struct BAArgs {
   const double* prior_meas;
   const double* prior_logw;
   double fx, fy, cx, cy, delta;
+  const double* delta_b;   // per-problem Huber radius, or NULL for delta
   void* orec;
   double* prec;
   double* E;
@@ -107,6 +108,8 @@ struct BAArgs {
   double* g_delta;         // per-observation Huber radius (implicit and DLM backward)
   double* adjoint_out;
 };
+
+__device__ __forceinline__ double huber_radius(const BAArgs& a, int b) { return a.delta_b ? a.delta_b[b] : a.delta; }
 
 __device__ double block_sum_ba(double v, double* red) {
 #pragma unroll
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(kBT) k_ba_lin(BAArgs a) {
                 Jc, Jp);
       const double w = a.obs_w[o];
       double rho, drho;
-      huber(w * w * (c[0] * c[0] + c[1] * c[1]), a.delta, rho, drho);
+      huber(w * w * (c[0] * c[0] + c[1] * c[1]), huber_radius(a, b), rho, drho);
       const double sw = ::sqrt(drho) * w;
       S* rec = reinterpret_cast<S*>(a.orec) + (size_t)o * kObsRec;
       const S ss = S(sw);
@@ -898,10 +901,11 @@ __global__ void __launch_bounds__(kBT) k_ba_bwd_obs(BAArgs a) {
       const double cn2 = c[0] * c[0] + c[1] * c[1];
       // g_o = rho'(s) w^2 C^T c with rho' = 1 inside, delta / sqrt(s) outside
       // (sqrt(s) = w |c|): d/dw and d/ddelta of -u^T g_o
-      if (w * w * cn2 <= a.delta * a.delta) {
+      const double hd = huber_radius(a, b);
+      if (w * w * cn2 <= hd * hd) {
         gw = -2.0 * w * yc;
       } else {
-        gw = -a.delta * yc / ::sqrt(cn2);
+        gw = -hd * yc / ::sqrt(cn2);
         gd = -w * yc / ::sqrt(cn2);
       }
     }
@@ -949,10 +953,11 @@ __global__ void __launch_bounds__(kBT) k_ba_param_grads(BAArgs a, const double* 
                      Jc, Jp);
       const double w = a.obs_w[o], cn2 = c[0] * c[0] + c[1] * c[1];
       double rho, drho;
-      huber(w * w * cn2, a.delta, rho, drho);
+      const double hd = huber_radius(a, b);
+      huber(w * w * cn2, hd, rho, drho);
       v = drho * w * cn2;
       // 1/2 d rho / d delta = sqrt(s) - delta outside the quadratic branch
-      if (w * w * cn2 > a.delta * a.delta) vd = w * ::sqrt(cn2) - a.delta;
+      if (w * w * cn2 > hd * hd) vd = w * ::sqrt(cn2) - hd;
     }
     if (a.g_w) a.g_w[o] = zero ? 0.0 : (accumulate ? a.g_w[o] : 0.0) + scale * v;
     if (a.g_delta) a.g_delta[o] = zero ? 0.0 : (accumulate ? a.g_delta[o] : 0.0) + scale * vd;
@@ -1242,6 +1247,7 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   bind_ws(p, a, s->workspace, s->factor);
   a.cams = s->poses;
   a.pts = s->points;
+  a.delta_b = s->huber_delta;
   a.obs_uv = s->obs_uv;
   a.obs_w = s->obs_w;
   a.prior_meas = s->prior_meas;
@@ -1322,6 +1328,7 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
   a.lam_g = nullptr;   // the backward's systems take the damping passed to the kernels
   a.cams = const_cast<double*>(s->poses);
   a.pts = const_cast<double*>(s->points);
+  a.delta_b = s->huber_delta;
   a.obs_uv = s->obs_uv;
   a.obs_w = s->obs_w;
   a.prior_meas = s->prior_meas;

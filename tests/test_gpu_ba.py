@@ -303,3 +303,41 @@ def test_ba_autograd_layer_dlm_mode():
                            seed_pt=seed_p, mode="dlm", eps=1e-2, **dev)
     torch.cuda.synchronize()
     assert torch.equal(obs_w.grad, ref["obs_w"])
+
+
+def test_ba_learnable_huber_radius_through_the_layer():
+    """The robust kernel's radius as a per-problem solve input (the paper's
+    BA example learns it): radii 1.5 and 3.0 px instead of the problem's 2;
+    the solve equals the oracle's with those radii, and loss.backward gives
+    the radius gradient (the sum of the per-observation ones) with the
+    weight gradients, equal to the oracle's implicit gradient."""
+    from paper_2207_09442_amd import BALayer, Plan
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=40, obs_per_point=4, seed=15, pixel_sigma=2.0)
+    plan = Plan(p, 6, lam=1e-3, solver="schur", device=t(0.0).device)
+    radii = t([1.5, 3.0]).requires_grad_(True)
+    obs_w = t(p["obs_w"]).requires_grad_(True)
+    sol, info = BALayer(plan).forward({"cams": t(p["poses_init"]), "points": t(p["points_init"]),
+                                       "obs_uv": t(p["obs_uv"]), "obs_w": obs_w, "prior_meas": t(p["prior_meas"]),
+                                       "prior_logw": t(p["prior_logw"]), "huber_delta": radii})
+    C, Q = sol["cams"], sol["points"]
+    (((C - t(p["poses_gt"])) ** 2).sum() + ((Q - t(p["points_gt"])) ** 2).sum()).backward()
+    assert info["status"].cpu().tolist() == [0, 0]
+    gs = S.graphs_of(p)
+    ref_d, ref_w = [], []
+    for b, g in enumerate(gs):
+        g.delta = [1.5, 3.0][b]
+        r = S.solve_graph(g, 6, 1e-3)
+        c0, c1 = p["pose_off"][b], p["pose_off"][b + 1]
+        q0, q1 = p["point_off"][b], p["point_off"][b + 1]
+        assert rel(C.detach().cpu().numpy()[c0:c1], lie.SE3.to_storage(r.X).numpy()) < 1e-10
+        assert rel(Q.detach().cpu().numpy()[q0:q1], r.pts.numpy()) < 1e-10
+        xi = torch.zeros(r.X.shape[0], 6, dtype=torch.float64, requires_grad=True)
+        Y = lie.SE3.to_storage(lie.SE3.retract(r.X, xi))
+        (vc,) = torch.autograd.grad(((Y - torch.as_tensor(p["poses_gt"][c0:c1])) ** 2).sum(), [xi])
+        o = S.implicit_grad_graph(g, r, vc, 2.0 * (r.pts - torch.as_tensor(p["points_gt"][q0:q1])))
+        lin = S.linearize_ba(g, r.X, r.pts)
+        assert bool((lin.extra["drho"] < 1).any())          # some observations in the linear branch
+        ref_d.append(float(o["obs_delta"].sum()))
+        ref_w.append(o["obs_w"].detach().numpy())
+    assert rel(radii.grad.cpu().numpy(), np.asarray(ref_d)) < 1e-9
+    assert rel(obs_w.grad.cpu().numpy(), np.concatenate(ref_w)) < 1e-9
