@@ -213,12 +213,30 @@ def linearize_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_
     return Lin(S=S, H=H, g=gvec, extra=k)
 
 
-def linearize_pose_graph_sparse(g: Graph, X: torch.Tensor):
+def objective_and_gradient_pose_graph(g: Graph, X: torch.Tensor, tau=None, logw_e=None, logw_p=None):
+    """S and g = sum_i J_i^T r_i of the (non-robust) pose-graph objective
+    without forming H: what the backward differentiates on graphs too large
+    for a dense matrix.  Returns (S, g [n], cost blocks)."""
+    d, N = g.G.dof, X.shape[0]
+    k = pose_costs(g, X, tau, logw_e, logw_p)
+    w2e = (k["w_e"] ** 2)[:, None, None]
+    w2p = (k["w_p"] ** 2)[:, None, None]
+    tr = lambda A: A.transpose(-1, -2)
+    ge_i = (w2e * tr(k["Ci"]) @ k["c_e"][..., None])[..., 0]
+    ge_j = (w2e * tr(k["Cj"]) @ k["c_e"][..., None])[..., 0]
+    gp = (w2p * tr(k["Cp"]) @ k["c_p"][..., None])[..., 0]
+    gvec = _scatter_vec(N, d, torch.cat([g.ei, g.ej, g.pv]), torch.cat([ge_i, ge_j, gp]))
+    S = 0.5 * ((k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)).sum() + \
+        0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
+    return S, gvec, k
+
+
+def linearize_pose_graph_sparse(g: Graph, X: torch.Tensor, tau=None):
     """Same normal equations as linearize_pose_graph, as a scipy CSR matrix
     (for graphs too large for a dense matrix); returns (S, H, g)."""
     import scipy.sparse as sp
     d, N = g.G.dof, X.shape[0]
-    k = pose_costs(g, X)
+    S, gvec, k = objective_and_gradient_pose_graph(g, X, tau)
     w2e = (k["w_e"] ** 2)[:, None, None]
     w2p = (k["w_p"] ** 2)[:, None, None]
     Ci, Cj, Cp = k["Ci"], k["Cj"], k["Cp"]
@@ -230,12 +248,6 @@ def linearize_pose_graph_sparse(g: Graph, X: torch.Tensor):
     rr = (rows[:, None, None] * d + np.arange(d)[None, :, None]) + 0 * np.arange(d)[None, None, :]
     cc = (cols[:, None, None] * d + np.arange(d)[None, None, :]) + 0 * np.arange(d)[None, :, None]
     H = sp.coo_matrix((blocks.ravel(), (rr.ravel(), cc.ravel())), shape=(N * d, N * d)).tocsr()
-    ge_i = (w2e * tr(Ci) @ k["c_e"][..., None])[..., 0]
-    ge_j = (w2e * tr(Cj) @ k["c_e"][..., None])[..., 0]
-    gp = (w2p * tr(Cp) @ k["c_p"][..., None])[..., 0]
-    gvec = _scatter_vec(N, d, torch.cat([g.ei, g.ej, g.pv]), torch.cat([ge_i, ge_j, gp]))
-    S = 0.5 * ((k["w_e"] ** 2) * (k["c_e"] ** 2).sum(-1)).sum() + \
-        0.5 * ((k["w_p"] ** 2) * (k["c_p"] ** 2).sum(-1)).sum()
     return float(S), H, gvec.numpy()
 
 
@@ -701,6 +713,84 @@ def backward(problem: dict, results: list, v_pose: np.ndarray, v_pts=None, graph
     if all("u" in o for o in outs):
         out["u"] = torch.cat([o["u"].reshape(-1, gs[0].G.dof) for o in outs]).numpy()
     return out
+
+
+# ---------------------------------------------------------------------------
+# large pose graphs: the same steps with a sparse factorisation (Section 4.2)
+# ---------------------------------------------------------------------------
+def _sparse_factor(H):
+    """LU of the symmetric matrix H with a symmetric minimum-degree ordering and
+    diagonal pivots (SuperLU), which for a symmetric positive definite matrix
+    is its Cholesky factorisation up to the scaling of the factors; a
+    non-positive pivot means H is not positive definite.  Returns the factor
+    or None."""
+    import scipy.sparse.linalg as sla
+    try:
+        lu = sla.splu(H.tocsc(), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                      options=dict(SymmetricMode=True))
+    except RuntimeError:                      # exactly singular
+        return None
+    if not np.all(lu.U.diagonal() > 0.0):
+        return None
+    return lu
+
+
+def solve_graph_sparse(g: Graph, iterations: int, lam: float, tau=None) -> GraphResult:
+    """K fixed-damping steps and the final linearisation of one pose graph,
+    as solve_graph (same steps, same order) but with a sparse H and a sparse
+    factorisation, for graphs whose dense H does not fit (the 16^3 lattice:
+    24576 unknowns).  The result's factor is the sparse factor of H*."""
+    if tau is None:
+        tau = g.tau
+    import scipy.sparse as sp
+    X = g.X.clone()
+    obj, status = [], OK
+    for _ in range(iterations):
+        s, H, gv = linearize_pose_graph_sparse(g, X, tau)
+        obj.append(s)
+        if not (np.isfinite(s) and np.all(np.isfinite(H.data)) and np.all(np.isfinite(gv))):
+            status = NONFINITE
+            break
+        lu = _sparse_factor(H + lam * sp.identity(H.shape[0], format="csr"))
+        if lu is None:
+            status = NOT_PD
+            break
+        delta = torch.as_tensor(lu.solve(gv), dtype=DT)
+        X = g.G.retract(X, -delta.reshape(-1, g.G.dof))
+    res = GraphResult(X=X, pts=None, objective=obj, status=status)
+    if status != OK:
+        res.objective = obj + [obj[-1]] * (iterations + 1 - len(obj))
+        return res
+    s, H, gv = linearize_pose_graph_sparse(g, X, tau)
+    res.objective = obj + [s]
+    res.lin = Lin(S=torch.tensor(s, dtype=DT), H=H, g=torch.as_tensor(gv, dtype=DT))
+    if not (np.isfinite(s) and np.all(np.isfinite(H.data)) and np.all(np.isfinite(gv))):
+        res.status = NONFINITE
+        return res
+    lu = _sparse_factor(H)
+    res.factor = None if lu is None else (lu,)
+    if lu is None:
+        res.status = NOT_PD
+    return res
+
+
+def implicit_grad_graph_sparse(g: Graph, res: GraphResult, v_pose) -> dict:
+    """Proposition 1 for a result of solve_graph_sparse: u = H*^-1 v with the
+    sparse factor, then dL/dphi = -d/dphi [u^T g(theta_K; phi)] by autograd
+    of the gradient vector alone (no H)."""
+    d = g.G.dof
+    if res.status != OK:
+        return dict(edge_logw=torch.zeros(len(g.ei), dtype=DT), prior_logw=torch.zeros(len(g.pv), dtype=DT),
+                    tau=torch.zeros(len(g.ei), d, dtype=DT))
+    (lu,) = res.factor
+    u = torch.as_tensor(lu.solve(np.asarray(v_pose, dtype=np.float64).reshape(-1)), dtype=DT)
+    le = g.logw_e.clone().requires_grad_(True)
+    lp = g.logw_p.clone().requires_grad_(True)
+    tau0 = g.tau if g.tau is not None else torch.zeros(len(g.ei), d, dtype=DT)
+    tau = tau0.clone().requires_grad_(True)
+    _, gvec, _ = objective_and_gradient_pose_graph(g, res.X, tau=tau, logw_e=le, logw_p=lp)
+    de, dp, dt = torch.autograd.grad((gvec * u).sum(), [le, lp, tau])
+    return dict(edge_logw=-de, prior_logw=-dp, tau=-dt, u=u.reshape(-1, d))
 
 
 # ---------------------------------------------------------------------------

@@ -820,3 +820,44 @@ def test_welsch_rejects_outliers():
     plain = S.solve_graph(g, 10, 1e-3)
     rob = S.solve_graph(dataclasses.replace(g, logc_e=torch.full((len(g.ei),), np.log(0.5), dtype=DT)), 10, 1e-3)
     assert err(rob.X) < 0.5 and err(plain.X) > 10 * err(rob.X)
+
+
+@pytest.mark.parametrize("lam,with_tau", [(0.0, False), (1e-3, True)])
+def test_sparse_oracle_equals_dense_oracle(lam, with_tau):
+    """The sparse-factorisation oracle (for graphs whose dense H does not fit)
+    takes the same steps as the dense one: iterates, objectives and the
+    implicit gradient agree on a small lattice with long-range edges."""
+    p = synth.lattice_se3(batch=1, side=4, seed=6)
+    g = S.graphs_of(p)[0]
+    if with_tau:
+        g.tau = torch.as_tensor(0.01 * np.random.default_rng(2).normal(size=(len(g.ei), 6)), dtype=torch.float64)
+    a = S.solve_graph(g, 4, lam)
+    b = S.solve_graph_sparse(g, 4, lam)
+    assert a.status == b.status == S.OK
+    assert float((lie.SE3.to_storage(a.X) - lie.SE3.to_storage(b.X)).abs().max()) < 1e-12
+    assert np.allclose(a.objective, b.objective, rtol=1e-12, atol=0)
+    _, v = S.pose_error_loss_and_seed("SE3", lie.SE3.to_storage(a.X).numpy(), p["poses_gt"])
+    ga = S.implicit_grad_graph(g, a, torch.as_tensor(v))
+    gb = S.implicit_grad_graph_sparse(g, b, v)
+    scale = max(float(ga[k].abs().max()) for k in ("edge_logw", "prior_logw", "tau"))
+    for k in ("edge_logw", "prior_logw", "tau", "u"):
+        ref = ga[k].detach().numpy()
+        floor = np.abs(ref).max() if k == "u" else scale
+        assert np.abs(gb[k].detach().numpy() - ref).max() < 1e-9 * floor, k
+
+
+def test_sparse_oracle_flags_a_singular_system():
+    """Without the prior the pose graph's H is singular (gauge freedom): the
+    sparse oracle reports NOT_PD, keeps theta_0 and gives zero gradients,
+    like the dense oracle."""
+    p = synth.lattice_se3(batch=1, side=3, seed=1)
+    g = S.graphs_of(p)[0]
+    g.pv = g.pv[:0]
+    g.PZ = g.PZ[:0]
+    g.logw_p = g.logw_p[:0]
+    a, b = S.solve_graph(g, 3, 0.0), S.solve_graph_sparse(g, 3, 0.0)
+    assert a.status == b.status == S.NOT_PD
+    assert torch.equal(b.X, g.X)
+    assert b.objective == a.objective
+    gr = S.implicit_grad_graph_sparse(g, b, np.ones((g.X.shape[0], 6)))
+    assert float(gr["tau"].abs().max()) == 0.0
