@@ -134,7 +134,8 @@ typedef enum {
 enum {
   /* SPARSE and SCHUR: record the launch sequence of dnls_solve into a HIP
    * graph on the first call and replay it while the argument pointers stay
-   * the same (recaptured when they change).  The plan then holds mutable
+   * the same (every pointer of dnls_solve_args, edge_logc and huber_delta
+   * included; recaptured when one changes).  The plan then holds mutable
    * state: calls with this flag must not overlap on one plan.  DENSE is a
    * single launch and ignores the flag. */
   DNLS_FLAG_GRAPH = 1,
@@ -268,6 +269,11 @@ typedef struct {
                                  radius, so their sum over a problem is the
                                  gradient of its radius; zero inside the
                                  quadratic branch (s <= delta^2) */
+  double* grad_huber_delta;   /* [B] out or NULL (SCHUR, implicit and DLM):
+                                 gradient with respect to each problem's
+                                 Huber radius, the sum of its observations'
+                                 per-radius gradients, reduced on the device
+                                 in a fixed order (needs no grad_obs_delta) */
 } dnls_backward_args;
 
 /* dnls_backward_args.mode */
@@ -320,13 +326,28 @@ typedef enum {
 
 /* Validate the structure and build the plan: per-graph offsets, cost
  * incidence lists, the dense / Schur / supernodal block maps (symbolic
- * analysis, done once per structure).  Returns DNLS_ERR_INVALID_ARG on
- * inconsistent offsets or indices, DNLS_ERR_UNSUPPORTED on a combination
- * the library does not implement. */
+ * analysis, done once per structure).  This is the paper's Objective built
+ * from Variables, CostFunctions and CostWeights (Section 3, core API) plus
+ * the optimizer's settings (Section 2 "Solving NLS"; Section 3 optimizers);
+ * the symbolic work is done once and reused by every numeric call, as the
+ * paper's sparse solvers split symbolic and numeric factorisation
+ * (Section 4.2; Appendix F).  `problem` and `options` are host pointers
+ * read during the call only; *out receives a plan the caller releases with
+ * dnls_plan_destroy.  Returns DNLS_ERR_INVALID_ARG on inconsistent offsets
+ * or indices, DNLS_ERR_UNSUPPORTED on a combination the library does not
+ * implement, DNLS_ERR_HIP if the index tables cannot be copied to the
+ * device; *out is left NULL on error. */
 dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* problem,
                              const dnls_options* options);
 
-/* Byte sizes of the caller-owned buffers of a plan. */
+/* Byte sizes of the caller-owned buffers of a plan (host outputs, any may
+ * be NULL): solve_ws, the workspace of dnls_solve; factor_bytes, the factor
+ * cache that dnls_solve fills and dnls_backward reads (the factorisation of
+ * the final linearisation that the backward reuses, Section 4.2 "Backward
+ * for custom linear solvers"); backward_ws, the workspace of dnls_backward.
+ * The library allocates none of them: like the paper's sparse solver
+ * library, it owns no numeric memory (Appendix F).  Every buffer must be
+ * 256-byte aligned.  DNLS_ERR_INVALID_ARG for a NULL plan. */
 dnls_status dnls_plan_workspace(dnls_plan plan, size_t* solve_ws, size_t* factor_bytes,
                                 size_t* backward_ws);
 
@@ -347,13 +368,28 @@ dnls_status dnls_plan_flops(dnls_plan plan, double* algorithmic, double* execute
 dnls_status dnls_plan_schedule(dnls_plan plan, int32_t* dense_pair, int32_t* sparse_solve);
 
 /* Run K optimizer steps and the final linearisation on `stream` (a
- * hipStream_t, NULL = default stream).  Enqueues kernels only. */
+ * hipStream_t, NULL = default stream): per step, cost evaluation, the
+ * weighted normal equations, damping, factorisation, the step and the
+ * retraction (Section 2 "Solving NLS", Eq. nls; Section 3 optimizers), then
+ * the undamped linearisation at theta_K whose factor goes to args->factor
+ * for the backward (Section 4.2).  Enqueues kernels only: the caller's
+ * buffers must stay valid until the stream reaches them.  Returns
+ * DNLS_ERR_INVALID_ARG for a missing required pointer,
+ * DNLS_ERR_WORKSPACE for a misaligned factor or workspace,
+ * DNLS_ERR_UNSUPPORTED for an input the plan's solver does not take,
+ * DNLS_ERR_HIP if a launch fails; numerical failures go to args->status. */
 dnls_status dnls_solve(dnls_plan plan, const dnls_solve_args* args, void* stream);
 
-/* Implicit backward (Proposition 1): u = H*^-1 v with the cached factor of
- * the undamped Gauss-Newton Hessian at theta_K, then
- * dL/dphi = -d/dphi [u^T g(theta_K; phi)] for the log-weights, the
- * measurement tangent perturbations and the observation weights. */
+/* Implicit backward (Section 4.3, Proposition 1 and its proof in Appendix
+ * H): u = H*^-1 v with the cached factor of the undamped Gauss-Newton
+ * Hessian at theta_K (Section 4.2 "Backward for custom linear solvers"),
+ * then dL/dphi = -d/dphi [u^T g(theta_K; phi)] for the log-weights, the
+ * measurement tangent perturbations and the observation weights; or the
+ * other modes of dnls_backward_mode.  Enqueues kernels only; outputs that
+ * are NULL are skipped.  Returns DNLS_ERR_INVALID_ARG for a missing
+ * required pointer or a bad mode parameter, DNLS_ERR_UNSUPPORTED for a mode
+ * the plan's solver does not have, DNLS_ERR_HIP if a launch fails.  Graphs
+ * whose status is not OK get zero gradients. */
 dnls_status dnls_backward(dnls_plan plan, const dnls_backward_args* args, void* stream);
 
 /* Projection operator of Appendix D: tangent gradient
@@ -362,7 +398,11 @@ dnls_status dnls_backward(dnls_plan plan, const dnls_backward_args* args, void* 
 dnls_status dnls_project_grad(int32_t group, int64_t n, const double* poses,
                               const double* grad, double* out, void* stream);
 
-/* Free the plan's device tables.  NULL is accepted. */
+/* Free the plan's device tables and launch state (the caller's buffers
+ * are not touched).  It waits for the plan's own work on the device to
+ * finish first, so it may be called right after dnls_solve or
+ * dnls_backward were enqueued.  NULL is accepted.  The paper's layer is a
+ * Python object; this is its explicit end of life for C callers. */
 dnls_status dnls_plan_destroy(dnls_plan plan);
 
 /* Message of the last error on this thread ("" if none). */

@@ -806,4 +806,4 @@ def pose_error_loss_and_seed(group: str, poses: np.ndarray, poses_gt: np.ndarray
     e = G.log(G.inv(Xg) @ G.retract(X, xi))
     L = (e ** 2).sum()
     (v,) = torch.autograd.grad(L, [xi])
-    return float(L), v.numpy()
+    return float(L.detach()), v.numpy()

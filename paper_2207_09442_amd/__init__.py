@@ -13,8 +13,11 @@ and the implicit backward mode (Section 4.3).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -72,7 +75,8 @@ class _BackwardArgs(ctypes.Structure):
                                    "workspace"]] + [("mode", ctypes.c_int32), ("dlm_eps", ctypes.c_double),
                                                   ("sweeps", ctypes.c_int32), ("steps", ctypes.c_int32),
                                                   ("edge_logc", _vp), ("grad_edge_logc", _vp),
-                                                  ("huber_delta", _vp), ("grad_obs_delta", _vp)]
+                                                  ("huber_delta", _vp), ("grad_obs_delta", _vp),
+                                                  ("grad_huber_delta", _vp)]
 
 
 _LIB = None
@@ -132,9 +136,23 @@ def _dev_f64(x, device):
                            dtype=torch.float64, device=device).contiguous()
 
 
+_LIVE_PLANS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_plans():
+    """Destroy the plans still alive at interpreter exit while the HIP runtime
+    is still up (a destructor run during interpreter finalisation may find it
+    torn down)."""
+    for p in list(_LIVE_PLANS):
+        p.close()
+
+
 class Plan:
     """A DNLS problem structure with its optimizer settings (dnls_plan_create)
-    plus the caller-owned workspace and factor cache (torch device tensors)."""
+    plus the caller-owned workspace and factor cache (torch device tensors).
+    close() (or leaving a `with` block) releases the plan's device tables;
+    plans still open at exit are closed by an atexit hook."""
 
     def __init__(self, problem: dict, iterations: int, lam: float = 0.0, solver: str = "dense",
                  precision: str = "fp64", refine: int = 0, device: str = "cuda", sparse_solve: str = "auto",
@@ -188,6 +206,10 @@ class Plan:
         h = _vp()
         _check(lib().dnls_plan_create(ctypes.byref(h), ctypes.byref(pr), ctypes.byref(op)), "dnls_plan_create")
         self._h = h
+        _LIVE_PLANS.add(self)
+        # solves run on this plan so far: a backward through the autograd
+        # functions must read the factor cache of its own forward
+        self.solves = 0
         sw, fb, bw = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib().dnls_plan_workspace(h, ctypes.byref(sw), ctypes.byref(fb), ctypes.byref(bw)),
                "dnls_plan_workspace")
@@ -217,11 +239,44 @@ class Plan:
         off = (-t.data_ptr()) % 256
         return ctypes.c_void_p(t.data_ptr() + off)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the plan's device tables (dnls_plan_destroy); idempotent."""
         h = getattr(self, "_h", None)
         if h is not None and _LIB is not None:
-            _LIB.dnls_plan_destroy(h)
             self._h = None
+            _LIB.dnls_plan_destroy(h)
+        _LIVE_PLANS.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # no HIP calls while the interpreter is shutting down: the atexit hook
+        # has closed every live plan before that
+        if not sys.is_finalizing():
+            self.close()
+
+    def _radii(self, huber_delta):
+        """Per-problem Huber radii: None, or a float64 tensor on the plan's
+        device, 0-dim (one radius shared by every problem, expanded) or [B],
+        every radius finite and > 0."""
+        import torch
+        if huber_delta is None:
+            return None
+        if not isinstance(huber_delta, torch.Tensor) or huber_delta.dtype != torch.float64 \
+                or huber_delta.device != self.device:
+            raise DnlsError(f"huber_delta must be a float64 tensor on {self.device}")
+        if huber_delta.dim() == 0:
+            huber_delta = huber_delta.expand(self.B)
+        if tuple(huber_delta.shape) != (self.B,):
+            raise DnlsError(f"huber_delta must have shape [B] = [{self.B}] or be 0-dim, "
+                            f"got {tuple(huber_delta.shape)}")
+        if not bool(torch.isfinite(huber_delta).all()) or not bool((huber_delta > 0).all()):
+            raise DnlsError("huber_delta must be finite and > 0")
+        return huber_delta.contiguous()
 
     # ------------------------------------------------------------------
     def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None, edge_logc=None):
@@ -240,6 +295,7 @@ class Plan:
         a.workspace = self._aligned(self.workspace)
         a.edge_logc = _ptr(edge_logc)
         _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
+        self.solves += 1
         return objective, status
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
@@ -300,22 +356,26 @@ class Plan:
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
         a.workspace = self._aligned(self.workspace)
-        a.huber_delta = _ptr(None if huber_delta is None else huber_delta.contiguous())
+        hd = self._radii(huber_delta)
+        a.huber_delta = _ptr(hd)
         _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
+        self.solves += 1
         return objective, status
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,
                     seed_pt=None, want_adjoint=False, mode="implicit", eps=1e-3, huber_delta=None):
         """Backward of bundle adjustment: gradients of the observation weights,
-        the prior log-weights and the per-observation Huber radii for tangent
-        seeds on cameras (and points);
+        the prior log-weights, the per-observation Huber radii ("obs_delta")
+        and the per-problem radii ("huber_delta" [B], their per-problem sums,
+        reduced on the device) for tangent seeds on cameras (and points);
         mode "implicit" (Proposition 1) or "dlm" (direct loss minimisation
         with this eps; the adjoint output is not written)."""
         import torch
         dev, f64 = self.device, torch.float64
         out = {"obs_w": torch.empty(self.O, dtype=f64, device=dev),
                "prior_logw": torch.empty(self.P, dtype=f64, device=dev),
-               "obs_delta": torch.empty(self.O, dtype=f64, device=dev)}
+               "obs_delta": torch.empty(self.O, dtype=f64, device=dev),
+               "huber_delta": torch.empty(self.B, dtype=f64, device=dev)}
         if want_adjoint:
             out["adjoint"] = torch.empty(self.V, 6, dtype=f64, device=dev)
         a = _BackwardArgs()
@@ -328,11 +388,13 @@ class Plan:
         a.seed_point = _ptr(None if seed_pt is None else seed_pt.contiguous())
         a.grad_obs_w, a.grad_prior_logw = _ptr(out["obs_w"]), _ptr(out["prior_logw"])
         a.grad_obs_delta = _ptr(out["obs_delta"])
+        a.grad_huber_delta = _ptr(out["huber_delta"])
         a.adjoint = _ptr(out.get("adjoint"))
         a.workspace = self._aligned(self.workspace)
         a.mode = BACKWARD_MODES[mode]
         a.dlm_eps = float(eps)
-        a.huber_delta = _ptr(None if huber_delta is None else huber_delta.contiguous())
+        hd = self._radii(huber_delta)
+        a.huber_delta = _ptr(hd)
         _check(lib().dnls_backward(self._h, ctypes.byref(a), _stream()), "dnls_backward")
         return out
 
@@ -347,6 +409,15 @@ def project_grad(group: str, poses, grad):
     _check(lib().dnls_project_grad(GROUPS[group], n, _ptr(poses.contiguous()), _ptr(grad.contiguous()),
                                    _ptr(out), _stream()), "dnls_project_grad")
     return out
+
+
+def _same_solve(ctx):
+    """The backward reads the plan's factor cache, which the next solve on
+    the plan overwrites: refuse a backward whose forward is not the plan's
+    latest solve."""
+    if ctx.plan.solves != ctx.solve_id:
+        raise DnlsError("backward after a later solve on the same Plan: its factor cache now holds the later "
+                        "solve's factorisation; use one Plan per forward that is differentiated")
 
 
 def _autograd_function():
@@ -365,6 +436,7 @@ def _autograd_function():
             objective, status = plan.solve(poses, edge_meas, edge_logw.detach(), prior_meas,
                                            prior_logw.detach(), edge_tau.detach(), edge_logc=logc)
             ctx.plan = plan
+            ctx.solve_id = plan.solves
             ctx.bwd = bwd
             ctx.logc = logc
             ctx.save_for_backward(poses, edge_meas, edge_logw, edge_tau, prior_meas, prior_logw, status)
@@ -377,6 +449,7 @@ def _autograd_function():
             plan = ctx.plan
             if g_poses is None:
                 return (None,) * 9
+            _same_solve(ctx)
             seed = project_grad(plan.group, poses.reshape(plan.V, -1), g_poses.reshape(plan.V, -1))
             gr = plan.backward(poses, edge_meas, edge_logw.detach(), prior_meas, prior_logw.detach(),
                                status, seed, edge_tau=edge_tau.detach(), edge_logc=ctx.logc, **ctx.bwd)
@@ -403,6 +476,7 @@ def _autograd_function_ba():
             objective, status = plan.solve_ba(cams, points, obs_uv, obs_w.detach(), prior_meas, prior_logw.detach(),
                                               huber_delta=hd)
             ctx.plan = plan
+            ctx.solve_id = plan.solves
             ctx.bwd = bwd
             ctx.hd = hd
             ctx.save_for_backward(cams, points, obs_uv, obs_w, prior_meas, prior_logw, status)
@@ -415,6 +489,7 @@ def _autograd_function_ba():
             plan = ctx.plan
             if g_cams is None and g_points is None:
                 return (None,) * 9
+            _same_solve(ctx)
             if g_cams is None:
                 g_cams = torch.zeros_like(cams)
             seed_cam = project_grad("SE3", cams.reshape(plan.V, -1), g_cams.reshape(plan.V, -1))
@@ -423,10 +498,9 @@ def _autograd_function_ba():
                                   seed_cam, seed_pt, huber_delta=ctx.hd, **ctx.bwd)
             g_delta = None
             if ctx.hd is not None:
-                # the radius of problem b is shared by its observations
-                cs = torch.cat([gr["obs_delta"].new_zeros(1), torch.cumsum(gr["obs_delta"], 0)])
-                off = torch.as_tensor(plan.obs_off, device=cs.device)
-                g_delta = cs[off[1:]] - cs[off[:-1]]
+                # per-problem radius gradient from the library; a 0-dim radius
+                # shared by every problem gets their sum
+                g_delta = gr["huber_delta"] if ctx.hd.dim() == 1 else gr["huber_delta"].sum()
             return (None, None, None, None, None, gr["obs_w"], None, gr["prior_logw"], g_delta)
 
     return DNLSFunctionBA

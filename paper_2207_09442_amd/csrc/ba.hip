@@ -1154,6 +1154,7 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
   p->ba_off[9] = off; off += align256((size_t)p->V * 12 * sizeof(double));  // camera backup / DLM theta_direct
   p->ba_off[10] = off; off += align256((size_t)Vp * 3 * sizeof(double));    // point backup / DLM theta_direct
   p->ba_off[11] = off; off += align256((size_t)B * sizeof(int));            // DLM: status of its factorisations
+  p->ba_off[16] = off; off += align256((size_t)O * sizeof(double));         // per-observation radius gradients
   p->ws_bytes = off;
   p->bwd_bytes = off;
   // factor cache: Schur factors, then E, F, C^-1, g_p of the final linearisation
@@ -1320,6 +1321,26 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
   return DNLS_OK;
 }
 
+// Gradient of each problem's Huber radius: the sum of its observations'
+// per-radius gradients (every observation of problem b uses the radius
+// delta_b), one workgroup per problem, strided partial sums then a fixed
+// tree in LDS (deterministic order).
+__global__ void __launch_bounds__(kBT) k_ba_delta_sum(BAArgs a, const double* __restrict__ g_obs,
+                                                      double* __restrict__ out) {
+  __shared__ double red[kBT];
+  const int b = blockIdx.x;
+  const BADesc g = a.bd[b];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < g.nobs; t += kBT) acc += g_obs[g.obs0 + t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
 dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
   if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)))
     return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv and obs_w are required");
@@ -1339,6 +1360,10 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
   a.g_w = s->grad_obs_w;
   a.g_logw_p = s->grad_prior_logw;
   a.g_delta = s->grad_obs_delta;
+  // the per-problem radius gradient needs the per-observation ones: in the
+  // workspace when the caller does not ask for them
+  if (s->grad_huber_delta && !a.g_delta)
+    a.g_delta = reinterpret_cast<double*>(static_cast<char*>(s->workspace) + p->ba_off[16]);
   a.adjoint_out = s->adjoint;
   const int B = p->B;
   const dim3 blk(kBT);
@@ -1388,12 +1413,16 @@ dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st
     hipLaunchKernelGGL(k_ba_schur<double>, g_blk, blk, 0, st, a, 0.0);
     fs = launch_ba_factor(p, a, true, st);
     if (fs != DNLS_OK) return fs;
+    if (s->grad_huber_delta)
+      hipLaunchKernelGGL(k_ba_delta_sum, dim3(B), blk, 0, st, a, (const double*)a.g_delta, s->grad_huber_delta);
     HIP_TRY(hipGetLastError());
     return DNLS_OK;
   }
   hipLaunchKernelGGL(k_ba_bwd_cam, dim3(B), dim3(kNT), lds, st, a);
   hipLaunchKernelGGL(k_ba_bwd_pt, g_pt, blk, 0, st, a);
   hipLaunchKernelGGL(k_ba_bwd_obs, g_obs, blk, 0, st, a);
+  if (s->grad_huber_delta)
+    hipLaunchKernelGGL(k_ba_delta_sum, dim3(B), blk, 0, st, a, (const double*)a.g_delta, s->grad_huber_delta);
   HIP_TRY(hipGetLastError());
   return DNLS_OK;
 }

@@ -1263,7 +1263,8 @@ static dnls_status solve_multi(dnls_plan p, const dnls_solve_args* s, hipStream_
   if (!(p->opt.flags & DNLS_FLAG_GRAPH)) return enqueue(st);
   const std::vector<const void*> key = {s->poses, s->points, s->edge_meas, s->edge_logw, s->edge_tau,
                                         s->prior_meas, s->prior_logw, s->obs_uv, s->obs_w,
-                                        s->objective, s->status, s->factor, s->workspace};
+                                        s->objective, s->status, s->factor, s->workspace,
+                                        s->edge_logc, s->huber_delta};
   std::lock_guard<std::mutex> lock(p->graph_mu);
   if (!p->graph_exec || p->graph_key != key) {
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));

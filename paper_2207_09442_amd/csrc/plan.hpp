@@ -114,7 +114,7 @@ struct dnls_plan_s {
   int* d_pt_obs = nullptr;
   int4* d_sblk = nullptr;         // (row cam, col cam, start, count) per Schur block
   int2* d_spair = nullptr;        // (obs a, obs b) contributions
-  size_t ba_off[16] = {0};        // byte offsets of the BA workspace regions
+  size_t ba_off[17] = {0};        // byte offsets of the BA workspace regions
   size_t ba_fac_off[4] = {0};     // byte offsets of the BA backward cache inside the factor
   // block-sparse path (solver SPARSE)
   std::vector<dnls::SpDesc> sd;

@@ -11,8 +11,12 @@ implicit gradient (Proposition 1) on
                     the one-workgroup sparse solve.
 
 The backward seed is the tangent gradient of L = sum_k ||Log(X_gt,k^-1 X_k)||^2
-at the oracle's theta_K.  Inputs come from the seeded generators in synth/;
-everything else from oracle/.  About ten minutes on one core:
+at the oracle's theta_K.  `grad_spread` is how far the oracle's own gradient
+moves (max norm, relative to the gradient's max norm) when the final
+linearisation is summed in a permuted edge order or theta_K is moved by a
+random right perturbation of relative size 1e-13: the floor below which two
+correct float64 implementations cannot be told apart on this graph.  Inputs come from the seeded generators in synth/;
+everything else from oracle/.  About twelve minutes on one core:
 
     python tests/golden/make_sparse_goldens.py
 """
@@ -38,6 +42,35 @@ CASES = {
 }
 
 
+def _flat(o, inv=None):
+    e, t = o["edge_logw"].detach().numpy(), o["tau"].detach().numpy()
+    if inv is not None:
+        e, t = e[inv], t[inv]
+    return np.concatenate([e, t.ravel(), o["prior_logw"].detach().numpy()])
+
+
+def grad_spread(g, res, v, pose_rel=1e-13, seed=0) -> float:
+    import dataclasses
+
+    import torch
+    rng = np.random.default_rng(seed)
+    ref = _flat(S.implicit_grad_graph_sparse(g, res, v))
+    scale = float(np.abs(ref).max())
+    perm = rng.permutation(len(g.ei))
+    pt = torch.as_tensor(perm)
+    gp = dataclasses.replace(g, ei=g.ei[pt], ej=g.ej[pt], Z=g.Z[pt], logw_e=g.logw_e[pt])
+    s, H, gv = S.linearize_pose_graph_sparse(gp, res.X)
+    r1 = dataclasses.replace(res, factor=(S._sparse_factor(H),))
+    a = _flat(S.implicit_grad_graph_sparse(gp, r1, v), inv=np.argsort(perm))
+    st = lie.SE3.to_storage(res.X)
+    xi = torch.as_tensor(rng.normal(size=(res.X.shape[0], 6)), dtype=torch.float64)
+    X2 = lie.SE3.retract(res.X, xi / xi.norm() * pose_rel * float(st.norm()))
+    s, H, gv = S.linearize_pose_graph_sparse(g, X2)
+    r2 = dataclasses.replace(res, X=X2, factor=(S._sparse_factor(H),))
+    b = _flat(S.implicit_grad_graph_sparse(g, r2, v))
+    return max(np.abs(a - ref).max(), np.abs(b - ref).max()) / scale
+
+
 def make(name: str) -> str:
     c = CASES[name]
     p = c["make"]()
@@ -50,12 +83,14 @@ def make(name: str) -> str:
     poses = lie.SE3.to_storage(res.X).numpy()
     _, v = S.pose_error_loss_and_seed("SE3", poses, p["poses_gt"][lo:hi])
     gr = S.implicit_grad_graph_sparse(g, res, v)
+    spread = grad_spread(g, res, v)
     out = os.path.join(HERE, name + ".npz")
     np.savez_compressed(out, poses=poses, objective=np.asarray(res.objective), status=np.int32(res.status),
                         seed=v, edge_logw=gr["edge_logw"].detach().numpy(), tau=gr["tau"].detach().numpy(),
                         prior_logw=gr["prior_logw"].detach().numpy(), K=np.int32(c["K"]), lam=np.float64(c["lam"]),
-                        graph=np.int32(b))
-    print(f"{name}: {time.time() - t0:.0f} s, objective {res.objective[0]:.6e} -> {res.objective[-1]:.6e}",
+                        graph=np.int32(b), grad_spread=np.float64(spread))
+    print(f"{name}: {time.time() - t0:.0f} s, objective {res.objective[0]:.6e} -> {res.objective[-1]:.6e}, "
+          f"gradient spread {spread:.2e}",
           flush=True)
     return out
 

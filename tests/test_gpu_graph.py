@@ -101,3 +101,46 @@ def test_autotuner_picks_a_feasible_schedule_and_caches_it(tmp_path):
     ref = _pose_graph_run(p, Plan(p, 5, lam=1e-3, device=poses0.device), poses0)
     got = _pose_graph_run(p, A.tuned_plan(p, 5, 1e-3, cache_path=cache), poses0)
     assert np.abs(got[0] - ref[0]).max() < 1e-10 * np.abs(ref[0]).max()
+
+
+def test_ba_graph_recaptures_when_the_radii_change():
+    """A captured Schur solve replays only while every argument pointer,
+    the per-problem Huber radii included, is the one it was captured with:
+    no radii, then radii tensor A, then tensor B (another address, other
+    values) each equal the eager plan's result bit for bit."""
+    from paper_2207_09442_amd import Plan
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=50, obs_per_point=4, seed=7, pixel_sigma=2.0)
+    dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]))
+    c0, q0 = t(p["poses_init"]), t(p["points_init"])
+    eager = Plan(p, 4, lam=1e-3, solver="schur", device=c0.device)
+    graph = Plan(p, 4, lam=1e-3, solver="schur", device=c0.device, graph=True)
+    cams_g, pts_g = c0.clone(), q0.clone()
+    for radii in (None, t([1.0, 3.0]), t([2.5, 0.7])):
+        cams, pts = c0.clone(), q0.clone()
+        obj_e, _ = eager.solve_ba(cams, pts, huber_delta=radii, **dev)
+        cams_g.copy_(c0)
+        pts_g.copy_(q0)
+        obj_g, _ = graph.solve_ba(cams_g, pts_g, huber_delta=radii, **dev)
+        torch.cuda.synchronize()
+        assert torch.equal(cams, cams_g) and torch.equal(pts, pts_g) and torch.equal(obj_e, obj_g)
+
+
+def test_sparse_graph_recaptures_when_the_welsch_radii_change():
+    """The same for the Welsch log-radii of the edges on the block-sparse
+    solver: none, tensor A, tensor B."""
+    from paper_2207_09442_amd import Plan
+    p = synth.walk_se3(batch=2, n_poses=20, n_loops=10, seed=8, outliers=2)
+    poses0 = t(p["poses_init"])
+    dev = [t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"])]
+    eager = Plan(p, 5, lam=1e-3, solver="sparse", device=poses0.device)
+    graph = Plan(p, 5, lam=1e-3, solver="sparse", device=poses0.device, graph=True)
+    x_g = poses0.clone()
+    E = len(p["edge_logw"])
+    for logc in (None, t(np.full(E, 0.0)), t(np.full(E, -1.0))):
+        x = poses0.clone()
+        obj_e, _ = eager.solve(x, *dev, edge_logc=logc)
+        x_g.copy_(poses0)
+        obj_g, _ = graph.solve(x_g, *dev, edge_logc=logc)
+        torch.cuda.synchronize()
+        assert torch.equal(x, x_g) and torch.equal(obj_e, obj_g)
