@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <string>
 #include <utility>
@@ -62,6 +63,7 @@ struct BAArgs {
   double fx, fy, cx, cy, delta;
   const double* delta_b;   // per-problem Huber radius, or NULL for delta
   void* orec;
+  double* gob;      // mixed: per-observation float64 gradient parts [obs][9] (camera 6, point 3)
   double* prec;
   double* E;
   double* F;
@@ -176,7 +178,12 @@ __device__ __forceinline__ void huber(double s, double delta, double& rho, doubl
   }
 }
 
-// 1. linearise observations (and the problem's priors in its first block)
+// 1. linearise observations (and the problem's priors in its first block).
+// S = float (mixed precision): the Jacobians of the J^T J blocks are rounded
+// to float, while the gradient contributions J~^T r~ of each observation
+// (camera 6, point 3) are formed from the float64 residual and Jacobians and
+// kept in float64 (a.gob): a float gradient moves the fixed point of the
+// iteration by far more than the float curvature does.
 template <class S>
 __global__ void __launch_bounds__(kBT) k_ba_lin(BAArgs a) {
   __shared__ double red[kBT / 64];
@@ -187,22 +194,28 @@ __global__ void __launch_bounds__(kBT) k_ba_lin(BAArgs a) {
     const int lo = blockIdx.x * kBT + threadIdx.x;
     if (lo < g.nobs) {
       const int o = g.obs0 + lo;
-      double c[2];
-      S Jc[12], Jp[6];
-      reproj<S>(a.cams + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2, a, c,
-                Jc, Jp);
+      double c[2], Jc[12], Jp[6];
+      reproj<double>(a.cams + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2,
+                     a, c, Jc, Jp);
       const double w = a.obs_w[o];
       double rho, drho;
       huber(w * w * (c[0] * c[0] + c[1] * c[1]), huber_radius(a, b), rho, drho);
       const double sw = ::sqrt(drho) * w;
       S* rec = reinterpret_cast<S*>(a.orec) + (size_t)o * kObsRec;
-      const S ss = S(sw);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) rec[k] = ss * Jc[k];
+      for (int k = 0; k < 12; ++k) rec[k] = S(sw * Jc[k]);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) rec[12 + k] = ss * Jp[k];
+      for (int k = 0; k < 6; ++k) rec[12 + k] = S(sw * Jp[k]);
       rec[18] = S(sw * c[0]);
       rec[19] = S(sw * c[1]);
+      if constexpr (!std::is_same<S, double>::value) {
+        const double s2 = sw * sw;
+        double* go = a.gob + (size_t)o * 9;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) go[k] = s2 * (Jc[k] * c[0] + Jc[6 + k] * c[1]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) go[6 + k] = s2 * (Jp[k] * c[0] + Jp[3 + k] * c[1]);
+      }
       sacc += 0.5 * rho;
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < g.nprior) {
@@ -252,18 +265,19 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
   if (lp >= g.npt) return;
   const int pt = g.pt0 + lp;
   const S* rec = reinterpret_cast<const S*>(a.orec);
-  S C[9], gg[3];
+  S C[9];
+  double gg[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 9; ++k) C[k] = S(0);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) gg[k] = S(0);
   for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
-    const S* r = rec + (size_t)a.pt_obs[s] * kObsRec;
+    const int o = a.pt_obs[s];
+    const S* r = rec + (size_t)o * kObsRec;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) C[i * 3 + j] += r[12 + i] * r[12 + j] + r[15 + i] * r[15 + j];
-      gg[i] += r[12 + i] * r[18] + r[15 + i] * r[19];
+      if constexpr (std::is_same<S, double>::value) gg[i] += r[12 + i] * r[18] + r[15 + i] * r[19];
+      else gg[i] += a.gob[(size_t)o * 9 + 6 + i];
     }
   }
   double Cd[9], Ci[9];
@@ -274,7 +288,7 @@ __global__ void __launch_bounds__(kBT) k_ba_point(BAArgs a, double lambda) {
   for (int k = 0; k < 9; ++k) a.Cinv[(size_t)pt * 9 + k] = Ci[k];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    a.gp[(size_t)pt * 3 + k] = double(gg[k]) - (a.dlm_eps > 0.0 && a.seed_p ? a.dlm_eps * a.seed_p[(size_t)pt * 3 + k] : 0.0);
+    a.gp[(size_t)pt * 3 + k] = gg[k] - (a.dlm_eps > 0.0 && a.seed_p ? a.dlm_eps * a.seed_p[(size_t)pt * 3 + k] : 0.0);
 }
 
 // 2b. per observation: E_o = J~c^T J~p and F_o = E_o C^-1 of its point
@@ -349,9 +363,7 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
     S h[36];
 #pragma unroll
     for (int k = 0; k < 36; ++k) h[k] = S(0);
-    S gsl[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) gsl[k] = S(0);
+    double gsl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int s = a.cam_obs_off[cam] + lane; s < a.cam_obs_off[cam + 1]; s += 64) {
       const int o = a.cam_obs[s];
       const S* r = rec + (size_t)o * kObsRec;
@@ -359,7 +371,8 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
       for (int i = 0; i < 6; ++i) {
 #pragma unroll
         for (int j = 0; j <= i; ++j) h[i * 6 + j] += r[i] * r[j] + r[6 + i] * r[6 + j];
-        gsl[i] += r[i] * r[18] + r[6 + i] * r[19];
+        if constexpr (std::is_same<S, double>::value) gsl[i] += r[i] * r[18] + r[6 + i] * r[19];
+        else gsl[i] += a.gob[(size_t)o * 9 + i];
       }
       // - F_o g_p
       const double* Fo = a.F + (size_t)o * 18;
@@ -372,7 +385,7 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
 #pragma unroll
       for (int j = 0; j <= i; ++j) v[i * 6 + j] = double(h[i * 6 + j]);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gs[k] += double(gsl[k]);
+    for (int k = 0; k < 6; ++k) gs[k] += gsl[k];
   }
   for (int s = blk.z + lane; s < blk.z + blk.w; s += 64) {
     const int2 pr = a.spair[s];
@@ -1134,7 +1147,11 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
     return st;
   // solve workspace: obs records, prior records, objective partials, camera steps, frozen flags
   size_t off = 0;
-  p->ba_off[0] = off; off += align256((size_t)O * kObsRec * sizeof(double));
+  // observation records: float64, or (mixed) float records followed by the
+  // float64 gradient parts of each observation
+  p->ba_off[0] = off;
+  off += align256(std::max((size_t)O * kObsRec * sizeof(double),
+                           align256((size_t)O * kObsRec * sizeof(float)) + (size_t)O * 9 * sizeof(double)));
   p->ba_off[1] = off; off += align256((size_t)P * kPriorRec * sizeof(double));
   p->ba_off[2] = off; off += align256((size_t)B * nx * sizeof(double));
   p->ba_off[3] = off; off += align256((size_t)B * p->npad_max * sizeof(double));
@@ -1192,6 +1209,7 @@ static void bind_ws(dnls_plan p, BAArgs& a, void* ws, void* factor) {
   char* w = static_cast<char*>(ws);
   char* f = static_cast<char*>(factor);
   a.orec = w + p->ba_off[0];
+  a.gob = reinterpret_cast<double*>(w + p->ba_off[0] + align256((size_t)p->O * kObsRec * sizeof(float)));
   a.prec = reinterpret_cast<double*>(w + p->ba_off[1]);
   a.partial = reinterpret_cast<double*>(w + p->ba_off[2]);
   a.dc = reinterpret_cast<double*>(w + p->ba_off[3]);
@@ -1278,8 +1296,12 @@ dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
     a.it = it;
     a.lam_g = (adaptive && !final_lin) ? lam_g : nullptr;   // the final linearisation is undamped
     // the final (cached) linearisation is float64 in both precisions, and so
-    // is every step of the dogleg (its model uses the records)
-    if (mixed && !final_lin && !dogleg) {
+    // is every step of the dogleg (its model uses the records) and of adaptive
+    // damping: the float curvature of the mixed steps moves an iterate that
+    // is still far from convergence (the trajectory of refused and damped
+    // steps) by more than 1e-5, and without float64 refinement on this path
+    // the accept / reject decisions would follow that trajectory
+    if (mixed && !final_lin && !dogleg && !adaptive) {
       hipLaunchKernelGGL(k_ba_lin<float>, g_lin, blk, 0, st, a);
       hipLaunchKernelGGL(k_ba_point<float>, g_pt, blk, 0, st, a, lam);
       hipLaunchKernelGGL(k_ba_obs_ef<float>, g_obs, blk, 0, st, a);
