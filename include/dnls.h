@@ -119,15 +119,23 @@ typedef struct {
  * WORKGROUP: both with one workgroup per graph (vector in LDS, no launches
  * between tile steps); SWEEPS: one launch per tile column / row with one
  * workgroup per tile, for both; HYBRID: per-column factorisation launches,
- * workgroup solves.  AUTO: WORKGROUP when every graph has at most 6144
- * (padded) unknowns and 16 tile columns, HYBRID when it has at most 6144
- * unknowns, else SWEEPS.  WORKGROUP and HYBRID on a plan whose graphs exceed
- * 6144 unknowns are DNLS_ERR_UNSUPPORTED. */
+ * workgroup solves; PERSISTENT: the whole solve (every step of every graph,
+ * linearisation to retraction, and the final linearisation) in one launch
+ * of at most one workgroup per resident slot, which take the graphs from a
+ * device-memory queue, largest first (Section 4.1 "Batching and
+ * vectorization": graphs of uneven size batched in one launch); not with
+ * DNLS_FLAG_ADAPTIVE_LM or DNLS_FLAG_DOGLEG, and the plan's solves must not
+ * overlap (the queue is the plan's).  AUTO: for graphs of at most 6144
+ * (padded) unknowns and 16 tile columns PERSISTENT with a fixed-damping
+ * optimizer, else WORKGROUP; HYBRID for at most 6144 unknowns, else SWEEPS.  WORKGROUP, HYBRID and PERSISTENT
+ * on a plan whose graphs exceed 6144 unknowns, and PERSISTENT with adaptive
+ * damping or the dogleg, are DNLS_ERR_UNSUPPORTED. */
 typedef enum {
   DNLS_SPSOLVE_AUTO = 0,
   DNLS_SPSOLVE_WORKGROUP = 1,
   DNLS_SPSOLVE_SWEEPS = 2,
-  DNLS_SPSOLVE_HYBRID = 3
+  DNLS_SPSOLVE_HYBRID = 3,
+  DNLS_SPSOLVE_PERSISTENT = 4
 } dnls_sparse_solve;
 
 /* dnls_options.flags */

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3}
+SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3, "persistent": 4}
 BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2, "unroll": 3}
 FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2
@@ -292,11 +292,14 @@ class Plan:
         a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
-        a.workspace = self._aligned(self.workspace)
         a.edge_logc = _ptr(edge_logc)
+        self._run_solve(a)
+        return objective, status
+
+    def _run_solve(self, a):
+        a.workspace = self._aligned(self.workspace)
         _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
         self.solves += 1
-        return objective, status
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
                  edge_tau=None, want_adjoint=False, mode="implicit", eps=1e-3, sweeps=8, steps=None,
@@ -355,11 +358,9 @@ class Plan:
         a.prior_meas, a.prior_logw = _ptr(prior_meas), _ptr(prior_logw)
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
-        a.workspace = self._aligned(self.workspace)
         hd = self._radii(huber_delta)
         a.huber_delta = _ptr(hd)
-        _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
-        self.solves += 1
+        self._run_solve(a)
         return objective, status
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,

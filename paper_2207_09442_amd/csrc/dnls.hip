@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -624,6 +625,28 @@ __device__ void hvp_exact(const DenseArgs& a, const GraphDesc& g, const double* 
   __syncthreads();
 }
 
+// The adjoint u = H*^-1 v of the implicit backward: the two triangular
+// solves with the cached factor, then one step of float64 iterative
+// refinement u <- u + H*^-1 (v - H* u) with H* applied matrix-free from the
+// float64 records at theta_K, so that u carries the rounding of that product
+// rather than the factorisation's rounding amplified by cond(H*).  vu holds
+// v on entry and u on return; vx is scratch (npad each, LDS).
+template <int G>
+__device__ void adjoint_solve(const DenseArgs& a, const GraphDesc& g, const double* A, const double* winv,
+                              double* vu, double* vx, KernelLds& L) {
+  constexpr int d = GroupTraits<G>::d;
+  const double* seed = a.seed + (size_t)g.pose0 * d;
+  trsv_lower(A, g.npad, winv, vu, L.dl);
+  trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  matvec_H<G>(a, g, a.ws64, vu, vx, 0.0);
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = ((u < g.n) ? seed[u] : 0.0) - vx[u];
+  __syncthreads();
+  trsv_lower(A, g.npad, winv, vx, L.dl);
+  trsv_upper_t(A, g.npad, winv, vx, L.dl);
+  for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] += vx[u];
+  __syncthreads();
+}
+
 template <int G>
 __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
   constexpr int d = GroupTraits<G>::d;
@@ -638,12 +661,13 @@ __global__ void __launch_bounds__(kNT) k_dense_backward(DenseArgs a) {
   const double* A = a.factor + g.fac_off;
   const double* winv = A + (size_t)(g.npad + 16) * g.npad;
   double* vu = dyn;
+  double* vx = dyn + g.npad;
   for (int u = threadIdx.x; u < g.npad; u += kNT) vu[u] = (u < g.n) ? a.seed[(size_t)g.pose0 * d + u] : 0.0;
   __syncthreads();
-  // float64 linearisation at theta_K: residuals and Jacobians for the VJP
+  // float64 linearisation at theta_K: residuals and Jacobians for the
+  // refinement of the adjoint and for the VJP
   linearize_graph<G, double>(a, g, a.ws64, L.red);
-  trsv_lower(A, g.npad, winv, vu, L.dl);
-  trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  adjoint_solve<G>(a, g, A, winv, vu, vx, L);
   if (a.adjoint_out)
     for (int u = threadIdx.x; u < g.n; u += kNT) a.adjoint_out[(size_t)g.pose0 * d + u] = vu[u];
   // per-cost VJP:  dL/dphi = -d/dphi [ (J u)^T r ]
@@ -674,8 +698,8 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_exact(DenseArgs a, int s
   __syncthreads();
   linearize_graph<G, double>(a, g, a.ws64, L.red);
   assemble_g<G, double>(a, g, a.ws64, vg, nullptr);
-  trsv_lower(A, g.npad, winv, vu, L.dl);
-  trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  // the Gauss-Newton adjoint of the implicit mode, then the exact sweeps
+  adjoint_solve<G>(a, g, A, winv, vu, vx, L);
   for (int it = 0; it < sweeps; ++it) {
     hvp_exact<G>(a, g, a.ws64, vu, vx, vg);
     for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = ((u < g.n) ? seed[u] : 0.0) - vx[u];
@@ -985,7 +1009,7 @@ dnls_status launch_backward(dnls_plan p, const DenseArgs& a, hipStream_t st, int
     HIP_TRY(hipGetLastError());
     return DNLS_OK;
   }
-  const size_t lds = (size_t)p->npad_max * sizeof(double);
+  const size_t lds = 2 * (size_t)p->npad_max * sizeof(double);
   hipLaunchKernelGGL((k_dense_backward<G>), dim3(p->B), dim3(kNT), lds, st, a);
   HIP_TRY(hipGetLastError());
   return DNLS_OK;
@@ -1015,7 +1039,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->refine_last < -op->iterations || op->refine_last > op->iterations)
     return fail(DNLS_ERR_INVALID_ARG, "refine_last must be in 0..iterations");
-  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_HYBRID)
+  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_PERSISTENT)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
   if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES |
                            DNLS_FLAG_PAIR))
@@ -1212,7 +1236,9 @@ dnls_status dnls_plan_schedule(dnls_plan p, int32_t* dense_pair, int32_t* sparse
   if (sparse_solve) {
     *sparse_solve = DNLS_SPSOLVE_AUTO;
     if (p->opt.solver == DNLS_SOLVER_SPARSE)
-      *sparse_solve = p->sp_factor_wg ? DNLS_SPSOLVE_WORKGROUP : (p->sp_solve_wg ? DNLS_SPSOLVE_HYBRID : DNLS_SPSOLVE_SWEEPS);
+      *sparse_solve = p->sp_persistent ? DNLS_SPSOLVE_PERSISTENT
+                      : p->sp_factor_wg ? DNLS_SPSOLVE_WORKGROUP
+                      : (p->sp_solve_wg ? DNLS_SPSOLVE_HYBRID : DNLS_SPSOLVE_SWEEPS);
   }
   return DNLS_OK;
 }

@@ -130,6 +130,10 @@ struct dnls_plan_s {
   std::vector<long long> sp_npair;
   int sp_maxP = 0;
   bool sp_solve_wg = false;       // triangular solves: one workgroup per graph (vector in LDS)
+  bool sp_persistent = false;     // the whole solve in one persistent launch (graph work queue)
+  int sp_grid = 0;                // its workgroups: min(B, resident slots)
+  int* d_sp_order = nullptr;      // its queue order: graphs by decreasing factor work
+  unsigned* d_sp_queue = nullptr; // its two queue counters (self-resetting)
   bool sp_factor_wg = false;      // factorisation: one workgroup per graph
   size_t sp_off[16] = {0};
   std::vector<void*> allocs;

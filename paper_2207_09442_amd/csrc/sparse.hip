@@ -37,6 +37,7 @@ constexpr int kBT = 256;           // threads of the grid kernels
 constexpr int kTW = 192;           // threads of the tile kernels (3 waves x 16 rows)
 constexpr int kWG = 512;           // threads of the one-workgroup-per-graph kernels (2 waves per SIMD)
 constexpr int kWGW = kWG / 64;
+constexpr int kPT = 256;           // threads of the persistent whole-solve kernel (one wave per SIMD)
 
 struct SpArgs {
   const SpDesc* sd;
@@ -81,7 +82,8 @@ struct SpArgs {
   double* s_t;             // adaptive damping: float64 objective at theta_t per graph
   int* rej;                // adaptive damping / dogleg: the graph's trial step was rejected
   double* dl;              // dogleg per graph: radius, predicted decrease, |delta|, on the boundary
-  int E, K, it, nx, refine;
+  double* traj;            // persistent schedule with DNLS_FLAG_KEEP_ITERATES: theta_t, [K][V][sz]
+  int E, V, K, it, nx, refine;
   double lambda, radius0;
 };
 
@@ -160,74 +162,65 @@ __device__ __forceinline__ void put(const SpArgs& a, const SpDesc& g, int row, i
   t[(row % kTS) * kTS + col % kTS] = v;
 }
 
-// Hessian blocks into the tiles (permuted, lower triangle), g into vec[1]
+// Hessian blocks into the tiles (permuted, lower triangle), g into vec[1].
+// Item u < npose + nod: one diagonal or off-diagonal block (and, for u <
+// npose with rhs_from_rec, that pose's segment of g).
 template <int G, class S>
-__global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, double lambda, int rhs_from_rec,
-                                                     int lam_per_graph) {
+__device__ __forceinline__ void sp_assemble_item(const SpArgs& a, const SpDesc& g, int u, const S* rec,
+                                                 double lambda, int rhs_from_rec) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
-  const int b = blockIdx.y;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
-  if (lam_per_graph) lambda = a.lam_g[b];
-  const int u = blockIdx.x * kBT + threadIdx.x;
-  if (u < g.npose + g.nod) {
-    S h[d * d];
+  S h[d * d];
 #pragma unroll
-    for (int q = 0; q < d * d; ++q) h[q] = S(0);
-    int pa, pb;
-    if (u < g.npose) {
-      pa = pb = u;
-      const int gp = g.pose0 + u;
-      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
-        const int slot = a.inc_slot[s];
-        const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+  for (int q = 0; q < d * d; ++q) h[q] = S(0);
+  int pa, pb;
+  if (u < g.npose) {
+    pa = pb = u;
+    const int gp = g.pose0 + u;
+    for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
+      const int slot = a.inc_slot[s];
+      const S* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
 #pragma unroll
-        for (int k = 0; k < d; ++k)
+      for (int k = 0; k < d; ++k)
 #pragma unroll
-          for (int r = 0; r < d; ++r)
+        for (int r = 0; r < d; ++r)
 #pragma unroll
-            for (int c = 0; c < d; ++c) h[r * d + c] += J[k * d + r] * J[k * d + c];
-      }
-    } else {
-      const int4 blk = a.od_blk[g.od0 + (u - g.npose)];
-      pa = blk.x;
-      pb = blk.y;
-      for (int s = blk.z; s < blk.z + blk.w; ++s) {
-        const int slot = a.od_slot[s];
-        const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
-        const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
+          for (int c = 0; c < d; ++c) h[r * d + c] += J[k * d + r] * J[k * d + c];
+    }
+  } else {
+    const int4 blk = a.od_blk[g.od0 + (u - g.npose)];
+    pa = blk.x;
+    pb = blk.y;
+    for (int s = blk.z; s < blk.z + blk.w; ++s) {
+      const int slot = a.od_slot[s];
+      const S* Jr = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
+      const S* Jc = rec + (size_t)(slot >> 1) * RN + ((slot & 1) ^ 1) * d * d;
 #pragma unroll
-        for (int k = 0; k < d; ++k)
+      for (int k = 0; k < d; ++k)
 #pragma unroll
-          for (int r = 0; r < d; ++r)
+        for (int r = 0; r < d; ++r)
 #pragma unroll
-            for (int c = 0; c < d; ++c) h[r * d + c] += Jr[k * d + r] * Jc[k * d + c];
+          for (int c = 0; c < d; ++c) h[r * d + c] += Jr[k * d + r] * Jc[k * d + c];
+    }
+  }
+  const int ra = a.pos[g.pose0 + pa], rb = a.pos[g.pose0 + pb];
+#pragma unroll
+  for (int r = 0; r < d; ++r)
+#pragma unroll
+    for (int c = 0; c < d; ++c) {
+      double v = double(h[r * d + c]);
+      if (pa == pb) {
+        if (c > r) continue;
+        if (c == r) v += lambda;
+        put(a, g, ra * d + r, ra * d + c, v);
+      } else if (ra > rb) {
+        put(a, g, ra * d + r, rb * d + c, v);
+      } else {
+        put(a, g, rb * d + c, ra * d + r, v);
       }
     }
-    const int ra = a.pos[g.pose0 + pa], rb = a.pos[g.pose0 + pb];
-#pragma unroll
-    for (int r = 0; r < d; ++r)
-#pragma unroll
-      for (int c = 0; c < d; ++c) {
-        double v = double(h[r * d + c]);
-        if (pa == pb) {
-          if (c > r) continue;
-          if (c == r) v += lambda;
-          put(a, g, ra * d + r, ra * d + c, v);
-        } else if (ra > rb) {
-          put(a, g, ra * d + r, rb * d + c, v);
-        } else {
-          put(a, g, rb * d + c, ra * d + r, v);
-        }
-      }
-  }
-  // padding of the last tile
-  if (blockIdx.x == 0)
-    for (int r = g.n + threadIdx.x; r < g.P * kTS; r += kBT) put(a, g, r, r, 1.0);
-  // right-hand side g (permuted) into vec[1]
-  double* rhs = a.vec + g.vec_off + g.nvec;
   if (rhs_from_rec && u < g.npose) {
-    const int gp = g.pose0 + u, ra = a.pos[gp];
+    double* rhs = a.vec + g.vec_off + g.nvec;
+    const int gp = g.pose0 + u;
     S acc[d];
 #pragma unroll
     for (int r = 0; r < d; ++r) acc[r] = S(0);
@@ -243,19 +236,32 @@ __global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, dou
 #pragma unroll
     for (int r = 0; r < d; ++r) rhs[ra * d + r] = double(acc[r]);
   }
-  if (blockIdx.x == 0)
-    for (int r = g.n + threadIdx.x; r < g.nvec; r += kBT) rhs[r] = 0.0;
+}
+
+// padding of the last tile (unit diagonal) and of the right-hand side
+// (zero), threads t = t0, t0 + stride, ...
+__device__ __forceinline__ void sp_assemble_pad(const SpArgs& a, const SpDesc& g, int t0, int stride) {
+  for (int r = g.n + t0; r < g.P * kTS; r += stride) put(a, g, r, r, 1.0);
+  double* rhs = a.vec + g.vec_off + g.nvec;
+  for (int r = g.n + t0; r < g.nvec; r += stride) rhs[r] = 0.0;
+}
+
+template <int G, class S>
+__global__ void __launch_bounds__(kBT) k_sp_assemble(SpArgs a, const S* rec, double lambda, int rhs_from_rec,
+                                                     int lam_per_graph) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  if (lam_per_graph) lambda = a.lam_g[b];
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose + g.nod) sp_assemble_item<G, S>(a, g, u, rec, lambda, rhs_from_rec);
+  if (blockIdx.x == 0) sp_assemble_pad(a, g, threadIdx.x, kBT);
 }
 
 // float64 right-hand side into vec[1] (mixed path with refinement)
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_rhs64(SpArgs a) {
+__device__ __forceinline__ void sp_rhs64_item(const SpArgs& a, const SpDesc& g, int u) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
-  const int b = blockIdx.y;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
-  const int u = blockIdx.x * kBT + threadIdx.x;
-  if (u >= g.npose) return;
   const int gp = g.pose0 + u, ra = a.pos[gp];
   double acc[d];
 #pragma unroll
@@ -272,6 +278,15 @@ __global__ void __launch_bounds__(kBT) k_sp_rhs64(SpArgs a) {
   double* rhs = a.vec + g.vec_off + g.nvec;
 #pragma unroll
   for (int r = 0; r < d; ++r) rhs[ra * d + r] = acc[r];
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_rhs64(SpArgs a) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose) sp_rhs64_item<G>(a, g, u);
 }
 
 // 1. diagonal tile of column J
@@ -440,21 +455,19 @@ __device__ __forceinline__ void wave_slab_update(double* T, const double* LI, co
     for (int r = 0; r < 4; ++r) T[(16 * sr + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
-__global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
-  __shared__ DenseLds s;
-  const int b = blockIdx.x;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
+// (NT threads, a multiple of 64) returns false if the graph is not positive definite
+template <int NT>
+__device__ bool sp_factor_wg_body(const SpArgs& a, int b, const SpDesc& g, DenseLds& s) {
   const int wave = threadIdx.x >> 6;
   for (int J = 0; J < g.P; ++J) {
     // 1. diagonal tile
     double* TJ = tile_ptr(a, g, J, J);
     double* D = s.stage[0];
-    for (int e = threadIdx.x; e < kTT; e += kWG) D[(e / kTS) * kSP + e % kTS] = TJ[e];
+    for (int e = threadIdx.x; e < kTT; e += NT) D[(e / kTS) * kSP + e % kTS] = TJ[e];
     __syncthreads();
     const bool ok = chol_block<3>(D, s.W, s);
     double* winv = a.factor + g.winv_off + (size_t)J * kTT;
-    for (int e = threadIdx.x; e < kTT; e += kWG) {
+    for (int e = threadIdx.x; e < kTT; e += NT) {
       const int r = e / kTS, c = e % kTS;
       TJ[e] = (c <= r) ? D[r * kSP + c] : 0.0;
       winv[e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
@@ -464,17 +477,17 @@ __global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
         a.failed[b] = DNLS_GRAPH_NOT_PD;
         a.status[b] = DNLS_GRAPH_NOT_PD;
       }
-      return;
+      return false;
     }
     const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
     // 2. L_IJ = A_IJ W^T for the tiles below the diagonal (W stays in LDS)
 #pragma unroll 1
-    for (int u = wave; u < 3 * m; u += kWGW) wave_slab_trsm(tile_ptr(a, g, a.rowidx[c0 + 1 + u / 3], J), s.W, u % 3);
+    for (int u = wave; u < 3 * m; u += (NT / 64)) wave_slab_trsm(tile_ptr(a, g, a.rowidx[c0 + 1 + u / 3], J), s.W, u % 3);
     __syncthreads();
     // 3. A_IK -= L_IJ L_KJ^T for every lower pair of them
     const int npair = m * (m + 1) / 2;
 #pragma unroll 1
-    for (int u = wave; u < 3 * npair; u += kWGW) {
+    for (int u = wave; u < 3 * npair; u += (NT / 64)) {
       const int t = u / 3;
       int p = (int)((::sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
       while ((p + 1) * (p + 2) / 2 <= t) ++p;
@@ -485,6 +498,15 @@ __global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
     }
     __syncthreads();
   }
+  return true;
+}
+
+__global__ void __launch_bounds__(kWG) k_sp_factor_wg(SpArgs a) {
+  __shared__ DenseLds s;
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  sp_factor_wg_body<kWG>(a, b, g, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,15 +630,12 @@ __global__ void __launch_bounds__(kTW) k_sp_bwd(SpArgs a, int I, int zs, int dst
 // launches, where the sweeps need two launches per tile column.
 constexpr int kSolveLds = 6144;
 constexpr int kFactorWgMaxP = 16;  // AUTO: one-workgroup factorisation up to 16 tile columns
-__global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst) {
-  __shared__ double v[kSolveLds];
-  __shared__ double Wl[kTS * kSW];
-  __shared__ double y[kTS];
-  const int b = blockIdx.x;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
+// (NT >= 192 threads, a multiple of 64) v: nvec doubles, Wl: kTS x kSW, y: kTS, all in LDS
+template <int NT>
+__device__ void sp_solve_wg_body(const SpArgs& a, const SpDesc& g, int src, int dst, double* v, double* Wl,
+                                 double* y) {
   const double* bsrc = slot(a, g, src);
-  for (int u = threadIdx.x; u < g.nvec; u += kWG) v[u] = bsrc[u];
+  for (int u = threadIdx.x; u < g.nvec; u += NT) v[u] = bsrc[u];
   // the 48 products with W are split over 4 adjacent lanes each (12 terms)
   const int wr = threadIdx.x >> 2, wp = threadIdx.x & 3;
   for (int J = 0; J < g.P; ++J) {
@@ -633,7 +652,7 @@ __global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst)
     __syncthreads();
     if (threadIdx.x < kTS) v[J * kTS + threadIdx.x] = y[threadIdx.x];
     const int c0 = a.colptr[g.col_off + J], m = a.colptr[g.col_off + J + 1] - c0 - 1;
-    for (int e = threadIdx.x; e < m * kTS; e += kWG) {
+    for (int e = threadIdx.x; e < m * kTS; e += NT) {
       const int I = a.rowidx[c0 + 1 + e / kTS], r = e % kTS;
       const d4v* row = reinterpret_cast<const d4v*>(tile_ptr(a, g, I, J) + r * kTS);
       double acc = 0.0;
@@ -660,7 +679,7 @@ __global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst)
     __syncthreads();
     if (threadIdx.x < kTS) v[I * kTS + threadIdx.x] = y[threadIdx.x];
     const int r0 = a.rowptr[g.row_off + I], nr = a.rowptr[g.row_off + I + 1] - r0;
-    for (int e = threadIdx.x; e < nr * kTS; e += kWG) {
+    for (int e = threadIdx.x; e < nr * kTS; e += NT) {
       const int J = a.rowcol[r0 + e / kTS], c = e % kTS;
       const double* T = tile_ptr(a, g, I, J);
       double acc = 0.0;
@@ -671,7 +690,17 @@ __global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst)
     __syncthreads();
   }
   double* xdst = slot(a, g, dst);
-  for (int u = threadIdx.x; u < g.nvec; u += kWG) xdst[u] = v[u];
+  for (int u = threadIdx.x; u < g.nvec; u += NT) xdst[u] = v[u];
+}
+
+__global__ void __launch_bounds__(kWG) k_sp_solve_wg(SpArgs a, int src, int dst) {
+  __shared__ double v[kSolveLds];
+  __shared__ double Wl[kTS * kSW];
+  __shared__ double y[kTS];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  sp_solve_wg_body<kWG>(a, g, src, dst, v, Wl, y);
 }
 
 // slot[to] = slot[from] (grid x over the vector, y over graphs)
@@ -686,32 +715,28 @@ __global__ void __launch_bounds__(kBT) k_sp_copy(SpArgs a, int from, int to) {
 
 // X <- X Exp(-x) per pose, x read in permuted order
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_retract(SpArgs a, int xs) {
+__device__ __forceinline__ void sp_retract_item(const SpArgs& a, const SpDesc& g, int p, int xs) {
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
+  retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, slot(a, g, xs) + a.pos[g.pose0 + p] * d);
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_retract(SpArgs a, int xs) {
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
   const int p = blockIdx.x * kBT + threadIdx.x;
-  if (p >= g.npose) return;
-  retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, slot(a, g, xs) + a.pos[g.pose0 + p] * d);
+  if (p < g.npose) sp_retract_item<G>(a, g, p, xs);
 }
 
 // refinement residual b = g64 - (H64 + lambda) x (matrix-free, float64
 // records and J x per cost in ycost), padding zero
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda, int lam_per_graph) {
+__device__ __forceinline__ void sp_residual_item(const SpArgs& a, const SpDesc& g, int p, double lambda) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
-  const int b = blockIdx.y;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
-  if (lam_per_graph) lambda = a.lam_g[b];
   const double* x = slot(a, g, 0);
   const double* rhs = slot(a, g, 1);
   double* res = slot(a, g, 2);
-  if (blockIdx.x == 0)
-    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
-  const int p = blockIdx.x * kBT + threadIdx.x;
-  if (p >= g.npose) return;
   const int gp = g.pose0 + p, ra = a.pos[gp];
   double hv[d];
 #pragma unroll
@@ -729,15 +754,24 @@ __global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda, in
   for (int r = 0; r < d; ++r) res[ra * d + r] = rhs[ra * d + r] - hv[r];
 }
 
-// refinement: J delta per cost (float64 records), delta read in permuted order
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a, int xs) {
-  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+__global__ void __launch_bounds__(kBT) k_sp_residual(SpArgs a, double lambda, int lam_per_graph) {
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
-  const int k = blockIdx.x * kBT + threadIdx.x;
-  if (k >= g.nedge + g.nprior) return;
+  if (lam_per_graph) lambda = a.lam_g[b];
+  if (blockIdx.x == 0) {
+    double* res = slot(a, g, 2);
+    for (int u = g.n + threadIdx.x; u < g.nvec; u += kBT) res[u] = 0.0;
+  }
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p < g.npose) sp_residual_item<G>(a, g, p, lambda);
+}
+
+// refinement: J delta per cost (float64 records), delta read in permuted order
+template <int G>
+__device__ __forceinline__ void sp_jx_item(const SpArgs& a, const SpDesc& g, int k, int xs) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
   const double* x = slot(a, g, xs);
   int rk, pi = -1, pj;
   if (k < g.nedge) {
@@ -759,6 +793,15 @@ __global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a, int xs) {
     }
     a.ycost[(size_t)rk * d + r] = acc;
   }
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_jx(SpArgs a, int xs) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int k = blockIdx.x * kBT + threadIdx.x;
+  if (k < g.nedge + g.nprior) sp_jx_item<G>(a, g, k, xs);
 }
 
 // y = (H64 + lambda I) x per pose from J x per cost (ycost), x and y slots
@@ -871,18 +914,22 @@ __global__ void __launch_bounds__(kBT) k_sp_dl_pred(SpArgs a) {
 
 // x += correction (slot 2) per pose, then retract on the last sweep
 template <int G>
-__global__ void __launch_bounds__(kBT) k_sp_accumulate(SpArgs a, int retract) {
+__device__ __forceinline__ void sp_accumulate_item(const SpArgs& a, const SpDesc& g, int p, int retract) {
   constexpr int d = GroupTraits<G>::d, sz = GroupTraits<G>::sz;
-  const int b = blockIdx.y;
-  const SpDesc g = a.sd[b];
-  if (a.failed[b]) return;
-  const int p = blockIdx.x * kBT + threadIdx.x;
-  if (p >= g.npose) return;
   double* x = slot(a, g, 0) + a.pos[g.pose0 + p] * d;
   const double* dx = slot(a, g, 2) + a.pos[g.pose0 + p] * d;
 #pragma unroll
   for (int r = 0; r < d; ++r) x[r] += dx[r];
   if (retract) retract_minus<G>(a.poses + (size_t)(g.pose0 + p) * sz, x);
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBT) k_sp_accumulate(SpArgs a, int retract) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const int p = blockIdx.x * kBT + threadIdx.x;
+  if (p < g.npose) sp_accumulate_item<G>(a, g, p, retract);
 }
 
 // exact-Hessian backward, per cost: J u (ycost) and the second-order terms
@@ -1212,6 +1259,145 @@ __global__ void __launch_bounds__(kBT) k_sp_vjp(SpArgs a) {
   cost_vjp<G>(cost_data(a), rk, a.ws64 + (size_t)rk * RN, ui, uj, a.g_logw_e, a.g_tau, a.g_logw_p, a.g_logc);
 }
 
+// ---------------------------------------------------------------------------
+// Persistent whole-solve kernel (schedule PERSISTENT): one launch runs every
+// step of every graph.  A grid of at most one workgroup per resident slot
+// takes graphs from a device-memory queue (largest first, the plan's launch
+// order), and each workgroup then runs the graph's K steps and its final
+// linearisation with no launch in between: linearisation, assembly into the
+// tile pool, the one-workgroup tile factorisation, the one-workgroup
+// triangular solves in LDS, the float64 refinement sweeps of the mixed path
+// and the retraction, separated by workgroup barriers.  The same per-item
+// code as the per-phase kernels, so the arithmetic is the same.
+// queue[0]: next graph slot; queue[1]: workgroups done (the last one resets
+// both, so every launch, or every replay of a captured graph, starts at 0).
+// ---------------------------------------------------------------------------
+union FusedLds {
+  DenseLds f;
+  struct {
+    double v[kSolveLds];
+    double Wl[kTS * kSW];
+    double y[kTS];
+  } s;
+};
+
+template <int G, bool MIXED>
+__global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* order, unsigned* queue, int B,
+                                                       int refine_from, int refine_until) {
+  constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n, sz = GroupTraits<G>::sz;
+  __shared__ FusedLds L;
+  __shared__ double red[kPT / 64];
+  __shared__ int q_slot, stop;
+  const PoseCostData cd = cost_data(a);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) q_slot = (int)atomicAdd(&queue[0], 1u);
+    __syncthreads();
+    if (q_slot >= B) break;
+    const int b = order[q_slot];
+    const SpDesc g = a.sd[b];
+    double* obj = a.objective + (size_t)b * (a.K + 1);
+    if (threadIdx.x == 0) {
+      a.failed[b] = 0;
+      a.status[b] = DNLS_GRAPH_OK;
+    }
+    const int ncost = g.nedge + g.nprior;
+    double last = 0.0;
+    int it = 0;
+    for (; it <= a.K; ++it) {
+      const bool final_lin = it == a.K;
+      const double lam = final_lin ? 0.0 : a.lambda;
+      if (a.traj && !final_lin) {
+        // DNLS_FLAG_KEEP_ITERATES: theta_t into the factor cache
+        double* dst = a.traj + ((size_t)it * a.V + g.pose0) * sz;
+        for (int u = threadIdx.x; u < g.npose * sz; u += kPT) dst[u] = a.poses[(size_t)g.pose0 * sz + u];
+      }
+      const bool lin32 = MIXED && !final_lin;
+      const bool refine_now = lin32 && a.refine > 0 && it >= refine_from && it < refine_until;
+      const bool lin64 = !MIXED || refine_now || final_lin;
+      // 1. linearisation (float64 last, so that S is the float64 objective
+      // whenever float64 records are made)
+      double s32 = 0.0, s64 = 0.0;
+      for (int k = threadIdx.x; k < ncost; k += kPT) {
+        const int rk = (k < g.nedge) ? g.edge0 + k : a.E + g.prior0 + (k - g.nedge);
+        if (lin32) s32 += linearize_cost<G, float>(cd, rk, a.ws32 + (size_t)rk * RN);
+        if (lin64) s64 += linearize_cost<G, double>(cd, rk, a.ws64 + (size_t)rk * RN);
+      }
+      const double S = block_sum_sp(lin64 ? s64 : s32, red);
+      last = S;
+      if (threadIdx.x == 0) obj[it] = S;
+      if (!isfinite(S)) {
+        if (threadIdx.x == 0) {
+          a.failed[b] = DNLS_GRAPH_NONFINITE;
+          a.status[b] = DNLS_GRAPH_NONFINITE;
+        }
+        break;
+      }
+      // 2. zero the tile pool, then assemble H (+ lambda I) and g
+      {
+        d4v* pool = reinterpret_cast<d4v*>(a.factor + g.pool_off);
+        const size_t n4 = (size_t)g.ntile * (kTT / 4);
+        for (size_t u = threadIdx.x; u < n4; u += kPT) pool[u] = d4v{0.0, 0.0, 0.0, 0.0};
+      }
+      __syncthreads();
+      const int nblk = g.npose + g.nod;
+      if (lin32) {
+        for (int u = threadIdx.x; u < nblk; u += kPT)
+          sp_assemble_item<G, float>(a, g, u, a.ws32, lam, refine_now ? 0 : 1);
+        if (refine_now)
+          for (int u = threadIdx.x; u < g.npose; u += kPT) sp_rhs64_item<G>(a, g, u);
+      } else {
+        for (int u = threadIdx.x; u < nblk; u += kPT) sp_assemble_item<G, double>(a, g, u, a.ws64, lam, 1);
+      }
+      sp_assemble_pad(a, g, threadIdx.x, kPT);
+      __syncthreads();
+      // 3. factorisation
+      if (!sp_factor_wg_body<kPT>(a, b, g, L.f)) break;
+      if (final_lin) break;
+      // 4. step: slot 2 = g, slot 0 = (L L^T)^-1 g
+      {
+        double* x = slot(a, g, 2);
+        const double* rhs = slot(a, g, 1);
+        for (int u = threadIdx.x; u < g.nvec; u += kPT) x[u] = rhs[u];
+      }
+      __syncthreads();
+      sp_solve_wg_body<kPT>(a, g, 2, 0, L.s.v, L.s.Wl, L.s.y);
+      __syncthreads();
+      if (!refine_now) {
+        for (int p = threadIdx.x; p < g.npose; p += kPT) sp_retract_item<G>(a, g, p, 0);
+      } else {
+        for (int sw = 0; sw < a.refine; ++sw) {
+          // slot 2 = g64 - (H64 + lambda I) x;  x += (L L^T)^-1 slot 2
+          for (int k = threadIdx.x; k < ncost; k += kPT) sp_jx_item<G>(a, g, k, 0);
+          __syncthreads();
+          {
+            double* res = slot(a, g, 2);
+            for (int u = g.n + threadIdx.x; u < g.nvec; u += kPT) res[u] = 0.0;
+          }
+          for (int p = threadIdx.x; p < g.npose; p += kPT) sp_residual_item<G>(a, g, p, lam);
+          __syncthreads();
+          sp_solve_wg_body<kPT>(a, g, 2, 2, L.s.v, L.s.Wl, L.s.y);
+          __syncthreads();
+          for (int p = threadIdx.x; p < g.npose; p += kPT) sp_accumulate_item<G>(a, g, p, sw + 1 == a.refine);
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+    }
+    // a failed graph keeps its poses and repeats its last objective
+    if (it < a.K && threadIdx.x == 0)
+      for (int t = it + 1; t <= a.K; ++t) obj[t] = last;
+  }
+  // the last workgroup to finish resets the queue for the next launch
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
+      atomicExch(&queue[0], 0u);
+      atomicExch(&queue[1], 0u);
+    }
+  }
+}
+
 __global__ void k_sp_reset(int* failed, int* status, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) {
@@ -1442,15 +1628,49 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sp_maxP = maxP;
   const bool fits = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
   const int mode = p->opt.sparse_solve;
-  if ((mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID) && !fits)
+  const bool fixed_damping = !(p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG));
+  if ((mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID || mode == DNLS_SPSOLVE_PERSISTENT) && !fits)
     return fail(DNLS_ERR_UNSUPPORTED, "the workgroup solve holds at most " + std::to_string(kSolveLds) +
                                           " unknowns per graph");
-  // AUTO: everything in one workgroup per graph for graphs of a few tile
-  // columns; the per-column launches spread larger graphs over the chip
+  if (mode == DNLS_SPSOLVE_PERSISTENT && !fixed_damping)
+    return fail(DNLS_ERR_UNSUPPORTED, "the persistent schedule runs fixed-damping steps only");
+  // AUTO: for graphs of a few tile columns everything in one workgroup per
+  // graph (the whole solve in one persistent launch with fixed damping); the
+  // per-column launches spread larger graphs over the chip (one workgroup's
+  // factorisation of a 32-column graph takes longer than the batch's
+  // per-column launches)
   const bool small = fits && maxP <= kFactorWgMaxP;
-  p->sp_solve_wg = mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID ||
+  p->sp_persistent = mode == DNLS_SPSOLVE_PERSISTENT || (mode == DNLS_SPSOLVE_AUTO && small && fixed_damping);
+  p->sp_solve_wg = mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID || p->sp_persistent ||
                    (mode == DNLS_SPSOLVE_AUTO && fits);
-  p->sp_factor_wg = mode == DNLS_SPSOLVE_WORKGROUP || (mode == DNLS_SPSOLVE_AUTO && small);
+  p->sp_factor_wg = mode == DNLS_SPSOLVE_WORKGROUP || p->sp_persistent || (mode == DNLS_SPSOLVE_AUTO && small);
+  if (p->sp_persistent) {
+    // queue order: decreasing factor work (tile-level flops), ties by index
+    std::vector<double> work(B);
+    for (int b = 0; b < B; ++b) {
+      const SpDesc& g = p->sd[b];
+      double w = 0.0;
+      for (int J = 0; J < g.P; ++J) {
+        const double m = colptr[g.col_off + J + 1] - colptr[g.col_off + J] - 1;
+        w += 1.0 + m + m * (m + 1) / 2.0;
+      }
+      work[b] = w;
+    }
+    std::vector<int> order(B);
+    for (int b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_sp_persistent<3, true>), kPT, 0));
+    p->sp_grid = std::max(1, std::min(B, std::max(1, per_cu) * std::max(1, cus)));
+    dnls_status ust = upload(p, &p->d_sp_order, order);
+    if (ust != DNLS_OK) return ust;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&p->d_sp_queue), 2 * sizeof(unsigned)));
+    p->allocs.push_back(p->d_sp_queue);
+    HIP_TRY(hipMemset(p->d_sp_queue, 0, 2 * sizeof(unsigned)));
+  }
   dnls_status st;
   if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_edge_ij, edge_ij)) != DNLS_OK ||
       (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK || (st = upload(p, &p->d_pos, pos)) != DNLS_OK ||
@@ -1586,6 +1806,22 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   const bool dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) != 0;
   const bool keep = (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) != 0;
   const int sz = GroupTraits<G>::sz;
+  // mixed: steps refine_from <= it < refine_until run the refinement sweeps
+  // (the last refine_last steps, or the first -refine_last, or all)
+  const int K = p->opt.iterations, rl = p->opt.refine_last;
+  const int refine_from = rl > 0 ? K - rl : 0, refine_until = rl < 0 ? -rl : K;
+  if (p->sp_persistent) {
+    a.traj = keep ? a.factor + p->traj_off : nullptr;
+    a.V = p->V;
+    if (mixed)
+      hipLaunchKernelGGL((k_sp_persistent<G, true>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+                         p->d_sp_queue, B, refine_from, refine_until);
+    else
+      hipLaunchKernelGGL((k_sp_persistent<G, false>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+                         p->d_sp_queue, B, refine_from, refine_until);
+    HIP_TRY(hipGetLastError());
+    return DNLS_OK;
+  }
   hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
   if (adaptive) hipLaunchKernelGGL(k_sp_lam_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
   if (dogleg) hipLaunchKernelGGL(k_sp_dl_init, dim3((B + 255) / 256), dim3(256), 0, st, a, B);
@@ -1600,8 +1836,7 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
       hipLaunchKernelGGL(k_sp_backup, g_pose, dim3(kBT), 0, st, ak, sz);
     }
     const bool lin32 = mixed && !final_lin;
-    const bool refine_now = lin32 && a.refine > 0 &&
-                            (p->opt.refine_last == 0 || it >= p->opt.iterations - p->opt.refine_last);
+    const bool refine_now = lin32 && a.refine > 0 && it >= refine_from && it < refine_until;
     // the dogleg's model and decision use the float64 gradient and objective
     const bool lin64 = !mixed || refine_now || final_lin || dogleg;
     if (lin32) hipLaunchKernelGGL((k_sp_lin<G, float>), g_cost, dim3(kBT), 0, st, a, a.ws32);
@@ -1759,7 +1994,17 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   }
   hipLaunchKernelGGL((k_sp_lin<G, double>), g_cost, dim3(kBT), 0, st, a, a.ws64);
   hipLaunchKernelGGL(k_sp_seed, g_pose, dim3(kBT), 0, st, a, GroupTraits<G>::d);
+  // u = H*^-1 v (slot 0; v kept in slot 1), then one step of float64
+  // iterative refinement u <- u + H*^-1 (v - H* u), H* matrix-free from the
+  // float64 records at theta_K: u then carries the rounding of that product
+  // rather than the factorisation's rounding amplified by cond(H*)
+  const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
+  hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 2, 1);
   sp_sweeps(p, a, 0, st);
+  hipLaunchKernelGGL(k_sp_jx<G>, g_cost, dim3(kBT), 0, st, a, 0);
+  hipLaunchKernelGGL(k_sp_residual<G>, g_pose, dim3(kBT), 0, st, a, 0.0, 0);
+  sp_sweeps(p, a, 2, st);
+  hipLaunchKernelGGL(k_sp_accumulate<G>, g_pose, dim3(kBT), 0, st, a, 0);
   if (s->mode == DNLS_BACKWARD_EXACT)
     // u <- u + H*^-1 (v - Hx u), preconditioned by the cached factor
     for (int sw = 0; sw < s->sweeps; ++sw) {
