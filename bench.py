@@ -171,7 +171,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=["se2_circle_b1", "se3_walk64_b128", "se3_lattice16_b8", "se3_uneven_b256",
                              "ba_ring64_b4"])
-    ap.add_argument("--refine", type=int, default=1, help="float64 refinement sweeps of the mixed path")
+    ap.add_argument("--refine", type=int, default=None,
+                    help="float64 refinement sweeps of the mixed path (default: the sweeps that hold 1e-5: "
+                         "2 on the 16^3 lattice, 3 on the 256-pose walks, else 1)")
     ap.add_argument("--refine-last", type=int, default=0,
                     help="mixed path: refinement sweeps in the last N steps only (N < 0: the first -N "
                          "steps; 0 = every step, the default, the one that holds 1e-5 on the gradients)")
@@ -219,6 +221,11 @@ def main():
     dev = torch.device("cuda:0")
     W = synth.WORKLOADS[args.workload]
     K, lam, solver = W["iterations"], W["lam"], W["solver"]
+    if args.refine is None:
+        # the sweeps that hold every result within 1e-5: more on the worse
+        # conditioned workloads (cond(H) ~4e8 walks, ~7e8 lattice, ~1e11
+        # for the 256-pose walks)
+        args.refine = {"se3_lattice16_b8": 2, "se3_uneven_b256": 3}.get(args.workload, 1)
     if args.solver and solver != "schur":
         solver = args.solver
     p = W["fn"](**W["kwargs"])

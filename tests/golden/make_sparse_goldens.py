@@ -15,8 +15,15 @@ at the oracle's theta_K.  `grad_spread` is how far the oracle's own gradient
 moves (max norm, relative to the gradient's max norm) when the final
 linearisation is summed in a permuted edge order or theta_K is moved by a
 random right perturbation of relative size 1e-13: the floor below which two
-correct float64 implementations cannot be told apart on this graph.  Inputs come from the seeded generators in synth/;
-everything else from oracle/.  About twelve minutes on one core:
+correct float64 implementations cannot be told apart on this graph.
+`order_pose`, `order_objective` and `order_grad` are the element-wise
+differences (poses with a floor of 1e-3 of the largest entry, objectives per
+entry, gradients against the largest element) between this solve and the same
+solve and backward on the graph with its poses relabelled at random, so that
+minimum degree eliminates in another order: how far two correct float64
+factorisations of these ill-conditioned systems drift apart through rounding
+alone.  Inputs come from the seeded generators in synth/;
+everything else from oracle/.  About twenty-five minutes on one core:
 
     python tests/golden/make_sparse_goldens.py
 """
@@ -40,6 +47,25 @@ CASES = {
     "lattice16_g0": dict(make=lambda: synth.lattice_se3(batch=8, side=16), graph=0, K=15, lam=0.0),
     "lattice11_sweeps": dict(make=lambda: synth.lattice_se3(batch=1, side=11, seed=4), graph=0, K=4, lam=1e-3),
 }
+
+
+def ew_ratio(a, b, floor):
+    """max_i |a_i - b_i| / max(|b_i|, floor max |b|)"""
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    den = np.maximum(np.abs(b), floor * np.abs(b).max())
+    return float(np.max(np.abs(a - b) / np.where(den > 0, den, 1.0)))
+
+
+def relabelled(g, rng):
+    """The graph with its poses renumbered by a random permutation (pose k of
+    the new graph is pose perm[k] of the old one); edges and priors keep
+    their order.  Returns (graph, perm)."""
+    import dataclasses
+
+    import torch
+    perm = rng.permutation(g.X.shape[0])
+    inv = torch.as_tensor(np.argsort(perm))
+    return dataclasses.replace(g, X=g.X[torch.as_tensor(perm)], ei=inv[g.ei], ej=inv[g.ej], pv=inv[g.pv]), perm
 
 
 def _flat(o, inv=None):
@@ -84,13 +110,28 @@ def make(name: str) -> str:
     _, v = S.pose_error_loss_and_seed("SE3", poses, p["poses_gt"][lo:hi])
     gr = S.implicit_grad_graph_sparse(g, res, v)
     spread = grad_spread(g, res, v)
+    # the same solve and backward on the graph with its poses relabelled by a
+    # random permutation: minimum degree then breaks its ties differently, so
+    # every factorisation runs in another elimination order; the element-wise
+    # drift between two correct float64 factorisations, per result
+    g2, perm = relabelled(g, np.random.default_rng(7))
+    alt = S.solve_graph_sparse(g2, c["K"], c["lam"])
+    assert alt.status == S.OK, alt.status
+    ga = S.implicit_grad_graph_sparse(g2, alt, v[perm])
+    ref = _flat(gr)
+    inv = np.argsort(perm)
+    order_pose = ew_ratio(lie.SE3.to_storage(alt.X).numpy()[inv], poses, 1e-3)
+    order_obj = ew_ratio(np.asarray(alt.objective), np.asarray(res.objective), 1e-12)
+    order_grad = float(np.abs(_flat(ga) - ref).max() / np.abs(ref).max())
     out = os.path.join(HERE, name + ".npz")
     np.savez_compressed(out, poses=poses, objective=np.asarray(res.objective), status=np.int32(res.status),
                         seed=v, edge_logw=gr["edge_logw"].detach().numpy(), tau=gr["tau"].detach().numpy(),
                         prior_logw=gr["prior_logw"].detach().numpy(), K=np.int32(c["K"]), lam=np.float64(c["lam"]),
-                        graph=np.int32(b), grad_spread=np.float64(spread))
+                        graph=np.int32(b), grad_spread=np.float64(spread), order_pose=np.float64(order_pose),
+                        order_objective=np.float64(order_obj), order_grad=np.float64(order_grad))
     print(f"{name}: {time.time() - t0:.0f} s, objective {res.objective[0]:.6e} -> {res.objective[-1]:.6e}, "
-          f"gradient spread {spread:.2e}",
+          f"gradient spread {spread:.2e}; other elimination order: poses {order_pose:.2e}, "
+          f"objective {order_obj:.2e}, gradient {order_grad:.2e}",
           flush=True)
     return out
 

@@ -127,3 +127,64 @@ def oracle_grads(gs, res, seeds):
         o = S.implicit_grad_graph(g, r, torch.as_tensor(v, dtype=torch.float64))
         out.append({k: x.detach().numpy() for k, x in o.items()})
     return out
+
+
+def oracle_grad_at(g, res, poses_storage, v):
+    """The oracle's implicit gradient (log-weights, tangents, prior
+    log-weights, flattened) with the same seed v but at another theta_K, the
+    GPU's: the final linearisation and its factor are recomputed there.  With
+    it the backward is compared at a shared point, apart from the forward's
+    own difference in theta_K."""
+    import dataclasses
+    G = g.G
+    X = G.from_storage(torch.as_tensor(np.asarray(poses_storage), dtype=torch.float64))
+    lin = S.linearize_pose_graph(g, X, tau=g.tau)
+    r = dataclasses.replace(res, X=X, lin=lin, factor=(torch.linalg.cholesky(lin.H),))
+    o = S.implicit_grad_graph(g, r, torch.as_tensor(np.asarray(v), dtype=torch.float64))
+    return {k: x.detach().numpy() for k, x in o.items()}
+
+
+def stationary_equivalent(g, res, poses_storage):
+    """On a graph whose float64 iteration has converged to the rounding floor
+    of its gradient, theta_K is fixed only up to that floor: along the soft
+    modes of an ill-conditioned H many points have a gradient as small as the
+    oracle's own, and two correct float64 implementations stop at different
+    ones.  Returns (ok, gradient norm at the GPU's theta_K, at the oracle's,
+    relative objective difference); ok when the oracle's converged gradient is
+    below 1e-9 of its initial one, the GPU's theta_K has an oracle gradient
+    at most twice the oracle's own and the objectives agree to 1e-12."""
+    G = g.G
+    X = G.from_storage(torch.as_tensor(np.asarray(poses_storage), dtype=torch.float64))
+    g0 = float(S.linearize_pose_graph(g, g.X, tau=g.tau).g.norm())
+    lin = S.linearize_pose_graph(g, X, tau=g.tau)
+    n_gpu, n_ref = float(lin.g.norm()), float(res.lin.g.norm())
+    ds = abs(float(lin.S) - float(res.lin.S)) / max(float(res.lin.S), 1e-300)
+    ok = n_ref <= 1e-9 * g0 and n_gpu <= 2.0 * n_ref + 1e-15 * g0 and ds <= 1e-12
+    return ok, n_gpu, n_ref, ds
+
+
+def oracle_order_spread(g, K, lam):
+    """How far the oracle's own K-step solve moves when every step solves its
+    system in the reversed elimination order (the Cholesky factorisation of
+    P (H + lambda I) P^T, P reversing the unknowns): the same steps in exact
+    arithmetic, a different rounding of each factorisation.  Returns the
+    element-wise differences (poses with a floor of 1e-3 of the largest
+    entry, objective history per entry) from the oracle's result: on
+    ill-conditioned graphs the early steps of two correct float64 solvers
+    already differ by more than 1e-10 there."""
+    G = g.G
+    X = g.X.clone()
+    obj = []
+    for _ in range(K):
+        lin = S.linearize_pose_graph(g, X, tau=g.tau)
+        obj.append(float(lin.S))
+        n = lin.H.shape[0]
+        rev = torch.arange(n - 1, -1, -1)
+        Lr = torch.linalg.cholesky(lin.H[rev][:, rev] + lam * torch.eye(n, dtype=torch.float64))
+        d = torch.empty(n, dtype=torch.float64)
+        d[rev] = torch.cholesky_solve(lin.g[rev][:, None], Lr)[:, 0]
+        X = G.retract(X, -d.reshape(-1, G.dof))
+    obj.append(float(S.linearize_pose_graph(g, X, tau=g.tau).S))
+    ref = S.solve_graph(g, K, lam, tau=g.tau)
+    return (ew_ratio(G.to_storage(X).numpy(), G.to_storage(ref.X).numpy(), 1e-3),
+            ew_ratio(np.asarray(obj), np.asarray(ref.objective), 1e-12))
