@@ -388,6 +388,26 @@ dnls_status dnls_plan_schedule(dnls_plan plan, int32_t* dense_pair, int32_t* spa
  * DNLS_ERR_HIP if a launch fails; numerical failures go to args->status. */
 dnls_status dnls_solve(dnls_plan plan, const dnls_solve_args* args, void* stream);
 
+/* dnls_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the solve workspace taken from a
+ * 256 MiB array inside the library instead of args->workspace, which must
+ * be NULL.  Each device the library runs on holds its own copy of that
+ * array until the process ends; its address is looked up once per device,
+ * on the first call there, with that device current (the current device
+ * must be the plan's and the stream's).  The call allocates nothing itself
+ * and asks for no HIP graph.  Every call on a device shares that device's
+ * array and nothing in it needs to start at zero (the solve writes before
+ * it reads), so calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller; the other buffers
+ * (poses, factor cache, outputs) are the caller's as for dnls_solve, and
+ * dnls_backward afterwards takes its own workspace as usual.  Returns
+ * DNLS_ERR_INVALID_ARG if args->workspace is not NULL, DNLS_ERR_WORKSPACE
+ * if the plan's solve_ws exceeds 256 MiB, DNLS_ERR_UNSUPPORTED for a plan
+ * made with DNLS_FLAG_GRAPH, DNLS_ERR_HIP if the array's address cannot be
+ * obtained; otherwise as dnls_solve. */
+dnls_status dnls_solve_noalloc(dnls_plan plan, const dnls_solve_args* args, void* stream);
+
 /* Implicit backward (Section 4.3, Proposition 1 and its proof in Appendix
  * H): u = H*^-1 v with the cached factor of the undamped Gauss-Newton
  * Hessian at theta_K (Section 4.2 "Backward for custom linear solvers"),

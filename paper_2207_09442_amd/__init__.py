@@ -95,13 +95,14 @@ def lib():
         L.dnls_plan_flops.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.dnls_plan_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.dnls_solve.argtypes = [_vp, ctypes.POINTER(_SolveArgs), _vp]
+        L.dnls_solve_noalloc.argtypes = [_vp, ctypes.POINTER(_SolveArgs), _vp]
         L.dnls_backward.argtypes = [_vp, ctypes.POINTER(_BackwardArgs), _vp]
         L.dnls_project_grad.argtypes = [ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.dnls_plan_destroy.argtypes = [_vp]
         L.dnls_last_error.restype = ctypes.c_char_p
         L.dnls_version.restype = ctypes.c_char_p
         for f in ["dnls_plan_create", "dnls_plan_workspace", "dnls_plan_flops", "dnls_plan_schedule", "dnls_solve",
-                  "dnls_backward",
+                  "dnls_solve_noalloc", "dnls_backward",
                   "dnls_project_grad", "dnls_plan_destroy"]:
             getattr(L, f).restype = ctypes.c_int
         _LIB = L
@@ -279,10 +280,13 @@ class Plan:
         return huber_delta.contiguous()
 
     # ------------------------------------------------------------------
-    def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None, edge_logc=None):
+    def solve(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, edge_tau=None, edge_logc=None,
+              noalloc=False):
         """Runs K steps in place on `poses` (float64 device tensor [V, 3, 4] or
         [V, 4]); returns (objective [B, K+1], status [B]).  edge_logc: Welsch
-        log-radii of the edges [E] (robust loss), or None."""
+        log-radii of the edges [E] (robust loss), or None.  noalloc: through
+        dnls_solve_noalloc (the library's scratch in place of the plan's
+        workspace)."""
         import torch
         objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
         status = torch.empty(self.B, dtype=torch.int32, device=self.device)
@@ -293,12 +297,16 @@ class Plan:
         a.objective, a.status = _ptr(objective), _ptr(status)
         a.factor = self._aligned(self.factor)
         a.edge_logc = _ptr(edge_logc)
-        self._run_solve(a)
+        self._run_solve(a, noalloc)
         return objective, status
 
-    def _run_solve(self, a):
-        a.workspace = self._aligned(self.workspace)
-        _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
+    def _run_solve(self, a, noalloc):
+        if noalloc:
+            a.workspace = None
+            _check(lib().dnls_solve_noalloc(self._h, ctypes.byref(a), _stream()), "dnls_solve_noalloc")
+        else:
+            a.workspace = self._aligned(self.workspace)
+            _check(lib().dnls_solve(self._h, ctypes.byref(a), _stream()), "dnls_solve")
         self.solves += 1
 
     def backward(self, poses, edge_meas, edge_logw, prior_meas, prior_logw, status, seed,
@@ -345,10 +353,11 @@ class Plan:
 
 
     # ------------------------------------------------------------------
-    def solve_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, huber_delta=None):
+    def solve_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, huber_delta=None, noalloc=False):
         """Bundle adjustment (solver "schur"): K steps in place on `cams`
         [Vc, 3, 4] and `points` [Vp, 3]; returns (objective [B, K+1], status [B]).
-        huber_delta: per-problem Huber radii [B], or None for the problem's."""
+        huber_delta: per-problem Huber radii [B], or None for the problem's;
+        noalloc as for solve."""
         import torch
         objective = torch.empty(self.B, self.K + 1, dtype=torch.float64, device=self.device)
         status = torch.empty(self.B, dtype=torch.int32, device=self.device)
@@ -360,7 +369,7 @@ class Plan:
         a.factor = self._aligned(self.factor)
         hd = self._radii(huber_delta)
         a.huber_delta = _ptr(hd)
-        self._run_solve(a)
+        self._run_solve(a, noalloc)
         return objective, status
 
     def backward_ba(self, cams, points, obs_uv, obs_w, prior_meas, prior_logw, status, seed_cam,

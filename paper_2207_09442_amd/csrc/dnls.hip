@@ -1358,6 +1358,55 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   return mixed ? launch_solve<2, true>(p, a, st) : launch_solve<2, false>(p, a, st);
 }
 
+// ---------------------------------------------------------------------------
+// dnls_solve_noalloc: dnls_solve with its workspace in a file-scope device
+// array, for callers that cannot allocate (graph capture, serving loops).
+// Each device that loads the library holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_addr;   // per device ordinal, set on the first call there
+
+static dnls_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_addr.size()) g_scratch_addr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(DNLS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return DNLS_OK;
+}
+
+dnls_status dnls_solve_noalloc(dnls_plan p, const dnls_solve_args* s, void* stream) {
+  g_err.clear();
+  if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");
+  if (s->workspace)
+    return fail(DNLS_ERR_INVALID_ARG, "workspace must be NULL: dnls_solve_noalloc uses the library's scratch");
+  if (p->opt.flags & DNLS_FLAG_GRAPH)
+    return fail(DNLS_ERR_UNSUPPORTED, "dnls_solve_noalloc does not take DNLS_FLAG_GRAPH plans (instantiating "
+                                      "a HIP graph allocates)");
+  if (p->ws_bytes > kScratchBytes)
+    return fail(DNLS_ERR_WORKSPACE, "the plan's solve workspace (" + std::to_string(p->ws_bytes) +
+                                        " bytes) exceeds the scratch of dnls_solve_noalloc (" +
+                                        std::to_string(kScratchBytes) + " bytes)");
+  void* ws = nullptr;
+  const dnls_status st = scratch_address(&ws);
+  if (st != DNLS_OK) return st;
+  dnls_solve_args a = *s;
+  a.workspace = ws;
+  return dnls_solve(p, &a, stream);
+}
+
 dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream) {
   g_err.clear();
   if (!p || !s) return fail(DNLS_ERR_INVALID_ARG, "null argument");

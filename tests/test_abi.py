@@ -97,6 +97,7 @@ def test_null_arguments():
     assert L.dnls_plan_create(None, None, None) == 1
     assert L.dnls_plan_destroy(None) == 0
     assert L.dnls_solve(None, None, None) == 1
+    assert L.dnls_solve_noalloc(None, None, None) == 1
     assert L.dnls_backward(None, None, None) == 1
     assert L.dnls_project_grad(7, 1, None, None, None, None) == 1
     assert L.dnls_project_grad(3, 0, None, None, None, None) == 0
