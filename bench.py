@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--refine-last", type=int, default=0,
                     help="mixed path: refinement sweeps in the last N steps only (N < 0: the first -N "
                          "steps; 0 = every step, the default, the one that holds 1e-5 on the gradients)")
+    ap.add_argument("--sparse-solve", choices=["auto", "block", "persistent", "workgroup", "hybrid", "sweeps"],
+                    default="auto", help="schedule of the block-sparse solver")
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
                     help="override the workload's solver (pose graphs only)")
     ap.add_argument("--adaptive", action="store_true",
@@ -242,7 +244,7 @@ def main():
     else:
         aux = (t(p["edge_meas"]), t(p["edge_logw"]), t(p["prior_meas"]), t(p["prior_logw"]))
 
-    schedule = dict(sparse_solve="auto", graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg,
+    schedule = dict(sparse_solve=args.sparse_solve, graph=False, adaptive=bool(args.adaptive), dogleg=args.dogleg,
                     keep_iterates=args.backward == "unroll", pair=not args.no_pair)
     if args.autotune and not ba:
         from paper_2207_09442_amd.autotune import autotune

@@ -129,13 +129,21 @@ typedef struct {
  * (padded) unknowns and 16 tile columns PERSISTENT with a fixed-damping
  * optimizer, else WORKGROUP; HYBRID for at most 6144 unknowns, else SWEEPS.  WORKGROUP, HYBRID and PERSISTENT
  * on a plan whose graphs exceed 6144 unknowns, and PERSISTENT with adaptive
- * damping or the dogleg, are DNLS_ERR_UNSUPPORTED. */
+ * damping or the dogleg, are DNLS_ERR_UNSUPPORTED.
+ * BLOCK: the factor in d x d pose blocks (the block-sparse structure of the
+ * Gauss-Newton matrix itself, no 48-wide tiles), factored left-looking by
+ * levels of the elimination tree (every column of a level at once) with
+ * the triangular solves by the same levels, one workgroup per graph, and
+ * the whole solve in one persistent launch as PERSISTENT; same limits as
+ * PERSISTENT (at most 6144 unknowns per graph, fixed damping).  Not chosen
+ * by AUTO. */
 typedef enum {
   DNLS_SPSOLVE_AUTO = 0,
   DNLS_SPSOLVE_WORKGROUP = 1,
   DNLS_SPSOLVE_SWEEPS = 2,
   DNLS_SPSOLVE_HYBRID = 3,
-  DNLS_SPSOLVE_PERSISTENT = 4
+  DNLS_SPSOLVE_PERSISTENT = 4,
+  DNLS_SPSOLVE_BLOCK = 5
 } dnls_sparse_solve;
 
 /* dnls_options.flags */

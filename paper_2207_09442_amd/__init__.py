@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdnls.so"
 
 SOLVERS = {"dense": 0, "schur": 1, "sparse": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3, "persistent": 4}
+SPARSE_SOLVES = {"auto": 0, "workgroup": 1, "sweeps": 2, "hybrid": 3, "persistent": 4, "block": 5}
 BACKWARD_MODES = {"implicit": 0, "dlm": 1, "exact": 2, "unroll": 3}
 FLAG_GRAPH = 1
 FLAG_ADAPTIVE_LM = 2

@@ -26,6 +26,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dnls_autotune.j
 CANDIDATES = [
     dict(solver="dense", sparse_solve="auto", graph=False),
     dict(solver="dense", sparse_solve="auto", graph=False, pair=True),
+    dict(solver="sparse", sparse_solve="block", graph=False),
     dict(solver="sparse", sparse_solve="persistent", graph=False),
     dict(solver="sparse", sparse_solve="workgroup", graph=False),
     dict(solver="sparse", sparse_solve="workgroup", graph=True),

@@ -1039,7 +1039,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->refine < 0 || op->refine > 4) return fail(DNLS_ERR_INVALID_ARG, "refine must be in 0..4");
   if (op->refine_last < -op->iterations || op->refine_last > op->iterations)
     return fail(DNLS_ERR_INVALID_ARG, "refine_last must be in 0..iterations");
-  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_PERSISTENT)
+  if (op->sparse_solve < DNLS_SPSOLVE_AUTO || op->sparse_solve > DNLS_SPSOLVE_BLOCK)
     return fail(DNLS_ERR_INVALID_ARG, "unknown sparse_solve");
   if (op->flags & ~int32_t(DNLS_FLAG_GRAPH | DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES |
                            DNLS_FLAG_PAIR))
@@ -1236,7 +1236,8 @@ dnls_status dnls_plan_schedule(dnls_plan p, int32_t* dense_pair, int32_t* sparse
   if (sparse_solve) {
     *sparse_solve = DNLS_SPSOLVE_AUTO;
     if (p->opt.solver == DNLS_SOLVER_SPARSE)
-      *sparse_solve = p->sp_persistent ? DNLS_SPSOLVE_PERSISTENT
+      *sparse_solve = p->sp_ts != 48 ? DNLS_SPSOLVE_BLOCK
+                      : p->sp_persistent ? DNLS_SPSOLVE_PERSISTENT
                       : p->sp_factor_wg ? DNLS_SPSOLVE_WORKGROUP
                       : (p->sp_solve_wg ? DNLS_SPSOLVE_HYBRID : DNLS_SPSOLVE_SWEEPS);
   }

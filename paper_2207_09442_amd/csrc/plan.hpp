@@ -69,6 +69,7 @@ struct SpDesc {
   long long vec_off;   // doubles: 4 vectors of nvec in the workspace
   long long pool_off;  // doubles: tile pool
   long long winv_off;  // doubles: inverses of the diagonal tiles
+  int lvl_off, nlvl;   // BLOCK schedule: elimination-tree levels ([lvl_off, lvl_off + nlvl] pointers)
 };
 
 }  // namespace dnls
@@ -131,6 +132,11 @@ struct dnls_plan_s {
   int sp_maxP = 0;
   bool sp_solve_wg = false;       // triangular solves: one workgroup per graph (vector in LDS)
   bool sp_persistent = false;     // the whole solve in one persistent launch (graph work queue)
+  int sp_ts = 48;                 // tile size of the factor: 48 (MFMA tiles) or d (pose blocks, BLOCK)
+  int* d_lvlptr = nullptr;        // BLOCK: columns of each level ([lvl_off + L] .. [+1] into d_lvlcol)
+  int* d_lvlcol = nullptr;
+  int* d_lvlbptr = nullptr;       // BLOCK: factor blocks of each level's columns (into d_lvlblk)
+  int2* d_lvlblk = nullptr;       //   (tile row I, tile column J), diagonal blocks included
   int sp_grid = 0;                // its workgroups: min(B, resident slots)
   int* d_sp_order = nullptr;      // its queue order: graphs by decreasing factor work
   unsigned* d_sp_queue = nullptr; // its two queue counters (self-resetting)

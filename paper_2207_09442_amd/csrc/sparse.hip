@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <map>
 #include <string>
 #include <utility>
@@ -83,6 +84,11 @@ struct SpArgs {
   int* rej;                // adaptive damping / dogleg: the graph's trial step was rejected
   double* dl;              // dogleg per graph: radius, predicted decrease, |delta|, on the boundary
   double* traj;            // persistent schedule with DNLS_FLAG_KEEP_ITERATES: theta_t, [K][V][sz]
+  const int* lvlptr;       // BLOCK: columns of each elimination-tree level, [lvl_off + L] .. [+1] into lvlcol
+  const int* lvlcol;
+  const int* lvlbptr;      // BLOCK: factor blocks (I, J) of each level's columns, into lvlblk
+  const int2* lvlblk;
+  int ts;                  // tile size: kTS (48) or the pose dimension d (BLOCK)
   int E, V, K, it, nx, refine;
   double lambda, radius0;
 };
@@ -94,7 +100,7 @@ __device__ __forceinline__ PoseCostData cost_data(const SpArgs& a) {
 
 __device__ __forceinline__ double* tile_ptr(const SpArgs& a, const SpDesc& g, int I, int J) {
   const int id = a.tix[g.tix_off + I * g.P + J];
-  return a.factor + g.pool_off + (size_t)id * kTT;
+  return a.factor + g.pool_off + (size_t)id * (a.ts * a.ts);
 }
 
 __device__ double block_sum_sp(double v, double* red) {
@@ -151,15 +157,15 @@ __global__ void __launch_bounds__(kBT) k_sp_zero(SpArgs a) {
   const int b = blockIdx.y;
   const SpDesc g = a.sd[b];
   if (a.failed[b]) return;
-  d4v* pool = reinterpret_cast<d4v*>(a.factor + g.pool_off);
-  const size_t n4 = (size_t)g.ntile * (kTT / 4);
-  for (size_t u = (size_t)blockIdx.x * kBT + threadIdx.x; u < n4; u += (size_t)gridDim.x * kBT)
-    pool[u] = d4v{0.0, 0.0, 0.0, 0.0};
+  double* pool = a.factor + g.pool_off;
+  const size_t n = (size_t)g.ntile * (a.ts * a.ts);
+  for (size_t u = (size_t)blockIdx.x * kBT + threadIdx.x; u < n; u += (size_t)gridDim.x * kBT) pool[u] = 0.0;
 }
 
 __device__ __forceinline__ void put(const SpArgs& a, const SpDesc& g, int row, int col, double v) {
-  double* t = tile_ptr(a, g, row / kTS, col / kTS);
-  t[(row % kTS) * kTS + col % kTS] = v;
+  const int ts = a.ts;
+  double* t = tile_ptr(a, g, row / ts, col / ts);
+  t[(row % ts) * ts + col % ts] = v;
 }
 
 // Hessian blocks into the tiles (permuted, lower triangle), g into vec[1].
@@ -241,7 +247,7 @@ __device__ __forceinline__ void sp_assemble_item(const SpArgs& a, const SpDesc& 
 // padding of the last tile (unit diagonal) and of the right-hand side
 // (zero), threads t = t0, t0 + stride, ...
 __device__ __forceinline__ void sp_assemble_pad(const SpArgs& a, const SpDesc& g, int t0, int stride) {
-  for (int r = g.n + t0; r < g.P * kTS; r += stride) put(a, g, r, r, 1.0);
+  for (int r = g.n + t0; r < g.P * a.ts; r += stride) put(a, g, r, r, 1.0);
   double* rhs = a.vec + g.vec_off + g.nvec;
   for (int r = g.n + t0; r < g.nvec; r += stride) rhs[r] = 0.0;
 }
@@ -1260,6 +1266,225 @@ __global__ void __launch_bounds__(kBT) k_sp_vjp(SpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// BLOCK schedule: the factor in d x d pose blocks (tile size d), factored
+// left-looking by levels of the elimination tree.  A column's level is one
+// more than the highest level of the columns it depends on (its children in
+// the tree), so all columns of a level are computed at once from lower
+// levels only:
+//   A. L_IJ = A_IJ - sum_{K < J} L_IK L_JK^T for every block (I, J) of the
+//      level's columns (K runs over row J's structure; the diagonal block's
+//      lower triangle only);
+//   B. L_JJ = chol(L_JJ) and W_J = L_JJ^-1, one thread per column;
+//   C. L_IJ <- L_IJ W_J^T below the diagonal, one thread per block row.
+// The triangular solves run by the same levels (forward: ascending,
+// backward: descending), the vector in LDS.  d <= 6.
+// ---------------------------------------------------------------------------
+template <int NT, int D>
+__device__ bool sb_factor_body(const SpArgs& a, int b, const SpDesc& g, int* flag) {
+  constexpr int ts = D, tt = D * D;
+  for (int L = 0; L < g.nlvl; ++L) {
+    // A. left-looking gather of the level's blocks
+    const int b0 = a.lvlbptr[g.lvl_off + L], b1 = a.lvlbptr[g.lvl_off + L + 1];
+    for (int u = threadIdx.x; u < (b1 - b0) * tt; u += NT) {
+      const int2 ij = a.lvlblk[b0 + u / tt];
+      const int e = u % tt, r = e / ts, c = e % ts;
+      const int I = ij.x, J = ij.y;
+      if (I == J && c > r) continue;
+      double* T = tile_ptr(a, g, I, J);
+      double acc = T[e];
+      const int k0 = a.rowptr[g.row_off + J], k1 = a.rowptr[g.row_off + J + 1];
+      for (int k = k0; k < k1; ++k) {
+        const int K = a.rowcol[k];
+        const int id = a.tix[g.tix_off + I * g.P + K];
+        if (id < 0) continue;
+        const double* LI = a.factor + g.pool_off + (size_t)id * tt + r * ts;
+        const double* LJ = tile_ptr(a, g, J, K) + c * ts;
+#pragma unroll
+        for (int q = 0; q < ts; ++q) acc -= LI[q] * LJ[q];
+      }
+      T[e] = acc;
+    }
+    __syncthreads();
+    // B. diagonal blocks: Cholesky and inverse, one thread per column
+    const int c0 = a.lvlptr[g.lvl_off + L], c1 = a.lvlptr[g.lvl_off + L + 1];
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int u = c0 + (int)threadIdx.x; u < c1; u += NT) {
+      const int J = a.lvlcol[u];
+      double* T = tile_ptr(a, g, J, J);
+      double l[D][D], w[D][D];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < ts; ++i)
+#pragma unroll
+        for (int j = 0; j < ts; ++j) l[i][j] = (j <= i) ? T[i * ts + j] : 0.0;
+#pragma unroll
+      for (int j = 0; j < ts; ++j) {
+        double dj = l[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dj -= l[j][k] * l[j][k];
+        ok = ok && dj > 0.0;
+        const double ljj = ::sqrt(dj > 0.0 ? dj : 1.0);
+        l[j][j] = ljj;
+        const double inv = 1.0 / ljj;
+#pragma unroll
+        for (int i = j + 1; i < ts; ++i) {
+          double v = l[i][j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= l[i][k] * l[j][k];
+          l[i][j] = v * inv;
+        }
+      }
+      // W = L^-1 (lower), column by column of the identity
+#pragma unroll
+      for (int j = 0; j < ts; ++j)
+#pragma unroll
+        for (int i = 0; i < ts; ++i) {
+          if (i < j) {
+            w[i][j] = 0.0;
+            continue;
+          }
+          double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+          for (int k = j; k < i; ++k) v -= l[i][k] * w[k][j];
+          w[i][j] = v / l[i][i];
+        }
+      double* W = a.factor + g.winv_off + (size_t)J * tt;
+#pragma unroll
+      for (int i = 0; i < ts; ++i)
+#pragma unroll
+        for (int j = 0; j < ts; ++j) {
+          T[i * ts + j] = (j <= i) ? l[i][j] : 0.0;
+          W[i * ts + j] = w[i][j];
+        }
+      if (!ok) *flag = 1;
+    }
+    __syncthreads();
+    if (*flag) {
+      if (threadIdx.x == 0) {
+        a.failed[b] = DNLS_GRAPH_NOT_PD;
+        a.status[b] = DNLS_GRAPH_NOT_PD;
+      }
+      return false;
+    }
+    // C. L_IJ <- L_IJ W_J^T below the diagonal, one thread per block row
+    for (int u = threadIdx.x; u < (b1 - b0) * ts; u += NT) {
+      const int2 ij = a.lvlblk[b0 + u / ts];
+      if (ij.x == ij.y) continue;
+      const int r = u % ts;
+      double* row = tile_ptr(a, g, ij.x, ij.y) + r * ts;
+      const double* W = a.factor + g.winv_off + (size_t)ij.y * tt;
+      double x[D], y[D];
+#pragma unroll
+      for (int q = 0; q < ts; ++q) x[q] = row[q];
+#pragma unroll
+      for (int c = 0; c < ts; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q <= c; ++q) v += x[q] * W[c * ts + q];
+        y[c] = v;
+      }
+#pragma unroll
+      for (int c = 0; c < ts; ++c) row[c] = y[c];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// x (slot dst) = (L L^T)^-1 b (slot src), v: nvec doubles of LDS
+template <int NT, int D>
+__device__ void sb_solve_body(const SpArgs& a, const SpDesc& g, int src, int dst, double* v) {
+  constexpr int ts = D, tt = D * D;
+  const double* bsrc = slot(a, g, src);
+  for (int u = threadIdx.x; u < g.nvec; u += NT) v[u] = bsrc[u];
+  __syncthreads();
+  // forward: v_J <- W_J (v_J - sum_{K < J} L_JK v_K), levels ascending
+  for (int L = 0; L < g.nlvl; ++L) {
+    const int c0 = a.lvlptr[g.lvl_off + L], c1 = a.lvlptr[g.lvl_off + L + 1];
+    for (int u = threadIdx.x; u < (c1 - c0) * ts; u += NT) {
+      const int J = a.lvlcol[c0 + u / ts], r = u % ts;
+      double acc = v[J * ts + r];
+      for (int k = a.rowptr[g.row_off + J]; k < a.rowptr[g.row_off + J + 1]; ++k) {
+        const int K = a.rowcol[k];
+        const double* row = tile_ptr(a, g, J, K) + r * ts;
+#pragma unroll
+        for (int q = 0; q < ts; ++q) acc -= row[q] * v[K * ts + q];
+      }
+      v[J * ts + r] = acc;
+    }
+    __syncthreads();
+    for (int u = c0 + (int)threadIdx.x; u < c1; u += NT) {
+      const int J = a.lvlcol[u];
+      const double* W = a.factor + g.winv_off + (size_t)J * tt;
+      double x[D];
+#pragma unroll
+      for (int q = 0; q < ts; ++q) x[q] = v[J * ts + q];
+#pragma unroll
+      for (int r = 0; r < ts; ++r) {
+        double y = 0.0;
+#pragma unroll
+        for (int q = 0; q <= r; ++q) y += W[r * ts + q] * x[q];
+        v[J * ts + r] = y;
+      }
+    }
+    __syncthreads();
+  }
+  // backward: v_J <- W_J^T (v_J - sum_{I > J} L_IJ^T v_I), levels descending
+  for (int L = g.nlvl - 1; L >= 0; --L) {
+    const int c0 = a.lvlptr[g.lvl_off + L], c1 = a.lvlptr[g.lvl_off + L + 1];
+    for (int u = threadIdx.x; u < (c1 - c0) * ts; u += NT) {
+      const int J = a.lvlcol[c0 + u / ts], r = u % ts;
+      double acc = v[J * ts + r];
+      for (int k = a.colptr[g.col_off + J] + 1; k < a.colptr[g.col_off + J + 1]; ++k) {
+        const int I = a.rowidx[k];
+        const double* T = tile_ptr(a, g, I, J);
+#pragma unroll
+        for (int q = 0; q < ts; ++q) acc -= T[q * ts + r] * v[I * ts + q];
+      }
+      v[J * ts + r] = acc;
+    }
+    __syncthreads();
+    for (int u = c0 + (int)threadIdx.x; u < c1; u += NT) {
+      const int J = a.lvlcol[u];
+      const double* W = a.factor + g.winv_off + (size_t)J * tt;
+      double x[D];
+#pragma unroll
+      for (int q = 0; q < ts; ++q) x[q] = v[J * ts + q];
+#pragma unroll
+      for (int r = 0; r < ts; ++r) {
+        double y = 0.0;
+#pragma unroll
+        for (int q = r; q < ts; ++q) y += W[q * ts + r] * x[q];
+        v[J * ts + r] = y;
+      }
+    }
+    __syncthreads();
+  }
+  double* xdst = slot(a, g, dst);
+  for (int u = threadIdx.x; u < g.nvec; u += NT) xdst[u] = v[u];
+  __syncthreads();
+}
+
+template <int D>
+__global__ void __launch_bounds__(kPT) k_sb_factor(SpArgs a) {
+  __shared__ int flag;
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  sb_factor_body<kPT, D>(a, b, g, &flag);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kPT) k_sb_solve(SpArgs a, int src, int dst) {
+  __shared__ double v[kSolveLds];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  sb_solve_body<kPT, D>(a, g, src, dst, v);
+}
+
+// ---------------------------------------------------------------------------
 // Persistent whole-solve kernel (schedule PERSISTENT): one launch runs every
 // step of every graph.  A grid of at most one workgroup per resident slot
 // takes graphs from a device-memory queue (largest first, the plan's launch
@@ -1280,12 +1505,17 @@ union FusedLds {
     double y[kTS];
   } s;
 };
+struct BlockLds {          // BLOCK: only the solve's vector
+  struct {
+    double v[kSolveLds];
+  } s;
+};
 
-template <int G, bool MIXED>
+template <int G, bool MIXED, bool BLOCK>
 __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* order, unsigned* queue, int B,
                                                        int refine_from, int refine_until) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n, sz = GroupTraits<G>::sz;
-  __shared__ FusedLds L;
+  __shared__ std::conditional_t<BLOCK, BlockLds, FusedLds> L;
   __shared__ double red[kPT / 64];
   __shared__ int q_slot, stop;
   const PoseCostData cd = cost_data(a);
@@ -1335,9 +1565,9 @@ __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* orde
       }
       // 2. zero the tile pool, then assemble H (+ lambda I) and g
       {
-        d4v* pool = reinterpret_cast<d4v*>(a.factor + g.pool_off);
-        const size_t n4 = (size_t)g.ntile * (kTT / 4);
-        for (size_t u = threadIdx.x; u < n4; u += kPT) pool[u] = d4v{0.0, 0.0, 0.0, 0.0};
+        double* pool = a.factor + g.pool_off;
+        const size_t n = (size_t)g.ntile * (a.ts * a.ts);
+        for (size_t u = threadIdx.x; u < n; u += kPT) pool[u] = 0.0;
       }
       __syncthreads();
       const int nblk = g.npose + g.nod;
@@ -1352,7 +1582,11 @@ __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* orde
       sp_assemble_pad(a, g, threadIdx.x, kPT);
       __syncthreads();
       // 3. factorisation
-      if (!sp_factor_wg_body<kPT>(a, b, g, L.f)) break;
+      if constexpr (BLOCK) {
+        if (!sb_factor_body<kPT, d>(a, b, g, &stop)) break;
+      } else {
+        if (!sp_factor_wg_body<kPT>(a, b, g, reinterpret_cast<FusedLds&>(L).f)) break;
+      }
       if (final_lin) break;
       // 4. step: slot 2 = g, slot 0 = (L L^T)^-1 g
       {
@@ -1361,7 +1595,9 @@ __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* orde
         for (int u = threadIdx.x; u < g.nvec; u += kPT) x[u] = rhs[u];
       }
       __syncthreads();
-      sp_solve_wg_body<kPT>(a, g, 2, 0, L.s.v, L.s.Wl, L.s.y);
+      if constexpr (BLOCK) sb_solve_body<kPT, d>(a, g, 2, 0, L.s.v);
+      else sp_solve_wg_body<kPT>(a, g, 2, 0, L.s.v, reinterpret_cast<FusedLds&>(L).s.Wl,
+                                 reinterpret_cast<FusedLds&>(L).s.y);
       __syncthreads();
       if (!refine_now) {
         for (int p = threadIdx.x; p < g.npose; p += kPT) sp_retract_item<G>(a, g, p, 0);
@@ -1376,7 +1612,9 @@ __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* orde
           }
           for (int p = threadIdx.x; p < g.npose; p += kPT) sp_residual_item<G>(a, g, p, lam);
           __syncthreads();
-          sp_solve_wg_body<kPT>(a, g, 2, 2, L.s.v, L.s.Wl, L.s.y);
+          if constexpr (BLOCK) sb_solve_body<kPT, d>(a, g, 2, 2, L.s.v);
+          else sp_solve_wg_body<kPT>(a, g, 2, 2, L.s.v, reinterpret_cast<FusedLds&>(L).s.Wl,
+                                     reinterpret_cast<FusedLds&>(L).s.y);
           __syncthreads();
           for (int p = threadIdx.x; p < g.npose; p += kPT) sp_accumulate_item<G>(a, g, p, sw + 1 == a.refine);
           __syncthreads();
@@ -1523,6 +1761,10 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sd.resize(B);
   long long fac = 0, vecoff = 0;
   int maxP = 0;
+  // tile size: 48 (three 16-wide MFMA tiles) or, for BLOCK, the pose blocks themselves
+  const int tsz = p->opt.sparse_solve == DNLS_SPSOLVE_BLOCK ? d : kTS;
+  const long long tt = (long long)tsz * tsz;
+  p->sp_ts = tsz;
   for (int b = 0; b < B; ++b) {
     SpDesc& g = p->sd[b];
     g.pose0 = pr->pose_off[b];
@@ -1563,9 +1805,9 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     for (int v = 0; v < g.npose; ++v) pos[g.pose0 + v] = lpos[v];
     std::vector<std::pair<int, int>> bl;
     for (auto& kv : blocks) bl.push_back(kv.first);
-    const sym::TileStructure ts = sym::tile_symbolic(g.npose, d, kTS, lpos, bl);
+    const sym::TileStructure ts = sym::tile_symbolic(g.npose, d, tsz, lpos, bl);
     p->flops_alg += sym::block_flops(sym::block_column_counts(g.npose, adj, lpos), d);
-    p->flops_exec += sym::tile_flops(ts, kTS);
+    p->flops_exec += sym::tile_flops(ts, tsz);
     g.P = ts.P;
     maxP = std::max(maxP, g.P);
     g.ntile = (int)ts.row_idx.size();
@@ -1593,11 +1835,13 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
       rowptr.push_back((int)rowcol.size());
     }
     g.pool_off = fac;
-    fac += (long long)g.ntile * kTT;
+    fac += (long long)g.ntile * tt;
     g.winv_off = fac;
-    fac += (long long)g.P * kTT;
+    fac += (long long)g.P * tt;
     fac = (fac + 31) / 32 * 32;
-    g.nvec = g.P * kTS;
+    g.nvec = g.P * tsz;
+    g.lvl_off = 0;
+    g.nlvl = 0;
     g.vec_off = vecoff;
     vecoff += 4LL * g.nvec;
     g.od0 = (int)od_blk.size();
@@ -1611,6 +1855,40 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   for (int v = 0; v < p->V; ++v) {
     inc_off[v + 1] = inc_off[v] + (int)inc[v].size();
     for (int s : inc[v]) inc_slot.push_back(s);
+  }
+  // BLOCK: elimination-tree levels of every graph (a column's parent is its
+  // first off-diagonal row; level = 1 + the highest level of its children)
+  std::vector<int> lvlptr, lvlcol, lvlbptr;
+  std::vector<int2> lvlblk;
+  if (tsz != kTS) {
+    for (int b = 0; b < B; ++b) {
+      SpDesc& g = p->sd[b];
+      std::vector<int> lev(g.P, 0);
+      int nl = 0;
+      for (int J = 0; J < g.P; ++J) {
+        const int k0 = colptr[g.col_off + J], k1 = colptr[g.col_off + J + 1];
+        if (k1 - k0 > 1) {
+          const int par = rowidx[k0 + 1];
+          lev[par] = std::max(lev[par], lev[J] + 1);
+        }
+        nl = std::max(nl, lev[J] + 1);
+      }
+      g.lvl_off = (int)lvlptr.size();
+      g.nlvl = nl;
+      std::vector<std::vector<int>> cols(nl);
+      for (int J = 0; J < g.P; ++J) cols[lev[J]].push_back(J);
+      for (int L = 0; L < nl; ++L) {
+        lvlptr.push_back((int)lvlcol.size());
+        lvlbptr.push_back((int)lvlblk.size());
+        for (int J : cols[L]) {
+          lvlcol.push_back(J);
+          for (int k = colptr[g.col_off + J]; k < colptr[g.col_off + J + 1]; ++k)
+            lvlblk.push_back(int2{rowidx[k], J});
+        }
+      }
+      lvlptr.push_back((int)lvlcol.size());
+      lvlbptr.push_back((int)lvlblk.size());
+    }
   }
   // per tile column: the widest column and pair count over the batch
   p->sp_ntrsm.assign(maxP, 0);
@@ -1629,18 +1907,19 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   const bool fits = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
   const int mode = p->opt.sparse_solve;
   const bool fixed_damping = !(p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG));
-  if ((mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID || mode == DNLS_SPSOLVE_PERSISTENT) && !fits)
+  const bool persistent_mode = mode == DNLS_SPSOLVE_PERSISTENT || mode == DNLS_SPSOLVE_BLOCK;
+  if ((mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID || persistent_mode) && !fits)
     return fail(DNLS_ERR_UNSUPPORTED, "the workgroup solve holds at most " + std::to_string(kSolveLds) +
                                           " unknowns per graph");
-  if (mode == DNLS_SPSOLVE_PERSISTENT && !fixed_damping)
-    return fail(DNLS_ERR_UNSUPPORTED, "the persistent schedule runs fixed-damping steps only");
+  if (persistent_mode && !fixed_damping)
+    return fail(DNLS_ERR_UNSUPPORTED, "the persistent schedules run fixed-damping steps only");
   // AUTO: for graphs of a few tile columns everything in one workgroup per
   // graph (the whole solve in one persistent launch with fixed damping); the
   // per-column launches spread larger graphs over the chip (one workgroup's
   // factorisation of a 32-column graph takes longer than the batch's
   // per-column launches)
   const bool small = fits && maxP <= kFactorWgMaxP;
-  p->sp_persistent = mode == DNLS_SPSOLVE_PERSISTENT || (mode == DNLS_SPSOLVE_AUTO && small && fixed_damping);
+  p->sp_persistent = persistent_mode || (mode == DNLS_SPSOLVE_AUTO && small && fixed_damping);
   p->sp_solve_wg = mode == DNLS_SPSOLVE_WORKGROUP || mode == DNLS_SPSOLVE_HYBRID || p->sp_persistent ||
                    (mode == DNLS_SPSOLVE_AUTO && fits);
   p->sp_factor_wg = mode == DNLS_SPSOLVE_WORKGROUP || p->sp_persistent || (mode == DNLS_SPSOLVE_AUTO && small);
@@ -1663,7 +1942,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_sp_persistent<3, true>), kPT, 0));
+        &per_cu, tsz != kTS ? reinterpret_cast<const void*>(&k_sp_persistent<3, true, true>)
+                            : reinterpret_cast<const void*>(&k_sp_persistent<3, true, false>), kPT, 0));
     p->sp_grid = std::max(1, std::min(B, std::max(1, per_cu) * std::max(1, cus)));
     dnls_status ust = upload(p, &p->d_sp_order, order);
     if (ust != DNLS_OK) return ust;
@@ -1679,6 +1959,10 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
       (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
       (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK || (st = upload(p, &p->d_rowptr, rowptr)) != DNLS_OK ||
       (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK)
+    return st;
+  if (tsz != kTS &&
+      ((st = upload(p, &p->d_lvlptr, lvlptr)) != DNLS_OK || (st = upload(p, &p->d_lvlcol, lvlcol)) != DNLS_OK ||
+       (st = upload(p, &p->d_lvlbptr, lvlbptr)) != DNLS_OK || (st = upload(p, &p->d_lvlblk, lvlblk)) != DNLS_OK))
     return st;
   const size_t ncost = (size_t)p->E + p->P;
   const size_t rn = 2 * (size_t)d * d + d;
@@ -1745,6 +2029,11 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
     a.rej = reinterpret_cast<int*>(w + p->sp_off[11]);
   }
   a.factor = static_cast<double*>(factor);
+  a.ts = p->sp_ts;
+  a.lvlptr = p->d_lvlptr;
+  a.lvlcol = p->d_lvlcol;
+  a.lvlbptr = p->d_lvlbptr;
+  a.lvlblk = p->d_lvlblk;
   a.E = p->E;
   a.K = p->opt.iterations;
   a.nx = p->nlin_blocks;
@@ -1756,6 +2045,11 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
 template <int G>
 static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
   const int B = p->B;
+  if (p->sp_ts != kTS) {
+    if (p->d == 6) hipLaunchKernelGGL(k_sb_factor<6>, dim3(B), dim3(kPT), 0, st, a);
+    else hipLaunchKernelGGL(k_sb_factor<3>, dim3(B), dim3(kPT), 0, st, a);
+    return;
+  }
   if (p->sp_factor_wg) {
     hipLaunchKernelGGL(k_sp_factor_wg, dim3(B), dim3(kWG), 0, st, a);
     return;
@@ -1772,6 +2066,11 @@ static void sp_factor(dnls_plan p, const SpArgs& a, hipStream_t st) {
 // x (slot dst) = (L L^T)^-1 b (slot 2, destroyed); slot 3 holds the forward result
 static void sp_sweeps(dnls_plan p, const SpArgs& a, int dst, hipStream_t st) {
   const int B = p->B;
+  if (p->sp_ts != kTS) {
+    if (p->d == 6) hipLaunchKernelGGL(k_sb_solve<6>, dim3(B), dim3(kPT), 0, st, a, 2, dst);
+    else hipLaunchKernelGGL(k_sb_solve<3>, dim3(B), dim3(kPT), 0, st, a, 2, dst);
+    return;
+  }
   if (p->sp_solve_wg) {
     hipLaunchKernelGGL(k_sp_solve_wg, dim3(B), dim3(kWG), 0, st, a, 2, dst);
     return;
@@ -1813,11 +2112,18 @@ static dnls_status sp_solve_impl(dnls_plan p, const dnls_solve_args* s, hipStrea
   if (p->sp_persistent) {
     a.traj = keep ? a.factor + p->traj_off : nullptr;
     a.V = p->V;
-    if (mixed)
-      hipLaunchKernelGGL((k_sp_persistent<G, true>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+    const bool blk = p->sp_ts != kTS;
+    if (mixed && blk)
+      hipLaunchKernelGGL((k_sp_persistent<G, true, true>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+                         p->d_sp_queue, B, refine_from, refine_until);
+    else if (mixed)
+      hipLaunchKernelGGL((k_sp_persistent<G, true, false>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+                         p->d_sp_queue, B, refine_from, refine_until);
+    else if (blk)
+      hipLaunchKernelGGL((k_sp_persistent<G, false, true>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
                          p->d_sp_queue, B, refine_from, refine_until);
     else
-      hipLaunchKernelGGL((k_sp_persistent<G, false>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
+      hipLaunchKernelGGL((k_sp_persistent<G, false, false>), dim3(p->sp_grid), dim3(kPT), 0, st, a, p->d_sp_order,
                          p->d_sp_queue, B, refine_from, refine_until);
     HIP_TRY(hipGetLastError());
     return DNLS_OK;

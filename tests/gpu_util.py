@@ -81,10 +81,10 @@ def oracle_grad_spread(g, res, v, pose_rel, seed=0):
 
 
 def gpu_solve(p, K, lam, precision="fp64", refine=0, tau=None, solver="dense", adaptive=False, dogleg=None,
-              refine_last=0, pair=False):
+              refine_last=0, pair=False, sparse_solve="auto"):
     from paper_2207_09442_amd import Plan
     plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=DEV, adaptive=adaptive,
-                dogleg=dogleg, refine_last=refine_last, pair=pair)
+                dogleg=dogleg, refine_last=refine_last, pair=pair, sparse_solve=sparse_solve)
     poses = t(p["poses_init"])
     dev = dict(edge_meas=t(p["edge_meas"]), edge_logw=t(p["edge_logw"]), prior_meas=t(p["prior_meas"]),
                prior_logw=t(p["prior_logw"]), edge_tau=None if tau is None else t(tau))

@@ -82,7 +82,7 @@ def test_invalid_problems_are_rejected_with_a_message():
     assert _create(P, p, lam=-1.0)[0] == 1
     assert _create(P, p, refine=9)[0] == 1
     assert _create(P, p, precision=5)[0] == 1
-    assert _create(P, p, sparse_solve=5)[0] == 1
+    assert _create(P, p, sparse_solve=6)[0] == 1
     assert _create(P, p, flags=32)[0] == 1
     assert _create(P, p, flags=8, solver=1)[0] == 2       # kept iterates: pose-graph solvers only
     assert _create(P, p, flags=10)[0] == 2                # kept iterates with adaptive damping

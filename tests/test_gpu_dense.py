@@ -43,7 +43,7 @@ def _seeds(p, poses_ref_by_graph, graphs):
 
 def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_pose=1e-10, tol_grad=1e-10,
              gate_grad=True, solver="dense", adaptive=False, dogleg=None, refine_last=0, pair=False,
-             pose_norm=False):
+             pose_norm=False, sparse_solve="auto"):
     """Element-wise comparison with the oracle on `graphs` (all by default):
     status; poses (storage entries, floor 1e-3 of the graph's largest);
     objective history (relative per entry); gradients per field (edge
@@ -61,7 +61,8 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
     0.5 cond(H*) eps64 (the reading for the 256-pose walks), the scaled ratio
     entering `worst_obj`."""
     plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver,
-                                                    adaptive=adaptive, dogleg=dogleg, refine_last=refine_last, pair=pair)
+                                                    adaptive=adaptive, dogleg=dogleg, refine_last=refine_last, pair=pair,
+                                                    sparse_solve=sparse_solve)
     B = len(p["pose_off"]) - 1
     graphs = list(range(B)) if graphs is None else graphs
     gs, res = oracle_solve(p, K, lam, tau=tau, graphs=graphs, adaptive=adaptive, dogleg=dogleg)

@@ -73,7 +73,8 @@ def test_ba_graph_replays_match_eager(opt):
 
 
 def test_forced_sparse_schedules_agree():
-    """PERSISTENT (the whole solve in one launch with a graph queue),
+    """BLOCK (pose-block factor by elimination-tree levels, one launch),
+    PERSISTENT (the whole solve in one launch with a graph queue),
     WORKGROUP (factor and solves in one workgroup per graph), HYBRID
     (per-column factor launches, workgroup solves) and SWEEPS on the same
     problem: the same tile arithmetic in different orders, so the results
@@ -82,7 +83,7 @@ def test_forced_sparse_schedules_agree():
     p = synth.uneven_walk_se3(batch=5, n_min=20, n_max=90, seed=22)
     poses0 = t(p["poses_init"])
     runs = [_pose_graph_run(p, Plan(p, 6, lam=0.0, solver="sparse", sparse_solve=m, device=poses0.device), poses0)
-            for m in ("persistent", "workgroup", "hybrid", "sweeps")]
+            for m in ("block", "persistent", "workgroup", "hybrid", "sweeps")]
     for r in runs[1:]:
         assert np.abs(r[0] - runs[0][0]).max() < 1e-12 * np.abs(runs[0][0]).max()
         assert r[2].tolist() == runs[0][2].tolist() == [0] * 5

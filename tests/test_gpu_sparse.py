@@ -34,12 +34,12 @@ def _solve(p, K, lam, precision="fp64", refine=0):
     return plan, poses, objective, status, dev
 
 
-def _parity(p, K, lam, precision="fp64", refine=0, tol=1e-10, graphs=None):
+def _parity(p, K, lam, precision="fp64", refine=0, tol=1e-10, graphs=None, sparse_solve="auto", tau=None):
     """Element-wise comparison with the oracle on `graphs` (all by default),
     the dense tests' comparison on the block-sparse solver."""
     from test_gpu_dense import _compare
     return _compare(p, K, lam, precision=precision, refine=refine, graphs=graphs, tol_pose=tol, tol_grad=tol,
-                    solver="sparse")
+                    solver="sparse", sparse_solve=sparse_solve, tau=tau)
 
 
 def test_lattice4_fp64():
@@ -55,6 +55,33 @@ def test_lattice6_fp64_and_mixed():
 def test_uneven_walks_sparse_fp64():
     """Different structures per graph and n not a multiple of the tile size."""
     _parity(synth.uneven_walk_se3(batch=4, n_min=20, n_max=70, seed=9), 6, 1e-3)
+
+
+@pytest.mark.parametrize("group", ["SE2", "SE3"])
+def test_block_schedule_ragged(group):
+    """The BLOCK schedule (pose-block factor, elimination-tree levels, one
+    persistent launch) on ragged batches with weights, measurement tangents
+    and damping, both precisions, against the oracle element by element."""
+    if group == "SE3":
+        p = synth.uneven_walk_se3(batch=6, n_min=3, n_max=60, seed=41)
+    else:
+        p = synth.circle_se2(batch=5, n_poses=30, n_loops=12, seed=42)
+    rng = np.random.default_rng(43)
+    p["edge_logw"] = rng.normal(scale=0.3, size=len(p["edge_logw"]))
+    dof = 6 if group == "SE3" else 3
+    tau = 0.01 * rng.normal(size=(len(p["edge_logw"]), dof))
+    _parity(p, 6, 1e-3, sparse_solve="block", tau=tau)
+    _parity(p, 6, 1e-3, precision="mixed", refine=1, tol=1e-5, sparse_solve="block", tau=tau)
+
+
+def test_block_schedule_uneven_b256_sampled_graphs():
+    """The 256-walk workload on the BLOCK schedule: the smallest, the largest
+    and two other graphs against the oracle in both precisions."""
+    p = synth.uneven_walk_se3(batch=256)
+    sizes = np.diff(p["pose_off"])
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 200})
+    _parity(p, 10, 0.0, graphs=pick, sparse_solve="block")
+    _parity(p, 10, 0.0, precision="mixed", refine=3, tol=1e-5, graphs=pick, sparse_solve="block")
 
 
 def test_uneven_b256_full_size_sampled_graphs():
