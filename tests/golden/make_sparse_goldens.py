@@ -22,10 +22,12 @@ entry, gradients against the largest element) between this solve and the same
 solve and backward on the graph with its poses relabelled at random, so that
 minimum degree eliminates in another order: how far two correct float64
 factorisations of these ill-conditioned systems drift apart through rounding
-alone.  Inputs come from the seeded generators in synth/;
+alone.  `cond` is cond(H*) at the stored theta_K (Lanczos), which bounds the
+early objectives of a float64 solver: 0.5 cond(H*) eps64.  Inputs come from the seeded generators in synth/;
 everything else from oracle/.  About twenty-five minutes on one core:
 
-    python tests/golden/make_sparse_goldens.py
+    python tests/golden/make_sparse_goldens.py            # everything
+    python tests/golden/make_sparse_goldens.py --cond     # only the cond field
 """
 from __future__ import annotations
 
@@ -136,6 +138,37 @@ def make(name: str) -> str:
     return out
 
 
+def condition(name: str) -> float:
+    """cond(H*) of the stored result (the oracle's final linearisation at its
+    theta_K): largest eigenvalue by Lanczos, smallest by shift-invert Lanczos
+    through the oracle's sparse factor.  Stored as `cond`: the condition-scaled
+    bound 0.5 cond(H*) eps64 holds the early objectives of the float64 path."""
+    import scipy.sparse.linalg as sla
+    import torch
+    c = CASES[name]
+    p = c["make"]()
+    g = S.graphs_of(p)[c["graph"]]
+    path = os.path.join(HERE, name + ".npz")
+    gd = dict(np.load(path))
+    X = lie.SE3.from_storage(torch.as_tensor(gd["poses"]))
+    _, H, _ = S.linearize_pose_graph_sparse(g, X)
+    lmax = sla.eigsh(H, k=1, which="LA", return_eigenvectors=False)[0]
+    lu = S._sparse_factor(H)
+    op = sla.LinearOperator(H.shape, matvec=lambda x: lu.solve(np.asarray(x, dtype=np.float64).ravel()))
+    mu = sla.eigsh(op, k=1, which="LA", return_eigenvectors=False)[0]   # 1 / smallest eigenvalue
+    cond = float(lmax * mu)
+    gd["cond"] = np.float64(cond)
+    np.savez_compressed(path, **gd)
+    print(f"{name}: cond(H*) {cond:.3e}", flush=True)
+    return cond
+
+
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(CASES)):
-        make(name)
+    args = sys.argv[1:]
+    if args and args[0] == "--cond":
+        for name in (args[1:] or list(CASES)):
+            condition(name)
+    else:
+        for name in (args or list(CASES)):
+            make(name)
+            condition(name)

@@ -57,9 +57,9 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
     precision study) and report the element-wise figures and the objectives.
     Float64 objectives that differ by more than the tolerance are held to
     three times the oracle's own drift under another elimination order
-    (gpu_util.oracle_order_spread), or on graphs with cond(H*) >= 1e10 to
-    0.5 cond(H*) eps64 (the reading for the 256-pose walks), the scaled ratio
-    entering `worst_obj`."""
+    (gpu_util.oracle_order_spread) at theta_0 and theta_K, and in between
+    also to 0.5 cond(H*) eps64, the forward error a float64 step may carry;
+    the scaled ratio enters `worst_obj`."""
     plan, poses, objective, status, dev = gpu_solve(p, K, lam, precision, refine, tau, solver=solver,
                                                     adaptive=adaptive, dogleg=dogleg, refine_last=refine_last, pair=pair,
                                                     sparse_solve=sparse_solve)
@@ -97,16 +97,20 @@ def _compare(p, K, lam, precision="fp64", refine=0, tau=None, graphs=None, tol_p
         eo = ew_ratio(obj[b], ro, 1e-12)
         if not mixed and eo >= max(tol_pose, 1e-12) and res[gi].status == S.OK and not adaptive \
                 and dogleg is None:
-            # the early objectives of an ill-conditioned graph: held to three
-            # times the oracle's own drift under another elimination order, and
-            # on graphs with cond(H*) >= 1e10 (the 256-pose walks) to the
-            # condition-scaled bound 0.5 cond(H*) eps64 of the gradients
+            # S at theta_0 and theta_K: held to three times the oracle's own
+            # drift under another elimination order; the objectives after the
+            # early steps also to 0.5 cond(H*) eps64, the forward error a
+            # float64 step may carry on an ill-conditioned graph
             _, so = oracle_order_spread(gs[gi], K, lam)
             cond = float(np.linalg.cond(res[gi].lin.H.numpy()))
-            tol_o = max(tol_pose, 3.0 * so, 0.5 * cond * 2.2e-16 if cond >= 1e10 else 0.0)
-            print(f"\n  graph {b}: objectives {eo:.2e} apart, the oracle's own drift {so:.2e}, "
-                  f"cond(H*) {cond:.1e}, tolerance {tol_o:.1e}")
-            eo = eo / max(1.0, tol_o / max(tol_pose, 1e-12))
+            tol_e = max(tol_pose, 3.0 * so)
+            tol_i = max(tol_e, 0.5 * cond * 2.2e-16)
+            ends = [0, K]
+            ee = ew_ratio(obj[b][ends], ro[ends], 1e-12)
+            ei = ew_ratio(obj[b][1:K], ro[1:K], 1e-12) if K > 1 else 0.0
+            print(f"\n  graph {b}: objectives {ee:.2e} apart at theta_0 / theta_K, {ei:.2e} in between; the "
+                  f"oracle's own drift {so:.2e}, cond(H*) {cond:.1e}: tolerances {tol_e:.1e} / {tol_i:.1e}")
+            eo = max(ee / max(1.0, tol_e / max(tol_pose, 1e-12)), ei / max(1.0, tol_i / max(tol_pose, 1e-12)))
         worst_obj = max(worst_obj, eo)
     # backward with the seed of the oracle's solution (same v on both sides)
     seeds = _seeds(p, ref_poses, graphs)
