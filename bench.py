@@ -180,7 +180,8 @@ def main():
     ap.add_argument("--sparse-solve", choices=["auto", "block", "persistent", "workgroup", "hybrid", "sweeps"],
                     default="auto", help="schedule of the block-sparse solver")
     ap.add_argument("--solver", choices=["dense", "sparse"], default=None,
-                    help="override the workload's solver (pose graphs only)")
+                    help="override the workload's solver (bundle adjustment: sparse eliminates the points "
+                         "inside the block-sparse factorisation instead of the explicit Schur complement)")
     ap.add_argument("--adaptive", action="store_true",
                     help="Levenberg-Marquardt with adaptive damping from the workload's lambda")
     ap.add_argument("--no-pair", action="store_true",
@@ -228,10 +229,12 @@ def main():
         # conditioned workloads (cond(H) ~4e8 walks, ~7e8 lattice, ~1e11
         # for the 256-pose walks)
         args.refine = {"se3_lattice16_b8": 2, "se3_uneven_b256": 3}.get(args.workload, 1)
-    if args.solver and solver != "schur":
-        solver = args.solver
-    p = W["fn"](**W["kwargs"])
     ba = solver == "schur"
+    if args.solver and not ba:
+        solver = args.solver
+    elif args.solver == "sparse" and ba:
+        solver = "sparse"      # bundle adjustment with the points eliminated inside the sparse factorisation
+    p = W["fn"](**W["kwargs"])
     if ba and args.backward not in ("implicit", "dlm"):
         raise SystemExit(f"--backward {args.backward}: the Schur solver has the implicit and DLM backward modes")
     B = len(p["pose_off"]) - 1

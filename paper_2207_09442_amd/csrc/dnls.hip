@@ -1056,14 +1056,14 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     if (!(op->trust_radius > 0.0) || !std::isfinite(op->trust_radius))
       return fail(DNLS_ERR_INVALID_ARG, "dogleg needs a positive finite trust_radius");
   }
-  if (op->solver == DNLS_SOLVER_SCHUR) {
+  if (op->solver == DNLS_SOLVER_SCHUR || (op->solver == DNLS_SOLVER_SPARSE && pr->point_off)) {
     auto* p = new dnls_plan_s();
     p->B = pr->batch;
     p->group = pr->group;
     p->d = 6;
     p->sz = 12;
     p->opt = *op;
-    const dnls_status st = ba_plan_create(p, pr, op);
+    const dnls_status st = op->solver == DNLS_SOLVER_SCHUR ? ba_plan_create(p, pr, op) : sp_plan_create_ba(p, pr);
     if (st != DNLS_OK) {
       const std::string msg = g_err;
       dnls_plan_destroy(p);
@@ -1324,7 +1324,7 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   if ((reinterpret_cast<uintptr_t>(s->factor) & 255) || (reinterpret_cast<uintptr_t>(s->workspace) & 255))
     return fail(DNLS_ERR_WORKSPACE, "factor and workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (p->opt.solver == DNLS_SOLVER_SCHUR) {
+  if (p->opt.solver == DNLS_SOLVER_SCHUR || p->sp_ba) {
     if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
       return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv, obs_w and prior data are required");
     return solve_multi(p, s, st);

@@ -70,6 +70,10 @@ struct SpDesc {
   long long pool_off;  // doubles: tile pool
   long long winv_off;  // doubles: inverses of the diagonal tiles
   int lvl_off, nlvl;   // BLOCK schedule: elimination-tree levels ([lvl_off, lvl_off + nlvl] pointers)
+  // bundle adjustment on this solver: points [pt0, pt0 + npt), observations,
+  // camera-point Hessian blocks [cp0, cp0 + ncp); unit diagonal on the
+  // padding scalars [pad0, pad1) between the points and the cameras
+  int pt0, npt, obs0, nobs, cp0, ncp, pad0, pad1;
 };
 
 }  // namespace dnls
@@ -133,6 +137,11 @@ struct dnls_plan_s {
   bool sp_solve_wg = false;       // triangular solves: one workgroup per graph (vector in LDS)
   bool sp_persistent = false;     // the whole solve in one persistent launch (graph work queue)
   int sp_ts = 48;                 // tile size of the factor: 48 (MFMA tiles) or d (pose blocks, BLOCK)
+  bool sp_ba = false;             // bundle adjustment on the block-sparse solver (points eliminated first)
+  int* d_soff_cam = nullptr;      // its scalar offset of every camera and point in the elimination order
+  int* d_soff_pt = nullptr;
+  int4* d_cp_blk = nullptr;       // (camera, point, first, count) per camera-point block
+  int* d_cp_obs = nullptr;
   int* d_lvlptr = nullptr;        // BLOCK: columns of each level ([lvl_off + L] .. [+1] into d_lvlcol)
   int* d_lvlcol = nullptr;
   int* d_lvlbptr = nullptr;       // BLOCK: factor blocks of each level's columns (into d_lvlblk)
@@ -141,7 +150,7 @@ struct dnls_plan_s {
   int* d_sp_order = nullptr;      // its queue order: graphs by decreasing factor work
   unsigned* d_sp_queue = nullptr; // its two queue counters (self-resetting)
   bool sp_factor_wg = false;      // factorisation: one workgroup per graph
-  size_t sp_off[16] = {0};
+  size_t sp_off[18] = {0};
   std::vector<void*> allocs;
   // captured launch sequence of dnls_solve (DNLS_FLAG_GRAPH)
   std::mutex graph_mu;
@@ -166,6 +175,7 @@ dnls_status ba_plan_create(dnls_plan p, const dnls_problem* pr, const dnls_optio
 dnls_status ba_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st);
 dnls_status ba_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st);
 dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr);
+dnls_status sp_plan_create_ba(dnls_plan p, const dnls_problem* pr);
 dnls_status sp_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st);
 dnls_status sp_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st);
 

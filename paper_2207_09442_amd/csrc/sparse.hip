@@ -27,6 +27,7 @@
 #include "dense.hpp"
 #include "plan.hpp"
 #include "pose_costs.hpp"
+#include "reproj.hpp"
 #include "symbolic.hpp"
 
 namespace dnls {
@@ -89,6 +90,28 @@ struct SpArgs {
   const int* lvlbptr;      // BLOCK: factor blocks (I, J) of each level's columns, into lvlblk
   const int2* lvlblk;
   int ts;                  // tile size: kTS (48) or the pose dimension d (BLOCK)
+  // bundle adjustment (points eliminated first inside the tile factorisation)
+  double* pts;             // [Vp][3]
+  const double* obs_uv;
+  const double* obs_w;
+  const double* delta_b;   // per-problem Huber radius, or NULL for huber
+  const int* obs_cam;
+  const int* obs_pt;
+  const int* soff_cam;     // scalar offset of every camera / point in its problem's elimination order
+  const int* soff_pt;
+  const int* cam_obs_off;  // observations of every camera
+  const int* cam_obs;
+  const int* pt_obs_off;   // observations of every point
+  const int* pt_obs;
+  const int4* cp_blk;      // (camera, point, first, count) per camera-point block
+  const int* cp_obs;
+  void* orec;              // [obs][20] J~cam (2x6), J~pt (2x3), r~ (2) in the linearisation's precision
+  double* gob;             // mixed: float64 gradient parts [obs][9] (camera 6, point 3)
+  const double* seed_pt;   // backward: point seed [Vp][3] or NULL
+  double* g_w;             // backward: observation weights, per-observation radii, per-problem radii
+  double* g_delta;
+  double* g_huber;
+  double fx, fy, cx, cy, huber;
   int E, V, K, it, nx, refine;
   double lambda, radius0;
 };
@@ -1636,6 +1659,296 @@ __global__ void __launch_bounds__(kPT) k_sp_persistent(SpArgs a, const int* orde
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bundle adjustment on the block-sparse solver: cameras (6) and points (3)
+// in one system, the points ordered first so that the tile factorisation
+// eliminates them before the cameras (the point columns are block diagonal
+// and their updates of the camera tiles form the Schur complement), the
+// cameras after them in minimum-degree order of their co-observation graph.
+// The same tile kernels factor and solve the system as for pose graphs.
+// ---------------------------------------------------------------------------
+constexpr int kObsRecSp = 20;
+
+__device__ __forceinline__ double spba_radius(const SpArgs& a, int b) { return a.delta_b ? a.delta_b[b] : a.huber; }
+
+// observation and prior records of problem blockIdx.y (grid x over its
+// observations, then its priors) and the objective partials
+template <class S>
+__global__ void __launch_bounds__(kBT) k_spba_lin(SpArgs a) {
+  constexpr int RN = CostRec<6>::n;
+  __shared__ double red[kBT / 64];
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  double s = 0.0;
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (!a.failed[b]) {
+    if (t < g.nobs) {
+      const int o = g.obs0 + t;
+      double c[2], Jc[12], Jp[6];
+      reproj<double>(a.poses + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2,
+                     a, c, Jc, Jp);
+      const double w = a.obs_w[o];
+      double rho, drho;
+      huber(w * w * (c[0] * c[0] + c[1] * c[1]), spba_radius(a, b), rho, drho);
+      const double sw = ::sqrt(drho) * w;
+      S* rec = reinterpret_cast<S*>(a.orec) + (size_t)o * kObsRecSp;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rec[k] = S(sw * Jc[k]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rec[12 + k] = S(sw * Jp[k]);
+      rec[18] = S(sw * c[0]);
+      rec[19] = S(sw * c[1]);
+      if constexpr (!std::is_same<S, double>::value) {
+        const double s2 = sw * sw;
+        double* go = a.gob + (size_t)o * 9;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) go[k] = s2 * (Jc[k] * c[0] + Jc[6 + k] * c[1]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) go[6 + k] = s2 * (Jp[k] * c[0] + Jp[3 + k] * c[1]);
+      }
+      s = 0.5 * rho;
+    } else if (t < g.nobs + g.nprior) {
+      const int rk = a.E + g.prior0 + (t - g.nobs);
+      s = linearize_cost<3, double>(cost_data(a), rk, a.ws64 + (size_t)rk * RN);
+    }
+  }
+  s = block_sum_sp(s, red);
+  if (threadIdx.x == 0) a.partial[b * a.nx + blockIdx.x] = s;
+}
+
+// Hessian blocks into the tiles and g into slot 1: item u < ncam a camera's
+// diagonal block (observations and priors), then the points' diagonal
+// blocks, then the camera-point blocks (cameras follow the points, so these
+// lie below the diagonal); the padding scalars get a unit diagonal
+template <class S>
+__global__ void __launch_bounds__(kBT) k_spba_assemble(SpArgs a, double lambda) {
+  constexpr int RN = CostRec<6>::n;
+  constexpr bool MIX = !std::is_same<S, double>::value;
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const S* rec = reinterpret_cast<const S*>(a.orec);
+  double* rhs = slot(a, g, 1);
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose) {
+    const int cam = g.pose0 + u, r0 = a.soff_cam[cam];
+    S h[36];
+    double gr[6], hp[36];
+#pragma unroll
+    for (int k = 0; k < 36; ++k) {
+      h[k] = S(0);
+      hp[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gr[k] = 0.0;
+    for (int s = a.cam_obs_off[cam]; s < a.cam_obs_off[cam + 1]; ++s) {
+      const int o = a.cam_obs[s];
+      const S* r = rec + (size_t)o * kObsRecSp;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) h[i * 6 + j] += r[i] * r[j] + r[6 + i] * r[6 + j];
+        if constexpr (MIX) gr[i] += a.gob[(size_t)o * 9 + i];
+        else gr[i] += r[i] * r[18] + r[6 + i] * r[19];
+      }
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      if (a.prior_var[q] != cam) continue;
+      const double* J = a.ws64 + (size_t)(a.E + q) * RN + 36;
+      const double* res = a.ws64 + (size_t)(a.E + q) * RN + 72;
+      for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j <= i; ++j) {
+          double v = 0.0;
+          for (int k = 0; k < 6; ++k) v += J[k * 6 + i] * J[k * 6 + j];
+          hp[i * 6 + j] += v;
+        }
+        double v = 0.0;
+        for (int k = 0; k < 6; ++k) v += J[k * 6 + i] * res[k];
+        gr[i] += v;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+      for (int j = 0; j <= i; ++j) put(a, g, r0 + i, r0 + j, double(h[i * 6 + j]) + hp[i * 6 + j] + (i == j ? lambda : 0.0));
+      rhs[r0 + i] = gr[i];
+    }
+  } else if (u < g.npose + g.npt) {
+    const int pt = g.pt0 + (u - g.npose), r0 = a.soff_pt[pt];
+    S h[9];
+    double gr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) h[k] = S(0);
+    for (int s = a.pt_obs_off[pt]; s < a.pt_obs_off[pt + 1]; ++s) {
+      const int o = a.pt_obs[s];
+      const S* r = rec + (size_t)o * kObsRecSp;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) h[i * 3 + j] += r[12 + i] * r[12 + j] + r[15 + i] * r[15 + j];
+        if constexpr (MIX) gr[i] += a.gob[(size_t)o * 9 + 6 + i];
+        else gr[i] += r[12 + i] * r[18] + r[15 + i] * r[19];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j <= i; ++j) put(a, g, r0 + i, r0 + j, double(h[i * 3 + j]) + (i == j ? lambda : 0.0));
+      rhs[r0 + i] = gr[i];
+    }
+  } else if (u < g.npose + g.npt + g.ncp) {
+    const int4 blk = a.cp_blk[g.cp0 + (u - g.npose - g.npt)];
+    const int rc = a.soff_cam[blk.x], rp = a.soff_pt[blk.y];
+    S h[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) h[k] = S(0);
+    for (int s = blk.z; s < blk.z + blk.w; ++s) {
+      const S* r = rec + (size_t)a.cp_obs[s] * kObsRecSp;
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) h[i * 3 + j] += r[i] * r[12 + j] + r[6 + i] * r[15 + j];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) put(a, g, rc + i, rp + j, double(h[i * 3 + j]));
+  }
+  if (blockIdx.x == 0) {
+    for (int r = g.pad0 + threadIdx.x; r < g.pad1; r += kBT) {
+      put(a, g, r, r, 1.0);
+      rhs[r] = 0.0;
+    }
+    sp_assemble_pad(a, g, threadIdx.x, kBT);
+  }
+}
+
+// cameras X <- X Exp(-x_c), points q <- q - x_q (x in slot xs, elimination order)
+__global__ void __launch_bounds__(kBT) k_spba_update(SpArgs a, int xs) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  const double* x = slot(a, g, xs);
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose) {
+    const int cam = g.pose0 + u;
+    retract_minus<3>(a.poses + (size_t)cam * 12, x + a.soff_cam[cam]);
+  } else if (u < g.npose + g.npt) {
+    const int pt = g.pt0 + (u - g.npose);
+    const double* xp = x + a.soff_pt[pt];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.pts[(size_t)pt * 3 + k] -= xp[k];
+  }
+}
+
+// backward: the seed (cameras, points) into slot 2 in elimination order, padding zero
+__global__ void __launch_bounds__(kBT) k_spba_seed(SpArgs a) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  if (a.failed[b]) return;
+  double* x = slot(a, g, 2);
+  if (blockIdx.x == 0) {
+    for (int r = g.pad0 + threadIdx.x; r < g.pad1; r += kBT) x[r] = 0.0;
+    for (int r = g.n + threadIdx.x; r < g.nvec; r += kBT) x[r] = 0.0;
+  }
+  const int u = blockIdx.x * kBT + threadIdx.x;
+  if (u < g.npose) {
+    const int cam = g.pose0 + u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[a.soff_cam[cam] + k] = a.seed[(size_t)cam * 6 + k];
+  } else if (u < g.npose + g.npt) {
+    const int pt = g.pt0 + (u - g.npose);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[a.soff_pt[pt] + k] = a.seed_pt ? a.seed_pt[(size_t)pt * 3 + k] : 0.0;
+  }
+}
+
+// backward, per observation and prior (Proposition 1): with u = H*^-1 v in
+// slot 0, dL/dphi = -d/dphi [u^T g(theta_K; phi)] for the observation
+// weights, each observation's Huber radius and the prior log-weights; the
+// camera adjoint into uout.  Zero for problems whose solve failed.
+__global__ void __launch_bounds__(kBT) k_spba_vjp(SpArgs a) {
+  const int b = blockIdx.y;
+  const SpDesc g = a.sd[b];
+  const bool ok = a.status[b] == DNLS_GRAPH_OK;
+  const double* u = slot(a, g, 0);
+  const int t = blockIdx.x * kBT + threadIdx.x;
+  if (t < g.nobs) {
+    const int o = g.obs0 + t;
+    double gw = 0.0, gd = 0.0;
+    if (ok) {
+      double c[2], Jc[12], Jp[6];
+      reproj<double>(a.poses + (size_t)a.obs_cam[o] * 12, a.pts + (size_t)a.obs_pt[o] * 3, a.obs_uv + (size_t)o * 2,
+                     a, c, Jc, Jp);
+      const double* uc = u + a.soff_cam[a.obs_cam[o]];
+      const double* up = u + a.soff_pt[a.obs_pt[o]];
+      double y[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc += Jc[r * 6 + k] * uc[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc += Jp[r * 3 + k] * up[k];
+        y[r] = acc;
+      }
+      const double w = a.obs_w[o];
+      const double yc = y[0] * c[0] + y[1] * c[1];
+      const double cn2 = c[0] * c[0] + c[1] * c[1];
+      const double hd = spba_radius(a, b);
+      // g_o = rho'(s) w^2 C^T c, rho' = 1 inside and delta / sqrt(s) outside
+      if (w * w * cn2 <= hd * hd) {
+        gw = -2.0 * w * yc;
+      } else {
+        gw = -hd * yc / ::sqrt(cn2);
+        gd = -w * yc / ::sqrt(cn2);
+      }
+    }
+    if (a.g_w) a.g_w[o] = gw;
+    if (a.g_delta) a.g_delta[o] = gd;
+  } else if (t < g.nobs + g.nprior) {
+    const int q = g.prior0 + (t - g.nobs);
+    double gl = 0.0;
+    if (ok) {
+      double c[6], C[36];
+      prior_cost<3, double>(a.poses + (size_t)a.prior_var[q] * 12, a.prior_meas + (size_t)q * 12, c, C);
+      const double w = exp(a.prior_logw[q]);
+      const double* uq = u + a.soff_cam[a.prior_var[q]];
+      double yr = 0.0;
+      for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 6; ++k) acc += C[r * 6 + k] * uq[k];
+        yr += w * acc * w * c[r];
+      }
+      gl = -2.0 * yr;
+    }
+    if (a.g_logw_p) a.g_logw_p[q] = gl;
+  }
+  if (t < g.npose && a.uout) {
+    const int cam = g.pose0 + t;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a.uout[(size_t)cam * 6 + k] = ok ? u[a.soff_cam[cam] + k] : 0.0;
+  }
+}
+
+// per-problem Huber radius gradient: the sum of its observations' per-radius
+// gradients, one workgroup per problem (strided partial sums, then a fixed
+// tree in LDS: the same order on every call)
+__global__ void __launch_bounds__(kBT) k_spba_delta_sum(SpArgs a) {
+  __shared__ double red[kBT];
+  const int b = blockIdx.x;
+  const SpDesc g = a.sd[b];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < g.nobs; t += kBT) s += a.g_delta[g.obs0 + t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.g_huber[b] = red[0];
+}
+
 __global__ void k_sp_reset(int* failed, int* status, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) {
@@ -1995,6 +2308,260 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   return DNLS_OK;
 }
 
+// Bundle adjustment on the block-sparse solver (solver SPARSE given a
+// problem with points).  Per problem: points first, ordered by their first
+// observing camera and index, at scalar offsets 3 k; then, from the next
+// multiple of the tile size, the cameras in minimum-degree order of their
+// co-observation graph (an elimination-tree postorder of it), 6 scalars
+// each; unit diagonal on the padding scalars.  The tile structure of the
+// factor and the numeric tile kernels are the pose-graph path's.
+dnls_status sp_plan_create_ba(dnls_plan p, const dnls_problem* pr) {
+  const int B = pr->batch;
+  int Vc = 0, Vp = 0, O = 0, P = 0;
+  auto offs = [&](const int32_t* off, int* tot) {
+    if (!off || off[0] != 0) return false;
+    for (int b = 0; b < B; ++b)
+      if (off[b + 1] < off[b]) return false;
+    *tot = off[B];
+    return true;
+  };
+  if (!offs(pr->pose_off, &Vc) || !offs(pr->point_off, &Vp) || !offs(pr->obs_off, &O) || !offs(pr->prior_off, &P))
+    return fail(DNLS_ERR_INVALID_ARG, "bundle adjustment needs pose/point/obs/prior offsets starting at 0, non-decreasing");
+  if (pr->group != DNLS_SE3) return fail(DNLS_ERR_UNSUPPORTED, "bundle adjustment uses SE3 cameras");
+  if (O > 0 && (!pr->obs_cam || !pr->obs_pt)) return fail(DNLS_ERR_INVALID_ARG, "obs_cam / obs_pt are NULL");
+  if (P > 0 && !pr->prior_var) return fail(DNLS_ERR_INVALID_ARG, "prior_var is NULL");
+  if (!(pr->huber_delta > 0.0)) return fail(DNLS_ERR_INVALID_ARG, "huber_delta must be > 0");
+  if (pr->edge_off && pr->edge_off[B] != 0)
+    return fail(DNLS_ERR_UNSUPPORTED, "relative-pose costs and points in one problem are not supported");
+  if (p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG | DNLS_FLAG_KEEP_ITERATES))
+    return fail(DNLS_ERR_UNSUPPORTED, "bundle adjustment on the block-sparse solver runs fixed-damping steps "
+                                      "(adaptive damping, the dogleg and kept iterates are on the Schur solver)");
+  const int mode = p->opt.sparse_solve;
+  if (mode == DNLS_SPSOLVE_PERSISTENT || mode == DNLS_SPSOLVE_BLOCK || mode == DNLS_SPSOLVE_WORKGROUP)
+    return fail(DNLS_ERR_UNSUPPORTED, "bundle adjustment on the block-sparse solver takes the HYBRID or SWEEPS schedule");
+  p->sp_ba = true;
+  p->V = Vc;
+  p->Vp = Vp;
+  p->O = O;
+  p->P = P;
+  p->E = 0;
+  p->intr[0] = pr->fx;
+  p->intr[1] = pr->fy;
+  p->intr[2] = pr->cx;
+  p->intr[3] = pr->cy;
+  p->huber = pr->huber_delta;
+  p->sp_ts = kTS;
+  std::vector<int> obs_cam(O), obs_pt(O), prior_var(P), soff_cam(Vc), soff_pt(Vp);
+  std::vector<std::vector<int>> cam_obs(Vc), pt_obs(Vp);
+  std::vector<int4> cp_blk;
+  std::vector<int> cp_obs, tix, colptr, rowidx, rowptr, rowcol;
+  p->sd.resize(B);
+  long long fac = 0, vecoff = 0;
+  int maxP = 0, maxn = 0;
+  for (int b = 0; b < B; ++b) {
+    SpDesc& g = p->sd[b];
+    g = SpDesc{};
+    g.pose0 = pr->pose_off[b];
+    g.npose = pr->pose_off[b + 1] - g.pose0;
+    g.pt0 = pr->point_off[b];
+    g.npt = pr->point_off[b + 1] - g.pt0;
+    g.obs0 = pr->obs_off[b];
+    g.nobs = pr->obs_off[b + 1] - g.obs0;
+    g.prior0 = pr->prior_off[b];
+    g.nprior = pr->prior_off[b + 1] - g.prior0;
+    g.edge0 = 0;
+    g.nedge = 0;
+    std::map<std::pair<int, int>, std::vector<int>> blocks;   // (camera, point) -> observations
+    std::vector<int> first_cam(g.npt, INT32_MAX);
+    std::vector<std::vector<int>> cam_pts(g.npose);
+    for (int o = g.obs0; o < g.obs0 + g.nobs; ++o) {
+      const int c = pr->obs_cam[o], q = pr->obs_pt[o];
+      if (c < g.pose0 || c >= g.pose0 + g.npose || q < g.pt0 || q >= g.pt0 + g.npt)
+        return fail(DNLS_ERR_INVALID_ARG, "observation " + std::to_string(o) + " refers to a camera or point "
+                                          "outside its problem");
+      obs_cam[o] = c;
+      obs_pt[o] = q;
+      cam_obs[c].push_back(o);
+      pt_obs[q].push_back(o);
+      blocks[{c, q}].push_back(o);
+      first_cam[q - g.pt0] = std::min(first_cam[q - g.pt0], c - g.pose0);
+      cam_pts[c - g.pose0].push_back(q - g.pt0);
+    }
+    for (int q = g.prior0; q < g.prior0 + g.nprior; ++q) {
+      const int v = pr->prior_var[q];
+      if (v < g.pose0 || v >= g.pose0 + g.npose)
+        return fail(DNLS_ERR_INVALID_ARG, "prior " + std::to_string(q) + " refers to a camera outside its problem");
+      prior_var[q] = v;
+    }
+    // points first, by first observing camera then index
+    std::vector<int> porder(g.npt);
+    for (int k = 0; k < g.npt; ++k) porder[k] = k;
+    std::stable_sort(porder.begin(), porder.end(), [&](int x, int y) { return first_cam[x] < first_cam[y]; });
+    for (int r = 0; r < g.npt; ++r) soff_pt[g.pt0 + porder[r]] = 3 * r;
+    // cameras: minimum degree on the co-observation graph, then a postorder
+    std::vector<std::vector<int>> cadj(g.npose);
+    {
+      std::vector<std::vector<int>> pt_cams(g.npt);
+      for (int c = 0; c < g.npose; ++c)
+        for (int q : cam_pts[c]) pt_cams[q].push_back(c);
+      for (int q = 0; q < g.npt; ++q)
+        for (size_t i = 0; i < pt_cams[q].size(); ++i)
+          for (size_t j = i + 1; j < pt_cams[q].size(); ++j) {
+            cadj[pt_cams[q][i]].push_back(pt_cams[q][j]);
+            cadj[pt_cams[q][j]].push_back(pt_cams[q][i]);
+          }
+      for (auto& l : cadj) {
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+      }
+    }
+    const std::vector<int> corder = sym::min_degree_order(g.npose, cadj);
+    std::vector<int> cpos(g.npose);
+    for (int k = 0; k < g.npose; ++k) cpos[corder[k]] = k;
+    cpos = sym::postorder_positions(g.npose, cadj, cpos);
+    g.pad0 = 3 * g.npt;
+    g.pad1 = (g.pad0 + kTS - 1) / kTS * kTS;
+    for (int c = 0; c < g.npose; ++c) soff_cam[g.pose0 + c] = g.pad1 + 6 * cpos[c];
+    g.n = g.pad1 + 6 * g.npose;
+    maxn = std::max(maxn, g.n);
+    // tile structure: variables are the points, the padding scalars (one
+    // unit block each) and the cameras
+    std::vector<int> start, size;
+    for (int q = 0; q < g.npt; ++q) {
+      start.push_back(soff_pt[g.pt0 + q]);
+      size.push_back(3);
+    }
+    for (int r = g.pad0; r < g.pad1; ++r) {
+      start.push_back(r);
+      size.push_back(1);
+    }
+    const int cam_var0 = (int)start.size();
+    for (int c = 0; c < g.npose; ++c) {
+      start.push_back(soff_cam[g.pose0 + c]);
+      size.push_back(6);
+    }
+    std::vector<std::pair<int, int>> bl;
+    for (auto& kv : blocks) bl.push_back({cam_var0 + kv.first.first - g.pose0, kv.first.second - g.pt0});
+    const sym::TileStructure ts = sym::tile_symbolic_vars(g.n, kTS, start, size, bl);
+    p->flops_exec += sym::tile_flops(ts, kTS);
+    // block flops of the points' elimination and the camera system (the
+    // Schur complement's pairs and the dense-ish camera factor)
+    {
+      double f = 0.0;
+      for (int q = 0; q < g.npt; ++q) {
+        const double k = (double)pt_obs[g.pt0 + q].size();
+        f += 9.0 + k * 27.0 * 2.0 + k * (k + 1) / 2.0 * 2.0 * 6 * 6 * 3;
+      }
+      const double nc = 6.0 * g.npose;
+      f += nc * nc * nc / 3.0;
+      p->flops_alg += f;
+    }
+    g.P = ts.P;
+    maxP = std::max(maxP, g.P);
+    g.ntile = (int)ts.row_idx.size();
+    g.tix_off = (int)tix.size();
+    tix.resize(tix.size() + (size_t)g.P * g.P, -1);
+    g.col_off = (int)colptr.size();
+    const int rbase = (int)rowidx.size();
+    for (int J = 0; J <= g.P; ++J) colptr.push_back(rbase + ts.col_ptr[J]);
+    for (int J = 0; J < g.P; ++J)
+      for (int k = ts.col_ptr[J]; k < ts.col_ptr[J + 1]; ++k) {
+        tix[g.tix_off + (size_t)ts.row_idx[k] * g.P + J] = k;
+        rowidx.push_back(ts.row_idx[k]);
+      }
+    {
+      std::vector<std::vector<int>> rows(g.P);
+      for (int J = 0; J < g.P; ++J)
+        for (int k = ts.col_ptr[J] + 1; k < ts.col_ptr[J + 1]; ++k) rows[ts.row_idx[k]].push_back(J);
+      g.row_off = (int)rowptr.size();
+      for (int I = 0; I < g.P; ++I) {
+        rowptr.push_back((int)rowcol.size());
+        for (int J : rows[I]) rowcol.push_back(J);
+      }
+      rowptr.push_back((int)rowcol.size());
+    }
+    g.pool_off = fac;
+    fac += (long long)g.ntile * kTT;
+    g.winv_off = fac;
+    fac += (long long)g.P * kTT;
+    fac = (fac + 31) / 32 * 32;
+    g.nvec = g.P * kTS;
+    g.vec_off = vecoff;
+    vecoff += 4LL * g.nvec;
+    g.cp0 = (int)cp_blk.size();
+    for (auto& kv : blocks) {
+      cp_blk.push_back(int4{kv.first.first, kv.first.second, (int)cp_obs.size(), (int)kv.second.size()});
+      for (int o : kv.second) cp_obs.push_back(o);
+    }
+    g.ncp = (int)cp_blk.size() - g.cp0;
+    g.od0 = 0;
+    g.nod = 0;
+    g.lvl_off = 0;
+    g.nlvl = 0;
+  }
+  std::vector<int> cam_off(Vc + 1, 0), cam_list, pt_off(Vp + 1, 0), pt_list;
+  for (int c = 0; c < Vc; ++c) {
+    cam_off[c + 1] = cam_off[c] + (int)cam_obs[c].size();
+    for (int o : cam_obs[c]) cam_list.push_back(o);
+  }
+  for (int q = 0; q < Vp; ++q) {
+    pt_off[q + 1] = pt_off[q] + (int)pt_obs[q].size();
+    for (int o : pt_obs[q]) pt_list.push_back(o);
+  }
+  p->sp_ntrsm.assign(maxP, 0);
+  p->sp_npair.assign(maxP, 0);
+  p->sp_nrow.assign(maxP, 0);
+  for (int b = 0; b < B; ++b) {
+    const SpDesc& g = p->sd[b];
+    for (int J = 0; J < g.P; ++J) {
+      const int m = colptr[g.col_off + J + 1] - colptr[g.col_off + J] - 1;
+      p->sp_ntrsm[J] = std::max(p->sp_ntrsm[J], m);
+      p->sp_npair[J] = std::max(p->sp_npair[J], (long long)m * (m + 1) / 2);
+      p->sp_nrow[J] = std::max(p->sp_nrow[J], rowptr[g.row_off + J + 1] - rowptr[g.row_off + J]);
+    }
+  }
+  p->sp_maxP = maxP;
+  const bool fits = max_desc(p->sd, &SpDesc::nvec) <= kSolveLds;
+  if (mode == DNLS_SPSOLVE_HYBRID && !fits)
+    return fail(DNLS_ERR_UNSUPPORTED, "the workgroup solve holds at most " + std::to_string(kSolveLds) +
+                                          " unknowns per problem");
+  p->sp_solve_wg = mode == DNLS_SPSOLVE_HYBRID || (mode == DNLS_SPSOLVE_AUTO && fits);
+  p->sp_factor_wg = false;
+  p->sp_persistent = false;
+  dnls_status st;
+  if ((st = upload(p, &p->d_sd, p->sd)) != DNLS_OK || (st = upload(p, &p->d_prior_var, prior_var)) != DNLS_OK ||
+      (st = upload(p, &p->d_obs_cam, obs_cam)) != DNLS_OK || (st = upload(p, &p->d_obs_pt, obs_pt)) != DNLS_OK ||
+      (st = upload(p, &p->d_soff_cam, soff_cam)) != DNLS_OK || (st = upload(p, &p->d_soff_pt, soff_pt)) != DNLS_OK ||
+      (st = upload(p, &p->d_cam_obs_off, cam_off)) != DNLS_OK || (st = upload(p, &p->d_cam_obs, cam_list)) != DNLS_OK ||
+      (st = upload(p, &p->d_pt_obs_off, pt_off)) != DNLS_OK || (st = upload(p, &p->d_pt_obs, pt_list)) != DNLS_OK ||
+      (st = upload(p, &p->d_cp_blk, cp_blk)) != DNLS_OK || (st = upload(p, &p->d_cp_obs, cp_obs)) != DNLS_OK ||
+      (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
+      (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK || (st = upload(p, &p->d_rowptr, rowptr)) != DNLS_OK ||
+      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK)
+    return st;
+  const size_t rn = CostRec<6>::n;
+  const int maxc = std::max(max_desc(p->sd, &SpDesc::nobs) + max_desc(p->sd, &SpDesc::nprior), 1);
+  p->nlin_blocks = (maxc + kBT - 1) / kBT;
+  size_t off = 0;
+  p->sp_off[0] = off; off += align256((size_t)std::max(P, 1) * rn * sizeof(double));   // prior records
+  p->sp_off[3] = off; off += align256((size_t)vecoff * sizeof(double));                 // vectors
+  p->sp_off[4] = off; off += align256((size_t)B * p->nlin_blocks * sizeof(double));     // partials
+  p->sp_off[5] = off; off += align256((size_t)B * sizeof(int));                         // failed
+  p->sp_off[6] = off; off += align256((size_t)B * sizeof(double));                      // last objective
+  p->sp_off[7] = off; off += align256((size_t)Vc * 6 * sizeof(double));                // camera adjoint
+  // observation records: float64, or (mixed) float records then the float64 gradient parts
+  p->sp_off[16] = off;
+  off += align256(std::max((size_t)O * kObsRecSp * sizeof(double),
+                           align256((size_t)O * kObsRecSp * sizeof(float)) + (size_t)O * 9 * sizeof(double)));
+  p->sp_off[17] = off; off += align256((size_t)std::max(O, 1) * sizeof(double));        // per-observation radius gradients
+  p->ws_bytes = off;
+  p->bwd_bytes = off;
+  p->traj_off = (long long)fac;
+  p->fac_bytes = (size_t)fac * sizeof(double);
+  (void)maxn;
+  return DNLS_OK;
+}
+
 static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   SpArgs a{};
   a.sd = p->d_sd;
@@ -2030,6 +2597,26 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   }
   a.factor = static_cast<double*>(factor);
   a.ts = p->sp_ts;
+  if (p->sp_ba) {
+    a.orec = w + p->sp_off[16];
+    a.gob = reinterpret_cast<double*>(w + p->sp_off[16] + align256((size_t)p->O * kObsRecSp * sizeof(float)));
+    a.g_delta = reinterpret_cast<double*>(w + p->sp_off[17]);
+    a.obs_cam = p->d_obs_cam;
+    a.obs_pt = p->d_obs_pt;
+    a.soff_cam = p->d_soff_cam;
+    a.soff_pt = p->d_soff_pt;
+    a.cam_obs_off = p->d_cam_obs_off;
+    a.cam_obs = p->d_cam_obs;
+    a.pt_obs_off = p->d_pt_obs_off;
+    a.pt_obs = p->d_pt_obs;
+    a.cp_blk = p->d_cp_blk;
+    a.cp_obs = p->d_cp_obs;
+    a.fx = p->intr[0];
+    a.fy = p->intr[1];
+    a.cx = p->intr[2];
+    a.cy = p->intr[3];
+    a.huber = p->huber;
+  }
   a.lvlptr = p->d_lvlptr;
   a.lvlcol = p->d_lvlcol;
   a.lvlbptr = p->d_lvlbptr;
@@ -2327,12 +2914,99 @@ static dnls_status sp_backward_impl(dnls_plan p, const dnls_backward_args* s, hi
   return DNLS_OK;
 }
 
+// Bundle adjustment on the block-sparse solver: K fixed-damping steps and
+// the final linearisation, all through the tile factorisation and solves
+static dnls_status sp_solve_ba(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+    return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv, obs_w and prior data are required");
+  SpArgs a = sp_args(p, s->workspace, s->factor);
+  a.poses = s->poses;
+  a.pts = s->points;
+  a.obs_uv = s->obs_uv;
+  a.obs_w = s->obs_w;
+  a.delta_b = s->huber_delta;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.objective = s->objective;
+  a.status = s->status;
+  const int B = p->B;
+  const bool mixed = p->opt.precision == DNLS_PREC_MIXED;
+  const dim3 g_lin(p->nlin_blocks, B);
+  const int nvar = max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::npt);
+  const dim3 g_asm((nvar + max_desc(p->sd, &SpDesc::ncp) + kBT - 1) / kBT, B);
+  const dim3 g_upd((nvar + kBT - 1) / kBT, B);
+  const dim3 g_zero(256, B);
+  const dim3 g_vec(std::min(64, (max_desc(p->sd, &SpDesc::nvec) + kBT - 1) / kBT), B);
+  hipLaunchKernelGGL(k_sp_reset, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  for (int it = 0; it <= p->opt.iterations; ++it) {
+    const bool final_lin = it == p->opt.iterations;
+    const double lam = final_lin ? 0.0 : p->opt.lambda;
+    a.it = it;
+    // float J^T J blocks inside the loop on the mixed path (float64 gradient
+    // parts); the final, cached linearisation is float64
+    const bool lin32 = mixed && !final_lin;
+    if (lin32) hipLaunchKernelGGL(k_spba_lin<float>, g_lin, dim3(kBT), 0, st, a);
+    else hipLaunchKernelGGL(k_spba_lin<double>, g_lin, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL(k_sp_objective, dim3((B + 63) / 64), dim3(64), 0, st, a, B);
+    hipLaunchKernelGGL(k_sp_zero, g_zero, dim3(kBT), 0, st, a);
+    if (lin32) hipLaunchKernelGGL(k_spba_assemble<float>, g_asm, dim3(kBT), 0, st, a, lam);
+    else hipLaunchKernelGGL(k_spba_assemble<double>, g_asm, dim3(kBT), 0, st, a, lam);
+    sp_factor<3>(p, a, st);
+    if (final_lin) break;
+    hipLaunchKernelGGL(k_sp_copy, g_vec, dim3(kBT), 0, st, a, 1, 2);
+    sp_sweeps(p, a, 0, st);
+    hipLaunchKernelGGL(k_spba_update, g_upd, dim3(kBT), 0, st, a, 0);
+  }
+  HIP_TRY(hipGetLastError());
+  return DNLS_OK;
+}
+
+// implicit backward of bundle adjustment on the block-sparse solver
+static dnls_status sp_backward_ba(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
+  if (s->mode != DNLS_BACKWARD_IMPLICIT)
+    return fail(DNLS_ERR_UNSUPPORTED, "bundle adjustment on the block-sparse solver has the implicit backward only");
+  if (!s->points || (p->O > 0 && (!s->obs_uv || !s->obs_w)) || (p->P > 0 && (!s->prior_meas || !s->prior_logw)))
+    return fail(DNLS_ERR_INVALID_ARG, "points, obs_uv, obs_w and prior data are required");
+  SpArgs a = sp_args(p, s->workspace, const_cast<void*>(s->factor));
+  a.poses = const_cast<double*>(s->poses);
+  a.pts = const_cast<double*>(s->points);
+  a.obs_uv = s->obs_uv;
+  a.obs_w = s->obs_w;
+  a.delta_b = s->huber_delta;
+  a.prior_meas = s->prior_meas;
+  a.prior_logw = s->prior_logw;
+  a.status = const_cast<int*>(s->status);
+  a.seed = s->seed_pose;
+  a.seed_pt = s->seed_point;
+  a.g_w = s->grad_obs_w;
+  a.g_logw_p = s->grad_prior_logw;
+  if (s->grad_obs_delta) a.g_delta = s->grad_obs_delta;
+  a.g_huber = s->grad_huber_delta;
+  const int B = p->B;
+  const dim3 g_lin(p->nlin_blocks, B);
+  const int nvar = max_desc(p->sd, &SpDesc::npose) + max_desc(p->sd, &SpDesc::npt);
+  const dim3 g_upd((nvar + kBT - 1) / kBT, B);
+  hipLaunchKernelGGL(k_sp_failed_from_status, dim3((B + 255) / 256), dim3(256), 0, st, a.failed, a.status, B);
+  hipLaunchKernelGGL(k_spba_seed, g_upd, dim3(kBT), 0, st, a);
+  sp_sweeps(p, a, 0, st);
+  const int nv = std::max(max_desc(p->sd, &SpDesc::nobs) + max_desc(p->sd, &SpDesc::nprior),
+                          max_desc(p->sd, &SpDesc::npose));
+  hipLaunchKernelGGL(k_spba_vjp, dim3((nv + kBT - 1) / kBT, B), dim3(kBT), 0, st, a);
+  if (a.g_huber) hipLaunchKernelGGL(k_spba_delta_sum, dim3(B), dim3(kBT), 0, st, a);
+  HIP_TRY(hipGetLastError());
+  if (s->adjoint)
+    HIP_TRY(hipMemcpyAsync(s->adjoint, a.uout, (size_t)p->V * 6 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return DNLS_OK;
+}
+
 dnls_status sp_solve(dnls_plan p, const dnls_solve_args* s, hipStream_t st) {
+  if (p->sp_ba) return sp_solve_ba(p, s, st);
   if (p->group == DNLS_SE3) return sp_solve_impl<3>(p, s, st);
   return sp_solve_impl<2>(p, s, st);
 }
 
 dnls_status sp_backward(dnls_plan p, const dnls_backward_args* s, hipStream_t st) {
+  if (p->sp_ba) return sp_backward_ba(p, s, st);
   if (p->group == DNLS_SE3) return sp_backward_impl<3>(p, s, st);
   return sp_backward_impl<2>(p, s, st);
 }

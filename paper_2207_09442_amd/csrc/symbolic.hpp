@@ -176,27 +176,27 @@ struct TileStructure {
   std::vector<int> row_idx;        // tile rows of column J, sorted, diagonal first
 };
 
-// Tile pattern of the Cholesky factor of the permuted matrix.
-// perm_pos[v] = position of pose v in the elimination order; blocks lists
-// the (pose a, pose b) pairs of the Hessian's non-zero off-diagonal blocks.
-inline TileStructure tile_symbolic(int npose, int d, int ts, const std::vector<int>& perm_pos,
-                                   const std::vector<std::pair<int, int>>& blocks) {
+// Tile pattern of the Cholesky factor of a matrix of n scalars whose
+// variables occupy the scalar ranges [start[v], start[v] + size[v]) in
+// elimination order; blocks lists the (variable a, variable b) pairs of the
+// Hessian's non-zero off-diagonal blocks (every diagonal block is non-zero).
+inline TileStructure tile_symbolic_vars(int n, int ts, const std::vector<int>& start, const std::vector<int>& size,
+                                        const std::vector<std::pair<int, int>>& blocks) {
   TileStructure t;
-  const int n = npose * d;
   t.P = (n + ts - 1) / ts;
   std::vector<std::vector<int>> cols(t.P);
   auto add = [&](int I, int J) {
     if (I < J) std::swap(I, J);
     cols[J].push_back(I);
   };
-  for (int k = 0; k < npose; ++k) {
-    const int s0 = perm_pos[k] * d, s1 = s0 + d - 1;
+  for (size_t k = 0; k < start.size(); ++k) {
+    const int s0 = start[k], s1 = s0 + size[k] - 1;
     for (int I = s0 / ts; I <= s1 / ts; ++I)
       for (int J = s0 / ts; J <= s1 / ts; ++J) add(I, J);
   }
   for (const auto& ab : blocks) {
-    const int ra0 = perm_pos[ab.first] * d, ra1 = ra0 + d - 1;
-    const int rb0 = perm_pos[ab.second] * d, rb1 = rb0 + d - 1;
+    const int ra0 = start[ab.first], ra1 = ra0 + size[ab.first] - 1;
+    const int rb0 = start[ab.second], rb1 = rb0 + size[ab.second] - 1;
     for (int I = ra0 / ts; I <= ra1 / ts; ++I)
       for (int J = rb0 / ts; J <= rb1 / ts; ++J) add(I, J);
   }
@@ -217,6 +217,15 @@ inline TileStructure tile_symbolic(int npose, int d, int ts, const std::vector<i
     for (int I : cols[J]) t.row_idx.push_back(I);
   }
   return t;
+}
+
+// The same for npose variables of d scalars each; perm_pos[v] = position
+// of pose v in the elimination order.
+inline TileStructure tile_symbolic(int npose, int d, int ts, const std::vector<int>& perm_pos,
+                                   const std::vector<std::pair<int, int>>& blocks) {
+  std::vector<int> start(npose), size(npose, d);
+  for (int k = 0; k < npose; ++k) start[k] = perm_pos[k] * d;
+  return tile_symbolic_vars(npose * d, ts, start, size, blocks);
 }
 
 // Work of the numeric factorisation on this structure, in flops

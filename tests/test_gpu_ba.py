@@ -22,9 +22,9 @@ rng = np.random.default_rng(5)
 
 
 def _run(p, K, lam, precision="fp64", problems=None, tol=1e-10, seed_points=True, pair=False, adaptive=False,
-         dogleg=None):
+         dogleg=None, solver="schur"):
     from paper_2207_09442_amd import Plan
-    plan = Plan(p, K, lam=lam, solver="schur", precision=precision, device=t(0.0).device, pair=pair,
+    plan = Plan(p, K, lam=lam, solver=solver, precision=precision, device=t(0.0).device, pair=pair,
                 adaptive=adaptive, dogleg=dogleg)
     assert plan.schedule()["pair"] == pair
     cams, pts = t(p["poses_init"]), t(p["points_init"])
@@ -111,6 +111,65 @@ def test_ba_ring64_full_size_fp64_and_mixed(pair):
     p = synth.bundle_adjustment(batch=4)
     _run(p, 10, 1e-3, pair=pair)
     _run(p, 10, 1e-3, precision="mixed", tol=1e-5, pair=pair)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ba_sparse_elimination_small_and_ragged(precision, tol):
+    """Bundle adjustment on the block-sparse solver (points eliminated first
+    inside the tile factorisation, no explicit Schur complement): small and
+    ragged problems with random observation weights against the oracle's
+    Schur solution, cameras, points, objectives and gradients element by
+    element, the implicit backward through the sparse factor."""
+    from paper_2207_09442_amd import Plan
+    p = synth.bundle_adjustment(batch=2, n_cams=8, n_points=60, obs_per_point=4, seed=1)
+    p["obs_w"] = np.exp(rng.normal(scale=0.2, size=len(p["obs_w"])))
+    assert Plan(p, 1, solver="sparse", device=t(0.0).device).schedule()["sparse_solve"] == "hybrid"
+    _run(p, 5, 1e-3, precision=precision, tol=tol, solver="sparse")
+    a = synth.bundle_adjustment(batch=1, n_cams=9, n_points=50, obs_per_point=4, seed=2)
+    b = synth.bundle_adjustment(batch=1, n_cams=14, n_points=70, obs_per_point=5, seed=3)
+    q = {}
+    for k in a:
+        if k in ("group", "intrinsics", "huber_delta"):
+            q[k] = a[k]
+        elif k.endswith("_off"):
+            q[k] = np.concatenate([a[k], a[k][-1] + b[k][1:]]).astype(np.int32)
+        elif k in ("obs_cam", "prior_var"):
+            q[k] = np.concatenate([a[k], b[k] + a["pose_off"][-1]]).astype(np.int32)
+        elif k == "obs_pt":
+            q[k] = np.concatenate([a[k], b[k] + a["point_off"][-1]]).astype(np.int32)
+        else:
+            q[k] = np.concatenate([a[k], b[k]])
+    _run(q, 4, 1e-3, precision=precision, tol=tol, solver="sparse")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_ba_sparse_elimination_ring64_full_size(precision, tol):
+    """The 4 x (64 cameras, 2048 points, 16384 observations) workload on the
+    block-sparse solver (6528 unknowns per problem: the per-column solve
+    sweeps), every problem against the oracle."""
+    from paper_2207_09442_amd import Plan
+    p = synth.bundle_adjustment(batch=4)
+    assert Plan(p, 1, solver="sparse", device=t(0.0).device).schedule()["sparse_solve"] == "sweeps"
+    _run(p, 10, 1e-3, precision=precision, tol=tol, solver="sparse")
+
+
+def test_ba_sparse_elimination_refuses_other_modes():
+    """The block-sparse BA path runs fixed damping and the implicit backward;
+    adaptive damping, the dogleg and the DLM backward stay on the Schur
+    solver."""
+    from paper_2207_09442_amd import DnlsError, Plan
+    p = synth.bundle_adjustment(batch=1, n_cams=8, n_points=40, obs_per_point=4, seed=5)
+    for kw in (dict(adaptive=True), dict(dogleg=1.0), dict(sparse_solve="block")):
+        with pytest.raises(DnlsError, match="not supported|takes the HYBRID|fixed-damping"):
+            Plan(p, 3, lam=1e-3, solver="sparse", device=t(0.0).device, **kw)
+    plan = Plan(p, 3, lam=1e-3, solver="sparse", device=t(0.0).device)
+    cams, pts = t(p["poses_init"]), t(p["points_init"])
+    dev = dict(obs_uv=t(p["obs_uv"]), obs_w=t(p["obs_w"]), prior_meas=t(p["prior_meas"]),
+               prior_logw=t(p["prior_logw"]))
+    _, status = plan.solve_ba(cams, pts, **dev)
+    with pytest.raises(DnlsError, match="implicit backward only"):
+        plan.backward_ba(cams, pts, status=status, seed_cam=torch.zeros(plan.V, 6, dtype=torch.float64,
+                                                                        device=cams.device), mode="dlm", **dev)
 
 
 @pytest.mark.parametrize("pair", [False, True])
