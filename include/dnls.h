@@ -127,7 +127,9 @@ typedef struct {
  * DNLS_FLAG_ADAPTIVE_LM or DNLS_FLAG_DOGLEG, and the plan's solves must not
  * overlap (the queue is the plan's).  AUTO: for graphs of at most 6144
  * (padded) unknowns and 16 tile columns PERSISTENT with a fixed-damping
- * optimizer, else WORKGROUP; HYBRID for at most 6144 unknowns, else SWEEPS.  WORKGROUP, HYBRID and PERSISTENT
+ * optimizer, else WORKGROUP; for graphs of at most 6144 unknowns beyond 16
+ * tile columns BLOCK with float64 and fixed damping, else HYBRID; SWEEPS
+ * beyond 6144 unknowns.  WORKGROUP, HYBRID and PERSISTENT
  * on a plan whose graphs exceed 6144 unknowns, and PERSISTENT with adaptive
  * damping or the dogleg, are DNLS_ERR_UNSUPPORTED.
  * BLOCK: the factor in d x d pose blocks (the block-sparse structure of the
@@ -135,8 +137,7 @@ typedef struct {
  * levels of the elimination tree (every column of a level at once) with
  * the triangular solves by the same levels, one workgroup per graph, and
  * the whole solve in one persistent launch as PERSISTENT; same limits as
- * PERSISTENT (at most 6144 unknowns per graph, fixed damping).  Not chosen
- * by AUTO. */
+ * PERSISTENT (at most 6144 unknowns per graph, fixed damping). */
 typedef enum {
   DNLS_SPSOLVE_AUTO = 0,
   DNLS_SPSOLVE_WORKGROUP = 1,

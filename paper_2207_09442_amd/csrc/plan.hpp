@@ -145,7 +145,9 @@ struct dnls_plan_s {
   int* d_lvlptr = nullptr;        // BLOCK: columns of each level ([lvl_off + L] .. [+1] into d_lvlcol)
   int* d_lvlcol = nullptr;
   int* d_lvlbptr = nullptr;       // BLOCK: factor blocks of each level's columns (into d_lvlblk)
-  int2* d_lvlblk = nullptr;       //   (tile row I, tile column J), diagonal blocks included
+  int4* d_lvlblk = nullptr;       //   (tile id, update pairs [first, end) in d_cpair, 2 J + diagonal)
+  int2* d_cpair = nullptr;        // BLOCK: (L_IK, L_JK) tile ids of the left-looking updates
+  int* d_rowid = nullptr;         // BLOCK: tile id of every row-structure entry
   int sp_grid = 0;                // its workgroups: min(B, resident slots)
   int* d_sp_order = nullptr;      // its queue order: graphs by decreasing factor work
   unsigned* d_sp_queue = nullptr; // its two queue counters (self-resetting)

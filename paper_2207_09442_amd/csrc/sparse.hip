@@ -87,8 +87,10 @@ struct SpArgs {
   double* traj;            // persistent schedule with DNLS_FLAG_KEEP_ITERATES: theta_t, [K][V][sz]
   const int* lvlptr;       // BLOCK: columns of each elimination-tree level, [lvl_off + L] .. [+1] into lvlcol
   const int* lvlcol;
-  const int* lvlbptr;      // BLOCK: factor blocks (I, J) of each level's columns, into lvlblk
-  const int2* lvlblk;
+  const int* lvlbptr;      // BLOCK: factor blocks of each level's columns, into lvlblk
+  const int4* lvlblk;      //   (tile id, first and end contribution in cpair, 2 J + diagonal)
+  const int2* cpair;       // BLOCK: the (L_IK, L_JK) tile-id pairs that update each level block
+  const int* rowid;        // BLOCK: tile id of every (I, rowcol) entry
   int ts;                  // tile size: kTS (48) or the pose dimension d (BLOCK)
   // bundle adjustment (points eliminated first inside the tile factorisation)
   double* pts;             // [Vp][3]
@@ -1308,20 +1310,18 @@ __device__ bool sb_factor_body(const SpArgs& a, int b, const SpDesc& g, int* fla
   for (int L = 0; L < g.nlvl; ++L) {
     // A. left-looking gather of the level's blocks
     const int b0 = a.lvlbptr[g.lvl_off + L], b1 = a.lvlbptr[g.lvl_off + L + 1];
+    double* pool = a.factor + g.pool_off;
     for (int u = threadIdx.x; u < (b1 - b0) * tt; u += NT) {
-      const int2 ij = a.lvlblk[b0 + u / tt];
+      const int4 t = a.lvlblk[b0 + u / tt];
       const int e = u % tt, r = e / ts, c = e % ts;
-      const int I = ij.x, J = ij.y;
-      if (I == J && c > r) continue;
-      double* T = tile_ptr(a, g, I, J);
+      if ((t.w & 1) && c > r) continue;
+      double* T = pool + (size_t)t.x * tt;
       double acc = T[e];
-      const int k0 = a.rowptr[g.row_off + J], k1 = a.rowptr[g.row_off + J + 1];
-      for (int k = k0; k < k1; ++k) {
-        const int K = a.rowcol[k];
-        const int id = a.tix[g.tix_off + I * g.P + K];
-        if (id < 0) continue;
-        const double* LI = a.factor + g.pool_off + (size_t)id * tt + r * ts;
-        const double* LJ = tile_ptr(a, g, J, K) + c * ts;
+#pragma unroll 4
+      for (int k = t.y; k < t.z; ++k) {
+        const int2 pr = a.cpair[k];
+        const double* LI = pool + (size_t)pr.x * tt + r * ts;
+        const double* LJ = pool + (size_t)pr.y * tt + c * ts;
 #pragma unroll
         for (int q = 0; q < ts; ++q) acc -= LI[q] * LJ[q];
       }
@@ -1334,7 +1334,7 @@ __device__ bool sb_factor_body(const SpArgs& a, int b, const SpDesc& g, int* fla
     __syncthreads();
     for (int u = c0 + (int)threadIdx.x; u < c1; u += NT) {
       const int J = a.lvlcol[u];
-      double* T = tile_ptr(a, g, J, J);
+      double* T = pool + (size_t)(a.colptr[g.col_off + J] - a.colptr[g.col_off]) * tt;
       double l[D][D], w[D][D];
       bool ok = true;
 #pragma unroll
@@ -1392,11 +1392,11 @@ __device__ bool sb_factor_body(const SpArgs& a, int b, const SpDesc& g, int* fla
     }
     // C. L_IJ <- L_IJ W_J^T below the diagonal, one thread per block row
     for (int u = threadIdx.x; u < (b1 - b0) * ts; u += NT) {
-      const int2 ij = a.lvlblk[b0 + u / ts];
-      if (ij.x == ij.y) continue;
+      const int4 t = a.lvlblk[b0 + u / ts];
+      if (t.w & 1) continue;
       const int r = u % ts;
-      double* row = tile_ptr(a, g, ij.x, ij.y) + r * ts;
-      const double* W = a.factor + g.winv_off + (size_t)ij.y * tt;
+      double* row = pool + (size_t)t.x * tt + r * ts;
+      const double* W = a.factor + g.winv_off + (size_t)(t.w >> 1) * tt;
       double x[D], y[D];
 #pragma unroll
       for (int q = 0; q < ts; ++q) x[q] = row[q];
@@ -1419,6 +1419,7 @@ __device__ bool sb_factor_body(const SpArgs& a, int b, const SpDesc& g, int* fla
 template <int NT, int D>
 __device__ void sb_solve_body(const SpArgs& a, const SpDesc& g, int src, int dst, double* v) {
   constexpr int ts = D, tt = D * D;
+  const double* pool = a.factor + g.pool_off;
   const double* bsrc = slot(a, g, src);
   for (int u = threadIdx.x; u < g.nvec; u += NT) v[u] = bsrc[u];
   __syncthreads();
@@ -1428,9 +1429,10 @@ __device__ void sb_solve_body(const SpArgs& a, const SpDesc& g, int src, int dst
     for (int u = threadIdx.x; u < (c1 - c0) * ts; u += NT) {
       const int J = a.lvlcol[c0 + u / ts], r = u % ts;
       double acc = v[J * ts + r];
+#pragma unroll 4
       for (int k = a.rowptr[g.row_off + J]; k < a.rowptr[g.row_off + J + 1]; ++k) {
         const int K = a.rowcol[k];
-        const double* row = tile_ptr(a, g, J, K) + r * ts;
+        const double* row = pool + (size_t)a.rowid[k] * tt + r * ts;
 #pragma unroll
         for (int q = 0; q < ts; ++q) acc -= row[q] * v[K * ts + q];
       }
@@ -1459,9 +1461,10 @@ __device__ void sb_solve_body(const SpArgs& a, const SpDesc& g, int src, int dst
     for (int u = threadIdx.x; u < (c1 - c0) * ts; u += NT) {
       const int J = a.lvlcol[c0 + u / ts], r = u % ts;
       double acc = v[J * ts + r];
+#pragma unroll 4
       for (int k = a.colptr[g.col_off + J] + 1; k < a.colptr[g.col_off + J + 1]; ++k) {
         const int I = a.rowidx[k];
-        const double* T = tile_ptr(a, g, I, J);
+        const double* T = pool + (size_t)(k - a.colptr[g.col_off]) * tt;
 #pragma unroll
         for (int q = 0; q < ts; ++q) acc -= T[q * ts + r] * v[I * ts + q];
       }
@@ -2074,7 +2077,17 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   p->sd.resize(B);
   long long fac = 0, vecoff = 0;
   int maxP = 0;
-  // tile size: 48 (three 16-wide MFMA tiles) or, for BLOCK, the pose blocks themselves
+  // tile size: 48 (three 16-wide MFMA tiles) or, for BLOCK, the pose blocks
+  // themselves.  AUTO takes BLOCK for float64 fixed-damping plans whose
+  // graphs fit one workgroup's solve but exceed 16 tile columns (measured on
+  // the 256-walk batch: 27 ms per step against 30 ms for HYBRID; with mixed
+  // precision the refinement sweeps' level-by-level solves make it slower)
+  int maxP48 = 0;
+  for (int b = 0; b < B; ++b) maxP48 = std::max(maxP48, ((pr->pose_off[b + 1] - pr->pose_off[b]) * d + kTS - 1) / kTS);
+  const bool auto_block = p->opt.sparse_solve == DNLS_SPSOLVE_AUTO && maxP48 * kTS <= kSolveLds &&
+                          maxP48 > kFactorWgMaxP && p->opt.precision == DNLS_PREC_FP64 &&
+                          !(p->opt.flags & (DNLS_FLAG_ADAPTIVE_LM | DNLS_FLAG_DOGLEG));
+  if (auto_block) p->opt.sparse_solve = DNLS_SPSOLVE_BLOCK;
   const int tsz = p->opt.sparse_solve == DNLS_SPSOLVE_BLOCK ? d : kTS;
   const long long tt = (long long)tsz * tsz;
   p->sp_ts = tsz;
@@ -2171,8 +2184,9 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   }
   // BLOCK: elimination-tree levels of every graph (a column's parent is its
   // first off-diagonal row; level = 1 + the highest level of its children)
-  std::vector<int> lvlptr, lvlcol, lvlbptr;
-  std::vector<int2> lvlblk;
+  std::vector<int> lvlptr, lvlcol, lvlbptr, rowid;
+  std::vector<int4> lvlblk;
+  std::vector<int2> cpair;
   if (tsz != kTS) {
     for (int b = 0; b < B; ++b) {
       SpDesc& g = p->sd[b];
@@ -2190,17 +2204,36 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
       g.nlvl = nl;
       std::vector<std::vector<int>> cols(nl);
       for (int J = 0; J < g.P; ++J) cols[lev[J]].push_back(J);
+      // every block (I, J) of a level's columns with the tile-id pairs
+      // (L_IK, L_JK), K < J, of its left-looking update
+      const int base = colptr[g.col_off];
+      auto tid = [&](int I, int J) { return tix[g.tix_off + (size_t)I * g.P + J]; };
       for (int L = 0; L < nl; ++L) {
         lvlptr.push_back((int)lvlcol.size());
         lvlbptr.push_back((int)lvlblk.size());
         for (int J : cols[L]) {
           lvlcol.push_back(J);
-          for (int k = colptr[g.col_off + J]; k < colptr[g.col_off + J + 1]; ++k)
-            lvlblk.push_back(int2{rowidx[k], J});
+          for (int k = colptr[g.col_off + J]; k < colptr[g.col_off + J + 1]; ++k) {
+            const int I = rowidx[k];
+            const int c0 = (int)cpair.size();
+            for (int q = rowptr[g.row_off + J]; q < rowptr[g.row_off + J + 1]; ++q) {
+              const int K = rowcol[q], ik = tid(I, K);
+              if (ik >= 0) cpair.push_back(int2{ik, tid(J, K)});
+            }
+            lvlblk.push_back(int4{k - base, c0, (int)cpair.size(), 2 * J + (I == J ? 1 : 0)});
+          }
         }
       }
       lvlptr.push_back((int)lvlcol.size());
       lvlbptr.push_back((int)lvlblk.size());
+    }
+    // tile id of every row-structure entry (I, rowcol) for the forward solve
+    rowid.resize(rowcol.size());
+    for (int b = 0; b < B; ++b) {
+      const SpDesc& g = p->sd[b];
+      for (int I = 0; I < g.P; ++I)
+        for (int q = rowptr[g.row_off + I]; q < rowptr[g.row_off + I + 1]; ++q)
+          rowid[q] = tix[g.tix_off + (size_t)I * g.P + rowcol[q]];
     }
   }
   // per tile column: the widest column and pair count over the batch
@@ -2275,7 +2308,9 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
     return st;
   if (tsz != kTS &&
       ((st = upload(p, &p->d_lvlptr, lvlptr)) != DNLS_OK || (st = upload(p, &p->d_lvlcol, lvlcol)) != DNLS_OK ||
-       (st = upload(p, &p->d_lvlbptr, lvlbptr)) != DNLS_OK || (st = upload(p, &p->d_lvlblk, lvlblk)) != DNLS_OK))
+       (st = upload(p, &p->d_lvlbptr, lvlbptr)) != DNLS_OK || (st = upload(p, &p->d_lvlblk, lvlblk)) != DNLS_OK ||
+       (st = upload(p, &p->d_cpair, cpair.empty() ? std::vector<int2>{int2{0, 0}} : cpair)) != DNLS_OK ||
+       (st = upload(p, &p->d_rowid, rowid.empty() ? std::vector<int>{0} : rowid)) != DNLS_OK))
     return st;
   const size_t ncost = (size_t)p->E + p->P;
   const size_t rn = 2 * (size_t)d * d + d;
@@ -2621,6 +2656,8 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.lvlcol = p->d_lvlcol;
   a.lvlbptr = p->d_lvlbptr;
   a.lvlblk = p->d_lvlblk;
+  a.cpair = p->d_cpair;
+  a.rowid = p->d_rowid;
   a.E = p->E;
   a.K = p->opt.iterations;
   a.nx = p->nlin_blocks;

@@ -83,6 +83,8 @@ def oracle_grad_spread(g, res, v, pose_rel, seed=0):
 def gpu_solve(p, K, lam, precision="fp64", refine=0, tau=None, solver="dense", adaptive=False, dogleg=None,
               refine_last=0, pair=False, sparse_solve="auto"):
     from paper_2207_09442_amd import Plan
+    if solver == "sparse-block":          # the block-sparse solver's BLOCK schedule
+        solver, sparse_solve = "sparse", "block"
     plan = Plan(p, K, lam=lam, solver=solver, precision=precision, refine=refine, device=DEV, adaptive=adaptive,
                 dogleg=dogleg, refine_last=refine_last, pair=pair, sparse_solve=sparse_solve)
     poses = t(p["poses_init"])

@@ -77,7 +77,7 @@ def _dlm_parity(p, tau, K, lam, eps, precision="fp64", refine=0, graphs=None, so
     return plan, poses, status, dev
 
 
-@pytest.mark.parametrize("solver", ["dense", "sparse"])
+@pytest.mark.parametrize("solver", ["dense", "sparse", "sparse-block"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
 @pytest.mark.parametrize("eps", [1e-3, 0.3])
 def test_dlm_matches_oracle_ragged_batch(group, eps, solver):

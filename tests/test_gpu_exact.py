@@ -65,7 +65,7 @@ def _errors(p, tau, plan, poses, status, dev, seed, gr, graphs):
     return out
 
 
-@pytest.mark.parametrize("solver", ["dense", "sparse"])
+@pytest.mark.parametrize("solver", ["dense", "sparse", "sparse-block"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
 def test_exact_backward_matches_oracle_ragged_batch(group, solver):
     p, tau = _problem(group, seed=41)

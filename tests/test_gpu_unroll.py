@@ -38,8 +38,8 @@ def _problem(group, seed):
 
 def _unroll(p, tau, K, lam, steps=None, precision="fp64", refine=0, graphs=None, tol_floor=1e-10, solver="dense"):
     from paper_2207_09442_amd import Plan
-    plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device="cuda", keep_iterates=True,
-                solver=solver)
+    kw = dict(solver="sparse", sparse_solve="block") if solver == "sparse-block" else dict(solver=solver)
+    plan = Plan(p, K, lam=lam, precision=precision, refine=refine, device="cuda", keep_iterates=True, **kw)
     poses = t(p["poses_init"])
     dev = dict(edge_meas=t(p["edge_meas"]), edge_logw=t(p["edge_logw"]), prior_meas=t(p["prior_meas"]),
                prior_logw=t(p["prior_logw"]), edge_tau=None if tau is None else t(tau))
@@ -78,7 +78,7 @@ def _unroll(p, tau, K, lam, steps=None, precision="fp64", refine=0, graphs=None,
     return worst
 
 
-@pytest.mark.parametrize("solver", ["dense", "sparse"])
+@pytest.mark.parametrize("solver", ["dense", "sparse", "sparse-block"])
 @pytest.mark.parametrize("group", ["SE2", "SE3"])
 def test_unrolled_matches_oracle_ragged_batch(group, solver):
     p, tau = _problem(group, seed=51)
