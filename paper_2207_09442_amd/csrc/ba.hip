@@ -272,7 +272,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// 3. Schur complement S (lower blocks, all) and g_s into the augmented row.
+// 3. Schur complement S (lower blocks, all) and g_s into the right-hand-side row.
 // One wave per camera-pair block: the lanes split the block's contribution
 // list (observations of the camera for a diagonal block, point-sharing
 // observation pairs for every block), then a butterfly sum.
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(kBT) k_ba_schur(BAArgs a, double lambda) {
   double* A = a.factor + g.fac_off;
   const int npad = g.npad;
   const S* rec = reinterpret_cast<const S*>(a.orec);
-  // padding rows and the augmented tile
+  // padding rows, the right-hand-side row and the padding rows after it
   if (blockIdx.x == 0) {
     for (int e = threadIdx.x; e < (npad - g.n) * npad; e += kBT) {
       const int r = g.n + e / npad, c = e % npad;

@@ -3,12 +3,13 @@
 // that reuse the factor.
 //
 // Storage: row-major, leading dimension npad (a multiple of 64), only the
-// lower triangle is read.  The buffer has 16 extra rows (row tile "T16"): row
-// npad holds the right-hand side b^T, so the factorisation also produces
-// y = L^-1 b in that row (the forward substitution rides along as an
-// augmented row).  After chol_dense the lower triangle holds L, and
-// winv[J] (64 x 64 row-major per panel) holds L_JJ^-1 of every diagonal
-// 64 x 64 block.
+// lower triangle is read.  The buffer has 16 extra rows: row npad holds the
+// right-hand side b^T, and the factorisation writes y = L^-1 b into row npad
+// of the factor (the forward substitution rides along: the diagonal group of
+// each panel forms b_J - sum_k L_Jk y_k from the panel rows it stages
+// anyway, and y_J = L_JJ^-1 of that); rows npad + 1 .. npad + 15 are padding.
+// After chol_dense the lower triangle holds L, and winv[J] (64 x 64 row-major
+// per panel) holds L_JJ^-1 of every diagonal 64 x 64 block.
 //
 // MFMA f64 16x16x4 operand layouts (lane l, lq = l / 16, lm = l % 16):
 //   A (16 x 4): lane supplies A[lm][k]     B (4 x 16): lane supplies B[k][lm]
@@ -217,6 +218,43 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
   return ok;
 }
 
+// Forward substitution of the diagonal group, three pieces.  The thread
+// (srow, scol) of the chunk staging holds L_J[srow][k + scol .. + 15] of the
+// chunk at column k in st; y[0 : 64 J] sits flat in LDS at y.
+__device__ __forceinline__ double ydot16(const d4v st[4], const double* y) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const d4v w = *reinterpret_cast<const d4v*>(y + 4 * q);
+    v = __builtin_fma(st[q][0], w[0], v);
+    v = __builtin_fma(st[q][1], w[1], v);
+    v = __builtin_fma(st[q][2], w[2], v);
+    v = __builtin_fma(st[q][3], w[3], v);
+  }
+  return v;
+}
+
+// sum of v over the four threads of a staging row (lanes 4 r .. 4 r + 3)
+__device__ __forceinline__ double row4_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+
+// y_J = L_JJ^-1 t (W = L_JJ^-1 at stride kSP, lower part; t = s.vec) written
+// to y[col0 ..]: thread (srow, scol) takes 16 columns, four threads a row.
+__device__ __forceinline__ void ypanel(const double* W, const double* t, double* y, int col0) {
+  const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  double v = 0.0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int c = scol + e;
+    v += (c <= srow) ? W[srow * kSP + c] * t[c] : 0.0;
+  }
+  v = row4_sum(v);
+  if ((threadIdx.x & 3) == 0) y[col0 + srow] = v;
+}
+
 // Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix H
 // (row npad = right-hand side; lower part read) into L (same layout; L may
 // be H itself): on return L holds the factor and y = L^-1 b in row npad,
@@ -226,9 +264,11 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
 __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad, double* __restrict__ winv, DenseLds& s) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
-  const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
+  const int T16 = npad >> 4;          // row tiles of the matrix
   const int P = npad / kNB;
   const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  const double* hb = H + (size_t)npad * npad;   // b
+  double* yrow = A + (size_t)npad * npad;       // y = L^-1 b
   bool ok = true;
   // the next group's H tile (transposed accumulator layout) and chunk 0 of
   // its own rows, loaded while the current group finishes (its triangular
@@ -236,66 +276,66 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
   d4v acc_n[4], bop_n[4];
   auto prefetch = [&](int J, int i0n) {
     const int in = i0n + wave, col0 = kNB * J;
-    const bool act = in <= T16;
     const double* Hr = H + (size_t)(16 * in + lm) * npad;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc_n[c][r] = act ? Hr[col0 + 16 * c + lq + 4 * r] : 0.0;
+      for (int r = 0; r < 4; ++r) acc_n[c][r] = Hr[col0 + 16 * c + lq + 4 * r];
     if (J > 0) {
       const double* Ar = A + (size_t)(16 * in + lm) * npad;
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt)
-        bop_n[kt] = act ? *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+      for (int kt = 0; kt < 4; ++kt) bop_n[kt] = *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq);
     }
   };
   prefetch(0, 0);
   for (int J = 0; J < P; ++J) {
     const int col0 = kNB * J;
     const int nchunk = J;             // k chunks of 64 columns
-    for (int i0 = 4 * J; i0 <= T16; i0 += kNW) {
+    for (int i0 = 4 * J; i0 < T16; i0 += kNW) {
       const int i = i0 + wave;
-      const bool active = i <= T16;
       const double* Arow = A + (size_t)(16 * i + lm) * npad;
-      // the last group of a panel is the augmented-row tile (T16 = 4 P), so
-      // the diagonal group always has a successor in its own panel
-      const bool last_group = i0 + kNW > T16;
+      const bool diag = i0 == 4 * J;
+      const bool last_group = i0 + kNW >= T16;
       // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
       d4v acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
+      // diagonal group: sum_k L_Jk y_k (this thread's row srow, 16 columns of each chunk)
+      double ypart = 0.0;
       if (nchunk > 0) {
         d4v st[4], bop[4], bnx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
+        // y of the panels before J, flat in W (L_{J-1,J-1}^-1 is no longer needed)
+        if (diag)
+          for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
 #pragma unroll
         for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
         __syncthreads();
         for (int ch = 0; ch < nchunk; ++ch) {
           const bool more = ch + 1 < nchunk;
+          const int k1 = kNB * (ch + 1);
+          // st still holds this thread's part of chunk ch
+          if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
           if (more) {
-            const int k1 = kNB * (ch + 1);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + k1 + scol + 4 * q);
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-              bnx[kt] = active ? *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+            for (int kt = 0; kt < 4; ++kt) bnx[kt] = *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq);
           }
           const double* buf = s.stage[ch & 1];
-          if (active) {
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) {
-              d4v aop[4];
+          for (int kt = 0; kt < 4; ++kt) {
+            d4v aop[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+            for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
-            }
+              for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
           }
           if (more) {
 #pragma unroll
@@ -307,7 +347,10 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
           __syncthreads();
         }
       }
-      if (i0 == 4 * J) {
+      if (diag) {
+        // t = b_J - sum_k L_Jk y_k for the forward substitution
+        ypart = row4_sum(ypart);
+        if ((threadIdx.x & 3) == 0) s.vec[srow] = hb[col0 + srow] - ypart;
         // the diagonal block: factor in LDS
         double* D = s.stage[0];
 #pragma unroll
@@ -317,30 +360,29 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
         __syncthreads();
         if (!chol_block<4>(D, s.W, s)) ok = false;
         if (!last_group) prefetch(J, i0 + kNW);
-        // write L_JJ (zero above the diagonal) and its inverse
+        // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
           A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
           winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
+        ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
       } else {
         // the next group's loads (H, and L of panels before J) overlap this
         // group's triangular solve, which writes panel J only
         if (!last_group) prefetch(J, i0 + kNW);
-        if (active) {
-          // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
+        // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
-          for (int cn = 0; cn < 4; ++cn) {
-            d4v out = {0.0, 0.0, 0.0, 0.0};
+        for (int cn = 0; cn < 4; ++cn) {
+          d4v out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kt = 0; kt <= cn; ++kt) {
+          for (int kt = 0; kt <= cn; ++kt) {
 #pragma unroll
-              for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
+            for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
         }
       }
     }
@@ -423,9 +465,11 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
                                                 DenseLds& s, const PairSync& ps, int f, bool& bail) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
-  const int T16 = npad >> 4;          // row tiles of the matrix; tile T16 is the augmented row
+  const int T16 = npad >> 4;          // row tiles of the matrix
   const int P = npad / kNB;
   const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  const double* hb = H + (size_t)npad * npad;   // b
+  double* yrow = A + (size_t)npad * npad;       // y = L^-1 b (the leader's)
   bool ok = true;
   // the next group's H tile (transposed accumulator layout) and chunk 0 of
   // its own rows, loaded while the current group finishes (its triangular
@@ -433,69 +477,71 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
   d4v acc_n[4], bop_n[4];
   auto prefetch = [&](int J, int i0n) {
     const int in = i0n + wave, col0 = kNB * J;
-    const bool act = in <= T16;
     const double* Hr = H + (size_t)(16 * in + lm) * npad;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc_n[c][r] = act ? Hr[col0 + 16 * c + lq + 4 * r] : 0.0;
+      for (int r = 0; r < 4; ++r) acc_n[c][r] = Hr[col0 + 16 * c + lq + 4 * r];
     if (J > 0) {
       const double* Ar = A + (size_t)(16 * in + lm) * npad;
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt)
-        bop_n[kt] = act ? *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+      for (int kt = 0; kt < 4; ++kt) bop_n[kt] = *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq);
     }
   };
   // this role's row groups of a panel: every nway-th group of 4 row tiles,
   // the leader's starting with the diagonal group
   const int first = ps.role * kNW, stride = ps.nway * kNW;
   const unsigned long long fbase = ps.base + (unsigned long long)f * P;
-  prefetch(0, first);
+  if (first < T16) prefetch(0, first);
   for (int J = 0; J < P; ++J) {
     const int col0 = kNB * J;
     const int nchunk = J;             // k chunks of 64 columns
     bool have_w = ps.role == 0;       // the leader factors the diagonal block itself
-    for (int i0 = 4 * J + first; i0 <= T16; i0 += stride) {
+    for (int i0 = 4 * J + first; i0 < T16; i0 += stride) {
       const int i = i0 + wave;
-      const bool active = i <= T16;
       const double* Arow = A + (size_t)(16 * i + lm) * npad;
-      const bool last_group = i0 + stride > T16;
+      const bool diag = i0 == 4 * J;
+      const bool last_group = i0 + stride >= T16;
       // transposed accumulators: acc[c][r] = D[lm][16 c + lq + 4 r] for tile (i, J)
       d4v acc[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
+      // diagonal group: sum_k L_Jk y_k (this thread's row srow, 16 columns of each chunk)
+      double ypart = 0.0;
       if (nchunk > 0) {
         d4v st[4], bop[4], bnx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
+        // y of the panels before J, flat in W (L_{J-1,J-1}^-1 is no longer needed)
+        if (diag)
+          for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
 #pragma unroll
         for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
         __syncthreads();
         for (int ch = 0; ch < nchunk; ++ch) {
           const bool more = ch + 1 < nchunk;
+          const int k1 = kNB * (ch + 1);
+          // st still holds this thread's part of chunk ch
+          if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
           if (more) {
-            const int k1 = kNB * (ch + 1);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + k1 + scol + 4 * q);
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-              bnx[kt] = active ? *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq) : d4v{0.0, 0.0, 0.0, 0.0};
+            for (int kt = 0; kt < 4; ++kt) bnx[kt] = *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq);
           }
           const double* buf = s.stage[ch & 1];
-          if (active) {
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) {
-              d4v aop[4];
+          for (int kt = 0; kt < 4; ++kt) {
+            d4v aop[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+            for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
-            }
+              for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
           }
           if (more) {
 #pragma unroll
@@ -507,7 +553,10 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
           __syncthreads();
         }
       }
-      if (i0 == 4 * J) {
+      if (diag) {
+        // t = b_J - sum_k L_Jk y_k for the forward substitution
+        ypart = row4_sum(ypart);
+        if ((threadIdx.x & 3) == 0) s.vec[srow] = hb[col0 + srow] - ypart;
         // the diagonal block: factor in LDS
         double* D = s.stage[0];
 #pragma unroll
@@ -517,12 +566,13 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         __syncthreads();
         if (!chol_block<4>(D, s.W, s)) ok = false;
         if (!last_group) prefetch(J, i0 + stride);
-        // write L_JJ (zero above the diagonal) and its inverse
+        // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
           A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
           winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
+        ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
         pair_post(ps.lead_diag, fbase + J + 1);
       } else {
@@ -539,19 +589,17 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         // the next group's loads (H, and L of panels before J) overlap this
         // group's triangular solve, which writes panel J only
         if (!last_group) prefetch(J, i0 + stride);
-        if (active) {
-          // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
+        // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
-          for (int cn = 0; cn < 4; ++cn) {
-            d4v out = {0.0, 0.0, 0.0, 0.0};
+        for (int cn = 0; cn < 4; ++cn) {
+          d4v out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int kt = 0; kt <= cn; ++kt) {
+          for (int kt = 0; kt <= cn; ++kt) {
 #pragma unroll
-              for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
+            for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
         }
       }
     }
@@ -563,7 +611,7 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         bail = true;
         return false;
       }
-    if (J + 1 < P && 4 * (J + 1) + first <= T16) prefetch(J + 1, 4 * (J + 1) + first);
+    if (J + 1 < P && 4 * (J + 1) + first < T16) prefetch(J + 1, 4 * (J + 1) + first);
   }
   return ok;
 }

@@ -132,7 +132,8 @@ __device__ double objective_graph(const DenseArgs& a, const GraphDesc& g, double
 }
 
 // Once per solve: zero every row of H up to the end of its 64-wide diagonal
-// block (the part the factorisation reads) and the augmented tile, and put
+// block (the part the factorisation reads) and the right-hand-side row with
+// the padding rows after it, and put
 // 1 on the diagonal of the padding.  The assembly then rewrites only the
 // structurally non-zero blocks, so the zeros persist across iterations.
 __device__ void init_H(const GraphDesc& g, double* A) {
@@ -208,7 +209,7 @@ __device__ void assemble_H(const DenseArgs& a, const GraphDesc& g, const S* rec,
 }
 
 // b[p*d + r] = sum over incident costs of J^T (w c), zero on the padding;
-// with aug != nullptr also written to the augmented row of the matrix.
+// with aug != nullptr also written to the right-hand-side row of the matrix.
 template <int G, class S>
 __device__ void assemble_g(const DenseArgs& a, const GraphDesc& g, const S* rec, double* b, double* aug) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
@@ -406,7 +407,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       break;
     }
     if (final_lin) break;
-    // delta = L^-T y with y = L^-1 g from the augmented row
+    // delta = L^-T y with y = L^-1 g from the right-hand-side row
     for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
     __syncthreads();
     trsv_upper_t(A, g.npad, winv, vb, L.dl);
@@ -1132,7 +1133,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     hsz += (long long)(g.npad + 16) * g.npad;
     g.dlm_winv_off = dlmw;
     dlmw += (long long)(g.npad / kNB) * kNB * kNB;
-    // L (npad x npad) + augmented right-hand-side tile (16 x npad) + panel inverses
+    // L (npad x npad) + right-hand-side row and 15 padding rows (16 x npad) + panel inverses
     fac += (long long)(g.npad + 16) * g.npad + (long long)(g.npad / kNB) * kNB * kNB;
     fac = (fac + 31) / 32 * 32;
     p->npad_max = std::max(p->npad_max, g.npad);
