@@ -112,16 +112,20 @@ __device__ __forceinline__ double bcast16(double v, int q) {
 }
 
 // Cholesky factor and inverse of the 16x16 SPD tile at t (stride ldt, lower
-// part read) on one wave: lane i (i = lane % 16) owns row i; the column
-// values each step needs are broadcast within the 16-lane row by DPP.
-// Entries above the diagonal are carried along unmasked (they never feed the
-// lower part) and cleared at the end.  The inverse is formed from unscaled
-// rows y_i = e_i - sum_{k<i} (L_ik / L_kk) y_k, then L^-1 row i = y_i / L_ii,
-// reusing 1/L_kk from the factorisation.  Writes L (upper part zero) back to
-// t and L^-1 to w.  Returns false if a pivot is not positive (NaN included).
+// part read) on one wave: lane i (i = lane % 16) of each 16-lane row owns
+// row i; the column values each step needs are broadcast within the 16-lane
+// row by DPP.  The factorisation runs in all four rows alike; entries above
+// the diagonal are carried along unmasked (they never feed the lower part)
+// and cleared at the end.  The inverse is formed from unscaled rows
+// y_i = e_i - sum_{k<i} (L_ik / L_kk) y_k, then L^-1 row i = y_i / L_ii,
+// reusing 1/L_kk from the factorisation; its columns are dealt to the four
+// rows (row g takes the columns 4 m + g; entries right of the diagonal of
+// every y_k are zero, so all four columns take every step).  Writes L (upper
+// part zero) back to t and L^-1 to w.  Returns false if a pivot is not
+// positive (NaN included).
 __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int ldw) {
   const int lane = threadIdx.x & 63;
-  const int i = lane & 15;
+  const int i = lane & 15, g = lane >> 4;
   double a[16], rdv[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) a[q] = t[i * ldt + q];
@@ -139,81 +143,87 @@ __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int l
 #pragma unroll
     for (int q = p + 1; q < 16; ++q) a[q] = __builtin_fma(-lip, bcast16(lip, q), a[q]);
   }
-  double y[16];
+  double y[4];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) y[c] = (c == i) ? 1.0 : 0.0;
+  for (int m = 0; m < 4; ++m) y[m] = (4 * m + g == i) ? 1.0 : 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const double coef = (k < i) ? a[k] * rdv[k] : 0.0;
 #pragma unroll
-    for (int c = 0; c <= k; ++c) y[c] = __builtin_fma(-coef, bcast16(y[c], k), y[c]);
+    for (int m = 0; m < 4; ++m) y[m] = __builtin_fma(-coef, bcast16(y[m], k), y[m]);
   }
   if (lane < 16) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      t[i * ldt + q] = (q > i) ? 0.0 : a[q];
-      w[i * ldw + q] = y[q] * myrd;
-    }
+    for (int q = 0; q < 16; ++q) t[i * ldt + q] = (q > i) ? 0.0 : a[q];
   }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) w[i * ldw + 4 * m + g] = y[m] * myrd;
   return ok;
 }
 
 // Factor the (16 NBLK)^2 diagonal block D (LDS, stride kSP, lower part read)
-// in place into L_JJ, and its inverse into W (stride kSP).  All threads of a
-// workgroup of at least NBLK waves call.
+// in place into L_JJ, and its inverse into W (stride kSP, lower blocks).  All
+// threads of a workgroup of at least four waves call (NBLK <= 4).  Per block
+// column b: the waves form L_rb = D_rb W_bb^T (r > b) and, on the waves left
+// over, the inverse blocks of row b, W_bc = -W_bb sum_{k=c}^{b-1} L_bk W_kc
+// (c < b); then wave 0 updates D_{b+1,b+1} and factors it while the other
+// waves update the rest of the trailing blocks, D_rc -= L_rb L_cb^T.  Two
+// barriers per block column.
 template <int NBLK>
 __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
   const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
   const int nw = blockDim.x >> 6;
+  auto dblk = [&](int r, int c) { return D + 16 * r * kSP + 16 * c; };
+  auto wblk = [&](int r, int c) { return W + 16 * r * kSP + 16 * c; };
   bool ok = true;
-  for (int b = 0; b < NBLK; ++b) {
-    double* Dbb = D + 16 * b * kSP + 16 * b;
-    if (wave == 0) {
-      const bool okb = chol16_wave(Dbb, kSP, W + 16 * b * kSP + 16 * b, kSP);
-      if (lane == 0) s.flag = okb ? 0 : 1;
-    }
-    __syncthreads();
-    if (s.flag) ok = false;
-    // L_rb = D_rb W_bb^T for r > b
-    {
-      const int r = b + 1 + wave;
-      if (r < NBLK) {
-        d4v acc = {0.0, 0.0, 0.0, 0.0};
-        mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, W + 16 * b * kSP + 16 * b, kSP, 1.0);
-        store_tile(D + 16 * r * kSP + 16 * b, kSP, acc);
-      }
-    }
-    __syncthreads();
-    // trailing update D_rc -= L_rb L_cb^T, b < c <= r < 4
-    {
-      int idx = 0;
-      for (int r = b + 1; r < NBLK; ++r)
-        for (int c = b + 1; c <= r; ++c, ++idx)
-          if ((idx % nw) == wave) {
-            d4v acc = load_tile(D + 16 * r * kSP + 16 * c, kSP);
-            mma_abt(acc, D + 16 * r * kSP + 16 * b, kSP, D + 16 * c * kSP + 16 * b, kSP, -1.0);
-            store_tile(D + 16 * r * kSP + 16 * c, kSP, acc);
-          }
-    }
-    __syncthreads();
+  if (wave == 0) {
+    const bool okb = chol16_wave(dblk(0, 0), kSP, wblk(0, 0), kSP);
+    if (lane == 0) s.flag = okb ? 0 : 1;
   }
-  // off-diagonal blocks of the inverse, by distance from the diagonal:
-  // W_rc = -W_rr sum_{k=c}^{r-1} L_rk W_kc
-  for (int dl = 1; dl < NBLK; ++dl) {
-    const int c = wave, r = c + dl;
-    d4v t = {0.0, 0.0, 0.0, 0.0};
-    if (r < NBLK)
-      for (int k = c; k < r; ++k) mma_ab(t, D + 16 * r * kSP + 16 * k, kSP, W + 16 * k * kSP + 16 * c, kSP, 1.0);
-    // stage T in the (still unused) upper triangle of D: block (c, r)
-    if (r < NBLK) store_tile(D + 16 * c * kSP + 16 * r, kSP, t);
-    __syncthreads();
-    if (r < NBLK) {
+  __syncthreads();
+  for (int b = 0; b < NBLK; ++b) {
+    if (s.flag) ok = false;
+    const int ntr = NBLK - 1 - b;   // blocks below the diagonal in column b
+    if (wave < ntr) {
+      const int r = b + 1 + wave;
       d4v acc = {0.0, 0.0, 0.0, 0.0};
-      mma_ab(acc, W + 16 * r * kSP + 16 * r, kSP, D + 16 * c * kSP + 16 * r, kSP, -1.0);
-      store_tile(W + 16 * r * kSP + 16 * c, kSP, acc);
+      mma_abt(acc, dblk(r, b), kSP, wblk(b, b), kSP, 1.0);
+      store_tile(dblk(r, b), kSP, acc);
+    } else if (wave - ntr < b) {
+      const int c = wave - ntr;
+      d4v tt = {0.0, 0.0, 0.0, 0.0};
+      for (int k = c; k < b; ++k) mma_ab(tt, dblk(b, k), kSP, wblk(k, c), kSP, 1.0);
+      // -W_bb T with T in the accumulator layout as the B operand: lane
+      // (lm, lq) holds T[lq + 4 r][lm], so MFMA number r takes k = lq + 4 r
+      const double* wbb = wblk(b, b) + lm * kSP + lq;
+      d4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc = mfma16(-wbb[4 * r], tt[r], acc);
+      store_tile(wblk(b, c), kSP, acc);
     }
     __syncthreads();
+    if (b + 1 < NBLK) {
+      if (wave == 0) {
+        d4v acc = load_tile(dblk(b + 1, b + 1), kSP);
+        mma_abt(acc, dblk(b + 1, b), kSP, dblk(b + 1, b), kSP, -1.0);
+        store_tile(dblk(b + 1, b + 1), kSP, acc);
+        const bool okb = chol16_wave(dblk(b + 1, b + 1), kSP, wblk(b + 1, b + 1), kSP);
+        if (lane == 0) s.flag = okb ? 0 : 1;
+      } else {
+        int idx = 0;
+        for (int r = b + 1; r < NBLK; ++r)
+          for (int c = b + 1; c <= r; ++c) {
+            if (r == b + 1 && c == b + 1) continue;
+            if (idx++ % (nw - 1) + 1 == wave) {
+              d4v acc = load_tile(dblk(r, c), kSP);
+              mma_abt(acc, dblk(r, b), kSP, dblk(c, b), kSP, -1.0);
+              store_tile(dblk(r, c), kSP, acc);
+            }
+          }
+      }
+      __syncthreads();
+    }
   }
   return ok;
 }
@@ -613,6 +623,223 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
       }
     if (J + 1 < P && 4 * (J + 1) + first < T16) prefetch(J + 1, 4 * (J + 1) + first);
   }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Pair factorisation with row ownership and look-ahead (the pose-graph solve
+// with DNLS_FLAG_PAIR).  Row group r (rows 64 r .. 64 r + 63) belongs to the
+// workgroup of role r mod 2, which computes every tile (r, J), J <= r, of it
+// in panel order, so its own rows never need a wait.  Role w runs
+//   [w = 1: the tile (1, 0)]
+//   for J = w, w + 2, ...:  the diagonal tile (J, J);
+//                           its rows' tiles of panel J - 1 (r >= J + 2);
+//                           its rows' tiles of panel J (r >= J + 2);
+//                           the look-ahead tile (J + 2, J + 1)
+// and the look-ahead tile is what the next diagonal tile waits for, so the
+// chain diagonal block -> look-ahead tile -> next diagonal block no longer
+// waits for the rest of a panel.  Events (monotone counters, this
+// factorisation's origin fbase = base + f P): diag = fbase + J + 1 when
+// L_JJ, L_JJ^-1 and y_J are written (posted by the owner of J, in J order),
+// la = fbase + r + 1 when row group r is complete up to panel r - 1 (tile
+// (r, r - 1) written).  A tile of another role's panel J reads that role's
+// rows J (after la >= fbase + J + 1) and L_JJ^-1 (after diag >= fbase + J +
+// 1).  Role 1 ends with done = base + f + 1 (and fail = the same value if
+// one of its diagonal blocks was not positive definite); role 0 waits for
+// it, so on return the whole factor, y and the inverses are written.
+// ---------------------------------------------------------------------------
+struct PairLa {
+  unsigned long long* diag;
+  unsigned long long* la;
+  unsigned long long* done;
+  unsigned long long* fail;
+  unsigned long long base;
+  int role;
+  int spin;
+};
+
+__device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, int npad, double* __restrict__ winv,
+                                                   DenseLds& s, const PairLa& ps, int f, bool& bail) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lm = lane & 15, lq = lane >> 4;
+  const int P = npad / kNB;
+  const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  const double* hb = H + (size_t)npad * npad;   // b
+  double* yrow = A + (size_t)npad * npad;       // y = L^-1 b
+  const int w = ps.role;
+  const unsigned long long fbase = ps.base + (unsigned long long)f * P;
+  enum { kEnd = 0, kDiag = 1, kTile = 2, kAhead = 3 };
+  bool ok = true;
+  int wcur = -1;                      // panel whose L_JJ^-1 is in s.W
+  // the task after (kind, r, J) in this role's sequence
+  auto next_task = [&](int& kind, int& r, int& J) {
+    if (kind == kAhead) {             // (J + 1, J) -> diagonal J + 1
+      kind = kDiag; r = J + 1; J = J + 1;
+    } else if (kind == kDiag) {       // diagonal Jd -> tiles (Jd + 2.., Jd - 1) or (Jd + 2.., Jd)
+      const int Jd = J;
+      if (Jd + 2 >= P) { kind = kEnd; return; }
+      kind = kTile; r = Jd + 2; J = Jd >= 1 ? Jd - 1 : Jd;
+    } else if (kind == kTile) {
+      const int Jd = ((J & 1) == w) ? J : J + 1;   // this iteration's diagonal panel
+      if (r + 2 < P) { r += 2; return; }
+      if (J + 1 == Jd) { r = Jd + 2; J = Jd; return; }       // from panel Jd - 1 to panel Jd
+      kind = kAhead; r = Jd + 2; J = Jd + 1;                 // Jd + 2 < P here
+    }
+  };
+  d4v acc_n[4], bop_n[4];
+  auto prefetch = [&](int r, int J, bool own_chunk0) {
+    const int in = 4 * r + wave, col0 = kNB * J;
+    const double* Hr = H + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc_n[c][q] = Hr[col0 + 16 * c + lq + 4 * q];
+    if (J > 0 && own_chunk0) {
+      const double* Ar = A + (size_t)(16 * in + lm) * npad;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) bop_n[kt] = *reinterpret_cast<const d4v*>(Ar + 16 * kt + 4 * lq);
+    }
+  };
+  int kind, r, J;
+  if (w == 1) {
+    kind = P > 1 ? kAhead : kEnd; r = 1; J = 0;
+  } else {
+    kind = kDiag; r = 0; J = 0;
+  }
+  bool have_b = true;                 // bop_n holds chunk 0 of the task's own rows
+  if (kind != kEnd) prefetch(r, J, true);
+  while (kind != kEnd) {
+    int kn = kind, rn = r, Jn = J;
+    next_task(kn, rn, Jn);
+    // the next task's chunk 0 is this task's tile when both are row group r
+    // and this is panel 0: load it after this task's writes
+    const bool pre_b = !(rn == r && J == 0);
+    const int i = 4 * r + wave, col0 = kNB * J, nchunk = J;
+    const double* Arow = A + (size_t)(16 * i + lm) * npad;
+    const bool diag = kind == kDiag;
+    if (kind == kAhead && J > 0) {
+      // row group J (the other role's) complete up to panel J - 1
+      if (!pair_wait(ps.la, fbase + J + 1, nullptr, ps.spin, s)) {
+        bail = true;
+        return false;
+      }
+    }
+    if (!have_b && nchunk > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) bop_n[kt] = *reinterpret_cast<const d4v*>(Arow + 16 * kt + 4 * lq);
+    }
+    d4v acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
+    double ypart = 0.0;
+    if (nchunk > 0) {
+      d4v st[4], bop[4], bnx[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
+      if (diag) {
+        for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
+        wcur = -1;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
+      __syncthreads();
+      for (int ch = 0; ch < nchunk; ++ch) {
+        const bool more = ch + 1 < nchunk;
+        const int k1 = kNB * (ch + 1);
+        if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
+        if (more) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + k1 + scol + 4 * q);
+#pragma unroll
+          for (int kt = 0; kt < 4; ++kt) bnx[kt] = *reinterpret_cast<const d4v*>(Arow + k1 + 16 * kt + 4 * lq);
+        }
+        const double* buf = s.stage[ch & 1];
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+          d4v aop[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bop[kt][q], acc[c]);
+        }
+        if (more) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<d4v*>(&s.stage[(ch + 1) & 1][srow * kSP + scol + 4 * q]) = st[q];
+#pragma unroll
+          for (int kt = 0; kt < 4; ++kt) bop[kt] = bnx[kt];
+        }
+        __syncthreads();
+      }
+    }
+    if (diag) {
+      // t = b_J - sum_k L_Jk y_k for the forward substitution
+      ypart = row4_sum(ypart);
+      if ((threadIdx.x & 3) == 0) s.vec[srow] = hb[col0 + srow] - ypart;
+      double* D = s.stage[0];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * q] = acc[c][q];
+      __syncthreads();
+      if (!chol_block<4>(D, s.W, s)) ok = false;
+      wcur = J;
+      if (kn != kEnd) prefetch(rn, Jn, pre_b);
+      // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
+      for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
+        const int rr = e >> 6, c = e & 63;
+        A[(size_t)(col0 + rr) * npad + col0 + c] = (c <= rr) ? D[rr * kSP + c] : 0.0;
+        winv[(size_t)J * kNB * kNB + e] = (c <= rr) ? s.W[rr * kSP + c] : 0.0;
+      }
+      ypanel(s.W, s.vec, yrow, col0);
+      pair_post(ps.diag, fbase + J + 1);
+    } else {
+      if (kind == kAhead && !pair_wait(ps.diag, fbase + J + 1, nullptr, ps.spin, s)) {
+        bail = true;
+        return false;
+      }
+      if (wcur != J) {
+        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) s.W[(e >> 6) * kSP + (e & 63)] = winv[(size_t)J * kNB * kNB + e];
+        __syncthreads();
+        wcur = J;
+      }
+      if (kn != kEnd) prefetch(rn, Jn, pre_b);
+      // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
+#pragma unroll
+      for (int cn = 0; cn < 4; ++cn) {
+        d4v out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kt = 0; kt <= cn; ++kt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) out = mfma16(acc[kt][q], s.W[(16 * cn + lm) * kSP + 16 * kt + lq + 4 * q], out);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(size_t)(16 * i + lq + 4 * q) * npad + col0 + 16 * cn + lm] = out[q];
+      }
+      if (kind == kAhead) pair_post(ps.la, fbase + r + 1);
+    }
+    have_b = pre_b;
+    kind = kn; r = rn; J = Jn;
+  }
+  if (w == 1) {
+    if (!ok) {
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(ps.fail, ps.base + f + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    pair_post(ps.done, ps.base + f + 1);
+    return ok;
+  }
+  if (!pair_wait(ps.done, ps.base + f + 1, nullptr, ps.spin, s)) {
+    bail = true;
+    return false;
+  }
+  if (__hip_atomic_load(ps.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= ps.base + f + 1) ok = false;
   return ok;
 }
 

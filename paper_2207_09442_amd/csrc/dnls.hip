@@ -331,15 +331,19 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
   double* H = a.hbuf + g.h_off;    // assembled system (workspace), read by the factorisation
   PairSync ps{};
+  PairLa pl{};
   bool timed_out = false;
   if constexpr (PAIR) {
+    // counters of the slot: system assembled, leader stopped, then the
+    // factorisation's diagonal / look-ahead / done / failed events
     unsigned long long* c = a.pair_ctr + (size_t)slot * 8;
-    ps = PairSync{c, c + 1, c + 2, c + 3, a.pair_base, (int)(blockIdx.x / nslot), 2, a.pair_spin};
+    ps = PairSync{c, c + 1, nullptr, nullptr, a.pair_base, (int)(blockIdx.x / nslot), 2, a.pair_spin};
+    pl = PairLa{c + 2, c + 3, c + 4, c + 5, a.pair_base, ps.role, a.pair_spin};
     if (ps.role == 1) {
       for (int f = 0; f <= a.K; ++f) {
         if (!pair_wait(ps.lead_h, ps.base + f + 1, ps.lead_stop, ps.spin, L.dl, ps.base + 1)) return;
         bool bail = false;
-        chol_dense_pair(A, H, g.npad, winv, L.dl, ps, f, bail);
+        chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail);
         if (bail) return;
       }
       return;
@@ -350,7 +354,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     if constexpr (PAIR) {
       pair_post(ps.lead_h, ps.base + f + 1);
       bool bail = false;
-      const bool ok = chol_dense_pair(A, H, g.npad, winv, L.dl, ps, f, bail);
+      const bool ok = chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail);
       timed_out = timed_out || bail;
       return ok && !bail;
     } else {
