@@ -791,14 +791,20 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
       if (!chol_block<4>(D, s.W, s)) ok = false;
       wcur = J;
       if (kn != kEnd) prefetch(rn, Jn, pre_b);
-      // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
+      // L_JJ^-1 and y_J = L_JJ^-1 t are what the other role waits for; L_JJ
+      // itself is read only by the solves (after the done event), so its
+      // stores go out after the post
       for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
         const int rr = e >> 6, c = e & 63;
-        A[(size_t)(col0 + rr) * npad + col0 + c] = (c <= rr) ? D[rr * kSP + c] : 0.0;
         winv[(size_t)J * kNB * kNB + e] = (c <= rr) ? s.W[rr * kSP + c] : 0.0;
       }
       ypanel(s.W, s.vec, yrow, col0);
       pair_post(ps.diag, fbase + J + 1);
+      for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
+        const int rr = e >> 6, c = e & 63;
+        A[(size_t)(col0 + rr) * npad + col0 + c] = (c <= rr) ? D[rr * kSP + c] : 0.0;
+      }
+      __syncthreads();   // D (stage 0) is read before the next task stages into it
     } else {
       if (kind == kAhead && !pair_wait(ps.diag, fbase + J + 1, nullptr, ps.spin, s)) {
         bail = true;
