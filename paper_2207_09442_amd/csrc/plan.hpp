@@ -130,6 +130,7 @@ struct dnls_plan_s {
   int* d_rowidx = nullptr;
   int* d_rowptr = nullptr;
   int* d_rowcol = nullptr;
+  int2* d_sn = nullptr;           // supernode (first, last tile column) of every tile column
   std::vector<int> sp_ntrsm;
   std::vector<int> sp_nrow;       // per tile row: widest row (off-diagonal tiles) over the batch
   std::vector<long long> sp_npair;

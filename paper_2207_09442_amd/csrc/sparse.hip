@@ -53,6 +53,7 @@ struct SpArgs {
   const int* tix;          // tile ids: [tix_off + I * P + J], -1 if zero
   const int* colptr;       // [col_off + J] .. [col_off + J + 1] -> rowidx
   const int* rowidx;       // tile rows of each column, diagonal first
+  const int2* sn;          // [col_off + J]: first and last tile column of J's supernode
   const int* rowptr;       // [row_off + I] .. [row_off + I + 1] -> rowcol
   const int* rowcol;       // tile columns J < I of each tile row
   double* poses;
@@ -382,7 +383,11 @@ __global__ void __launch_bounds__(kTW) k_sp_trsm(SpArgs a, int J) {
     for (int r = 0; r < 4; ++r) T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm] = acc[c][r];
 }
 
-// 3. A_IK -= L_IJ L_KJ^T for every pair I >= K of tiles below the diagonal of J
+// 3. A_IK -= L_IJ L_KJ^T for every pair I >= K of tiles below the diagonal of
+// J.  Inside a supernode [s, e] (the runs of tile_supernodes) a column J < e
+// updates only the targets with K <= e, which the next columns of the run
+// need; its last column e applies A_IK -= sum_{J'=s}^{e} L_IJ' L_KJ'^T to the
+// targets right of the run, each target read and written once.
 __global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
   __shared__ double LK[kTS * (kTS + 4)];
   constexpr int LW = kTS + 4;
@@ -398,32 +403,39 @@ __global__ void __launch_bounds__(kTW) k_sp_update(SpArgs a, int J) {
   while ((long long)(p + 1) * (p + 2) / 2 <= t) ++p;
   while ((long long)p * (p + 1) / 2 > t) --p;
   const int q = (int)(t - (long long)p * (p + 1) / 2);
+  const int2 sn = a.sn[g.col_off + J];
+  // rows J + 1 .. sn.y come first below the diagonal of a column of the run
+  if (J < sn.y && q >= sn.y - J) return;
+  const int jfirst = J == sn.y ? sn.x : J;
   const int I = a.rowidx[c0 + 1 + p], Kt = a.rowidx[c0 + 1 + q];
-  const double* LI = tile_ptr(a, g, I, J);
-  const double* LKg = tile_ptr(a, g, Kt, J);
   double* T = tile_ptr(a, g, I, Kt);
-  for (int e = threadIdx.x; e < kTT / 4; e += kTW) {
-    const int r = (4 * e) / kTS, c = (4 * e) % kTS;
-    *reinterpret_cast<d4v*>(&LK[r * LW + c]) = *reinterpret_cast<const d4v*>(LKg + 4 * e);
-  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
   d4v acc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[c][r] = T[(16 * wave + lq + 4 * r) * kTS + 16 * c + lm];
-  d4v av[3];
-#pragma unroll
-  for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * wave + lm) * kTS + 16 * kt + 4 * lq);
-  __syncthreads();
-#pragma unroll
-  for (int kt = 0; kt < 3; ++kt)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const d4v bv = *reinterpret_cast<const d4v*>(&LK[(16 * c + lm) * LW + 16 * kt + 4 * lq]);
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) acc[c] = mfma16(-av[kt][qq], bv[qq], acc[c]);
+  for (int Jp = jfirst; Jp <= J; ++Jp) {
+    const double* LI = tile_ptr(a, g, I, Jp);
+    const double* LKg = tile_ptr(a, g, Kt, Jp);
+    if (Jp > jfirst) __syncthreads();   // the previous column's LK is read
+    for (int e = threadIdx.x; e < kTT / 4; e += kTW) {
+      const int r = (4 * e) / kTS, c = (4 * e) % kTS;
+      *reinterpret_cast<d4v*>(&LK[r * LW + c]) = *reinterpret_cast<const d4v*>(LKg + 4 * e);
     }
+    d4v av[3];
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) av[kt] = *reinterpret_cast<const d4v*>(LI + (16 * wave + lm) * kTS + 16 * kt + 4 * lq);
+    __syncthreads();
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const d4v bv = *reinterpret_cast<const d4v*>(&LK[(16 * c + lm) * LW + 16 * kt + 4 * lq]);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) acc[c] = mfma16(-av[kt][qq], bv[qq], acc[c]);
+      }
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -2068,6 +2080,36 @@ int max_desc(const std::vector<SpDesc>& v, int SpDesc::*f) {
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// Supernodes of the tile factor, per graph: consecutive tile columns J, J + 1
+// whose structures below the diagonal are {J + 1} and then the same rows
+// (column J's rows are J + 1 followed by column J + 1's), at most
+// kSnMax columns.  The per-column update launches apply the updates of such
+// a run to the tiles right of it once, at its last column, summed over its
+// columns (one read and write of each target tile instead of one per
+// column); sn[col_off + J] = (first, last) column of J's run.
+constexpr int kSnMax = 32;
+static std::vector<int2> tile_supernodes(const std::vector<dnls::SpDesc>& sd, const std::vector<int>& colptr,
+                                         const std::vector<int>& rowidx) {
+  std::vector<int2> sn(colptr.size(), int2{0, 0});
+  auto same_tail = [&](int col_off, int J) {   // column J = {J + 1} + column J + 1
+    const int a0 = colptr[col_off + J] + 1, a1 = colptr[col_off + J + 1];
+    const int b0 = colptr[col_off + J + 1] + 1, b1 = colptr[col_off + J + 2];
+    if (a1 - a0 != b1 - b0 + 1 || a1 == a0 || rowidx[a0] != J + 1) return false;
+    for (int k = 0; k < b1 - b0; ++k)
+      if (rowidx[a0 + 1 + k] != rowidx[b0 + k]) return false;
+    return true;
+  };
+  for (const dnls::SpDesc& g : sd) {
+    for (int J = 0; J < g.P;) {
+      int e = J;
+      while (e + 1 < g.P && e - J + 1 < kSnMax && same_tail(g.col_off, e)) ++e;
+      for (int j = J; j <= e; ++j) sn[g.col_off + j] = int2{J, e};
+      J = e + 1;
+    }
+  }
+  return sn;
+}
+
 dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
   const int B = pr->batch, d = p->d;
   std::vector<int> edge_ij(2 * (size_t)p->E), prior_var(p->P), pos(p->V);
@@ -2304,7 +2346,8 @@ dnls_status sp_plan_create(dnls_plan p, const dnls_problem* pr) {
       (st = upload(p, &p->d_od_blk, od_blk)) != DNLS_OK || (st = upload(p, &p->d_od_slot, od_slot)) != DNLS_OK ||
       (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
       (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK || (st = upload(p, &p->d_rowptr, rowptr)) != DNLS_OK ||
-      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK)
+      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK ||
+      (st = upload(p, &p->d_sn, tile_supernodes(p->sd, colptr, rowidx))) != DNLS_OK)
     return st;
   if (tsz != kTS &&
       ((st = upload(p, &p->d_lvlptr, lvlptr)) != DNLS_OK || (st = upload(p, &p->d_lvlcol, lvlcol)) != DNLS_OK ||
@@ -2572,7 +2615,8 @@ dnls_status sp_plan_create_ba(dnls_plan p, const dnls_problem* pr) {
       (st = upload(p, &p->d_cp_blk, cp_blk)) != DNLS_OK || (st = upload(p, &p->d_cp_obs, cp_obs)) != DNLS_OK ||
       (st = upload(p, &p->d_tix, tix)) != DNLS_OK || (st = upload(p, &p->d_colptr, colptr)) != DNLS_OK ||
       (st = upload(p, &p->d_rowidx, rowidx)) != DNLS_OK || (st = upload(p, &p->d_rowptr, rowptr)) != DNLS_OK ||
-      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK)
+      (st = upload(p, &p->d_rowcol, rowcol)) != DNLS_OK ||
+      (st = upload(p, &p->d_sn, tile_supernodes(p->sd, colptr, rowidx))) != DNLS_OK)
     return st;
   const size_t rn = CostRec<6>::n;
   const int maxc = std::max(max_desc(p->sd, &SpDesc::nobs) + max_desc(p->sd, &SpDesc::nprior), 1);
@@ -2610,6 +2654,7 @@ static SpArgs sp_args(dnls_plan p, void* ws, void* factor) {
   a.tix = p->d_tix;
   a.colptr = p->d_colptr;
   a.rowidx = p->d_rowidx;
+  a.sn = p->d_sn;
   a.rowptr = p->d_rowptr;
   a.rowcol = p->d_rowcol;
   char* w = static_cast<char*>(ws);

@@ -150,3 +150,15 @@ def test_pair_gives_up_without_hanging(monkeypatch):
     torch.cuda.synchronize()
     codes = set(stb.cpu().tolist())
     assert codes <= {S.OK, 3} and 3 in codes
+
+
+def test_pair_deep_panel_chains():
+    """Graphs of 178 and 108 poses in one launch (npad 1088 and 704: 17 and
+    11 panels, so the look-ahead chain, the tiles of the panel before the
+    diagonal one and the inverse reloads run many times on both roles, with
+    two panel counts): the pair matches one workgroup per graph to the
+    rounding of the split factorisation, and the oracle on the smaller
+    graph."""
+    p = synth.uneven_walk_se3(batch=2, n_min=100, n_max=180, seed=93)
+    assert list(np.diff(p["pose_off"])) == [178, 108]
+    _check(p, 4, 1e-3, graphs=[1])
