@@ -170,7 +170,7 @@ __device__ __forceinline__ bool chol16_wave(double* t, int ldt, double* w, int l
 // waves update the rest of the trailing blocks, D_rc -= L_rb L_cb^T.  Two
 // barriers per block column.
 template <int NBLK>
-__device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
+__device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s, int nlive = NBLK) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
   const int nw = blockDim.x >> 6;
@@ -182,9 +182,9 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
     if (lane == 0) s.flag = okb ? 0 : 1;
   }
   __syncthreads();
-  for (int b = 0; b < NBLK; ++b) {
+  for (int b = 0; b < nlive; ++b) {
     if (s.flag) ok = false;
-    const int ntr = NBLK - 1 - b;   // blocks below the diagonal in column b
+    const int ntr = nlive - 1 - b;  // blocks below the diagonal in column b
     if (wave < ntr) {
       const int r = b + 1 + wave;
       d4v acc = {0.0, 0.0, 0.0, 0.0};
@@ -203,7 +203,7 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
       store_tile(wblk(b, c), kSP, acc);
     }
     __syncthreads();
-    if (b + 1 < NBLK) {
+    if (b + 1 < nlive) {
       if (wave == 0) {
         d4v acc = load_tile(dblk(b + 1, b + 1), kSP);
         mma_abt(acc, dblk(b + 1, b), kSP, dblk(b + 1, b), kSP, -1.0);
@@ -212,7 +212,7 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
         if (lane == 0) s.flag = okb ? 0 : 1;
       } else {
         int idx = 0;
-        for (int r = b + 1; r < NBLK; ++r)
+        for (int r = b + 1; r < nlive; ++r)
           for (int c = b + 1; c <= r; ++c) {
             if (r == b + 1 && c == b + 1) continue;
             if (idx++ % (nw - 1) + 1 == wave) {
@@ -224,6 +224,15 @@ __device__ __forceinline__ bool chol_block(double* D, double* W, DenseLds& s) {
       }
       __syncthreads();
     }
+  }
+  // blocks past the live ones hold unit diagonal padding (their coupling to
+  // the live unknowns is zero): L = I there already, and its inverse is I
+  if (nlive < NBLK) {
+    for (int e = threadIdx.x; e < (NBLK - nlive) * 16 * 16 * NBLK; e += blockDim.x) {
+      const int r = 16 * nlive + e / (16 * NBLK), c = e % (16 * NBLK);
+      W[r * kSP + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
   }
   return ok;
 }
@@ -265,13 +274,21 @@ __device__ __forceinline__ void ypanel(const double* W, const double* t, double*
   if ((threadIdx.x & 3) == 0) y[col0 + srow] = v;
 }
 
+// 16-row blocks of the 64-wide diagonal block at column col0 that hold
+// unknowns (n < 0: all four); the rest is the unit-diagonal padding
+__device__ __forceinline__ int live_blocks(int n, int col0) {
+  if (n < 0 || n >= col0 + kNB) return 4;
+  return max(1, (n - col0 + 15) >> 4);
+}
+
 // Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix H
 // (row npad = right-hand side; lower part read) into L (same layout; L may
 // be H itself): on return L holds the factor and y = L^-1 b in row npad,
 // winv holds the inverses of the diagonal blocks.  H is only read, so a
 // caller can keep its structural zeros across factorisations.  All threads
 // call; returns false (uniformly) if the matrix is not positive definite.
-__device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad, double* __restrict__ winv, DenseLds& s) {
+__device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad, double* __restrict__ winv, DenseLds& s,
+                                           int n = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
   const int T16 = npad >> 4;          // row tiles of the matrix
@@ -368,7 +385,7 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
 #pragma unroll
           for (int r = 0; r < 4; ++r) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * r] = acc[c][r];
         __syncthreads();
-        if (!chol_block<4>(D, s.W, s)) ok = false;
+        if (!chol_block<4>(D, s.W, s, live_blocks(n, col0))) ok = false;
         if (!last_group) prefetch(J, i0 + kNW);
         // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
@@ -659,7 +676,7 @@ struct PairLa {
 };
 
 __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, int npad, double* __restrict__ winv,
-                                                   DenseLds& s, const PairLa& ps, int f, bool& bail) {
+                                                   DenseLds& s, const PairLa& ps, int f, bool& bail, int n = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
   const int P = npad / kNB;
@@ -788,7 +805,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
 #pragma unroll
         for (int q = 0; q < 4; ++q) D[(16 * wave + lm) * kSP + 16 * c + lq + 4 * q] = acc[c][q];
       __syncthreads();
-      if (!chol_block<4>(D, s.W, s)) ok = false;
+      if (!chol_block<4>(D, s.W, s, live_blocks(n, col0))) ok = false;
       wcur = J;
       if (kn != kEnd) prefetch(rn, Jn, pre_b);
       // L_JJ^-1 and y_J = L_JJ^-1 t are what the other role waits for; L_JJ

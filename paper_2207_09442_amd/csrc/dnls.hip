@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       for (int f = 0; f <= a.K; ++f) {
         if (!pair_wait(ps.lead_h, ps.base + f + 1, ps.lead_stop, ps.spin, L.dl, ps.base + 1)) return;
         bool bail = false;
-        chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail);
+        chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n);
         if (bail) return;
       }
       return;
@@ -354,11 +354,11 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     if constexpr (PAIR) {
       pair_post(ps.lead_h, ps.base + f + 1);
       bool bail = false;
-      const bool ok = chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail);
+      const bool ok = chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n);
       timed_out = timed_out || bail;
       return ok && !bail;
     } else {
-      return chol_dense(A, H, g.npad, winv, L.dl);
+      return chol_dense(A, H, g.npad, winv, L.dl, g.n);
     }
   };
   double* vb = dyn;                // step
@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_unroll(DenseArgs a, int 
     init_H(g, H);
     assemble_H<G, double>(at, g, a.ws64, H, a.lambda);
     assemble_g<G, double>(at, g, a.ws64, vd, haug);
-    if (!chol_dense(H, H, g.npad, winv, L.dl)) {
+    if (!chol_dense(H, H, g.npad, winv, L.dl, g.n)) {
       // the forward factored this system (in float32 on the mixed path): give up on the graph
       zero_grads<G>(a, g, true);
       return;
@@ -895,7 +895,7 @@ __global__ void __launch_bounds__(kNT) k_dense_backward_dlm(DenseArgs a, double 
   assemble_g<G, double>(a, g, a.ws64, vy, haug);
   for (int u = threadIdx.x; u < g.n; u += kNT) haug[u] = -haug[u] + eps * a.seed[(size_t)g.pose0 * d + u];
   __syncthreads();
-  const bool ok = chol_dense(H, H, g.npad, winv, L.dl);
+  const bool ok = chol_dense(H, H, g.npad, winv, L.dl, g.n);
   if (!ok) {
     // cannot happen for a positive definite H* (it was factored in the solve)
     zero_grads<G>(a, g, false);
@@ -1218,8 +1218,11 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   if (op->flags & DNLS_FLAG_PAIR) {
     p->pair_spin = pair_spin_limit();
     const bool mixed = op->precision == DNLS_PREC_MIXED;
-    p->pair_ok = p->group == DNLS_SE3 ? (mixed ? pair_fits<3, true>(p) : pair_fits<3, false>(p))
-                                      : (mixed ? pair_fits<2, true>(p) : pair_fits<2, false>(p));
+    // a pair needs a second row group to share: with one 64-wide panel per
+    // graph the follower would only add its synchronisation to every step
+    p->pair_ok = p->npad_max > kNB &&
+                 (p->group == DNLS_SE3 ? (mixed ? pair_fits<3, true>(p) : pair_fits<3, false>(p))
+                                       : (mixed ? pair_fits<2, true>(p) : pair_fits<2, false>(p)));
     if (p->pair_ok) {
       const size_t bytes = (size_t)p->B * 8 * sizeof(unsigned long long);
       if (hipMalloc(reinterpret_cast<void**>(&p->d_pair), bytes) != hipSuccess ||

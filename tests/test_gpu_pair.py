@@ -114,15 +114,16 @@ def test_pair_adaptive():
 
 
 def test_pair_failed_graphs_are_frozen():
-    p = synth.walk_se3(batch=3, n_poses=8, n_loops=4, seed=17)
-    last = int(p["pose_off"][1]) + 7
+    p = synth.walk_se3(batch=3, n_poses=24, n_loops=8, seed=17)
+    last = int(p["pose_off"][1]) + 23
     keep = ~((p["edge_ij"][:, 0] == last) | (p["edge_ij"][:, 1] == last))
     counts = [int(keep[p["edge_off"][b]:p["edge_off"][b + 1]].sum()) for b in range(3)]
     p["edge_ij"], p["edge_meas"], p["edge_logw"] = p["edge_ij"][keep], p["edge_meas"][keep], p["edge_logw"][keep]
     p["edge_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
     p["edge_meas"] = p["edge_meas"].copy()
     p["edge_meas"][p["edge_off"][2] + 1, 0, 3] = np.nan
-    _, poses, obj, st, _, _ = _solve(p, 5, 0.0, True)
+    plan, poses, obj, st, _, _ = _solve(p, 5, 0.0, True)
+    assert plan.schedule()["pair"]
     assert st.cpu().tolist() == [0, 1, 2]
     got = poses.cpu().numpy()
     for b in (1, 2):
@@ -162,3 +163,14 @@ def test_pair_deep_panel_chains():
     p = synth.uneven_walk_se3(batch=2, n_min=100, n_max=180, seed=93)
     assert list(np.diff(p["pose_off"])) == [178, 108]
     _check(p, 4, 1e-3, graphs=[1])
+
+
+def test_pair_not_used_for_one_panel():
+    """With every graph within one 64-wide panel the follower would have no
+    row group: the plan keeps one workgroup per graph (the schedule query
+    says so) and the solve is the one-workgroup kernel's."""
+    p = synth.circle_se2(batch=2, n_poses=16, n_loops=8, seed=3)
+    plan, poses, obj, st, _, _ = _solve(p, 4, 0.0, True)
+    assert not plan.schedule()["pair"]
+    _, poses1, _, st1, _, _ = _solve(p, 4, 0.0, False)
+    assert np.array_equal(poses.cpu().numpy(), poses1.cpu().numpy())
