@@ -281,6 +281,68 @@ __device__ __forceinline__ int live_blocks(int n, int col0) {
   return max(1, (n - col0 + 15) >> 4);
 }
 
+// Chunk loop of a panel's diagonal tile (J, J): its own rows are the staged
+// panel rows, so each chunk is loaded once (no separate own-row operand),
+// two chunks ahead; adds -sum_k L_Jk L_Jk^T to acc (wave w: rows 16 w ..
+// 16 w + 15, transposed accumulator layout) and this thread's part of
+// sum_k L_Jk y_k to ypart.  y of the panels before col0 must be in yrow;
+// s.W is used for it.  All threads call, nchunk > 0.
+__device__ __forceinline__ void diag_chunks(const double* A, int npad, int col0, int nchunk, const double* yrow,
+                                            DenseLds& s, d4v (&acc)[4], double& ypart) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lm = lane & 15, lq = lane >> 4;
+  const int srow = threadIdx.x >> 2, scol = (threadIdx.x & 3) * 16;
+  const double* Brow = A + (size_t)(col0 + srow) * npad + scol;
+  d4v st1[4], st2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) st1[q] = *reinterpret_cast<const d4v*>(Brow + 4 * q);
+  for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st1[q];
+  if (nchunk > 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st1[q] = *reinterpret_cast<const d4v*>(Brow + kNB + 4 * q);
+  }
+  if (nchunk > 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st2[q] = *reinterpret_cast<const d4v*>(Brow + 2 * kNB + 4 * q);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const double* buf = s.stage[ch & 1];
+    {
+      d4v sv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sv[q] = *reinterpret_cast<const d4v*>(buf + srow * kSP + scol + 4 * q);
+      ypart += ydot16(sv, s.W + kNB * ch + scol);
+    }
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      d4v aop[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) aop[c] = *reinterpret_cast<const d4v*>(buf + (16 * c + lm) * kSP + 16 * kt + 4 * lq);
+      const d4v bv = *reinterpret_cast<const d4v*>(buf + (16 * wave + lm) * kSP + 16 * kt + 4 * lq);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = mfma16(-aop[c][q], bv[q], acc[c]);
+    }
+    if (ch + 1 < nchunk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[(ch + 1) & 1][srow * kSP + scol + 4 * q]) = st1[q];
+      if (ch + 2 < nchunk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st1[q] = st2[q];
+      }
+      if (ch + 3 < nchunk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st2[q] = *reinterpret_cast<const d4v*>(Brow + kNB * (ch + 3) + 4 * q);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Blocked left-looking Cholesky of the (npad + 16) x npad row-major matrix H
 // (row npad = right-hand side; lower part read) into L (same layout; L may
 // be H itself): on return L holds the factor and y = L^-1 b in row npad,
@@ -329,15 +391,15 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
       for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
       // diagonal group: sum_k L_Jk y_k (this thread's row srow, 16 columns of each chunk)
       double ypart = 0.0;
-      if (nchunk > 0) {
+      if (nchunk > 0 && diag) {
+        diag_chunks(A, npad, col0, nchunk, yrow, s, acc, ypart);
+      } else if (nchunk > 0) {
         d4v st[4], bop[4], bnx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
         // y of the panels before J, flat in W (L_{J-1,J-1}^-1 is no longer needed)
-        if (diag)
-          for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
 #pragma unroll
         for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
         __syncthreads();
@@ -345,7 +407,6 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
           const bool more = ch + 1 < nchunk;
           const int k1 = kNB * (ch + 1);
           // st still holds this thread's part of chunk ch
-          if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
           if (more) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -535,15 +596,15 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
       for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
       // diagonal group: sum_k L_Jk y_k (this thread's row srow, 16 columns of each chunk)
       double ypart = 0.0;
-      if (nchunk > 0) {
+      if (nchunk > 0 && diag) {
+        diag_chunks(A, npad, col0, nchunk, yrow, s, acc, ypart);
+      } else if (nchunk > 0) {
         d4v st[4], bop[4], bnx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
         for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
         // y of the panels before J, flat in W (L_{J-1,J-1}^-1 is no longer needed)
-        if (diag)
-          for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
 #pragma unroll
         for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
         __syncthreads();
@@ -551,7 +612,6 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
           const bool more = ch + 1 < nchunk;
           const int k1 = kNB * (ch + 1);
           // st still holds this thread's part of chunk ch
-          if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
           if (more) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -741,7 +801,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
         return false;
       }
     }
-    if (!have_b && nchunk > 0) {
+    if (!have_b && nchunk > 0 && !diag) {
       __syncthreads();
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt) bop_n[kt] = *reinterpret_cast<const d4v*>(Arow + 16 * kt + 4 * lq);
@@ -750,23 +810,21 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = acc_n[c];
     double ypart = 0.0;
-    if (nchunk > 0) {
+    if (nchunk > 0 && diag) {
+      diag_chunks(A, npad, col0, nchunk, yrow, s, acc, ypart);
+      wcur = -1;
+    } else if (nchunk > 0) {
       d4v st[4], bop[4], bnx[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) st[q] = *reinterpret_cast<const d4v*>(A + (size_t)(col0 + srow) * npad + scol + 4 * q);
 #pragma unroll
       for (int kt = 0; kt < 4; ++kt) bop[kt] = bop_n[kt];
-      if (diag) {
-        for (int u = threadIdx.x; u < col0; u += kNT) s.W[u] = yrow[u];
-        wcur = -1;
-      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) *reinterpret_cast<d4v*>(&s.stage[0][srow * kSP + scol + 4 * q]) = st[q];
       __syncthreads();
       for (int ch = 0; ch < nchunk; ++ch) {
         const bool more = ch + 1 < nchunk;
         const int k1 = kNB * (ch + 1);
-        if (diag) ypart += ydot16(st, s.W + kNB * ch + scol);
         if (more) {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
@@ -807,7 +865,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
       __syncthreads();
       if (!chol_block<4>(D, s.W, s, live_blocks(n, col0))) ok = false;
       wcur = J;
-      if (kn != kEnd) prefetch(rn, Jn, pre_b);
+      if (kn != kEnd) prefetch(rn, Jn, pre_b && kn != kDiag);
       // L_JJ^-1 and y_J = L_JJ^-1 t are what the other role waits for; L_JJ
       // itself is read only by the solves (after the done event), so its
       // stores go out after the post
@@ -832,7 +890,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
         __syncthreads();
         wcur = J;
       }
-      if (kn != kEnd) prefetch(rn, Jn, pre_b);
+      if (kn != kEnd) prefetch(rn, Jn, pre_b && kn != kDiag);
       // L_iJ = D L_JJ^-T:  out[m][n] = sum_k D[m][k] W[n][k]
 #pragma unroll
       for (int cn = 0; cn < 4; ++cn) {
