@@ -244,55 +244,88 @@ __device__ void assemble_g(const DenseArgs& a, const GraphDesc& g, const S* rec,
 }
 
 // y = (H + lambda I) x with H = sum J^T J applied matrix-free in float64.
+// Each cost's thread reads its record once, row by row, and forms both pose
+// terms J_i^T (J x) and J_j^T (J x) into LDS (the staging buffers of s, free
+// outside the factorisation); each unknown then sums the terms of its
+// incident costs, four incidence entries per round of loads.  Costs go in
+// chunks of what the buffers hold.
 template <int G>
 __device__ void matvec_H(const DenseArgs& a, const GraphDesc& g, const double* rec, const double* x,
-                         double* y, double lambda) {
+                         double* y, double lambda, DenseLds& s) {
   constexpr int d = GroupTraits<G>::d, RN = CostRec<d>::n;
+  constexpr int kCh = (2 * kNB * kSP) / (2 * d);   // costs per chunk of zs
+  double* zs = &s.stage[0][0];
   const int ncost = g.nedge + g.nprior;
-  for (int k = threadIdx.x; k < ncost; k += kNT) {
-    int cost, pi, pj;
-    if (k < g.nedge) {
-      cost = g.edge0 + k;
-      pi = a.edge_ij[2 * cost] - g.pose0;
-      pj = a.edge_ij[2 * cost + 1] - g.pose0;
-    } else {
-      const int p = g.prior0 + (k - g.nedge);
-      cost = a.E + p;
-      pi = -1;
-      pj = a.prior_var[p] - g.pose0;
-    }
-    const double* J = rec + (size_t)cost * RN;
-    double out[d];
-#pragma unroll
-    for (int r = 0; r < d; ++r) {
-      double acc = 0.0;
+  for (int c0 = 0; c0 == 0 || c0 < ncost; c0 += kCh) {
+    const int c1 = min(ncost, c0 + kCh);
+    for (int k = c0 + threadIdx.x; k < c1; k += kNT) {
+      int cost, pi, pj;
+      if (k < g.nedge) {
+        cost = g.edge0 + k;
+        pi = a.edge_ij[2 * cost] - g.pose0;
+        pj = a.edge_ij[2 * cost + 1] - g.pose0;
+      } else {
+        const int p = g.prior0 + (k - g.nedge);
+        cost = a.E + p;
+        pi = -1;
+        pj = a.prior_var[p] - g.pose0;
+      }
+      const double* J = rec + (size_t)cost * RN;
+      double xi[d], xj[d], zi[d], zj[d];
 #pragma unroll
       for (int q = 0; q < d; ++q) {
-        if (pi >= 0) acc += J[r * d + q] * x[pi * d + q];
-        acc += J[d * d + r * d + q] * x[pj * d + q];
+        xi[q] = pi >= 0 ? x[pi * d + q] : 0.0;
+        xj[q] = x[pj * d + q];
+        zi[q] = 0.0;
+        zj[q] = 0.0;
       }
-      out[r] = acc;
-    }
 #pragma unroll
-    for (int r = 0; r < d; ++r) a.ycost[(size_t)cost * d + r] = out[r];
-  }
-  __syncthreads();
-  for (int u = threadIdx.x; u < g.npad; u += kNT) {
-    double v = 0.0;
-    if (u < g.n) {
-      const int p = u / d, r = u % d, gp = g.pose0 + p;
-      for (int s = a.inc_off[gp]; s < a.inc_off[gp + 1]; ++s) {
-        const int slot = a.inc_slot[s];
-        const double* J = rec + (size_t)(slot >> 1) * RN + (slot & 1) * d * d;
-        const double* yc = a.ycost + (size_t)(slot >> 1) * d;
+      for (int r = 0; r < d; ++r) {
+        double ji[d], jj[d];
 #pragma unroll
-        for (int k = 0; k < d; ++k) v += J[k * d + r] * yc[k];
+        for (int q = 0; q < d; ++q) {
+          ji[q] = pi >= 0 ? J[r * d + q] : 0.0;
+          jj[q] = J[d * d + r * d + q];
+        }
+        double yr = 0.0;
+#pragma unroll
+        for (int q = 0; q < d; ++q) yr += ji[q] * xi[q] + jj[q] * xj[q];
+#pragma unroll
+        for (int q = 0; q < d; ++q) {
+          zi[q] += ji[q] * yr;
+          zj[q] += jj[q] * yr;
+        }
       }
-      v += lambda * x[u];
+      double* z = zs + (size_t)(k - c0) * 2 * d;
+#pragma unroll
+      for (int q = 0; q < d; ++q) {
+        z[q] = zi[q];
+        z[d + q] = zj[q];
+      }
     }
-    y[u] = v;
+    __syncthreads();
+    for (int u = threadIdx.x; u < g.npad; u += kNT) {
+      double v = c0 > 0 ? y[u] : (u < g.n ? lambda * x[u] : 0.0);
+      if (u < g.n) {
+        const int p = u / d, r = u % d, gp = g.pose0 + p;
+        const int s0 = a.inc_off[gp], s1 = a.inc_off[gp + 1];
+        for (int e = s0; e < s1; e += 4) {
+          int sl[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) sl[j] = e + j < s1 ? a.inc_slot[e + j] : -1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (sl[j] < 0) continue;
+            const int rid = sl[j] >> 1;   // record: edge, or a.E + prior
+            const int k = rid < a.E ? rid - g.edge0 : g.nedge + (rid - a.E - g.prior0);
+            if (k >= c0 && k < c1) v += zs[(size_t)(k - c0) * 2 * d + (sl[j] & 1) * d + r];
+          }
+        }
+      }
+      y[u] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 constexpr double kLambdaMin = 1e-7, kLambdaMax = 1e7;   // adaptive damping range
@@ -426,7 +459,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     if (MIXED) {
       for (int sweep = 0; sweep < (refine_now ? a.refine : 0); ++sweep) {
         // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
-        matvec_H<G>(a, g, a.ws64, vb, vx, lam);
+        matvec_H<G>(a, g, a.ws64, vb, vx, lam, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
         __syncthreads();
         trsv_lower_f32(F, P, vx, L.dl);
@@ -444,7 +477,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       bool boundary = false;
       if (!(n_gn <= radius)) {
         boundary = true;
-        matvec_H<G>(a, g, a.ws64, vy, vx, lam);   // (H + lambda I) g
+        matvec_H<G>(a, g, a.ws64, vy, vx, lam, L.dl);   // (H + lambda I) g
         double p1 = 0.0, p2 = 0.0;
         for (int u = threadIdx.x; u < g.n; u += kNT) {
           p1 += vy[u] * vy[u];
@@ -478,7 +511,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         }
       }
       // predicted decrease g^T delta - 1/2 delta^T (H + lambda I) delta
-      matvec_H<G>(a, g, a.ws64, vb, vx, lam);
+      matvec_H<G>(a, g, a.ws64, vb, vx, lam, L.dl);
       double r1 = 0.0, r2 = 0.0;
       for (int u = threadIdx.x; u < g.n; u += kNT) {
         r1 += vy[u] * vb[u];
@@ -651,7 +684,7 @@ __device__ void adjoint_solve(const DenseArgs& a, const GraphDesc& g, const doub
   const double* seed = a.seed + (size_t)g.pose0 * d;
   trsv_lower(A, g.npad, winv, vu, L.dl);
   trsv_upper_t(A, g.npad, winv, vu, L.dl);
-  matvec_H<G>(a, g, a.ws64, vu, vx, 0.0);
+  matvec_H<G>(a, g, a.ws64, vu, vx, 0.0, L.dl);
   for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = ((u < g.n) ? seed[u] : 0.0) - vx[u];
   __syncthreads();
   trsv_lower(A, g.npad, winv, vx, L.dl);
