@@ -36,15 +36,6 @@ constexpr int kNB = 64;              // panel width
 constexpr int kSP = 68;              // LDS row stride (doubles) of a 64-wide panel
 constexpr int kMaxDenseN = 2048;     // npad limit of the one-workgroup dense path
 
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-// Float32 copy of a factor, read by the mixed path's refinement solves: the
-// 64x64 tiles (I, J), I > J, below the diagonal blocks, each row-major and
-// contiguous in the order (1,0), (2,0), (2,1), (3,0), ..., then the P panel
-// inverses L_JJ^-1 (row-major): P (P + 1) / 2 tiles of 64 x 64 floats.
-__device__ __forceinline__ size_t f32_tile(int I, int J) { return ((size_t)I * (I - 1) / 2 + J) * (kNB * kNB); }
-__device__ __forceinline__ size_t f32_winv(int P, int J) { return ((size_t)P * (P - 1) / 2 + J) * (kNB * kNB); }
-
 struct DenseLds {
   double stage[2][kNB * kSP];        // double-buffered panel chunk L_J[0:64][k0:k0+64]
   double W[kNB * kSP];               // L_JJ^-1 of the current panel
@@ -359,7 +350,7 @@ __device__ __forceinline__ void diag_chunks(const double* A, int npad, int col0,
 // caller can keep its structural zeros across factorisations.  All threads
 // call; returns false (uniformly) if the matrix is not positive definite.
 __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad, double* __restrict__ winv, DenseLds& s,
-                                           int n = -1, float* __restrict__ F = nullptr) {
+                                           int n = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
   const int T16 = npad >> 4;          // row tiles of the matrix
@@ -461,9 +452,7 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
           A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
-          const double wv = (c <= r) ? s.W[r * kSP + c] : 0.0;
-          winv[(size_t)J * kNB * kNB + e] = wv;
-          if (F) F[f32_winv(P, J) + e] = (float)wv;
+          winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
         ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
@@ -482,11 +471,6 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) A[(size_t)(16 * i + lq + 4 * r) * npad + col0 + 16 * cn + lm] = out[r];
-          if (F) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              F[f32_tile(i >> 2, J) + (16 * (i & 3) + lq + 4 * r) * kNB + 16 * cn + lm] = (float)out[r];
-          }
         }
       }
     }
@@ -752,8 +736,7 @@ struct PairLa {
 };
 
 __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, int npad, double* __restrict__ winv,
-                                                   DenseLds& s, const PairLa& ps, int f, bool& bail, int n = -1,
-                                                   float* __restrict__ F = nullptr) {
+                                                   DenseLds& s, const PairLa& ps, int f, bool& bail, int n = -1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lm = lane & 15, lq = lane >> 4;
   const int P = npad / kNB;
@@ -888,9 +871,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
       // stores go out after the post
       for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
         const int rr = e >> 6, c = e & 63;
-        const double wv = (c <= rr) ? s.W[rr * kSP + c] : 0.0;
-        winv[(size_t)J * kNB * kNB + e] = wv;
-        if (F) F[f32_winv(P, J) + e] = (float)wv;
+        winv[(size_t)J * kNB * kNB + e] = (c <= rr) ? s.W[rr * kSP + c] : 0.0;
       }
       ypanel(s.W, s.vec, yrow, col0);
       pair_post(ps.diag, fbase + J + 1);
@@ -921,10 +902,6 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) A[(size_t)(16 * i + lq + 4 * q) * npad + col0 + 16 * cn + lm] = out[q];
-        if (F) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) F[f32_tile(r, J) + (16 * wave + lq + 4 * q) * kNB + 16 * cn + lm] = (float)out[q];
-        }
       }
       if (kind == kAhead) pair_post(ps.la, fbase + r + 1);
     }
@@ -947,64 +924,34 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
   return ok;
 }
 
-// Where the triangular solves find a factor.  FactorRows: the row-major
-// factor cache (leading dimension npad) and the panel inverses after it, in
-// float64.  FactorTiles32: the float32 copy in the tile layout above.  row(r,
-// J) points at L[r][64 J .. 64 J + 63] (contiguous); col(J, c) at L[64 J][c],
-// with L[64 J + k][c] at col(J, c)[k * cstride()]; inv(J) at L_JJ^-1.
-struct FactorRows {
-  typedef double T;
-  typedef d4v V4;
-  const double* L;
-  const double* W;
-  int npad;
-  __device__ __forceinline__ const double* row(int r, int J) const { return L + (size_t)r * npad + kNB * J; }
-  __device__ __forceinline__ const double* col(int J, int c) const { return L + (size_t)kNB * J * npad + c; }
-  __device__ __forceinline__ size_t cstride() const { return (size_t)npad; }
-  __device__ __forceinline__ const double* inv(int J) const { return W + (size_t)J * kNB * kNB; }
-};
-struct FactorTiles32 {
-  typedef float T;
-  typedef f4v V4;
-  const float* F;
-  int P;
-  __device__ __forceinline__ const float* row(int r, int J) const {
-    return F + f32_tile(r >> 6, J) + (size_t)(r & 63) * kNB;
-  }
-  __device__ __forceinline__ const float* col(int J, int c) const { return F + f32_tile(J, c >> 6) + (c & 63); }
-  __device__ __forceinline__ size_t cstride() const { return (size_t)kNB; }
-  __device__ __forceinline__ const float* inv(int J) const { return F + f32_winv(P, J); }
-};
-
 // v[0:64] <- W v (lower = true) or W^T v (lower = false) for the 64x64
 // lower-triangular panel inverse W (global, row-major); all threads call,
 // 4 partial sums per output reduced through LDS.
-template <class T, class V4>
-__device__ __forceinline__ void panel_inv_matvec(const T* __restrict__ W, const double* v, double* out, bool lower,
-                                                 DenseLds& s) {
+__device__ __forceinline__ void panel_inv_matvec(const double* __restrict__ W, const double* v, double* out,
+                                                 bool lower, DenseLds& s) {
   const int c = threadIdx.x & 63, part = threadIdx.x >> 6;
   double acc = 0.0;
   if (lower) {
     // out[c] = sum_{k <= c} W[c][k] v[k], k in this part's 16 columns
-    const V4* row = reinterpret_cast<const V4*>(W + c * kNB + 16 * part);
+    const d4v* row = reinterpret_cast<const d4v*>(W + c * kNB + 16 * part);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const V4 w = row[q];
+      const d4v w = row[q];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 16 * part + 4 * q + e;
-        acc += (k <= c) ? (double)w[e] * v[k] : 0.0;
+        acc += (k <= c) ? w[e] * v[k] : 0.0;
       }
     }
   } else {
     // out[c] = sum_{r >= c} W[r][c] v[r], r in this part's 16 rows
-    T w[16];
+    double w[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) w[q] = W[(16 * part + q) * kNB + c];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int r = 16 * part + q;
-      acc += (r >= c) ? (double)w[q] * v[r] : 0.0;
+      acc += (r >= c) ? w[q] * v[r] : 0.0;
     }
   }
   s.W[part * kNB + c] = acc;
@@ -1013,38 +960,36 @@ __device__ __forceinline__ void panel_inv_matvec(const T* __restrict__ W, const 
   __syncthreads();
 }
 
-// x <- L^-T x (x in LDS, length 64 P, float64 arithmetic), each thread owning
-// whole columns of the update (no reductions).  Per panel J (descending):
+// x <- L^-T x (x in LDS, length npad), each thread owning whole columns of
+// the update (no reductions).  Per panel J (descending):
 // x_J = W_J^T x_J, then x[0:r0] -= L[r0:r0+64][0:r0]^T x_J.  The L loads of
 // the update do not depend on x, so they are issued before the W_J product
 // and their latency overlaps it.
-template <class M>
-__device__ __forceinline__ void trsv_upper_t_m(const M& m, int P, double* x, DenseLds& s) {
-  typedef typename M::T T;
+__device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
+                                             double* x, DenseLds& s) {
+  const int P = npad / kNB;
   for (int J = P - 1; J >= 0; --J) {
     const int r0 = kNB * J;
     const int c = threadIdx.x;
-    T l[kNB];
+    double l[kNB];
     if (c < r0) {
-      const T* cp = m.col(J, c);
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) l[r] = cp[r * m.cstride()];
+      for (int r = 0; r < kNB; ++r) l[r] = L[(size_t)(r0 + r) * npad + c];
     }
-    panel_inv_matvec<T, typename M::V4>(m.inv(J), x + r0, s.vec, false, s);
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, false, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
     if (c < r0) {
       double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) acc += (double)l[r] * s.vec[r];
+      for (int r = 0; r < kNB; ++r) acc += l[r] * s.vec[r];
       x[c] -= acc;
     }
     for (int c2 = c + kNT; c2 < r0; c2 += kNT) {
-      const T* cp = m.col(J, c2);
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) l[r] = cp[r * m.cstride()];
+      for (int r = 0; r < kNB; ++r) l[r] = L[(size_t)(r0 + r) * npad + c2];
       double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < kNB; ++r) acc += (double)l[r] * s.vec[r];
+      for (int r = 0; r < kNB; ++r) acc += l[r] * s.vec[r];
       x[c2] -= acc;
     }
     __syncthreads();
@@ -1054,59 +999,39 @@ __device__ __forceinline__ void trsv_upper_t_m(const M& m, int P, double* x, Den
 // x <- L^-1 x (x in LDS).  Per panel J (ascending): x_J = W_J x_J, then
 // x[r] -= L[r][r0:r0+64] x_J for the rows below; the row loads are issued
 // before the W_J product.
-template <class M>
-__device__ __forceinline__ void trsv_lower_m(const M& m, int P, double* x, DenseLds& s) {
-  typedef typename M::V4 V4;
-  const int npad = P * kNB;
+__device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
+                                           double* x, DenseLds& s) {
+  const int P = npad / kNB;
   for (int J = 0; J < P; ++J) {
     const int r0 = kNB * J;
     const int r = r0 + kNB + threadIdx.x;
-    V4 v[kNB / 4];
+    d4v v[kNB / 4];
     if (r < npad) {
-      const V4* row = reinterpret_cast<const V4*>(m.row(r, J));
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0);
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
     }
-    panel_inv_matvec<typename M::T, V4>(m.inv(J), x + r0, s.vec, true, s);
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, true, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
     if (r < npad) {
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q)
-        acc += (double)v[q][0] * s.vec[4 * q] + (double)v[q][1] * s.vec[4 * q + 1] +
-               (double)v[q][2] * s.vec[4 * q + 2] + (double)v[q][3] * s.vec[4 * q + 3];
+        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
       x[r] -= acc;
     }
     for (int r2 = r + kNT; r2 < npad; r2 += kNT) {
-      const V4* row = reinterpret_cast<const V4*>(m.row(r2, J));
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r2 * npad + r0);
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < kNB / 4; ++q)
-        acc += (double)v[q][0] * s.vec[4 * q] + (double)v[q][1] * s.vec[4 * q + 1] +
-               (double)v[q][2] * s.vec[4 * q + 2] + (double)v[q][3] * s.vec[4 * q + 3];
+        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
       x[r2] -= acc;
     }
     __syncthreads();
   }
-}
-
-// the solves on the float64 factor cache (row-major L, inverses winv)
-__device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
-                                             double* x, DenseLds& s) {
-  trsv_upper_t_m(FactorRows{L, winv, npad}, npad / kNB, x, s);
-}
-__device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
-                                           double* x, DenseLds& s) {
-  trsv_lower_m(FactorRows{L, winv, npad}, npad / kNB, x, s);
-}
-// ... and on the float32 tile copy F of a factor with P panels
-__device__ __forceinline__ void trsv_upper_t_f32(const float* __restrict__ F, int P, double* x, DenseLds& s) {
-  trsv_upper_t_m(FactorTiles32{F, P}, P, x, s);
-}
-__device__ __forceinline__ void trsv_lower_f32(const float* __restrict__ F, int P, double* x, DenseLds& s) {
-  trsv_lower_m(FactorTiles32{F, P}, P, x, s);
 }
 
 }  // namespace dnls

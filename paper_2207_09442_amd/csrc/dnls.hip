@@ -59,7 +59,6 @@ struct DenseArgs {
   float* ws32;       // per-cost records, float32 (mixed)
   double* ycost;     // per-cost J delta (d values)
   double* hbuf;      // assembled systems (per graph at GraphDesc::h_off)
-  float* l32;        // mixed: float32 copies of the step factors (per graph at GraphDesc::l32_off)
   double* pose_bak;  // adaptive damping: theta_t while the trial step is evaluated; DLM: theta_direct
   double* dlm_winv;  // DLM backward: inverses of the diagonal panels of the factor of H* + 2 eps^2 I
   double* hvp;       // exact / unrolled backward: [cost][2][d] per-cost pose terms
@@ -364,8 +363,6 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   double* A = a.factor + g.fac_off;
   double* winv = A + (size_t)(g.npad + 16) * g.npad;
   double* H = a.hbuf + g.h_off;    // assembled system (workspace), read by the factorisation
-  float* F = MIXED ? a.l32 + g.l32_off : nullptr;   // float32 copy of the step factor for the solves
-  const int P = g.npad / kNB;
   PairSync ps{};
   PairLa pl{};
   bool timed_out = false;
@@ -379,7 +376,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
       for (int f = 0; f <= a.K; ++f) {
         if (!pair_wait(ps.lead_h, ps.base + f + 1, ps.lead_stop, ps.spin, L.dl, ps.base + 1)) return;
         bool bail = false;
-        chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n, f < a.K ? F : nullptr);
+        chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n);
         if (bail) return;
       }
       return;
@@ -387,15 +384,14 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
   }
   // factorisation number f of this launch (the step index; K for the final one)
   auto factor = [&](int f) -> bool {
-    float* Ff = f < a.K ? F : nullptr;
     if constexpr (PAIR) {
       pair_post(ps.lead_h, ps.base + f + 1);
       bool bail = false;
-      const bool ok = chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n, Ff);
+      const bool ok = chol_dense_pair_la(A, H, g.npad, winv, L.dl, pl, f, bail, g.n);
       timed_out = timed_out || bail;
       return ok && !bail;
     } else {
-      return chol_dense(A, H, g.npad, winv, L.dl, g.n, Ff);
+      return chol_dense(A, H, g.npad, winv, L.dl, g.n);
     }
   };
   double* vb = dyn;                // step
@@ -451,19 +447,15 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // delta = L^-T y with y = L^-1 g from the right-hand-side row
     for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
     __syncthreads();
-    // the mixed path solves with the float32 copy of the step's factor (it
-    // perturbs the factor no more than the float32 assembly of H does); the
-    // float64 sweeps take the step to the float64 one
-    if constexpr (MIXED) trsv_upper_t_f32(F, P, vb, L.dl);
-    else trsv_upper_t(A, g.npad, winv, vb, L.dl);
+    trsv_upper_t(A, g.npad, winv, vb, L.dl);
     if (MIXED) {
       for (int sweep = 0; sweep < (refine_now ? a.refine : 0); ++sweep) {
         // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
         matvec_H<G>(a, g, a.ws64, vb, vx, lam, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
         __syncthreads();
-        trsv_lower_f32(F, P, vx, L.dl);
-        trsv_upper_t_f32(F, P, vx, L.dl);
+        trsv_lower(A, g.npad, winv, vx, L.dl);
+        trsv_upper_t(A, g.npad, winv, vx, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
@@ -1155,7 +1147,7 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   std::vector<int4> od_blk;
   std::vector<int> od_slot;
   p->gd.resize(B);
-  long long fac = 0, hsz = 0, dlmw = 0, l32sz = 0;
+  long long fac = 0, hsz = 0, dlmw = 0;
   for (int b = 0; b < B; ++b) {
     GraphDesc& g = p->gd[b];
     g.pose0 = pr->pose_off[b];
@@ -1176,8 +1168,6 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
     g.fac_off = fac;
     g.h_off = hsz;
     hsz += (long long)(g.npad + 16) * g.npad;
-    g.l32_off = l32sz;
-    l32sz += (long long)(g.npad / kNB) * (g.npad / kNB + 1) / 2 * kNB * kNB;
     g.dlm_winv_off = dlmw;
     dlmw += (long long)(g.npad / kNB) * kNB * kNB;
     // L (npad x npad) + right-hand-side row and 15 padding rows (16 x npad) + panel inverses
@@ -1251,9 +1241,6 @@ dnls_status dnls_plan_create(dnls_plan* out, const dnls_problem* pr, const dnls_
   ws += align256((size_t)V * p->sz * sizeof(double));   // adaptive damping backup / DLM theta_direct
   p->dlmw_off = ws;
   ws += align256((size_t)dlmw * sizeof(double));        // DLM backward: panel inverses
-  p->l32_off = ws;
-  if (op->precision == DNLS_PREC_MIXED)
-    ws += align256((size_t)l32sz * sizeof(float));      // float32 copies of the step factors
   p->hvp_off = ws;
   ws += align256(ncost * 2 * d * sizeof(double));       // exact backward: residual terms per cost side
   p->ws_bytes = ws;
@@ -1404,7 +1391,6 @@ dnls_status dnls_solve(dnls_plan p, const dnls_solve_args* s, void* stream) {
   a.hbuf = reinterpret_cast<double*>(ws + p->h_off);
   a.pose_bak = reinterpret_cast<double*>(ws + p->bak_off);
   a.dlm_winv = reinterpret_cast<double*>(ws + p->dlmw_off);
-  a.l32 = p->opt.precision == DNLS_PREC_MIXED ? reinterpret_cast<float*>(ws + p->l32_off) : nullptr;
   a.adaptive = (p->opt.flags & DNLS_FLAG_ADAPTIVE_LM) ? 1 : 0;
   a.dogleg = (p->opt.flags & DNLS_FLAG_DOGLEG) ? 1 : 0;
   a.radius0 = p->opt.trust_radius;

@@ -45,7 +45,6 @@ struct GraphDesc {
   long long fac_off;   // doubles: L ((npad + 16) x npad) then the 64x64 panel inverses
   long long h_off;     // doubles: assembled H ((npad + 16) x npad) in the solve workspace
   long long dlm_winv_off;   // doubles: panel inverses of the DLM backward system
-  long long l32_off;   // floats: float32 copy of the step factor (mixed), P (P + 1) / 2 tiles of 64x64
   int od0, nod;        // off-diagonal Hessian blocks of the graph
 };
 
@@ -87,7 +86,7 @@ struct dnls_plan_s {
   std::vector<dnls::GraphDesc> gd;
   size_t ws_bytes = 0, fac_bytes = 0, bwd_bytes = 0;
   double flops_alg = 0.0, flops_exec = 0.0;   // one numeric factorisation over the batch
-  size_t ws32_off = 0, ycost_off = 0, h_off = 0, bak_off = 0, dlmw_off = 0, hvp_off = 0, l32_off = 0;
+  size_t ws32_off = 0, ycost_off = 0, h_off = 0, bak_off = 0, dlmw_off = 0, hvp_off = 0;
   long long traj_off = 0;   // doubles into the factor cache: kept iterates (DNLS_FLAG_KEEP_ITERATES)
   // DNLS_FLAG_PAIR: whether the pair kernel fits, its counters and launch epoch
   bool pair_ok = false;
