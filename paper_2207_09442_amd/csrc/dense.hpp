@@ -997,38 +997,53 @@ __device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int n
 }
 
 // x <- L^-1 x (x in LDS).  Per panel J (ascending): x_J = W_J x_J, then
-// x[r] -= L[r][r0:r0+64] x_J for the rows below; the row loads are issued
-// before the W_J product.
+// x[r] -= L[r][r0:r0+64] x_J for the rows below, four threads a row (thread
+// j of a row reads the doubles 16 q + 4 j .. + 3, so each load instruction
+// takes whole cache lines; the partial sums meet by shuffles).  The loads
+// of the first 256 rows are issued before the W_J product.
 __device__ __forceinline__ void trsv_lower(const double* __restrict__ L, int npad, const double* __restrict__ winv,
                                            double* x, DenseLds& s) {
   const int P = npad / kNB;
-  for (int J = 0; J < P; ++J) {
-    const int r0 = kNB * J;
-    const int r = r0 + kNB + threadIdx.x;
-    d4v v[kNB / 4];
-    if (r < npad) {
-      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0);
+  const int rq = threadIdx.x >> 2, j = threadIdx.x & 3;
+  auto row_dot = [&](const d4v (&v)[4]) {
+    double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
+    for (int q = 0; q < 4; ++q) {
+      const d4v w = *reinterpret_cast<const d4v*>(s.vec + 16 * q + 4 * j);
+      acc += v[q][0] * w[0] + v[q][1] * w[1] + v[q][2] * w[2] + v[q][3] * w[3];
+    }
+    return row4_sum(acc);
+  };
+  for (int J = 0; J < P; ++J) {
+    const int r0 = kNB * J, rb = r0 + kNB;
+    d4v v[4][4];
+#pragma unroll
+    for (int ps = 0; ps < 4; ++ps) {
+      const int r = rb + kNB * ps + rq;
+      if (r < npad) {
+        const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0 + 4 * j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[ps][q] = row[4 * q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[ps][q] = d4v{0.0, 0.0, 0.0, 0.0};
+      }
     }
     panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, true, s);
     if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
-    if (r < npad) {
-      double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < kNB / 4; ++q)
-        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
-      x[r] -= acc;
+    for (int ps = 0; ps < 4; ++ps) {
+      const int r = rb + kNB * ps + rq;
+      const double acc = row_dot(v[ps]);
+      if (r < npad && j == 0) x[r] -= acc;
     }
-    for (int r2 = r + kNT; r2 < npad; r2 += kNT) {
-      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r2 * npad + r0);
+    for (int r = rb + kNT + rq; r < npad; r += kNB) {
+      const d4v* row = reinterpret_cast<const d4v*>(L + (size_t)r * npad + r0 + 4 * j);
+      d4v u[4];
 #pragma unroll
-      for (int q = 0; q < kNB / 4; ++q) v[q] = row[q];
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < kNB / 4; ++q)
-        acc += v[q][0] * s.vec[4 * q] + v[q][1] * s.vec[4 * q + 1] + v[q][2] * s.vec[4 * q + 2] + v[q][3] * s.vec[4 * q + 3];
-      x[r2] -= acc;
+      for (int q = 0; q < 4; ++q) u[q] = row[4 * q];
+      const double acc = row_dot(u);
+      if (j == 0) x[r] -= acc;
     }
     __syncthreads();
   }
