@@ -960,12 +960,67 @@ __device__ __forceinline__ void panel_inv_matvec(const double* __restrict__ W, c
   __syncthreads();
 }
 
-// x <- L^-T x (x in LDS, length npad), each thread owning whole columns of
-// the update (no reductions).  Per panel J (descending):
+// x <- L^-T x (x in LDS, length npad).  Per panel J (descending):
+// x_J = W_J^T x_J, then x[0:r0] -= L[r0:r0+64][0:r0]^T x_J.  A pass takes 64
+// columns: wave w the columns 16 w .. 16 w + 15 of it, the four 16-lane
+// rows of a wave the four quarters of the panel's 64 rows (each load
+// instruction reads 128 contiguous bytes per quarter), the quarters' sums
+// joined by shuffles; so every panel keeps all 256 threads busy.  The L
+// loads of the first four passes do not depend on x and are issued before
+// the W_J product.
+__device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
+                                             double* x, DenseLds& s) {
+  const int P = npad / kNB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = 16 * wave + (lane & 15), k = lane >> 4;
+  auto col_dot = [&](const double (&l)[16]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc += l[i] * s.vec[16 * k + i];
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    return acc;
+  };
+  for (int J = P - 1; J >= 0; --J) {
+    const int r0 = kNB * J;
+    // this thread's column of the first pass in its quarter's 16 rows; pass
+    // ps is 64 ps columns on (the passes below J are uniform)
+    const double* Lc = L + (size_t)(r0 + 16 * k) * npad + cl;
+    double l[4][16];
+#pragma unroll
+    for (int ps = 0; ps < 4; ++ps) {
+      if (ps < J) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) l[ps][i] = Lc[i * npad + kNB * ps];
+      }
+    }
+    panel_inv_matvec(winv + (size_t)J * kNB * kNB, x + r0, s.vec, false, s);
+    if (threadIdx.x < kNB) x[r0 + threadIdx.x] = s.vec[threadIdx.x];
+#pragma unroll
+    for (int ps = 0; ps < 4; ++ps) {
+      if (ps < J) {
+        const double acc = col_dot(l[ps]);
+        if (k == 0) x[kNB * ps + cl] -= acc;
+      }
+    }
+    for (int ps = 4; ps < J; ++ps) {
+      double u[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) u[i] = Lc[i * npad + kNB * ps];
+      const double acc = col_dot(u);
+      if (k == 0) x[kNB * ps + cl] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// x <- L^-T x (x in LDS, length npad) as trsv_upper_t, each thread owning
+// whole columns of the update (no reductions, fewer live registers: the form
+// the fused solve kernel takes).  Per panel J (descending):
 // x_J = W_J^T x_J, then x[0:r0] -= L[r0:r0+64][0:r0]^T x_J.  The L loads of
 // the update do not depend on x, so they are issued before the W_J product
 // and their latency overlaps it.
-__device__ __forceinline__ void trsv_upper_t(const double* __restrict__ L, int npad, const double* __restrict__ winv,
+__device__ __forceinline__ void trsv_upper_t_cols(const double* __restrict__ L, int npad, const double* __restrict__ winv,
                                              double* x, DenseLds& s) {
   const int P = npad / kNB;
   for (int J = P - 1; J >= 0; --J) {
