@@ -295,7 +295,9 @@ typedef struct {
 
 /* dnls_backward_args.mode */
 typedef enum {
-  /* Proposition 1: u = H*^-1 v with the cached factor. */
+  /* Proposition 1: u = H*^-1 v with the cached factor (DENSE, FP64 plans:
+   * plus one float64 refinement step u += H*^-1 (v - H* u) with H* applied
+   * matrix-free; MIXED plans, held to 1e-5 of float64, skip it). */
   DNLS_BACKWARD_IMPLICIT = 0,
   /* Direct loss minimisation (Section 4.3, Appendix G), every solver: one
    * Gauss-Newton step from theta_K on S(theta) + ||eps theta - v/2||^2,

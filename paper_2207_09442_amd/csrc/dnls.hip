@@ -81,6 +81,7 @@ struct DenseArgs {
   int refine;
   int refine_from;   // mixed: steps refine_from <= it < refine_until run the refinement sweeps
   int refine_until;
+  int adj_refine;    // backward: the float64 refinement step of the adjoint (float64 plans)
   double lambda;
 };
 
@@ -667,8 +668,11 @@ __device__ void hvp_exact(const DenseArgs& a, const GraphDesc& g, const double* 
 // solves with the cached factor, then one step of float64 iterative
 // refinement u <- u + H*^-1 (v - H* u) with H* applied matrix-free from the
 // float64 records at theta_K, so that u carries the rounding of that product
-// rather than the factorisation's rounding amplified by cond(H*).  vu holds
-// v on entry and u on return; vx is scratch (npad each, LDS).
+// rather than the factorisation's rounding amplified by cond(H*).  Mixed
+// plans skip the refinement: their results are held to 1e-5 of the float64
+// ones, and the adjoint through the float64 factor of H* is within
+// cond(H*) eps64 of it.  vu holds v on entry and u on return; vx is scratch
+// (npad each, LDS).
 template <int G>
 __device__ void adjoint_solve(const DenseArgs& a, const GraphDesc& g, const double* A, const double* winv,
                               double* vu, double* vx, KernelLds& L) {
@@ -676,6 +680,7 @@ __device__ void adjoint_solve(const DenseArgs& a, const GraphDesc& g, const doub
   const double* seed = a.seed + (size_t)g.pose0 * d;
   trsv_lower(A, g.npad, winv, vu, L.dl);
   trsv_upper_t(A, g.npad, winv, vu, L.dl);
+  if (!a.adj_refine) return;
   matvec_H<G>(a, g, a.ws64, vu, vx, 0.0, L.dl);
   for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = ((u < g.n) ? seed[u] : 0.0) - vx[u];
   __syncthreads();
@@ -1496,6 +1501,7 @@ dnls_status dnls_backward(dnls_plan p, const dnls_backward_args* s, void* stream
   a.hvp = reinterpret_cast<double*>(ws + p->hvp_off);
   a.traj = (p->opt.flags & DNLS_FLAG_KEEP_ITERATES) ? a.factor + p->traj_off : nullptr;
   a.seed = s->seed_pose;
+  a.adj_refine = p->opt.precision == DNLS_PREC_MIXED ? 0 : 1;
   a.g_logw_e = s->grad_edge_logw;
   a.g_tau = s->grad_edge_tau;
   a.g_logw_p = s->grad_prior_logw;
