@@ -281,6 +281,25 @@ __device__ __forceinline__ int live_blocks(int n, int col0) {
   return max(1, (n - col0 + 15) >> 4);
 }
 
+// dst (64x64 row-major, global) <- the lower triangle of W (LDS, stride
+// kSP), zeros above it; and the way back.  Four values per thread and
+// access.  All threads call.
+__device__ __forceinline__ void store_inv(double* __restrict__ dst, const double* W) {
+  for (int e = threadIdx.x; e < kNB * kNB / 4; e += kNT) {
+    const int rr = e >> 4, c = (e & 15) * 4;
+    d4v v = *reinterpret_cast<const d4v*>(W + rr * kSP + c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (c + k <= rr) ? v[k] : 0.0;
+    *reinterpret_cast<d4v*>(dst + rr * kNB + c) = v;
+  }
+}
+__device__ __forceinline__ void load_inv(double* W, const double* __restrict__ src) {
+  for (int e = threadIdx.x; e < kNB * kNB / 4; e += kNT) {
+    const int rr = e >> 4, c = (e & 15) * 4;
+    *reinterpret_cast<d4v*>(W + rr * kSP + c) = *reinterpret_cast<const d4v*>(src + rr * kNB + c);
+  }
+}
+
 // Chunk loop of a panel's diagonal tile (J, J): its own rows are the staged
 // panel rows, so each chunk is loaded once (no separate own-row operand),
 // two chunks ahead; adds -sum_k L_Jk L_Jk^T to acc (wave w: rows 16 w ..
@@ -449,10 +468,10 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
         if (!chol_block<4>(D, s.W, s, live_blocks(n, col0))) ok = false;
         if (!last_group) prefetch(J, i0 + kNW);
         // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
+        store_inv(winv + (size_t)J * kNB * kNB, s.W);
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
           A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
-          winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
         ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
@@ -654,10 +673,10 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         if (!chol_block<4>(D, s.W, s)) ok = false;
         if (!last_group) prefetch(J, i0 + stride);
         // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
+        store_inv(winv + (size_t)J * kNB * kNB, s.W);
         for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
           const int r = e >> 6, c = e & 63;
           A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
-          winv[(size_t)J * kNB * kNB + e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
         }
         ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
@@ -669,7 +688,7 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
             bail = true;
             return false;
           }
-          for (int e = threadIdx.x; e < kNB * kNB; e += kNT) s.W[(e >> 6) * kSP + (e & 63)] = winv[(size_t)J * kNB * kNB + e];
+          load_inv(s.W, winv + (size_t)J * kNB * kNB);
           __syncthreads();
           have_w = true;
         }
@@ -869,10 +888,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
       // L_JJ^-1 and y_J = L_JJ^-1 t are what the other role waits for; L_JJ
       // itself is read only by the solves (after the done event), so its
       // stores go out after the post
-      for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
-        const int rr = e >> 6, c = e & 63;
-        winv[(size_t)J * kNB * kNB + e] = (c <= rr) ? s.W[rr * kSP + c] : 0.0;
-      }
+      store_inv(winv + (size_t)J * kNB * kNB, s.W);
       ypanel(s.W, s.vec, yrow, col0);
       pair_post(ps.diag, fbase + J + 1);
       for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
@@ -886,7 +902,7 @@ __device__ __forceinline__ bool chol_dense_pair_la(double* A, const double* H, i
         return false;
       }
       if (wcur != J) {
-        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) s.W[(e >> 6) * kSP + (e & 63)] = winv[(size_t)J * kNB * kNB + e];
+        load_inv(s.W, winv + (size_t)J * kNB * kNB);
         __syncthreads();
         wcur = J;
       }
