@@ -281,18 +281,19 @@ __device__ __forceinline__ int live_blocks(int n, int col0) {
   return max(1, (n - col0 + 15) >> 4);
 }
 
-// dst (64x64 row-major, global) <- the lower triangle of W (LDS, stride
-// kSP), zeros above it; and the way back.  Four values per thread and
-// access.  All threads call.
-__device__ __forceinline__ void store_inv(double* __restrict__ dst, const double* W) {
+// dst (64x64, global, row stride ld; kNB for store_inv) <- the lower
+// triangle of W (LDS, stride kSP), zeros above it; and the way back.  Four
+// values per thread and access.  All threads call.
+__device__ __forceinline__ void store_lower(double* __restrict__ dst, int ld, const double* W) {
   for (int e = threadIdx.x; e < kNB * kNB / 4; e += kNT) {
     const int rr = e >> 4, c = (e & 15) * 4;
     d4v v = *reinterpret_cast<const d4v*>(W + rr * kSP + c);
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = (c + k <= rr) ? v[k] : 0.0;
-    *reinterpret_cast<d4v*>(dst + rr * kNB + c) = v;
+    *reinterpret_cast<d4v*>(dst + (size_t)rr * ld + c) = v;
   }
 }
+__device__ __forceinline__ void store_inv(double* __restrict__ dst, const double* W) { store_lower(dst, kNB, W); }
 __device__ __forceinline__ void load_inv(double* W, const double* __restrict__ src) {
   for (int e = threadIdx.x; e < kNB * kNB / 4; e += kNT) {
     const int rr = e >> 4, c = (e & 15) * 4;
@@ -469,10 +470,7 @@ __device__ __forceinline__ bool chol_dense(double* A, const double* H, int npad,
         if (!last_group) prefetch(J, i0 + kNW);
         // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
         store_inv(winv + (size_t)J * kNB * kNB, s.W);
-        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
-          const int r = e >> 6, c = e & 63;
-          A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
-        }
+        store_lower(A + (size_t)col0 * npad + col0, npad, D);
         ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
       } else {
@@ -674,10 +672,7 @@ __device__ __forceinline__ bool chol_dense_pair(double* A, const double* H, int 
         if (!last_group) prefetch(J, i0 + stride);
         // write L_JJ (zero above the diagonal), its inverse and y_J = L_JJ^-1 t
         store_inv(winv + (size_t)J * kNB * kNB, s.W);
-        for (int e = threadIdx.x; e < kNB * kNB; e += kNT) {
-          const int r = e >> 6, c = e & 63;
-          A[(size_t)(col0 + r) * npad + col0 + c] = (c <= r) ? D[r * kSP + c] : 0.0;
-        }
+        store_lower(A + (size_t)col0 * npad + col0, npad, D);
         ypanel(s.W, s.vec, yrow, col0);
         __syncthreads();
         pair_post(ps.lead_diag, fbase + J + 1);
