@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
         __syncthreads();
         trsv_lower(A, g.npad, winv, vx, L.dl);
-        trsv_upper_t_cols(A, g.npad, winv, vx, L.dl);
+        trsv_upper_t(A, g.npad, winv, vx, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
