@@ -448,7 +448,8 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // delta = L^-T y with y = L^-1 g from the right-hand-side row
     for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
     __syncthreads();
-    trsv_upper_t_cols(A, g.npad, winv, vb, L.dl);
+    if constexpr (MIXED) trsv_upper_t(A, g.npad, winv, vb, L.dl);
+    else trsv_upper_t_cols(A, g.npad, winv, vb, L.dl);
     if (MIXED) {
       for (int sweep = 0; sweep < (refine_now ? a.refine : 0); ++sweep) {
         // vx = g - (H64 + lambda I) delta ; delta += (L L^T)^-1 vx
