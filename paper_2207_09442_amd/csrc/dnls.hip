@@ -448,7 +448,8 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
     // delta = L^-T y with y = L^-1 g from the right-hand-side row
     for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] = aug[u];
     __syncthreads();
-    if constexpr (MIXED) trsv_upper_t(A, g.npad, winv, vb, L.dl);
+    // the quarter form where its registers fit (the mixed pair kernels)
+    if constexpr (MIXED && PAIR) trsv_upper_t(A, g.npad, winv, vb, L.dl);
     else trsv_upper_t_cols(A, g.npad, winv, vb, L.dl);
     if (MIXED) {
       for (int sweep = 0; sweep < (refine_now ? a.refine : 0); ++sweep) {
@@ -457,7 +458,8 @@ __global__ void __launch_bounds__(kNT) k_dense_solve(DenseArgs a) {
         for (int u = threadIdx.x; u < g.npad; u += kNT) vx[u] = vy[u] - vx[u];
         __syncthreads();
         trsv_lower(A, g.npad, winv, vx, L.dl);
-        trsv_upper_t(A, g.npad, winv, vx, L.dl);
+        if constexpr (PAIR) trsv_upper_t(A, g.npad, winv, vx, L.dl);
+        else trsv_upper_t_cols(A, g.npad, winv, vx, L.dl);
         for (int u = threadIdx.x; u < g.npad; u += kNT) vb[u] += vx[u];
         __syncthreads();
       }
