@@ -329,14 +329,25 @@ __global__ void __launch_bounds__(kNT) k_sp_diag(SpArgs a, int J) {
   if (a.failed[b] || J >= g.P) return;
   double* T = tile_ptr(a, g, J, J);
   double* D = s.stage[0];
-  for (int e = threadIdx.x; e < kTT; e += kNT) D[(e / kTS) * kSP + e % kTS] = T[e];
+  // four values per thread and access (a tile row is 12 of them)
+  for (int e = threadIdx.x; e < kTT / 4; e += kNT) {
+    const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+    *reinterpret_cast<d4v*>(D + r * kSP + c) = *reinterpret_cast<const d4v*>(T + 4 * e);
+  }
   __syncthreads();
   const bool ok = chol_block<3>(D, s.W, s);
   double* winv = a.factor + g.winv_off + (size_t)J * kTT;
-  for (int e = threadIdx.x; e < kTT; e += kNT) {
-    const int r = e / kTS, c = e % kTS;
-    T[e] = (c <= r) ? D[r * kSP + c] : 0.0;
-    winv[e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+  for (int e = threadIdx.x; e < kTT / 4; e += kNT) {
+    const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+    d4v l = *reinterpret_cast<const d4v*>(D + r * kSP + c);
+    d4v w = *reinterpret_cast<const d4v*>(s.W + r * kSP + c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      l[k] = (c + k <= r) ? l[k] : 0.0;
+      w[k] = (c + k <= r) ? w[k] : 0.0;
+    }
+    *reinterpret_cast<d4v*>(T + 4 * e) = l;
+    *reinterpret_cast<d4v*>(winv + 4 * e) = w;
   }
   if (!ok && threadIdx.x == 0) {
     a.failed[b] = DNLS_GRAPH_NOT_PD;
@@ -356,7 +367,10 @@ __global__ void __launch_bounds__(kTW) k_sp_trsm(SpArgs a, int J) {
   const int I = a.rowidx[c0 + 1 + t];
   const double* winv = a.factor + g.winv_off + (size_t)J * kTT;
   constexpr int LW = kTS + 4;
-  for (int e = threadIdx.x; e < kTT; e += kTW) W[(e / kTS) * LW + e % kTS] = winv[e];
+  for (int e = threadIdx.x; e < kTT / 4; e += kTW) {
+    const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+    *reinterpret_cast<d4v*>(&W[r * LW + c]) = *reinterpret_cast<const d4v*>(winv + 4 * e);
+  }
   __syncthreads();
   double* T = tile_ptr(a, g, I, J);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lm = lane & 15, lq = lane >> 4;
@@ -506,14 +520,24 @@ __device__ bool sp_factor_wg_body(const SpArgs& a, int b, const SpDesc& g, Dense
     // 1. diagonal tile
     double* TJ = tile_ptr(a, g, J, J);
     double* D = s.stage[0];
-    for (int e = threadIdx.x; e < kTT; e += NT) D[(e / kTS) * kSP + e % kTS] = TJ[e];
+    for (int e = threadIdx.x; e < kTT / 4; e += NT) {
+      const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+      *reinterpret_cast<d4v*>(D + r * kSP + c) = *reinterpret_cast<const d4v*>(TJ + 4 * e);
+    }
     __syncthreads();
     const bool ok = chol_block<3>(D, s.W, s);
     double* winv = a.factor + g.winv_off + (size_t)J * kTT;
-    for (int e = threadIdx.x; e < kTT; e += NT) {
-      const int r = e / kTS, c = e % kTS;
-      TJ[e] = (c <= r) ? D[r * kSP + c] : 0.0;
-      winv[e] = (c <= r) ? s.W[r * kSP + c] : 0.0;
+    for (int e = threadIdx.x; e < kTT / 4; e += NT) {
+      const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+      d4v l = *reinterpret_cast<const d4v*>(D + r * kSP + c);
+      d4v w = *reinterpret_cast<const d4v*>(s.W + r * kSP + c);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        l[k] = (c + k <= r) ? l[k] : 0.0;
+        w[k] = (c + k <= r) ? w[k] : 0.0;
+      }
+      *reinterpret_cast<d4v*>(TJ + 4 * e) = l;
+      *reinterpret_cast<d4v*>(winv + 4 * e) = w;
     }
     if (!ok) {
       if (threadIdx.x == 0) {
@@ -567,7 +591,12 @@ __device__ __forceinline__ double* slot(const SpArgs& a, const SpDesc& g, int k)
 
 // stage a 48 x 48 tile (row-major, global) into LDS with stride kSW
 __device__ __forceinline__ void stage_tile(double* dst, const double* src) {
-  for (int e = threadIdx.x; e < kTT; e += blockDim.x) dst[(e / kTS) * kSW + e % kTS] = src[e];
+  for (int e = threadIdx.x; e < kTT / 4; e += blockDim.x) {
+    const d4v v = *reinterpret_cast<const d4v*>(src + 4 * e);
+    const int r = e / (kTS / 4), c = (e % (kTS / 4)) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[r * kSW + c + k] = v[k];
+  }
 }
 
 // forward step of column J: x_J = W_J b_J; b_I -= L_IJ x_J for the tiles I of the column
